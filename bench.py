@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Headline benchmark: candidate poses rendered + NCC-scored per second.
+
+Workload (the driving-scale relocalisation case): a 1,000,000-Gaussian
+street-corridor map, cropped on the host to the 10 m voxel cells within 50 m
+of the prior (500,143 Gaussians), 64 candidate poses at 1408x376, full-
+resolution NCC against the query, top-1 selection. One step = one pass of the
+whole hot path on device-resident inputs: pack the submap from the map
+(gather by the crop index), preprocess + tile keys + per-tile sort + blend for
+all 64 poses, NCC of the 64 renders, top-1. The crop itself is host code run
+once per query and is not timed.
+
+Prints one JSON line (rank 0). See --help for flags.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+FP32_VECTOR_PEAK = 157.3     # TFLOP/s, MI355X published fp32 vector (packed FMA)
+FLOPS_PER_CONTRIB = 25       # flops of one (pixel, Gaussian) contribution, Eq. 1, 2, 5
+BLEND_SRC = os.path.join(ROOT, "paper_2403_11367_amd", "csrc", "blend.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blend_config1_traffic.md")
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _blend_traffic():
+    """HBM bytes per blend launch from the committed rocprofv3 counter summary,
+    if it was taken on the current blend source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m_h = re.search(r"blend_source_sha256:\s*([0-9a-f]{64})", txt)
+    if not (m_b and m_h):
+        return None
+    cur = hashlib.sha256(open(BLEND_SRC, "rb").read()).hexdigest()
+    return float(m_b.group(1)) if m_h.group(1) == cur else None
+
+
+def cpu_baseline(scene, sub_idx, n_cand):
+    """The oracle, untouched, on a bounded sample: n_cand full-frame candidates,
+    single thread (BLAS pools limited to 1)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ncc as oncc
+    from oracle import search
+
+    sub = scene.gaussians.take(sub_idx)
+    query = (0.5 + scene.query_noise).astype(np.float32)  # synthetic stand-in query
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        prep = search.prepare(sub)
+        renders = []
+        for p in range(n_cand):
+            renders.append(search.render_pose(prep, scene.poses[p], scene.camera).rgb)
+        oncc.ncc(query, np.stack(renders))
+        dt = time.perf_counter() - t0
+    return {"value": n_cand / dt, "unit": "candidates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_cand} of the 64 full-frame candidates of the same workload (pack + project + "
+                      f"keys + sort + float64 blend + NCC), {dt:.1f} s, 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-candidates", type=int, default=2, help="oracle sample size (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy before the timed loop (for rocprofv3 counter scaling)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (the path shards by candidate pose, "
+              "see DESIGN.md); run with --gpus 1", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2403_11367_amd import Camera, Context, crop, default_cfg
+    from paper_2403_11367_amd.gsr import RENDER_COUNT_EVALS
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    t_setup = time.perf_counter()
+    sc = W.config1()
+    idx = crop(sc.gaussians.means, sc.crop_cell, sc.prior_center[:2], sc.crop_radius)
+    P = sc.poses.shape[0]
+    cam = Camera(sc.camera.width, sc.camera.height, sc.camera.fx, sc.camera.fy, sc.camera.cx, sc.camera.cy)
+    H, Wd = cam.height, cam.width
+    ctx = Context(0)
+    gmap = [torch.as_tensor(a, device=dev) for a in sc.gaussians.arrays()]
+    idx_t = torch.as_tensor(idx, device=dev)
+    poses_t = torch.as_tensor(sc.poses, device=dev)
+    # query: render of the full (uncropped) map at the hidden pose + N(0, 0.02) noise
+    full = ctx.load_submap(*gmap)
+    q_rgb, _ = ctx.render(full, cam, torch.as_tensor(sc.hidden_pose[None], device=dev))
+    query = (q_rgb[0] + torch.as_tensor(sc.query_noise, device=dev)).contiguous()
+    full.free()
+    _log(f"setup: crop {idx.size} of {sc.gaussians.n} Gaussians, {P} poses, {Wd}x{H}")
+
+    # one counting render (untimed): exact pair total and evaluation counts of this workload
+    sm = ctx.load_submap(*gmap, index=idx_t)
+    ctx.render(sm, cam, poses_t, default_cfg(flags=RENDER_COUNT_EVALS))
+    st0 = ctx.stats()
+    n_pairs, n_vis = st0["n_pairs"], st0["n_visible"]
+    cfg = default_cfg(pair_capacity=int(n_pairs * 1.05) + 4096)  # fixed capacity: no host wait per step
+    rgb = torch.empty((P, 3, H, Wd), dtype=torch.float32, device=dev)
+    depth = torch.empty((P, H, Wd), dtype=torch.float32, device=dev)
+    scores = torch.empty((P,), dtype=torch.float32, device=dev)
+    best = torch.empty((1,), dtype=torch.int32, device=dev)
+
+    def step():
+        nonlocal sm
+        sm = ctx.load_submap(*gmap, index=idx_t, into=sm)           # S0
+        ctx.render(sm, cam, poses_t, cfg, rgb=rgb, depth=depth)     # S1-S5
+        ctx.ncc(query, rgb, scores)                                  # S6
+        ctx.topk(scores, 1, out=best)                                # S7
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.sync()
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    _log(f"setup done in {time.perf_counter() - t_setup:.1f} s; pairs {n_pairs}, visible {n_vis}")
+
+    ctx.set_profiling(True)
+    ctx.stats()  # reset the profiled-call window
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = ctx.stats()
+    ctx.set_profiling(False)
+    ctx.sync()  # raises on overflow: the timed images would be invalid
+    elapsed = t1 - t0
+    ms_step = elapsed / args.steps * 1e3
+    cand_s = P * args.steps / elapsed
+    best_i = int(best.cpu()[0])
+    _log(f"timed: {args.steps} steps in {elapsed * 1e3:.1f} ms; stage means (ms): preprocess "
+         f"{st['ms_preprocess']:.3f} sort {st['ms_sort']:.3f} blend {st['ms_blend']:.3f} ncc {st['ms_ncc']:.3f}; "
+         f"best candidate {best_i}")
+
+    # roofline of the dominant kernel (blend): algorithmic flops / mean duration
+    e_contrib, e_lanes = st0["evals_contrib"], st0["evals_lanes"]
+    blend_s = st["ms_blend"] * 1e-3
+    achieved = e_contrib * FLOPS_PER_CONTRIB / blend_s / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_VECTOR_PEAK, 4), "traffic": _blend_traffic(),
+            "kernel": "k_blend", "ms_per_launch": round(st["ms_blend"], 4),
+            "flops_per_launch": e_contrib * FLOPS_PER_CONTRIB, "evals_contrib": e_contrib,
+            "evals_lane_slots": e_lanes}
+    # end to end against HBM with the algorithmic bytes of the whole path
+    n_c, px = int(idx.size), H * Wd
+    bytes_step = 52 * n_c + 60 * n_vis + 88 * n_pairs + 28 * px * P
+    e2e_gbs = bytes_step / (ms_step * 1e-3) / 1e9
+
+    out = {
+        "metric": "candidate poses rendered+NCC-scored/sec @1408x376,1M Gaussians; learned vs plain",
+        "value": round(cand_s, 2), "unit": "candidates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "config1: 1M-Gaussian street-corridor map, 10 m voxel / 50 m crop "
+                               f"({n_c} Gaussians), {P} candidate poses, {Wd}x{H}, full-res NCC, top-1",
+                   "global_batch": P, "parallelism": "single GPU",
+                   "path": "plain: every candidate rendered at full resolution and NCC-scored"},
+        "pixels_per_s": round(cand_s * px, 1),
+        "roofline": roof,
+        "e2e_hbm": {"bytes_per_step": bytes_step, "achieved_GBs": round(e2e_gbs, 1), "peak_GBs": HBM_PEAK_GBS,
+                    "frac": round(e2e_gbs / HBM_PEAK_GBS, 4)},
+        "stages_ms": {k: round(st[k], 4) for k in ("ms_preprocess", "ms_sort", "ms_blend", "ms_ncc")},
+        "counts": {"n_submap": n_c, "n_visible": n_vis, "n_pairs": n_pairs, "best_candidate": best_i},
+    }
+    if args.cpu_candidates > 0:
+        _log(f"cpu baseline: oracle on {args.cpu_candidates} candidates ...")
+        out["cpu_baseline"] = cpu_baseline(sc, idx, args.cpu_candidates)
+    print(json.dumps(out), flush=True)
+    sm.free()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

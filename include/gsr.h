@@ -1,0 +1,221 @@
+/*
+ * gsr.h - C ABI of the MI355X (gfx950) render + NCC hot path of 3DGS-ReLoc
+ * (arXiv 2403.11367): render RGB and depth of a cropped 3D Gaussian submap for
+ * many candidate camera poses, then score every render against the query image
+ * by normalised cross-correlation, on one GPU.
+ *
+ * Paper passages each call follows:
+ *   gsr_submap_load  Sec. III-A (Gaussian parameters mu, S, R = q2R(q), colour,
+ *                    opacity; Sigma = R S S^T R^T) and Sec. III-B2 (RGB colour,
+ *                    no spherical harmonics; submaps cut from a voxel map).
+ *   gsr_render       Sec. III-A, Eq. 1-5: transform by the world-to-camera pose
+ *                    W_t, EWA screen covariance (Eq. 3) with the Jacobian of the
+ *                    projection (Eq. 4), depth sort, front-to-back compositing of
+ *                    colour (Eq. 1) with footprint (Eq. 2) and of depth (Eq. 5).
+ *   gsr_ncc          Sec. III-C1, Eq. 10: zero-mean normalised cross-correlation
+ *                    between the query and each render.
+ *   gsr_topk         Sec. III-C1: the brute-force search keeps the most similar
+ *                    render(s).
+ *   gsr_crop         Sec. III-B2 / III-C1: 2D voxel grid with a hash per cell and
+ *                    a KD-tree over cell centres answering a radius query around
+ *                    the prior pose (host code; not on the timed path).
+ *
+ * Conventions (readings of points the paper leaves open):
+ *   - pose = world-to-camera [R | t], 3x4 row-major float32; OpenCV camera axes
+ *     (x right, y down, z forward); pixel (i, j) is sampled at (i+0.5, j+0.5).
+ *   - Eq. 2 footprint q = o * exp(-d^2/2) (normalisation factor read as 1);
+ *     screen covariance dilated by eps on the diagonal; a pair contributes only
+ *     where d^2 <= cutoff_d2, alpha = min(alpha_max, q) >= alpha_min; a pixel
+ *     stops after the layer that takes its transmittance below t_min (that layer
+ *     counts). Background 0. Depth is camera-space z of the mean, not divided
+ *     by coverage. Near plane: cull unless t_z > z_near.
+ *   - Grey for NCC = 0.299 R + 0.587 G + 0.114 B; NCC = 0 if either image has
+ *     zero variance.
+ *
+ * Memory and ownership: every pointer argument named *_dev is device memory
+ * owned by the caller (e.g. a torch tensor's data_ptr()); *_host is host
+ * memory owned by the caller. The library owns the context, the submap copy
+ * and its workspace. All calls enqueue on the context's stream and return
+ * without waiting for the device, except where noted. Argument errors are
+ * returned at once; device-side conditions (pair-buffer overflow, bad submap
+ * index) are raised as flags and reported by gsr_sync / gsr_get_stats.
+ *
+ * Threading: a context belongs to one host thread at a time. Calls on two
+ * contexts may run concurrently.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes: 0 = success, negative = error. */
+#define GSR_OK 0
+#define GSR_EINVAL (-1)       /* bad argument (null pointer, size, layout) */
+#define GSR_ENOMEM (-2)       /* device or host allocation failed */
+#define GSR_EHIP (-3)         /* a HIP runtime call failed; see gsr_last_error */
+#define GSR_ENODEV (-4)       /* no usable GPU / bad device ordinal */
+#define GSR_EOVERFLOW (-5)    /* fixed pair capacity exceeded in a render */
+#define GSR_EUNSUPPORTED (-6) /* valid request this build does not implement */
+#define GSR_EDEVICE (-7)      /* device-side check failed (e.g. index out of range) */
+
+typedef struct gsr_ctx gsr_ctx;
+typedef struct gsr_submap gsr_submap;
+
+/* Pinhole intrinsics K (Sec. III-A): image width x height in pixels, focal
+ * lengths and principal point in pixels. 1 <= width, height <= 32768. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+} gsr_camera;
+
+/* Render constants. gsr_default_cfg fills the defaults given in brackets. */
+typedef struct {
+    int32_t tile_w, tile_h;  /* screen tile in pixels [16, 16]; this build: 16 x 16 */
+    float eps_dilate;        /* screen-covariance dilation, px^2 [0.3] */
+    float z_near;            /* near plane, metres; cull unless t_z > z_near [0.2] */
+    float jac_clamp;         /* Jacobian point clamp, x of half field of view [1.3] */
+    float cutoff_d2;         /* footprint support d^2 <= cutoff_d2 [9] */
+    float alpha_min;         /* skip layers with alpha < alpha_min [float32(1/255)] */
+    float alpha_max;         /* alpha = min(alpha_max, q) [0.99] */
+    float t_min;             /* stop after transmittance drops below t_min [1e-4] */
+    int32_t flags;           /* GSR_RENDER_* bits [0] */
+    int64_t pair_capacity;   /* (Gaussian, tile) pair buffer: 0 = size exactly, with one
+                              * host wait per gsr_render for the pair count; > 0 = fixed
+                              * capacity, no host wait; an overflow leaves the images
+                              * undefined and is reported by gsr_sync as GSR_EOVERFLOW */
+} gsr_render_cfg;
+
+/* gsr_render_cfg.flags: count compositing work into gsr_stats (evals_*), for
+ * measurement; a slower kernel variant, same images. */
+#define GSR_RENDER_COUNT_EVALS 1
+
+/* Counters of the most recent gsr_render / gsr_ncc on the context. */
+typedef struct {
+    int64_t n_submap;        /* Gaussians in the rendered submap */
+    int64_t n_poses;         /* poses of the last render */
+    int64_t n_visible;       /* (pose, Gaussian) records that survived culling */
+    int64_t n_pairs;         /* (pose, Gaussian, tile) pairs */
+    int64_t pair_capacity;   /* pair buffer size used */
+    int64_t n_long_tiles;    /* tiles whose list exceeded the in-LDS sort size */
+    int64_t evals_contrib;   /* with GSR_RENDER_COUNT_EVALS: (pixel, Gaussian) pairs that
+                              * contributed to a pixel before it stopped */
+    int64_t evals_lanes;     /* with GSR_RENDER_COUNT_EVALS: lane slots spent on evaluations */
+    int32_t overflow;        /* 1 if the pair buffer overflowed */
+    int32_t bad_index;       /* 1 if gsr_submap_load saw an index out of range */
+    /* Stage times from HIP events on the context's stream, when profiling is on:
+     * mean per call over the calls profiled since the previous gsr_get_stats. */
+    int32_t n_profiled_renders;
+    int32_t n_profiled_ncc;
+    float ms_preprocess;     /* counter reset + preprocess + tile histogram */
+    float ms_sort;           /* scan + pair scatter + per-tile sort */
+    float ms_blend;          /* compositing kernel */
+    float ms_ncc;            /* whole gsr_ncc */
+} gsr_stats;
+
+/* Create a context on GPU `device`, enqueueing on `hip_stream` (a hipStream_t;
+ * NULL = the null stream). Returns GSR_ENODEV if the device is absent. */
+int gsr_create(gsr_ctx **out, int device, void *hip_stream);
+/* Waits for the context's stream, then frees the context and its workspace.
+ * Submaps must be freed first. */
+int gsr_destroy(gsr_ctx *ctx);
+/* Switch the stream later calls enqueue on. */
+int gsr_set_stream(gsr_ctx *ctx, void *hip_stream);
+/* 1 = record HIP events around the stages of gsr_render / gsr_ncc. */
+int gsr_set_profiling(gsr_ctx *ctx, int on);
+/* Fill `out` with the default constants (see gsr_render_cfg). */
+int gsr_default_cfg(gsr_render_cfg *out);
+
+/* Pack a submap on the device (Sec. III-A): for i in [0, n_sel), Gaussian
+ * src = index_dev ? index_dev[i] : i of the caller's map is normalised
+ * (quaternion), turned into Sigma = R diag(s)^2 R^T and stored with its mean,
+ * opacity and colour in a library-owned record.
+ *   n_map                  Gaussians in the caller's arrays
+ *   means_dev   [n_map,3]  float32 world positions
+ *   scales_dev  [n_map,3]  float32 linear scales (> 0)
+ *   quats_dev   [n_map,4]  float32 rotation quaternions (w, x, y, z), any nonzero norm
+ *   opacity_dev [n_map]    float32 opacities in (0, 1] (post-sigmoid)
+ *   rgb_dev     [n_map,3]  float32 colours
+ *   index_dev   [n_sel]    int64 indices into the map, or NULL (then n_sel == n_map);
+ *                          the index order is the submap order (ties in depth sort by
+ *                          submap position). Out-of-range entries raise bad_index.
+ * If *out is a submap of this context with capacity >= n_sel it is refilled in
+ * place without allocating; otherwise a new submap is allocated and *out set.
+ * The inputs are only read by work enqueued here: the caller may free them
+ * once the stream has passed this call. */
+int gsr_submap_load(gsr_ctx *ctx, int64_t n_map, const float *means_dev, const float *scales_dev,
+                    const float *quats_dev, const float *opacity_dev, const float *rgb_dev,
+                    const int64_t *index_dev, int64_t n_sel, gsr_submap **out);
+int gsr_submap_free(gsr_submap *sm);
+int64_t gsr_submap_size(const gsr_submap *sm);
+
+/* Render the submap at P poses (Sec. III-A, Eq. 1-5).
+ *   poses_dev  [P,3,4]  float32 world-to-camera [R | t], device memory
+ *   rgb_dev    [P,3,H,W] float32 output, planar colour
+ *   depth_dev  [P,H,W]   float32 output, Eq. 5 depth
+ *   tfinal_dev [P,H,W]   float32 output, final transmittance, or NULL
+ * cfg may be NULL (defaults). 1 <= P <= 65535. */
+int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const float *poses_dev,
+               int32_t n_poses, const gsr_render_cfg *cfg, float *rgb_dev, float *depth_dev,
+               float *tfinal_dev);
+
+/* NCC (Eq. 10) of the query against each of P renders, on grey images.
+ *   query_dev   [3,H,W]   float32 planar RGB
+ *   renders_dev [P,3,H,W] float32 planar RGB
+ *   scores_dev  [P]       float32 output in [-1, 1] */
+int gsr_ncc(gsr_ctx *ctx, const float *query_dev, const float *renders_dev, int32_t n_poses,
+            int32_t height, int32_t width, float *scores_dev);
+
+/* Indices of the k best scores, best first; ties go to the lower index
+ * (Sec. III-C1 keeps the most similar render). 1 <= k <= P <= 8192.
+ *   scores_dev [P] float32, idx_dev [k] int32 output. */
+int gsr_topk(gsr_ctx *ctx, const float *scores_dev, int32_t n_poses, int32_t k, int32_t *idx_dev);
+
+/* Wait for the context's stream. Returns GSR_EOVERFLOW / GSR_EDEVICE if a
+ * device-side flag was raised since the last gsr_sync (and clears it). */
+int gsr_sync(gsr_ctx *ctx);
+/* Wait for the stream and read the counters of the last render / ncc, and the
+ * mean stage times of the calls profiled since the previous call. */
+int gsr_get_stats(gsr_ctx *ctx, gsr_stats *out);
+
+/* Introspection of the last gsr_render for tests (waits for the stream, then
+ * copies a library buffer to host memory `dst_host` of `bytes` bytes, which
+ * must equal the size reported by gsr_debug_size). Buffers:
+ *   GSR_BUF_RECORDS    [P][N][12] float32 screen records: u, v, conic A, B,
+ *                      C, opacity, r, g, b, z, rect_x = i0 | i1 << 16,
+ *                      rect_y = j0 | j1 << 16 (the last two as uint32 bits);
+ *                      valid where the tile count is nonzero
+ *   GSR_BUF_NTILES     [P][N] uint32 tiles touched (0 = culled)
+ *   GSR_BUF_OFFSETS    [P*T + 1] uint64 start of each (pose, tile) list; the last
+ *                      entry is the pair total
+ *   GSR_BUF_PAIRS      [n_pairs] uint64 sorted (depth bits << 32 | submap index)
+ */
+#define GSR_BUF_RECORDS 0
+#define GSR_BUF_NTILES 1
+#define GSR_BUF_OFFSETS 2
+#define GSR_BUF_PAIRS 3
+int gsr_debug_size(gsr_ctx *ctx, int which, int64_t *bytes);
+int gsr_debug_copy(gsr_ctx *ctx, int which, void *dst_host, int64_t bytes);
+
+/* Submap retrieval on the host (Sec. III-B2, III-C1): Gaussians are binned in
+ * a 2D grid of `cell`-metre cells keyed by (floor(x/cell), floor(y/cell)) in a
+ * hash map; a KD-tree over the occupied cell centres returns the cells whose
+ * centre lies within `radius` of (px, py); their Gaussians' indices are written
+ * to idx_host in ascending order.
+ *   means_host [n,3] float32; idx_host [cap] int64 output; *n_out = count
+ *   (GSR_EINVAL with *n_out set if cap is too small). Synchronous, no GPU. */
+int gsr_crop(const float *means_host, int64_t n, double cell, double px, double py, double radius,
+             int64_t *idx_host, int64_t cap, int64_t *n_out);
+
+const char *gsr_status_string(int status);
+/* Message of the last error on this context (empty if none). */
+const char *gsr_last_error(gsr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H */

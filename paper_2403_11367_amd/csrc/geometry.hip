@@ -1,0 +1,243 @@
+// Submap packing, EWA preprocessing and (Gaussian, tile) pair scatter.
+//
+// Built with -ffp-contract=off and correctly rounded float32 division and
+// square root, so that every record and depth key is a deterministic function
+// of the float32 inputs with the operation order written below (each
+// parenthesised sum is evaluated as written; no fused multiply-add).
+//
+// Paper: Sec. III-A. A Gaussian has mean mu, covariance Sigma = R S S^T R^T with
+// S = diag(s) and R = q2R(q), q = (w, x, y, z), colour c and opacity o. For a
+// camera with intrinsics K and world-to-camera pose W_t it is moved to camera
+// space, projected by m(mu) = K (W mu / (W mu)_z) (Eq. 4) and given the screen
+// covariance J W Sigma W^T J^T (Eq. 3, top-left 2x2), with J the Jacobian of m.
+#include "internal.h"
+
+namespace gsr {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPosesPerThread = 8;
+
+// S0: q normalised, R = q2R(q), M = R diag(s), Sigma = M M^T (6 unique entries).
+__global__ __launch_bounds__(kThreads) void k_pack(int64_t n_map, const float *__restrict__ means,
+                                                   const float *__restrict__ scales,
+                                                   const float *__restrict__ quats,
+                                                   const float *__restrict__ opacity,
+                                                   const float *__restrict__ rgb,
+                                                   const int64_t *__restrict__ index, int64_t n_sel,
+                                                   float4 *__restrict__ packed, int *__restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n_sel) return;
+    const int64_t src = index ? index[i] : i;
+    float4 *out = packed + i * kPackedQuads;
+    if (src < 0 || src >= n_map) {
+        // an invalid entry becomes a Gaussian that every pose culls (NaN depth)
+        const float nan = __builtin_nanf("");
+        out[0] = make_float4(nan, nan, nan, 0.f);
+        out[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        out[3] = make_float4(0.f, 0.f, 0.f, 0.f);
+        atomicOr(&flags[FLAG_BAD_INDEX], 1);
+        return;
+    }
+    float w = quats[src * 4 + 0], x = quats[src * 4 + 1], y = quats[src * 4 + 2], z = quats[src * 4 + 3];
+    const float n = sqrtf(((w * w + x * x) + y * y) + z * z);
+    w = w / n;
+    x = x / n;
+    y = y / n;
+    z = z / n;
+    const float r00 = 1.0f - 2.0f * (y * y + z * z);
+    const float r01 = 2.0f * (x * y - w * z);
+    const float r02 = 2.0f * (x * z + w * y);
+    const float r10 = 2.0f * (x * y + w * z);
+    const float r11 = 1.0f - 2.0f * (x * x + z * z);
+    const float r12 = 2.0f * (y * z - w * x);
+    const float r20 = 2.0f * (x * z - w * y);
+    const float r21 = 2.0f * (y * z + w * x);
+    const float r22 = 1.0f - 2.0f * (x * x + y * y);
+    const float sx = scales[src * 3 + 0], sy = scales[src * 3 + 1], sz = scales[src * 3 + 2];
+    const float m00 = r00 * sx, m01 = r01 * sy, m02 = r02 * sz;
+    const float m10 = r10 * sx, m11 = r11 * sy, m12 = r12 * sz;
+    const float m20 = r20 * sx, m21 = r21 * sy, m22 = r22 * sz;
+    const float s00 = (m00 * m00 + m01 * m01) + m02 * m02;
+    const float s01 = (m00 * m10 + m01 * m11) + m02 * m12;
+    const float s02 = (m00 * m20 + m01 * m21) + m02 * m22;
+    const float s11 = (m10 * m10 + m11 * m11) + m12 * m12;
+    const float s12 = (m10 * m20 + m11 * m21) + m12 * m22;
+    const float s22 = (m20 * m20 + m21 * m21) + m22 * m22;
+    out[0] = make_float4(means[src * 3 + 0], means[src * 3 + 1], means[src * 3 + 2], opacity[src]);
+    out[1] = make_float4(s00, s01, s02, s11);
+    out[2] = make_float4(s12, s22, rgb[src * 3 + 0], rgb[src * 3 + 1]);
+    out[3] = make_float4(rgb[src * 3 + 2], 0.f, 0.f, 0.f);
+}
+
+// S1 + tile histogram. One thread per Gaussian, looping over a chunk of poses
+// (blockIdx.y), so the packed record is read once per chunk. For each pose the
+// screen record is written, the number of tiles its 3-sigma rectangle touches
+// is stored (0 = culled), and every touched (pose, tile) counter is incremented.
+__global__ __launch_bounds__(kThreads) void k_preprocess(
+    const float4 *__restrict__ packed, int64_t n, const float *__restrict__ poses, int n_poses, Camera cam,
+    Consts k, TileGrid tg, float4 *__restrict__ records, uint32_t *__restrict__ ntiles,
+    uint32_t *__restrict__ tile_count, unsigned long long *__restrict__ counters) {
+    __shared__ unsigned s_vis;
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int p0 = blockIdx.y * kPosesPerThread;
+    const int p1 = min(p0 + kPosesPerThread, n_poses);
+    const bool in = g < n;
+    if (threadIdx.x == 0) s_vis = 0;
+    __syncthreads();
+    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0, q3 = q0;
+    if (in) {
+        const float4 *src = packed + g * kPackedQuads;
+        q0 = src[0];
+        q1 = src[1];
+        q2 = src[2];
+        q3 = src[3];
+    }
+    const float mx = q0.x, my = q0.y, mz = q0.z;
+    const float s00 = q1.x, s01 = q1.y, s02 = q1.z, s11 = q1.w, s12 = q2.x, s22 = q2.y;
+    // Jacobian clamp limits: 1.3 x tan(half field of view)
+    const float lim_x = k.jac_clamp * ((0.5f * (float)cam.width) / cam.fx);
+    const float lim_y = k.jac_clamp * ((0.5f * (float)cam.height) / cam.fy);
+    const float wmax = (float)(cam.width - 1), hmax = (float)(cam.height - 1);
+    unsigned vis_count = 0;
+    for (int p = p0; p < p1; ++p) {
+        const float *P = poses + p * 12;  // [R | t] row-major, uniform across the block
+        const float R00 = P[0], R01 = P[1], R02 = P[2], T0 = P[3];
+        const float R10 = P[4], R11 = P[5], R12 = P[6], T1 = P[7];
+        const float R20 = P[8], R21 = P[9], R22 = P[10], T2 = P[11];
+        uint32_t nt = 0;
+        if (in) {
+            const float tx = ((R00 * mx + R01 * my) + R02 * mz) + T0;
+            const float ty = ((R10 * mx + R11 * my) + R12 * mz) + T1;
+            const float tz = ((R20 * mx + R21 * my) + R22 * mz) + T2;
+            if (tz > k.z_near) {
+                const float xt = tx / tz, yt = ty / tz;
+                const float xc = fminf(fmaxf(xt, -lim_x), lim_x);
+                const float yc = fminf(fmaxf(yt, -lim_y), lim_y);
+                const float j00 = cam.fx / tz;
+                const float j02 = -(cam.fx * xc) / tz;
+                const float j11 = cam.fy / tz;
+                const float j12 = -(cam.fy * yc) / tz;
+                // T = J R_w (2x3)
+                const float t00 = j00 * R00 + j02 * R20, t01 = j00 * R01 + j02 * R21, t02 = j00 * R02 + j02 * R22;
+                const float t10 = j11 * R10 + j12 * R20, t11 = j11 * R11 + j12 * R21, t12 = j11 * R12 + j12 * R22;
+                // U = T Sigma (2x3)
+                const float u00 = (t00 * s00 + t01 * s01) + t02 * s02;
+                const float u01 = (t00 * s01 + t01 * s11) + t02 * s12;
+                const float u02 = (t00 * s02 + t01 * s12) + t02 * s22;
+                const float u10 = (t10 * s00 + t11 * s01) + t12 * s02;
+                const float u11 = (t10 * s01 + t11 * s11) + t12 * s12;
+                const float u12 = (t10 * s02 + t11 * s12) + t12 * s22;
+                const float a = ((u00 * t00 + u01 * t01) + u02 * t02) + k.eps;
+                const float b = (u00 * t10 + u01 * t11) + u02 * t12;
+                const float c = ((u10 * t10 + u11 * t11) + u12 * t12) + k.eps;
+                const float det = a * c - b * b;
+                if (det > 0.f) {
+                    const float ca = c / det, cb = (-b) / det, cc = a / det;
+                    const float rx = 3.0f * sqrtf(a), ry = 3.0f * sqrtf(c);
+                    const float u = cam.fx * xt + cam.cx;
+                    const float v = cam.fy * yt + cam.cy;
+                    const bool fin = __builtin_isfinite(u) && __builtin_isfinite(v) && __builtin_isfinite(rx) &&
+                                     __builtin_isfinite(ry) && __builtin_isfinite(ca) &&
+                                     __builtin_isfinite(cb) && __builtin_isfinite(cc);
+                    if (fin) {
+                        const float i0f = fmaxf(ceilf((u - rx) - 0.5f), 0.f);
+                        const float i1f = fminf(floorf((u + rx) - 0.5f), wmax);
+                        const float j0f = fmaxf(ceilf((v - ry) - 0.5f), 0.f);
+                        const float j1f = fminf(floorf((v + ry) - 0.5f), hmax);
+                        if (i0f <= i1f && j0f <= j1f) {
+                            const int i0 = (int)i0f, i1 = (int)i1f, j0 = (int)j0f, j1 = (int)j1f;
+                            const int tx0 = i0 >> tg.log2_w, tx1 = i1 >> tg.log2_w;
+                            const int ty0 = j0 >> tg.log2_h, ty1 = j1 >> tg.log2_h;
+                            nt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+                            float4 *r = records + ((int64_t)p * n + g) * kRecordQuads;
+                            r[0] = make_float4(u, v, ca, cb);
+                            r[1] = make_float4(cc, q0.w, q2.z, q2.w);
+                            r[2] = make_float4(q3.x, tz, __uint_as_float((uint32_t)i0 | ((uint32_t)i1 << 16)),
+                                               __uint_as_float((uint32_t)j0 | ((uint32_t)j1 << 16)));
+                            uint32_t *cnt = tile_count + (int64_t)p * tg.n_tiles;
+                            for (int yy = ty0; yy <= ty1; ++yy)
+                                for (int xx = tx0; xx <= tx1; ++xx) atomicAdd(&cnt[yy * tg.tiles_x + xx], 1u);
+                        }
+                    }
+                }
+            }
+            ntiles[(int64_t)p * n + g] = nt;
+        }
+        vis_count += (nt != 0);
+    }
+    // one counter update per block
+    if (vis_count) atomicAdd(&s_vis, vis_count);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_vis) atomicAdd(&counters[CNT_VISIBLE], (unsigned long long)s_vis);
+}
+
+// S2: every (pose, Gaussian, tile) pair takes a slot in its tile's list.
+// The slot order inside a list is arbitrary here; k_tile_sort then orders each
+// list by the 64-bit key (depth bits << 32 | submap index), which is unique.
+__global__ __launch_bounds__(kThreads) void k_scatter(const float4 *__restrict__ records,
+                                                      const uint32_t *__restrict__ ntiles, int64_t n,
+                                                      int n_poses, TileGrid tg,
+                                                      const uint64_t *__restrict__ offsets,
+                                                      uint32_t *__restrict__ cursor, uint64_t *__restrict__ pairs,
+                                                      uint64_t capacity, int *__restrict__ flags) {
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g >= n) return;
+    const int p0 = blockIdx.y * kPosesPerThread;
+    const int p1 = min(p0 + kPosesPerThread, n_poses);
+    bool over = false;
+    for (int p = p0; p < p1; ++p) {
+        const int64_t rg = (int64_t)p * n + g;
+        if (ntiles[rg] == 0) continue;
+        const float4 q2 = records[rg * kRecordQuads + 2];
+        const uint64_t zbits = __float_as_uint(q2.y);
+        const uint32_t rxb = __float_as_uint(q2.z), ryb = __float_as_uint(q2.w);
+        const int tx0 = (int)(rxb & 0xffffu) >> tg.log2_w, tx1 = (int)(rxb >> 16) >> tg.log2_w;
+        const int ty0 = (int)(ryb & 0xffffu) >> tg.log2_h, ty1 = (int)(ryb >> 16) >> tg.log2_h;
+        const uint64_t key = (zbits << 32) | (uint64_t)(uint32_t)g;
+        const int64_t base = (int64_t)p * tg.n_tiles;
+        for (int yy = ty0; yy <= ty1; ++yy)
+            for (int xx = tx0; xx <= tx1; ++xx) {
+                const int64_t t = base + yy * tg.tiles_x + xx;
+                const uint64_t pos = offsets[t] + atomicAdd(&cursor[t], 1u);
+                if (pos < capacity)
+                    pairs[pos] = key;
+                else
+                    over = true;
+            }
+    }
+    if (over) atomicOr(&flags[FLAG_OVERFLOW], 1);
+}
+
+}  // namespace
+
+void launch_pack(hipStream_t s, int64_t n_map, const float *means, const float *scales, const float *quats,
+                 const float *opacity, const float *rgb, const int64_t *index, int64_t n_sel, float4 *packed,
+                 int *flags) {
+    if (n_sel <= 0) return;
+    const unsigned blocks = (unsigned)((n_sel + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(kThreads), 0, s, n_map, means, scales, quats, opacity, rgb,
+                       index, n_sel, packed, flags);
+}
+
+void launch_preprocess(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
+                       const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
+                       uint32_t *ntiles, uint32_t *tile_count, unsigned long long *counters) {
+    if (n <= 0) return;
+    const dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)((n_poses + kPosesPerThread - 1) / kPosesPerThread));
+    hipLaunchKernelGGL(k_preprocess, grid, dim3(kThreads), 0, s, packed, n, poses, n_poses, cam, k, tg, records,
+                       ntiles, tile_count, counters);
+}
+
+void launch_scatter(hipStream_t s, const float4 *records, const uint32_t *ntiles, int64_t n, int n_poses,
+                    const TileGrid &tg, const uint64_t *offsets, uint32_t *cursor, uint64_t *pairs,
+                    uint64_t capacity, int *flags) {
+    if (n <= 0) return;
+    const dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)((n_poses + kPosesPerThread - 1) / kPosesPerThread));
+    hipLaunchKernelGGL(k_scatter, grid, dim3(kThreads), 0, s, records, ntiles, n, n_poses, tg, offsets, cursor,
+                       pairs, capacity, flags);
+}
+
+}  // namespace gsr

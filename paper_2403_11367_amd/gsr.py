@@ -1,0 +1,304 @@
+"""ctypes binding of libgsr (include/gsr.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module checks tensor
+devices, dtypes and shapes, passes ``data_ptr()`` and the current torch
+stream, and turns status codes into exceptions. PyTorch is used for device
+memory and streams only. If ``libgsr.so`` has not been built, importing this
+module raises ``ImportError``: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsr.so")
+
+GSR_OK = 0
+STATUS = {0: "GSR_OK", -1: "GSR_EINVAL", -2: "GSR_ENOMEM", -3: "GSR_EHIP", -4: "GSR_ENODEV",
+          -5: "GSR_EOVERFLOW", -6: "GSR_EUNSUPPORTED", -7: "GSR_EDEVICE"}
+BUF_RECORDS, BUF_NTILES, BUF_OFFSETS, BUF_PAIRS = 0, 1, 2, 3
+RENDER_COUNT_EVALS = 1
+
+# every symbol declared in include/gsr.h
+EXPORTS = [
+    "gsr_create", "gsr_destroy", "gsr_set_stream", "gsr_set_profiling", "gsr_default_cfg",
+    "gsr_submap_load", "gsr_submap_free", "gsr_submap_size", "gsr_render", "gsr_ncc", "gsr_topk",
+    "gsr_sync", "gsr_get_stats", "gsr_debug_size", "gsr_debug_copy", "gsr_crop",
+    "gsr_status_string", "gsr_last_error",
+]
+
+
+class GsrError(RuntimeError):
+    def __init__(self, status: int, message: str = ""):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+
+
+class CameraC(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class RenderCfg(C.Structure):
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("eps_dilate", C.c_float),
+                ("z_near", C.c_float), ("jac_clamp", C.c_float), ("cutoff_d2", C.c_float),
+                ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
+                ("flags", C.c_int32), ("pair_capacity", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_submap", C.c_int64), ("n_poses", C.c_int64), ("n_visible", C.c_int64),
+                ("n_pairs", C.c_int64), ("pair_capacity", C.c_int64), ("n_long_tiles", C.c_int64),
+                ("evals_contrib", C.c_int64), ("evals_lanes", C.c_int64),
+                ("overflow", C.c_int32), ("bad_index", C.c_int32),
+                ("n_profiled_renders", C.c_int32), ("n_profiled_ncc", C.c_int32),
+                ("ms_preprocess", C.c_float), ("ms_sort", C.c_float), ("ms_blend", C.c_float),
+                ("ms_ncc", C.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2403_11367_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, I, I32, I64, F, D = C.c_void_p, C.c_int, C.c_int32, C.c_int64, C.c_float, C.c_double
+    sig = {
+        "gsr_create": (I, [C.POINTER(P), I, P]),
+        "gsr_destroy": (I, [P]),
+        "gsr_set_stream": (I, [P, P]),
+        "gsr_set_profiling": (I, [P, I]),
+        "gsr_default_cfg": (I, [C.POINTER(RenderCfg)]),
+        "gsr_submap_load": (I, [P, I64, P, P, P, P, P, P, I64, C.POINTER(P)]),
+        "gsr_submap_free": (I, [P]),
+        "gsr_submap_size": (I64, [P]),
+        "gsr_render": (I, [P, P, C.POINTER(CameraC), P, I32, C.POINTER(RenderCfg), P, P, P]),
+        "gsr_ncc": (I, [P, P, P, I32, I32, I32, P]),
+        "gsr_topk": (I, [P, P, I32, I32, P]),
+        "gsr_sync": (I, [P]),
+        "gsr_get_stats": (I, [P, C.POINTER(Stats)]),
+        "gsr_debug_size": (I, [P, I, C.POINTER(I64)]),
+        "gsr_debug_copy": (I, [P, I, P, I64]),
+        "gsr_crop": (I, [P, I64, D, D, D, D, P, I64, C.POINTER(I64)]),
+        "gsr_status_string": (C.c_char_p, [I]),
+        "gsr_last_error": (C.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def default_cfg(**overrides) -> RenderCfg:
+    cfg = RenderCfg()
+    LIB.gsr_default_cfg(C.byref(cfg))
+    for k, v in overrides.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+def crop(means: np.ndarray, cell: float, center_xy: Sequence[float], radius: float) -> np.ndarray:
+    """Indices (ascending int64) of the Gaussians in voxel cells within `radius` of the prior."""
+    m = np.ascontiguousarray(means, dtype=np.float32)
+    n = m.shape[0]
+    out = np.empty(max(n, 1), dtype=np.int64)
+    cnt = C.c_int64(0)
+    rc = LIB.gsr_crop(m.ctypes.data, n, float(cell), float(center_xy[0]), float(center_xy[1]),
+                      float(radius), out.ctypes.data, out.size, C.byref(cnt))
+    if rc != GSR_OK:
+        raise GsrError(rc, "gsr_crop")
+    return out[: cnt.value].copy()
+
+
+@dataclasses.dataclass
+class Camera:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+
+    def c(self) -> CameraC:
+        return CameraC(self.width, self.height, self.fx, self.fy, self.cx, self.cy)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_f32(t, name, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+class Submap:
+    def __init__(self, ctx: "Context", handle: C.c_void_p):
+        self.ctx = ctx
+        self.handle = handle
+
+    @property
+    def n(self) -> int:
+        return int(LIB.gsr_submap_size(self.handle))
+
+    def free(self):
+        if self.handle:
+            LIB.gsr_submap_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """One GPU context; every call enqueues on the current torch stream of its device."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        self.device = int(device)
+        self.handle = C.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        rc = LIB.gsr_create(C.byref(self.handle), self.device, C.c_void_p(stream))
+        if rc != GSR_OK:
+            raise GsrError(rc, "gsr_create")
+
+    def _check(self, rc: int, what: str):
+        if rc != GSR_OK:
+            msg = LIB.gsr_last_error(self.handle)
+            raise GsrError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def _bind_stream(self):
+        s = _torch().cuda.current_stream(self.device).cuda_stream
+        self._check(LIB.gsr_set_stream(self.handle, C.c_void_p(s)), "gsr_set_stream")
+
+    def close(self):
+        if self.handle:
+            LIB.gsr_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_profiling(self, on: bool):
+        self._check(LIB.gsr_set_profiling(self.handle, int(bool(on))), "gsr_set_profiling")
+
+    def load_submap(self, means, scales, quats, opacity, rgb, index=None,
+                    into: Optional[Submap] = None) -> Submap:
+        torch = _torch()
+        n = means.shape[0]
+        _dev_f32(means, "means", (n, 3))
+        _dev_f32(scales, "scales", (n, 3))
+        _dev_f32(quats, "quats", (n, 4))
+        _dev_f32(opacity, "opacity", (n,))
+        _dev_f32(rgb, "rgb", (n, 3))
+        if index is not None:
+            if index.dtype != torch.int64 or index.device.type != "cuda" or index.dim() != 1 \
+                    or not index.is_contiguous():
+                raise TypeError("index must be a contiguous 1-D int64 CUDA tensor")
+            n_sel, iptr = index.shape[0], index.data_ptr()
+        else:
+            n_sel, iptr = n, None
+        self._bind_stream()
+        reuse = into is not None and bool(into.handle)
+        h = C.c_void_p(into.handle.value) if reuse else C.c_void_p()
+        rc = LIB.gsr_submap_load(self.handle, n, means.data_ptr(), scales.data_ptr(), quats.data_ptr(),
+                                 opacity.data_ptr(), rgb.data_ptr(), iptr, n_sel, C.byref(h))
+        self._check(rc, "gsr_submap_load")
+        if reuse and h.value == into.handle.value:
+            return into  # refilled in place
+        if reuse:
+            into.handle = None  # the library freed it when it allocated a larger one
+        return Submap(self, h)
+
+    def render(self, submap: Submap, camera: Camera, poses, cfg: Optional[RenderCfg] = None,
+               rgb=None, depth=None, tfinal=None, with_tfinal: bool = False):
+        torch = _torch()
+        P = poses.shape[0]
+        _dev_f32(poses, "poses", (P, 3, 4))
+        H, W = camera.height, camera.width
+        dev = poses.device
+        if rgb is None:
+            rgb = torch.empty((P, 3, H, W), dtype=torch.float32, device=dev)
+        if depth is None:
+            depth = torch.empty((P, H, W), dtype=torch.float32, device=dev)
+        if with_tfinal and tfinal is None:
+            tfinal = torch.empty((P, H, W), dtype=torch.float32, device=dev)
+        _dev_f32(rgb, "rgb", (P, 3, H, W))
+        _dev_f32(depth, "depth", (P, H, W))
+        if tfinal is not None:
+            _dev_f32(tfinal, "tfinal", (P, H, W))
+        self._bind_stream()
+        cam = camera.c()
+        rc = LIB.gsr_render(self.handle, submap.handle, C.byref(cam), poses.data_ptr(), P,
+                            C.byref(cfg) if cfg is not None else None, rgb.data_ptr(), depth.data_ptr(),
+                            tfinal.data_ptr() if tfinal is not None else None)
+        self._check(rc, "gsr_render")
+        return (rgb, depth, tfinal) if tfinal is not None else (rgb, depth)
+
+    def ncc(self, query, renders, scores=None):
+        torch = _torch()
+        P, _, H, W = renders.shape
+        _dev_f32(query, "query", (3, H, W))
+        _dev_f32(renders, "renders", (P, 3, H, W))
+        if scores is None:
+            scores = torch.empty((P,), dtype=torch.float32, device=renders.device)
+        _dev_f32(scores, "scores", (P,))
+        self._bind_stream()
+        self._check(LIB.gsr_ncc(self.handle, query.data_ptr(), renders.data_ptr(), P, H, W,
+                                scores.data_ptr()), "gsr_ncc")
+        return scores
+
+    def topk(self, scores, k: int = 1, out=None):
+        torch = _torch()
+        P = scores.shape[0]
+        _dev_f32(scores, "scores", (P,))
+        if out is None:
+            out = torch.empty((k,), dtype=torch.int32, device=scores.device)
+        if out.dtype != torch.int32 or out.shape != (k,) or out.device.type != "cuda":
+            raise TypeError("out must be an int32 CUDA tensor of shape (k,)")
+        self._bind_stream()
+        self._check(LIB.gsr_topk(self.handle, scores.data_ptr(), P, k, out.data_ptr()), "gsr_topk")
+        return out
+
+    def sync(self):
+        self._check(LIB.gsr_sync(self.handle), "gsr_sync")
+
+    def stats(self) -> dict:
+        st = Stats()
+        self._check(LIB.gsr_get_stats(self.handle, C.byref(st)), "gsr_get_stats")
+        return st.as_dict()
+
+    def debug_buffer(self, which: int) -> np.ndarray:
+        nb = C.c_int64(0)
+        self._check(LIB.gsr_debug_size(self.handle, which, C.byref(nb)), "gsr_debug_size")
+        dt = {BUF_RECORDS: np.float32, BUF_NTILES: np.uint32, BUF_OFFSETS: np.uint64,
+              BUF_PAIRS: np.uint64}[which]
+        out = np.empty(nb.value // np.dtype(dt).itemsize, dtype=dt)
+        if out.size:
+            self._check(LIB.gsr_debug_copy(self.handle, which, out.ctypes.data, nb.value), "gsr_debug_copy")
+        return out

@@ -1,0 +1,117 @@
+"""Shared helpers for the GPU parity tests: upload seeded scenes, run the HIP
+path through the C ABI, run the oracle on the same inputs, compare."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+from oracle import blend, gaussians, keys, project, search
+
+# parity bar (float32 render vs float64 oracle on identical float32 records)
+TOL_RGB = 1e-4       # abs, unflagged pixels
+TOL_DEPTH = 1e-4     # abs, unflagged pixels
+TOL_T = 1e-4         # abs, final transmittance
+TOL_NCC = 1e-4       # abs
+FLAG_RGB = 0.03      # abs bound on flagged pixels (one decision flips at its threshold)
+FLAG_FRAC = 0.01     # flagged pixels may be at most this fraction
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a, dev="cuda"):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device=dev)
+
+
+def camera(cam):
+    from paper_2403_11367_amd import Camera
+    return Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy)
+
+
+def load(ctx, g, index=None):
+    arrs = [to_dev(a.astype(np.float32)) for a in g.arrays()]
+    idx = None if index is None else to_dev(np.asarray(index, np.int64))
+    return ctx.load_submap(*arrs, index=idx)
+
+
+def gpu_render(ctx, sm, cam, poses, cfg=None):
+    import torch
+    rgb, dep, tf = ctx.render(sm, camera(cam), to_dev(poses.astype(np.float32)), cfg, with_tfinal=True)
+    torch.cuda.synchronize()
+    return rgb.cpu().numpy(), dep.cpu().numpy(), tf.cpu().numpy()
+
+
+def gpu_buffers(ctx):
+    from paper_2403_11367_amd import BUF_NTILES, BUF_OFFSETS, BUF_PAIRS, BUF_RECORDS
+    return (ctx.debug_buffer(BUF_RECORDS), ctx.debug_buffer(BUF_NTILES), ctx.debug_buffer(BUF_OFFSETS),
+            ctx.debug_buffer(BUF_PAIRS))
+
+
+def oracle_pose(prep, pose, cam, tile=(16, 16)):
+    """(Render, ScreenRecords, sorted keys, sorted values, ranges) for one pose."""
+    return search.render_pose(prep, pose, cam, tile, with_pairs=True)
+
+
+def check_records(rec_gpu, nt_gpu, rec, n, p):
+    """Bit-exact screen records and tile counts of pose p against the oracle."""
+    r = rec_gpu.reshape(-1, n, 12)[p]
+    nt = nt_gpu.reshape(-1, n)[p]
+    vis = nt > 0
+    assert np.array_equal(vis, rec.visible), f"visibility differs at {np.nonzero(vis != rec.visible)[0][:10]}"
+    v = rec.visible
+    for col, ref in ((0, rec.u), (1, rec.v), (2, rec.conic[:, 0]), (3, rec.conic[:, 1]), (4, rec.conic[:, 2]),
+                     (9, rec.z), (5, rec.opacity), (6, rec.rgb[:, 0]), (7, rec.rgb[:, 1]), (8, rec.rgb[:, 2])):
+        a = r[v, col].view(np.uint32)
+        b = ref[v].astype(np.float32).view(np.uint32)
+        bad = np.nonzero(a != b)[0]
+        assert bad.size == 0, f"record column {col} differs for {bad.size} Gaussians, first {np.nonzero(v)[0][bad[:5]]}"
+    rx = r[v, 10].view(np.uint32)
+    ry = r[v, 11].view(np.uint32)
+    got = np.stack([rx & 0xFFFF, rx >> 16, ry & 0xFFFF, ry >> 16], 1).astype(np.int64)
+    assert np.array_equal(got, rec.rect[v])
+    assert np.array_equal(nt[v].astype(np.int64), rec.n_tiles[v])
+
+
+def check_pairs(off_gpu, pairs_gpu, ks, vs, rng, p, n_tiles):
+    """Bit-exact keys and sorted order of pose p against the oracle's lexsort."""
+    lo, hi = int(off_gpu[p * n_tiles]), int(off_gpu[(p + 1) * n_tiles])
+    seg = pairs_gpu[lo:hi]
+    starts = off_gpu[p * n_tiles:(p + 1) * n_tiles].astype(np.int64) - lo
+    ends = off_gpu[p * n_tiles + 1:(p + 1) * n_tiles + 1].astype(np.int64) - lo
+    assert np.array_equal(starts, rng[:, 0]) and np.array_equal(ends, rng[:, 1]), "tile ranges differ"
+    tile_of = np.repeat(np.arange(n_tiles, dtype=np.uint64), (ends - starts))
+    gkeys = (tile_of << np.uint64(32)) | (seg >> np.uint64(32))
+    gvals = (seg & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    assert gkeys.size == ks.size
+    assert np.array_equal(gkeys, ks), "keys differ"
+    assert np.array_equal(gvals, vs), "sort order differs"
+
+
+def compare_render(rgb, dep, tf, ref, label="", tol_depth=TOL_DEPTH):
+    """GPU image vs oracle Render: tight on unflagged pixels, bounded on flagged ones."""
+    ok = ~ref.flag
+    e_rgb = np.abs(rgb - ref.rgb)
+    e_dep = np.abs(dep - ref.depth)
+    e_t = np.abs(tf - ref.t_final)
+    m_rgb = e_rgb[:, ok].max() if ok.any() else 0.0
+    m_dep = e_dep[ok].max() if ok.any() else 0.0
+    m_t = e_t[ok].max() if ok.any() else 0.0
+    say(f"  {label}: max|drgb| {m_rgb:.2e} max|ddepth| {m_dep:.2e} max|dT| {m_t:.2e} "
+        f"flagged {int((~ok).sum())}/{ok.size}")
+    assert m_rgb <= TOL_RGB, f"{label}: rgb error {m_rgb}"
+    assert m_dep <= tol_depth, f"{label}: depth error {m_dep}"
+    assert m_t <= TOL_T, f"{label}: T error {m_t}"
+    assert (~ok).mean() <= FLAG_FRAC
+    if (~ok).any():
+        assert e_rgb[:, ~ok].max() <= FLAG_RGB
+
+
+def prep(g):
+    return search.prepare(g)
+
+
+__all__ = ["blend", "gaussians", "keys", "project"]

@@ -1,0 +1,312 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: screen records, tile counts, keys and per-tile order bit-exact;
+renders within 1e-4 abs on pixels the oracle does not flag; NCC within 1e-4.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import (TOL_NCC, check_pairs, check_records, compare_render, gpu_buffers, gpu_render, load,
+                     oracle_pose, prep, say, to_dev)
+from oracle import crop as ocrop
+from oracle import ncc as oncc
+from oracle import search
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2403_11367_amd import Context
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _tiles(cam):
+    return ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+
+
+def test_config0_records_pairs_render(ctx):
+    say("config0: 4096 Gaussians, 16 poses, 128x96")
+    sc = W.config0()
+    sm = load(ctx, sc.gaussians)
+    rgb, dep, tf = gpu_render(ctx, sm, sc.camera, sc.poses)
+    recs, nts, offs, pairs = gpu_buffers(ctx)
+    pr = prep(sc.gaussians)
+    T = _tiles(sc.camera)
+    for p in range(sc.poses.shape[0]):
+        out, rec, ks, vs, rng = oracle_pose(pr, sc.poses[p], sc.camera)
+        check_records(recs, nts, rec, sc.gaussians.n, p)
+        check_pairs(offs, pairs, ks, vs, rng, p, T)
+        compare_render(rgb[p], dep[p], tf[p], out, f"pose {p}")
+
+
+@pytest.mark.parametrize("seed,n,w,h", [(21, 300, 64, 48), (22, 500, 37, 21), (23, 64, 16, 16),
+                                        (24, 1000, 200, 9), (25, 1, 33, 17)])
+def test_tiny_scenes_ragged_sizes(ctx, seed, n, w, h):
+    say(f"tiny scene seed {seed}: n {n}, {w}x{h}")
+    sc = W.tiny_scene(seed, n=n, width=w, height=h, n_poses=3)
+    sm = load(ctx, sc.gaussians)
+    rgb, dep, tf = gpu_render(ctx, sm, sc.camera, sc.poses)
+    recs, nts, offs, pairs = gpu_buffers(ctx)
+    pr = prep(sc.gaussians)
+    T = _tiles(sc.camera)
+    for p in range(3):
+        out, rec, ks, vs, rng = oracle_pose(pr, sc.poses[p], sc.camera)
+        check_records(recs, nts, rec, n, p)
+        check_pairs(offs, pairs, ks, vs, rng, p, T)
+        compare_render(rgb[p], dep[p], tf[p], out, f"pose {p}")
+
+
+def test_empty_and_all_culled(ctx):
+    say("empty submap and a scene entirely behind the camera")
+    sc = W.tiny_scene(30, n=50)
+    empty = W.Gaussians(*[a[:0] for a in sc.gaussians.arrays()])
+    sm = load(ctx, empty)
+    rgb, dep, tf = gpu_render(ctx, sm, sc.camera, sc.poses)
+    assert np.all(rgb == 0) and np.all(dep == 0) and np.all(tf == 1)
+    g = sc.gaussians
+    behind = W.Gaussians(g.means * np.array([1, -1, 1], np.float32), g.scales, g.quats, g.opacity, g.rgb)
+    sm2 = load(ctx, behind)
+    rgb, dep, tf = gpu_render(ctx, sm2, sc.camera, sc.poses)
+    assert np.all(rgb == 0) and np.all(dep == 0) and np.all(tf == 1)
+    assert ctx.stats()["n_visible"] == 0
+
+
+def test_nan_and_degenerate_inputs_are_culled(ctx):
+    say("NaN means, zero scales, zero quaternion")
+    sc = W.tiny_scene(31, n=200)
+    g = sc.gaussians
+    means = g.means.copy()
+    means[5] = np.nan
+    scales = g.scales.copy()
+    scales[7] = 0.0
+    quats = g.quats.copy()
+    quats[9] = 0.0
+    bad = W.Gaussians(means, scales, quats, g.opacity, g.rgb)
+    sm = load(ctx, bad)
+    rgb, dep, tf = gpu_render(ctx, sm, sc.camera, sc.poses)
+    recs, nts, offs, pairs = gpu_buffers(ctx)
+    pr = prep(bad)
+    for p in range(sc.poses.shape[0]):
+        out, rec, ks, vs, rng = oracle_pose(pr, sc.poses[p], sc.camera)
+        assert not rec.visible[5] and not rec.visible[9]
+        check_records(recs, nts, rec, g.n, p)
+        check_pairs(offs, pairs, ks, vs, rng, p, _tiles(sc.camera))
+        compare_render(rgb[p], dep[p], tf[p], out, f"pose {p}")
+
+
+def _stack_scene(n, spread, seed):
+    """n small Gaussians crowded over one 16x16 tile: a very long tile list."""
+    rng = np.random.default_rng(seed)
+    y = rng.uniform(3.0, 30.0, n)
+    x = rng.uniform(-spread, spread, n) * y
+    z = rng.uniform(-spread, spread, n) * y
+    means = np.stack([x, y, z], 1).astype(np.float32)
+    scales = np.full((n, 3), 0.002, np.float32) * y[:, None].astype(np.float32)
+    quats = rng.normal(size=(n, 4)).astype(np.float32)
+    op = np.full(n, 0.05, np.float32)  # low opacity: the pixel walks deep into the list
+    rgb = rng.uniform(0, 1, (n, 3)).astype(np.float32)
+    g = W.Gaussians(means, scales, quats, op, rgb)
+    cam = W.Camera(64, 48, 400.0, 400.0, 32.0, 24.0)
+    poses = W.yaw_grid_poses(np.zeros(3), W.AXES_ALONG_Y, [0.0], [0.0], [0.0])
+    return g, cam, poses
+
+
+@pytest.mark.parametrize("n,label", [(3500, "mid (LDS 64 KB)"), (12000, "long (global radix)")])
+def test_long_tile_lists(ctx, n, label):
+    say(f"long tile lists: {n} Gaussians over one tile -> {label} sort path")
+    g, cam, poses = _stack_scene(n, 0.01, 40 + n)
+    sm = load(ctx, g)
+    rgb, dep, tf = gpu_render(ctx, sm, cam, poses)
+    recs, nts, offs, pairs = gpu_buffers(ctx)
+    out, rec, ks, vs, rng = oracle_pose(prep(g), poses[0], cam)
+    lens = rng[:, 1] - rng[:, 0]
+    say(f"  longest list {lens.max()}, long tiles {ctx.stats()['n_long_tiles']}")
+    assert lens.max() > (8192 if n > 8192 else 2048)
+    check_records(recs, nts, rec, n, 0)
+    check_pairs(offs, pairs, ks, vs, rng, 0, _tiles(cam))
+    compare_render(rgb[0], dep[0], tf[0], out, "pose 0")
+
+
+def test_determinism_and_fixed_capacity(ctx):
+    say("config0 twice (exact sizing) and once with a fixed pair capacity")
+    from paper_2403_11367_amd import default_cfg
+    sc = W.config0()
+    sm = load(ctx, sc.gaussians)
+    a = gpu_render(ctx, sm, sc.camera, sc.poses)
+    b = gpu_render(ctx, sm, sc.camera, sc.poses)
+    n_pairs = ctx.stats()["n_pairs"]
+    c = gpu_render(ctx, sm, sc.camera, sc.poses, default_cfg(pair_capacity=n_pairs + 7))
+    ctx.sync()
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+def test_overflow_and_bad_index_are_reported(ctx):
+    say("forced pair overflow (capacity 1) and an out-of-range submap index")
+    from paper_2403_11367_amd import GsrError, default_cfg
+    sc = W.config0()
+    sm = load(ctx, sc.gaussians)
+    gpu_render(ctx, sm, sc.camera, sc.poses[:2], default_cfg(pair_capacity=1))
+    with pytest.raises(GsrError) as e:
+        ctx.sync()
+    assert e.value.status == -5
+    ctx.sync()  # flag cleared
+    good = gpu_render(ctx, sm, sc.camera, sc.poses[:2])
+    assert good[0].max() > 0
+    idx = np.arange(10, dtype=np.int64)
+    idx[3] = sc.gaussians.n + 5
+    load(ctx, sc.gaussians, index=idx)
+    with pytest.raises(GsrError) as e:
+        ctx.sync()
+    assert e.value.status == -7
+
+
+def test_argument_errors(ctx):
+    say("argument validation")
+    import torch
+    from paper_2403_11367_amd import GsrError, default_cfg
+    sc = W.tiny_scene(32, n=10)
+    sm = load(ctx, sc.gaussians)
+    with pytest.raises(GsrError) as e:
+        gpu_render(ctx, sm, sc.camera, sc.poses, default_cfg(tile_w=8, tile_h=8))
+    assert e.value.status == -6
+    with pytest.raises(GsrError):
+        gpu_render(ctx, sm, sc.camera, sc.poses, default_cfg(tile_w=12))
+    s = torch.zeros(4, device="cuda")
+    with pytest.raises(GsrError):
+        ctx.topk(s, 5)
+
+
+def test_ncc_matches_oracle_full_size(ctx):
+    """Full headline size: 64 renders at 1408x376, seeded synthetic images."""
+    say("NCC: 64 x 1408x376 seeded images")
+    import torch
+    imgs = W.random_images(7, 65, 376, 1408)
+    q = imgs[0]
+    r = imgs[1:].copy()
+    r[3] = 0.25  # constant render -> 0
+    r[5] = 2.0 * r[4] + 0.5  # affine copy -> same score as r[4]
+    got = ctx.ncc(to_dev(q), to_dev(r)).cpu().numpy()
+    ref = oncc.ncc(q, r)
+    err = np.abs(got - ref).max()
+    say(f"  max |dncc| {err:.2e}")
+    assert err <= TOL_NCC
+    assert got[3] == 0.0
+    assert abs(got[5] - got[4]) <= 2 * TOL_NCC
+    # ragged block and self-correlation
+    small = W.random_images(8, 3, 37, 53)
+    s = ctx.ncc(to_dev(small[0]), to_dev(small)).cpu().numpy()
+    assert abs(s[0] - 1.0) <= TOL_NCC
+    assert np.abs(s - oncc.ncc(small[0], small)).max() <= TOL_NCC
+    torch.cuda.synchronize()
+
+
+def test_topk_ties_and_order(ctx):
+    say("top-k with ties")
+    rng = np.random.default_rng(3)
+    for n in (1, 5, 64, 1000, 8192):
+        s = rng.integers(0, 20, n).astype(np.float32) / 7.0
+        k = min(n, 16)
+        got = ctx.topk(to_dev(s), k).cpu().numpy()
+        assert np.array_equal(got, search.topk(s, k))
+        assert int(ctx.topk(to_dev(s), 1).cpu().numpy()[0]) == search.argmax(s)
+
+
+def test_config0_end_to_end_search(ctx):
+    say("config0 end to end: render 16 candidates, NCC against the query, argmax")
+    sc = W.config0()
+    pr = prep(sc.gaussians)
+    q_ref = search.render_pose(pr, sc.hidden_pose, sc.camera)
+    query = (q_ref.rgb + sc.query_noise).astype(np.float32)
+    refs = [search.render_pose(pr, sc.poses[p], sc.camera) for p in range(16)]
+    ref_scores = oncc.ncc(query, np.stack([r.rgb for r in refs]))
+    sm = load(ctx, sc.gaussians)
+    import torch
+    rgb, dep = ctx.render(sm, __import__("helpers").camera(sc.camera), to_dev(sc.poses))
+    scores = ctx.ncc(to_dev(query), rgb)
+    best = ctx.topk(scores, 1)
+    torch.cuda.synchronize()
+    got = scores.cpu().numpy()
+    say(f"  scores max err {np.abs(got - ref_scores).max():.2e}; best {int(best.cpu()[0])} "
+        f"oracle {search.argmax(ref_scores)}")
+    assert np.abs(got - ref_scores).max() <= TOL_NCC
+    srt = np.sort(ref_scores)
+    if srt[-1] - srt[-2] > 2 * TOL_NCC:
+        assert int(best.cpu()[0]) == search.argmax(ref_scores)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    sc = W.config1()
+    idx = ocrop.crop_indices(sc.gaussians.means, sc.crop_cell, sc.prior_center[:2], sc.crop_radius)
+    return sc, idx
+
+
+def test_config1_full_size_sampled(ctx, cfg1):
+    """Headline shape: 500,143-Gaussian crop, 64 poses, 1408x376 (the bench launch)."""
+    sc, idx = cfg1
+    say(f"config1: crop {idx.size} of {sc.gaussians.n}, 64 poses, 1408x376")
+    sm = load(ctx, sc.gaussians, index=idx)
+    rgb, dep, tf = gpu_render(ctx, sm, sc.camera, sc.poses)
+    st = ctx.stats()
+    say(f"  stats {st}")
+    recs, nts, offs, pairs = gpu_buffers(ctx)
+    sub = sc.gaussians.take(idx)
+    pr = prep(sub)
+    T = _tiles(sc.camera)
+    rng_px = np.random.default_rng(5)
+    for p in (0, 21, 42, 63):
+        out_rec = search.project.preprocess(pr[0], pr[1], pr[2], pr[3], sc.poses[p], sc.camera.width,
+                                            sc.camera.height, sc.camera.fx, sc.camera.fy, sc.camera.cx,
+                                            sc.camera.cy)
+        check_records(recs, nts, out_rec, idx.size, p)
+        k, v = search.keys.make_pairs_fast(out_rec, sc.camera.width, sc.camera.height, 16, 16)
+        ks, vs = search.keys.sort_pairs(k, v)
+        rng = search.keys.tile_ranges(ks, T)
+        check_pairs(offs, pairs, ks, vs, rng, p, T)
+        pi = rng_px.integers(0, sc.camera.width, 3000)
+        pj = rng_px.integers(0, sc.camera.height, 3000)
+        c, d, t, f = search.blend.render_pixels(out_rec, vs, rng, sc.camera.width, pi, pj)
+        ok = ~f
+        e_rgb = np.abs(rgb[p][:, pj, pi] - c)[:, ok].max()
+        e_dep = np.abs(dep[p][pj, pi] - d)[ok].max()
+        e_t = np.abs(tf[p][pj, pi] - t)[ok].max()
+        say(f"  pose {p}: sampled 3000 px, max|drgb| {e_rgb:.2e} max|ddepth| {e_dep:.2e} "
+            f"max|dT| {e_t:.2e} flagged {int(f.sum())}")
+        assert e_rgb <= 1e-4 and e_t <= 1e-4
+        assert e_dep <= 1e-4 * max(1.0, float(np.abs(d).max()))
+    # properties at full size: T in [0, 1], colours in [0, 1] (all inputs are)
+    assert tf.min() >= 0 and tf.max() <= 1
+    assert rgb.min() >= 0 and rgb.max() <= 1 + 1e-5
+
+
+def test_eval_counters_match_oracle(ctx):
+    """GSR_RENDER_COUNT_EVALS: same images; contribution count equals the oracle's."""
+    say("config0 with evaluation counting")
+    from paper_2403_11367_amd import default_cfg
+    from paper_2403_11367_amd.gsr import RENDER_COUNT_EVALS
+    sc = W.config0()
+    sm = load(ctx, sc.gaussians)
+    a = gpu_render(ctx, sm, sc.camera, sc.poses)
+    b = gpu_render(ctx, sm, sc.camera, sc.poses, default_cfg(flags=RENDER_COUNT_EVALS))
+    st = ctx.stats()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    pr = prep(sc.gaussians)
+    ref = 0
+    flagged = 0
+    for p in range(sc.poses.shape[0]):
+        out = search.render_pose(pr, sc.poses[p], sc.camera)
+        ref += int(out.n_contrib.sum())
+        flagged += int(out.flag.sum())
+    say(f"  contributions gpu {st['evals_contrib']} oracle {ref} (flagged px {flagged}); "
+        f"lane slots {st['evals_lanes']}")
+    assert abs(st["evals_contrib"] - ref) <= 2 * flagged
+    assert st["evals_lanes"] >= st["evals_contrib"]
