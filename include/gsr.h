@@ -184,19 +184,25 @@ int gsr_get_stats(gsr_ctx *ctx, gsr_stats *out);
 /* Introspection of the last gsr_render for tests (waits for the stream, then
  * copies a library buffer to host memory `dst_host` of `bytes` bytes, which
  * must equal the size reported by gsr_debug_size). Buffers:
- *   GSR_BUF_RECORDS    [P][N][12] float32 screen records: u, v, conic A, B,
- *                      C, opacity, r, g, b, z, rect_x = i0 | i1 << 16,
+ * The library keeps each submap in a spatial (Morton) order of its means; k
+ * below is a Gaussian's position in that internal order.
+ *   GSR_BUF_RECORDS    [P][N][12] float32 screen records by (pose, k): u, v,
+ *                      conic A, B, C, opacity, r, g, b, z, rect_x = i0 | i1 << 16,
  *                      rect_y = j0 | j1 << 16 (the last two as uint32 bits);
  *                      valid where the tile count is nonzero
- *   GSR_BUF_NTILES     [P][N] uint32 tiles touched (0 = culled)
+ *   GSR_BUF_NTILES     [P][N] uint32 tiles touched by (pose, k) (0 = culled)
  *   GSR_BUF_OFFSETS    [P*T + 1] uint64 start of each (pose, tile) list; the last
  *                      entry is the pair total
- *   GSR_BUF_PAIRS      [n_pairs] uint64 sorted (depth bits << 32 | submap index)
+ *   GSR_BUF_PAIRS      [n_pairs] uint64 per-tile lists, each sorted by
+ *                      (depth bits, submap index), stored as depth bits << 32 | k
+ *   GSR_BUF_PERM       [N] uint32 submap index of internal position k (valid
+ *                      while the last rendered submap is alive)
  */
 #define GSR_BUF_RECORDS 0
 #define GSR_BUF_NTILES 1
 #define GSR_BUF_OFFSETS 2
 #define GSR_BUF_PAIRS 3
+#define GSR_BUF_PERM 4
 int gsr_debug_size(gsr_ctx *ctx, int which, int64_t *bytes);
 int gsr_debug_copy(gsr_ctx *ctx, int which, void *dst_host, int64_t bytes);
 

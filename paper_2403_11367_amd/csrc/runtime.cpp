@@ -34,11 +34,13 @@ struct gsr_ctx {
     struct Buf {
         void *p = nullptr;
         size_t bytes = 0;
-    } records, ntiles, counts, offsets, scan_tmp, pairs, pairs_tmp, long_list, grey_q, partials;
+    } records, ntiles, counts, offsets, scan_tmp, pairs, pairs_tmp, long_list, grey_q, partials, pack_tmp;
     // last render
     int64_t last_n = 0, last_poses = 0, last_tiles = 0;
     uint64_t last_capacity = 0;
     int64_t last_pairs = -1;  // known on host in exact mode
+    const uint32_t *last_perm = nullptr;  // submap of the last render (internal -> submap index)
+    uint64_t last_sm_id = 0, next_sm_id = 1;
     // profiling: event sets of the calls profiled since the last gsr_get_stats
     struct RenderEv {
         hipEvent_t e[4] = {};
@@ -54,8 +56,11 @@ struct gsr_ctx {
 struct gsr_submap {
     gsr_ctx *ctx = nullptr;
     int device = 0;
+    uint64_t id = 0;
     int64_t n = 0, cap = 0;
-    float4 *packed = nullptr;
+    float4 *packed = nullptr;    // [cap * kPackedQuads], spatial order
+    uint32_t *perm = nullptr;    // [cap] internal position -> submap index
+    uint32_t *inv_perm = nullptr;  // [cap] submap index -> internal position
 };
 
 namespace {
@@ -199,8 +204,9 @@ int gsr_destroy(gsr_ctx *ctx) {
     if (!ctx) return GSR_EINVAL;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    gsr_ctx::Buf *bufs[] = {&ctx->records, &ctx->ntiles, &ctx->counts, &ctx->offsets, &ctx->scan_tmp,
-                            &ctx->pairs, &ctx->pairs_tmp, &ctx->long_list, &ctx->grey_q, &ctx->partials};
+    gsr_ctx::Buf *bufs[] = {&ctx->records, &ctx->ntiles, &ctx->counts,    &ctx->offsets,  &ctx->scan_tmp,
+                            &ctx->pairs,   &ctx->pairs_tmp, &ctx->long_list, &ctx->grey_q, &ctx->partials,
+                            &ctx->pack_tmp};
     for (auto *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
@@ -245,11 +251,14 @@ int gsr_submap_load(gsr_ctx *ctx, int64_t n_map, const float *means, const float
         if (!nsm) return GSR_ENOMEM;
         nsm->ctx = ctx;
         nsm->device = ctx->device;
+        nsm->id = ctx->next_sm_id++;
         nsm->cap = n_sel > 0 ? n_sel : 1;
         hipError_t e = hipMalloc(&nsm->packed, (size_t)nsm->cap * gsr::kPackedQuads * sizeof(float4));
+        if (e == hipSuccess) e = hipMalloc(&nsm->perm, (size_t)nsm->cap * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&nsm->inv_perm, (size_t)nsm->cap * sizeof(uint32_t));
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            delete nsm;
+            gsr_submap_free(nsm);
             return fail(ctx, GSR_ENOMEM, "submap allocation failed");
         }
         if (sm) gsr_submap_free(sm);
@@ -257,16 +266,36 @@ int gsr_submap_load(gsr_ctx *ctx, int64_t n_map, const float *means, const float
         *out = sm;
     }
     sm->n = n_sel;
-    gsr::launch_pack(ctx->stream, n_map, means, scales, quats, opacity, rgb, index, n_sel, sm->packed,
-                     ctx->d_flags);
+    if (n_sel == 0) return GSR_OK;
+    // pack scratch: packed copy in submap order, Morton keys / order (x2), radix tmp, bbox
+    const size_t n = (size_t)n_sel;
+    const size_t b_packed = n * gsr::kPackedQuads * sizeof(float4);
+    const size_t b_u32 = ((n * sizeof(uint32_t) + 255) / 256) * 256;
+    const size_t b_radix = (size_t)gsr::radix_tmp_elems(n) * sizeof(uint64_t);
+    int rc = ensure(ctx, ctx->pack_tmp, b_packed + 4 * b_u32 + b_radix + 256, "pack scratch");
+    if (rc) return rc;
+    char *base = (char *)ctx->pack_tmp.p;
+    gsr::PackScratch sc;
+    sc.packed_tmp = (float4 *)base;
+    sc.code = (uint32_t *)(base + b_packed);
+    sc.order = (uint32_t *)(base + b_packed + b_u32);
+    sc.code_tmp = (uint32_t *)(base + b_packed + 2 * b_u32);
+    sc.order_tmp = (uint32_t *)(base + b_packed + 3 * b_u32);
+    sc.radix_tmp = (uint64_t *)(base + b_packed + 4 * b_u32);
+    sc.bbox = (uint32_t *)(base + b_packed + 4 * b_u32 + b_radix);
+    gsr::launch_pack(ctx->stream, n_map, means, scales, quats, opacity, rgb, index, n_sel, sc, sm->packed, sm->perm,
+                     sm->inv_perm, ctx->d_flags);
     return check_launch(ctx, "pack");
 }
 
 int gsr_submap_free(gsr_submap *sm) {
     if (!sm) return GSR_EINVAL;
+    if (sm->ctx && sm->ctx->last_sm_id == sm->id) sm->ctx->last_perm = nullptr;
     // hipFree waits for work on the device that may still read the submap
     (void)hipSetDevice(sm->device);
     if (sm->packed) (void)hipFree(sm->packed);
+    if (sm->perm) (void)hipFree(sm->perm);
+    if (sm->inv_perm) (void)hipFree(sm->inv_perm);
     delete sm;
     return GSR_OK;
 }
@@ -351,11 +380,11 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     if ((rc = ensure(ctx, ctx->pairs, (size_t)std::max<uint64_t>(1, capacity) * sizeof(uint64_t), "pairs")) ||
         (rc = ensure(ctx, ctx->pairs_tmp, (size_t)std::max<uint64_t>(1, capacity) * sizeof(uint64_t), "pairs tmp")))
         return rc;
-    gsr::launch_scatter(s, (const float4 *)ctx->records.p, (const uint32_t *)ctx->ntiles.p, n, n_poses, tg, offsets,
-                        cursor, (uint64_t *)ctx->pairs.p, capacity, ctx->d_flags);
+    gsr::launch_scatter(s, sm->packed, (const float4 *)ctx->records.p, (const uint32_t *)ctx->ntiles.p, n, n_poses,
+                        tg, offsets, cursor, (uint64_t *)ctx->pairs.p, capacity, ctx->d_flags);
     if ((rc = check_launch(ctx, "scatter"))) return rc;
     gsr::launch_tile_sort(s, (uint64_t *)ctx->pairs.p, (uint64_t *)ctx->pairs_tmp.p, offsets, tg.n_tiles, n_poses,
-                          capacity, (uint32_t *)ctx->long_list.p, ctx->d_counters);
+                          capacity, sm->inv_perm, (uint32_t *)ctx->long_list.p, ctx->d_counters);
     if ((rc = check_launch(ctx, "tile sort"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[2], s));
     gsr::launch_blend(s, (const float4 *)ctx->records.p, n, n_poses, (const uint64_t *)ctx->pairs.p, offsets,
@@ -365,6 +394,8 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     if (ev) HIPC(ctx, hipEventRecord(ev->e[3], s));
 
     ctx->last_n = n;
+    ctx->last_perm = sm->perm;
+    ctx->last_sm_id = sm->id;
     ctx->last_poses = P;
     ctx->last_tiles = tg.n_tiles;
     ctx->last_capacity = capacity;
@@ -478,6 +509,10 @@ int gsr_debug_size(gsr_ctx *ctx, int which, int64_t *bytes) {
         case GSR_BUF_RECORDS: *bytes = pn * gsr::kRecordQuads * (int64_t)sizeof(float4); break;
         case GSR_BUF_NTILES: *bytes = pn * (int64_t)sizeof(uint32_t); break;
         case GSR_BUF_OFFSETS: *bytes = (ctx->last_poses ? lists + 1 : 0) * (int64_t)sizeof(uint64_t); break;
+        case GSR_BUF_PERM:
+            if (!ctx->last_perm && ctx->last_n > 0) return fail(ctx, GSR_EINVAL, "the last rendered submap was freed");
+            *bytes = ctx->last_n * (int64_t)sizeof(uint32_t);
+            break;
         case GSR_BUF_PAIRS: {
             gsr_stats st;
             int rc = gsr_get_stats(ctx, &st);
@@ -498,10 +533,11 @@ int gsr_debug_copy(gsr_ctx *ctx, int which, void *dst, int64_t bytes) {
     if (bytes != want) return fail(ctx, GSR_EINVAL, "byte count differs from gsr_debug_size");
     if (bytes == 0) return GSR_OK;
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
-    const void *src = which == GSR_BUF_RECORDS  ? ctx->records.p
-                      : which == GSR_BUF_NTILES ? ctx->ntiles.p
+    const void *src = which == GSR_BUF_RECORDS   ? ctx->records.p
+                      : which == GSR_BUF_NTILES  ? ctx->ntiles.p
                       : which == GSR_BUF_OFFSETS ? ctx->offsets.p
-                                                  : ctx->pairs.p;
+                      : which == GSR_BUF_PERM    ? (const void *)ctx->last_perm
+                                                 : ctx->pairs.p;
     HIPC(ctx, hipMemcpy(dst, src, (size_t)bytes, hipMemcpyDeviceToHost));
     return GSR_OK;
 }

@@ -122,17 +122,89 @@ __device__ int pow2_ceil(int x) {
     return n;
 }
 
+// Stable scatter of src[beg, end) by the 8-bit digit at `shift` into dst, one
+// 256-thread block, in chunks of 256 elements taken in order. s_off[d] holds
+// the next output position of digit d and is advanced; s_wcnt (4 x 256) must
+// be zero on entry and is zero on exit. Within a chunk each wave finds the
+// lanes that share its digit with 8 ballots, so equal digits keep their input
+// order (lanes, then waves, then chunks).
+template <typename K, bool kVals>
+__device__ void stable_scatter(const K *src, const uint32_t *src_v, K *dst, uint32_t *dst_v, uint64_t beg,
+                               uint64_t end, int shift, uint32_t *s_off, uint32_t *s_wcnt) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (uint64_t c0 = beg; c0 < end; c0 += kThreads) {
+        const uint64_t i = c0 + tid;
+        const bool valid = i < end;
+        const K key = valid ? src[i] : K(0);
+        uint32_t val = 0;
+        if (kVals && valid) val = src_v[i];
+        const uint32_t d = (uint32_t)((key >> shift) & 0xff);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        if (!valid) peers = 0;
+        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+        const uint32_t cnt = (uint32_t)__popcll(peers);
+        const bool leader = valid && rank == 0;
+        if (leader) s_wcnt[wave * 256 + d] = cnt;
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = 0;
+            for (int w = 0; w < wave; ++w) pre += s_wcnt[w * 256 + d];
+            const uint64_t o = (uint64_t)s_off[d] + pre + rank;
+            dst[o] = key;
+            if (kVals) dst_v[o] = val;
+        }
+        __syncthreads();
+        if (leader) {
+            atomicAdd(&s_off[d], cnt);
+            s_wcnt[wave * 256 + d] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// Exclusive scan of a 256-entry LDS array in place (256 threads); s_tmp[4].
+__device__ void scan256(uint32_t *a, uint32_t *s_tmp) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t h = a[tid];
+    uint32_t x = h;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_tmp[wave] = x;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < wave; ++w) add += s_tmp[w];
+    __syncthreads();
+    a[tid] = x - h + add;
+    __syncthreads();
+}
+
+// Replace the low 32 bits (submap index) of sorted pairs by the Gaussian's
+// internal position (the blend gathers screen records by that position).
+__device__ __forceinline__ uint64_t to_internal(uint64_t key, const uint32_t *inv_perm) {
+    return (key & 0xffffffff00000000ull) | inv_perm[(uint32_t)key];
+}
+
 // Lists of length <= kSmallSortCap are sorted here; longer ones are queued.
 __global__ __launch_bounds__(kThreads) void k_tile_sort(uint64_t *__restrict__ pairs,
                                                         const uint64_t *__restrict__ offsets, int n_tiles,
-                                                        uint64_t capacity, uint32_t *__restrict__ long_list,
+                                                        uint64_t capacity, const uint32_t *__restrict__ inv_perm,
+                                                        uint32_t *__restrict__ long_list,
                                                         unsigned long long *__restrict__ counters) {
     __shared__ uint64_t s[kSmallSortCap];
     const uint64_t list = (uint64_t)blockIdx.y * n_tiles + blockIdx.x;
     const uint64_t beg = offsets[list];
     const uint64_t end = min(offsets[list + 1], capacity);
-    if (end <= beg + 1) return;
-    const int len = (int)min(end - beg, (uint64_t)0x7fffffff);
+    if (end <= beg) return;
     if (end - beg > (uint64_t)kSmallSortCap) {
         if (threadIdx.x == 0) {
             const unsigned long long slot = atomicAdd(&counters[CNT_LONG_TILES], 1ull);
@@ -140,18 +212,20 @@ __global__ __launch_bounds__(kThreads) void k_tile_sort(uint64_t *__restrict__ p
         }
         return;
     }
+    const int len = (int)(end - beg);
     const int n = pow2_ceil(len);
     for (int i = threadIdx.x; i < n; i += kThreads) s[i] = i < len ? pairs[beg + i] : ~0ull;
     __syncthreads();
     bitonic_lds(s, n);
-    for (int i = threadIdx.x; i < len; i += kThreads) pairs[beg + i] = s[i];
+    for (int i = threadIdx.x; i < len; i += kThreads) pairs[beg + i] = to_internal(s[i], inv_perm);
 }
 
 // Stable LSD radix sort of keys[0..len) (8-bit digits, only digits that vary),
 // ping-ponging with tmp; the result ends in keys. One 256-thread block.
-__device__ void radix_sort_global(uint64_t *keys, uint64_t *tmp, uint64_t len, uint32_t *s_hist /*[256]*/,
-                                  uint32_t *s_wcnt /*[4][256]*/, unsigned long long *s_red /*[2]*/) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ void radix_sort_global(uint64_t *keys, uint64_t *tmp, uint64_t len, uint32_t *s_off /*[256]*/,
+                                  uint32_t *s_wcnt /*[4][256]*/, uint32_t *s_tmp /*[4]*/,
+                                  unsigned long long *s_red /*[2]*/) {
+    const int tid = threadIdx.x;
     if (tid == 0) {
         s_red[0] = 0ull;
         s_red[1] = ~0ull;
@@ -168,61 +242,14 @@ __device__ void radix_sort_global(uint64_t *keys, uint64_t *tmp, uint64_t len, u
     __syncthreads();
     const uint64_t vary = s_red[0] ^ s_red[1];
     uint64_t *src = keys, *dst = tmp;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int shift = 0; shift < 64; shift += 8) {
         if (((vary >> shift) & 0xffull) == 0) continue;
-        s_hist[tid] = 0;
+        s_off[tid] = 0;
         __syncthreads();
-        for (uint64_t i = tid; i < len; i += kThreads) atomicAdd(&s_hist[(src[i] >> shift) & 0xff], 1u);
+        for (uint64_t i = tid; i < len; i += kThreads) atomicAdd(&s_off[(src[i] >> shift) & 0xff], 1u);
         __syncthreads();
-        // exclusive scan of the 256-bin histogram
-        {
-            const uint32_t h = s_hist[tid];
-            uint32_t x = h;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = __shfl_up(x, off, 64);
-                if (lane >= off) x += y;
-            }
-            if (lane == 63) s_wcnt[wave * 256] = x;  // borrow: wave totals
-            __syncthreads();
-            uint32_t add = 0;
-            for (int w = 0; w < wave; ++w) add += s_wcnt[w * 256];
-            __syncthreads();
-            if (lane == 63) s_wcnt[wave * 256] = 0;
-            s_hist[tid] = x - h + add;  // base offset of digit tid
-            __syncthreads();
-        }
-        for (uint64_t c0 = 0; c0 < len; c0 += kThreads) {
-            const uint64_t i = c0 + tid;
-            const bool valid = i < len;
-            const uint64_t key = valid ? src[i] : 0ull;
-            const uint32_t d = (uint32_t)((key >> shift) & 0xff);
-            uint64_t peers = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const uint64_t m = __ballot(bit);
-                peers &= bit ? m : ~m;
-            }
-            if (!valid) peers = 0;
-            const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-            const uint32_t cnt = (uint32_t)__popcll(peers);
-            const bool leader = valid && rank == 0;
-            if (leader) s_wcnt[wave * 256 + d] = cnt;
-            __syncthreads();
-            if (valid) {
-                uint32_t pre = 0;
-                for (int w = 0; w < wave; ++w) pre += s_wcnt[w * 256 + d];
-                dst[s_hist[d] + pre + rank] = key;
-            }
-            __syncthreads();
-            if (leader) {
-                atomicAdd(&s_hist[d], cnt);
-                s_wcnt[wave * 256 + d] = 0;
-            }
-            __syncthreads();
-        }
+        scan256(s_off, s_tmp);
+        stable_scatter<uint64_t, false>(src, nullptr, dst, nullptr, 0, len, shift, s_off, s_wcnt);
         uint64_t *t = src;
         src = dst;
         dst = t;
@@ -237,6 +264,7 @@ __device__ void radix_sort_global(uint64_t *keys, uint64_t *tmp, uint64_t len, u
 // sorted in LDS, longer ones by the global-memory radix sort.
 __global__ __launch_bounds__(kThreads) void k_long_sort(uint64_t *__restrict__ pairs, uint64_t *__restrict__ tmp,
                                                         const uint64_t *__restrict__ offsets, uint64_t capacity,
+                                                        const uint32_t *__restrict__ inv_perm,
                                                         const uint32_t *__restrict__ long_list,
                                                         const unsigned long long *__restrict__ counters) {
     __shared__ uint64_t s[kMidSortCap];
@@ -251,14 +279,47 @@ __global__ __launch_bounds__(kThreads) void k_long_sort(uint64_t *__restrict__ p
             for (int i = threadIdx.x; i < n; i += kThreads) s[i] = (uint64_t)i < len ? pairs[beg + i] : ~0ull;
             __syncthreads();
             bitonic_lds(s, n);
-            for (int i = threadIdx.x; (uint64_t)i < len; i += kThreads) pairs[beg + i] = s[i];
+            for (int i = threadIdx.x; (uint64_t)i < len; i += kThreads) pairs[beg + i] = to_internal(s[i], inv_perm);
             __syncthreads();
         } else {
             uint32_t *s32 = reinterpret_cast<uint32_t *>(s);
-            radix_sort_global(pairs + beg, tmp + beg, len, s32, s32 + 256,
-                              reinterpret_cast<unsigned long long *>(s32 + 256 + 4 * 256));
+            radix_sort_global(pairs + beg, tmp + beg, len, s32, s32 + 256, s32 + 256 + 1024,
+                              reinterpret_cast<unsigned long long *>(s32 + 256 + 1024 + 8));
+            for (uint64_t i = threadIdx.x; i < len; i += kThreads) pairs[beg + i] = to_internal(pairs[beg + i], inv_perm);
+            __syncthreads();
         }
     }
+}
+
+// ---- device-wide stable LSD radix sort of (uint32 key, uint32 value) ----
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kThreads * kRsItems;  // keys per block and pass
+
+__global__ __launch_bounds__(kThreads) void k_rs_hist(const uint32_t *__restrict__ keys, uint64_t n, int shift,
+                                                      int nb, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s_h[256];
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t beg = (uint64_t)blockIdx.x * kRsTile;
+    const uint64_t end = min(beg + kRsTile, n);
+    for (uint64_t i = beg + threadIdx.x; i < end; i += kThreads) atomicAdd(&s_h[(keys[i] >> shift) & 0xff], 1u);
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = s_h[threadIdx.x];  // digit-major
+}
+
+__global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t *__restrict__ keys,
+                                                         const uint32_t *__restrict__ vals,
+                                                         uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
+                                                         uint64_t n, int shift, int nb,
+                                                         const uint64_t *__restrict__ offsets) {
+    __shared__ uint32_t s_off[256];
+    __shared__ uint32_t s_wcnt[4 * 256];
+    for (int i = threadIdx.x; i < 4 * 256; i += kThreads) s_wcnt[i] = 0;
+    s_off[threadIdx.x] = (uint32_t)offsets[(uint64_t)threadIdx.x * nb + blockIdx.x];
+    __syncthreads();
+    const uint64_t beg = (uint64_t)blockIdx.x * kRsTile;
+    const uint64_t end = min(beg + kRsTile, n);
+    stable_scatter<uint32_t, true>(keys, vals, keys_out, vals_out, beg, end, shift, s_off, s_wcnt);
 }
 
 }  // namespace
@@ -289,12 +350,42 @@ void launch_scan(hipStream_t s, const uint32_t *count, uint64_t n, uint64_t *off
 }
 
 void launch_tile_sort(hipStream_t s, uint64_t *pairs, uint64_t *pairs_tmp, const uint64_t *offsets, int n_tiles,
-                      int n_poses, uint64_t capacity, uint32_t *long_list, unsigned long long *counters) {
+                      int n_poses, uint64_t capacity, const uint32_t *inv_perm, uint32_t *long_list,
+                      unsigned long long *counters) {
     if (n_tiles <= 0 || n_poses <= 0) return;
     hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)n_tiles, (unsigned)n_poses), dim3(kThreads), 0, s, pairs,
-                       offsets, n_tiles, capacity, long_list, counters);
+                       offsets, n_tiles, capacity, inv_perm, long_list, counters);
     hipLaunchKernelGGL(k_long_sort, dim3(1024), dim3(kThreads), 0, s, pairs, pairs_tmp, offsets, capacity,
-                       long_list, counters);
+                       inv_perm, long_list, counters);
+}
+
+uint64_t radix_tmp_elems(uint64_t n) {
+    const uint64_t nb = (n + kRsTile - 1) / kRsTile;
+    return 256 * nb / 2 + 1 + (256 * nb + 1) + scan_tmp_elems(256 * nb);  // u64 units
+}
+
+void launch_radix_sort_u32(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp,
+                           uint64_t n, int bits, uint64_t *tmp) {
+    if (n <= 1) return;
+    const uint64_t nb = (n + kRsTile - 1) / kRsTile;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(tmp);
+    uint64_t *offs = tmp + 256 * nb / 2 + 1;
+    uint64_t *stmp = offs + 256 * nb + 1;
+    uint32_t *ks = keys, *vs = vals, *kd = keys_tmp, *vd = vals_tmp;
+    const int passes = (bits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kThreads), 0, s, ks, n, shift, (int)nb, hist);
+        launch_scan(s, hist, 256 * nb, offs, stmp);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kThreads), 0, s, ks, vs, kd, vd, n, shift,
+                           (int)nb, offs);
+        std::swap(ks, kd);
+        std::swap(vs, vd);
+    }
+    if (ks != keys) {
+        (void)hipMemcpyAsync(keys, ks, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        (void)hipMemcpyAsync(vals, vs, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    }
 }
 
 }  // namespace gsr

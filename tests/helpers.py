@@ -46,9 +46,22 @@ def gpu_render(ctx, sm, cam, poses, cfg=None):
 
 
 def gpu_buffers(ctx):
-    from paper_2403_11367_amd import BUF_NTILES, BUF_OFFSETS, BUF_PAIRS, BUF_RECORDS
-    return (ctx.debug_buffer(BUF_RECORDS), ctx.debug_buffer(BUF_NTILES), ctx.debug_buffer(BUF_OFFSETS),
-            ctx.debug_buffer(BUF_PAIRS))
+    """Records and tile counts reordered to submap order; sorted pairs with their
+    low 32 bits mapped back to submap indices."""
+    from paper_2403_11367_amd import BUF_NTILES, BUF_OFFSETS, BUF_PAIRS, BUF_PERM, BUF_RECORDS
+    perm = ctx.debug_buffer(BUF_PERM).astype(np.int64)
+    n = perm.size
+    rec = ctx.debug_buffer(BUF_RECORDS).reshape(-1, n, 12)
+    nt = ctx.debug_buffer(BUF_NTILES).reshape(-1, n)
+    assert np.array_equal(np.sort(perm), np.arange(n)), "internal order is not a permutation"
+    rec_s = np.empty_like(rec)
+    rec_s[:, perm] = rec
+    nt_s = np.empty_like(nt)
+    nt_s[:, perm] = nt
+    pairs = ctx.debug_buffer(BUF_PAIRS)
+    hi = pairs & np.uint64(0xFFFFFFFF00000000)
+    low = perm[(pairs & np.uint64(0xFFFFFFFF)).astype(np.int64)].astype(np.uint64) if n else pairs
+    return rec_s.reshape(-1), nt_s.reshape(-1), ctx.debug_buffer(BUF_OFFSETS), hi | low
 
 
 def oracle_pose(prep, pose, cam, tile=(16, 16)):
