@@ -100,7 +100,6 @@ typedef struct {
     int64_t n_visible;       /* (pose, Gaussian) records that survived culling */
     int64_t n_pairs;         /* (pose, Gaussian, tile) pairs */
     int64_t pair_capacity;   /* pair buffer size used */
-    int64_t n_long_tiles;    /* tiles whose list exceeded the in-LDS sort size */
     int64_t evals_contrib;   /* with GSR_RENDER_COUNT_EVALS: (pixel, Gaussian) pairs that
                               * contributed to a pixel before it stopped */
     int64_t evals_lanes;     /* with GSR_RENDER_COUNT_EVALS: lane slots spent on evaluations */
@@ -152,7 +151,7 @@ int gsr_submap_load(gsr_ctx *ctx, int64_t n_map, const float *means_dev, const f
 int gsr_submap_free(gsr_submap *sm);
 int64_t gsr_submap_size(const gsr_submap *sm);
 
-/* Render the submap at P poses (Sec. III-A, Eq. 1-5).
+/* Render the submap at P poses (Sec. III-A, Eq. 1-5). P x tiles < 2^32.
  *   poses_dev  [P,3,4]  float32 world-to-camera [R | t], device memory
  *   rgb_dev    [P,3,H,W] float32 output, planar colour
  *   depth_dev  [P,H,W]   float32 output, Eq. 5 depth
@@ -184,25 +183,21 @@ int gsr_get_stats(gsr_ctx *ctx, gsr_stats *out);
 /* Introspection of the last gsr_render for tests (waits for the stream, then
  * copies a library buffer to host memory `dst_host` of `bytes` bytes, which
  * must equal the size reported by gsr_debug_size). Buffers:
- * The library keeps each submap in a spatial (Morton) order of its means; k
- * below is a Gaussian's position in that internal order.
- *   GSR_BUF_RECORDS    [P][N][12] float32 screen records by (pose, k): u, v,
- *                      conic A, B, C, opacity, r, g, b, z, rect_x = i0 | i1 << 16,
+ *   GSR_BUF_RECORDS    [P][N][12] float32 screen records: u, v, conic A, B, C,
+ *                      opacity, r, g, b, z, rect_x = i0 | i1 << 16,
  *                      rect_y = j0 | j1 << 16 (the last two as uint32 bits);
  *                      valid where the tile count is nonzero
- *   GSR_BUF_NTILES     [P][N] uint32 tiles touched by (pose, k) (0 = culled)
- *   GSR_BUF_OFFSETS    [P*T + 1] uint64 start of each (pose, tile) list; the last
- *                      entry is the pair total
- *   GSR_BUF_PAIRS      [n_pairs] uint64 per-tile lists, each sorted by
- *                      (depth bits, submap index), stored as depth bits << 32 | k
- *   GSR_BUF_PERM       [N] uint32 submap index of internal position k (valid
- *                      while the last rendered submap is alive)
+ *   GSR_BUF_NTILES     [P][N] uint32 tiles touched (0 = culled)
+ *   GSR_BUF_OFFSETS    [P*T + 1] uint64 start of each (pose, tile) list in the
+ *                      pair list; the last entry is the pair count
+ *   GSR_BUF_PAIRS      [n_pairs] uint32 submap index of each pair; each (pose,
+ *                      tile) list is in front-to-back order: ascending depth
+ *                      bits, then ascending submap index
  */
 #define GSR_BUF_RECORDS 0
 #define GSR_BUF_NTILES 1
 #define GSR_BUF_OFFSETS 2
 #define GSR_BUF_PAIRS 3
-#define GSR_BUF_PERM 4
 int gsr_debug_size(gsr_ctx *ctx, int which, int64_t *bytes);
 int gsr_debug_copy(gsr_ctx *ctx, int which, void *dst_host, int64_t bytes);
 

@@ -35,7 +35,7 @@ struct BlendConsts {
 
 template <bool kCount>
 __global__ __launch_bounds__(kThreads) void k_blend(const float4 *__restrict__ records, int64_t n,
-                                                    const uint64_t *__restrict__ pairs,
+                                                    const uint32_t *__restrict__ pairs,
                                                     const uint64_t *__restrict__ offsets, uint64_t capacity,
                                                     int width, int height, int tiles_x, int n_tiles,
                                                     BlendConsts k, float *__restrict__ out_rgb,
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kThreads) void k_blend(const float4 *__restrict__ r
         const uint64_t kk = c0 + tid;
         uint32_t bands = 0;
         if (kk < end) {
-            const uint32_t g = (uint32_t)pairs[kk];
+            const uint32_t g = pairs[kk];
             const float4 *r = rec_pose + (int64_t)g * 3;
             const float4 q0 = r[0], q1 = r[1], q2 = r[2];
             const float o = q1.y;
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kThreads) void k_blend(const float4 *__restrict__ r
 
 }  // namespace
 
-void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint64_t *pairs,
+void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
                   const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
                   const TileGrid &tg, float *rgb, float *depth, float *tfinal, bool count_evals,
                   unsigned long long *counters) {

@@ -34,13 +34,13 @@ struct gsr_ctx {
     struct Buf {
         void *p = nullptr;
         size_t bytes = 0;
-    } records, ntiles, counts, offsets, scan_tmp, pairs, pairs_tmp, long_list, grey_q, partials, pack_tmp;
+    } records, ntiles, vcount, voff, scan_tmp, dkey, dval, dkey_tmp, dval_tmp, pkey, pval, pkey_tmp, pval_tmp,
+        radix_tmp, offsets, grey_q, partials;
     // last render
     int64_t last_n = 0, last_poses = 0, last_tiles = 0;
     uint64_t last_capacity = 0;
     int64_t last_pairs = -1;  // known on host in exact mode
-    const uint32_t *last_perm = nullptr;  // submap of the last render (internal -> submap index)
-    uint64_t last_sm_id = 0, next_sm_id = 1;
+    int64_t last_vis_slot = 0;  // index of the visible total in voff
     // profiling: event sets of the calls profiled since the last gsr_get_stats
     struct RenderEv {
         hipEvent_t e[4] = {};
@@ -56,11 +56,8 @@ struct gsr_ctx {
 struct gsr_submap {
     gsr_ctx *ctx = nullptr;
     int device = 0;
-    uint64_t id = 0;
     int64_t n = 0, cap = 0;
-    float4 *packed = nullptr;    // [cap * kPackedQuads], spatial order
-    uint32_t *perm = nullptr;    // [cap] internal position -> submap index
-    uint32_t *inv_perm = nullptr;  // [cap] submap index -> internal position
+    float4 *packed = nullptr;  // [cap * kPackedQuads]
 };
 
 namespace {
@@ -204,9 +201,10 @@ int gsr_destroy(gsr_ctx *ctx) {
     if (!ctx) return GSR_EINVAL;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    gsr_ctx::Buf *bufs[] = {&ctx->records, &ctx->ntiles, &ctx->counts,    &ctx->offsets,  &ctx->scan_tmp,
-                            &ctx->pairs,   &ctx->pairs_tmp, &ctx->long_list, &ctx->grey_q, &ctx->partials,
-                            &ctx->pack_tmp};
+    gsr_ctx::Buf *bufs[] = {&ctx->records,  &ctx->ntiles,   &ctx->vcount,   &ctx->voff,     &ctx->scan_tmp,
+                            &ctx->dkey,     &ctx->dval,     &ctx->dkey_tmp, &ctx->dval_tmp, &ctx->pkey,
+                            &ctx->pval,     &ctx->pkey_tmp, &ctx->pval_tmp, &ctx->radix_tmp, &ctx->offsets,
+                            &ctx->grey_q,   &ctx->partials};
     for (auto *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
@@ -251,14 +249,11 @@ int gsr_submap_load(gsr_ctx *ctx, int64_t n_map, const float *means, const float
         if (!nsm) return GSR_ENOMEM;
         nsm->ctx = ctx;
         nsm->device = ctx->device;
-        nsm->id = ctx->next_sm_id++;
         nsm->cap = n_sel > 0 ? n_sel : 1;
         hipError_t e = hipMalloc(&nsm->packed, (size_t)nsm->cap * gsr::kPackedQuads * sizeof(float4));
-        if (e == hipSuccess) e = hipMalloc(&nsm->perm, (size_t)nsm->cap * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMalloc(&nsm->inv_perm, (size_t)nsm->cap * sizeof(uint32_t));
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            gsr_submap_free(nsm);
+            delete nsm;
             return fail(ctx, GSR_ENOMEM, "submap allocation failed");
         }
         if (sm) gsr_submap_free(sm);
@@ -266,36 +261,15 @@ int gsr_submap_load(gsr_ctx *ctx, int64_t n_map, const float *means, const float
         *out = sm;
     }
     sm->n = n_sel;
-    if (n_sel == 0) return GSR_OK;
-    // pack scratch: packed copy in submap order, Morton keys / order (x2), radix tmp, bbox
-    const size_t n = (size_t)n_sel;
-    const size_t b_packed = n * gsr::kPackedQuads * sizeof(float4);
-    const size_t b_u32 = ((n * sizeof(uint32_t) + 255) / 256) * 256;
-    const size_t b_radix = (size_t)gsr::radix_tmp_elems(n) * sizeof(uint64_t);
-    int rc = ensure(ctx, ctx->pack_tmp, b_packed + 4 * b_u32 + b_radix + 256, "pack scratch");
-    if (rc) return rc;
-    char *base = (char *)ctx->pack_tmp.p;
-    gsr::PackScratch sc;
-    sc.packed_tmp = (float4 *)base;
-    sc.code = (uint32_t *)(base + b_packed);
-    sc.order = (uint32_t *)(base + b_packed + b_u32);
-    sc.code_tmp = (uint32_t *)(base + b_packed + 2 * b_u32);
-    sc.order_tmp = (uint32_t *)(base + b_packed + 3 * b_u32);
-    sc.radix_tmp = (uint64_t *)(base + b_packed + 4 * b_u32);
-    sc.bbox = (uint32_t *)(base + b_packed + 4 * b_u32 + b_radix);
-    gsr::launch_pack(ctx->stream, n_map, means, scales, quats, opacity, rgb, index, n_sel, sc, sm->packed, sm->perm,
-                     sm->inv_perm, ctx->d_flags);
+    gsr::launch_pack(ctx->stream, n_map, means, scales, quats, opacity, rgb, index, n_sel, sm->packed, ctx->d_flags);
     return check_launch(ctx, "pack");
 }
 
 int gsr_submap_free(gsr_submap *sm) {
     if (!sm) return GSR_EINVAL;
-    if (sm->ctx && sm->ctx->last_sm_id == sm->id) sm->ctx->last_perm = nullptr;
     // hipFree waits for work on the device that may still read the submap
     (void)hipSetDevice(sm->device);
     if (sm->packed) (void)hipFree(sm->packed);
-    if (sm->perm) (void)hipFree(sm->perm);
-    if (sm->inv_perm) (void)hipFree(sm->inv_perm);
     delete sm;
     return GSR_OK;
 }
@@ -340,36 +314,62 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     const int64_t n = sm->n;
     const int64_t P = n_poses;
     const uint64_t n_lists = (uint64_t)P * tg.n_tiles;
+    if (n_lists >= 0xffffffffull) return fail(ctx, GSR_EINVAL, "poses x tiles must be below 2^32");
+    const uint64_t pn = (uint64_t)std::max<int64_t>(1, P * n);
+    const uint64_t nbp = (uint64_t)std::max<int64_t>(1, gsr::preprocess_blocks(n));
+    const uint64_t nvc = (uint64_t)P * nbp;  // visible-count entries
     int rc;
-    if ((rc = ensure(ctx, ctx->records, (size_t)std::max<int64_t>(1, P * n) * gsr::kRecordQuads * sizeof(float4), "records")) ||
-        (rc = ensure(ctx, ctx->ntiles, (size_t)std::max<int64_t>(1, P * n) * sizeof(uint32_t), "ntiles")) ||
-        (rc = ensure(ctx, ctx->counts, (size_t)n_lists * 2 * sizeof(uint32_t), "counts")) ||
-        (rc = ensure(ctx, ctx->offsets, (size_t)(n_lists + 1) * sizeof(uint64_t), "offsets")) ||
-        (rc = ensure(ctx, ctx->scan_tmp, (size_t)gsr::scan_tmp_elems(n_lists) * sizeof(uint64_t), "scan")) ||
-        (rc = ensure(ctx, ctx->long_list, (size_t)n_lists * sizeof(uint32_t), "long list")))
+    if ((rc = ensure(ctx, ctx->records, pn * gsr::kRecordQuads * sizeof(float4), "records")) ||
+        (rc = ensure(ctx, ctx->ntiles, pn * sizeof(uint32_t), "ntiles")) ||
+        (rc = ensure(ctx, ctx->vcount, nvc * sizeof(uint32_t), "visible counts")) ||
+        (rc = ensure(ctx, ctx->voff, (nvc + 1) * sizeof(uint64_t), "visible offsets")) ||
+        (rc = ensure(ctx, ctx->scan_tmp, gsr::scan_tmp_elems(std::max(nvc, pn)) * sizeof(uint64_t), "scan")) ||
+        (rc = ensure(ctx, ctx->dkey, pn * sizeof(uint64_t), "depth keys")) ||
+        (rc = ensure(ctx, ctx->dval, pn * sizeof(uint32_t), "depth values")) ||
+        (rc = ensure(ctx, ctx->dkey_tmp, (pn + 1) * sizeof(uint64_t), "depth keys tmp")) ||
+        (rc = ensure(ctx, ctx->dval_tmp, pn * sizeof(uint32_t), "depth values tmp")) ||
+        (rc = ensure(ctx, ctx->offsets, (n_lists + 1) * sizeof(uint64_t), "offsets")))
         return rc;
-    uint32_t *tile_count = (uint32_t *)ctx->counts.p;
-    uint32_t *cursor = tile_count + n_lists;
-    uint64_t *offsets = (uint64_t *)ctx->offsets.p;
     hipStream_t s = ctx->stream;
+    uint32_t *vcount = (uint32_t *)ctx->vcount.p;
+    uint64_t *voff = (uint64_t *)ctx->voff.p;
+    uint64_t *dkey = (uint64_t *)ctx->dkey.p, *dkey_tmp = (uint64_t *)ctx->dkey_tmp.p;
+    uint32_t *dval = (uint32_t *)ctx->dval.p, *dval_tmp = (uint32_t *)ctx->dval_tmp.p;
+    uint32_t *ntiles = (uint32_t *)ctx->ntiles.p;
+    const float4 *records = (const float4 *)ctx->records.p;
+    uint64_t *offsets = (uint64_t *)ctx->offsets.p;
+    const uint64_t *d_nvis = voff + nvc;
+    int pose_bits = 0;
+    while ((1ll << pose_bits) < P) ++pose_bits;
+    int list_bits = 1;
+    while ((1ull << list_bits) < n_lists) ++list_bits;
 
     gsr_ctx::RenderEv *ev = nullptr;
     if (ctx->profile) {
         if ((rc = next_events(ctx, ctx->ev_render, ctx->n_ev_render, &ev))) return rc;
         HIPC(ctx, hipEventRecord(ev->e[0], s));
     }
-    gsr::launch_fill_u32(s, tile_count, n_lists * 2, 0u);
     gsr::launch_fill_u64(s, ctx->d_counters, gsr::CNT_COUNT, 0ull);
-    gsr::launch_preprocess(s, sm->packed, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p,
-                           (uint32_t *)ctx->ntiles.p, tile_count, ctx->d_counters);
+    if (n == 0) gsr::launch_fill_u32(s, vcount, nvc, 0u);
+    gsr::launch_preprocess(s, sm->packed, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p, ntiles, vcount);
     if ((rc = check_launch(ctx, "preprocess"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[1], s));
-    gsr::launch_scan(s, tile_count, n_lists, offsets, (uint64_t *)ctx->scan_tmp.p);
-    if ((rc = check_launch(ctx, "scan"))) return rc;
+    // S2: visible entries, depth order, pair counts and offsets
+    gsr::launch_scan(s, vcount, nvc, voff, (uint64_t *)ctx->scan_tmp.p, nullptr);
+    gsr::launch_compact(s, records, ntiles, n, n_poses, voff, dkey, dval);
+    if ((rc = ensure(ctx, ctx->radix_tmp, gsr::radix_tmp_elems(pn) * sizeof(uint64_t), "radix"))) return rc;
+    gsr::launch_radix_sort<uint64_t>(s, dkey, dval, dkey_tmp, dval_tmp, pn, d_nvis, 0, 32 + pose_bits,
+                                     (uint64_t *)ctx->radix_tmp.p);
+    uint32_t *cnt = dval_tmp;
+    uint64_t *pair_off = dkey_tmp;
+    gsr::launch_pair_counts(s, dkey, dval, d_nvis, pn, ntiles, n, cnt);
+    gsr::launch_scan(s, cnt, pn, pair_off, (uint64_t *)ctx->scan_tmp.p, d_nvis);
+    const uint64_t *d_npairs = pair_off + pn;
+    if ((rc = check_launch(ctx, "depth order"))) return rc;
 
     uint64_t capacity;
     if (cfg.pair_capacity == 0) {
-        HIPC(ctx, hipMemcpyAsync(ctx->h_pin, offsets + n_lists, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        HIPC(ctx, hipMemcpyAsync(ctx->h_pin, d_npairs, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
         HIPC(ctx, hipStreamSynchronize(s));
         capacity = ctx->h_pin[0];
         ctx->last_pairs = (int64_t)capacity;
@@ -377,28 +377,32 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
         capacity = (uint64_t)cfg.pair_capacity;
         ctx->last_pairs = -1;
     }
-    if ((rc = ensure(ctx, ctx->pairs, (size_t)std::max<uint64_t>(1, capacity) * sizeof(uint64_t), "pairs")) ||
-        (rc = ensure(ctx, ctx->pairs_tmp, (size_t)std::max<uint64_t>(1, capacity) * sizeof(uint64_t), "pairs tmp")))
+    const uint64_t cap1 = std::max<uint64_t>(1, capacity);
+    if ((rc = ensure(ctx, ctx->pkey, cap1 * sizeof(uint32_t), "pair keys")) ||
+        (rc = ensure(ctx, ctx->pval, cap1 * sizeof(uint32_t), "pair values")) ||
+        (rc = ensure(ctx, ctx->pkey_tmp, cap1 * sizeof(uint32_t), "pair keys tmp")) ||
+        (rc = ensure(ctx, ctx->pval_tmp, cap1 * sizeof(uint32_t), "pair values tmp")) ||
+        (rc = ensure(ctx, ctx->radix_tmp, gsr::radix_tmp_elems(std::max<uint64_t>(pn, cap1)) * sizeof(uint64_t),
+                     "radix")))
         return rc;
-    gsr::launch_scatter(s, sm->packed, (const float4 *)ctx->records.p, (const uint32_t *)ctx->ntiles.p, n, n_poses,
-                        tg, offsets, cursor, (uint64_t *)ctx->pairs.p, capacity, ctx->d_flags);
-    if ((rc = check_launch(ctx, "scatter"))) return rc;
-    gsr::launch_tile_sort(s, (uint64_t *)ctx->pairs.p, (uint64_t *)ctx->pairs_tmp.p, offsets, tg.n_tiles, n_poses,
-                          capacity, sm->inv_perm, (uint32_t *)ctx->long_list.p, ctx->d_counters);
-    if ((rc = check_launch(ctx, "tile sort"))) return rc;
+    uint32_t *pkey = (uint32_t *)ctx->pkey.p, *pval = (uint32_t *)ctx->pval.p;
+    // S3: pairs in depth order, then a stable sort by (pose, tile); S4: list ranges
+    gsr::launch_emit(s, dkey, dval, d_nvis, pn, pair_off, records, n, tg, pkey, pval, capacity, ctx->d_flags);
+    gsr::launch_radix_sort<uint32_t>(s, pkey, pval, (uint32_t *)ctx->pkey_tmp.p, (uint32_t *)ctx->pval_tmp.p,
+                                     capacity, d_npairs, 0, list_bits, (uint64_t *)ctx->radix_tmp.p);
+    gsr::launch_ranges(s, pkey, d_npairs, capacity, n_lists, offsets);
+    if ((rc = check_launch(ctx, "pair sort"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[2], s));
-    gsr::launch_blend(s, (const float4 *)ctx->records.p, n, n_poses, (const uint64_t *)ctx->pairs.p, offsets,
-                      capacity, c, k, tg, rgb, depth, tfinal, (cfg.flags & GSR_RENDER_COUNT_EVALS) != 0,
-                      ctx->d_counters);
+    gsr::launch_blend(s, records, n, n_poses, pval, offsets, capacity, c, k, tg, rgb, depth, tfinal,
+                      (cfg.flags & GSR_RENDER_COUNT_EVALS) != 0, ctx->d_counters);
     if ((rc = check_launch(ctx, "blend"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[3], s));
 
     ctx->last_n = n;
-    ctx->last_perm = sm->perm;
-    ctx->last_sm_id = sm->id;
     ctx->last_poses = P;
     ctx->last_tiles = tg.n_tiles;
     ctx->last_capacity = capacity;
+    ctx->last_vis_slot = (int64_t)nvc;
     return GSR_OK;
 }
 
@@ -461,14 +465,14 @@ int gsr_get_stats(gsr_ctx *ctx, gsr_stats *out) {
     HIPC(ctx, hipMemcpy(flags, ctx->d_flags, sizeof(flags), hipMemcpyDeviceToHost));
     out->n_submap = ctx->last_n;
     out->n_poses = ctx->last_poses;
-    out->n_visible = (int64_t)cnt[gsr::CNT_VISIBLE];
-    out->n_long_tiles = (int64_t)cnt[gsr::CNT_LONG_TILES];
     out->pair_capacity = (int64_t)ctx->last_capacity;
-    if (ctx->offsets.p && ctx->last_poses > 0) {
-        uint64_t total = 0;
-        const uint64_t n_lists = (uint64_t)ctx->last_poses * ctx->last_tiles;
-        HIPC(ctx, hipMemcpy(&total, (uint64_t *)ctx->offsets.p + n_lists, sizeof(total), hipMemcpyDeviceToHost));
-        out->n_pairs = (int64_t)total;
+    if (ctx->last_poses > 0) {
+        uint64_t v = 0;
+        HIPC(ctx, hipMemcpy(&v, (uint64_t *)ctx->voff.p + ctx->last_vis_slot, sizeof(v), hipMemcpyDeviceToHost));
+        out->n_visible = (int64_t)v;
+        const uint64_t pn = (uint64_t)std::max<int64_t>(1, ctx->last_poses * ctx->last_n);
+        HIPC(ctx, hipMemcpy(&v, (uint64_t *)ctx->dkey_tmp.p + pn, sizeof(v), hipMemcpyDeviceToHost));
+        out->n_pairs = (int64_t)v;
     }
     out->overflow = flags[gsr::FLAG_OVERFLOW];
     out->bad_index = flags[gsr::FLAG_BAD_INDEX];
@@ -509,15 +513,11 @@ int gsr_debug_size(gsr_ctx *ctx, int which, int64_t *bytes) {
         case GSR_BUF_RECORDS: *bytes = pn * gsr::kRecordQuads * (int64_t)sizeof(float4); break;
         case GSR_BUF_NTILES: *bytes = pn * (int64_t)sizeof(uint32_t); break;
         case GSR_BUF_OFFSETS: *bytes = (ctx->last_poses ? lists + 1 : 0) * (int64_t)sizeof(uint64_t); break;
-        case GSR_BUF_PERM:
-            if (!ctx->last_perm && ctx->last_n > 0) return fail(ctx, GSR_EINVAL, "the last rendered submap was freed");
-            *bytes = ctx->last_n * (int64_t)sizeof(uint32_t);
-            break;
         case GSR_BUF_PAIRS: {
             gsr_stats st;
             int rc = gsr_get_stats(ctx, &st);
             if (rc) return rc;
-            *bytes = std::min<int64_t>(st.n_pairs, (int64_t)ctx->last_capacity) * (int64_t)sizeof(uint64_t);
+            *bytes = std::min<int64_t>(st.n_pairs, (int64_t)ctx->last_capacity) * (int64_t)sizeof(uint32_t);
             break;
         }
         default: return fail(ctx, GSR_EINVAL, "unknown buffer");
@@ -536,8 +536,7 @@ int gsr_debug_copy(gsr_ctx *ctx, int which, void *dst, int64_t bytes) {
     const void *src = which == GSR_BUF_RECORDS   ? ctx->records.p
                       : which == GSR_BUF_NTILES  ? ctx->ntiles.p
                       : which == GSR_BUF_OFFSETS ? ctx->offsets.p
-                      : which == GSR_BUF_PERM    ? (const void *)ctx->last_perm
-                                                 : ctx->pairs.p;
+                                                 : ctx->pval.p;
     HIPC(ctx, hipMemcpy(dst, src, (size_t)bytes, hipMemcpyDeviceToHost));
     return GSR_OK;
 }

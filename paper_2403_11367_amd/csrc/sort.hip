@@ -1,14 +1,19 @@
-// Pair ordering: the (pose, tile) counts are turned into list offsets by an
-// exclusive scan, pairs are scattered into their tile's list (geometry.hip),
-// and every list is then sorted by its 64-bit key (depth bits << 32 | submap
-// index). The result is, per (pose, tile), the front-to-back order that
-// Eq. 1 and Eq. 5 composite in (Sec. III-A: Gaussians "sorted by depth"), with
-// equal depths ordered by submap index.
+// Ordering of the (Gaussian, tile) pairs of every pose (S2-S4).
 //
-// Bucketing by tile is a one-digit counting sort; the in-list order comes from
-// a bitonic network in LDS for lists up to kMidSortCap pairs and from an LSD
-// radix sort (8-bit digits, stable block-level multisplit) in global memory
-// beyond that.
+// Paper: Sec. III-A - the Gaussians are sorted by depth and composited front to
+// back. Per (pose, tile) the blend needs its Gaussians in ascending depth, with
+// equal depths in ascending submap index (a total order).
+//
+// Everything here is built on one primitive, a device-wide stable LSD radix
+// sort with 8-bit digits (k_rs_hist -> exclusive scan -> k_rs_scatter per
+// digit). Stability is what carries the order through:
+//   1. visible (pose, Gaussian) entries are compacted in (pose, index) order;
+//   2. they are radix-sorted by (pose, depth bits): ties keep index order;
+//   3. each entry emits one pair per tile it touches, in that depth order;
+//   4. the pairs are radix-sorted by (pose * T + tile): within a tile they keep
+//      depth order;
+//   5. each list's [start, end) is found by binary search in the sorted keys.
+// No atomics, so the result is deterministic run to run.
 #include "internal.h"
 
 namespace gsr {
@@ -18,6 +23,8 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kScanItems = 8;  // per thread
 constexpr int kScanTile = kThreads * kScanItems;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kThreads * kRsItems;  // keys per block and pass
 
 __global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
@@ -45,9 +52,11 @@ __device__ uint64_t block_inclusive_scan(uint64_t x, uint64_t *s_wave /*[4]*/) {
     return x + add;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ count, uint64_t n,
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ count, uint64_t n_max,
+                                                          const uint64_t *__restrict__ d_n,
                                                           uint64_t *__restrict__ block_sums) {
     __shared__ uint64_t s_wave[4];
+    const uint64_t n = d_n ? min(*d_n, n_max) : n_max;
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
     uint64_t sum = 0;
 #pragma unroll
@@ -77,10 +86,12 @@ __global__ __launch_bounds__(kThreads) void k_scan_blocks(uint64_t *__restrict__
     if (threadIdx.x == 0) *out_total = s_carry;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restrict__ count, uint64_t n,
+__global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restrict__ count, uint64_t n_max,
+                                                         const uint64_t *__restrict__ d_n,
                                                          const uint64_t *__restrict__ block_prefix,
                                                          uint64_t *__restrict__ offsets) {
     __shared__ uint64_t s_wave[4];
+    const uint64_t n = d_n ? min(*d_n, n_max) : n_max;
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint64_t sum = 0;
@@ -97,48 +108,50 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restr
     }
 }
 
-// Bitonic sort of s[0..n) ascending, n a power of two, by a 256-thread block.
-__device__ void bitonic_lds(uint64_t *s, int n) {
-    for (int k = 2; k <= n; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < (n >> 1); i += kThreads) {
-                const int lo = 2 * j * (i / j) + (i % j);
-                const int hi = lo + j;
-                const bool up = (lo & k) == 0;
-                const uint64_t a = s[lo], b = s[hi];
-                if ((a > b) == up) {
-                    s[lo] = b;
-                    s[hi] = a;
-                }
-            }
-            __syncthreads();
-        }
-    }
+__device__ __forceinline__ uint64_t dev_count(const uint64_t *d_n, uint64_t n_max) {
+    return d_n ? min(*d_n, n_max) : n_max;
 }
 
-__device__ int pow2_ceil(int x) {
-    int n = 1;
-    while (n < x) n <<= 1;
-    return n;
+// Per-block digit histogram, stored digit-major: hist[d * nb + block].
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_rs_hist(const K *__restrict__ keys, const uint64_t *__restrict__ d_n,
+                                                      uint64_t n_max, int shift, int nb, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s_h[256];
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t n = dev_count(d_n, n_max);
+    const uint64_t beg = (uint64_t)blockIdx.x * kRsTile;
+    const uint64_t end = min(beg + kRsTile, n);
+    for (uint64_t i = beg + threadIdx.x; i < end; i += kThreads) atomicAdd(&s_h[(keys[i] >> shift) & 0xff], 1u);
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = s_h[threadIdx.x];
 }
 
-// Stable scatter of src[beg, end) by the 8-bit digit at `shift` into dst, one
-// 256-thread block, in chunks of 256 elements taken in order. s_off[d] holds
-// the next output position of digit d and is advanced; s_wcnt (4 x 256) must
-// be zero on entry and is zero on exit. Within a chunk each wave finds the
-// lanes that share its digit with 8 ballots, so equal digits keep their input
-// order (lanes, then waves, then chunks).
-template <typename K, bool kVals>
-__device__ void stable_scatter(const K *src, const uint32_t *src_v, K *dst, uint32_t *dst_v, uint64_t beg,
-                               uint64_t end, int shift, uint32_t *s_off, uint32_t *s_wcnt) {
+// Stable scatter of one block's keys by the digit at `shift`. The block walks
+// its range in chunks of 256 in order; within a chunk each wave finds the
+// lanes sharing its digit with 8 ballots, and per-wave counts in LDS order the
+// waves, so equal digits keep their input order. s_off[d] starts at the
+// block's global offset for digit d (from the scanned histogram).
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_rs_scatter(const K *__restrict__ keys, const uint32_t *__restrict__ vals,
+                                                         K *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
+                                                         const uint64_t *__restrict__ d_n, uint64_t n_max, int shift,
+                                                         int nb, const uint64_t *__restrict__ offsets) {
+    __shared__ unsigned long long s_off[256];
+    __shared__ uint32_t s_wcnt[4 * 256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < 4 * 256; i += kThreads) s_wcnt[i] = 0;
+    s_off[tid] = offsets[(uint64_t)tid * nb + blockIdx.x];
+    __syncthreads();
+    const uint64_t n = dev_count(d_n, n_max);
+    const uint64_t beg = (uint64_t)blockIdx.x * kRsTile;
+    const uint64_t end = min(beg + kRsTile, n);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (uint64_t c0 = beg; c0 < end; c0 += kThreads) {
         const uint64_t i = c0 + tid;
         const bool valid = i < end;
-        const K key = valid ? src[i] : K(0);
-        uint32_t val = 0;
-        if (kVals && valid) val = src_v[i];
+        const K key = valid ? keys[i] : K(0);
+        const uint32_t val = valid ? vals[i] : 0u;
         const uint32_t d = (uint32_t)((key >> shift) & 0xff);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -156,170 +169,50 @@ __device__ void stable_scatter(const K *src, const uint32_t *src_v, K *dst, uint
         if (valid) {
             uint32_t pre = 0;
             for (int w = 0; w < wave; ++w) pre += s_wcnt[w * 256 + d];
-            const uint64_t o = (uint64_t)s_off[d] + pre + rank;
-            dst[o] = key;
-            if (kVals) dst_v[o] = val;
+            const uint64_t o = s_off[d] + pre + rank;
+            keys_out[o] = key;
+            vals_out[o] = val;
         }
         __syncthreads();
         if (leader) {
-            atomicAdd(&s_off[d], cnt);
+            atomicAdd(&s_off[d], (unsigned long long)cnt);
             s_wcnt[wave * 256 + d] = 0;
         }
         __syncthreads();
     }
 }
 
-// Exclusive scan of a 256-entry LDS array in place (256 threads); s_tmp[4].
-__device__ void scan256(uint32_t *a, uint32_t *s_tmp) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t h = a[tid];
-    uint32_t x = h;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) s_tmp[wave] = x;
-    __syncthreads();
-    uint32_t add = 0;
-    for (int w = 0; w < wave; ++w) add += s_tmp[w];
-    __syncthreads();
-    a[tid] = x - h + add;
-    __syncthreads();
+__global__ void k_copy_u32(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, const uint64_t *d_n,
+                           uint64_t n_max) {
+    const uint64_t n = dev_count(d_n, n_max);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
-// Replace the low 32 bits (submap index) of sorted pairs by the Gaussian's
-// internal position (the blend gathers screen records by that position).
-__device__ __forceinline__ uint64_t to_internal(uint64_t key, const uint32_t *inv_perm) {
-    return (key & 0xffffffff00000000ull) | inv_perm[(uint32_t)key];
+__global__ void k_copy_u64(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, const uint64_t *d_n,
+                           uint64_t n_max) {
+    const uint64_t n = dev_count(d_n, n_max);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
-// Lists of length <= kSmallSortCap are sorted here; longer ones are queued.
-__global__ __launch_bounds__(kThreads) void k_tile_sort(uint64_t *__restrict__ pairs,
-                                                        const uint64_t *__restrict__ offsets, int n_tiles,
-                                                        uint64_t capacity, const uint32_t *__restrict__ inv_perm,
-                                                        uint32_t *__restrict__ long_list,
-                                                        unsigned long long *__restrict__ counters) {
-    __shared__ uint64_t s[kSmallSortCap];
-    const uint64_t list = (uint64_t)blockIdx.y * n_tiles + blockIdx.x;
-    const uint64_t beg = offsets[list];
-    const uint64_t end = min(offsets[list + 1], capacity);
-    if (end <= beg) return;
-    if (end - beg > (uint64_t)kSmallSortCap) {
-        if (threadIdx.x == 0) {
-            const unsigned long long slot = atomicAdd(&counters[CNT_LONG_TILES], 1ull);
-            long_list[slot] = (uint32_t)list;
+// [start, end) of list t (0 <= t < n_lists) in keys[0, n) sorted ascending:
+// offsets[t] = lower_bound(t); offsets[n_lists] = n.
+__global__ void k_ranges(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ d_n, uint64_t n_max,
+                         uint64_t n_lists, uint64_t *__restrict__ offsets) {
+    const uint64_t n = dev_count(d_n, n_max);
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= n_lists;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if ((uint64_t)keys[mid] < t)
+                lo = mid + 1;
+            else
+                hi = mid;
         }
-        return;
+        offsets[t] = t == n_lists ? n : lo;
     }
-    const int len = (int)(end - beg);
-    const int n = pow2_ceil(len);
-    for (int i = threadIdx.x; i < n; i += kThreads) s[i] = i < len ? pairs[beg + i] : ~0ull;
-    __syncthreads();
-    bitonic_lds(s, n);
-    for (int i = threadIdx.x; i < len; i += kThreads) pairs[beg + i] = to_internal(s[i], inv_perm);
-}
-
-// Stable LSD radix sort of keys[0..len) (8-bit digits, only digits that vary),
-// ping-ponging with tmp; the result ends in keys. One 256-thread block.
-__device__ void radix_sort_global(uint64_t *keys, uint64_t *tmp, uint64_t len, uint32_t *s_off /*[256]*/,
-                                  uint32_t *s_wcnt /*[4][256]*/, uint32_t *s_tmp /*[4]*/,
-                                  unsigned long long *s_red /*[2]*/) {
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        s_red[0] = 0ull;
-        s_red[1] = ~0ull;
-    }
-    for (int i = tid; i < 4 * 256; i += kThreads) s_wcnt[i] = 0;
-    __syncthreads();
-    unsigned long long o = 0ull, a = ~0ull;
-    for (uint64_t i = tid; i < len; i += kThreads) {
-        o |= keys[i];
-        a &= keys[i];
-    }
-    atomicOr(&s_red[0], o);
-    atomicAnd(&s_red[1], a);
-    __syncthreads();
-    const uint64_t vary = s_red[0] ^ s_red[1];
-    uint64_t *src = keys, *dst = tmp;
-    for (int shift = 0; shift < 64; shift += 8) {
-        if (((vary >> shift) & 0xffull) == 0) continue;
-        s_off[tid] = 0;
-        __syncthreads();
-        for (uint64_t i = tid; i < len; i += kThreads) atomicAdd(&s_off[(src[i] >> shift) & 0xff], 1u);
-        __syncthreads();
-        scan256(s_off, s_tmp);
-        stable_scatter<uint64_t, false>(src, nullptr, dst, nullptr, 0, len, shift, s_off, s_wcnt);
-        uint64_t *t = src;
-        src = dst;
-        dst = t;
-    }
-    if (src != keys) {
-        for (uint64_t i = tid; i < len; i += kThreads) keys[i] = src[i];
-    }
-    __syncthreads();
-}
-
-// Queued long lists: a fixed grid walks the queue. Lists up to kMidSortCap are
-// sorted in LDS, longer ones by the global-memory radix sort.
-__global__ __launch_bounds__(kThreads) void k_long_sort(uint64_t *__restrict__ pairs, uint64_t *__restrict__ tmp,
-                                                        const uint64_t *__restrict__ offsets, uint64_t capacity,
-                                                        const uint32_t *__restrict__ inv_perm,
-                                                        const uint32_t *__restrict__ long_list,
-                                                        const unsigned long long *__restrict__ counters) {
-    __shared__ uint64_t s[kMidSortCap];
-    const uint64_t n_long = counters[CNT_LONG_TILES];
-    for (uint64_t q = blockIdx.x; q < n_long; q += gridDim.x) {
-        const uint32_t list = long_list[q];
-        const uint64_t beg = offsets[list];
-        const uint64_t end = min(offsets[list + 1], capacity);
-        const uint64_t len = end - beg;
-        if (len <= (uint64_t)kMidSortCap) {
-            const int n = pow2_ceil((int)len);
-            for (int i = threadIdx.x; i < n; i += kThreads) s[i] = (uint64_t)i < len ? pairs[beg + i] : ~0ull;
-            __syncthreads();
-            bitonic_lds(s, n);
-            for (int i = threadIdx.x; (uint64_t)i < len; i += kThreads) pairs[beg + i] = to_internal(s[i], inv_perm);
-            __syncthreads();
-        } else {
-            uint32_t *s32 = reinterpret_cast<uint32_t *>(s);
-            radix_sort_global(pairs + beg, tmp + beg, len, s32, s32 + 256, s32 + 256 + 1024,
-                              reinterpret_cast<unsigned long long *>(s32 + 256 + 1024 + 8));
-            for (uint64_t i = threadIdx.x; i < len; i += kThreads) pairs[beg + i] = to_internal(pairs[beg + i], inv_perm);
-            __syncthreads();
-        }
-    }
-}
-
-// ---- device-wide stable LSD radix sort of (uint32 key, uint32 value) ----
-constexpr int kRsItems = 16;
-constexpr int kRsTile = kThreads * kRsItems;  // keys per block and pass
-
-__global__ __launch_bounds__(kThreads) void k_rs_hist(const uint32_t *__restrict__ keys, uint64_t n, int shift,
-                                                      int nb, uint32_t *__restrict__ hist) {
-    __shared__ uint32_t s_h[256];
-    s_h[threadIdx.x] = 0;
-    __syncthreads();
-    const uint64_t beg = (uint64_t)blockIdx.x * kRsTile;
-    const uint64_t end = min(beg + kRsTile, n);
-    for (uint64_t i = beg + threadIdx.x; i < end; i += kThreads) atomicAdd(&s_h[(keys[i] >> shift) & 0xff], 1u);
-    __syncthreads();
-    hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = s_h[threadIdx.x];  // digit-major
-}
-
-__global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t *__restrict__ keys,
-                                                         const uint32_t *__restrict__ vals,
-                                                         uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
-                                                         uint64_t n, int shift, int nb,
-                                                         const uint64_t *__restrict__ offsets) {
-    __shared__ uint32_t s_off[256];
-    __shared__ uint32_t s_wcnt[4 * 256];
-    for (int i = threadIdx.x; i < 4 * 256; i += kThreads) s_wcnt[i] = 0;
-    s_off[threadIdx.x] = (uint32_t)offsets[(uint64_t)threadIdx.x * nb + blockIdx.x];
-    __syncthreads();
-    const uint64_t beg = (uint64_t)blockIdx.x * kRsTile;
-    const uint64_t end = min(beg + kRsTile, n);
-    stable_scatter<uint32_t, true>(keys, vals, keys_out, vals_out, beg, end, shift, s_off, s_wcnt);
 }
 
 }  // namespace
@@ -338,54 +231,63 @@ void launch_fill_u64(hipStream_t s, unsigned long long *p, uint64_t n, unsigned 
 
 uint64_t scan_tmp_elems(uint64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
-void launch_scan(hipStream_t s, const uint32_t *count, uint64_t n, uint64_t *offsets, uint64_t *tmp) {
+void launch_scan(hipStream_t s, const uint32_t *count, uint64_t n, uint64_t *offsets, uint64_t *tmp,
+                 const uint64_t *d_n) {
     const uint64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb == 0) {
         launch_fill_u64(s, reinterpret_cast<unsigned long long *>(offsets), 1, 0ull);
         return;
     }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, count, n, tmp);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, count, n, d_n, tmp);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kThreads), 0, s, tmp, nb, offsets + n);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, count, n, tmp, offsets);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, count, n, d_n, tmp, offsets);
 }
 
-void launch_tile_sort(hipStream_t s, uint64_t *pairs, uint64_t *pairs_tmp, const uint64_t *offsets, int n_tiles,
-                      int n_poses, uint64_t capacity, const uint32_t *inv_perm, uint32_t *long_list,
-                      unsigned long long *counters) {
-    if (n_tiles <= 0 || n_poses <= 0) return;
-    hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)n_tiles, (unsigned)n_poses), dim3(kThreads), 0, s, pairs,
-                       offsets, n_tiles, capacity, inv_perm, long_list, counters);
-    hipLaunchKernelGGL(k_long_sort, dim3(1024), dim3(kThreads), 0, s, pairs, pairs_tmp, offsets, capacity,
-                       inv_perm, long_list, counters);
+uint64_t radix_tmp_elems(uint64_t n_max) {
+    const uint64_t nb = std::max<uint64_t>(1, (n_max + kRsTile - 1) / kRsTile);
+    return (256 * nb + 1) / 2 + 1 + (256 * nb + 1) + scan_tmp_elems(256 * nb);  // uint64 units
 }
 
-uint64_t radix_tmp_elems(uint64_t n) {
-    const uint64_t nb = (n + kRsTile - 1) / kRsTile;
-    return 256 * nb / 2 + 1 + (256 * nb + 1) + scan_tmp_elems(256 * nb);  // u64 units
-}
-
-void launch_radix_sort_u32(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp,
-                           uint64_t n, int bits, uint64_t *tmp) {
-    if (n <= 1) return;
-    const uint64_t nb = (n + kRsTile - 1) / kRsTile;
+template <typename K>
+void launch_radix_sort(hipStream_t s, K *keys, uint32_t *vals, K *keys_tmp, uint32_t *vals_tmp, uint64_t n_max,
+                       const uint64_t *d_n, int begin_bit, int end_bit, uint64_t *tmp) {
+    if (n_max == 0 || end_bit <= begin_bit) return;
+    const uint64_t nb = (n_max + kRsTile - 1) / kRsTile;
     uint32_t *hist = reinterpret_cast<uint32_t *>(tmp);
-    uint64_t *offs = tmp + 256 * nb / 2 + 1;
+    uint64_t *offs = tmp + (256 * nb + 1) / 2 + 1;
     uint64_t *stmp = offs + 256 * nb + 1;
-    uint32_t *ks = keys, *vs = vals, *kd = keys_tmp, *vd = vals_tmp;
-    const int passes = (bits + 7) / 8;
-    for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(kThreads), 0, s, ks, n, shift, (int)nb, hist);
-        launch_scan(s, hist, 256 * nb, offs, stmp);
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kThreads), 0, s, ks, vs, kd, vd, n, shift,
-                           (int)nb, offs);
+    K *ks = keys, *kd = keys_tmp;
+    uint32_t *vs = vals, *vd = vals_tmp;
+    for (int shift = begin_bit; shift < end_bit; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nb), dim3(kThreads), 0, s, ks, d_n, n_max, shift, (int)nb,
+                           hist);
+        launch_scan(s, hist, 256 * nb, offs, stmp, nullptr);
+        hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nb), dim3(kThreads), 0, s, ks, vs, kd, vd, d_n, n_max,
+                           shift, (int)nb, offs);
         std::swap(ks, kd);
         std::swap(vs, vd);
     }
     if (ks != keys) {
-        (void)hipMemcpyAsync(keys, ks, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
-        (void)hipMemcpyAsync(vals, vs, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        const unsigned blocks = (unsigned)std::min<uint64_t>((n_max + kThreads - 1) / kThreads, 4096);
+        if (sizeof(K) == 8)
+            hipLaunchKernelGGL(k_copy_u64, dim3(blocks), dim3(kThreads), 0, s, (const uint64_t *)ks,
+                               (uint64_t *)keys, d_n, n_max);
+        else
+            hipLaunchKernelGGL(k_copy_u32, dim3(blocks), dim3(kThreads), 0, s, (const uint32_t *)ks,
+                               (uint32_t *)keys, d_n, n_max);
+        hipLaunchKernelGGL(k_copy_u32, dim3(blocks), dim3(kThreads), 0, s, vs, vals, d_n, n_max);
     }
+}
+
+template void launch_radix_sort<uint32_t>(hipStream_t, uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint64_t,
+                                          const uint64_t *, int, int, uint64_t *);
+template void launch_radix_sort<uint64_t>(hipStream_t, uint64_t *, uint32_t *, uint64_t *, uint32_t *, uint64_t,
+                                          const uint64_t *, int, int, uint64_t *);
+
+void launch_ranges(hipStream_t s, const uint32_t *keys, const uint64_t *d_n, uint64_t n_max, uint64_t n_lists,
+                   uint64_t *offsets) {
+    const unsigned blocks = (unsigned)std::min<uint64_t>((n_lists + 1 + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(kThreads), 0, s, keys, d_n, n_max, n_lists, offsets);
 }
 
 }  // namespace gsr

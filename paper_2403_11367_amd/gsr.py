@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libgsr.so")
 GSR_OK = 0
 STATUS = {0: "GSR_OK", -1: "GSR_EINVAL", -2: "GSR_ENOMEM", -3: "GSR_EHIP", -4: "GSR_ENODEV",
           -5: "GSR_EOVERFLOW", -6: "GSR_EUNSUPPORTED", -7: "GSR_EDEVICE"}
-BUF_RECORDS, BUF_NTILES, BUF_OFFSETS, BUF_PAIRS, BUF_PERM = 0, 1, 2, 3, 4
+BUF_RECORDS, BUF_NTILES, BUF_OFFSETS, BUF_PAIRS = 0, 1, 2, 3
 RENDER_COUNT_EVALS = 1
 
 # every symbol declared in include/gsr.h
@@ -53,7 +53,7 @@ class RenderCfg(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("n_submap", C.c_int64), ("n_poses", C.c_int64), ("n_visible", C.c_int64),
-                ("n_pairs", C.c_int64), ("pair_capacity", C.c_int64), ("n_long_tiles", C.c_int64),
+                ("n_pairs", C.c_int64), ("pair_capacity", C.c_int64),
                 ("evals_contrib", C.c_int64), ("evals_lanes", C.c_int64),
                 ("overflow", C.c_int32), ("bad_index", C.c_int32),
                 ("n_profiled_renders", C.c_int32), ("n_profiled_ncc", C.c_int32),
@@ -297,7 +297,7 @@ class Context:
         nb = C.c_int64(0)
         self._check(LIB.gsr_debug_size(self.handle, which, C.byref(nb)), "gsr_debug_size")
         dt = {BUF_RECORDS: np.float32, BUF_NTILES: np.uint32, BUF_OFFSETS: np.uint64,
-              BUF_PAIRS: np.uint64, BUF_PERM: np.uint32}[which]
+              BUF_PAIRS: np.uint32}[which]
         out = np.empty(nb.value // np.dtype(dt).itemsize, dtype=dt)
         if out.size:
             self._check(LIB.gsr_debug_copy(self.handle, which, out.ctypes.data, nb.value), "gsr_debug_copy")

@@ -46,22 +46,11 @@ def gpu_render(ctx, sm, cam, poses, cfg=None):
 
 
 def gpu_buffers(ctx):
-    """Records and tile counts reordered to submap order; sorted pairs with their
-    low 32 bits mapped back to submap indices."""
-    from paper_2403_11367_amd import BUF_NTILES, BUF_OFFSETS, BUF_PAIRS, BUF_PERM, BUF_RECORDS
-    perm = ctx.debug_buffer(BUF_PERM).astype(np.int64)
-    n = perm.size
-    rec = ctx.debug_buffer(BUF_RECORDS).reshape(-1, n, 12)
-    nt = ctx.debug_buffer(BUF_NTILES).reshape(-1, n)
-    assert np.array_equal(np.sort(perm), np.arange(n)), "internal order is not a permutation"
-    rec_s = np.empty_like(rec)
-    rec_s[:, perm] = rec
-    nt_s = np.empty_like(nt)
-    nt_s[:, perm] = nt
-    pairs = ctx.debug_buffer(BUF_PAIRS)
-    hi = pairs & np.uint64(0xFFFFFFFF00000000)
-    low = perm[(pairs & np.uint64(0xFFFFFFFF)).astype(np.int64)].astype(np.uint64) if n else pairs
-    return rec_s.reshape(-1), nt_s.reshape(-1), ctx.debug_buffer(BUF_OFFSETS), hi | low
+    """Records, tile counts, list offsets and the sorted pair list (submap indices);
+    check_pairs rebuilds the keys from the offsets and the records' depth bits."""
+    from paper_2403_11367_amd import BUF_NTILES, BUF_OFFSETS, BUF_PAIRS, BUF_RECORDS
+    recs = ctx.debug_buffer(BUF_RECORDS)
+    return recs, ctx.debug_buffer(BUF_NTILES), ctx.debug_buffer(BUF_OFFSETS), (recs, ctx.debug_buffer(BUF_PAIRS))
 
 
 def oracle_pose(prep, pose, cam, tile=(16, 16)):
@@ -90,18 +79,22 @@ def check_records(rec_gpu, nt_gpu, rec, n, p):
 
 
 def check_pairs(off_gpu, pairs_gpu, ks, vs, rng, p, n_tiles):
-    """Bit-exact keys and sorted order of pose p against the oracle's lexsort."""
+    """Bit-exact keys and sorted order of pose p against the oracle's lexsort.
+    The GPU key of a pair is rebuilt as (tile << 32) | depth bits of its record."""
+    recs, vals = pairs_gpu
     lo, hi = int(off_gpu[p * n_tiles]), int(off_gpu[(p + 1) * n_tiles])
-    seg = pairs_gpu[lo:hi]
+    seg = vals[lo:hi].astype(np.int64)
     starts = off_gpu[p * n_tiles:(p + 1) * n_tiles].astype(np.int64) - lo
     ends = off_gpu[p * n_tiles + 1:(p + 1) * n_tiles + 1].astype(np.int64) - lo
     assert np.array_equal(starts, rng[:, 0]) and np.array_equal(ends, rng[:, 1]), "tile ranges differ"
+    assert seg.size == vs.size
+    assert np.array_equal(seg.astype(np.uint32), vs), "sort order differs"
     tile_of = np.repeat(np.arange(n_tiles, dtype=np.uint64), (ends - starts))
-    gkeys = (tile_of << np.uint64(32)) | (seg >> np.uint64(32))
-    gvals = (seg & np.uint64(0xFFFFFFFF)).astype(np.uint32)
-    assert gkeys.size == ks.size
+    n_total = recs.size // 12
+    n_g = n_total // ((off_gpu.size - 1) // n_tiles)
+    z = recs.reshape(-1, n_g, 12)[p][seg, 9].view(np.uint32).astype(np.uint64)
+    gkeys = (tile_of << np.uint64(32)) | z
     assert np.array_equal(gkeys, ks), "keys differ"
-    assert np.array_equal(gvals, vs), "sort order differs"
 
 
 def compare_render(rgb, dep, tf, ref, label="", tol_depth=TOL_DEPTH):
