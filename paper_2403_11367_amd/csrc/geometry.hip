@@ -172,66 +172,36 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
         vcount[(int64_t)(p0 + threadIdx.x) * gridDim.x + blockIdx.x] = s_vis[threadIdx.x];
 }
 
-// Compaction of visible entries in (pose, index) order: entry j gets
-// key (pose << 32 | depth bits) and value index. voff holds the exclusive scan
-// of vcount (same block layout as k_preprocess, one pose per blockIdx.y).
-__global__ __launch_bounds__(kThreads) void k_compact(const float4 *__restrict__ records,
-                                                      const uint32_t *__restrict__ ntiles, int64_t n,
-                                                      const uint64_t *__restrict__ voff,
-                                                      uint64_t *__restrict__ dkey, uint32_t *__restrict__ dval) {
-    __shared__ uint32_t s_wave[4];
+// S2, pair emission in (pose, index) order: Gaussian (p, g) writes one pair per
+// tile of its rectangle (row-major) at pair_off[p * n + g] (exclusive scan of
+// the tile counts): tile id within the pose, depth bits, submap index.
+__global__ __launch_bounds__(kThreads) void k_emit(const float4 *__restrict__ records,
+                                                   const uint32_t *__restrict__ ntiles, int64_t n,
+                                                   const uint64_t *__restrict__ pair_off, TileGrid tg,
+                                                   uint32_t *__restrict__ ptile, uint32_t *__restrict__ pz,
+                                                   uint32_t *__restrict__ pk, uint64_t capacity,
+                                                   int *__restrict__ flags) {
     const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const int p = blockIdx.y;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const bool vis = g < n && ntiles[(int64_t)p * n + g] != 0;
-    const uint64_t m = __ballot(vis);
-    if (lane == 0) s_wave[wave] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (!vis) return;
-    uint32_t pre = (uint32_t)__popcll(m & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
-    for (int w = 0; w < wave; ++w) pre += s_wave[w];
-    const uint64_t j = voff[(int64_t)p * gridDim.x + blockIdx.x] + pre;
-    const float z = records[((int64_t)p * n + g) * kRecordQuads + 2].y;
-    dkey[j] = ((uint64_t)p << 32) | __float_as_uint(z);
-    dval[j] = (uint32_t)g;
-}
-
-// Tiles touched by each depth-sorted entry (entries past the visible count get 0).
-__global__ void k_pair_counts(const uint64_t *__restrict__ dkey, const uint32_t *__restrict__ dval,
-                              const uint64_t *__restrict__ d_nvis, uint64_t n_max, const uint32_t *__restrict__ ntiles,
-                              int64_t n, uint32_t *__restrict__ cnt) {
-    const uint64_t nv = min(*d_nvis, n_max);
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nv; j += (uint64_t)gridDim.x * blockDim.x)
-        cnt[j] = ntiles[(int64_t)(dkey[j] >> 32) * n + dval[j]];
-}
-
-// Pair emission in depth order: entry j writes its tiles (row-major) at
-// pair_off[j]..: key = pose * n_tiles + tile, value = submap index.
-__global__ void k_emit(const uint64_t *__restrict__ dkey, const uint32_t *__restrict__ dval,
-                       const uint64_t *__restrict__ d_nvis, uint64_t n_max, const uint64_t *__restrict__ pair_off,
-                       const float4 *__restrict__ records, int64_t n, TileGrid tg, uint32_t *__restrict__ pkey,
-                       uint32_t *__restrict__ pval, uint64_t capacity, int *__restrict__ flags) {
-    const uint64_t nv = min(*d_nvis, n_max);
+    if (g >= n) return;
+    const int64_t rg = (int64_t)blockIdx.y * n + g;
+    if (ntiles[rg] == 0) return;
+    const float4 q2 = records[rg * kRecordQuads + 2];
+    const uint32_t zb = __float_as_uint(q2.y);
+    const uint32_t rxb = __float_as_uint(q2.z), ryb = __float_as_uint(q2.w);
+    const int tx0 = (int)(rxb & 0xffffu) >> tg.log2_w, tx1 = (int)(rxb >> 16) >> tg.log2_w;
+    const int ty0 = (int)(ryb & 0xffffu) >> tg.log2_h, ty1 = (int)(ryb >> 16) >> tg.log2_h;
+    uint64_t pos = pair_off[rg];
     bool over = false;
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nv; j += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t p = (uint32_t)(dkey[j] >> 32);
-        const uint32_t g = dval[j];
-        const float4 q2 = records[((int64_t)p * n + g) * kRecordQuads + 2];
-        const uint32_t rxb = __float_as_uint(q2.z), ryb = __float_as_uint(q2.w);
-        const int tx0 = (int)(rxb & 0xffffu) >> tg.log2_w, tx1 = (int)(rxb >> 16) >> tg.log2_w;
-        const int ty0 = (int)(ryb & 0xffffu) >> tg.log2_h, ty1 = (int)(ryb >> 16) >> tg.log2_h;
-        uint64_t pos = pair_off[j];
-        const uint32_t base = p * (uint32_t)tg.n_tiles;
-        for (int yy = ty0; yy <= ty1; ++yy)
-            for (int xx = tx0; xx <= tx1; ++xx, ++pos) {
-                if (pos < capacity) {
-                    pkey[pos] = base + (uint32_t)(yy * tg.tiles_x + xx);
-                    pval[pos] = g;
-                } else {
-                    over = true;
-                }
+    for (int yy = ty0; yy <= ty1; ++yy)
+        for (int xx = tx0; xx <= tx1; ++xx, ++pos) {
+            if (pos < capacity) {
+                ptile[pos] = (uint32_t)(yy * tg.tiles_x + xx);
+                pz[pos] = zb;
+                pk[pos] = (uint32_t)g;
+            } else {
+                over = true;
             }
-    }
+        }
     if (over) atomicOr(&flags[FLAG_OVERFLOW], 1);
 }
 
@@ -257,27 +227,13 @@ void launch_preprocess(hipStream_t s, const float4 *packed, int64_t n, const flo
                        ntiles, vcount);
 }
 
-void launch_compact(hipStream_t s, const float4 *records, const uint32_t *ntiles, int64_t n, int n_poses,
-                    const uint64_t *voff, uint64_t *dkey, uint32_t *dval) {
+void launch_emit(hipStream_t s, const float4 *records, const uint32_t *ntiles, int64_t n, int n_poses,
+                 const uint64_t *pair_off, const TileGrid &tg, uint32_t *ptile, uint32_t *pz, uint32_t *pk,
+                 uint64_t capacity, int *flags) {
     if (n <= 0) return;
     const dim3 grid((unsigned)preprocess_blocks(n), (unsigned)n_poses);
-    hipLaunchKernelGGL(k_compact, grid, dim3(kThreads), 0, s, records, ntiles, n, voff, dkey, dval);
-}
-
-void launch_pair_counts(hipStream_t s, const uint64_t *dkey, const uint32_t *dval, const uint64_t *d_nvis,
-                        uint64_t n_max, const uint32_t *ntiles, int64_t n, uint32_t *cnt) {
-    if (n_max == 0) return;
-    const unsigned blocks = (unsigned)std::min<uint64_t>((n_max + kThreads - 1) / kThreads, 8192);
-    hipLaunchKernelGGL(k_pair_counts, dim3(blocks), dim3(kThreads), 0, s, dkey, dval, d_nvis, n_max, ntiles, n, cnt);
-}
-
-void launch_emit(hipStream_t s, const uint64_t *dkey, const uint32_t *dval, const uint64_t *d_nvis, uint64_t n_max,
-                 const uint64_t *pair_off, const float4 *records, int64_t n, const TileGrid &tg, uint32_t *pkey,
-                 uint32_t *pval, uint64_t capacity, int *flags) {
-    if (n_max == 0) return;
-    const unsigned blocks = (unsigned)std::min<uint64_t>((n_max + kThreads - 1) / kThreads, 8192);
-    hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(kThreads), 0, s, dkey, dval, d_nvis, n_max, pair_off, records, n,
-                       tg, pkey, pval, capacity, flags);
+    hipLaunchKernelGGL(k_emit, grid, dim3(kThreads), 0, s, records, ntiles, n, pair_off, tg, ptile, pz, pk, capacity,
+                       flags);
 }
 
 }  // namespace gsr

@@ -12,7 +12,7 @@ namespace gsr {
 // Device flag slots (int32 each), raised by kernels, read and cleared by gsr_sync.
 enum : int { FLAG_OVERFLOW = 0, FLAG_BAD_INDEX = 1, FLAG_COUNT = 4 };
 // Device counter slots (uint64 each), reset at the start of a render.
-enum : int { CNT_EVALS_CONTRIB = 0, CNT_EVALS_LANES = 1, CNT_COUNT = 4 };
+enum : int { CNT_EVALS_CONTRIB = 0, CNT_EVALS_LANES = 1, CNT_LONG_LISTS = 2, CNT_COUNT = 4 };
 
 // Packed submap record: 4 float4 (64 B) per Gaussian.
 //   q0 = (mu_x, mu_y, mu_z, opacity)
@@ -27,6 +27,9 @@ constexpr int kPackedQuads = 4;
 //   q2 = (b, z, rect_x bits, rect_y bits)   rect_x = i0 | i1 << 16
 constexpr int kRecordQuads = 3;
 
+
+// Tiles per pose the LDS bucketing handles (larger images are rejected).
+constexpr int kMaxTilesPerPose = 16384;
 
 struct Camera {
     int width, height;
@@ -59,14 +62,10 @@ int64_t preprocess_blocks(int64_t n);
 void launch_preprocess(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
                        uint32_t *ntiles, uint32_t *vcount);
-// Visible entries in (pose, index) order: dkey = pose << 32 | depth bits, dval = index.
-void launch_compact(hipStream_t s, const float4 *records, const uint32_t *ntiles, int64_t n, int n_poses,
-                    const uint64_t *voff, uint64_t *dkey, uint32_t *dval);
-void launch_pair_counts(hipStream_t s, const uint64_t *dkey, const uint32_t *dval, const uint64_t *d_nvis,
-                        uint64_t n_max, const uint32_t *ntiles, int64_t n, uint32_t *cnt);
-void launch_emit(hipStream_t s, const uint64_t *dkey, const uint32_t *dval, const uint64_t *d_nvis, uint64_t n_max,
-                 const uint64_t *pair_off, const float4 *records, int64_t n, const TileGrid &tg, uint32_t *pkey,
-                 uint32_t *pval, uint64_t capacity, int *flags);
+// Pairs in (pose, index) order: tile id within the pose, depth bits, submap index.
+void launch_emit(hipStream_t s, const float4 *records, const uint32_t *ntiles, int64_t n, int n_poses,
+                 const uint64_t *pair_off, const TileGrid &tg, uint32_t *ptile, uint32_t *pz, uint32_t *pk,
+                 uint64_t capacity, int *flags);
 
 // ---- sort.hip ----
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t value);
@@ -77,16 +76,19 @@ void launch_fill_u64(hipStream_t s, unsigned long long *p, uint64_t n, unsigned 
 uint64_t scan_tmp_elems(uint64_t n);
 void launch_scan(hipStream_t s, const uint32_t *count, uint64_t n, uint64_t *offsets, uint64_t *tmp,
                  const uint64_t *d_n);
-// Device-wide stable LSD radix sort (8-bit digits) of min(*d_n, n_max) (or
-// n_max) key/value pairs on key bits [begin_bit, end_bit); the result ends in
-// keys/vals. tmp must hold radix_tmp_elems(n_max) uint64.
-uint64_t radix_tmp_elems(uint64_t n_max);
-template <typename K>
-void launch_radix_sort(hipStream_t s, K *keys, uint32_t *vals, K *keys_tmp, uint32_t *vals_tmp, uint64_t n_max,
-                       const uint64_t *d_n, int begin_bit, int end_bit, uint64_t *tmp);
-// offsets[t] = first position of key t in sorted keys, t in [0, n_lists]; offsets[n_lists] = n.
-void launch_ranges(hipStream_t s, const uint32_t *keys, const uint64_t *d_n, uint64_t n_max, uint64_t n_lists,
-                   uint64_t *offsets);
+// Stable counting sort of the emitted pairs by tile within each pose. Writes
+// the per-(pose, tile) list offsets [P*T + 1] and the bucketed (depth bits,
+// index) arrays sz, sk. cnt holds bucket_blocks_max(capacity, P) * T entries,
+// total P * T, block_base P + 1; n_tiles <= kMaxTilesPerPose.
+uint64_t bucket_blocks_max(uint64_t capacity, int n_poses);
+void launch_bucket(hipStream_t s, const uint32_t *ptile, const uint32_t *pz, const uint32_t *pk,
+                   const uint64_t *pair_off, int64_t n, int n_poses, uint64_t capacity, int n_tiles, int tile_bits,
+                   uint32_t *block_base, uint32_t *cnt, uint32_t *total, uint64_t *offsets, uint64_t *scan_tmp,
+                   uint32_t *sz, uint32_t *sk);
+// Sorts every list by depth bits (stable); sk ends in front-to-back order.
+// tz, tk: scratch as large as sz, sk; queue: P * T entries.
+void launch_list_sort(hipStream_t s, uint32_t *sz, uint32_t *sk, uint32_t *tz, uint32_t *tk, const uint64_t *offsets,
+                      int n_tiles, int n_poses, uint32_t *queue, unsigned long long *counters);
 
 // ---- blend.hip ----
 void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,

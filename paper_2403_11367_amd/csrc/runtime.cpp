@@ -34,8 +34,8 @@ struct gsr_ctx {
     struct Buf {
         void *p = nullptr;
         size_t bytes = 0;
-    } records, ntiles, vcount, voff, scan_tmp, dkey, dval, dkey_tmp, dval_tmp, pkey, pval, pkey_tmp, pval_tmp,
-        radix_tmp, offsets, grey_q, partials;
+    } records, ntiles, vcount, voff, pair_off, scan_tmp, ptile, pz, pk, sz, sk, cnt, total, block_base, queue,
+        offsets, grey_q, partials;
     // last render
     int64_t last_n = 0, last_poses = 0, last_tiles = 0;
     uint64_t last_capacity = 0;
@@ -201,10 +201,10 @@ int gsr_destroy(gsr_ctx *ctx) {
     if (!ctx) return GSR_EINVAL;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    gsr_ctx::Buf *bufs[] = {&ctx->records,  &ctx->ntiles,   &ctx->vcount,   &ctx->voff,     &ctx->scan_tmp,
-                            &ctx->dkey,     &ctx->dval,     &ctx->dkey_tmp, &ctx->dval_tmp, &ctx->pkey,
-                            &ctx->pval,     &ctx->pkey_tmp, &ctx->pval_tmp, &ctx->radix_tmp, &ctx->offsets,
-                            &ctx->grey_q,   &ctx->partials};
+    gsr_ctx::Buf *bufs[] = {&ctx->records, &ctx->ntiles, &ctx->vcount, &ctx->voff,       &ctx->pair_off,
+                            &ctx->scan_tmp, &ctx->ptile, &ctx->pz,     &ctx->pk,         &ctx->sz,
+                            &ctx->sk,       &ctx->cnt,   &ctx->total,  &ctx->block_base, &ctx->queue,
+                            &ctx->offsets,  &ctx->grey_q, &ctx->partials};
     for (auto *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
@@ -314,6 +314,8 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     const int64_t n = sm->n;
     const int64_t P = n_poses;
     const uint64_t n_lists = (uint64_t)P * tg.n_tiles;
+    if (tg.n_tiles > gsr::kMaxTilesPerPose)
+        return fail(ctx, GSR_EUNSUPPORTED, "more than 16384 tiles per image");
     if (n_lists >= 0xffffffffull) return fail(ctx, GSR_EINVAL, "poses x tiles must be below 2^32");
     const uint64_t pn = (uint64_t)std::max<int64_t>(1, P * n);
     const uint64_t nbp = (uint64_t)std::max<int64_t>(1, gsr::preprocess_blocks(n));
@@ -323,26 +325,23 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
         (rc = ensure(ctx, ctx->ntiles, pn * sizeof(uint32_t), "ntiles")) ||
         (rc = ensure(ctx, ctx->vcount, nvc * sizeof(uint32_t), "visible counts")) ||
         (rc = ensure(ctx, ctx->voff, (nvc + 1) * sizeof(uint64_t), "visible offsets")) ||
-        (rc = ensure(ctx, ctx->scan_tmp, gsr::scan_tmp_elems(std::max(nvc, pn)) * sizeof(uint64_t), "scan")) ||
-        (rc = ensure(ctx, ctx->dkey, pn * sizeof(uint64_t), "depth keys")) ||
-        (rc = ensure(ctx, ctx->dval, pn * sizeof(uint32_t), "depth values")) ||
-        (rc = ensure(ctx, ctx->dkey_tmp, (pn + 1) * sizeof(uint64_t), "depth keys tmp")) ||
-        (rc = ensure(ctx, ctx->dval_tmp, pn * sizeof(uint32_t), "depth values tmp")) ||
-        (rc = ensure(ctx, ctx->offsets, (n_lists + 1) * sizeof(uint64_t), "offsets")))
+        (rc = ensure(ctx, ctx->pair_off, (pn + 1) * sizeof(uint64_t), "pair offsets")) ||
+        (rc = ensure(ctx, ctx->scan_tmp, gsr::scan_tmp_elems(std::max(std::max(nvc, pn), n_lists)) * sizeof(uint64_t),
+                     "scan")) ||
+        (rc = ensure(ctx, ctx->offsets, (n_lists + 1) * sizeof(uint64_t), "offsets")) ||
+        (rc = ensure(ctx, ctx->total, n_lists * sizeof(uint32_t), "list totals")) ||
+        (rc = ensure(ctx, ctx->block_base, ((uint64_t)P + 1) * sizeof(uint32_t), "block bases")) ||
+        (rc = ensure(ctx, ctx->queue, n_lists * sizeof(uint32_t), "long-list queue")))
         return rc;
     hipStream_t s = ctx->stream;
-    uint32_t *vcount = (uint32_t *)ctx->vcount.p;
-    uint64_t *voff = (uint64_t *)ctx->voff.p;
-    uint64_t *dkey = (uint64_t *)ctx->dkey.p, *dkey_tmp = (uint64_t *)ctx->dkey_tmp.p;
-    uint32_t *dval = (uint32_t *)ctx->dval.p, *dval_tmp = (uint32_t *)ctx->dval_tmp.p;
     uint32_t *ntiles = (uint32_t *)ctx->ntiles.p;
+    uint32_t *vcount = (uint32_t *)ctx->vcount.p;
+    uint64_t *pair_off = (uint64_t *)ctx->pair_off.p;
+    uint64_t *scan_tmp = (uint64_t *)ctx->scan_tmp.p;
     const float4 *records = (const float4 *)ctx->records.p;
     uint64_t *offsets = (uint64_t *)ctx->offsets.p;
-    const uint64_t *d_nvis = voff + nvc;
-    int pose_bits = 0;
-    while ((1ll << pose_bits) < P) ++pose_bits;
-    int list_bits = 1;
-    while ((1ull << list_bits) < n_lists) ++list_bits;
+    int tile_bits = 1;
+    while ((1 << tile_bits) < tg.n_tiles) ++tile_bits;
 
     gsr_ctx::RenderEv *ev = nullptr;
     if (ctx->profile) {
@@ -350,26 +349,21 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
         HIPC(ctx, hipEventRecord(ev->e[0], s));
     }
     gsr::launch_fill_u64(s, ctx->d_counters, gsr::CNT_COUNT, 0ull);
-    if (n == 0) gsr::launch_fill_u32(s, vcount, nvc, 0u);
+    if (n == 0) {
+        gsr::launch_fill_u32(s, vcount, nvc, 0u);
+        gsr::launch_fill_u32(s, ntiles, pn, 0u);
+    }
     gsr::launch_preprocess(s, sm->packed, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p, ntiles, vcount);
     if ((rc = check_launch(ctx, "preprocess"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[1], s));
-    // S2: visible entries, depth order, pair counts and offsets
-    gsr::launch_scan(s, vcount, nvc, voff, (uint64_t *)ctx->scan_tmp.p, nullptr);
-    gsr::launch_compact(s, records, ntiles, n, n_poses, voff, dkey, dval);
-    if ((rc = ensure(ctx, ctx->radix_tmp, gsr::radix_tmp_elems(pn) * sizeof(uint64_t), "radix"))) return rc;
-    gsr::launch_radix_sort<uint64_t>(s, dkey, dval, dkey_tmp, dval_tmp, pn, d_nvis, 0, 32 + pose_bits,
-                                     (uint64_t *)ctx->radix_tmp.p);
-    uint32_t *cnt = dval_tmp;
-    uint64_t *pair_off = dkey_tmp;
-    gsr::launch_pair_counts(s, dkey, dval, d_nvis, pn, ntiles, n, cnt);
-    gsr::launch_scan(s, cnt, pn, pair_off, (uint64_t *)ctx->scan_tmp.p, d_nvis);
-    const uint64_t *d_npairs = pair_off + pn;
-    if ((rc = check_launch(ctx, "depth order"))) return rc;
+    // S2: visible count (stats), pair offsets in (pose, index) order
+    gsr::launch_scan(s, vcount, nvc, (uint64_t *)ctx->voff.p, scan_tmp, nullptr);
+    gsr::launch_scan(s, ntiles, pn, pair_off, scan_tmp, nullptr);
+    if ((rc = check_launch(ctx, "pair offsets"))) return rc;
 
     uint64_t capacity;
     if (cfg.pair_capacity == 0) {
-        HIPC(ctx, hipMemcpyAsync(ctx->h_pin, d_npairs, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        HIPC(ctx, hipMemcpyAsync(ctx->h_pin, pair_off + pn, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
         HIPC(ctx, hipStreamSynchronize(s));
         capacity = ctx->h_pin[0];
         ctx->last_pairs = (int64_t)capacity;
@@ -377,23 +371,29 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
         capacity = (uint64_t)cfg.pair_capacity;
         ctx->last_pairs = -1;
     }
+    if (capacity >= 0xffffffffull) return fail(ctx, GSR_EINVAL, "pair count must be below 2^32");
     const uint64_t cap1 = std::max<uint64_t>(1, capacity);
-    if ((rc = ensure(ctx, ctx->pkey, cap1 * sizeof(uint32_t), "pair keys")) ||
-        (rc = ensure(ctx, ctx->pval, cap1 * sizeof(uint32_t), "pair values")) ||
-        (rc = ensure(ctx, ctx->pkey_tmp, cap1 * sizeof(uint32_t), "pair keys tmp")) ||
-        (rc = ensure(ctx, ctx->pval_tmp, cap1 * sizeof(uint32_t), "pair values tmp")) ||
-        (rc = ensure(ctx, ctx->radix_tmp, gsr::radix_tmp_elems(std::max<uint64_t>(pn, cap1)) * sizeof(uint64_t),
-                     "radix")))
+    const uint64_t nbm = gsr::bucket_blocks_max(capacity, n_poses);
+    if ((rc = ensure(ctx, ctx->ptile, cap1 * sizeof(uint32_t), "pair tiles")) ||
+        (rc = ensure(ctx, ctx->pz, cap1 * sizeof(uint32_t), "pair depths")) ||
+        (rc = ensure(ctx, ctx->pk, cap1 * sizeof(uint32_t), "pair indices")) ||
+        (rc = ensure(ctx, ctx->sz, cap1 * sizeof(uint32_t), "list depths")) ||
+        (rc = ensure(ctx, ctx->sk, cap1 * sizeof(uint32_t), "list indices")) ||
+        (rc = ensure(ctx, ctx->cnt, nbm * tg.n_tiles * sizeof(uint32_t), "bucket counts")))
         return rc;
-    uint32_t *pkey = (uint32_t *)ctx->pkey.p, *pval = (uint32_t *)ctx->pval.p;
-    // S3: pairs in depth order, then a stable sort by (pose, tile); S4: list ranges
-    gsr::launch_emit(s, dkey, dval, d_nvis, pn, pair_off, records, n, tg, pkey, pval, capacity, ctx->d_flags);
-    gsr::launch_radix_sort<uint32_t>(s, pkey, pval, (uint32_t *)ctx->pkey_tmp.p, (uint32_t *)ctx->pval_tmp.p,
-                                     capacity, d_npairs, 0, list_bits, (uint64_t *)ctx->radix_tmp.p);
-    gsr::launch_ranges(s, pkey, d_npairs, capacity, n_lists, offsets);
+    uint32_t *pz = (uint32_t *)ctx->pz.p, *pk = (uint32_t *)ctx->pk.p;
+    uint32_t *sz = (uint32_t *)ctx->sz.p, *sk = (uint32_t *)ctx->sk.p;
+    gsr::launch_emit(s, records, ntiles, n, n_poses, pair_off, tg, (uint32_t *)ctx->ptile.p, pz, pk, capacity,
+                     ctx->d_flags);
+    // S3: bucket by tile (stable), then sort every list by depth bits
+    gsr::launch_bucket(s, (const uint32_t *)ctx->ptile.p, pz, pk, pair_off, n, n_poses, capacity, tg.n_tiles,
+                       tile_bits, (uint32_t *)ctx->block_base.p, (uint32_t *)ctx->cnt.p, (uint32_t *)ctx->total.p,
+                       offsets, scan_tmp, sz, sk);
+    gsr::launch_list_sort(s, sz, sk, pz, pk, offsets, tg.n_tiles, n_poses, (uint32_t *)ctx->queue.p,
+                          ctx->d_counters);
     if ((rc = check_launch(ctx, "pair sort"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[2], s));
-    gsr::launch_blend(s, records, n, n_poses, pval, offsets, capacity, c, k, tg, rgb, depth, tfinal,
+    gsr::launch_blend(s, records, n, n_poses, sk, offsets, capacity, c, k, tg, rgb, depth, tfinal,
                       (cfg.flags & GSR_RENDER_COUNT_EVALS) != 0, ctx->d_counters);
     if ((rc = check_launch(ctx, "blend"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[3], s));
@@ -471,7 +471,7 @@ int gsr_get_stats(gsr_ctx *ctx, gsr_stats *out) {
         HIPC(ctx, hipMemcpy(&v, (uint64_t *)ctx->voff.p + ctx->last_vis_slot, sizeof(v), hipMemcpyDeviceToHost));
         out->n_visible = (int64_t)v;
         const uint64_t pn = (uint64_t)std::max<int64_t>(1, ctx->last_poses * ctx->last_n);
-        HIPC(ctx, hipMemcpy(&v, (uint64_t *)ctx->dkey_tmp.p + pn, sizeof(v), hipMemcpyDeviceToHost));
+        HIPC(ctx, hipMemcpy(&v, (uint64_t *)ctx->pair_off.p + pn, sizeof(v), hipMemcpyDeviceToHost));
         out->n_pairs = (int64_t)v;
     }
     out->overflow = flags[gsr::FLAG_OVERFLOW];
@@ -536,7 +536,7 @@ int gsr_debug_copy(gsr_ctx *ctx, int which, void *dst, int64_t bytes) {
     const void *src = which == GSR_BUF_RECORDS   ? ctx->records.p
                       : which == GSR_BUF_NTILES  ? ctx->ntiles.p
                       : which == GSR_BUF_OFFSETS ? ctx->offsets.p
-                                                 : ctx->pval.p;
+                                                 : ctx->sk.p;
     HIPC(ctx, hipMemcpy(dst, src, (size_t)bytes, hipMemcpyDeviceToHost));
     return GSR_OK;
 }

@@ -4,16 +4,15 @@
 // back. Per (pose, tile) the blend needs its Gaussians in ascending depth, with
 // equal depths in ascending submap index (a total order).
 //
-// Everything here is built on one primitive, a device-wide stable LSD radix
-// sort with 8-bit digits (k_rs_hist -> exclusive scan -> k_rs_scatter per
-// digit). Stability is what carries the order through:
-//   1. visible (pose, Gaussian) entries are compacted in (pose, index) order;
-//   2. they are radix-sorted by (pose, depth bits): ties keep index order;
-//   3. each entry emits one pair per tile it touches, in that depth order;
-//   4. the pairs are radix-sorted by (pose * T + tile): within a tile they keep
-//      depth order;
-//   5. each list's [start, end) is found by binary search in the sorted keys.
-// No atomics, so the result is deterministic run to run.
+// The pairs are emitted in (pose, submap index) order (geometry.hip). Then:
+//   1. a stable counting sort by tile, per pose, buckets them into per-(pose,
+//      tile) lists that keep index order (one pass over the pairs, no atomics
+//      outside LDS);
+//   2. every list is sorted by the depth bits with a stable LSD radix sort
+//      (8-bit digits, only the digits that vary in the list): in LDS for short
+//      and medium lists, in global memory by one block for very long ones.
+// Stability carries the index order through, so each list ends in (depth bits,
+// index) order. The result does not depend on scheduling.
 #include "internal.h"
 
 namespace gsr {
@@ -23,8 +22,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kScanItems = 8;  // per thread
 constexpr int kScanTile = kThreads * kScanItems;
-constexpr int kRsItems = 16;
-constexpr int kRsTile = kThreads * kRsItems;  // keys per block and pass
 
 __global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
@@ -108,110 +105,298 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restr
     }
 }
 
-__device__ __forceinline__ uint64_t dev_count(const uint64_t *d_n, uint64_t n_max) {
-    return d_n ? min(*d_n, n_max) : n_max;
+// ---- tile bucketing: a stable counting sort of the pairs by tile, per pose ----
+// The pairs of pose p occupy [seg(p), seg(p+1)) of the emission arrays, in
+// (submap index, tile) order. They are cut into blocks of kBP pairs; each block
+// counts its pairs per tile, the counts are summed per (pose, tile) and
+// scanned into list offsets, and each block then writes its pairs to
+// offset(list) + (pairs of the list in earlier blocks) + (rank within the
+// block), which keeps the emission order inside every list.
+constexpr int kBP = 4096;
+
+__device__ __forceinline__ uint64_t seg_start(const uint64_t *pair_off, int64_t n, int p, uint64_t capacity) {
+    return min(pair_off[(int64_t)p * n], capacity);
 }
 
-// Per-block digit histogram, stored digit-major: hist[d * nb + block].
-template <typename K>
-__global__ __launch_bounds__(kThreads) void k_rs_hist(const K *__restrict__ keys, const uint64_t *__restrict__ d_n,
-                                                      uint64_t n_max, int shift, int nb, uint32_t *__restrict__ hist) {
-    __shared__ uint32_t s_h[256];
-    s_h[threadIdx.x] = 0;
+// block_base[p] = sum over q < p of ceil(len(q) / kBP), for p in [0, P]. One block.
+__global__ __launch_bounds__(kThreads) void k_seg_blocks(const uint64_t *__restrict__ pair_off, int64_t n, int P,
+                                                         uint64_t capacity, uint32_t *__restrict__ block_base) {
+    __shared__ uint64_t s_wave[4];
+    __shared__ uint64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
-    const uint64_t n = dev_count(d_n, n_max);
-    const uint64_t beg = (uint64_t)blockIdx.x * kRsTile;
-    const uint64_t end = min(beg + kRsTile, n);
-    for (uint64_t i = beg + threadIdx.x; i < end; i += kThreads) atomicAdd(&s_h[(keys[i] >> shift) & 0xff], 1u);
-    __syncthreads();
-    hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = s_h[threadIdx.x];
+    for (int c0 = 0; c0 <= P; c0 += kThreads) {
+        const int p = c0 + threadIdx.x;
+        uint64_t nb = 0;
+        if (p < P) {
+            const uint64_t len = seg_start(pair_off, n, p + 1, capacity) - seg_start(pair_off, n, p, capacity);
+            nb = (len + kBP - 1) / kBP;
+        }
+        const uint64_t inc = block_inclusive_scan(nb, s_wave);
+        const uint64_t carry = s_carry;
+        if (p <= P) block_base[p] = (uint32_t)(carry + inc - nb);
+        __syncthreads();
+        if (threadIdx.x == kThreads - 1) s_carry = carry + inc;
+        __syncthreads();
+    }
 }
 
-// Stable scatter of one block's keys by the digit at `shift`. The block walks
-// its range in chunks of 256 in order; within a chunk each wave finds the
-// lanes sharing its digit with 8 ballots, and per-wave counts in LDS order the
-// waves, so equal digits keep their input order. s_off[d] starts at the
-// block's global offset for digit d (from the scanned histogram).
-template <typename K>
-__global__ __launch_bounds__(kThreads) void k_rs_scatter(const K *__restrict__ keys, const uint32_t *__restrict__ vals,
-                                                         K *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
-                                                         const uint64_t *__restrict__ d_n, uint64_t n_max, int shift,
-                                                         int nb, const uint64_t *__restrict__ offsets) {
-    __shared__ unsigned long long s_off[256];
-    __shared__ uint32_t s_wcnt[4 * 256];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i < 4 * 256; i += kThreads) s_wcnt[i] = 0;
-    s_off[tid] = offsets[(uint64_t)tid * nb + blockIdx.x];
+// Pose of bucketing block gb (block_base is non-decreasing); -1 past the last block.
+__device__ __forceinline__ int block_pose(const uint32_t *block_base, int P, uint32_t gb) {
+    if (gb >= block_base[P]) return -1;
+    int lo = 0, hi = P - 1;  // largest p with block_base[p] <= gb
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (block_base[mid] <= gb)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_tile_count(const uint32_t *__restrict__ ptile,
+                                                         const uint64_t *__restrict__ pair_off, int64_t n, int P,
+                                                         uint64_t capacity, const uint32_t *__restrict__ block_base,
+                                                         int n_tiles, uint32_t *__restrict__ cnt) {
+    extern __shared__ uint32_t s_hist[];
+    const uint32_t gb = blockIdx.x;
+    const int p = block_pose(block_base, P, gb);
+    if (p < 0) return;
+    for (int t = threadIdx.x; t < n_tiles; t += kThreads) s_hist[t] = 0;
     __syncthreads();
-    const uint64_t n = dev_count(d_n, n_max);
-    const uint64_t beg = (uint64_t)blockIdx.x * kRsTile;
-    const uint64_t end = min(beg + kRsTile, n);
+    const uint64_t beg = seg_start(pair_off, n, p, capacity) + (uint64_t)(gb - block_base[p]) * kBP;
+    const uint64_t end = min(beg + kBP, seg_start(pair_off, n, p + 1, capacity));
+    for (uint64_t i = beg + threadIdx.x; i < end; i += kThreads) atomicAdd(&s_hist[ptile[i]], 1u);
+    __syncthreads();
+    for (int t = threadIdx.x; t < n_tiles; t += kThreads) cnt[(uint64_t)gb * n_tiles + t] = s_hist[t];
+}
+
+// total[p * T + t] = pairs of list (p, t), summed over the pose's blocks.
+__global__ void k_col_sum(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ block_base, int P,
+                          int n_tiles, uint32_t *__restrict__ total) {
+    const uint64_t l = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= (uint64_t)P * n_tiles) return;
+    const int p = (int)(l / n_tiles), t = (int)(l % n_tiles);
+    uint32_t sum = 0;
+    for (uint32_t gb = block_base[p]; gb < block_base[p + 1]; ++gb) sum += cnt[(uint64_t)gb * n_tiles + t];
+    total[l] = sum;
+}
+
+// cnt[gb][t] <- first output position of block gb's pairs of list (p, t).
+__global__ void k_col_prefix(uint32_t *__restrict__ cnt, const uint32_t *__restrict__ block_base, int P, int n_tiles,
+                             const uint64_t *__restrict__ offsets) {
+    const uint64_t l = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= (uint64_t)P * n_tiles) return;
+    const int p = (int)(l / n_tiles), t = (int)(l % n_tiles);
+    uint32_t run = (uint32_t)offsets[l];
+    for (uint32_t gb = block_base[p]; gb < block_base[p + 1]; ++gb) {
+        const uint64_t i = (uint64_t)gb * n_tiles + t;
+        const uint32_t c = cnt[i];
+        cnt[i] = run;
+        run += c;
+    }
+}
+
+// One wave per block walks its pairs in order, 64 at a time: lanes that name
+// the same tile are matched with tile_bits ballots, take consecutive slots in
+// lane order, and the group's leader advances that tile's cursor in LDS.
+__global__ __launch_bounds__(64) void k_tile_scatter(const uint32_t *__restrict__ ptile, const uint32_t *__restrict__ pz,
+                                                     const uint32_t *__restrict__ pk,
+                                                     const uint64_t *__restrict__ pair_off, int64_t n, int P,
+                                                     uint64_t capacity, const uint32_t *__restrict__ block_base,
+                                                     const uint32_t *__restrict__ cnt, int n_tiles, int tile_bits,
+                                                     uint32_t *__restrict__ sz, uint32_t *__restrict__ sk) {
+    extern __shared__ uint32_t s_run[];
+    const uint32_t gb = blockIdx.x;
+    const int p = block_pose(block_base, P, gb);
+    if (p < 0) return;
+    const int lane = threadIdx.x;
+    for (int t = lane; t < n_tiles; t += 64) s_run[t] = cnt[(uint64_t)gb * n_tiles + t];
+    __syncthreads();
+    const uint64_t beg = seg_start(pair_off, n, p, capacity) + (uint64_t)(gb - block_base[p]) * kBP;
+    const uint64_t end = min(beg + kBP, seg_start(pair_off, n, p + 1, capacity));
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (uint64_t c0 = beg; c0 < end; c0 += kThreads) {
-        const uint64_t i = c0 + tid;
+    for (uint64_t c0 = beg; c0 < end; c0 += 64) {
+        const uint64_t i = c0 + lane;
         const bool valid = i < end;
-        const K key = valid ? keys[i] : K(0);
-        const uint32_t val = valid ? vals[i] : 0u;
-        const uint32_t d = (uint32_t)((key >> shift) & 0xff);
+        const uint32_t t = valid ? ptile[i] : 0u;
         uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
+        for (int b = 0; b < tile_bits; ++b) {
+            const bool bit = (t >> b) & 1u;
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
         if (!valid) peers = 0;
         const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-        const uint32_t cnt = (uint32_t)__popcll(peers);
-        const bool leader = valid && rank == 0;
-        if (leader) s_wcnt[wave * 256 + d] = cnt;
+        const uint32_t base = valid ? s_run[t] : 0u;
+        __syncthreads();
+        if (valid && rank == 0) s_run[t] = base + (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t pre = 0;
-            for (int w = 0; w < wave; ++w) pre += s_wcnt[w * 256 + d];
-            const uint64_t o = s_off[d] + pre + rank;
-            keys_out[o] = key;
-            vals_out[o] = val;
+            sz[base + rank] = pz[i];
+            sk[base + rank] = pk[i];
         }
-        __syncthreads();
-        if (leader) {
-            atomicAdd(&s_off[d], (unsigned long long)cnt);
-            s_wcnt[wave * 256 + d] = 0;
-        }
-        __syncthreads();
     }
 }
 
-__global__ void k_copy_u32(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, const uint64_t *d_n,
-                           uint64_t n_max) {
-    const uint64_t n = dev_count(d_n, n_max);
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+// ---- per-list depth sort: stable LSD radix sort on the depth bits ----
+// Keys are the float32 depth bits (positive, so they order like the depths);
+// values are submap indices. The bucketing left each list in index order, so
+// the stable sort yields (depth bits, index) order. Only digits that differ
+// within the list are sorted.
+constexpr int kSmallList = 1024;  // sorted in LDS by k_list_sort
+constexpr int kMidList = 3584;    // sorted in LDS by k_long_sort; longer lists in global memory
+
+struct SortScratch {
+    uint32_t off[256];
+    uint32_t wcnt[4 * 256];
+    uint32_t red[2];
+    uint32_t wtmp[4];
+};
+
+// Exclusive scan of a 256-entry LDS array in place (256 threads).
+__device__ __forceinline__ void scan256(uint32_t *a, uint32_t *s_tmp) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t h = a[tid];
+    uint32_t x = h;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_tmp[wave] = x;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < wave; ++w) add += s_tmp[w];
+    __syncthreads();
+    a[tid] = x - h + add;
+    __syncthreads();
 }
 
-__global__ void k_copy_u64(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, const uint64_t *d_n,
-                           uint64_t n_max) {
-    const uint64_t n = dev_count(d_n, n_max);
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
-}
-
-// [start, end) of list t (0 <= t < n_lists) in keys[0, n) sorted ascending:
-// offsets[t] = lower_bound(t); offsets[n_lists] = n.
-__global__ void k_ranges(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ d_n, uint64_t n_max,
-                         uint64_t n_lists, uint64_t *__restrict__ offsets) {
-    const uint64_t n = dev_count(d_n, n_max);
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= n_lists;
-         t += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t lo = 0, hi = n;
-        while (lo < hi) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if ((uint64_t)keys[mid] < t)
-                lo = mid + 1;
-            else
-                hi = mid;
+// Sort (k0, v0)[0, len) by key; (k1, v1) is the ping-pong buffer. Returns true
+// if the result ends in (k0, v0). 256 threads; pointers may be LDS or global.
+__device__ __forceinline__ bool block_sort_zk(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, uint32_t len,
+                                              SortScratch &sc) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) {
+        sc.red[0] = 0u;
+        sc.red[1] = 0xffffffffu;
+    }
+    for (int i = tid; i < 4 * 256; i += kThreads) sc.wcnt[i] = 0;
+    __syncthreads();
+    uint32_t o = 0u, a = 0xffffffffu;
+    for (uint32_t i = tid; i < len; i += kThreads) {
+        o |= k0[i];
+        a &= k0[i];
+    }
+    atomicOr(&sc.red[0], o);
+    atomicAnd(&sc.red[1], a);
+    __syncthreads();
+    const uint32_t vary = sc.red[0] ^ sc.red[1];
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t *sk = k0, *sv = v0, *dk = k1, *dv = v1;
+    bool first = true;
+    for (int shift = 0; shift < 32; shift += 8) {
+        if (((vary >> shift) & 0xffu) == 0) continue;
+        sc.off[tid] = 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < len; i += kThreads) atomicAdd(&sc.off[(sk[i] >> shift) & 0xffu], 1u);
+        __syncthreads();
+        scan256(sc.off, sc.wtmp);
+        for (uint32_t c0 = 0; c0 < len; c0 += kThreads) {
+            const uint32_t i = c0 + tid;
+            const bool valid = i < len;
+            const uint32_t key = valid ? sk[i] : 0u;
+            const uint32_t val = valid ? sv[i] : 0u;
+            const uint32_t d = (key >> shift) & 0xffu;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            if (!valid) peers = 0;
+            const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+            const uint32_t cnt = (uint32_t)__popcll(peers);
+            const bool leader = valid && rank == 0;
+            if (leader) sc.wcnt[wave * 256 + d] = cnt;
+            __syncthreads();
+            if (valid) {
+                uint32_t pre = 0;
+                for (int w = 0; w < wave; ++w) pre += sc.wcnt[w * 256 + d];
+                const uint32_t o2 = sc.off[d] + pre + rank;
+                dk[o2] = key;
+                dv[o2] = val;
+            }
+            __syncthreads();
+            if (leader) {
+                atomicAdd(&sc.off[d], cnt);
+                sc.wcnt[wave * 256 + d] = 0;
+            }
+            __syncthreads();
         }
-        offsets[t] = t == n_lists ? n : lo;
+        uint32_t *t;
+        t = sk, sk = dk, dk = t;
+        t = sv, sv = dv, dv = t;
+        first = !first;
+    }
+    return first;
+}
+
+__global__ __launch_bounds__(kThreads) void k_list_sort(const uint32_t *__restrict__ sz, uint32_t *__restrict__ sk,
+                                                        const uint64_t *__restrict__ offsets, int n_tiles,
+                                                        uint32_t *__restrict__ queue,
+                                                        unsigned long long *__restrict__ counters) {
+    __shared__ uint32_t a_k[kSmallList], a_v[kSmallList], b_k[kSmallList], b_v[kSmallList];
+    __shared__ SortScratch sc;
+    const uint64_t l = (uint64_t)blockIdx.y * n_tiles + blockIdx.x;
+    const uint64_t beg = offsets[l], end = offsets[l + 1];
+    if (end <= beg + 1) return;
+    const uint32_t len = (uint32_t)(end - beg);
+    if (len > (uint32_t)kSmallList) {
+        if (threadIdx.x == 0) queue[atomicAdd(&counters[CNT_LONG_LISTS], 1ull)] = (uint32_t)l;
+        return;
+    }
+    for (uint32_t i = threadIdx.x; i < len; i += kThreads) {
+        a_k[i] = sz[beg + i];
+        a_v[i] = sk[beg + i];
+    }
+    __syncthreads();
+    const bool first = block_sort_zk(a_k, a_v, b_k, b_v, len, sc);
+    const uint32_t *res = first ? a_v : b_v;
+    for (uint32_t i = threadIdx.x; i < len; i += kThreads) sk[beg + i] = res[i];
+}
+
+// Queued long lists; a fixed grid walks the queue.
+__global__ __launch_bounds__(kThreads) void k_long_sort(uint32_t *__restrict__ sz, uint32_t *__restrict__ sk,
+                                                        uint32_t *__restrict__ tz, uint32_t *__restrict__ tk,
+                                                        const uint64_t *__restrict__ offsets,
+                                                        const uint32_t *__restrict__ queue,
+                                                        const unsigned long long *__restrict__ counters) {
+    __shared__ uint32_t a_k[kMidList], a_v[kMidList], b_k[kMidList], b_v[kMidList];
+    __shared__ SortScratch sc;
+    const uint64_t n_long = counters[CNT_LONG_LISTS];
+    for (uint64_t q = blockIdx.x; q < n_long; q += gridDim.x) {
+        const uint32_t l = queue[q];
+        const uint64_t beg = offsets[l], end = offsets[l + 1];
+        const uint32_t len = (uint32_t)(end - beg);
+        if (len <= (uint32_t)kMidList) {
+            for (uint32_t i = threadIdx.x; i < len; i += kThreads) {
+                a_k[i] = sz[beg + i];
+                a_v[i] = sk[beg + i];
+            }
+            __syncthreads();
+            const bool first = block_sort_zk(a_k, a_v, b_k, b_v, len, sc);
+            const uint32_t *res = first ? a_v : b_v;
+            for (uint32_t i = threadIdx.x; i < len; i += kThreads) sk[beg + i] = res[i];
+        } else {
+            const bool first = block_sort_zk(sz + beg, sk + beg, tz + beg, tk + beg, len, sc);
+            if (!first)
+                for (uint32_t i = threadIdx.x; i < len; i += kThreads) sk[beg + i] = tk[beg + i];
+        }
+        __syncthreads();
     }
 }
 
@@ -243,51 +428,31 @@ void launch_scan(hipStream_t s, const uint32_t *count, uint64_t n, uint64_t *off
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, count, n, d_n, tmp, offsets);
 }
 
-uint64_t radix_tmp_elems(uint64_t n_max) {
-    const uint64_t nb = std::max<uint64_t>(1, (n_max + kRsTile - 1) / kRsTile);
-    return (256 * nb + 1) / 2 + 1 + (256 * nb + 1) + scan_tmp_elems(256 * nb);  // uint64 units
+uint64_t bucket_blocks_max(uint64_t capacity, int n_poses) { return (capacity + kBP - 1) / kBP + (uint64_t)n_poses; }
+
+void launch_bucket(hipStream_t s, const uint32_t *ptile, const uint32_t *pz, const uint32_t *pk,
+                   const uint64_t *pair_off, int64_t n, int n_poses, uint64_t capacity, int n_tiles, int tile_bits,
+                   uint32_t *block_base, uint32_t *cnt, uint32_t *total, uint64_t *offsets, uint64_t *scan_tmp,
+                   uint32_t *sz, uint32_t *sk) {
+    const uint64_t nbm = bucket_blocks_max(capacity, n_poses);
+    const uint64_t n_lists = (uint64_t)n_poses * n_tiles;
+    const unsigned lblocks = (unsigned)((n_lists + kThreads - 1) / kThreads);
+    const size_t lds = (size_t)n_tiles * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_seg_blocks, dim3(1), dim3(kThreads), 0, s, pair_off, n, n_poses, capacity, block_base);
+    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)nbm), dim3(kThreads), lds, s, ptile, pair_off, n, n_poses,
+                       capacity, block_base, n_tiles, cnt);
+    hipLaunchKernelGGL(k_col_sum, dim3(lblocks), dim3(kThreads), 0, s, cnt, block_base, n_poses, n_tiles, total);
+    launch_scan(s, total, n_lists, offsets, scan_tmp, nullptr);
+    hipLaunchKernelGGL(k_col_prefix, dim3(lblocks), dim3(kThreads), 0, s, cnt, block_base, n_poses, n_tiles, offsets);
+    hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)nbm), dim3(64), lds, s, ptile, pz, pk, pair_off, n, n_poses,
+                       capacity, block_base, cnt, n_tiles, tile_bits, sz, sk);
 }
 
-template <typename K>
-void launch_radix_sort(hipStream_t s, K *keys, uint32_t *vals, K *keys_tmp, uint32_t *vals_tmp, uint64_t n_max,
-                       const uint64_t *d_n, int begin_bit, int end_bit, uint64_t *tmp) {
-    if (n_max == 0 || end_bit <= begin_bit) return;
-    const uint64_t nb = (n_max + kRsTile - 1) / kRsTile;
-    uint32_t *hist = reinterpret_cast<uint32_t *>(tmp);
-    uint64_t *offs = tmp + (256 * nb + 1) / 2 + 1;
-    uint64_t *stmp = offs + 256 * nb + 1;
-    K *ks = keys, *kd = keys_tmp;
-    uint32_t *vs = vals, *vd = vals_tmp;
-    for (int shift = begin_bit; shift < end_bit; shift += 8) {
-        hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nb), dim3(kThreads), 0, s, ks, d_n, n_max, shift, (int)nb,
-                           hist);
-        launch_scan(s, hist, 256 * nb, offs, stmp, nullptr);
-        hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nb), dim3(kThreads), 0, s, ks, vs, kd, vd, d_n, n_max,
-                           shift, (int)nb, offs);
-        std::swap(ks, kd);
-        std::swap(vs, vd);
-    }
-    if (ks != keys) {
-        const unsigned blocks = (unsigned)std::min<uint64_t>((n_max + kThreads - 1) / kThreads, 4096);
-        if (sizeof(K) == 8)
-            hipLaunchKernelGGL(k_copy_u64, dim3(blocks), dim3(kThreads), 0, s, (const uint64_t *)ks,
-                               (uint64_t *)keys, d_n, n_max);
-        else
-            hipLaunchKernelGGL(k_copy_u32, dim3(blocks), dim3(kThreads), 0, s, (const uint32_t *)ks,
-                               (uint32_t *)keys, d_n, n_max);
-        hipLaunchKernelGGL(k_copy_u32, dim3(blocks), dim3(kThreads), 0, s, vs, vals, d_n, n_max);
-    }
-}
-
-template void launch_radix_sort<uint32_t>(hipStream_t, uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint64_t,
-                                          const uint64_t *, int, int, uint64_t *);
-template void launch_radix_sort<uint64_t>(hipStream_t, uint64_t *, uint32_t *, uint64_t *, uint32_t *, uint64_t,
-                                          const uint64_t *, int, int, uint64_t *);
-
-void launch_ranges(hipStream_t s, const uint32_t *keys, const uint64_t *d_n, uint64_t n_max, uint64_t n_lists,
-                   uint64_t *offsets) {
-    const unsigned blocks = (unsigned)std::min<uint64_t>((n_lists + 1 + kThreads - 1) / kThreads, 4096);
-    hipLaunchKernelGGL(k_ranges, dim3(blocks), dim3(kThreads), 0, s, keys, d_n, n_max, n_lists, offsets);
+void launch_list_sort(hipStream_t s, uint32_t *sz, uint32_t *sk, uint32_t *tz, uint32_t *tk, const uint64_t *offsets,
+                      int n_tiles, int n_poses, uint32_t *queue, unsigned long long *counters) {
+    hipLaunchKernelGGL(k_list_sort, dim3((unsigned)n_tiles, (unsigned)n_poses), dim3(kThreads), 0, s, sz, sk, offsets,
+                       n_tiles, queue, counters);
+    hipLaunchKernelGGL(k_long_sort, dim3(1024), dim3(kThreads), 0, s, sz, sk, tz, tk, offsets, queue, counters);
 }
 
 }  // namespace gsr
