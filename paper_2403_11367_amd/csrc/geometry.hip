@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void k_pack(int64_t n_map, const float *_
 // (vcount[pose * n_blocks + block]) for the compaction.
 __global__ __launch_bounds__(kThreads) void k_preprocess(
     const float4 *__restrict__ packed, int64_t n, const float *__restrict__ poses, int n_poses, Camera cam,
-    Consts k, TileGrid tg, float4 *__restrict__ records, uint32_t *__restrict__ ntiles,
+    Consts k, TileGrid tg, float4 *__restrict__ records, uint32_t *__restrict__ ntiles, uint4 *__restrict__ einfo,
     uint32_t *__restrict__ vcount) {
     __shared__ uint32_t s_vis[kPosesPerThread];
     const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -158,6 +158,10 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
                             r[1] = make_float4(cc, q0.w, q2.z, q2.w);
                             r[2] = make_float4(q3.x, tz, __uint_as_float((uint32_t)i0 | ((uint32_t)i1 << 16)),
                                                __uint_as_float((uint32_t)j0 | ((uint32_t)j1 << 16)));
+                            // emission record: depth bits and the tile rectangle
+                            einfo[(int64_t)p * n + g] =
+                                make_uint4(__float_as_uint(tz), (uint32_t)tx0 | ((uint32_t)tx1 << 16),
+                                           (uint32_t)ty0 | ((uint32_t)ty1 << 16), 0u);
                         }
                     }
                 }
@@ -175,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
 // S2, pair emission in (pose, index) order: Gaussian (p, g) writes one pair per
 // tile of its rectangle (row-major) at pair_off[p * n + g] (exclusive scan of
 // the tile counts): tile id within the pose, depth bits, submap index.
-__global__ __launch_bounds__(kThreads) void k_emit(const float4 *__restrict__ records,
+__global__ __launch_bounds__(kThreads) void k_emit(const uint4 *__restrict__ einfo,
                                                    const uint32_t *__restrict__ ntiles, int64_t n,
                                                    const uint64_t *__restrict__ pair_off, TileGrid tg,
                                                    uint32_t *__restrict__ ptile, uint32_t *__restrict__ pz,
@@ -185,11 +189,10 @@ __global__ __launch_bounds__(kThreads) void k_emit(const float4 *__restrict__ re
     if (g >= n) return;
     const int64_t rg = (int64_t)blockIdx.y * n + g;
     if (ntiles[rg] == 0) return;
-    const float4 q2 = records[rg * kRecordQuads + 2];
-    const uint32_t zb = __float_as_uint(q2.y);
-    const uint32_t rxb = __float_as_uint(q2.z), ryb = __float_as_uint(q2.w);
-    const int tx0 = (int)(rxb & 0xffffu) >> tg.log2_w, tx1 = (int)(rxb >> 16) >> tg.log2_w;
-    const int ty0 = (int)(ryb & 0xffffu) >> tg.log2_h, ty1 = (int)(ryb >> 16) >> tg.log2_h;
+    const uint4 e = einfo[rg];
+    const uint32_t zb = e.x;
+    const int tx0 = (int)(e.y & 0xffffu), tx1 = (int)(e.y >> 16);
+    const int ty0 = (int)(e.z & 0xffffu), ty1 = (int)(e.z >> 16);
     uint64_t pos = pair_off[rg];
     bool over = false;
     for (int yy = ty0; yy <= ty1; ++yy)
@@ -220,19 +223,19 @@ int64_t preprocess_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }
 
 void launch_preprocess(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
-                       uint32_t *ntiles, uint32_t *vcount) {
+                       uint32_t *ntiles, uint4 *einfo, uint32_t *vcount) {
     if (n <= 0) return;
     const dim3 grid((unsigned)preprocess_blocks(n), (unsigned)((n_poses + kPosesPerThread - 1) / kPosesPerThread));
     hipLaunchKernelGGL(k_preprocess, grid, dim3(kThreads), 0, s, packed, n, poses, n_poses, cam, k, tg, records,
-                       ntiles, vcount);
+                       ntiles, einfo, vcount);
 }
 
-void launch_emit(hipStream_t s, const float4 *records, const uint32_t *ntiles, int64_t n, int n_poses,
+void launch_emit(hipStream_t s, const uint4 *einfo, const uint32_t *ntiles, int64_t n, int n_poses,
                  const uint64_t *pair_off, const TileGrid &tg, uint32_t *ptile, uint32_t *pz, uint32_t *pk,
                  uint64_t capacity, int *flags) {
     if (n <= 0) return;
     const dim3 grid((unsigned)preprocess_blocks(n), (unsigned)n_poses);
-    hipLaunchKernelGGL(k_emit, grid, dim3(kThreads), 0, s, records, ntiles, n, pair_off, tg, ptile, pz, pk, capacity,
+    hipLaunchKernelGGL(k_emit, grid, dim3(kThreads), 0, s, einfo, ntiles, n, pair_off, tg, ptile, pz, pk, capacity,
                        flags);
 }
 

@@ -61,9 +61,10 @@ void launch_pack(hipStream_t s, int64_t n_map, const float *means, const float *
 int64_t preprocess_blocks(int64_t n);
 void launch_preprocess(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
-                       uint32_t *ntiles, uint32_t *vcount);
+                       uint32_t *ntiles, uint4 *einfo, uint32_t *vcount);
 // Pairs in (pose, index) order: tile id within the pose, depth bits, submap index.
-void launch_emit(hipStream_t s, const float4 *records, const uint32_t *ntiles, int64_t n, int n_poses,
+// einfo[p][g] = (depth bits, tx0 | tx1 << 16, ty0 | ty1 << 16, 0), written by the preprocess.
+void launch_emit(hipStream_t s, const uint4 *einfo, const uint32_t *ntiles, int64_t n, int n_poses,
                  const uint64_t *pair_off, const TileGrid &tg, uint32_t *ptile, uint32_t *pz, uint32_t *pk,
                  uint64_t capacity, int *flags);
 

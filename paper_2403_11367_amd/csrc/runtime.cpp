@@ -34,7 +34,7 @@ struct gsr_ctx {
     struct Buf {
         void *p = nullptr;
         size_t bytes = 0;
-    } records, ntiles, vcount, voff, pair_off, scan_tmp, ptile, pz, pk, sz, sk, cnt, total, block_base, queue,
+    } records, ntiles, einfo, vcount, voff, pair_off, scan_tmp, ptile, pz, pk, sz, sk, cnt, total, block_base, queue,
         offsets, grey_q, partials;
     // last render
     int64_t last_n = 0, last_poses = 0, last_tiles = 0;
@@ -201,7 +201,7 @@ int gsr_destroy(gsr_ctx *ctx) {
     if (!ctx) return GSR_EINVAL;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    gsr_ctx::Buf *bufs[] = {&ctx->records, &ctx->ntiles, &ctx->vcount, &ctx->voff,       &ctx->pair_off,
+    gsr_ctx::Buf *bufs[] = {&ctx->records, &ctx->ntiles, &ctx->einfo, &ctx->vcount, &ctx->voff, &ctx->pair_off,
                             &ctx->scan_tmp, &ctx->ptile, &ctx->pz,     &ctx->pk,         &ctx->sz,
                             &ctx->sk,       &ctx->cnt,   &ctx->total,  &ctx->block_base, &ctx->queue,
                             &ctx->offsets,  &ctx->grey_q, &ctx->partials};
@@ -323,6 +323,7 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     int rc;
     if ((rc = ensure(ctx, ctx->records, pn * gsr::kRecordQuads * sizeof(float4), "records")) ||
         (rc = ensure(ctx, ctx->ntiles, pn * sizeof(uint32_t), "ntiles")) ||
+        (rc = ensure(ctx, ctx->einfo, pn * sizeof(uint4), "emission records")) ||
         (rc = ensure(ctx, ctx->vcount, nvc * sizeof(uint32_t), "visible counts")) ||
         (rc = ensure(ctx, ctx->voff, (nvc + 1) * sizeof(uint64_t), "visible offsets")) ||
         (rc = ensure(ctx, ctx->pair_off, (pn + 1) * sizeof(uint64_t), "pair offsets")) ||
@@ -353,7 +354,8 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
         gsr::launch_fill_u32(s, vcount, nvc, 0u);
         gsr::launch_fill_u32(s, ntiles, pn, 0u);
     }
-    gsr::launch_preprocess(s, sm->packed, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p, ntiles, vcount);
+    gsr::launch_preprocess(s, sm->packed, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p, ntiles,
+                           (uint4 *)ctx->einfo.p, vcount);
     if ((rc = check_launch(ctx, "preprocess"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[1], s));
     // S2: visible count (stats), pair offsets in (pose, index) order
@@ -383,8 +385,8 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
         return rc;
     uint32_t *pz = (uint32_t *)ctx->pz.p, *pk = (uint32_t *)ctx->pk.p;
     uint32_t *sz = (uint32_t *)ctx->sz.p, *sk = (uint32_t *)ctx->sk.p;
-    gsr::launch_emit(s, records, ntiles, n, n_poses, pair_off, tg, (uint32_t *)ctx->ptile.p, pz, pk, capacity,
-                     ctx->d_flags);
+    gsr::launch_emit(s, (const uint4 *)ctx->einfo.p, ntiles, n, n_poses, pair_off, tg, (uint32_t *)ctx->ptile.p, pz,
+                     pk, capacity, ctx->d_flags);
     // S3: bucket by tile (stable), then sort every list by depth bits
     gsr::launch_bucket(s, (const uint32_t *)ctx->ptile.p, pz, pk, pair_off, n, n_poses, capacity, tg.n_tiles,
                        tile_bits, (uint32_t *)ctx->block_base.p, (uint32_t *)ctx->cnt.p, (uint32_t *)ctx->total.p,

@@ -198,9 +198,12 @@ __global__ void k_col_prefix(uint32_t *__restrict__ cnt, const uint32_t *__restr
     }
 }
 
-// One wave per block walks its pairs in order, 64 at a time: lanes that name
-// the same tile are matched with tile_bits ballots, take consecutive slots in
-// lane order, and the group's leader advances that tile's cursor in LDS.
+// One wave per block walks its pairs in order, 64 at a time (loads issued
+// kAhead chunks ahead): lanes that name the same tile are matched with
+// tile_bits ballots, take consecutive slots in lane order, and the group's
+// leader advances that tile's cursor in LDS.
+constexpr int kAhead = 4;
+
 __global__ __launch_bounds__(64) void k_tile_scatter(const uint32_t *__restrict__ ptile, const uint32_t *__restrict__ pz,
                                                      const uint32_t *__restrict__ pk,
                                                      const uint64_t *__restrict__ pair_off, int64_t n, int P,
@@ -217,25 +220,36 @@ __global__ __launch_bounds__(64) void k_tile_scatter(const uint32_t *__restrict_
     const uint64_t beg = seg_start(pair_off, n, p, capacity) + (uint64_t)(gb - block_base[p]) * kBP;
     const uint64_t end = min(beg + kBP, seg_start(pair_off, n, p + 1, capacity));
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (uint64_t c0 = beg; c0 < end; c0 += 64) {
-        const uint64_t i = c0 + lane;
-        const bool valid = i < end;
-        const uint32_t t = valid ? ptile[i] : 0u;
-        uint64_t peers = __ballot(valid);
-        for (int b = 0; b < tile_bits; ++b) {
-            const bool bit = (t >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+    for (uint64_t c0 = beg; c0 < end; c0 += 64 * kAhead) {
+        uint32_t tt[kAhead], zz[kAhead], kk[kAhead];
+#pragma unroll
+        for (int a = 0; a < kAhead; ++a) {
+            const uint64_t i = c0 + a * 64 + lane;
+            const bool valid = i < end;
+            tt[a] = valid ? ptile[i] : 0xffffffffu;
+            zz[a] = valid ? pz[i] : 0u;
+            kk[a] = valid ? pk[i] : 0u;
         }
-        if (!valid) peers = 0;
-        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-        const uint32_t base = valid ? s_run[t] : 0u;
-        __syncthreads();
-        if (valid && rank == 0) s_run[t] = base + (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            sz[base + rank] = pz[i];
-            sk[base + rank] = pk[i];
+#pragma unroll
+        for (int a = 0; a < kAhead; ++a) {
+            const uint32_t t = tt[a];
+            const bool valid = t != 0xffffffffu;
+            uint64_t peers = __ballot(valid);
+            for (int b = 0; b < tile_bits; ++b) {
+                const bool bit = (t >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            if (!valid) peers = 0;
+            const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+            // one wave: its LDS reads and writes take effect in program order, so no
+            // barrier (which would also wait for the scattered global stores)
+            const uint32_t base = valid ? s_run[t] : 0u;
+            if (valid && rank == 0) s_run[t] = base + (uint32_t)__popcll(peers);
+            if (valid) {
+                sz[base + rank] = zz[a];
+                sk[base + rank] = kk[a];
+            }
         }
     }
 }
@@ -245,7 +259,7 @@ __global__ __launch_bounds__(64) void k_tile_scatter(const uint32_t *__restrict_
 // values are submap indices. The bucketing left each list in index order, so
 // the stable sort yields (depth bits, index) order. Only digits that differ
 // within the list are sorted.
-constexpr int kSmallList = 1024;  // sorted in LDS by k_list_sort
+constexpr int kWaveList = 256;    // sorted in registers, one wave per list (k_list_sort)
 constexpr int kMidList = 3584;    // sorted in LDS by k_long_sort; longer lists in global memory
 
 struct SortScratch {
@@ -345,28 +359,79 @@ __device__ __forceinline__ bool block_sort_zk(uint32_t *k0, uint32_t *v0, uint32
     return first;
 }
 
+// Bitonic sort of 64 * R keys held by one wave, R per lane: element e lives in
+// lane e / R, register e % R. Stages with partner distance j >= R exchange with
+// lane ^ (j / R) through cross-lane shuffles; stages with j < R compare two
+// registers of the same lane. Fully unrolled so the keys stay in registers.
+template <int R>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&key)[R]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= 64 * R; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= R) {
+                const int lx = j / R;
+                const bool lower = (lane & lx) == 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const bool up = ((lane * R + r) & k) == 0;
+                    const uint64_t other = __shfl_xor(key[r], lx, 64);
+                    const bool take_min = (lower == up);
+                    const uint64_t mn = key[r] < other ? key[r] : other;
+                    const uint64_t mx = key[r] < other ? other : key[r];
+                    key[r] = take_min ? mn : mx;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if ((r & j) == 0) {
+                        const bool up = ((lane * R + r) & k) == 0;
+                        const uint64_t a = key[r], b = key[r + j];
+                        const bool swap = (a > b) == up;
+                        key[r] = swap ? b : a;
+                        key[r + j] = swap ? a : b;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void wave_sort_list(const uint32_t *sz, uint32_t *sk, uint64_t beg, uint32_t len) {
+    const int lane = threadIdx.x & 63;
+    uint64_t key[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t e = lane * R + r;
+        key[r] = e < len ? (((uint64_t)sz[beg + e] << 32) | sk[beg + e]) : ~0ull;
+    }
+    wave_bitonic<R>(key);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t e = lane * R + r;
+        if (e < len) sk[beg + e] = (uint32_t)key[r];
+    }
+}
+
+// One wave per list: lists up to kWaveList pairs are sorted in registers by
+// (depth bits, index); longer ones are queued for k_long_sort.
 __global__ __launch_bounds__(kThreads) void k_list_sort(const uint32_t *__restrict__ sz, uint32_t *__restrict__ sk,
-                                                        const uint64_t *__restrict__ offsets, int n_tiles,
+                                                        const uint64_t *__restrict__ offsets, uint64_t n_lists,
                                                         uint32_t *__restrict__ queue,
                                                         unsigned long long *__restrict__ counters) {
-    __shared__ uint32_t a_k[kSmallList], a_v[kSmallList], b_k[kSmallList], b_v[kSmallList];
-    __shared__ SortScratch sc;
-    const uint64_t l = (uint64_t)blockIdx.y * n_tiles + blockIdx.x;
+    const uint64_t l = (uint64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (l >= n_lists) return;
     const uint64_t beg = offsets[l], end = offsets[l + 1];
     if (end <= beg + 1) return;
     const uint32_t len = (uint32_t)(end - beg);
-    if (len > (uint32_t)kSmallList) {
-        if (threadIdx.x == 0) queue[atomicAdd(&counters[CNT_LONG_LISTS], 1ull)] = (uint32_t)l;
-        return;
-    }
-    for (uint32_t i = threadIdx.x; i < len; i += kThreads) {
-        a_k[i] = sz[beg + i];
-        a_v[i] = sk[beg + i];
-    }
-    __syncthreads();
-    const bool first = block_sort_zk(a_k, a_v, b_k, b_v, len, sc);
-    const uint32_t *res = first ? a_v : b_v;
-    for (uint32_t i = threadIdx.x; i < len; i += kThreads) sk[beg + i] = res[i];
+    if (len <= 64)
+        wave_sort_list<1>(sz, sk, beg, len);
+    else if (len <= (uint32_t)kWaveList)
+        wave_sort_list<4>(sz, sk, beg, len);
+    else if ((threadIdx.x & 63) == 0)
+        queue[atomicAdd(&counters[CNT_LONG_LISTS], 1ull)] = (uint32_t)l;
 }
 
 // Queued long lists; a fixed grid walks the queue.
@@ -450,8 +515,9 @@ void launch_bucket(hipStream_t s, const uint32_t *ptile, const uint32_t *pz, con
 
 void launch_list_sort(hipStream_t s, uint32_t *sz, uint32_t *sk, uint32_t *tz, uint32_t *tk, const uint64_t *offsets,
                       int n_tiles, int n_poses, uint32_t *queue, unsigned long long *counters) {
-    hipLaunchKernelGGL(k_list_sort, dim3((unsigned)n_tiles, (unsigned)n_poses), dim3(kThreads), 0, s, sz, sk, offsets,
-                       n_tiles, queue, counters);
+    const uint64_t n_lists = (uint64_t)n_tiles * n_poses;
+    hipLaunchKernelGGL(k_list_sort, dim3((unsigned)((n_lists + 3) / 4)), dim3(kThreads), 0, s, sz, sk, offsets,
+                       n_lists, queue, counters);
     hipLaunchKernelGGL(k_long_sort, dim3(1024), dim3(kThreads), 0, s, sz, sk, tz, tk, offsets, queue, counters);
 }
 
