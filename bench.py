@@ -100,7 +100,7 @@ def main():
     dev = torch.device("cuda", 0)
     t_setup = time.perf_counter()
     sc = W.config1()
-    idx = crop(sc.gaussians.means, sc.crop_cell, sc.prior_center[:2], sc.crop_radius)
+    idx = crop(sc.gaussians.means, sc.crop_cell, sc.prior_center[:2], sc.crop_radius, sc.crop_voxel)
     P = sc.poses.shape[0]
     cam = Camera(sc.camera.width, sc.camera.height, sc.camera.fx, sc.camera.fy, sc.camera.cx, sc.camera.cy)
     H, Wd = cam.height, cam.width

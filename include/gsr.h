@@ -205,10 +205,14 @@ int gsr_debug_copy(gsr_ctx *ctx, int which, void *dst_host, int64_t bytes);
  * a 2D grid of `cell`-metre cells keyed by (floor(x/cell), floor(y/cell)) in a
  * hash map; a KD-tree over the occupied cell centres returns the cells whose
  * centre lies within `radius` of (px, py); their Gaussians' indices are written
- * to idx_host in ascending order.
+ * to idx_host in Morton order of their `voxel`-metre 3D voxels (v =
+ * floor(coord / voxel) + 2^20 clamped to [0, 2^21 - 1]; x, y, z bit b -> code
+ * bit 3b, 3b+1, 3b+2), ties by ascending index; voxel <= 0: ascending index.
+ * A spatially coherent submap order keeps the per-tile pair lists local in
+ * memory, which gsr_render relies on for speed (any order renders correctly).
  *   means_host [n,3] float32; idx_host [cap] int64 output; *n_out = count
  *   (GSR_EINVAL with *n_out set if cap is too small). Synchronous, no GPU. */
-int gsr_crop(const float *means_host, int64_t n, double cell, double px, double py, double radius,
+int gsr_crop(const float *means_host, int64_t n, double cell, double px, double py, double radius, double voxel,
              int64_t *idx_host, int64_t cap, int64_t *n_out);
 
 const char *gsr_status_string(int status);

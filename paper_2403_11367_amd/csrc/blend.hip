@@ -92,9 +92,13 @@ __global__ __launch_bounds__(kThreads) void k_blend(const float4 *__restrict__ r
 
         if (__ballot(live) != 0) {
             for (int sw = 0; sw < 4; ++sw) {
-                uint64_t m = s_mask[wave][sw];
+                // the mask is the same in every lane: move it to scalar registers so
+                // the walk over its set bits is scalar control flow
+                const uint64_t mv = s_mask[wave][sw];
+                uint64_t m = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(mv >> 32)) << 32) |
+                             (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mv);
                 while (m) {
-                    const int j = __builtin_ctzll(m);
+                    const int j = (int)__builtin_ctzll(m);
                     m &= m - 1;
                     const int idx = sw * 64 + j;
                     const float4 a = s_rec[idx * 3 + 0];
@@ -116,8 +120,8 @@ __global__ __launch_bounds__(kThreads) void k_blend(const float4 *__restrict__ r
                     dep += b.w * w;
                     T -= w;
                     live = live && !(T < k.t_min);
-                    if (__ballot(live) == 0) goto wave_done;
                 }
+                if (__ballot(live) == 0) goto wave_done;
             }
         }
     wave_done:

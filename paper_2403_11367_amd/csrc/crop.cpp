@@ -5,7 +5,10 @@
 // within a range of a camera; Sec. III-C1 retrieves the submap around the raw
 // (e.g. GPS) prior pose this way. Cells here are `cell` metres wide, keyed by
 // (floor(x / cell), floor(y / cell)); a cell is kept when its centre lies
-// within `radius` of the prior (px, py); all its Gaussians come with it, in
+// within `radius` of the prior (px, py); all its Gaussians come with it. The
+// kept Gaussians are listed in Morton order of their `voxel`-metre 3D voxels
+// (the paper stores the map in 1 m voxels), ties by ascending index, so that
+// Gaussians close in the submap order are close in space; voxel <= 0 keeps
 // ascending index order. This runs once per query, off the timed GPU path.
 #include <algorithm>
 #include <cmath>
@@ -54,8 +57,21 @@ struct KdTree {
 
 }  // namespace
 
+// Morton code of a 3D voxel: v = floor(coord / voxel) + 2^20 clamped to
+// [0, 2^21 - 1] (0 if not finite); bit b of x, y, z goes to code bit 3b, 3b + 1, 3b + 2.
+static uint64_t voxel_code(const float *m, double voxel) {
+    uint64_t code = 0;
+    for (int a = 0; a < 3; ++a) {
+        double v = std::floor((double)m[a] / voxel) + (double)(1 << 20);
+        v = std::isfinite(v) ? std::min(std::max(v, 0.0), (double)((1 << 21) - 1)) : 0.0;
+        const uint64_t q = (uint64_t)v;
+        for (int b = 0; b < 21; ++b) code |= ((q >> b) & 1ull) << (3 * b + a);
+    }
+    return code;
+}
+
 extern "C" int gsr_crop(const float *means, int64_t n, double cell, double px, double py, double radius,
-                        int64_t *idx, int64_t cap, int64_t *n_out) {
+                        double voxel, int64_t *idx, int64_t cap, int64_t *n_out) {
     if (!n_out) return GSR_EINVAL;
     *n_out = 0;
     if (n < 0 || (n > 0 && !means) || !(cell > 0.0) || !(radius >= 0.0) || !std::isfinite(px) ||
@@ -93,6 +109,12 @@ extern "C" int gsr_crop(const float *means, int64_t n, double cell, double px, d
     std::vector<int64_t> sel;
     for (int c : hit) sel.insert(sel.end(), cells[c].members.begin(), cells[c].members.end());
     std::sort(sel.begin(), sel.end());
+    if (voxel > 0.0) {
+        std::vector<std::pair<uint64_t, int64_t>> keyed(sel.size());
+        for (size_t i = 0; i < sel.size(); ++i) keyed[i] = {voxel_code(means + sel[i] * 3, voxel), sel[i]};
+        std::sort(keyed.begin(), keyed.end());
+        for (size_t i = 0; i < sel.size(); ++i) sel[i] = keyed[i].second;
+    }
     *n_out = (int64_t)sel.size();
     if ((int64_t)sel.size() > cap) return GSR_EINVAL;
     std::copy(sel.begin(), sel.end(), idx);

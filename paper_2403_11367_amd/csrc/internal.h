@@ -12,7 +12,8 @@ namespace gsr {
 // Device flag slots (int32 each), raised by kernels, read and cleared by gsr_sync.
 enum : int { FLAG_OVERFLOW = 0, FLAG_BAD_INDEX = 1, FLAG_COUNT = 4 };
 // Device counter slots (uint64 each), reset at the start of a render.
-enum : int { CNT_EVALS_CONTRIB = 0, CNT_EVALS_LANES = 1, CNT_LONG_LISTS = 2, CNT_COUNT = 4 };
+// CNT_QUEUE + 0..2: lists queued per size class for the list sort.
+enum : int { CNT_EVALS_CONTRIB = 0, CNT_EVALS_LANES = 1, CNT_QUEUE = 2, CNT_COUNT = 8 };
 
 // Packed submap record: 4 float4 (64 B) per Gaussian.
 //   q0 = (mu_x, mu_y, mu_z, opacity)
@@ -87,7 +88,7 @@ void launch_bucket(hipStream_t s, const uint32_t *ptile, const uint32_t *pz, con
                    uint32_t *block_base, uint32_t *cnt, uint32_t *total, uint64_t *offsets, uint64_t *scan_tmp,
                    uint32_t *sz, uint32_t *sk);
 // Sorts every list by depth bits (stable); sk ends in front-to-back order.
-// tz, tk: scratch as large as sz, sk; queue: P * T entries.
+// tz, tk: scratch as large as sz, sk; queue: 3 * P * T entries.
 void launch_list_sort(hipStream_t s, uint32_t *sz, uint32_t *sk, uint32_t *tz, uint32_t *tk, const uint64_t *offsets,
                       int n_tiles, int n_poses, uint32_t *queue, unsigned long long *counters);
 

@@ -332,7 +332,7 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
         (rc = ensure(ctx, ctx->offsets, (n_lists + 1) * sizeof(uint64_t), "offsets")) ||
         (rc = ensure(ctx, ctx->total, n_lists * sizeof(uint32_t), "list totals")) ||
         (rc = ensure(ctx, ctx->block_base, ((uint64_t)P + 1) * sizeof(uint32_t), "block bases")) ||
-        (rc = ensure(ctx, ctx->queue, n_lists * sizeof(uint32_t), "long-list queue")))
+        (rc = ensure(ctx, ctx->queue, 3 * n_lists * sizeof(uint32_t), "list queues")))
         return rc;
     hipStream_t s = ctx->stream;
     uint32_t *ntiles = (uint32_t *)ctx->ntiles.p;

@@ -260,7 +260,8 @@ __global__ __launch_bounds__(64) void k_tile_scatter(const uint32_t *__restrict_
 // the stable sort yields (depth bits, index) order. Only digits that differ
 // within the list are sorted.
 constexpr int kWaveList = 256;    // sorted in registers, one wave per list (k_list_sort)
-constexpr int kMidList = 3584;    // sorted in LDS by k_long_sort; longer lists in global memory
+constexpr int kLdsList1 = 1024;   // sorted in LDS by one wave (k_wave_radix, 16 KB)
+constexpr int kLdsList2 = 3840;   // sorted in LDS by one wave (k_wave_radix, 61 KB); longer: k_long_sort
 
 struct SortScratch {
     uint32_t off[256];
@@ -426,41 +427,120 @@ __global__ __launch_bounds__(kThreads) void k_list_sort(const uint32_t *__restri
     const uint64_t beg = offsets[l], end = offsets[l + 1];
     if (end <= beg + 1) return;
     const uint32_t len = (uint32_t)(end - beg);
-    if (len <= 64)
+    if (len <= 64) {
         wave_sort_list<1>(sz, sk, beg, len);
-    else if (len <= (uint32_t)kWaveList)
+    } else if (len <= (uint32_t)kWaveList) {
         wave_sort_list<4>(sz, sk, beg, len);
-    else if ((threadIdx.x & 63) == 0)
-        queue[atomicAdd(&counters[CNT_LONG_LISTS], 1ull)] = (uint32_t)l;
+    } else if ((threadIdx.x & 63) == 0) {
+        const int q = len <= (uint32_t)kLdsList1 ? 0 : len <= (uint32_t)kLdsList2 ? 1 : 2;
+        queue[(uint64_t)q * n_lists + atomicAdd(&counters[CNT_QUEUE + q], 1ull)] = (uint32_t)l;
+    }
 }
 
-// Queued long lists; a fixed grid walks the queue.
+// One wave sorts a queued list in LDS (CAP pairs at most) with a stable LSD
+// radix sort on the depth bits, 8-bit digits, only the digits that vary.
+// A single wave needs no barrier: its LDS operations take effect in program
+// order, so the histogram, the scan and the rank-and-scatter of each 64-pair
+// chunk are visible to all lanes in sequence.
+template <int CAP>
+__global__ __launch_bounds__(64) void k_wave_radix(const uint32_t *__restrict__ sz, uint32_t *__restrict__ sk,
+                                                   const uint64_t *__restrict__ offsets,
+                                                   const uint32_t *__restrict__ queue,
+                                                   const unsigned long long *__restrict__ counters, int which) {
+    __shared__ uint32_t ak[CAP], av[CAP], bk[CAP], bv[CAP];
+    __shared__ uint32_t hist[256];
+    const int lane = threadIdx.x;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint64_t n_q = counters[CNT_QUEUE + which];
+    for (uint64_t q = blockIdx.x; q < n_q; q += gridDim.x) {
+        const uint32_t l = queue[q];
+        const uint64_t beg = offsets[l];
+        const uint32_t len = (uint32_t)(offsets[l + 1] - beg);
+        uint32_t o = 0u, a = 0xffffffffu;
+        for (uint32_t i = lane; i < len; i += 64) {
+            const uint32_t z = sz[beg + i];
+            ak[i] = z;
+            av[i] = sk[beg + i];
+            o |= z;
+            a &= z;
+        }
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) {
+            o |= __shfl_xor(o, m, 64);
+            a &= __shfl_xor(a, m, 64);
+        }
+        const uint32_t vary = o ^ a;
+        uint32_t *srk = ak, *srv = av, *dsk = bk, *dsv = bv;
+        for (int shift = 0; shift < 32; shift += 8) {
+            if (((vary >> shift) & 0xffu) == 0) continue;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) hist[lane * 4 + h] = 0;
+            for (uint32_t i = lane; i < len; i += 64) atomicAdd(&hist[(srk[i] >> shift) & 0xffu], 1u);
+            // exclusive scan of the 256 counters: 4 per lane, then across lanes
+            uint32_t c[4], sum = 0;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                c[h] = hist[lane * 4 + h];
+                sum += c[h];
+            }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += y;
+            }
+            uint32_t run = incl - sum;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                hist[lane * 4 + h] = run;
+                run += c[h];
+            }
+            for (uint32_t c0 = 0; c0 < len; c0 += 64) {
+                const uint32_t i = c0 + lane;
+                const bool valid = i < len;
+                const uint32_t key = valid ? srk[i] : 0u;
+                const uint32_t val = valid ? srv[i] : 0u;
+                const uint32_t d = (key >> shift) & 0xffu;
+                uint64_t peers = __ballot(valid);
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const bool bit = (d >> b) & 1u;
+                    const uint64_t m = __ballot(bit);
+                    peers &= bit ? m : ~m;
+                }
+                if (!valid) peers = 0;
+                const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+                const uint32_t base = valid ? hist[d] : 0u;
+                if (valid && rank == 0) hist[d] = base + (uint32_t)__popcll(peers);
+                if (valid) {
+                    dsk[base + rank] = key;
+                    dsv[base + rank] = val;
+                }
+            }
+            uint32_t *t;
+            t = srk, srk = dsk, dsk = t;
+            t = srv, srv = dsv, dsv = t;
+        }
+        for (uint32_t i = lane; i < len; i += 64) sk[beg + i] = srv[i];
+    }
+}
+
+// Lists longer than kLdsList2: one 256-thread block each, stable LSD radix
+// sort in global memory (the pair arrays of the emission serve as scratch).
 __global__ __launch_bounds__(kThreads) void k_long_sort(uint32_t *__restrict__ sz, uint32_t *__restrict__ sk,
                                                         uint32_t *__restrict__ tz, uint32_t *__restrict__ tk,
                                                         const uint64_t *__restrict__ offsets,
                                                         const uint32_t *__restrict__ queue,
                                                         const unsigned long long *__restrict__ counters) {
-    __shared__ uint32_t a_k[kMidList], a_v[kMidList], b_k[kMidList], b_v[kMidList];
     __shared__ SortScratch sc;
-    const uint64_t n_long = counters[CNT_LONG_LISTS];
+    const uint64_t n_long = counters[CNT_QUEUE + 2];
     for (uint64_t q = blockIdx.x; q < n_long; q += gridDim.x) {
         const uint32_t l = queue[q];
         const uint64_t beg = offsets[l], end = offsets[l + 1];
         const uint32_t len = (uint32_t)(end - beg);
-        if (len <= (uint32_t)kMidList) {
-            for (uint32_t i = threadIdx.x; i < len; i += kThreads) {
-                a_k[i] = sz[beg + i];
-                a_v[i] = sk[beg + i];
-            }
-            __syncthreads();
-            const bool first = block_sort_zk(a_k, a_v, b_k, b_v, len, sc);
-            const uint32_t *res = first ? a_v : b_v;
-            for (uint32_t i = threadIdx.x; i < len; i += kThreads) sk[beg + i] = res[i];
-        } else {
-            const bool first = block_sort_zk(sz + beg, sk + beg, tz + beg, tk + beg, len, sc);
-            if (!first)
-                for (uint32_t i = threadIdx.x; i < len; i += kThreads) sk[beg + i] = tk[beg + i];
-        }
+        const bool first = block_sort_zk(sz + beg, sk + beg, tz + beg, tk + beg, len, sc);
+        if (!first)
+            for (uint32_t i = threadIdx.x; i < len; i += kThreads) sk[beg + i] = tk[beg + i];
         __syncthreads();
     }
 }
@@ -518,7 +598,11 @@ void launch_list_sort(hipStream_t s, uint32_t *sz, uint32_t *sk, uint32_t *tz, u
     const uint64_t n_lists = (uint64_t)n_tiles * n_poses;
     hipLaunchKernelGGL(k_list_sort, dim3((unsigned)((n_lists + 3) / 4)), dim3(kThreads), 0, s, sz, sk, offsets,
                        n_lists, queue, counters);
-    hipLaunchKernelGGL(k_long_sort, dim3(1024), dim3(kThreads), 0, s, sz, sk, tz, tk, offsets, queue, counters);
+    hipLaunchKernelGGL(k_wave_radix<kLdsList1>, dim3(4096), dim3(64), 0, s, sz, sk, offsets, queue, counters, 0);
+    hipLaunchKernelGGL(k_wave_radix<kLdsList2>, dim3(1024), dim3(64), 0, s, sz, sk, offsets, queue + n_lists,
+                       counters, 1);
+    hipLaunchKernelGGL(k_long_sort, dim3(1024), dim3(kThreads), 0, s, sz, sk, tz, tk, offsets, queue + 2 * n_lists,
+                       counters);
 }
 
 }  // namespace gsr

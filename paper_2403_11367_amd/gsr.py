@@ -85,7 +85,7 @@ def _load() -> C.CDLL:
         "gsr_get_stats": (I, [P, C.POINTER(Stats)]),
         "gsr_debug_size": (I, [P, I, C.POINTER(I64)]),
         "gsr_debug_copy": (I, [P, I, P, I64]),
-        "gsr_crop": (I, [P, I64, D, D, D, D, P, I64, C.POINTER(I64)]),
+        "gsr_crop": (I, [P, I64, D, D, D, D, D, P, I64, C.POINTER(I64)]),
         "gsr_status_string": (C.c_char_p, [I]),
         "gsr_last_error": (C.c_char_p, [P]),
     }
@@ -107,14 +107,16 @@ def default_cfg(**overrides) -> RenderCfg:
     return cfg
 
 
-def crop(means: np.ndarray, cell: float, center_xy: Sequence[float], radius: float) -> np.ndarray:
-    """Indices (ascending int64) of the Gaussians in voxel cells within `radius` of the prior."""
+def crop(means: np.ndarray, cell: float, center_xy: Sequence[float], radius: float,
+         voxel: float = 1.0) -> np.ndarray:
+    """Indices (int64) of the Gaussians in cells within `radius` of the prior, in Morton
+    order of their `voxel`-metre voxels (ascending index if voxel <= 0)."""
     m = np.ascontiguousarray(means, dtype=np.float32)
     n = m.shape[0]
     out = np.empty(max(n, 1), dtype=np.int64)
     cnt = C.c_int64(0)
     rc = LIB.gsr_crop(m.ctypes.data, n, float(cell), float(center_xy[0]), float(center_xy[1]),
-                      float(radius), out.ctypes.data, out.size, C.byref(cnt))
+                      float(radius), float(voxel), out.ctypes.data, out.size, C.byref(cnt))
     if rc != GSR_OK:
         raise GsrError(rc, "gsr_crop")
     return out[: cnt.value].copy()

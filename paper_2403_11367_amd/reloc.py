@@ -33,10 +33,10 @@ class Relocalizer:
         self.map = [as_dev(a) for a in (means, scales, quats, opacity, rgb)]
         self.submap: Optional[Submap] = None
 
-    def select_submap(self, prior_xy, radius: float, cell: float):
+    def select_submap(self, prior_xy, radius: float, cell: float, voxel: float = 1.0):
         """Crop (host) + pack (device): the submap nearest the prior."""
         import torch
-        idx = crop(self.host_means, cell, prior_xy, radius)
+        idx = crop(self.host_means, cell, prior_xy, radius, voxel)
         index = torch.as_tensor(idx, device=self.map[0].device)
         self.submap = self.ctx.load_submap(*self.map, index=index, into=self.submap)
         return idx.size

@@ -86,9 +86,10 @@ def test_native_crop_matches_oracle_on_config1(gsr):
     import workloads as W
     from oracle import crop as ocrop
     sc = W.config1()
-    got = gsr.crop(sc.gaussians.means, sc.crop_cell, sc.prior_center[:2], sc.crop_radius)
-    ref = ocrop.crop_indices(sc.gaussians.means, sc.crop_cell, sc.prior_center[:2], sc.crop_radius)
-    assert np.array_equal(got, ref)
+    for voxel in (sc.crop_voxel, 0.0, 0.25):
+        got = gsr.crop(sc.gaussians.means, sc.crop_cell, sc.prior_center[:2], sc.crop_radius, voxel)
+        ref = ocrop.crop_indices(sc.gaussians.means, sc.crop_cell, sc.prior_center[:2], sc.crop_radius, voxel)
+        assert np.array_equal(got, ref)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
@@ -99,21 +100,24 @@ def test_native_crop_matches_oracle_random(gsr, seed):
     cx, cy = rng.uniform(-50, 50, 2)
     r = float(rng.uniform(5, 70))
     cell = float(rng.choice([1.0, 2.5, 10.0]))
-    got = gsr.crop(means, cell, (cx, cy), r)
-    ref = ocrop.crop_indices(means, cell, (cx, cy), r)
-    assert np.array_equal(got, ref)
+    for voxel in (0.0, 1.0, 3.0):
+        got = gsr.crop(means, cell, (cx, cy), r, voxel)
+        ref = ocrop.crop_indices(means, cell, (cx, cy), r, voxel)
+        assert np.array_equal(got, ref)
 
 
 def test_native_crop_edge_cases(gsr):
     empty = np.zeros((0, 3), np.float32)
     assert gsr.crop(empty, 10.0, (0, 0), 50.0).size == 0
-    m = np.array([[1, 1, 0], [np.nan, 0, 0], [500, 500, 0]], np.float32)
-    assert gsr.crop(m, 10.0, (0, 0), 20.0).tolist() == [0]
+    m = np.array([[1, 1, 0], [np.nan, 0, 0], [500, 500, 0], [2, 2, np.nan], [3, 1, 0]], np.float32)
+    from oracle import crop as ocrop
+    assert gsr.crop(m, 10.0, (0, 0), 20.0).tolist() == ocrop.crop_indices(m, 10.0, (0, 0), 20.0).tolist()
+    assert sorted(gsr.crop(m, 10.0, (0, 0), 20.0).tolist()) == [0, 3, 4]
     with pytest.raises(gsr.GsrError):
         gsr.crop(m, 0.0, (0, 0), 20.0)
     # capacity too small is an error that still reports the count
     cnt = C.c_int64(0)
     out = np.empty(1, np.int64)
     m2 = np.zeros((5, 3), np.float32)
-    assert gsr.LIB.gsr_crop(m2.ctypes.data, 5, 10.0, 0.0, 0.0, 50.0, out.ctypes.data, 1, C.byref(cnt)) == -1
+    assert gsr.LIB.gsr_crop(m2.ctypes.data, 5, 10.0, 0.0, 0.0, 50.0, 1.0, out.ctypes.data, 1, C.byref(cnt)) == -1
     assert cnt.value == 5

@@ -245,7 +245,7 @@ def test_config0_end_to_end_search(ctx):
 @pytest.fixture(scope="module")
 def cfg1():
     sc = W.config1()
-    idx = ocrop.crop_indices(sc.gaussians.means, sc.crop_cell, sc.prior_center[:2], sc.crop_radius)
+    idx = ocrop.crop_indices(sc.gaussians.means, sc.crop_cell, sc.prior_center[:2], sc.crop_radius, sc.crop_voxel)
     return sc, idx
 
 

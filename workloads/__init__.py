@@ -73,6 +73,7 @@ class Scene:
     prior_center: np.ndarray  # [3] f64, camera centre of the prior pose
     crop_cell: float = 0.0    # 2D voxel cell edge (m); 0 = no crop
     crop_radius: float = 0.0  # crop radius around the prior (m)
+    crop_voxel: float = 1.0   # fine voxel (m) whose Morton order orders the submap
 
 
 def _f32(a) -> np.ndarray:
