@@ -1,5 +1,6 @@
 // Submap packing (S0), EWA preprocessing (S1) and the per-Gaussian steps of
-// the pair ordering (S2): compaction of visible entries and pair emission.
+// the pair ordering (S2): per-wave packing of the visible entries and pair
+// emission.
 //
 // Built with -ffp-contract=off and correctly rounded float32 division and
 // square root, so that every record and depth key is a deterministic function
@@ -76,19 +77,23 @@ __global__ __launch_bounds__(kThreads) void k_pack(int64_t n_map, const float *_
 // S1. One thread per Gaussian, looping over a chunk of poses (blockIdx.y), so
 // the packed record is read once per chunk. For each pose the screen record is
 // written, the number of tiles its 3-sigma rectangle touches is stored (0 =
-// culled), and each block counts its visible Gaussians per pose
-// (vcount[pose * n_blocks + block]) for the compaction.
+// culled) with the tile rectangle, and each wave packs the (depth bits, index)
+// of its visible Gaussians, in index order, at the front of its 64-slot region
+// of vz / vg, with their number in vcount[pose * n_regions + region]: the
+// input of the per-pose depth sort.
 __global__ __launch_bounds__(kThreads) void k_preprocess(
     const float4 *__restrict__ packed, int64_t n, const float *__restrict__ poses, int n_poses, Camera cam,
-    Consts k, TileGrid tg, float4 *__restrict__ records, uint32_t *__restrict__ ntiles, uint4 *__restrict__ einfo,
-    uint32_t *__restrict__ vcount) {
-    __shared__ uint32_t s_vis[kPosesPerThread];
+    Consts k, TileGrid tg, float4 *__restrict__ records, uint32_t *__restrict__ ntiles, uint2 *__restrict__ rect,
+    uint32_t *__restrict__ vz, uint32_t *__restrict__ vg, uint32_t *__restrict__ vcount) {
     const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int p0 = blockIdx.y * kPosesPerThread;
     const int p1 = min(p0 + kPosesPerThread, n_poses);
     const bool in = g < n;
-    if (threadIdx.x < kPosesPerThread) s_vis[threadIdx.x] = 0;
-    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t region = g >> 6;  // the same for the whole wave
+    const int64_t n_regions = (n + 63) >> 6;
+    const bool region_in = (region << 6) < n;
+    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0, q3 = q0;
     if (in) {
         const float4 *src = packed + g * kPackedQuads;
@@ -108,7 +113,7 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
         const float R00 = P[0], R01 = P[1], R02 = P[2], T0 = P[3];
         const float R10 = P[4], R11 = P[5], R12 = P[6], T1 = P[7];
         const float R20 = P[8], R21 = P[9], R22 = P[10], T2 = P[11];
-        uint32_t nt = 0;
+        uint32_t nt = 0, zb = 0;
         if (in) {
             const float tx = ((R00 * mx + R01 * my) + R02 * mz) + T0;
             const float ty = ((R10 * mx + R11 * my) + R12 * mz) + T1;
@@ -158,53 +163,57 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
                             r[1] = make_float4(cc, q0.w, q2.z, q2.w);
                             r[2] = make_float4(q3.x, tz, __uint_as_float((uint32_t)i0 | ((uint32_t)i1 << 16)),
                                                __uint_as_float((uint32_t)j0 | ((uint32_t)j1 << 16)));
-                            // emission record: depth bits and the tile rectangle
-                            einfo[(int64_t)p * n + g] =
-                                make_uint4(__float_as_uint(tz), (uint32_t)tx0 | ((uint32_t)tx1 << 16),
-                                           (uint32_t)ty0 | ((uint32_t)ty1 << 16), 0u);
+                            rect[(int64_t)p * n + g] = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16),
+                                                                  (uint32_t)ty0 | ((uint32_t)ty1 << 16));
+                            zb = __float_as_uint(tz);
                         }
                     }
                 }
             }
             ntiles[(int64_t)p * n + g] = nt;
         }
-        const uint32_t wave_vis = (uint32_t)__popcll(__ballot(nt != 0));
-        if ((threadIdx.x & 63) == 0 && wave_vis) atomicAdd(&s_vis[p - p0], wave_vis);
-    }
-    __syncthreads();
-    if (threadIdx.x < (unsigned)(p1 - p0))
-        vcount[(int64_t)(p0 + threadIdx.x) * gridDim.x + blockIdx.x] = s_vis[threadIdx.x];
-}
-
-// S2, pair emission in (pose, index) order: Gaussian (p, g) writes one pair per
-// tile of its rectangle (row-major) at pair_off[p * n + g] (exclusive scan of
-// the tile counts): tile id within the pose, depth bits, submap index.
-__global__ __launch_bounds__(kThreads) void k_emit(const uint4 *__restrict__ einfo,
-                                                   const uint32_t *__restrict__ ntiles, int64_t n,
-                                                   const uint64_t *__restrict__ pair_off, TileGrid tg,
-                                                   uint32_t *__restrict__ ptile, uint32_t *__restrict__ pz,
-                                                   uint32_t *__restrict__ pk, uint64_t capacity,
-                                                   int *__restrict__ flags) {
-    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (g >= n) return;
-    const int64_t rg = (int64_t)blockIdx.y * n + g;
-    if (ntiles[rg] == 0) return;
-    const uint4 e = einfo[rg];
-    const uint32_t zb = e.x;
-    const int tx0 = (int)(e.y & 0xffffu), tx1 = (int)(e.y >> 16);
-    const int ty0 = (int)(e.z & 0xffffu), ty1 = (int)(e.z >> 16);
-    uint64_t pos = pair_off[rg];
-    bool over = false;
-    for (int yy = ty0; yy <= ty1; ++yy)
-        for (int xx = tx0; xx <= tx1; ++xx, ++pos) {
-            if (pos < capacity) {
-                ptile[pos] = (uint32_t)(yy * tg.tiles_x + xx);
-                pz[pos] = zb;
-                pk[pos] = (uint32_t)g;
-            } else {
-                over = true;
+        const uint64_t vis = __ballot(nt != 0);
+        if (region_in) {
+            if (lane == 0) vcount[(int64_t)p * n_regions + region] = (uint32_t)__popcll(vis);
+            if (nt != 0) {
+                const int64_t slot = (int64_t)p * n + (region << 6) + __popcll(vis & lt_mask);
+                vz[slot] = zb;
+                vg[slot] = (uint32_t)g;
             }
         }
+    }
+}
+
+// S2, pair emission in front-to-back order: element i of pose p's depth-sorted
+// segment [vbase[p], vbase[p+1]) is Gaussian sg[i]; it writes one pair per tile
+// of its rectangle (row-major) at poff[i] (exclusive scan of the tile counts in
+// that order): the tile id within the pose and the submap index.
+__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ sg,
+                                                   const uint64_t *__restrict__ poff,
+                                                   const uint32_t *__restrict__ vbase,
+                                                   const uint2 *__restrict__ rect, int64_t n, TileGrid tg,
+                                                   uint16_t *__restrict__ ptile, uint32_t *__restrict__ pk,
+                                                   uint64_t capacity, int *__restrict__ flags) {
+    const int p = blockIdx.y;
+    const uint64_t end = vbase[p + 1];
+    bool over = false;
+    for (uint64_t i = vbase[p] + (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < end;
+         i += (uint64_t)gridDim.x * kThreads) {
+        const uint32_t g = sg[i];
+        const uint2 e = rect[(int64_t)p * n + g];
+        const int tx0 = (int)(e.x & 0xffffu), tx1 = (int)(e.x >> 16);
+        const int ty0 = (int)(e.y & 0xffffu), ty1 = (int)(e.y >> 16);
+        uint64_t pos = poff[i];
+        for (int yy = ty0; yy <= ty1; ++yy)
+            for (int xx = tx0; xx <= tx1; ++xx, ++pos) {
+                if (pos < capacity) {
+                    ptile[pos] = (uint16_t)(yy * tg.tiles_x + xx);
+                    pk[pos] = g;
+                } else {
+                    over = true;
+                }
+            }
+    }
     if (over) atomicOr(&flags[FLAG_OVERFLOW], 1);
 }
 
@@ -223,20 +232,21 @@ int64_t preprocess_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }
 
 void launch_preprocess(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
-                       uint32_t *ntiles, uint4 *einfo, uint32_t *vcount) {
+                       uint32_t *ntiles, uint2 *rect, uint32_t *vz, uint32_t *vg, uint32_t *vcount) {
     if (n <= 0) return;
     const dim3 grid((unsigned)preprocess_blocks(n), (unsigned)((n_poses + kPosesPerThread - 1) / kPosesPerThread));
     hipLaunchKernelGGL(k_preprocess, grid, dim3(kThreads), 0, s, packed, n, poses, n_poses, cam, k, tg, records,
-                       ntiles, einfo, vcount);
+                       ntiles, rect, vz, vg, vcount);
 }
 
-void launch_emit(hipStream_t s, const uint4 *einfo, const uint32_t *ntiles, int64_t n, int n_poses,
-                 const uint64_t *pair_off, const TileGrid &tg, uint32_t *ptile, uint32_t *pz, uint32_t *pk,
-                 uint64_t capacity, int *flags) {
+void launch_emit(hipStream_t s, const uint32_t *sg, const uint64_t *poff, const uint32_t *vbase, const uint2 *rect,
+                 int64_t n, int n_poses, const TileGrid &tg, uint16_t *ptile, uint32_t *pk, uint64_t capacity,
+                 int *flags) {
     if (n <= 0) return;
-    const dim3 grid((unsigned)preprocess_blocks(n), (unsigned)n_poses);
-    hipLaunchKernelGGL(k_emit, grid, dim3(kThreads), 0, s, einfo, ntiles, n, pair_off, tg, ptile, pz, pk, capacity,
-                       flags);
+    // about 8 Gaussians per thread at full visibility
+    const int64_t per_pose = std::min<int64_t>(256, std::max<int64_t>(1, (n + 8 * kThreads - 1) / (8 * kThreads)));
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)per_pose, (unsigned)n_poses), dim3(kThreads), 0, s, sg, poff, vbase,
+                       rect, n, tg, ptile, pk, capacity, flags);
 }
 
 }  // namespace gsr

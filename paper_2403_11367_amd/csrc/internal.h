@@ -12,8 +12,7 @@ namespace gsr {
 // Device flag slots (int32 each), raised by kernels, read and cleared by gsr_sync.
 enum : int { FLAG_OVERFLOW = 0, FLAG_BAD_INDEX = 1, FLAG_COUNT = 4 };
 // Device counter slots (uint64 each), reset at the start of a render.
-// CNT_QUEUE + 0..2: lists queued per size class for the list sort.
-enum : int { CNT_EVALS_CONTRIB = 0, CNT_EVALS_LANES = 1, CNT_QUEUE = 2, CNT_COUNT = 8 };
+enum : int { CNT_EVALS_CONTRIB = 0, CNT_EVALS_LANES = 1, CNT_COUNT = 8 };
 
 // Packed submap record: 4 float4 (64 B) per Gaussian.
 //   q0 = (mu_x, mu_y, mu_z, opacity)
@@ -58,16 +57,21 @@ struct TileGrid {
 void launch_pack(hipStream_t s, int64_t n_map, const float *means, const float *scales,
                  const float *quats, const float *opacity, const float *rgb, const int64_t *index,
                  int64_t n_sel, float4 *packed, int *flags);
-// Blocks of the preprocess grid along the Gaussians (vcount has P * this entries).
+// Blocks of the preprocess grid along the Gaussians.
 int64_t preprocess_blocks(int64_t n);
+// Screen records, tile counts ntiles[p][g] (0 = culled) and tile rectangles
+// rect[p][g] = (tx0 | tx1 << 16, ty0 | ty1 << 16); per pose and 64-Gaussian
+// region, the (depth bits, index) of the visible Gaussians packed at the front
+// of the region's slots of vz / vg (P * n each) and their count in
+// vcount[p * ceil(n / 64) + region].
 void launch_preprocess(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
-                       uint32_t *ntiles, uint4 *einfo, uint32_t *vcount);
-// Pairs in (pose, index) order: tile id within the pose, depth bits, submap index.
-// einfo[p][g] = (depth bits, tx0 | tx1 << 16, ty0 | ty1 << 16, 0), written by the preprocess.
-void launch_emit(hipStream_t s, const uint4 *einfo, const uint32_t *ntiles, int64_t n, int n_poses,
-                 const uint64_t *pair_off, const TileGrid &tg, uint32_t *ptile, uint32_t *pz, uint32_t *pk,
-                 uint64_t capacity, int *flags);
+                       uint32_t *ntiles, uint2 *rect, uint32_t *vz, uint32_t *vg, uint32_t *vcount);
+// Pairs in front-to-back order per pose: tile id within the pose and submap
+// index, at the pair offsets poff of the depth-sorted elements sg.
+void launch_emit(hipStream_t s, const uint32_t *sg, const uint64_t *poff, const uint32_t *vbase, const uint2 *rect,
+                 int64_t n, int n_poses, const TileGrid &tg, uint16_t *ptile, uint32_t *pk, uint64_t capacity,
+                 int *flags);
 
 // ---- sort.hip ----
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t value);
@@ -78,19 +82,27 @@ void launch_fill_u64(hipStream_t s, unsigned long long *p, uint64_t n, unsigned 
 uint64_t scan_tmp_elems(uint64_t n);
 void launch_scan(hipStream_t s, const uint32_t *count, uint64_t n, uint64_t *offsets, uint64_t *tmp,
                  const uint64_t *d_n);
+// Per-pose stable sort of the visible Gaussians by depth bits. Input: the
+// preprocess's regions in (kb, vb) with vcount. Output: vb[vbase[p] ..
+// vbase[p+1]) = pose p's indices front to back, kb = their tile counts,
+// vbase[P] = visible total, roff[radix_count_elems] = visible total (uint64).
+// ka, va, kb, vb hold P * n entries; rcnt radix_count_elems, roff one more.
+uint64_t radix_blocks_per_pose(int64_t n);
+uint64_t radix_count_elems(int64_t n, int n_poses);
+void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vcount, const uint32_t *ntiles,
+                       uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t *rcnt, uint64_t *roff,
+                       uint64_t *scan_tmp, uint32_t *vbase);
+// pseg[p] = min(first pair of pose p, capacity), p in [0, P]; poff[total_slot] is the pair total.
+void launch_pair_segments(hipStream_t s, const uint64_t *poff, uint64_t total_slot, const uint32_t *vbase,
+                          int n_poses, uint64_t capacity, uint64_t *pseg);
 // Stable counting sort of the emitted pairs by tile within each pose. Writes
-// the per-(pose, tile) list offsets [P*T + 1] and the bucketed (depth bits,
-// index) arrays sz, sk. cnt holds bucket_blocks_max(capacity, P) * T entries,
-// total P * T, block_base P + 1; n_tiles <= kMaxTilesPerPose.
+// the per-(pose, tile) list offsets [P*T + 1] and the bucketed indices sk.
+// cnt holds bucket_blocks_max(capacity, P) * T entries, total P * T,
+// block_base P + 1; n_tiles <= kMaxTilesPerPose.
 uint64_t bucket_blocks_max(uint64_t capacity, int n_poses);
-void launch_bucket(hipStream_t s, const uint32_t *ptile, const uint32_t *pz, const uint32_t *pk,
-                   const uint64_t *pair_off, int64_t n, int n_poses, uint64_t capacity, int n_tiles, int tile_bits,
-                   uint32_t *block_base, uint32_t *cnt, uint32_t *total, uint64_t *offsets, uint64_t *scan_tmp,
-                   uint32_t *sz, uint32_t *sk);
-// Sorts every list by depth bits (stable); sk ends in front-to-back order.
-// tz, tk: scratch as large as sz, sk; queue: 3 * P * T entries.
-void launch_list_sort(hipStream_t s, uint32_t *sz, uint32_t *sk, uint32_t *tz, uint32_t *tk, const uint64_t *offsets,
-                      int n_tiles, int n_poses, uint32_t *queue, unsigned long long *counters);
+void launch_bucket(hipStream_t s, const uint16_t *ptile, const uint32_t *pk, const uint64_t *pseg, int n_poses,
+                   uint64_t capacity, int n_tiles, int tile_bits, uint32_t *block_base, uint32_t *cnt,
+                   uint32_t *total, uint64_t *offsets, uint64_t *scan_tmp, uint32_t *sk);
 
 // ---- blend.hip ----
 void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,

@@ -2,8 +2,9 @@
 //
 // The context owns a stream binding, device flags and counters, a grow-only
 // workspace, and (when profiling) HIP events around the stages. gsr_render
-// enqueues: zero fill of the (pose, tile) counters -> preprocess + tile
-// histogram -> exclusive scan -> pair scatter -> per-tile sort -> blend.
+// enqueues: preprocess (screen records, tile counts, per-wave packing of the
+// visible Gaussians) -> per-pose depth sort -> scan of the tile counts in depth
+// order -> pair emission -> stable bucketing by tile -> blend.
 // The pair count is known only on the device after the scan; with
 // pair_capacity == 0 the host waits for that one number and sizes the pair
 // buffer exactly, otherwise the fixed capacity is used with no host wait and
@@ -34,13 +35,12 @@ struct gsr_ctx {
     struct Buf {
         void *p = nullptr;
         size_t bytes = 0;
-    } records, ntiles, einfo, vcount, voff, pair_off, scan_tmp, ptile, pz, pk, sz, sk, cnt, total, block_base, queue,
-        offsets, grey_q, partials;
+    } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, vbase, poff, pseg, scan_tmp,
+        ptile, pk, sk, cnt, total, block_base, offsets, grey_q, partials;
     // last render
     int64_t last_n = 0, last_poses = 0, last_tiles = 0;
     uint64_t last_capacity = 0;
     int64_t last_pairs = -1;  // known on host in exact mode
-    int64_t last_vis_slot = 0;  // index of the visible total in voff
     // profiling: event sets of the calls profiled since the last gsr_get_stats
     struct RenderEv {
         hipEvent_t e[4] = {};
@@ -201,10 +201,11 @@ int gsr_destroy(gsr_ctx *ctx) {
     if (!ctx) return GSR_EINVAL;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    gsr_ctx::Buf *bufs[] = {&ctx->records, &ctx->ntiles, &ctx->einfo, &ctx->vcount, &ctx->voff, &ctx->pair_off,
-                            &ctx->scan_tmp, &ctx->ptile, &ctx->pz,     &ctx->pk,         &ctx->sz,
-                            &ctx->sk,       &ctx->cnt,   &ctx->total,  &ctx->block_base, &ctx->queue,
-                            &ctx->offsets,  &ctx->grey_q, &ctx->partials};
+    gsr_ctx::Buf *bufs[] = {&ctx->records, &ctx->ntiles,  &ctx->rect,     &ctx->vcount,  &ctx->sort_ka,
+                            &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb,  &ctx->rcnt,    &ctx->roff,
+                            &ctx->vbase,   &ctx->poff,    &ctx->pseg,     &ctx->scan_tmp, &ctx->ptile,
+                            &ctx->pk,      &ctx->sk,      &ctx->cnt,      &ctx->total,   &ctx->block_base,
+                            &ctx->offsets, &ctx->grey_q,  &ctx->partials};
     for (auto *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
@@ -317,27 +318,39 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     if (tg.n_tiles > gsr::kMaxTilesPerPose)
         return fail(ctx, GSR_EUNSUPPORTED, "more than 16384 tiles per image");
     if (n_lists >= 0xffffffffull) return fail(ctx, GSR_EINVAL, "poses x tiles must be below 2^32");
+    if ((uint64_t)P * (uint64_t)n >= 0xffffffffull)
+        return fail(ctx, GSR_EINVAL, "poses x submap size must be below 2^32");
     const uint64_t pn = (uint64_t)std::max<int64_t>(1, P * n);
-    const uint64_t nbp = (uint64_t)std::max<int64_t>(1, gsr::preprocess_blocks(n));
-    const uint64_t nvc = (uint64_t)P * nbp;  // visible-count entries
+    const uint64_t n_regions = (uint64_t)(n + 63) / 64;
+    const uint64_t nvc = std::max<uint64_t>(1, (uint64_t)P * n_regions);  // visible-count entries
+    const uint64_t n_rc = gsr::radix_count_elems(n, n_poses);
     int rc;
     if ((rc = ensure(ctx, ctx->records, pn * gsr::kRecordQuads * sizeof(float4), "records")) ||
         (rc = ensure(ctx, ctx->ntiles, pn * sizeof(uint32_t), "ntiles")) ||
-        (rc = ensure(ctx, ctx->einfo, pn * sizeof(uint4), "emission records")) ||
+        (rc = ensure(ctx, ctx->rect, pn * sizeof(uint2), "tile rectangles")) ||
         (rc = ensure(ctx, ctx->vcount, nvc * sizeof(uint32_t), "visible counts")) ||
-        (rc = ensure(ctx, ctx->voff, (nvc + 1) * sizeof(uint64_t), "visible offsets")) ||
-        (rc = ensure(ctx, ctx->pair_off, (pn + 1) * sizeof(uint64_t), "pair offsets")) ||
-        (rc = ensure(ctx, ctx->scan_tmp, gsr::scan_tmp_elems(std::max(std::max(nvc, pn), n_lists)) * sizeof(uint64_t),
+        (rc = ensure(ctx, ctx->sort_ka, pn * sizeof(uint32_t), "depth sort")) ||
+        (rc = ensure(ctx, ctx->sort_va, pn * sizeof(uint32_t), "depth sort")) ||
+        (rc = ensure(ctx, ctx->sort_kb, pn * sizeof(uint32_t), "depth sort")) ||
+        (rc = ensure(ctx, ctx->sort_vb, pn * sizeof(uint32_t), "depth sort")) ||
+        (rc = ensure(ctx, ctx->rcnt, n_rc * sizeof(uint32_t), "radix counts")) ||
+        (rc = ensure(ctx, ctx->roff, (n_rc + 1) * sizeof(uint64_t), "radix offsets")) ||
+        (rc = ensure(ctx, ctx->vbase, ((uint64_t)P + 1) * sizeof(uint32_t), "pose bases")) ||
+        (rc = ensure(ctx, ctx->poff, (pn + 1) * sizeof(uint64_t), "pair offsets")) ||
+        (rc = ensure(ctx, ctx->pseg, ((uint64_t)P + 1) * sizeof(uint64_t), "pair segments")) ||
+        (rc = ensure(ctx, ctx->scan_tmp, gsr::scan_tmp_elems(std::max(std::max(n_rc, pn), n_lists)) * sizeof(uint64_t),
                      "scan")) ||
         (rc = ensure(ctx, ctx->offsets, (n_lists + 1) * sizeof(uint64_t), "offsets")) ||
         (rc = ensure(ctx, ctx->total, n_lists * sizeof(uint32_t), "list totals")) ||
-        (rc = ensure(ctx, ctx->block_base, ((uint64_t)P + 1) * sizeof(uint32_t), "block bases")) ||
-        (rc = ensure(ctx, ctx->queue, 3 * n_lists * sizeof(uint32_t), "list queues")))
+        (rc = ensure(ctx, ctx->block_base, ((uint64_t)P + 1) * sizeof(uint32_t), "block bases")))
         return rc;
     hipStream_t s = ctx->stream;
     uint32_t *ntiles = (uint32_t *)ctx->ntiles.p;
-    uint32_t *vcount = (uint32_t *)ctx->vcount.p;
-    uint64_t *pair_off = (uint64_t *)ctx->pair_off.p;
+    uint32_t *sort_kb = (uint32_t *)ctx->sort_kb.p, *sort_vb = (uint32_t *)ctx->sort_vb.p;
+    uint32_t *vbase = (uint32_t *)ctx->vbase.p;
+    uint64_t *roff = (uint64_t *)ctx->roff.p;
+    uint64_t *poff = (uint64_t *)ctx->poff.p;
+    uint64_t *pseg = (uint64_t *)ctx->pseg.p;
     uint64_t *scan_tmp = (uint64_t *)ctx->scan_tmp.p;
     const float4 *records = (const float4 *)ctx->records.p;
     uint64_t *offsets = (uint64_t *)ctx->offsets.p;
@@ -350,22 +363,20 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
         HIPC(ctx, hipEventRecord(ev->e[0], s));
     }
     gsr::launch_fill_u64(s, ctx->d_counters, gsr::CNT_COUNT, 0ull);
-    if (n == 0) {
-        gsr::launch_fill_u32(s, vcount, nvc, 0u);
-        gsr::launch_fill_u32(s, ntiles, pn, 0u);
-    }
     gsr::launch_preprocess(s, sm->packed, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p, ntiles,
-                           (uint4 *)ctx->einfo.p, vcount);
+                           (uint2 *)ctx->rect.p, sort_kb, sort_vb, (uint32_t *)ctx->vcount.p);
     if ((rc = check_launch(ctx, "preprocess"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[1], s));
-    // S2: visible count (stats), pair offsets in (pose, index) order
-    gsr::launch_scan(s, vcount, nvc, (uint64_t *)ctx->voff.p, scan_tmp, nullptr);
-    gsr::launch_scan(s, ntiles, pn, pair_off, scan_tmp, nullptr);
-    if ((rc = check_launch(ctx, "pair offsets"))) return rc;
+    // S2-S3: per-pose depth order of the visible Gaussians, then pair offsets in that order
+    gsr::launch_depth_sort(s, n, n_poses, (const uint32_t *)ctx->vcount.p, ntiles, (uint32_t *)ctx->sort_ka.p,
+                           (uint32_t *)ctx->sort_va.p, sort_kb, sort_vb, (uint32_t *)ctx->rcnt.p, roff, scan_tmp,
+                           vbase);
+    gsr::launch_scan(s, sort_kb, pn, poff, scan_tmp, roff + n_rc);
+    if ((rc = check_launch(ctx, "depth sort"))) return rc;
 
     uint64_t capacity;
     if (cfg.pair_capacity == 0) {
-        HIPC(ctx, hipMemcpyAsync(ctx->h_pin, pair_off + pn, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        HIPC(ctx, hipMemcpyAsync(ctx->h_pin, poff + pn, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
         HIPC(ctx, hipStreamSynchronize(s));
         capacity = ctx->h_pin[0];
         ctx->last_pairs = (int64_t)capacity;
@@ -376,23 +387,19 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     if (capacity >= 0xffffffffull) return fail(ctx, GSR_EINVAL, "pair count must be below 2^32");
     const uint64_t cap1 = std::max<uint64_t>(1, capacity);
     const uint64_t nbm = gsr::bucket_blocks_max(capacity, n_poses);
-    if ((rc = ensure(ctx, ctx->ptile, cap1 * sizeof(uint32_t), "pair tiles")) ||
-        (rc = ensure(ctx, ctx->pz, cap1 * sizeof(uint32_t), "pair depths")) ||
+    if ((rc = ensure(ctx, ctx->ptile, cap1 * sizeof(uint16_t), "pair tiles")) ||
         (rc = ensure(ctx, ctx->pk, cap1 * sizeof(uint32_t), "pair indices")) ||
-        (rc = ensure(ctx, ctx->sz, cap1 * sizeof(uint32_t), "list depths")) ||
         (rc = ensure(ctx, ctx->sk, cap1 * sizeof(uint32_t), "list indices")) ||
         (rc = ensure(ctx, ctx->cnt, nbm * tg.n_tiles * sizeof(uint32_t), "bucket counts")))
         return rc;
-    uint32_t *pz = (uint32_t *)ctx->pz.p, *pk = (uint32_t *)ctx->pk.p;
-    uint32_t *sz = (uint32_t *)ctx->sz.p, *sk = (uint32_t *)ctx->sk.p;
-    gsr::launch_emit(s, (const uint4 *)ctx->einfo.p, ntiles, n, n_poses, pair_off, tg, (uint32_t *)ctx->ptile.p, pz,
-                     pk, capacity, ctx->d_flags);
-    // S3: bucket by tile (stable), then sort every list by depth bits
-    gsr::launch_bucket(s, (const uint32_t *)ctx->ptile.p, pz, pk, pair_off, n, n_poses, capacity, tg.n_tiles,
-                       tile_bits, (uint32_t *)ctx->block_base.p, (uint32_t *)ctx->cnt.p, (uint32_t *)ctx->total.p,
-                       offsets, scan_tmp, sz, sk);
-    gsr::launch_list_sort(s, sz, sk, pz, pk, offsets, tg.n_tiles, n_poses, (uint32_t *)ctx->queue.p,
-                          ctx->d_counters);
+    uint16_t *ptile = (uint16_t *)ctx->ptile.p;
+    uint32_t *pk = (uint32_t *)ctx->pk.p, *sk = (uint32_t *)ctx->sk.p;
+    gsr::launch_pair_segments(s, poff, pn, vbase, n_poses, capacity, pseg);
+    gsr::launch_emit(s, sort_vb, poff, vbase, (const uint2 *)ctx->rect.p, n, n_poses, tg, ptile, pk, capacity,
+                     ctx->d_flags);
+    // S3-S4: stable bucketing by tile keeps the depth order inside every list
+    gsr::launch_bucket(s, ptile, pk, pseg, n_poses, capacity, tg.n_tiles, tile_bits, (uint32_t *)ctx->block_base.p,
+                       (uint32_t *)ctx->cnt.p, (uint32_t *)ctx->total.p, offsets, scan_tmp, sk);
     if ((rc = check_launch(ctx, "pair sort"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[2], s));
     gsr::launch_blend(s, records, n, n_poses, sk, offsets, capacity, c, k, tg, rgb, depth, tfinal,
@@ -404,7 +411,6 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     ctx->last_poses = P;
     ctx->last_tiles = tg.n_tiles;
     ctx->last_capacity = capacity;
-    ctx->last_vis_slot = (int64_t)nvc;
     return GSR_OK;
 }
 
@@ -469,11 +475,12 @@ int gsr_get_stats(gsr_ctx *ctx, gsr_stats *out) {
     out->n_poses = ctx->last_poses;
     out->pair_capacity = (int64_t)ctx->last_capacity;
     if (ctx->last_poses > 0) {
+        uint32_t nv = 0;
+        HIPC(ctx, hipMemcpy(&nv, (uint32_t *)ctx->vbase.p + ctx->last_poses, sizeof(nv), hipMemcpyDeviceToHost));
+        out->n_visible = (int64_t)nv;
         uint64_t v = 0;
-        HIPC(ctx, hipMemcpy(&v, (uint64_t *)ctx->voff.p + ctx->last_vis_slot, sizeof(v), hipMemcpyDeviceToHost));
-        out->n_visible = (int64_t)v;
         const uint64_t pn = (uint64_t)std::max<int64_t>(1, ctx->last_poses * ctx->last_n);
-        HIPC(ctx, hipMemcpy(&v, (uint64_t *)ctx->pair_off.p + pn, sizeof(v), hipMemcpyDeviceToHost));
+        HIPC(ctx, hipMemcpy(&v, (uint64_t *)ctx->poff.p + pn, sizeof(v), hipMemcpyDeviceToHost));
         out->n_pairs = (int64_t)v;
     }
     out->overflow = flags[gsr::FLAG_OVERFLOW];
