@@ -7,14 +7,18 @@
 // takes T below t_min (that layer counts).
 //
 // One 256-thread block per (tile, pose); wave w owns pixel rows 4w..4w+3 of the
-// tile (a 16x4 band), one pixel per lane. The block walks the tile's list in
-// chunks of 256 records: every thread stages one record in LDS (with the conic
-// pre-scaled by -log2(e)/2 and a per-record log2 threshold that folds both the
-// cutoff and the alpha floor into one compare) and marks which bands its pixel
-// rectangle overlaps; a ballot per band turns the marks into one 256-bit mask
-// per wave. Each wave then visits only the set bits, in list order, so a record
-// costs a band nothing unless it can reach it. A wave stops when all of its
-// pixels have stopped; the block stops loading when all waves have.
+// tile (a 16x4 band), one pixel per lane, and the band is split into four 4x4
+// quarters (lanes 16q..16q+15). The block walks the tile's list in chunks of
+// 252 records: every thread but the last of each wave stages one record in LDS (conic pre-scaled by
+// -log2(e)/2, log2 of the opacity, and one log2 threshold that folds the
+// cutoff and the alpha floor) and marks which (band, quarter) cells its pixel
+// rectangle overlaps; ballots turn the marks into one 64-bit mask per (band,
+// quarter, 64-record group). A wave then walks its four quarters side by side:
+// step i takes the i-th record of every quarter (a quarter with fewer reads a
+// record that cannot contribute; the per-step slots are laid out in LDS once
+// per chunk), so a chunk costs the longest of the four walks rather than their
+// union. Each pixel still sees its records in list order. A wave stops when all of its pixels have stopped; the block stops
+// loading when all waves have.
 #include "internal.h"
 
 namespace gsr {
@@ -22,7 +26,9 @@ namespace gsr {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kChunk = kThreads;
+constexpr int kStage = 63;              // records staged per wave and chunk (lane 63 idle)
+constexpr int kChunk = 4 * kStage;      // records per chunk
+constexpr int kDummy = 255;             // LDS slot (wave 3, lane 63) of a record that never contributes
 constexpr float kLog2e = 1.4426950408889634f;
 
 struct BlendConsts {
@@ -41,91 +47,154 @@ __global__ __launch_bounds__(kThreads) void k_blend(const float4 *__restrict__ r
                                                     BlendConsts k, float *__restrict__ out_rgb,
                                                     float *__restrict__ out_depth, float *__restrict__ out_t,
                                                     unsigned long long *__restrict__ counters) {
-    __shared__ float4 s_rec[kChunk * 3];
-    __shared__ uint64_t s_mask[4][4];  // [band][wave that staged the records]
+    __shared__ float4 s_rec[kThreads * 3];  // slot = staging thread
+    __shared__ uint64_t s_mask[4][4][4];  // [band][quarter][64-record group]
+    __shared__ uint32_t s_words[4][256];  // per wave: slot of every quarter, one byte each, per step
 
     const int tile = blockIdx.x, pose = blockIdx.y;
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int pi = tx * 16 + (lane & 15);
-    const int pj = ty * 16 + wave * 4 + (lane >> 4);
+    const int quarter = lane >> 4;
+    const int pi = tx * 16 + quarter * 4 + (lane & 3);
+    const int pj = ty * 16 + wave * 4 + ((lane >> 2) & 3);
     const float px = (float)pi + 0.5f, py = (float)pj + 0.5f;
     const bool in_image = pi < width && pj < height;
-    const int row0 = ty * 16;
+    const int row0 = ty * 16, col0 = tx * 16;
 
     const uint64_t list = (uint64_t)pose * n_tiles + tile;
     const uint64_t beg = offsets[list];
     const uint64_t end = min(offsets[list + 1], capacity);
     const float4 *rec_pose = records + (int64_t)pose * n * 3;
 
-    float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f;
-    bool live = in_image;
+    if (tid == kDummy) {  // this thread never stages a record
+        const float inf = __builtin_inff();
+        s_rec[kDummy * 3 + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_rec[kDummy * 3 + 1] = make_float4(0.f, inf, 0.f, 0.f);
+        s_rec[kDummy * 3 + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+
+    // A pixel is live (still compositing) while T >= t_min: T never increases and
+    // stops changing once the pixel has stopped, so no separate flag is kept.
+    float T = in_image ? 1.f : 0.f, cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f;
     unsigned n_contrib = 0, n_visits = 0;  // only with kCount
+    const uint32_t lane_sh = 8u * quarter;  // the lane's byte of a slot word
+    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const char *s_rec_bytes = reinterpret_cast<const char *>(s_rec);
 
     for (uint64_t c0 = beg; c0 < end; c0 += kChunk) {
-        // stage one record per thread
-        const uint64_t kk = c0 + tid;
-        uint32_t bands = 0;
-        if (kk < end) {
+        // stage one record per thread (lanes 0..62 of every wave)
+        const uint64_t kk = c0 + (uint64_t)wave * kStage + lane;
+        uint32_t cells = 0;  // bit 4 * band + quarter
+        if (lane < kStage && kk < end) {
             const uint32_t g = pairs[kk];
             const float4 *r = rec_pose + (int64_t)g * 3;
             const float4 q0 = r[0], q1 = r[1], q2 = r[2];
-            const float o = q1.y;
-            const float thr = fmaxf(k.cut_p2, k.log2_amin - __log2f(o));
+            const float lo = __log2f(q1.y);
+            const float thr = fmaxf(k.cut_p2 + lo, k.log2_amin);
             s_rec[tid * 3 + 0] = make_float4(q0.x, q0.y, q0.z * k.neg_half_log2e, q0.w * (2.f * k.neg_half_log2e));
-            s_rec[tid * 3 + 1] = make_float4(q1.x * k.neg_half_log2e, thr, o, q2.y);
+            s_rec[tid * 3 + 1] = make_float4(q1.x * k.neg_half_log2e, thr, lo, q2.y);
             s_rec[tid * 3 + 2] = make_float4(q1.z, q1.w, q2.x, 0.f);
-            const uint32_t ry = __float_as_uint(q2.w);
-            const int j0 = (int)(ry & 0xffffu), j1 = (int)(ry >> 16);
+            const uint32_t rx = __float_as_uint(q2.z), ry = __float_as_uint(q2.w);
+            const int i0 = (int)(rx & 0xffffu) - col0, i1 = (int)(rx >> 16) - col0;
+            const int j0 = (int)(ry & 0xffffu) - row0, j1 = (int)(ry >> 16) - row0;
+            uint32_t xs = 0, ys = 0;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int b0 = row0 + 4 * b, b1 = b0 + 3;
-                if (j0 <= b1 && j1 >= b0) bands |= 1u << b;
+                if (i0 <= 4 * b + 3 && i1 >= 4 * b) xs |= 1u << b;
+                if (j0 <= 4 * b + 3 && j1 >= 4 * b) ys |= 1u << b;
             }
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if ((ys >> b) & 1u) cells |= xs << (4 * b);
         }
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint64_t m = __ballot((bands >> b) & 1u);
-            if (lane == 0) s_mask[b][wave] = m;
+        for (int c = 0; c < 16; ++c) {
+            const uint64_t m = __ballot((cells >> c) & 1u);
+            if (lane == 0) s_mask[c >> 2][c & 3][wave] = m;
         }
         __syncthreads();
 
-        if (__ballot(live) != 0) {
-            for (int sw = 0; sw < 4; ++sw) {
-                // the mask is the same in every lane: move it to scalar registers so
-                // the walk over its set bits is scalar control flow
-                const uint64_t mv = s_mask[wave][sw];
-                uint64_t m = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(mv >> 32)) << 32) |
-                             (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mv);
-                while (m) {
-                    const int j = (int)__builtin_ctzll(m);
-                    m &= m - 1;
-                    const int idx = sw * 64 + j;
-                    const float4 a = s_rec[idx * 3 + 0];
-                    const float4 b = s_rec[idx * 3 + 1];
-                    const float4 c = s_rec[idx * 3 + 2];
-                    const float dx = px - a.x, dy = py - a.y;
-                    const float p2 = (a.z * dx + a.w * dy) * dx + b.x * dy * dy;
-                    float al = fminf(k.alpha_max, b.z * __builtin_amdgcn_exp2f(p2));
-                    const bool ok = live && p2 >= b.y;
-                    al = ok ? al : 0.f;
-                    if (kCount) {
-                        n_contrib += ok;
-                        ++n_visits;
+        const uint32_t n_groups = (uint32_t)min<uint64_t>(4, (end - c0 + kStage - 1) / kStage);
+        uint64_t lm = __ballot(!(T < k.t_min));  // live lanes
+        if (lm != 0) {
+            // Step i visits the i-th record (in list order) of every quarter that
+            // overlaps it, or the dummy slot when the quarter has fewer. The record
+            // in slot 64 g + l is entered by lane l at its rank in each quarter's
+            // walk. One wave: its LDS accesses complete in program order.
+#pragma unroll
+            for (int e = 0; e < 4; ++e) s_words[wave][e * 64 + lane] = 0xffffffffu;
+            uint8_t *words = reinterpret_cast<uint8_t *>(&s_words[wave][0]);
+            uint32_t cnt[4], steps = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t run = 0;
+                if (((lm >> (16 * q)) & 0xffffull) != 0) {
+                    for (uint32_t grp = 0; grp < n_groups; ++grp) {
+                        const uint64_t mv = s_mask[wave][q][grp];
+                        const uint32_t mlo = __builtin_amdgcn_readfirstlane((uint32_t)mv);
+                        const uint32_t mhi = __builtin_amdgcn_readfirstlane((uint32_t)(mv >> 32));
+                        const uint64_t m = ((uint64_t)mhi << 32) | mlo;
+                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, 0u));
+                        if (__builtin_amdgcn_inverse_ballot_w64(m)) words[(run + rank) * 4 + q] = (uint8_t)(grp * 64 + lane);
+                        run += (uint32_t)__popcll(m);
                     }
+                }
+                cnt[q] = run;
+                steps = max(steps, run);
+            }
+            // Software pipeline, unrolled twice so the two register sets alternate:
+            // the slots and geometry of step i + 1 are read during step i.
+            auto load = [&](uint32_t w, uint32_t &o, float4 &ra, float4 &rb) {
+                o = ((w >> lane_sh) & 0xffu) * 48u;
+                ra = *reinterpret_cast<const float4 *>(s_rec_bytes + o);
+                rb = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 16);
+            };
+            // one step on a staged record; false when the wave is done with the chunk
+            auto step = [&](uint32_t o, const float4 &ra, const float4 &rb) -> bool {
+                const float dx = px - ra.x, dy = py - ra.y;
+                const float p2 = (ra.z * dx + ra.w * dy) * dx + (rb.x * dy * dy + rb.z);
+                const bool ok = __builtin_amdgcn_inverse_ballot_w64(lm) && p2 >= rb.y;
+                if (kCount) {
+                    n_contrib += ok;
+                    ++n_visits;
+                }
+                if (ok) {
+                    const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
+                    const float al = fminf(k.alpha_max, __builtin_amdgcn_exp2f(p2));
                     const float w = al * T;
                     cr += c.x * w;
                     cg += c.y * w;
                     cb += c.z * w;
-                    dep += b.w * w;
+                    dep += rb.w * w;
                     T -= w;
-                    live = live && !(T < k.t_min);
                 }
-                if (__ballot(live) == 0) goto wave_done;
+                const uint64_t lm_next = __ballot(!(T < k.t_min));
+                if (lm_next != lm) {
+                    lm = lm_next;
+                    if (lm == 0) return false;
+                    // steps still needed by the quarters that have live pixels
+                    uint32_t need = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (((lm >> (16 * q)) & 0xffffull) != 0) need = max(need, cnt[q]);
+                    steps = __builtin_amdgcn_readfirstlane(need);
+                }
+                return true;
+            };
+            uint32_t o0, o1;
+            float4 a0, b0, a1, b1;
+            load(s_words[wave][0], o0, a0, b0);
+            uint32_t word = s_words[wave][1];
+            for (uint32_t i = 0; i < steps; i += 2) {
+                load(word, o1, a1, b1);      // step i + 1 (slot index <= 252)
+                word = s_words[wave][i + 2];  // (<= 253)
+                if (!step(o0, a0, b0) || i + 1 >= steps) break;
+                load(word, o0, a0, b0);      // step i + 2
+                word = s_words[wave][i + 3];  // i + 1 < steps <= 252, so <= 253
+                if (!step(o1, a1, b1)) break;
             }
         }
-    wave_done:
-        if (__syncthreads_count(live) == 0) break;
+        if (__syncthreads_count(!(T < k.t_min)) == 0) break;
     }
 
     if (kCount) {

@@ -81,17 +81,17 @@ void launch_fill_u64(hipStream_t s, unsigned long long *p, uint64_t n, unsigned 
 // tmp must hold scan_tmp_elems(n) uint64.
 uint64_t scan_tmp_elems(uint64_t n);
 void launch_scan(hipStream_t s, const uint32_t *count, uint64_t n, uint64_t *offsets, uint64_t *tmp,
-                 const uint64_t *d_n);
+                 const uint32_t *d_n);
 // Per-pose stable sort of the visible Gaussians by depth bits. Input: the
 // preprocess's regions in (kb, vb) with vcount. Output: vb[vbase[p] ..
 // vbase[p+1]) = pose p's indices front to back, kb = their tile counts,
-// vbase[P] = visible total, roff[radix_count_elems] = visible total (uint64).
-// ka, va, kb, vb hold P * n entries; rcnt radix_count_elems, roff one more.
+// vbase[P] = visible total; nv[p] = pose p's visible count.
+// ka, va, kb, vb hold P * n entries; rcnt and roff radix_count_elems each.
 uint64_t radix_blocks_per_pose(int64_t n);
 uint64_t radix_count_elems(int64_t n, int n_poses);
 void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vcount, const uint32_t *ntiles,
-                       uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t *rcnt, uint64_t *roff,
-                       uint64_t *scan_tmp, uint32_t *vbase);
+                       uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t *rcnt, uint32_t *roff,
+                       uint32_t *nv, uint32_t *vbase);
 // pseg[p] = min(first pair of pose p, capacity), p in [0, P]; poff[total_slot] is the pair total.
 void launch_pair_segments(hipStream_t s, const uint64_t *poff, uint64_t total_slot, const uint32_t *vbase,
                           int n_poses, uint64_t capacity, uint64_t *pseg);

@@ -35,7 +35,7 @@ struct gsr_ctx {
     struct Buf {
         void *p = nullptr;
         size_t bytes = 0;
-    } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, vbase, poff, pseg, scan_tmp,
+    } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, poff, pseg, scan_tmp,
         ptile, pk, sk, cnt, total, block_base, offsets, grey_q, partials;
     // last render
     int64_t last_n = 0, last_poses = 0, last_tiles = 0;
@@ -202,7 +202,7 @@ int gsr_destroy(gsr_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     gsr_ctx::Buf *bufs[] = {&ctx->records, &ctx->ntiles,  &ctx->rect,     &ctx->vcount,  &ctx->sort_ka,
-                            &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb,  &ctx->rcnt,    &ctx->roff,
+                            &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb,  &ctx->rcnt,    &ctx->roff,    &ctx->nv,
                             &ctx->vbase,   &ctx->poff,    &ctx->pseg,     &ctx->scan_tmp, &ctx->ptile,
                             &ctx->pk,      &ctx->sk,      &ctx->cnt,      &ctx->total,   &ctx->block_base,
                             &ctx->offsets, &ctx->grey_q,  &ctx->partials};
@@ -334,11 +334,12 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
         (rc = ensure(ctx, ctx->sort_kb, pn * sizeof(uint32_t), "depth sort")) ||
         (rc = ensure(ctx, ctx->sort_vb, pn * sizeof(uint32_t), "depth sort")) ||
         (rc = ensure(ctx, ctx->rcnt, n_rc * sizeof(uint32_t), "radix counts")) ||
-        (rc = ensure(ctx, ctx->roff, (n_rc + 1) * sizeof(uint64_t), "radix offsets")) ||
+        (rc = ensure(ctx, ctx->roff, n_rc * sizeof(uint32_t), "radix offsets")) ||
+        (rc = ensure(ctx, ctx->nv, (uint64_t)P * sizeof(uint32_t), "pose visible counts")) ||
         (rc = ensure(ctx, ctx->vbase, ((uint64_t)P + 1) * sizeof(uint32_t), "pose bases")) ||
         (rc = ensure(ctx, ctx->poff, (pn + 1) * sizeof(uint64_t), "pair offsets")) ||
         (rc = ensure(ctx, ctx->pseg, ((uint64_t)P + 1) * sizeof(uint64_t), "pair segments")) ||
-        (rc = ensure(ctx, ctx->scan_tmp, gsr::scan_tmp_elems(std::max(std::max(n_rc, pn), n_lists)) * sizeof(uint64_t),
+        (rc = ensure(ctx, ctx->scan_tmp, gsr::scan_tmp_elems(std::max(pn, n_lists)) * sizeof(uint64_t),
                      "scan")) ||
         (rc = ensure(ctx, ctx->offsets, (n_lists + 1) * sizeof(uint64_t), "offsets")) ||
         (rc = ensure(ctx, ctx->total, n_lists * sizeof(uint32_t), "list totals")) ||
@@ -348,7 +349,7 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     uint32_t *ntiles = (uint32_t *)ctx->ntiles.p;
     uint32_t *sort_kb = (uint32_t *)ctx->sort_kb.p, *sort_vb = (uint32_t *)ctx->sort_vb.p;
     uint32_t *vbase = (uint32_t *)ctx->vbase.p;
-    uint64_t *roff = (uint64_t *)ctx->roff.p;
+    uint32_t *roff = (uint32_t *)ctx->roff.p;
     uint64_t *poff = (uint64_t *)ctx->poff.p;
     uint64_t *pseg = (uint64_t *)ctx->pseg.p;
     uint64_t *scan_tmp = (uint64_t *)ctx->scan_tmp.p;
@@ -369,9 +370,9 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     if (ev) HIPC(ctx, hipEventRecord(ev->e[1], s));
     // S2-S3: per-pose depth order of the visible Gaussians, then pair offsets in that order
     gsr::launch_depth_sort(s, n, n_poses, (const uint32_t *)ctx->vcount.p, ntiles, (uint32_t *)ctx->sort_ka.p,
-                           (uint32_t *)ctx->sort_va.p, sort_kb, sort_vb, (uint32_t *)ctx->rcnt.p, roff, scan_tmp,
-                           vbase);
-    gsr::launch_scan(s, sort_kb, pn, poff, scan_tmp, roff + n_rc);
+                           (uint32_t *)ctx->sort_va.p, sort_kb, sort_vb, (uint32_t *)ctx->rcnt.p, roff,
+                           (uint32_t *)ctx->nv.p, vbase);
+    gsr::launch_scan(s, sort_kb, pn, poff, scan_tmp, vbase + P);
     if ((rc = check_launch(ctx, "depth sort"))) return rc;
 
     uint64_t capacity;

@@ -50,10 +50,14 @@ __device__ uint64_t block_inclusive_scan(uint64_t x, uint64_t *s_wave /*[4]*/) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ count, uint64_t n_max,
-                                                          const uint64_t *__restrict__ d_n,
+                                                          const uint32_t *__restrict__ d_n,
                                                           uint64_t *__restrict__ block_sums) {
     __shared__ uint64_t s_wave[4];
-    const uint64_t n = d_n ? min(*d_n, n_max) : n_max;
+    const uint64_t n = d_n ? min((uint64_t)*d_n, n_max) : n_max;
+    if ((uint64_t)blockIdx.x * kScanTile >= n) {  // whole block past the end
+        if (threadIdx.x == 0) block_sums[blockIdx.x] = 0;
+        return;
+    }
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
     uint64_t sum = 0;
 #pragma unroll
@@ -84,11 +88,12 @@ __global__ __launch_bounds__(kThreads) void k_scan_blocks(uint64_t *__restrict__
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restrict__ count, uint64_t n_max,
-                                                         const uint64_t *__restrict__ d_n,
+                                                         const uint32_t *__restrict__ d_n,
                                                          const uint64_t *__restrict__ block_prefix,
                                                          uint64_t *__restrict__ offsets) {
     __shared__ uint64_t s_wave[4];
-    const uint64_t n = d_n ? min(*d_n, n_max) : n_max;
+    const uint64_t n = d_n ? min((uint64_t)*d_n, n_max) : n_max;
+    if ((uint64_t)blockIdx.x * kScanTile >= n) return;
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint64_t sum = 0;
@@ -144,12 +149,13 @@ __device__ __forceinline__ bool radix_elem(const RadixSrc &src, int p, uint32_t 
     return i < (uint64_t)src.vbase[p + 1];
 }
 
-// cnt[(p * 256 + digit) * nbp + j] = elements of radix block (p, j) with that digit.
+// cnt[(p * nbp + j) * 256 + digit] = elements of radix block (p, j) with that digit.
 __global__ __launch_bounds__(kThreads) void k_radix_count(RadixSrc src, int shift, uint32_t nbp,
                                                           uint32_t *__restrict__ cnt) {
     __shared__ uint32_t s_h[kDigits];
     const int p = blockIdx.y;
     const uint32_t j = blockIdx.x;
+    if (!src.vcount && (uint64_t)src.vbase[p] + (uint64_t)j * kRB >= src.vbase[p + 1]) return;  // empty block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     s_h[threadIdx.x] = 0;
     __syncthreads();
@@ -158,24 +164,92 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(RadixSrc src, int shif
         if (radix_elem(src, p, j, wave, c, lane, idx)) atomicAdd(&s_h[(src.keys[idx] >> shift) & 0xffu], 1u);
     }
     __syncthreads();
-    cnt[((uint64_t)p * kDigits + threadIdx.x) * nbp + j] = s_h[threadIdx.x];
+    cnt[((uint64_t)p * nbp + j) * kDigits + threadIdx.x] = s_h[threadIdx.x];
+}
+
+// Exclusive scan of one uint32 per thread across a 256-thread block; *total gets the sum.
+__device__ uint32_t block_exclusive_scan_u32(uint32_t x, uint32_t *s_wave /*[4]*/, uint32_t *total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < wave; ++w) add += s_wave[w];
+    *total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    __syncthreads();
+    return add + inc - x;
+}
+
+// Per pose (one block, thread = digit): off[(p * nbp + j) * 256 + d] = position,
+// relative to the pose's first element, of radix block j's first element with
+// digit d (digits in order, blocks in order within a digit). With nv non-null
+// (first pass) the pose's element count is stored there.
+__global__ __launch_bounds__(kThreads) void k_radix_offsets(const uint32_t *__restrict__ cnt, uint32_t nbp,
+                                                            const uint32_t *__restrict__ vbase,
+                                                            uint32_t *__restrict__ off, uint32_t *__restrict__ nv) {
+    __shared__ uint32_t s_wave[4];
+    const int p = blockIdx.x;
+    const int d = threadIdx.x;
+    const uint32_t nb = nv ? nbp : (uint32_t)(((uint64_t)vbase[p + 1] - vbase[p] + kRB - 1) / kRB);
+    const uint32_t *c = cnt + (uint64_t)p * nbp * kDigits + d;
+    uint32_t tot = 0;
+    for (uint32_t j = 0; j < nb; ++j) tot += c[(uint64_t)j * kDigits];
+    uint32_t all = 0;
+    uint32_t run = block_exclusive_scan_u32(tot, s_wave, &all);
+    uint32_t *o = off + (uint64_t)p * nbp * kDigits + d;
+    for (uint32_t j = 0; j < nb; ++j) {
+        const uint32_t x = c[(uint64_t)j * kDigits];
+        o[(uint64_t)j * kDigits] = run;
+        run += x;
+    }
+    if (nv && d == 0) nv[p] = all;
+}
+
+// vbase[p] = sum of nv[q] over q < p, for p in [0, P]. One block.
+__global__ __launch_bounds__(kThreads) void k_pose_bases(const uint32_t *__restrict__ nv, int P,
+                                                         uint32_t *__restrict__ vbase) {
+    __shared__ uint32_t s_wave[4];
+    __shared__ uint32_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 <= P; c0 += kThreads) {
+        const int p = c0 + threadIdx.x;
+        const uint32_t x = p < P ? nv[p] : 0u;
+        uint32_t all = 0;
+        const uint32_t ex = block_exclusive_scan_u32(x, s_wave, &all);
+        const uint32_t carry = s_carry;
+        if (p <= P) vbase[p] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + all;
+        __syncthreads();
+    }
 }
 
 // Stable scatter of radix block (p, j). Each wave walks its share 64 elements at
 // a time: lanes with equal digits are matched with ballots and ranked in lane
-// order, and a per-wave, per-digit LDS counter carries the rank across chunks
-// (one wave: its LDS accesses take effect in program order). The block then
+// order; the group's leader adds the group size to a per-wave, per-digit LDS
+// counter and the value it returns (the wave's earlier elements with that
+// digit) is broadcast to the group. One wave's LDS operations complete in
+// program order, so the counters carry the order across chunks without a
+// barrier, and the chunks' atomics need not wait for each other. The block then
 // turns the per-wave counts into output positions from off[]. With kLast the
 // keys are not written: vout gets the sorted indices and kout their tile counts
 // (ntiles[p][index]), the input of the pair-offset scan.
 template <bool kLast>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixSrc src, int shift, uint32_t nbp,
-                                                            const uint64_t *__restrict__ off,
+                                                            const uint32_t *__restrict__ off,
                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                             const uint32_t *__restrict__ ntiles, int64_t n) {
     __shared__ uint32_t s_cnt[4][kDigits];
     const int p = blockIdx.y;
     const uint32_t j = blockIdx.x;
+    const uint32_t pose_base = src.vbase[p];
+    if (!src.vcount && (uint64_t)pose_base + (uint64_t)j * kRB >= src.vbase[p + 1]) return;  // empty block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int w = 0; w < 4; ++w) s_cnt[w][threadIdx.x] = 0;
@@ -203,15 +277,17 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixSrc src, int sh
             peers &= bit ? m : ~m;
         }
         const uint32_t r = (uint32_t)__popcll(peers & lt_mask);
-        const uint32_t base = valid ? s_cnt[wave][d] : 0u;
-        if (valid && r == 0) s_cnt[wave][d] = base + (uint32_t)__popcll(peers);
+        uint32_t old = 0;
+        if (valid && r == 0) old = atomicAdd(&s_cnt[wave][d], (uint32_t)__popcll(peers));
+        const int leader = (int)__builtin_ctzll(peers | (1ull << 63));
+        const uint32_t base = (uint32_t)__shfl((int)old, leader, 64);
         rnk[c] = valid ? base + r : 0xffffffffu;
     }
     __syncthreads();
     {
         // s_cnt[w][d] <- output position of wave w's first element with digit d
         const int d = threadIdx.x;
-        uint32_t run = (uint32_t)off[((uint64_t)p * kDigits + d) * nbp + j];
+        uint32_t run = pose_base + off[((uint64_t)p * nbp + j) * kDigits + d];
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             const uint32_t c = s_cnt[w][d];
@@ -232,12 +308,6 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixSrc src, int sh
             vout[pos] = val[c];
         }
     }
-}
-
-// vbase[p] = first dense position of pose p (p in [0, P]; vbase[P] = visible total).
-__global__ void k_radix_bases(const uint64_t *__restrict__ off, int P, uint32_t nbp, uint32_t *__restrict__ vbase) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p <= P) vbase[p] = (uint32_t)off[(uint64_t)p * kDigits * nbp];
 }
 
 // pseg[p] = first pair of pose p, clamped to the capacity (p in [0, P]).
@@ -340,7 +410,8 @@ __global__ void k_col_prefix(uint32_t *__restrict__ cnt, const uint32_t *__restr
 // One wave per block walks its pairs in order, 64 at a time (loads issued
 // kAhead chunks ahead): lanes that name the same tile are matched with
 // tile_bits ballots, take consecutive slots in lane order, and the group's
-// leader advances that tile's cursor in LDS.
+// leader advances that tile's cursor in LDS with an atomic whose return value
+// (the group's first slot) is broadcast to the group.
 constexpr int kAhead = 4;
 
 __global__ __launch_bounds__(64) void k_tile_scatter(const uint16_t *__restrict__ ptile,
@@ -380,10 +451,12 @@ __global__ __launch_bounds__(64) void k_tile_scatter(const uint16_t *__restrict_
             }
             if (!valid) peers = 0;
             const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-            // one wave: its LDS reads and writes take effect in program order, so no
-            // barrier (which would also wait for the scattered global stores)
-            const uint32_t base = valid ? s_run[t] : 0u;
-            if (valid && rank == 0) s_run[t] = base + (uint32_t)__popcll(peers);
+            // one wave: its LDS operations complete in program order, so no barrier
+            // (which would also wait for the scattered global stores)
+            uint32_t old = 0;
+            if (valid && rank == 0) old = atomicAdd(&s_run[t], (uint32_t)__popcll(peers));
+            const int leader = (int)__builtin_ctzll(peers | (1ull << 63));
+            const uint32_t base = (uint32_t)__shfl((int)old, leader, 64);
             if (valid) sk[base + rank] = kk[a];
         }
     }
@@ -406,7 +479,7 @@ void launch_fill_u64(hipStream_t s, unsigned long long *p, uint64_t n, unsigned 
 uint64_t scan_tmp_elems(uint64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
 void launch_scan(hipStream_t s, const uint32_t *count, uint64_t n, uint64_t *offsets, uint64_t *tmp,
-                 const uint64_t *d_n) {
+                 const uint32_t *d_n) {
     const uint64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb == 0) {
         launch_fill_u64(s, reinterpret_cast<unsigned long long *>(offsets), 1, 0ull);
@@ -424,10 +497,9 @@ uint64_t radix_count_elems(int64_t n, int n_poses) {
 }
 
 void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vcount, const uint32_t *ntiles,
-                       uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t *rcnt, uint64_t *roff,
-                       uint64_t *scan_tmp, uint32_t *vbase) {
+                       uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t *rcnt, uint32_t *roff,
+                       uint32_t *nv, uint32_t *vbase) {
     const uint32_t nbp = (uint32_t)radix_blocks_per_pose(n);
-    const uint64_t n_cnt = radix_count_elems(n, n_poses);
     const dim3 grid(nbp, (unsigned)n_poses);
     // pass 0: regions in (kb, vb) -> dense (ka, va); passes 1, 2 ping-pong; pass 3 -> (kb = tile counts, vb = index)
     const uint32_t *kin = kb, *vin = vb;
@@ -435,10 +507,9 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
         RadixSrc src{kin, vin, pass == 0 ? vcount : nullptr, n, vbase};
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_radix_count, grid, dim3(kThreads), 0, s, src, shift, nbp, rcnt);
-        launch_scan(s, rcnt, n_cnt, roff, scan_tmp, nullptr);
-        if (pass == 0)
-            hipLaunchKernelGGL(k_radix_bases, dim3((unsigned)((n_poses + kThreads) / kThreads)), dim3(kThreads), 0, s,
-                               roff, n_poses, nbp, vbase);
+        hipLaunchKernelGGL(k_radix_offsets, dim3((unsigned)n_poses), dim3(kThreads), 0, s, rcnt, nbp, vbase, roff,
+                           pass == 0 ? nv : nullptr);
+        if (pass == 0) hipLaunchKernelGGL(k_pose_bases, dim3(1), dim3(kThreads), 0, s, nv, n_poses, vbase);
         uint32_t *ko = (pass & 1) ? kb : ka, *vo = (pass & 1) ? vb : va;
         if (pass == 3)
             hipLaunchKernelGGL(k_radix_scatter<true>, grid, dim3(kThreads), 0, s, src, shift, nbp, roff, ko, vo, ntiles,
