@@ -9,16 +9,17 @@
 // One 256-thread block per (tile, pose); wave w owns pixel rows 4w..4w+3 of the
 // tile (a 16x4 band), one pixel per lane, and the band is split into four 4x4
 // quarters (lanes 16q..16q+15). The block walks the tile's list in chunks of
-// 252 records: every thread but the last of each wave stages one record in LDS (conic pre-scaled by
-// -log2(e)/2, log2 of the opacity, and one log2 threshold that folds the
-// cutoff and the alpha floor) and marks which (band, quarter) cells its pixel
-// rectangle overlaps; ballots turn the marks into one 64-bit mask per (band,
-// quarter, 64-record group). A wave then walks its four quarters side by side:
-// step i takes the i-th record of every quarter (a quarter with fewer reads a
-// record that cannot contribute; the per-step slots are laid out in LDS once
-// per chunk), so a chunk costs the longest of the four walks rather than their
-// union. Each pixel still sees its records in list order. A wave stops when all of its pixels have stopped; the block stops
-// loading when all waves have.
+// 252 records: every thread but the last of each wave stages one record in LDS
+// (the conic as two scaled square-root factors, log2 of the opacity, and one
+// log2 threshold that folds the cutoff and the alpha floor) and marks which
+// (band, quarter) cells its support ellipse overlaps; ballots turn the marks
+// into one 64-bit mask per (band, quarter, 64-record group). A wave then walks
+// its four quarters side by side: step i takes the i-th record of every
+// quarter (a quarter with fewer reads a record that cannot contribute; the
+// per-step slots are laid out in LDS once per chunk), so a chunk costs the
+// longest of the four walks rather than their union. Each pixel still sees its
+// records in list order. A wave stops when all of its pixels have stopped; the
+// block stops loading when all waves have.
 #include "internal.h"
 
 namespace gsr {
@@ -32,7 +33,8 @@ constexpr int kDummy = 255;             // LDS slot (wave 3, lane 63) of a recor
 constexpr float kLog2e = 1.4426950408889634f;
 
 struct BlendConsts {
-    float neg_half_log2e;  // -log2(e)/2: p2 = -log2(e)/2 * d^2
+    float cull_r2;         // cutoff with a margin, for the (band, quarter) overlap test
+    float sqrt_half_log2e;  // sqrt(log2(e)/2): scales the conic factors
     float cut_p2;          // -log2(e)/2 * cutoff_d2
     float log2_amin;       // log2(alpha_min)
     float alpha_max;
@@ -40,7 +42,7 @@ struct BlendConsts {
 };
 
 template <bool kCount>
-__global__ __launch_bounds__(kThreads) void k_blend(const float4 *__restrict__ records, int64_t n,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_blend(const float4 *__restrict__ records, int64_t n,
                                                     const uint32_t *__restrict__ pairs,
                                                     const uint64_t *__restrict__ offsets, uint64_t capacity,
                                                     int width, int height, int tiles_x, int n_tiles,
@@ -78,7 +80,6 @@ __global__ __launch_bounds__(kThreads) void k_blend(const float4 *__restrict__ r
     float T = in_image ? 1.f : 0.f, cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f;
     unsigned n_contrib = 0, n_visits = 0;  // only with kCount
     const uint32_t lane_sh = 8u * quarter;  // the lane's byte of a slot word
-    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const char *s_rec_bytes = reinterpret_cast<const char *>(s_rec);
 
     for (uint64_t c0 = beg; c0 < end; c0 += kChunk) {
@@ -89,23 +90,67 @@ __global__ __launch_bounds__(kThreads) void k_blend(const float4 *__restrict__ r
             const uint32_t g = pairs[kk];
             const float4 *r = rec_pose + (int64_t)g * 3;
             const float4 q0 = r[0], q1 = r[1], q2 = r[2];
+            const uint32_t rx = __float_as_uint(q2.z), ry = __float_as_uint(q2.w);
+            const int j0 = (int)(ry & 0xffffu) - row0, j1 = (int)(ry >> 16) - row0;
+            // Cells are (band, quarter) pixel blocks. The support ellipse
+            // E = {d^2 <= cutoff} meets a cell iff the x-extent of E within the
+            // band's rows overlaps the quarter's columns (E is convex). With
+            // dx = x - u, dy = y - v: the chord of E at height dy spans
+            // (-B dy -+ sqrt(A R2 - det dy^2)) / A; its right end is concave in dy
+            // and peaks at dy = -(B / C) dxm with value dxm = sqrt(R2 C / det)
+            // (the left end mirrors it), so over a band the extreme is either that
+            // peak or the chord at the nearer band edge. R2 carries a margin that
+            // covers float32 rounding, so the test never drops a contributing cell.
+            const float A = q0.z, B = q0.w, C = q1.x;
+            // products of floats are exact in double, so det keeps its accuracy for
+            // thin, tilted ellipses where A C and B^2 nearly cancel
+            const float det = (float)((double)A * (double)C - (double)B * (double)B);
+            // d^2 = A dx^2 + 2 B dx dy + C dy^2 = (m11 dx + m12 dy)^2 + (m22 dy)^2 with
+            // m11 = sqrt(A), m12 = B / m11, m22 = sqrt(det / A): a sum of squares, so a
+            // needle-thin footprint loses about sqrt(A C / det) times less to rounding
+            // than the expanded form. Scaled by sqrt(log2(e) / 2), the exponent of
+            // o exp(-d^2 / 2) in base 2 is log2(o) - t1^2 - t2^2.
+            const float iA = __builtin_amdgcn_rcpf(A), idet = __builtin_amdgcn_rcpf(det);
+            const float m11 = sqrtf(A);
+            const float m12 = B / m11;
+            const float m22 = sqrtf(fmaxf(det, 0.f) / A);  // 0: the limit of a degenerate streak
             const float lo = __log2f(q1.y);
             const float thr = fmaxf(k.cut_p2 + lo, k.log2_amin);
-            s_rec[tid * 3 + 0] = make_float4(q0.x, q0.y, q0.z * k.neg_half_log2e, q0.w * (2.f * k.neg_half_log2e));
-            s_rec[tid * 3 + 1] = make_float4(q1.x * k.neg_half_log2e, thr, lo, q2.y);
+            s_rec[tid * 3 + 0] = make_float4(q0.x, q0.y, m11 * k.sqrt_half_log2e, m12 * k.sqrt_half_log2e);
+            s_rec[tid * 3 + 1] = make_float4(m22 * k.sqrt_half_log2e, thr, lo, q2.y);
             s_rec[tid * 3 + 2] = make_float4(q1.z, q1.w, q2.x, 0.f);
-            const uint32_t rx = __float_as_uint(q2.z), ry = __float_as_uint(q2.w);
-            const int i0 = (int)(rx & 0xffffu) - col0, i1 = (int)(rx >> 16) - col0;
-            const int j0 = (int)(ry & 0xffffu) - row0, j1 = (int)(ry >> 16) - row0;
-            uint32_t xs = 0, ys = 0;
+            const float R2 = k.cull_r2;
+            // hardware reciprocal and square root (about 1 ulp) for the overlap test:
+            // the margin in R2 covers them
+            const float ryv = __builtin_amdgcn_sqrtf(R2 * A * idet);
+            const float dxm = __builtin_amdgcn_sqrtf(R2 * C * idet);
+            const float dys = -B * __builtin_amdgcn_rcpf(C) * dxm;  // dy of the rightmost point of E
+            const float u_rel = q0.x - (float)col0, v_rel = q0.y - (float)row0;
+            if (det > 0.f && __builtin_isfinite(ryv) && __builtin_isfinite(dxm) && __builtin_isfinite(dys)) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if (i0 <= 4 * b + 3 && i1 >= 4 * b) xs |= 1u << b;
-                if (j0 <= 4 * b + 3 && j1 >= 4 * b) ys |= 1u << b;
+                for (int b = 0; b < 4; ++b) {
+                    if (!(j0 <= 4 * b + 3 && j1 >= 4 * b)) continue;
+                    const float ylo = fmaxf(((float)(4 * b) + 0.5f) - v_rel, -ryv);
+                    const float yhi = fminf(((float)(4 * b) + 3.5f) - v_rel, ryv);
+                    if (!(ylo <= yhi)) continue;
+                    const float yr = fminf(fmaxf(dys, ylo), yhi);   // where the right end peaks in the band
+                    const float yl = fminf(fmaxf(-dys, ylo), yhi);  // where the left end bottoms
+                    const float xr = (-B * yr + __builtin_amdgcn_sqrtf(fmaxf(A * R2 - det * yr * yr, 0.f))) * iA;
+                    const float xl = (-B * yl - __builtin_amdgcn_sqrtf(fmaxf(A * R2 - det * yl * yl, 0.f))) * iA;
+                    const float x_hi = u_rel + xr + 1e-3f, x_lo = u_rel + xl - 1e-3f;  // tile-relative
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (x_hi >= (float)(4 * q) + 0.5f && x_lo <= (float)(4 * q) + 3.5f) cells |= 1u << (4 * b + q);
+                }
+            } else {
+                // fall back to the pixel rectangle
+                const int i0 = (int)(rx & 0xffffu) - col0, i1 = (int)(rx >> 16) - col0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (j0 <= 4 * b + 3 && j1 >= 4 * b && i0 <= 4 * q + 3 && i1 >= 4 * q) cells |= 1u << (4 * b + q);
             }
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if ((ys >> b) & 1u) cells |= xs << (4 * b);
         }
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
@@ -152,7 +197,8 @@ __global__ __launch_bounds__(kThreads) void k_blend(const float4 *__restrict__ r
             // one step on a staged record; false when the wave is done with the chunk
             auto step = [&](uint32_t o, const float4 &ra, const float4 &rb) -> bool {
                 const float dx = px - ra.x, dy = py - ra.y;
-                const float p2 = (ra.z * dx + ra.w * dy) * dx + (rb.x * dy * dy + rb.z);
+                const float t1 = ra.z * dx + ra.w * dy, t2 = rb.x * dy;
+                const float p2 = (rb.z - t1 * t1) - t2 * t2;
                 const bool ok = __builtin_amdgcn_inverse_ballot_w64(lm) && p2 >= rb.y;
                 if (kCount) {
                     n_contrib += ok;
@@ -227,7 +273,8 @@ void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, 
                   const TileGrid &tg, float *rgb, float *depth, float *tfinal, bool count_evals,
                   unsigned long long *counters) {
     BlendConsts bc;
-    bc.neg_half_log2e = -0.5f * kLog2e;
+    bc.cull_r2 = k.cutoff_d2 * 1.001f + 1e-3f;
+    bc.sqrt_half_log2e = sqrtf(0.5f * kLog2e);
     bc.cut_p2 = -0.5f * kLog2e * k.cutoff_d2;
     bc.log2_amin = log2f(k.alpha_min);
     bc.alpha_max = k.alpha_max;

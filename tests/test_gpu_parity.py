@@ -63,6 +63,31 @@ def test_tiny_scenes_ragged_sizes(ctx, seed, n, w, h):
         compare_render(rgb[p], dep[p], tf[p], out, f"pose {p}")
 
 
+@pytest.mark.parametrize("seed", [41, 42])
+def test_thin_tilted_and_huge_gaussians(ctx, seed):
+    """Needle-thin tilted footprints and a few that cover the whole image: the
+    cases where a (band, quarter) overlap test of the support ellipse is most
+    easily wrong, and where A C - B^2 of the conic cancels the most."""
+    say(f"anisotropic scene seed {seed}")
+    sc = W.tiny_scene(seed, n=400, width=96, height=64, n_poses=3)
+    g = sc.gaussians
+    rng = np.random.default_rng(seed + 1000)
+    s = np.exp(np.stack([rng.normal(-0.3, 0.8, g.n), rng.normal(-5.0, 0.5, g.n),
+                         rng.normal(-4.0, 1.0, g.n)], 1))
+    s[:6] = np.exp(rng.normal(0.8, 0.2, (6, 3)))  # a few very large ones
+    thin = W.Gaussians(g.means, s.astype(np.float32), g.quats, g.opacity, g.rgb)
+    sm = load(ctx, thin)
+    rgb, dep, tf = gpu_render(ctx, sm, sc.camera, sc.poses)
+    recs, nts, offs, pairs = gpu_buffers(ctx)
+    pr = prep(thin)
+    T = _tiles(sc.camera)
+    for p in range(3):
+        out, rec, ks, vs, rng_ = oracle_pose(pr, sc.poses[p], sc.camera)
+        check_records(recs, nts, rec, thin.n, p)
+        check_pairs(offs, pairs, ks, vs, rng_, p, T)
+        compare_render(rgb[p], dep[p], tf[p], out, f"pose {p}")
+
+
 def test_empty_and_all_culled(ctx):
     say("empty submap and a scene entirely behind the camera")
     sc = W.tiny_scene(30, n=50)
