@@ -77,10 +77,10 @@ __global__ __launch_bounds__(kThreads) void k_pack(int64_t n_map, const float *_
 // S1. One thread per Gaussian, looping over a chunk of poses (blockIdx.y), so
 // the packed record is read once per chunk. For each pose the screen record is
 // written, the number of tiles its 3-sigma rectangle touches is stored (0 =
-// culled) with the tile rectangle, and each wave packs the (depth bits, index)
-// of its visible Gaussians, in index order, at the front of its 64-slot region
-// of vz / vg, with their number in vcount[pose * n_regions + region]: the
-// input of the per-pose depth sort.
+// culled) with the tile rectangle, and each wave packs the (depth bits, record
+// slot = pose * n + index) of its visible Gaussians, in index order, at the
+// front of its 64-slot region of vz / vg, with their number in
+// vcount[pose * n_regions + region]: the input of the per-pose depth sort.
 __global__ __launch_bounds__(kThreads) void k_preprocess(
     const float4 *__restrict__ packed, int64_t n, const float *__restrict__ poses, int n_poses, Camera cam,
     Consts k, TileGrid tg, float4 *__restrict__ records, uint32_t *__restrict__ ntiles, uint2 *__restrict__ rect,
@@ -178,41 +178,161 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
             if (nt != 0) {
                 const int64_t slot = (int64_t)p * n + (region << 6) + __popcll(vis & lt_mask);
                 vz[slot] = zb;
-                vg[slot] = (uint32_t)g;
+                vg[slot] = (uint32_t)((int64_t)p * n + g);  // the record slot of (pose, Gaussian)
             }
         }
     }
 }
 
-// S2, pair emission in front-to-back order: element i of pose p's depth-sorted
-// segment [vbase[p], vbase[p+1]) is Gaussian sg[i]; it writes one pair per tile
-// of its rectangle (row-major) at poff[i] (exclusive scan of the tile counts in
-// that order): the tile id within the pose and the submap index.
-__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ sg,
-                                                   const uint64_t *__restrict__ poff,
-                                                   const uint32_t *__restrict__ vbase,
-                                                   const uint2 *__restrict__ rect, int64_t n, TileGrid tg,
+// S2, pair emission in front-to-back order. The depth-sorted visible Gaussians of
+// all poses are cut into emission blocks of kEmitTile elements (pose p owns
+// [vbase[p], vbase[p+1]); snt holds their tile counts, sg their indices). Block
+// sums of the tile counts are scanned (sort.hip), and each block then lays its
+// pairs out contiguously from its prefix: element i writes one pair per tile of
+// its rectangle (row-major): the tile id within the pose and the submap index.
+constexpr int kEmitItems = 8;
+constexpr int kEmitTile = kThreads * kEmitItems;
+
+// Exclusive scan of one uint32 per thread across a kThreads block; *total = sum.
+__device__ uint32_t emit_block_scan(uint32_t x, uint32_t *s_wave /*[4]*/, uint32_t *total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < wave; ++w) add += s_wave[w];
+    *total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    __syncthreads();
+    return add + inc - x;
+}
+
+// sums[b] = tile counts of emission block b (0 past the visible total vbase[P]).
+__global__ __launch_bounds__(kThreads) void k_emit_sums(const uint32_t *__restrict__ snt,
+                                                        const uint32_t *__restrict__ vbase, int P,
+                                                        uint64_t *__restrict__ sums) {
+    __shared__ uint32_t s_wave[4];
+    const uint64_t nv = vbase[P];
+    const uint64_t e0 = (uint64_t)blockIdx.x * kEmitTile;
+    if (e0 >= nv) {
+        if (threadIdx.x == 0) sums[blockIdx.x] = 0;
+        return;
+    }
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kEmitItems; ++k) {
+        const uint64_t e = e0 + (uint64_t)k * kThreads + threadIdx.x;
+        if (e < nv) sum += snt[e];
+    }
+    // tile counts per element are < 2^15 and a block has 2048 elements: fits 32 bits
+    uint32_t total = 0;
+    (void)emit_block_scan((uint32_t)sum, s_wave, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// pseg[p] = min(first pair of pose p, capacity) for p in [0, P]; prefix holds the
+// scanned block sums and prefix[n_blocks] the pair total.
+__global__ __launch_bounds__(kThreads) void k_pair_segments(const uint32_t *__restrict__ snt,
+                                                            const uint32_t *__restrict__ vbase, int P,
+                                                            const uint64_t *__restrict__ prefix, uint64_t n_blocks,
+                                                            uint64_t capacity, uint64_t *__restrict__ pseg) {
+    __shared__ uint32_t s_wave[4];
+    const int p = blockIdx.x;
+    const uint64_t e = vbase[p], nv = vbase[P];
+    if (e >= nv) {
+        if (threadIdx.x == 0) pseg[p] = min(prefix[n_blocks], capacity);
+        return;
+    }
+    const uint64_t b = e / kEmitTile, e0 = b * kEmitTile;
+    uint32_t part = 0;
+    for (uint64_t i = e0 + threadIdx.x; i < e; i += kThreads) part += snt[i];
+    uint32_t total = 0;
+    (void)emit_block_scan(part, s_wave, &total);
+    if (threadIdx.x == 0) pseg[p] = min(prefix[b] + total, capacity);
+}
+
+// One block per emission block. The block scans its elements' tile counts, then
+// lays the pairs out window by window in LDS: every thread expands its own
+// elements' rectangles (row-major) into the window slots given by the scan, and
+// the block copies the window to the output with coalesced stores.
+constexpr int kEmitWin = 8192;  // pairs per LDS window
+
+__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ snt, const uint32_t *__restrict__ slots,
+                                                   const uint32_t *__restrict__ vbase, int P,
+                                                   const uint2 *__restrict__ rect, int64_t n,
+                                                   const uint64_t *__restrict__ prefix, TileGrid tg,
                                                    uint16_t *__restrict__ ptile, uint32_t *__restrict__ pk,
                                                    uint64_t capacity, int *__restrict__ flags) {
-    const int p = blockIdx.y;
-    const uint64_t end = vbase[p + 1];
+    __shared__ uint16_t s_tile[kEmitWin];
+    __shared__ uint32_t s_key[kEmitWin];
+    __shared__ uint32_t s_wave[4];
+    const uint64_t nv = vbase[P];
+    const uint64_t e0 = (uint64_t)blockIdx.x * kEmitTile;
+    if (e0 >= nv) return;
+    // this thread's elements: e0 + t * kEmitItems + k (consecutive, for the scan)
+    const uint64_t et = e0 + (uint64_t)threadIdx.x * kEmitItems;
+    uint32_t cnt[kEmitItems], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kEmitItems; ++k) {
+        cnt[k] = et + k < nv ? snt[et + k] : 0u;
+        sum += cnt[k];
+    }
+    uint32_t total = 0;
+    const uint32_t first = emit_block_scan(sum, s_wave, &total);
+    uint32_t key[kEmitItems];
+    uint2 rc[kEmitItems];
+#pragma unroll
+    for (int k = 0; k < kEmitItems; ++k) {
+        key[k] = 0;
+        rc[k] = make_uint2(0u, 0u);
+        if (cnt[k]) {
+            const uint32_t slot = slots[et + k];
+            rc[k] = rect[slot];
+            key[k] = slot - (uint32_t)((uint64_t)slot / (uint64_t)n) * (uint32_t)n;  // submap index
+        }
+    }
+    const uint64_t base = prefix[blockIdx.x];
     bool over = false;
-    for (uint64_t i = vbase[p] + (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < end;
-         i += (uint64_t)gridDim.x * kThreads) {
-        const uint32_t g = sg[i];
-        const uint2 e = rect[(int64_t)p * n + g];
-        const int tx0 = (int)(e.x & 0xffffu), tx1 = (int)(e.x >> 16);
-        const int ty0 = (int)(e.y & 0xffffu), ty1 = (int)(e.y >> 16);
-        uint64_t pos = poff[i];
-        for (int yy = ty0; yy <= ty1; ++yy)
-            for (int xx = tx0; xx <= tx1; ++xx, ++pos) {
-                if (pos < capacity) {
-                    ptile[pos] = (uint16_t)(yy * tg.tiles_x + xx);
-                    pk[pos] = g;
-                } else {
-                    over = true;
+    for (uint32_t w0 = 0; w0 < total; w0 += kEmitWin) {
+        const uint32_t w1 = min(total, w0 + kEmitWin);
+        uint32_t pos = first;
+#pragma unroll
+        for (int k = 0; k < kEmitItems; ++k) {
+            const uint32_t c = cnt[k];
+            // this element's pairs [pos, pos + c) clipped to the window
+            const uint32_t j0 = pos < w0 ? w0 - pos : 0u;
+            const uint32_t j1 = min(c, w1 > pos ? w1 - pos : 0u);
+            if (j0 < j1) {
+                const uint32_t tx0 = rc[k].x & 0xffffu, tx1 = rc[k].x >> 16, ty0 = rc[k].y & 0xffffu;
+                const uint32_t w = tx1 - tx0 + 1;
+                uint32_t ty = ty0 + j0 / w, tx = tx0 + j0 % w;
+                for (uint32_t j = j0; j < j1; ++j) {
+                    const uint32_t q = pos + j - w0;
+                    s_tile[q] = (uint16_t)(ty * (uint32_t)tg.tiles_x + tx);
+                    s_key[q] = key[k];
+                    if (++tx > tx1) {
+                        tx = tx0;
+                        ++ty;
+                    }
                 }
             }
+            pos += c;
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < w1 - w0; i += kThreads) {
+            const uint64_t o = base + w0 + i;
+            if (o < capacity) {
+                ptile[o] = s_tile[i];
+                pk[o] = s_key[i];
+            } else {
+                over = true;
+            }
+        }
+        __syncthreads();
     }
     if (over) atomicOr(&flags[FLAG_OVERFLOW], 1);
 }
@@ -239,14 +359,26 @@ void launch_preprocess(hipStream_t s, const float4 *packed, int64_t n, const flo
                        ntiles, rect, vz, vg, vcount);
 }
 
-void launch_emit(hipStream_t s, const uint32_t *sg, const uint64_t *poff, const uint32_t *vbase, const uint2 *rect,
-                 int64_t n, int n_poses, const TileGrid &tg, uint16_t *ptile, uint32_t *pk, uint64_t capacity,
-                 int *flags) {
+uint64_t emit_blocks(uint64_t n_max) { return std::max<uint64_t>(1, (n_max + kEmitTile - 1) / kEmitTile); }
+
+void launch_emit_sums(hipStream_t s, const uint32_t *snt, const uint32_t *vbase, int n_poses, uint64_t n_max,
+                      uint64_t *sums) {
+    hipLaunchKernelGGL(k_emit_sums, dim3((unsigned)emit_blocks(n_max)), dim3(kThreads), 0, s, snt, vbase, n_poses,
+                       sums);
+}
+
+void launch_pair_segments(hipStream_t s, const uint32_t *snt, const uint32_t *vbase, int n_poses,
+                          const uint64_t *prefix, uint64_t n_max, uint64_t capacity, uint64_t *pseg) {
+    hipLaunchKernelGGL(k_pair_segments, dim3((unsigned)n_poses + 1), dim3(kThreads), 0, s, snt, vbase, n_poses,
+                       prefix, emit_blocks(n_max), capacity, pseg);
+}
+
+void launch_emit(hipStream_t s, const uint32_t *snt, const uint32_t *sg, const uint32_t *vbase, int n_poses,
+                 const uint2 *rect, int64_t n, uint64_t n_max, const uint64_t *prefix, const TileGrid &tg,
+                 uint16_t *ptile, uint32_t *pk, uint64_t capacity, int *flags) {
     if (n <= 0) return;
-    // about 8 Gaussians per thread at full visibility
-    const int64_t per_pose = std::min<int64_t>(256, std::max<int64_t>(1, (n + 8 * kThreads - 1) / (8 * kThreads)));
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)per_pose, (unsigned)n_poses), dim3(kThreads), 0, s, sg, poff, vbase,
-                       rect, n, tg, ptile, pk, capacity, flags);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks(n_max)), dim3(kThreads), 0, s, snt, sg, vbase, n_poses,
+                       rect, n, prefix, tg, ptile, pk, capacity, flags);
 }
 
 }  // namespace gsr

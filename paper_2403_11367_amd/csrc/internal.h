@@ -61,17 +61,28 @@ void launch_pack(hipStream_t s, int64_t n_map, const float *means, const float *
 int64_t preprocess_blocks(int64_t n);
 // Screen records, tile counts ntiles[p][g] (0 = culled) and tile rectangles
 // rect[p][g] = (tx0 | tx1 << 16, ty0 | ty1 << 16); per pose and 64-Gaussian
-// region, the (depth bits, index) of the visible Gaussians packed at the front
-// of the region's slots of vz / vg (P * n each) and their count in
-// vcount[p * ceil(n / 64) + region].
+// region, the (depth bits, record slot p * n + g) of the visible Gaussians
+// packed at the front of the region's slots of vz / vg (P * n each) and their
+// count in vcount[p * ceil(n / 64) + region].
 void launch_preprocess(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
                        uint32_t *ntiles, uint2 *rect, uint32_t *vz, uint32_t *vg, uint32_t *vcount);
-// Pairs in front-to-back order per pose: tile id within the pose and submap
-// index, at the pair offsets poff of the depth-sorted elements sg.
-void launch_emit(hipStream_t s, const uint32_t *sg, const uint64_t *poff, const uint32_t *vbase, const uint2 *rect,
-                 int64_t n, int n_poses, const TileGrid &tg, uint16_t *ptile, uint32_t *pk, uint64_t capacity,
-                 int *flags);
+// Pair emission in front-to-back order. The depth-sorted visible Gaussians
+// (snt: tile counts, sg: record slots p * n + g; pose p owns [vbase[p],
+// vbase[p+1]), at most n_max = P * n of them) are cut into emit_blocks(n_max)
+// blocks.
+//   launch_emit_sums:     sums[b] = tile counts of block b
+//   (launch_block_scan:   sums -> exclusive prefix, pair total in sums[emit_blocks])
+//   launch_pair_segments: pseg[p] = min(first pair of pose p, capacity), p in [0, P]
+//   launch_emit:          ptile / pk = tile id within the pose / submap index per pair
+uint64_t emit_blocks(uint64_t n_max);
+void launch_emit_sums(hipStream_t s, const uint32_t *snt, const uint32_t *vbase, int n_poses, uint64_t n_max,
+                      uint64_t *sums);
+void launch_pair_segments(hipStream_t s, const uint32_t *snt, const uint32_t *vbase, int n_poses,
+                          const uint64_t *prefix, uint64_t n_max, uint64_t capacity, uint64_t *pseg);
+void launch_emit(hipStream_t s, const uint32_t *snt, const uint32_t *sg, const uint32_t *vbase, int n_poses,
+                 const uint2 *rect, int64_t n, uint64_t n_max, const uint64_t *prefix, const TileGrid &tg,
+                 uint16_t *ptile, uint32_t *pk, uint64_t capacity, int *flags);
 
 // ---- sort.hip ----
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t value);
@@ -84,7 +95,7 @@ void launch_scan(hipStream_t s, const uint32_t *count, uint64_t n, uint64_t *off
                  const uint32_t *d_n);
 // Per-pose stable sort of the visible Gaussians by depth bits. Input: the
 // preprocess's regions in (kb, vb) with vcount. Output: vb[vbase[p] ..
-// vbase[p+1]) = pose p's indices front to back, kb = their tile counts,
+// vbase[p+1]) = pose p's record slots front to back, kb = their tile counts,
 // vbase[P] = visible total; nv[p] = pose p's visible count.
 // ka, va, kb, vb hold P * n entries; rcnt and roff radix_count_elems each.
 uint64_t radix_blocks_per_pose(int64_t n);
@@ -92,13 +103,14 @@ uint64_t radix_count_elems(int64_t n, int n_poses);
 void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vcount, const uint32_t *ntiles,
                        uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t *rcnt, uint32_t *roff,
                        uint32_t *nv, uint32_t *vbase);
-// pseg[p] = min(first pair of pose p, capacity), p in [0, P]; poff[total_slot] is the pair total.
-void launch_pair_segments(hipStream_t s, const uint64_t *poff, uint64_t total_slot, const uint32_t *vbase,
-                          int n_poses, uint64_t capacity, uint64_t *pseg);
+// Exclusive scan of sums[0 .. nb_max) in place (only the first *d_nb with d_nb),
+// total to *total. One block.
+void launch_block_scan(hipStream_t s, uint64_t *sums, uint64_t nb_max, const uint64_t *d_nb, uint64_t *total);
 // Stable counting sort of the emitted pairs by tile within each pose. Writes
 // the per-(pose, tile) list offsets [P*T + 1] and the bucketed indices sk.
 // cnt holds bucket_blocks_max(capacity, P) * T entries, total P * T,
-// block_base P + 1; n_tiles <= kMaxTilesPerPose.
+// block_base P + 1, scan_tmp scan_tmp_elems(P * T);
+// 1 <= tile_bits <= 14 with 2^tile_bits >= n_tiles (n_tiles <= kMaxTilesPerPose).
 uint64_t bucket_blocks_max(uint64_t capacity, int n_poses);
 void launch_bucket(hipStream_t s, const uint16_t *ptile, const uint32_t *pk, const uint64_t *pseg, int n_poses,
                    uint64_t capacity, int n_tiles, int tile_bits, uint32_t *block_base, uint32_t *cnt,

@@ -35,7 +35,7 @@ struct gsr_ctx {
     struct Buf {
         void *p = nullptr;
         size_t bytes = 0;
-    } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, poff, pseg, scan_tmp,
+    } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, esum, pseg, scan_tmp,
         ptile, pk, sk, cnt, total, block_base, offsets, grey_q, partials;
     // last render
     int64_t last_n = 0, last_poses = 0, last_tiles = 0;
@@ -203,7 +203,7 @@ int gsr_destroy(gsr_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     gsr_ctx::Buf *bufs[] = {&ctx->records, &ctx->ntiles,  &ctx->rect,     &ctx->vcount,  &ctx->sort_ka,
                             &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb,  &ctx->rcnt,    &ctx->roff,    &ctx->nv,
-                            &ctx->vbase,   &ctx->poff,    &ctx->pseg,     &ctx->scan_tmp, &ctx->ptile,
+                            &ctx->vbase,   &ctx->esum,    &ctx->pseg,     &ctx->scan_tmp, &ctx->ptile,
                             &ctx->pk,      &ctx->sk,      &ctx->cnt,      &ctx->total,   &ctx->block_base,
                             &ctx->offsets, &ctx->grey_q,  &ctx->partials};
     for (auto *b : bufs)
@@ -337,7 +337,7 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
         (rc = ensure(ctx, ctx->roff, n_rc * sizeof(uint32_t), "radix offsets")) ||
         (rc = ensure(ctx, ctx->nv, (uint64_t)P * sizeof(uint32_t), "pose visible counts")) ||
         (rc = ensure(ctx, ctx->vbase, ((uint64_t)P + 1) * sizeof(uint32_t), "pose bases")) ||
-        (rc = ensure(ctx, ctx->poff, (pn + 1) * sizeof(uint64_t), "pair offsets")) ||
+        (rc = ensure(ctx, ctx->esum, (gsr::emit_blocks(pn) + 1) * sizeof(uint64_t), "emission sums")) ||
         (rc = ensure(ctx, ctx->pseg, ((uint64_t)P + 1) * sizeof(uint64_t), "pair segments")) ||
         (rc = ensure(ctx, ctx->scan_tmp, gsr::scan_tmp_elems(std::max(pn, n_lists)) * sizeof(uint64_t),
                      "scan")) ||
@@ -350,7 +350,8 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     uint32_t *sort_kb = (uint32_t *)ctx->sort_kb.p, *sort_vb = (uint32_t *)ctx->sort_vb.p;
     uint32_t *vbase = (uint32_t *)ctx->vbase.p;
     uint32_t *roff = (uint32_t *)ctx->roff.p;
-    uint64_t *poff = (uint64_t *)ctx->poff.p;
+    uint64_t *esum = (uint64_t *)ctx->esum.p;  // scanned block sums; the pair total at [emit_blocks]
+    const uint64_t n_eb = gsr::emit_blocks(pn);
     uint64_t *pseg = (uint64_t *)ctx->pseg.p;
     uint64_t *scan_tmp = (uint64_t *)ctx->scan_tmp.p;
     const float4 *records = (const float4 *)ctx->records.p;
@@ -372,12 +373,13 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     gsr::launch_depth_sort(s, n, n_poses, (const uint32_t *)ctx->vcount.p, ntiles, (uint32_t *)ctx->sort_ka.p,
                            (uint32_t *)ctx->sort_va.p, sort_kb, sort_vb, (uint32_t *)ctx->rcnt.p, roff,
                            (uint32_t *)ctx->nv.p, vbase);
-    gsr::launch_scan(s, sort_kb, pn, poff, scan_tmp, vbase + P);
+    gsr::launch_emit_sums(s, sort_kb, vbase, n_poses, pn, esum);
+    gsr::launch_block_scan(s, esum, n_eb, nullptr, esum + n_eb);
     if ((rc = check_launch(ctx, "depth sort"))) return rc;
 
     uint64_t capacity;
     if (cfg.pair_capacity == 0) {
-        HIPC(ctx, hipMemcpyAsync(ctx->h_pin, poff + pn, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        HIPC(ctx, hipMemcpyAsync(ctx->h_pin, esum + n_eb, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
         HIPC(ctx, hipStreamSynchronize(s));
         capacity = ctx->h_pin[0];
         ctx->last_pairs = (int64_t)capacity;
@@ -395,9 +397,9 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
         return rc;
     uint16_t *ptile = (uint16_t *)ctx->ptile.p;
     uint32_t *pk = (uint32_t *)ctx->pk.p, *sk = (uint32_t *)ctx->sk.p;
-    gsr::launch_pair_segments(s, poff, pn, vbase, n_poses, capacity, pseg);
-    gsr::launch_emit(s, sort_vb, poff, vbase, (const uint2 *)ctx->rect.p, n, n_poses, tg, ptile, pk, capacity,
-                     ctx->d_flags);
+    gsr::launch_pair_segments(s, sort_kb, vbase, n_poses, esum, pn, capacity, pseg);
+    gsr::launch_emit(s, sort_kb, sort_vb, vbase, n_poses, (const uint2 *)ctx->rect.p, n, pn, esum, tg, ptile, pk,
+                     capacity, ctx->d_flags);
     // S3-S4: stable bucketing by tile keeps the depth order inside every list
     gsr::launch_bucket(s, ptile, pk, pseg, n_poses, capacity, tg.n_tiles, tile_bits, (uint32_t *)ctx->block_base.p,
                        (uint32_t *)ctx->cnt.p, (uint32_t *)ctx->total.p, offsets, scan_tmp, sk);
@@ -481,7 +483,7 @@ int gsr_get_stats(gsr_ctx *ctx, gsr_stats *out) {
         out->n_visible = (int64_t)nv;
         uint64_t v = 0;
         const uint64_t pn = (uint64_t)std::max<int64_t>(1, ctx->last_poses * ctx->last_n);
-        HIPC(ctx, hipMemcpy(&v, (uint64_t *)ctx->poff.p + pn, sizeof(v), hipMemcpyDeviceToHost));
+        HIPC(ctx, hipMemcpy(&v, (uint64_t *)ctx->esum.p + gsr::emit_blocks(pn), sizeof(v), hipMemcpyDeviceToHost));
         out->n_pairs = (int64_t)v;
     }
     out->overflow = flags[gsr::FLAG_OVERFLOW];

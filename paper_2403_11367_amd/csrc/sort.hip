@@ -67,21 +67,46 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__rest
     if (threadIdx.x == kThreads - 1) block_sums[blockIdx.x] = inc;
 }
 
-// Single block: exclusive scan of the block sums in place; total to out_total.
-__global__ __launch_bounds__(kThreads) void k_scan_blocks(uint64_t *__restrict__ block_sums, uint64_t nb,
-                                                          uint64_t *__restrict__ out_total) {
-    __shared__ uint64_t s_wave[4];
+// Single block of kBigThreads: exclusive scan of the block sums in place (4 per
+// thread per round); total to out_total. With d_nb only the first *d_nb sums are
+// scanned (the rest are zero and left alone).
+constexpr int kBigThreads = 1024;
+constexpr int kBigItems = 4;
+
+__global__ __launch_bounds__(kBigThreads) void k_scan_blocks(uint64_t *__restrict__ block_sums, uint64_t nb_max,
+                                                             const uint64_t *__restrict__ d_nb,
+                                                             uint64_t *__restrict__ out_total) {
+    __shared__ uint64_t s_wave[kBigThreads / 64];
     __shared__ uint64_t s_carry;
+    const uint64_t nb = d_nb ? min(*d_nb, nb_max) : nb_max;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
-    for (uint64_t c0 = 0; c0 < nb; c0 += kThreads) {
-        const uint64_t i = c0 + threadIdx.x;
-        const uint64_t x = i < nb ? block_sums[i] : 0;
-        const uint64_t inc = block_inclusive_scan(x, s_wave);
-        const uint64_t carry = s_carry;
-        if (i < nb) block_sums[i] = carry + inc - x;
+    for (uint64_t c0 = 0; c0 < nb; c0 += (uint64_t)kBigThreads * kBigItems) {
+        const uint64_t i0 = c0 + (uint64_t)threadIdx.x * kBigItems;
+        uint64_t v[kBigItems], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kBigItems; ++k) {
+            v[k] = i0 + k < nb ? block_sums[i0 + k] : 0;
+            sum += v[k];
+        }
+        uint64_t inc = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) s_wave[wave] = inc;
         __syncthreads();
-        if (threadIdx.x == kThreads - 1) s_carry = carry + inc;
+        uint64_t run = s_carry + inc - sum;
+        for (int w = 0; w < wave; ++w) run += s_wave[w];
+#pragma unroll
+        for (int k = 0; k < kBigItems; ++k) {
+            if (i0 + k < nb) block_sums[i0 + k] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == kBigThreads - 1) s_carry = run;
         __syncthreads();
     }
     if (threadIdx.x == 0) *out_total = s_carry;
@@ -112,11 +137,12 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restr
 
 // ---- per-pose depth sort: stable LSD radix sort of the visible Gaussians ----
 // Keys are float32 depth bits (depths are above the near plane, so positive,
-// and order like their bits); values are submap indices. A pose's elements are
+// and order like their bits); values are record slots (pose * n + submap
+// index), which within a pose order like the indices. A pose's elements are
 // cut into radix blocks of kRB; per pass every block counts its digits, one
-// exclusive scan over (pose, digit, block) gives each block the output position
-// of its first element of every digit, and the block writes its elements there
-// in order. The first pass reads the preprocess's 64-slot regions (visible
+// block per pose scans the counts in (digit, block) order into each block's
+// output position for its first element of every digit, and the block writes
+// its elements there in order. The first pass reads the preprocess's 64-slot regions (visible
 // entries packed at the front of each), later passes the dense per-pose
 // segments [vbase[p], vbase[p+1]).
 constexpr int kRB = 4096;                  // elements per radix block
@@ -238,8 +264,8 @@ __global__ __launch_bounds__(kThreads) void k_pose_bases(const uint32_t *__restr
 // program order, so the counters carry the order across chunks without a
 // barrier, and the chunks' atomics need not wait for each other. The block then
 // turns the per-wave counts into output positions from off[]. With kLast the
-// keys are not written: vout gets the sorted indices and kout their tile counts
-// (ntiles[p][index]), the input of the pair-offset scan.
+// keys are not written: vout gets the sorted record slots and kout their tile
+// counts, the input of the pair emission.
 template <bool kLast>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixSrc src, int shift, uint32_t nbp,
                                                             const uint32_t *__restrict__ off,
@@ -302,23 +328,12 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixSrc src, int sh
         const uint32_t pos = s_cnt[wave][(key[c] >> shift) & 0xffu] + rnk[c];
         if (kLast) {
             vout[pos] = val[c];
-            kout[pos] = ntiles[(uint64_t)p * (uint64_t)n + val[c]];
+            kout[pos] = ntiles[val[c]];  // values are record slots (pose * n + index)
         } else {
             kout[pos] = key[c];
             vout[pos] = val[c];
         }
     }
-}
-
-// pseg[p] = first pair of pose p, clamped to the capacity (p in [0, P]).
-__global__ void k_pair_segments(const uint64_t *__restrict__ poff, uint64_t total_slot,
-                                const uint32_t *__restrict__ vbase, int P, uint64_t capacity,
-                                uint64_t *__restrict__ pseg) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > P) return;
-    const uint32_t v = vbase[p];
-    const uint64_t x = v < vbase[P] ? poff[v] : poff[total_slot];
-    pseg[p] = min(x, capacity);
 }
 
 // ---- tile bucketing: a stable counting sort of the pairs by tile, per pose ----
@@ -381,25 +396,48 @@ __global__ __launch_bounds__(kThreads) void k_tile_count(const uint16_t *__restr
     for (int t = threadIdx.x; t < n_tiles; t += kThreads) cnt[(uint64_t)gb * n_tiles + t] = s_hist[t];
 }
 
-// total[p * T + t] = pairs of list (p, t), summed over the pose's blocks.
+// total[p * T + t] = pairs of list (p, t), summed over the pose's blocks
+// (8 rows per step, so several loads are in flight per thread).
 __global__ void k_col_sum(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ block_base, int P,
                           int n_tiles, uint32_t *__restrict__ total) {
     const uint64_t l = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= (uint64_t)P * n_tiles) return;
     const int p = (int)(l / n_tiles), t = (int)(l % n_tiles);
-    uint32_t sum = 0;
-    for (uint32_t gb = block_base[p]; gb < block_base[p + 1]; ++gb) sum += cnt[(uint64_t)gb * n_tiles + t];
+    const uint32_t gb1 = block_base[p + 1];
+    uint32_t gb = block_base[p], sum = 0;
+    for (; gb + 8 <= gb1; gb += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = cnt[(uint64_t)(gb + u) * n_tiles + t];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sum += v[u];
+    }
+    for (; gb < gb1; ++gb) sum += cnt[(uint64_t)gb * n_tiles + t];
     total[l] = sum;
 }
 
-// cnt[gb][t] <- first output position of block gb's pairs of list (p, t).
+// cnt[gb][t] <- first output position of block gb's pairs of list (p, t). The
+// lists of a pose hold exactly the pose's pairs [pseg[p], pseg[p+1]), so the
+// exclusive scan of the totals over all P * T lists is the list start.
 __global__ void k_col_prefix(uint32_t *__restrict__ cnt, const uint32_t *__restrict__ block_base, int P, int n_tiles,
                              const uint64_t *__restrict__ offsets) {
     const uint64_t l = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= (uint64_t)P * n_tiles) return;
     const int p = (int)(l / n_tiles), t = (int)(l % n_tiles);
+    const uint32_t gb1 = block_base[p + 1];
+    uint32_t gb = block_base[p];
     uint32_t run = (uint32_t)offsets[l];
-    for (uint32_t gb = block_base[p]; gb < block_base[p + 1]; ++gb) {
+    for (; gb + 8 <= gb1; gb += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = cnt[(uint64_t)(gb + u) * n_tiles + t];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            cnt[(uint64_t)(gb + u) * n_tiles + t] = run;
+            run += v[u];
+        }
+    }
+    for (; gb < gb1; ++gb) {
         const uint64_t i = (uint64_t)gb * n_tiles + t;
         const uint32_t c = cnt[i];
         cnt[i] = run;
@@ -414,11 +452,12 @@ __global__ void k_col_prefix(uint32_t *__restrict__ cnt, const uint32_t *__restr
 // (the group's first slot) is broadcast to the group.
 constexpr int kAhead = 4;
 
+template <int kTileBits>
 __global__ __launch_bounds__(64) void k_tile_scatter(const uint16_t *__restrict__ ptile,
                                                      const uint32_t *__restrict__ pk,
                                                      const uint64_t *__restrict__ pseg, int P,
                                                      const uint32_t *__restrict__ block_base,
-                                                     const uint32_t *__restrict__ cnt, int n_tiles, int tile_bits,
+                                                     const uint32_t *__restrict__ cnt, int n_tiles,
                                                      uint32_t *__restrict__ sk) {
     extern __shared__ uint32_t s_run[];
     const uint32_t gb = blockIdx.x;
@@ -444,7 +483,8 @@ __global__ __launch_bounds__(64) void k_tile_scatter(const uint16_t *__restrict_
             const uint32_t t = tt[a];
             const bool valid = t != 0xffffffffu;
             uint64_t peers = __ballot(valid);
-            for (int b = 0; b < tile_bits; ++b) {
+#pragma unroll
+            for (int b = 0; b < kTileBits; ++b) {
                 const bool bit = (t >> b) & 1u;
                 const uint64_t m = __ballot(bit);
                 peers &= bit ? m : ~m;
@@ -486,8 +526,12 @@ void launch_scan(hipStream_t s, const uint32_t *count, uint64_t n, uint64_t *off
         return;
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, count, n, d_n, tmp);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kThreads), 0, s, tmp, nb, offsets + n);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBigThreads), 0, s, tmp, nb, nullptr, offsets + n);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, count, n, d_n, tmp, offsets);
+}
+
+void launch_block_scan(hipStream_t s, uint64_t *sums, uint64_t nb_max, const uint64_t *d_nb, uint64_t *total) {
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBigThreads), 0, s, sums, nb_max, d_nb, total);
 }
 
 uint64_t radix_blocks_per_pose(int64_t n) { return std::max<uint64_t>(1, ((uint64_t)n + kRB - 1) / kRB); }
@@ -522,29 +566,34 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
     }
 }
 
-void launch_pair_segments(hipStream_t s, const uint64_t *poff, uint64_t total_slot, const uint32_t *vbase,
-                          int n_poses, uint64_t capacity, uint64_t *pseg) {
-    hipLaunchKernelGGL(k_pair_segments, dim3((unsigned)((n_poses + kThreads) / kThreads)), dim3(kThreads), 0, s, poff,
-                       total_slot, vbase, n_poses, capacity, pseg);
-}
-
 uint64_t bucket_blocks_max(uint64_t capacity, int n_poses) { return (capacity + kBP - 1) / kBP + (uint64_t)n_poses; }
 
 void launch_bucket(hipStream_t s, const uint16_t *ptile, const uint32_t *pk, const uint64_t *pseg, int n_poses,
                    uint64_t capacity, int n_tiles, int tile_bits, uint32_t *block_base, uint32_t *cnt,
                    uint32_t *total, uint64_t *offsets, uint64_t *scan_tmp, uint32_t *sk) {
     const uint64_t nbm = bucket_blocks_max(capacity, n_poses);
-    const uint64_t n_lists = (uint64_t)n_poses * n_tiles;
-    const unsigned lblocks = (unsigned)((n_lists + kThreads - 1) / kThreads);
     const size_t lds = (size_t)n_tiles * sizeof(uint32_t);
     hipLaunchKernelGGL(k_seg_blocks, dim3(1), dim3(kThreads), 0, s, pseg, n_poses, block_base);
     hipLaunchKernelGGL(k_tile_count, dim3((unsigned)nbm), dim3(kThreads), lds, s, ptile, pseg, n_poses, block_base,
                        n_tiles, cnt);
+    const uint64_t n_lists = (uint64_t)n_poses * n_tiles;
+    const unsigned lblocks = (unsigned)((n_lists + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_col_sum, dim3(lblocks), dim3(kThreads), 0, s, cnt, block_base, n_poses, n_tiles, total);
     launch_scan(s, total, n_lists, offsets, scan_tmp, nullptr);
     hipLaunchKernelGGL(k_col_prefix, dim3(lblocks), dim3(kThreads), 0, s, cnt, block_base, n_poses, n_tiles, offsets);
-    hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)nbm), dim3(64), lds, s, ptile, pk, pseg, n_poses, block_base,
-                       cnt, n_tiles, tile_bits, sk);
+    const dim3 grid((unsigned)nbm), block(64);
+    switch (tile_bits) {
+#define GSR_SCATTER(B)                                                                                          \
+    case B:                                                                                                     \
+        hipLaunchKernelGGL(k_tile_scatter<B>, grid, block, lds, s, ptile, pk, pseg, n_poses, block_base, cnt,   \
+                           n_tiles, sk);                                                                        \
+        break;
+        GSR_SCATTER(1) GSR_SCATTER(2) GSR_SCATTER(3) GSR_SCATTER(4) GSR_SCATTER(5) GSR_SCATTER(6) GSR_SCATTER(7)
+        GSR_SCATTER(8) GSR_SCATTER(9) GSR_SCATTER(10) GSR_SCATTER(11) GSR_SCATTER(12) GSR_SCATTER(13)
+        GSR_SCATTER(14)
+#undef GSR_SCATTER
+        default: break;  // n_tiles <= kMaxTilesPerPose = 2^14 is checked by the caller
+    }
 }
 
 }  // namespace gsr
