@@ -145,8 +145,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restr
 // its elements there in order. The first pass reads the preprocess's 64-slot regions (visible
 // entries packed at the front of each), later passes the dense per-pose
 // segments [vbase[p], vbase[p+1]).
-constexpr int kRB = 4096;                  // elements per radix block
-constexpr int kRBWave = kRB / 4;           // per wave, contiguous
+constexpr int kRBWaves = 8;                // waves per radix block
+constexpr int kRBThreads = 64 * kRBWaves;
+constexpr int kRBWave = 1024;              // elements per wave, contiguous
+constexpr int kRB = kRBWaves * kRBWave;    // elements per radix block
 constexpr int kRBChunks = kRBWave / 64;    // 64-element chunks per wave
 constexpr int kRegionsPerBlock = kRB / 64;
 constexpr int kDigits = 256;
@@ -176,21 +178,21 @@ __device__ __forceinline__ bool radix_elem(const RadixSrc &src, int p, uint32_t 
 }
 
 // cnt[(p * nbp + j) * 256 + digit] = elements of radix block (p, j) with that digit.
-__global__ __launch_bounds__(kThreads) void k_radix_count(RadixSrc src, int shift, uint32_t nbp,
+__global__ __launch_bounds__(kRBThreads) void k_radix_count(RadixSrc src, int shift, uint32_t nbp,
                                                           uint32_t *__restrict__ cnt) {
     __shared__ uint32_t s_h[kDigits];
     const int p = blockIdx.y;
     const uint32_t j = blockIdx.x;
     if (!src.vcount && (uint64_t)src.vbase[p] + (uint64_t)j * kRB >= src.vbase[p + 1]) return;  // empty block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    s_h[threadIdx.x] = 0;
+    if (threadIdx.x < kDigits) s_h[threadIdx.x] = 0;
     __syncthreads();
     for (int c = 0; c < kRBChunks; ++c) {
         uint64_t idx = 0;
         if (radix_elem(src, p, j, wave, c, lane, idx)) atomicAdd(&s_h[(src.keys[idx] >> shift) & 0xffu], 1u);
     }
     __syncthreads();
-    cnt[((uint64_t)p * nbp + j) * kDigits + threadIdx.x] = s_h[threadIdx.x];
+    if (threadIdx.x < kDigits) cnt[((uint64_t)p * nbp + j) * kDigits + threadIdx.x] = s_h[threadIdx.x];
 }
 
 // Exclusive scan of one uint32 per thread across a 256-thread block; *total gets the sum.
@@ -267,18 +269,17 @@ __global__ __launch_bounds__(kThreads) void k_pose_bases(const uint32_t *__restr
 // keys are not written: vout gets the sorted record slots and kout their tile
 // counts, the input of the pair emission.
 template <bool kLast>
-__global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixSrc src, int shift, uint32_t nbp,
+__global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int shift, uint32_t nbp,
                                                             const uint32_t *__restrict__ off,
                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                             const uint32_t *__restrict__ ntiles, int64_t n) {
-    __shared__ uint32_t s_cnt[4][kDigits];
+    __shared__ uint32_t s_cnt[kRBWaves][kDigits];
     const int p = blockIdx.y;
     const uint32_t j = blockIdx.x;
     const uint32_t pose_base = src.vbase[p];
     if (!src.vcount && (uint64_t)pose_base + (uint64_t)j * kRB >= src.vbase[p + 1]) return;  // empty block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) s_cnt[w][threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < kRBWaves * kDigits; i += kRBThreads) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     uint32_t key[kRBChunks], val[kRBChunks], rnk[kRBChunks];
@@ -310,12 +311,12 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixSrc src, int sh
         rnk[c] = valid ? base + r : 0xffffffffu;
     }
     __syncthreads();
-    {
+    if (threadIdx.x < kDigits) {
         // s_cnt[w][d] <- output position of wave w's first element with digit d
         const int d = threadIdx.x;
         uint32_t run = pose_base + off[((uint64_t)p * nbp + j) * kDigits + d];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < kRBWaves; ++w) {
             const uint32_t c = s_cnt[w][d];
             s_cnt[w][d] = run;
             run += c;
@@ -550,16 +551,16 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
     for (int pass = 0; pass < 4; ++pass) {
         RadixSrc src{kin, vin, pass == 0 ? vcount : nullptr, n, vbase};
         const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_radix_count, grid, dim3(kThreads), 0, s, src, shift, nbp, rcnt);
+        hipLaunchKernelGGL(k_radix_count, grid, dim3(kRBThreads), 0, s, src, shift, nbp, rcnt);
         hipLaunchKernelGGL(k_radix_offsets, dim3((unsigned)n_poses), dim3(kThreads), 0, s, rcnt, nbp, vbase, roff,
                            pass == 0 ? nv : nullptr);
         if (pass == 0) hipLaunchKernelGGL(k_pose_bases, dim3(1), dim3(kThreads), 0, s, nv, n_poses, vbase);
         uint32_t *ko = (pass & 1) ? kb : ka, *vo = (pass & 1) ? vb : va;
         if (pass == 3)
-            hipLaunchKernelGGL(k_radix_scatter<true>, grid, dim3(kThreads), 0, s, src, shift, nbp, roff, ko, vo, ntiles,
+            hipLaunchKernelGGL(k_radix_scatter<true>, grid, dim3(kRBThreads), 0, s, src, shift, nbp, roff, ko, vo, ntiles,
                                n);
         else
-            hipLaunchKernelGGL(k_radix_scatter<false>, grid, dim3(kThreads), 0, s, src, shift, nbp, roff, ko, vo,
+            hipLaunchKernelGGL(k_radix_scatter<false>, grid, dim3(kRBThreads), 0, s, src, shift, nbp, roff, ko, vo,
                                ntiles, n);
         kin = ko;
         vin = vo;
