@@ -35,15 +35,17 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _blend_traffic():
-    """HBM bytes per blend launch from the committed rocprofv3 counter summary,
-    if it was taken on the current blend source; else None."""
+def _blend_traffic(n_groups):
+    """HBM bytes per blend launch from the committed rocprofv3 counter summary, if
+    it was taken on the current blend source with the same number of launches per
+    render; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     txt = open(TRAFFIC_FILE).read()
     m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     m_h = re.search(r"blend_source_sha256:\s*([0-9a-f]{64})", txt)
-    if not (m_b and m_h):
+    m_g = re.search(r"launches_per_render:\s*([0-9]+)", txt)
+    if not (m_b and m_h and m_g) or int(m_g.group(1)) != n_groups:
         return None
     cur = hashlib.sha256(open(BLEND_SRC, "rb").read()).hexdigest()
     return float(m_b.group(1)) if m_h.group(1) == cur else None
@@ -79,6 +81,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-candidates", type=int, default=2, help="oracle sample size (0 = skip)")
+    ap.add_argument("--pose-groups", type=int, default=0,
+                    help="pose groups per render (0 = the library's automatic choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy before the timed loop (for rocprofv3 counter scaling)")
     args = ap.parse_args()
@@ -117,10 +121,11 @@ def main():
 
     # one counting render (untimed): exact pair total and evaluation counts of this workload
     sm = ctx.load_submap(*gmap, index=idx_t)
-    ctx.render(sm, cam, poses_t, default_cfg(flags=RENDER_COUNT_EVALS))
+    ctx.render(sm, cam, poses_t, default_cfg(flags=RENDER_COUNT_EVALS, pose_groups=args.pose_groups))
     st0 = ctx.stats()
-    n_pairs, n_vis = st0["n_pairs"], st0["n_visible"]
-    cfg = default_cfg(pair_capacity=int(n_pairs * 1.05) + 4096)  # fixed capacity: no host wait per step
+    n_pairs, n_vis, n_groups = st0["n_pairs"], st0["n_visible"], st0["n_groups"]
+    # fixed capacity (it bounds each pose group): no host wait per step
+    cfg = default_cfg(pair_capacity=int(n_pairs * 1.05) + 4096, pose_groups=args.pose_groups)
     rgb = torch.empty((P, 3, H, Wd), dtype=torch.float32, device=dev)
     depth = torch.empty((P, H, Wd), dtype=torch.float32, device=dev)
     scores = torch.empty((P,), dtype=torch.float32, device=dev)
@@ -161,18 +166,21 @@ def main():
     cand_s = P * args.steps / elapsed
     best_i = int(best.cpu()[0])
     _log(f"timed: {args.steps} steps in {elapsed * 1e3:.1f} ms; stage means (ms): preprocess "
-         f"{st['ms_preprocess']:.3f} sort {st['ms_sort']:.3f} blend {st['ms_blend']:.3f} ncc {st['ms_ncc']:.3f}; "
+         f"{st['ms_preprocess']:.3f} sort/group {st['ms_sort']:.3f} blend/group {st['ms_blend']:.3f} render "
+         f"{st['ms_render']:.3f} ({n_groups} groups) ncc {st['ms_ncc']:.3f}; "
          f"best candidate {best_i}")
 
-    # roofline of the dominant kernel (blend): algorithmic flops / mean duration
+    # roofline of the dominant kernel (blend): algorithmic flops of one launch (one
+    # pose group: the render's contributions / groups) / mean launch duration
     e_contrib, e_lanes = st0["evals_contrib"], st0["evals_lanes"]
     blend_s = st["ms_blend"] * 1e-3
-    achieved = e_contrib * FLOPS_PER_CONTRIB / blend_s / 1e12
+    flops_launch = e_contrib * FLOPS_PER_CONTRIB / n_groups
+    achieved = flops_launch / blend_s / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
-            "frac": round(achieved / FP32_VECTOR_PEAK, 4), "traffic": _blend_traffic(),
-            "kernel": "k_blend", "ms_per_launch": round(st["ms_blend"], 4),
-            "flops_per_launch": e_contrib * FLOPS_PER_CONTRIB, "evals_contrib": e_contrib,
-            "evals_lane_slots": e_lanes}
+            "frac": round(achieved / FP32_VECTOR_PEAK, 4), "traffic": _blend_traffic(n_groups),
+            "kernel": "k_blend", "ms_per_launch": round(st["ms_blend"], 4), "launches_per_render": n_groups,
+            "flops_per_launch": int(flops_launch), "evals_contrib_per_render": e_contrib,
+            "evals_lane_slots_per_render": e_lanes}
     # end to end against HBM with the algorithmic bytes of the whole path
     n_c, px = int(idx.size), H * Wd
     bytes_step = 52 * n_c + 60 * n_vis + 88 * n_pairs + 28 * px * P
@@ -191,7 +199,7 @@ def main():
         "roofline": roof,
         "e2e_hbm": {"bytes_per_step": bytes_step, "achieved_GBs": round(e2e_gbs, 1), "peak_GBs": HBM_PEAK_GBS,
                     "frac": round(e2e_gbs / HBM_PEAK_GBS, 4)},
-        "stages_ms": {k: round(st[k], 4) for k in ("ms_preprocess", "ms_sort", "ms_blend", "ms_ncc")},
+        "stages_ms": {k: round(st[k], 4) for k in ("ms_preprocess", "ms_sort", "ms_blend", "ms_render", "ms_ncc")},
         "counts": {"n_submap": n_c, "n_visible": n_vis, "n_pairs": n_pairs, "best_candidate": best_i},
     }
     if args.cpu_candidates > 0:

@@ -83,10 +83,16 @@ typedef struct {
     float alpha_max;         /* alpha = min(alpha_max, q) [0.99] */
     float t_min;             /* stop after transmittance drops below t_min [1e-4] */
     int32_t flags;           /* GSR_RENDER_* bits [0] */
-    int64_t pair_capacity;   /* (Gaussian, tile) pair buffer: 0 = size exactly, with one
-                              * host wait per gsr_render for the pair count; > 0 = fixed
-                              * capacity, no host wait; an overflow leaves the images
-                              * undefined and is reported by gsr_sync as GSR_EOVERFLOW */
+    int64_t pair_capacity;   /* (Gaussian, tile) pair buffer of each pose group: 0 = size
+                              * exactly, with one host wait per gsr_render for the pair
+                              * counts; > 0 = fixed capacity per group, no host wait; an
+                              * overflow leaves the images undefined and is reported by
+                              * gsr_sync as GSR_EOVERFLOW */
+    int32_t pose_groups;     /* the poses are rendered in this many groups, in [1, 8]; 0 =
+                              * automatic (one group) [0]. Each group orders its pairs and
+                              * then composites on a stream of its own (the context's
+                              * stream for the first), concurrently with the other groups;
+                              * the images do not depend on the grouping */
 } gsr_render_cfg;
 
 /* gsr_render_cfg.flags: count compositing work into gsr_stats (evals_*), for
@@ -105,14 +111,17 @@ typedef struct {
     int64_t evals_lanes;     /* with GSR_RENDER_COUNT_EVALS: lane slots spent on evaluations */
     int32_t overflow;        /* 1 if the pair buffer overflowed */
     int32_t bad_index;       /* 1 if gsr_submap_load saw an index out of range */
-    /* Stage times from HIP events on the context's stream, when profiling is on:
-     * mean per call over the calls profiled since the previous gsr_get_stats. */
+    /* Stage times from HIP events recorded on the stream each stage runs on, when
+     * profiling is on: means over the calls profiled since the previous
+     * gsr_get_stats. Groups overlap, so ms_render is less than the sum. */
     int32_t n_profiled_renders;
     int32_t n_profiled_ncc;
-    float ms_preprocess;     /* counter reset + preprocess + tile histogram */
-    float ms_sort;           /* scan + pair scatter + per-tile sort */
-    float ms_blend;          /* compositing kernel */
+    float ms_preprocess;     /* counter reset + preprocess, per render */
+    float ms_sort;           /* ordering of one pose group (depth sort, emission, bucketing) */
+    float ms_blend;          /* one compositing launch (one pose group) */
     float ms_ncc;            /* whole gsr_ncc */
+    float ms_render;         /* whole gsr_render, first launch to the join */
+    int32_t n_groups;        /* pose groups of the last render */
 } gsr_stats;
 
 /* Create a context on GPU `device`, enqueueing on `hip_stream` (a hipStream_t;

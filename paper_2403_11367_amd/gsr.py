@@ -48,7 +48,7 @@ class RenderCfg(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("eps_dilate", C.c_float),
                 ("z_near", C.c_float), ("jac_clamp", C.c_float), ("cutoff_d2", C.c_float),
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
-                ("flags", C.c_int32), ("pair_capacity", C.c_int64)]
+                ("flags", C.c_int32), ("pair_capacity", C.c_int64), ("pose_groups", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -58,7 +58,7 @@ class Stats(C.Structure):
                 ("overflow", C.c_int32), ("bad_index", C.c_int32),
                 ("n_profiled_renders", C.c_int32), ("n_profiled_ncc", C.c_int32),
                 ("ms_preprocess", C.c_float), ("ms_sort", C.c_float), ("ms_blend", C.c_float),
-                ("ms_ncc", C.c_float)]
+                ("ms_ncc", C.c_float), ("ms_render", C.c_float), ("n_groups", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

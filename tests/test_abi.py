@@ -63,7 +63,7 @@ def test_default_cfg_values(gsr):
     assert (c.tile_w, c.tile_h) == (16, 16)
     assert c.eps_dilate == np.float32(0.3) and c.z_near == np.float32(0.2) and c.jac_clamp == np.float32(1.3)
     assert c.cutoff_d2 == 9.0 and c.alpha_max == np.float32(0.99) and c.t_min == np.float32(1e-4)
-    assert c.alpha_min == np.float32(1.0 / 255.0) and c.pair_capacity == 0
+    assert c.alpha_min == np.float32(1.0 / 255.0) and c.pair_capacity == 0 and c.pose_groups == 0
 
 
 def test_create_without_gpu_reports_enodev(gsr):

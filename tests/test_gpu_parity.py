@@ -173,6 +173,28 @@ def test_determinism_and_fixed_capacity(ctx):
         assert np.array_equal(x, y) and np.array_equal(x, z)
 
 
+def test_pose_groups_do_not_change_results(ctx):
+    """The poses may be rendered in groups on concurrent streams: images, pair
+    lists and list offsets are the same for every grouping and capacity mode."""
+    say("config0 with 1, 2, 3, 5 and 8 pose groups, exact and fixed capacity")
+    from paper_2403_11367_amd import BUF_OFFSETS, BUF_PAIRS, default_cfg
+    sc = W.config0()
+    sm = load(ctx, sc.gaussians)
+    ref = gpu_render(ctx, sm, sc.camera, sc.poses, default_cfg(pose_groups=1))
+    ref_off, ref_pairs = ctx.debug_buffer(BUF_OFFSETS), ctx.debug_buffer(BUF_PAIRS)
+    n_pairs = ctx.stats()["n_pairs"]
+    for groups in (2, 3, 5, 8):
+        for cap in (0, n_pairs):
+            out = gpu_render(ctx, sm, sc.camera, sc.poses, default_cfg(pose_groups=groups, pair_capacity=cap))
+            st = ctx.stats()
+            assert st["n_groups"] == groups and st["n_pairs"] == n_pairs
+            ctx.sync()
+            for x, y in zip(ref, out):
+                assert np.array_equal(x, y), f"{groups} groups, capacity {cap}"
+            assert np.array_equal(ctx.debug_buffer(BUF_OFFSETS), ref_off)
+            assert np.array_equal(ctx.debug_buffer(BUF_PAIRS), ref_pairs)
+
+
 def test_overflow_and_bad_index_are_reported(ctx):
     say("forced pair overflow (capacity 1) and an out-of-range submap index")
     from paper_2403_11367_amd import GsrError, default_cfg
