@@ -182,6 +182,28 @@ int gsr_ncc(gsr_ctx *ctx, const float *query_dev, const float *renders_dev, int3
  *   scores_dev [P] float32, idx_dev [k] int32 output. */
 int gsr_topk(gsr_ctx *ctx, const float *scores_dev, int32_t n_poses, int32_t k, int32_t *idx_dev);
 
+/* Random-order candidate search with an early stop (Sec. IV, initial
+ * relocalisation: a random search over the first share of the candidates that
+ * stops on an NCC criterion; read here as "the best NCC so far reaches
+ * `threshold`"). Candidates are rendered and scored in the order given, `batch`
+ * at a time; the search stops after the first batch whose best score is >=
+ * threshold, or once `max_eval` candidates are scored (e.g. 20% of P). One host
+ * wait per batch.
+ *   poses_dev  [P,3,4] float32, as for gsr_render
+ *   order_host [P] int32, a permutation of [0, P) (the random order, drawn by the caller)
+ *   query_dev  [3,H,W] float32; cfg as for gsr_render (NULL = defaults)
+ *   scores_dev [P] float32: the NCC of every scored candidate is written at its
+ *              index; entries of unscored candidates are left as they were
+ *   best / best_score: the best scored candidate (ties: lowest index) and its NCC
+ *   n_scored: candidates scored (a multiple of batch, or max_eval)
+ * Renders go to library-owned buffers of `batch` images.
+ * Errors: GSR_EINVAL for null pointers, 1 <= max_eval <= P <= 65535 or batch < 1
+ * violated, a NaN threshold, or an order that is not a permutation. */
+int gsr_search(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const float *poses_dev,
+               int32_t n_poses, const int32_t *order_host, int32_t batch, int32_t max_eval, float threshold,
+               const float *query_dev, const gsr_render_cfg *cfg, float *scores_dev, int32_t *best,
+               float *best_score, int32_t *n_scored);
+
 /* Wait for the context's stream. Returns GSR_EOVERFLOW / GSR_EDEVICE if a
  * device-side flag was raised since the last gsr_sync (and clears it). */
 int gsr_sync(gsr_ctx *ctx);

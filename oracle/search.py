@@ -5,6 +5,14 @@ against the query with NCC (Eq. 10) and keep the most similar. Ties go to the
 lowest candidate index. ``render_pose`` chains the other oracle modules for
 one pose: covariance, projection (Eq. 3-4), keys and sort, compositing
 (Eq. 1, 2, 5).
+
+``early_stop_search`` is the random-order variant of Sec. IV (initial
+relocalisation): candidates are scored in a given random order, in batches,
+and the search stops after the first batch whose best score reaches the
+threshold, or once a fixed share of the candidates has been scored. Reading:
+the paper's stop test on NCC is garbled ("dropped below" for a similarity);
+it is read as "the best NCC so far reaches the threshold". Its second test,
+on feature matches of a later stage, is outside this path.
 """
 from __future__ import annotations
 
@@ -42,3 +50,21 @@ def render_pose(prep, pose, cam, tile=(16, 16), with_pairs=False):
     if with_pairs:
         return out, rec, ks, vs, rng
     return out
+
+
+def early_stop_search(scores, order, batch: int, max_eval: int, threshold: float):
+    """Score candidates order[0], order[1], ... in batches of ``batch``; stop after
+    the first batch whose best score is >= threshold, or once ``max_eval``
+    candidates are scored. Returns (best candidate, its score, number scored);
+    ties go to the lowest candidate index among those scored."""
+    scores = np.asarray(scores, dtype=np.float64)
+    order = [int(i) for i in order]
+    best, best_score, n = -1, -np.inf, 0
+    while n < max_eval:
+        for c in order[n:min(n + batch, max_eval)]:
+            if scores[c] > best_score or (scores[c] == best_score and c < best):
+                best, best_score = c, scores[c]
+        n = min(n + batch, max_eval)
+        if best_score >= threshold:
+            break
+    return best, float(best_score), n

@@ -4,6 +4,19 @@ The compute runs in ``libgsr.so`` (hand-written HIP kernels for gfx950 behind
 the C ABI in ``include/gsr.h``); ``gsr`` is its ctypes binding and
 ``reloc`` the small driver of Sec. III-C1 (crop -> load -> render -> NCC ->
 select). Build the library with ``python -m paper_2403_11367_amd.build``.
+
+The binding is imported on first use of one of its names, so that the build
+module can run before the library exists; using the package without a built
+library raises ImportError.
 """
-from .gsr import (BUF_NTILES, BUF_OFFSETS, BUF_PAIRS, BUF_RECORDS, Camera, Context, GsrError,  # noqa: F401
-                  RenderCfg, Submap, crop, default_cfg)
+_BINDING = ("BUF_NTILES", "BUF_OFFSETS", "BUF_PAIRS", "BUF_RECORDS", "Camera", "Context", "GsrError",
+            "RenderCfg", "Submap", "crop", "default_cfg")
+
+__all__ = list(_BINDING)
+
+
+def __getattr__(name):
+    if name in _BINDING:
+        from . import gsr
+        return getattr(gsr, name)
+    raise AttributeError(f"module {__name__!r} has no attribute {name!r}")

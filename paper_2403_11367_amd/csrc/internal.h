@@ -127,5 +127,8 @@ int ncc_pixels_per_block();
 void launch_ncc(hipStream_t s, const float *query, const float *renders, int n_poses, int height,
                 int width, float *grey_q, double *partials, float *scores);
 void launch_topk(hipStream_t s, const float *scores, int n, int k, int32_t *idx);
+// out[i] = poses[order[i]] (3x4 each), i < nb; scores[order[i]] = batch_scores[i].
+void launch_gather_poses(hipStream_t s, const float *poses, const int32_t *order, int nb, float *out);
+void launch_scatter_scores(hipStream_t s, const float *batch_scores, const int32_t *order, int nb, float *scores);
 
 }  // namespace gsr

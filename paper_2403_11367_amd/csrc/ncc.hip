@@ -180,6 +180,21 @@ __global__ __launch_bounds__(1024) void k_topk(const float *__restrict__ scores,
     for (int i = threadIdx.x; i < k; i += blockDim.x) out[i] = (int32_t)(uint32_t)(s[i] & 0xffffffffu);
 }
 
+// Random-order search (S7): the poses of one batch, poses[order[i]], gathered into
+// a dense [nb][3][4] array; and the batch's scores written back to their candidates.
+__global__ void k_gather_poses(const float *__restrict__ poses, const int32_t *__restrict__ order, int nb,
+                               float *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb * 12) return;
+    out[i] = poses[(int64_t)order[i / 12] * 12 + i % 12];
+}
+
+__global__ void k_scatter_scores(const float *__restrict__ batch_scores, const int32_t *__restrict__ order, int nb,
+                                 float *__restrict__ scores) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) scores[order[i]] = batch_scores[i];
+}
+
 }  // namespace
 
 int ncc_pixels_per_block() { return kPix; }
@@ -197,6 +212,17 @@ void launch_ncc(hipStream_t s, const float *query, const float *renders, int n_p
 
 void launch_topk(hipStream_t s, const float *scores, int n, int k, int32_t *idx) {
     hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, s, scores, n, k, idx);
+}
+
+void launch_gather_poses(hipStream_t s, const float *poses, const int32_t *order, int nb, float *out) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_gather_poses, dim3((unsigned)((nb * 12 + 255) / 256)), dim3(256), 0, s, poses, order, nb, out);
+}
+
+void launch_scatter_scores(hipStream_t s, const float *batch_scores, const int32_t *order, int nb, float *scores) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_scatter_scores, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, batch_scores, order, nb,
+                       scores);
 }
 
 }  // namespace gsr

@@ -35,8 +35,10 @@ struct gsr_ctx {
     // device flags (int32) and counters (uint64)
     int *d_flags = nullptr;
     unsigned long long *d_counters = nullptr;
-    // pinned host staging for small readbacks (kMaxGroups uint64)
+    // pinned host staging for small readbacks (kMaxGroups uint64) and a search batch's scores
     uint64_t *h_pin = nullptr;
+    float *h_scores = nullptr;
+    size_t h_scores_n = 0;
     // internal streams (default priority) for pose groups 1.., and the events
     // that chain and join them (timing disabled)
     hipStream_t aux[kMaxGroups - 1] = {};
@@ -46,7 +48,8 @@ struct gsr_ctx {
         void *p = nullptr;
         size_t bytes = 0;
     } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, esum, pseg, scan_tmp,
-        ptile, pk, sk, cnt, total, block_base, offsets, grey_q, partials;
+        ptile, pk, sk, cnt, total, block_base, offsets, grey_q, partials, s_order, s_poses, s_rgb, s_depth,
+        s_scores;
     // layout of the last render's pose groups
     struct Group {
         int64_t p0 = 0, np = 0;        // poses [p0, p0 + np)
@@ -247,12 +250,14 @@ int gsr_destroy(gsr_ctx *ctx) {
                             &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb,  &ctx->rcnt,    &ctx->roff,    &ctx->nv,
                             &ctx->vbase,   &ctx->esum,    &ctx->pseg,     &ctx->scan_tmp, &ctx->ptile,
                             &ctx->pk,      &ctx->sk,      &ctx->cnt,      &ctx->total,   &ctx->block_base,
-                            &ctx->offsets, &ctx->grey_q,  &ctx->partials};
+                            &ctx->offsets, &ctx->grey_q,  &ctx->partials, &ctx->s_order, &ctx->s_poses,
+                            &ctx->s_rgb,   &ctx->s_depth, &ctx->s_scores};
     for (auto *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     if (ctx->d_counters) (void)hipFree(ctx->d_counters);
     if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
+    if (ctx->h_scores) (void)hipHostFree(ctx->h_scores);
     for (auto &r : ctx->ev_render)
         for (auto &e : r.e)
             if (e) (void)hipEventDestroy(e);
@@ -572,6 +577,78 @@ int gsr_topk(gsr_ctx *ctx, const float *scores, int32_t n_poses, int32_t k, int3
     HIPC(ctx, hipSetDevice(ctx->device));
     gsr::launch_topk(ctx->stream, scores, n_poses, k, idx);
     return check_launch(ctx, "topk");
+}
+
+int gsr_search(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const float *poses, int32_t n_poses,
+               const int32_t *order, int32_t batch, int32_t max_eval, float threshold, const float *query,
+               const gsr_render_cfg *cfg, float *scores, int32_t *best, float *best_score, int32_t *n_scored) {
+    if (!ctx) return GSR_EINVAL;
+    if (!sm || !cam || !poses || !order || !query || !scores || !best || !best_score || !n_scored)
+        return fail(ctx, GSR_EINVAL, "null argument");
+    if (n_poses < 1 || n_poses > 65535 || batch < 1 || max_eval < 1 || max_eval > n_poses)
+        return fail(ctx, GSR_EINVAL, "need 1 <= max_eval <= P <= 65535 and batch >= 1");
+    if (std::isnan(threshold)) return fail(ctx, GSR_EINVAL, "threshold is NaN");
+    // order must be a permutation of the candidates
+    std::vector<char> seen((size_t)n_poses, 0);
+    for (int32_t i = 0; i < n_poses; ++i) {
+        if (order[i] < 0 || order[i] >= n_poses || seen[(size_t)order[i]])
+            return fail(ctx, GSR_EINVAL, "order is not a permutation of [0, P)");
+        seen[(size_t)order[i]] = 1;
+    }
+    HIPC(ctx, hipSetDevice(ctx->device));
+    const int32_t B = std::min(batch, max_eval);
+    const int64_t hw = (int64_t)cam->width * cam->height;
+    int rc;
+    if ((rc = ensure(ctx, ctx->s_order, (size_t)n_poses * sizeof(int32_t), "search order")) ||
+        (rc = ensure(ctx, ctx->s_poses, (size_t)B * 12 * sizeof(float), "search poses")) ||
+        (rc = ensure(ctx, ctx->s_rgb, (size_t)B * 3 * hw * sizeof(float), "search renders")) ||
+        (rc = ensure(ctx, ctx->s_depth, (size_t)B * hw * sizeof(float), "search depths")) ||
+        (rc = ensure(ctx, ctx->s_scores, (size_t)B * sizeof(float), "search scores")))
+        return rc;
+    // pinned staging for a batch's scores (grown as needed)
+    if ((size_t)B > ctx->h_scores_n) {
+        if (ctx->h_scores) HIPC(ctx, hipHostFree(ctx->h_scores));
+        ctx->h_scores = nullptr;
+        ctx->h_scores_n = 0;
+        HIPC(ctx, hipHostMalloc(&ctx->h_scores, (size_t)B * sizeof(float), hipHostMallocDefault));
+        ctx->h_scores_n = (size_t)B;
+    }
+    hipStream_t s = ctx->stream;
+    int32_t *order_d = (int32_t *)ctx->s_order.p;
+    HIPC(ctx, hipMemcpyAsync(order_d, order, (size_t)n_poses * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    int32_t b_best = -1;
+    float b_score = -INFINITY;
+    int32_t n = 0;
+    while (n < max_eval) {
+        const int32_t nb = std::min(B, max_eval - n);
+        gsr::launch_gather_poses(s, poses, order_d + n, nb, (float *)ctx->s_poses.p);
+        if ((rc = check_launch(ctx, "search poses"))) return rc;
+        if ((rc = gsr_render(ctx, sm, cam, (const float *)ctx->s_poses.p, nb, cfg, (float *)ctx->s_rgb.p,
+                             (float *)ctx->s_depth.p, nullptr)))
+            return rc;
+        if ((rc = gsr_ncc(ctx, query, (const float *)ctx->s_rgb.p, nb, cam->height, cam->width,
+                          (float *)ctx->s_scores.p)))
+            return rc;
+        gsr::launch_scatter_scores(s, (const float *)ctx->s_scores.p, order_d + n, nb, scores);
+        if ((rc = check_launch(ctx, "search scores"))) return rc;
+        HIPC(ctx, hipMemcpyAsync(ctx->h_scores, ctx->s_scores.p, (size_t)nb * sizeof(float), hipMemcpyDeviceToHost,
+                                 s));
+        HIPC(ctx, hipStreamSynchronize(s));
+        for (int32_t i = 0; i < nb; ++i) {
+            const float v = ctx->h_scores[i];
+            const int32_t c = order[n + i];
+            if (v > b_score || (v == b_score && c < b_best)) {
+                b_score = v;
+                b_best = c;
+            }
+        }
+        n += nb;
+        if (b_score >= threshold) break;
+    }
+    *best = b_best;
+    *best_score = b_score;
+    *n_scored = n;
+    return GSR_OK;
 }
 
 int gsr_sync(gsr_ctx *ctx) {

@@ -27,7 +27,7 @@ RENDER_COUNT_EVALS = 1
 # every symbol declared in include/gsr.h
 EXPORTS = [
     "gsr_create", "gsr_destroy", "gsr_set_stream", "gsr_set_profiling", "gsr_default_cfg",
-    "gsr_submap_load", "gsr_submap_free", "gsr_submap_size", "gsr_render", "gsr_ncc", "gsr_topk",
+    "gsr_submap_load", "gsr_submap_free", "gsr_submap_size", "gsr_render", "gsr_ncc", "gsr_topk", "gsr_search",
     "gsr_sync", "gsr_get_stats", "gsr_debug_size", "gsr_debug_copy", "gsr_crop",
     "gsr_status_string", "gsr_last_error",
 ]
@@ -81,6 +81,8 @@ def _load() -> C.CDLL:
         "gsr_render": (I, [P, P, C.POINTER(CameraC), P, I32, C.POINTER(RenderCfg), P, P, P]),
         "gsr_ncc": (I, [P, P, P, I32, I32, I32, P]),
         "gsr_topk": (I, [P, P, I32, I32, P]),
+        "gsr_search": (I, [P, P, C.POINTER(CameraC), P, I32, P, I32, I32, F, P, C.POINTER(RenderCfg), P,
+                           C.POINTER(I32), C.POINTER(F), C.POINTER(I32)]),
         "gsr_sync": (I, [P]),
         "gsr_get_stats": (I, [P, C.POINTER(Stats)]),
         "gsr_debug_size": (I, [P, I, C.POINTER(I64)]),
@@ -286,6 +288,30 @@ class Context:
         self._bind_stream()
         self._check(LIB.gsr_topk(self.handle, scores.data_ptr(), P, k, out.data_ptr()), "gsr_topk")
         return out
+
+    def search(self, submap: Submap, camera: Camera, poses, order, batch: int, max_eval: int,
+               threshold: float, query, cfg: Optional[RenderCfg] = None, scores=None):
+        """Random-order search with an early stop (gsr_search). Returns
+        (best candidate, its NCC, candidates scored, scores tensor)."""
+        torch = _torch()
+        P = poses.shape[0]
+        _dev_f32(poses, "poses", (P, 3, 4))
+        _dev_f32(query, "query", (3, camera.height, camera.width))
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        if order.shape != (P,):
+            raise ValueError("order must hold one entry per candidate")
+        if scores is None:
+            scores = torch.full((P,), float("nan"), dtype=torch.float32, device=poses.device)
+        _dev_f32(scores, "scores", (P,))
+        self._bind_stream()
+        cam = camera.c()
+        best, score, n = C.c_int32(0), C.c_float(0), C.c_int32(0)
+        rc = LIB.gsr_search(self.handle, submap.handle, C.byref(cam), poses.data_ptr(), P,
+                            order.ctypes.data, batch, max_eval, threshold, query.data_ptr(),
+                            C.byref(cfg) if cfg is not None else None, scores.data_ptr(),
+                            C.byref(best), C.byref(score), C.byref(n))
+        self._check(rc, "gsr_search")
+        return best.value, score.value, n.value, scores
 
     def sync(self):
         self._check(LIB.gsr_sync(self.handle), "gsr_sync")

@@ -48,3 +48,14 @@ class Relocalizer:
         s = scores.cpu().numpy()
         t = top.cpu().numpy()
         return SearchResult(int(t[0]), t, s)
+
+    def search_random(self, camera: Camera, poses, query, order, share: float = 0.2, batch: int = 8,
+                      threshold: float = 0.9, cfg: Optional[RenderCfg] = None):
+        """Random-order search with an early stop (Sec. IV): candidates in `order`,
+        `batch` at a time, over at most `share` of them, stopping once the best NCC
+        reaches `threshold`. Returns (best candidate, its NCC, candidates scored)."""
+        P = poses.shape[0]
+        max_eval = max(1, min(P, int(np.ceil(share * P))))
+        best, score, n, _ = self.ctx.search(self.submap, camera, poses, order, batch, max_eval, threshold,
+                                            query, cfg)
+        return best, score, n

@@ -289,6 +289,42 @@ def test_config0_end_to_end_search(ctx):
         assert int(best.cpu()[0]) == search.argmax(ref_scores)
 
 
+def test_random_order_search_with_early_stop(ctx):
+    """gsr_search against the oracle's early_stop_search on the oracle's scores
+    (config0, 16 candidates in a seeded random order)."""
+    say("config0 random-order search: batches, scored share, NCC threshold")
+    sc = W.config0()
+    pr = prep(sc.gaussians)
+    q_ref = search.render_pose(pr, sc.hidden_pose, sc.camera)
+    query = (q_ref.rgb + sc.query_noise).astype(np.float32)
+    ref = oncc.ncc(query, np.stack([search.render_pose(pr, sc.poses[p], sc.camera).rgb for p in range(16)]))
+    order = W.search_order(7, 16)
+    sm = load(ctx, sc.gaussians)
+    cam = __import__("helpers").camera(sc.camera)
+    poses, q = to_dev(sc.poses), to_dev(query)
+    # thresholds half-way between well separated oracle scores, so that float32 rounding
+    # cannot move a score across one
+    srt = np.sort(ref)
+    mids = [(a + b) / 2 for a, b in zip(srt[:-1], srt[1:]) if b - a > 4 * TOL_NCC]
+    cases = [(4, 16, np.inf), (3, 12, np.inf), (1, 16, mids[-1]), (4, 16, mids[len(mids) // 2]),
+             (5, 13, mids[0]), (16, 16, mids[-1])]
+    for batch, max_eval, thr in cases:
+        best, score, n, scores = ctx.search(sm, cam, poses, order, batch, max_eval, float(thr), q)
+        rb, rs, rn = search.early_stop_search(ref, order, batch, max_eval, thr)
+        got = scores.cpu().numpy()
+        scored = order[:n]
+        say(f"  batch {batch} max {max_eval} thr {thr:.4f}: gpu ({best}, {score:.5f}, {n}) oracle ({rb}, {rs:.5f}, {rn})")
+        assert n == rn
+        assert abs(score - rs) <= TOL_NCC
+        assert np.abs(got[scored] - ref[scored]).max() <= TOL_NCC
+        assert np.all(np.isnan(np.delete(got, scored)))
+        top = np.sort(ref[scored])
+        if top.size < 2 or top[-1] - top[-2] > 2 * TOL_NCC:
+            assert best == rb
+    with pytest.raises(__import__("paper_2403_11367_amd").GsrError):
+        ctx.search(sm, cam, poses, np.zeros(16, np.int32), 4, 16, 0.5, q)  # not a permutation
+
+
 @pytest.fixture(scope="module")
 def cfg1():
     sc = W.config1()

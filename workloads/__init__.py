@@ -253,6 +253,11 @@ def tiny_scene(seed: int, n: int = 64, width: int = 64, height: int = 48,
     return Scene(f"tiny{seed}", g, cam, (16, 16), poses, poses[0].copy(), noise, center)
 
 
+def search_order(seed: int, n: int) -> np.ndarray:
+    """A seeded random visiting order of n candidates (int32 permutation)."""
+    return np.random.default_rng(seed).permutation(n).astype(np.int32)
+
+
 def random_images(seed: int, n: int, height: int, width: int, channels: int = 3) -> np.ndarray:
     """Smooth-plus-noise float32 images [n, channels, H, W] for NCC checks."""
     rng = np.random.default_rng(seed)
