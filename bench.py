@@ -202,6 +202,26 @@ def main():
         "stages_ms": {k: round(st[k], 4) for k in ("ms_preprocess", "ms_sort", "ms_blend", "ms_render", "ms_ncc")},
         "counts": {"n_submap": n_c, "n_visible": n_vis, "n_pairs": n_pairs, "best_candidate": best_i},
     }
+    # random-order search with an early stop (Sec. IV) on the same workload: a seeded
+    # order, at most 20% of the candidates in batches of 8, stopping once the best NCC
+    # reaches 95% of the plain search's best
+    order = W.search_order(12, P)
+    s_np = scores.cpu().numpy()
+    thr = float(0.95 * s_np.max())
+    max_eval = max(1, int(np.ceil(0.2 * P)))
+    ctx.search(sm, cam, poses_t, order, 8, max_eval, thr, query, cfg)  # warm-up (buffers)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        e_best, e_score, e_n, _ = ctx.search(sm, cam, poses_t, order, 8, max_eval, thr, query, cfg)
+    torch.cuda.synchronize()
+    t_s = (time.perf_counter() - t0) / reps
+    out["early_stop"] = {"order_seed": 12, "share": 0.2, "batch": 8, "threshold": round(thr, 5),
+                         "candidates_scored": e_n, "best": e_best, "best_ncc": round(e_score, 5),
+                         "plain_best": best_i, "ms_per_search": round(t_s * 1e3, 3),
+                         "scored_candidates_per_s": round(e_n / t_s, 1)}
+    _log(f"early-stop search: {e_n} of {P} scored in {t_s * 1e3:.2f} ms, best {e_best} (plain {best_i})")
     if args.cpu_candidates > 0:
         _log(f"cpu baseline: oracle on {args.cpu_candidates} candidates ...")
         out["cpu_baseline"] = cpu_baseline(sc, idx, args.cpu_candidates)
