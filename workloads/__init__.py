@@ -258,6 +258,21 @@ def search_order(seed: int, n: int) -> np.ndarray:
     return np.random.default_rng(seed).permutation(n).astype(np.int32)
 
 
+def scorer_params(seed: int) -> np.ndarray:
+    """Initial parameters of the learned scorer (flat float32, the layout of the
+    scorer's parameter vector): He-normal weights, zero biases.
+    Shapes: per conv layer (2->32->64->64->128->128) W[co][3][3][ci], b[co];
+    then fc1 W[128][128], b[128]; fc2 W[128], b[1]."""
+    rng = np.random.default_rng(seed)
+    chans = [2, 32, 64, 64, 128, 128]
+    parts = []
+    for ci, co in zip(chans[:-1], chans[1:]):
+        parts += [rng.normal(0.0, np.sqrt(2.0 / (9 * ci)), (co, 3, 3, ci)), np.zeros(co)]
+    parts += [rng.normal(0.0, np.sqrt(2.0 / 128), (128, 128)), np.zeros(128),
+              rng.normal(0.0, np.sqrt(2.0 / 128), 128), np.zeros(1)]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
 def random_images(seed: int, n: int, height: int, width: int, channels: int = 3) -> np.ndarray:
     """Smooth-plus-noise float32 images [n, channels, H, W] for NCC checks."""
     rng = np.random.default_rng(seed)
