@@ -111,11 +111,14 @@ def conv3x3_backward(x, w, dy, stride):
 
 
 def standardise(img):
-    """Zero mean, unit variance over all pixels (float64); a constant image -> zeros."""
+    """Zero mean, unit variance over all pixels (float64). A constant image (all
+    pixels equal) gives zeros; this is decided by equality, since the rounded
+    mean of equal values need not equal them."""
     img = np.asarray(img, dtype=np.float64)
+    if np.all(img == img.flat[0]):
+        return np.zeros_like(img)
     c = img - img.mean()
-    v = (c * c).mean()
-    return c / np.sqrt(v) if v > 0 else np.zeros_like(c)
+    return c / np.sqrt((c * c).mean())
 
 
 def grey(rgb):
@@ -182,3 +185,23 @@ def loss_and_grads(params, x, labels, bf16: bool = False):
         if l > 0:
             dy = dx * (acts[l] > 0)
     return loss, flatten(grads + [dw1, db1, dw2, db2])
+
+
+def decay_mask():
+    """1.0 for the entries that weight decay applies to (weights), 0.0 for biases."""
+    return flatten([np.full(s, 1.0 if len(s) > 1 or i == len(param_shapes()) - 2 else 0.0)
+                    for i, s in enumerate(param_shapes())])
+
+
+def adamw_step(params, grads, m, v, t, lr, beta1, beta2, eps, weight_decay):
+    """One AdamW step (Adam moments with bias correction, weight decay decoupled
+    from the gradient and applied to weights only); t counts this step from 1.
+    Returns new (params, m, v), float64."""
+    p = np.asarray(params, dtype=np.float64)
+    g = np.asarray(grads, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1 - beta2) * g * g
+    mh = m / (1 - beta1 ** t)
+    vh = v / (1 - beta2 ** t)
+    p = p - lr * weight_decay * decay_mask() * p - lr * mh / (np.sqrt(vh) + eps)
+    return p, m, v

@@ -10,7 +10,7 @@ module can run before the library exists; using the package without a built
 library raises ImportError.
 """
 _BINDING = ("BUF_NTILES", "BUF_OFFSETS", "BUF_PAIRS", "BUF_RECORDS", "Camera", "Context", "GsrError",
-            "RenderCfg", "Submap", "crop", "default_cfg")
+            "RenderCfg", "Scorer", "Submap", "crop", "default_cfg")
 
 __all__ = list(_BINDING)
 

@@ -35,6 +35,8 @@ SOURCES = [
     ("sort.hip", "hip", []),
     ("blend.hip", "hip", []),
     ("ncc.hip", "hip", []),
+    ("scorer.hip", "hip", []),
+    ("scorer_rt.cpp", "hip", ["-x", "hip"]),
     ("runtime.cpp", "hip", ["-x", "hip"]),
     ("crop.cpp", "cxx", []),
 ]

@@ -7,6 +7,8 @@
 
 #include <algorithm>
 
+#include "gsr.h"
+
 namespace gsr {
 
 // Device flag slots (int32 each), raised by kernels, read and cleared by gsr_sync.
@@ -130,5 +132,53 @@ void launch_topk(hipStream_t s, const float *scores, int n, int k, int32_t *idx)
 // out[i] = poses[order[i]] (3x4 each), i < nb; scores[order[i]] = batch_scores[i].
 void launch_gather_poses(hipStream_t s, const float *poses, const int32_t *order, int nb, float *out);
 void launch_scatter_scores(hipStream_t s, const float *batch_scores, const int32_t *order, int nb, float *scores);
+
+// ---- scorer.hip ----
+constexpr int kScorerLayers = 5;
+constexpr int kScorerChannels[kScorerLayers + 1] = {2, 32, 64, 64, 128, 128};
+constexpr int kScorerStride[kScorerLayers] = {2, 1, 2, 1, 2};
+constexpr int kScorerHidden = 128;
+
+// Device buffers of one scorer call. Convolution weights in bf16 are kept in
+// two copies indexed like the flat parameters: wt in the parameter layout
+// [co][tap][ci], wd in [tap][ci][co]; w_off, b_off, fc_off are offsets into
+// the flat parameter vector (fc: W1, b1, w2, b2). act[l] (l = 1..5) holds
+// layer l's output [B][h_l][w_l][c_l] in bf16; dbuf[2] are gradient ping-pong
+// buffers of the largest activation; part holds part_cap float32 partial sums.
+struct ScorerBufs {
+    int H, W;
+    const uint16_t *x;
+    uint16_t *act[kScorerLayers + 1];
+    const float *params;
+    uint16_t *wt, *wd;
+    int64_t w_off[kScorerLayers], b_off[kScorerLayers], fc_off[4];
+    float *g, *h, *ds, *dh;  // [B][128] pooled features, hidden units, [B] dscore, [B][128] dhidden
+    uint16_t *dbuf[2];
+    float *part;
+    int64_t part_cap;
+};
+// dims[l] = (height, width) of the input of layer l (dims[5] = last output).
+void scorer_dims(int H, int W, int dims[kScorerLayers + 1][2]);
+// out[p] = f x f mean pool of the grey of rgb[p] ([3][H][W] planar).
+void launch_pool_grey(hipStream_t s, const float *rgb, int P, int H, int W, int f, float *out);
+// Network input x [B][h][w][2] bf16 from renders rgb [B][3][h][w] and the
+// pooled query grey q [h][w]; qstats holds 2 floats of scratch.
+void launch_scorer_input(hipStream_t s, const float *rgb, int B, int h, int w, const float *q, float *qstats,
+                         uint16_t *x);
+void launch_scorer_forward(hipStream_t s, const ScorerBufs &b, int B, float *score);
+// After launch_scorer_forward on the same buffers: gradient of the mean squared
+// error against label[B] into grad (flat parameter layout), the loss into
+// loss[0] (or not, if null).
+void launch_scorer_backward(hipStream_t s, const ScorerBufs &b, int B, const float *score, const float *label,
+                            float *grad, float *loss);
+void launch_scorer_weights(hipStream_t s, const ScorerBufs &b);
+void launch_adamw(hipStream_t s, float *p, const float *g, float *m, float *v, const uint8_t *decay, int64_t n,
+                  float lr, float b1, float b2, float eps, float wd, float bc1, float bc2);
+
+// ---- runtime.cpp: context access for the other host units ----
+hipStream_t ctx_stream(gsr_ctx *ctx);
+int ctx_device(gsr_ctx *ctx);
+int ctx_fail(gsr_ctx *ctx, int code, const char *msg);
+int ctx_hip_fail(gsr_ctx *ctx, hipError_t e, const char *what);
 
 }  // namespace gsr

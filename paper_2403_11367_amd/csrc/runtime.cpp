@@ -158,6 +158,13 @@ int ilog2(int x) {
 
 }  // namespace
 
+namespace gsr {
+hipStream_t ctx_stream(gsr_ctx *ctx) { return ctx->stream; }
+int ctx_device(gsr_ctx *ctx) { return ctx->device; }
+int ctx_fail(gsr_ctx *ctx, int code, const char *msg) { return fail(ctx, code, msg); }
+int ctx_hip_fail(gsr_ctx *ctx, hipError_t e, const char *what) { return hip_fail(ctx, e, what); }
+}  // namespace gsr
+
 extern "C" {
 
 const char *gsr_status_string(int status) {

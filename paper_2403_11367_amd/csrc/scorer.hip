@@ -1,0 +1,692 @@
+// Learned candidate scorer: a small CNN that predicts the NCC of a candidate
+// from its low-resolution render and the low-resolution query, used to prune
+// the candidate set before the full-resolution comparison of Eq. 10.
+//
+// Network (NHWC activations, 3x3 convolutions with zero padding 1):
+//   conv 2->32 /2, ReLU; conv 32->64, ReLU; conv 64->64 /2, ReLU;
+//   conv 64->128, ReLU; conv 128->128 /2, ReLU; global average pool;
+//   linear 128->128, ReLU; linear 128->1.
+// Weights and activations are bfloat16 (round to nearest even), sums are
+// float32 on the matrix cores (v_mfma_f32_32x32x16_bf16); the pooled features,
+// the two linear layers, the loss and AdamW are float32 on the vector ALUs.
+//
+// The three convolution products are implicit GEMMs:
+//   forward        rows = output pixels, cols = output channels, K = (tap, c_in)
+//   backward data  rows = input pixels of one sub-pixel class (for stride 2 the
+//                  four (y mod 2, x mod 2) classes each see a fixed set of taps,
+//                  so no MFMA is spent on taps that skip the pixel),
+//                  cols = input channels, K = (tap, c_out)
+//   backward weight rows = output channels, cols = (tap, c_in), K = output
+//                  pixels, split over row ranges into float32 partial sums that
+//                  a second kernel adds in a fixed order (deterministic).
+// MFMA operand layout of 32x32x16: lane l supplies row (or column) l % 32 and
+// the eight K entries 8 (l / 32) .. 8 (l / 32) + 7; accumulator element i of
+// lane l is row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace gsr {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint16_t u16;
+
+__device__ inline u16 to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u16)((u >> 16) | 0x40u);  // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+__device__ inline float from_bf16(u16 h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline bf16x8 load8(const u16 *p) { return __builtin_bit_cast(bf16x8, *(const u32x4 *)p); }
+__device__ inline bf16x8 zero8() {
+    u32x4 z = {0u, 0u, 0u, 0u};
+    return __builtin_bit_cast(bf16x8, z);
+}
+__device__ inline bf16x8 pack8(const uint32_t (&w)[4]) {
+    u32x4 v = {w[0], w[1], w[2], w[3]};
+    return __builtin_bit_cast(bf16x8, v);
+}
+__device__ inline f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ inline T block_sum(T v, T *red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    T s = 0;
+    for (int w = 0; w < nw; ++w) s += red[w];
+    return s;
+}
+
+// ---- input preparation ----
+
+__device__ inline float grey_of(float r, float g, float b) { return 0.299f * r + 0.587f * g + 0.114f * b; }
+
+// out[p][y][x] = mean over the f x f block of the grey of rgb[p][3][H][W].
+__global__ void k_pool_grey(const float *__restrict__ rgb, int P, int H, int W, int f, float *__restrict__ out) {
+    const int h = H / f, w = W / f;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)P * h * w) return;
+    const int p = (int)(i / ((int64_t)h * w));
+    const int r = (int)(i - (int64_t)p * h * w), y = r / w, x = r - y * w;
+    const int64_t plane = (int64_t)H * W;
+    const float *src = rgb + (int64_t)p * 3 * plane;
+    float s = 0.f;
+    for (int dy = 0; dy < f; ++dy)
+        for (int dx = 0; dx < f; ++dx) {
+            const int64_t o = (int64_t)(y * f + dy) * W + x * f + dx;
+            s += grey_of(src[o], src[plane + o], src[2 * plane + o]);
+        }
+    out[i] = s / (float)(f * f);
+}
+
+// Mean and reciprocal standard deviation of an image, summed in float64 (the
+// sum of a constant image is then exact and its variance exactly 0); rstd = 0
+// for a constant image, which then standardises to zeros.
+__device__ inline void image_stats(double sum, double m2, int n, float &mean, float &rstd) {
+    mean = (float)(sum / n);
+    rstd = m2 > 0.0 ? (float)(1.0 / sqrt(m2 / n)) : 0.f;
+}
+
+// stats[0], stats[1] = mean and rstd of the query grey image q[n].
+__global__ __launch_bounds__(1024) void k_query_stats(const float *__restrict__ q, int n, float *__restrict__ stats) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += q[i];
+    const double sum = block_sum(s, red), mu = sum / n;
+    double m2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double d = q[i] - mu;
+        m2 += d * d;
+    }
+    m2 = block_sum(m2, red);
+    if (threadIdx.x == 0) {
+        float mean, rstd;
+        image_stats(sum, m2, n, mean, rstd);
+        stats[0] = mean;
+        stats[1] = rstd;
+    }
+}
+
+// x[b][y][x][0] = standardised grey of render b, x[b][y][x][1] = standardised
+// query; one block per render.
+__global__ __launch_bounds__(1024) void k_scorer_input(const float *__restrict__ rgb, int h, int w,
+                                                        const float *__restrict__ q, const float *__restrict__ qstats,
+                                                        u16 *__restrict__ x) {
+    __shared__ double red[16];
+    const int n = h * w;
+    const float *src = rgb + (int64_t)blockIdx.x * 3 * n;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += grey_of(src[i], src[n + i], src[2 * n + i]);
+    const double sum = block_sum(s, red), mu = sum / n;
+    double m2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double d = grey_of(src[i], src[n + i], src[2 * n + i]) - mu;
+        m2 += d * d;
+    }
+    m2 = block_sum(m2, red);
+    float mean, rstd;
+    image_stats(sum, m2, n, mean, rstd);
+    const float qm = qstats[0], qr = qstats[1];
+    uint32_t *dst = (uint32_t *)(x + (int64_t)blockIdx.x * 2 * n);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const float g = (grey_of(src[i], src[n + i], src[2 * n + i]) - mean) * rstd;
+        const float v = (q[i] - qm) * qr;
+        dst[i] = (uint32_t)to_bf16(g) | ((uint32_t)to_bf16(v) << 16);
+    }
+}
+
+// ---- convolutions ----
+
+struct ConvDims {
+    int n, H, W, Ho, Wo;  // images, input height and width, output height and width
+};
+
+// Forward: y = relu(conv(x, W) + b) in bf16. Block = 4 waves in a WGM x WGN
+// grid; each wave owns RM x RN accumulator tiles of 32 x 32.
+template <int CI, int CO, int S, int RM, int RN, int WGN>
+__global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ x, ConvDims d, const u16 *__restrict__ wt,
+                                                   const float *__restrict__ bias, u16 *__restrict__ y) {
+    constexpr int WGM = 4 / WGN, BM = WGM * RM * 32;
+    static_assert(WGN * RN * 32 == CO, "wave grid must cover the output channels");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave % WGM, wn = wave / WGM;
+    const int r32 = lane & 31, kq = lane >> 5;
+    const int64_t M = (int64_t)d.n * d.Ho * d.Wo;
+    const int64_t m0 = (int64_t)blockIdx.x * BM + wm * RM * 32;
+    const int hw = d.Ho * d.Wo;
+    int iy0[RM], ix0[RM];
+    int64_t img[RM];
+    bool live[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const int64_t m = m0 + 32 * r + r32;
+        live[r] = m < M;
+        const int64_t mm = live[r] ? m : 0;
+        const int n = (int)(mm / hw), rem = (int)(mm - (int64_t)n * hw);
+        const int oy = rem / d.Wo, ox = rem - oy * d.Wo;
+        iy0[r] = oy * S - 1;
+        ix0[r] = ox * S - 1;
+        img[r] = (int64_t)n * d.H * d.W;
+    }
+    f32x16 acc[RM][RN];
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int c = 0; c < RN; ++c)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[r][c][i] = 0.f;
+    const int cob = wn * RN * 32;
+    if constexpr (CI == 2) {
+        // K = 18 = (tap, c_in), padded to 32: two K steps of 16.
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+            bf16x8 a[RM], b[RN];
+#pragma unroll
+            for (int r = 0; r < RM; ++r) {
+                uint32_t wv[4];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int tap = 8 * sub + 4 * kq + jj;
+                    const int iy = iy0[r] + tap / 3, ix = ix0[r] + tap % 3;
+                    const bool ok = live[r] && tap < 9 && iy >= 0 && iy < d.H && ix >= 0 && ix < d.W;
+                    const int64_t o = img[r] + (ok ? (int64_t)iy * d.W + ix : 0);
+                    wv[jj] = ok ? *(const uint32_t *)(x + o * 2) : 0u;
+                }
+                a[r] = pack8(wv);
+            }
+#pragma unroll
+            for (int c = 0; c < RN; ++c) {
+                uint32_t wv[4];
+                const int co = cob + 32 * c + r32;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int tap = 8 * sub + 4 * kq + jj;
+                    wv[jj] = tap < 9 ? *(const uint32_t *)(wt + co * 18 + 2 * (tap < 9 ? tap : 0)) : 0u;
+                }
+                b[c] = pack8(wv);
+            }
+#pragma unroll
+            for (int r = 0; r < RM; ++r)
+#pragma unroll
+                for (int c = 0; c < RN; ++c) acc[r][c] = mfma(a[r], b[c], acc[r][c]);
+        }
+    } else {
+        for (int tap = 0; tap < 9; ++tap) {
+            const int kh = tap / 3, kw = tap - 3 * kh;
+            const u16 *src[RM];
+            bool ok[RM];
+#pragma unroll
+            for (int r = 0; r < RM; ++r) {
+                const int iy = iy0[r] + kh, ix = ix0[r] + kw;
+                ok[r] = live[r] && iy >= 0 && iy < d.H && ix >= 0 && ix < d.W;
+                src[r] = x + (img[r] + (int64_t)(ok[r] ? iy : 0) * d.W + (ok[r] ? ix : 0)) * CI + 8 * kq;
+            }
+            const u16 *wsrc = wt + ((int64_t)(cob + r32) * 9 + tap) * CI + 8 * kq;
+#pragma unroll
+            for (int c0 = 0; c0 < CI; c0 += 16) {
+                bf16x8 a[RM], b[RN];
+#pragma unroll
+                for (int r = 0; r < RM; ++r) a[r] = ok[r] ? load8(src[r] + c0) : zero8();
+#pragma unroll
+                for (int c = 0; c < RN; ++c) b[c] = load8(wsrc + (int64_t)32 * c * 9 * CI + c0);
+#pragma unroll
+                for (int r = 0; r < RM; ++r)
+#pragma unroll
+                    for (int c = 0; c < RN; ++c) acc[r][c] = mfma(a[r], b[c], acc[r][c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < RN; ++c) {
+        const int co = cob + 32 * c + r32;
+        const float bv = bias[co];
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int64_t m = m0 + 32 * r + 8 * (i / 4) + 4 * kq + (i % 4);
+                if (m < M) {
+                    const float v = acc[r][c][i] + bv;
+                    y[m * CO + co] = to_bf16(v > 0.f ? v : 0.f);
+                }
+            }
+    }
+}
+
+// Backward data: dx = (conv^T(dy, W)) * (a_in > 0) in bf16, for the input
+// pixels of sub-pixel class blockIdx.y (stride 2: (y mod 2, x mod 2)).
+// wd is the weight in [tap][c_in][c_out] layout.
+template <int CI, int CO, int S, int RM, int RN, int WGN>
+__global__ __launch_bounds__(256) void k_conv_bwd_data(const u16 *__restrict__ dy, ConvDims d,
+                                                        const u16 *__restrict__ wd, const u16 *__restrict__ a_in,
+                                                        u16 *__restrict__ dx) {
+    constexpr int WGM = 4 / WGN, BM = WGM * RM * 32;
+    static_assert(WGN * RN * 32 == CI, "wave grid must cover the input channels");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave % WGM, wn = wave / WGM;
+    const int r32 = lane & 31, kq = lane >> 5;
+    const int py = S == 2 ? (int)(blockIdx.y >> 1) : 0, px = S == 2 ? (int)(blockIdx.y & 1) : 0;
+    const int Hc = (d.H - py + S - 1) / S, Wc = (d.W - px + S - 1) / S;
+    const int64_t Mc = (int64_t)d.n * Hc * Wc;
+    if ((int64_t)blockIdx.x * BM >= Mc) return;
+    const int64_t m0 = (int64_t)blockIdx.x * BM + wm * RM * 32;
+    const int hwc = Hc * Wc;
+    int iy[RM], ix[RM], nn[RM];
+    bool live[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const int64_t m = m0 + 32 * r + r32;
+        live[r] = m < Mc;
+        const int64_t mm = live[r] ? m : 0;
+        nn[r] = (int)(mm / hwc);
+        const int rem = (int)(mm - (int64_t)nn[r] * hwc);
+        const int a = rem / Wc, b = rem - a * Wc;
+        iy[r] = S * a + py;
+        ix[r] = S * b + px;
+    }
+    f32x16 acc[RM][RN];
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int c = 0; c < RN; ++c)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[r][c][i] = 0.f;
+    const int cib = wn * RN * 32;
+    for (int kh = 0; kh < 3; ++kh) {
+        if (S == 2 && ((py + 1 - kh) & 1)) continue;
+        for (int kw = 0; kw < 3; ++kw) {
+            if (S == 2 && ((px + 1 - kw) & 1)) continue;
+            const int tap = kh * 3 + kw;
+            const u16 *src[RM];
+            bool ok[RM];
+#pragma unroll
+            for (int r = 0; r < RM; ++r) {
+                const int ty = iy[r] + 1 - kh, tx = ix[r] + 1 - kw;
+                const int oy = ty / S, ox = tx / S;  // exact: ty, tx are multiples of S here
+                ok[r] = live[r] && ty >= 0 && tx >= 0 && oy < d.Ho && ox < d.Wo;
+                src[r] = dy + (((int64_t)nn[r] * d.Ho + (ok[r] ? oy : 0)) * d.Wo + (ok[r] ? ox : 0)) * CO + 8 * kq;
+            }
+            const u16 *wsrc = wd + ((int64_t)tap * CI + cib + r32) * CO + 8 * kq;
+#pragma unroll
+            for (int c0 = 0; c0 < CO; c0 += 16) {
+                bf16x8 a[RM], b[RN];
+#pragma unroll
+                for (int r = 0; r < RM; ++r) a[r] = ok[r] ? load8(src[r] + c0) : zero8();
+#pragma unroll
+                for (int c = 0; c < RN; ++c) b[c] = load8(wsrc + (int64_t)32 * c * CO + c0);
+#pragma unroll
+                for (int r = 0; r < RM; ++r)
+#pragma unroll
+                    for (int c = 0; c < RN; ++c) acc[r][c] = mfma(a[r], b[c], acc[r][c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int64_t m = m0 + 32 * r + 8 * (i / 4) + 4 * kq + (i % 4);
+            if (m >= Mc) continue;
+            const int n = (int)(m / hwc), rem = (int)(m - (int64_t)n * hwc);
+            const int a = rem / Wc, b = rem - a * Wc;
+            const int64_t pix = ((int64_t)n * d.H + S * a + py) * d.W + S * b + px;
+#pragma unroll
+            for (int c = 0; c < RN; ++c) {
+                const int ci = cib + 32 * c + r32;
+                const bool on = from_bf16(a_in[pix * CI + ci]) > 0.f;
+                dx[pix * CI + ci] = to_bf16(on ? acc[r][c][i] : 0.f);
+            }
+        }
+}
+
+// Backward weight, partial sums: part_w[split][co][tap][ci] = sum over the
+// output pixels of rows [split * rows, (split + 1) * rows) (a row is one
+// (image, output y)) of dy[pixel][co] * x[input pixel of tap][ci];
+// part_b[split][co] = sum of dy[pixel][co] over the same pixels.
+// Block: 4 waves, one 32 x 32 tile each: co block = blockIdx.y, column block
+// (tap, ci) = 4 blockIdx.x + wave. K runs over 16 consecutive output x at a time.
+template <int CI, int CO, int S>
+__global__ __launch_bounds__(256) void k_conv_wgrad(const u16 *__restrict__ x, const u16 *__restrict__ dy, ConvDims d,
+                                                     int rows_per_split, float *__restrict__ part_w,
+                                                     float *__restrict__ part_b) {
+    constexpr int NCOL = 9 * CI;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r32 = lane & 31, kq = lane >> 5;
+    const int colblk = blockIdx.x * 4 + wave;
+    if (colblk * 32 >= NCOL) return;
+    const int col = colblk * 32 + r32;
+    const bool col_ok = col < NCOL;
+    const int tap = col_ok ? col / CI : 0, ci = col_ok ? col - tap * CI : 0;
+    const int kh = tap / 3, kw = tap - 3 * kh;
+    const int co = blockIdx.y * 32 + r32;
+    const int split = blockIdx.z;
+    const int R = d.n * d.Ho;
+    const int rb = split * rows_per_split, re = min(R, rb + rows_per_split);
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+    float bsum = 0.f;
+    for (int row = rb; row < re; ++row) {
+        const int n = row / d.Ho, oy = row - n * d.Ho;
+        const int iy = oy * S - 1 + kh;
+        const bool row_ok = col_ok && iy >= 0 && iy < d.H;
+        const u16 *dyrow = dy + (int64_t)row * d.Wo * CO + co;
+        const u16 *xrow = x + ((int64_t)n * d.H + (row_ok ? iy : 0)) * d.W * CI + ci;
+        for (int ox0 = 0; ox0 < d.Wo; ox0 += 16) {
+            uint32_t aw[4], bw[4];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                uint32_t av2 = 0, bv2 = 0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int ox = ox0 + 8 * kq + 2 * jj + h;
+                    const bool okp = ox < d.Wo;
+                    const uint32_t av = okp ? dyrow[(int64_t)(okp ? ox : 0) * CO] : 0u;
+                    const int ix = ox * S - 1 + kw;
+                    const bool okx = okp && row_ok && ix >= 0 && ix < d.W;
+                    const uint32_t bv = okx ? xrow[(int64_t)(okx ? ix : 0) * CI] : 0u;
+                    av2 |= av << (16 * h);
+                    bv2 |= bv << (16 * h);
+                    if (colblk == 0) bsum += from_bf16((u16)av);
+                }
+                aw[jj] = av2;
+                bw[jj] = bv2;
+            }
+            acc = mfma(pack8(aw), pack8(bw), acc);
+        }
+    }
+    if (col_ok) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int rco = blockIdx.y * 32 + 8 * (i / 4) + 4 * kq + (i % 4);
+            part_w[((int64_t)split * CO + rco) * NCOL + col] = acc[i];
+        }
+    }
+    if (colblk == 0) {
+        bsum += __shfl_xor(bsum, 32, 64);
+        if (kq == 0) part_b[(int64_t)split * CO + co] = bsum;
+    }
+}
+
+// grad_w[e] = sum over splits of part_w, grad_b likewise, in split order.
+__global__ void k_wgrad_reduce(const float *__restrict__ part_w, const float *__restrict__ part_b, int nsplit,
+                               int nw, int nb, float *__restrict__ grad_w, float *__restrict__ grad_b) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nw) {
+        float s = 0.f;
+        for (int k = 0; k < nsplit; ++k) s += part_w[(int64_t)k * nw + e];
+        grad_w[e] = s;
+    } else if (e < nw + nb) {
+        const int c = e - nw;
+        float s = 0.f;
+        for (int k = 0; k < nsplit; ++k) s += part_b[(int64_t)k * nb + c];
+        grad_b[c] = s;
+    }
+}
+
+// ---- head: global average pool and the two linear layers ----
+
+constexpr int kFeat = 128, kHidden = 128;
+
+// One block of 256 threads per candidate: g = mean over pixels of a5,
+// h = relu(W1 g + b1), score = w2 . h + b2.
+__global__ __launch_bounds__(256) void k_head_fwd(const u16 *__restrict__ a5, int npix, const float *__restrict__ w1,
+                                                   const float *__restrict__ b1, const float *__restrict__ w2,
+                                                   const float *__restrict__ b2, float *__restrict__ g_out,
+                                                   float *__restrict__ h_out, float *__restrict__ score) {
+    __shared__ float s_part[256], s_g[kFeat], s_h[kHidden], red[4];
+    const int t = threadIdx.x, c = t & (kFeat - 1), half = t >> 7;
+    const u16 *src = a5 + (int64_t)blockIdx.x * npix * kFeat + c;
+    float s = 0.f;
+    for (int p = half; p < npix; p += 2) s += from_bf16(src[(int64_t)p * kFeat]);
+    s_part[t] = s;
+    __syncthreads();
+    if (t < kFeat) {
+        const float g = (s_part[t] + s_part[t + kFeat]) / (float)npix;
+        s_g[t] = g;
+        g_out[(int64_t)blockIdx.x * kFeat + t] = g;
+    }
+    __syncthreads();
+    if (t < kHidden) {
+        float v = b1[t];
+        const float *row = w1 + t * kFeat;
+        for (int i = 0; i < kFeat; ++i) v += row[i] * s_g[i];
+        v = v > 0.f ? v : 0.f;
+        s_h[t] = v;
+        h_out[(int64_t)blockIdx.x * kHidden + t] = v;
+    }
+    __syncthreads();
+    float v = t < kHidden ? w2[t] * s_h[t] : 0.f;
+    v = block_sum(v, red);
+    if (t == 0) score[blockIdx.x] = v + b2[0];
+}
+
+// Per candidate: ds = 2 (score - label) / B, dh = ds w2 (h > 0),
+// dg = W1^T dh, dy5 = dg / npix where a5 > 0 (bf16).
+__global__ __launch_bounds__(256) void k_head_bwd(const float *__restrict__ score, const float *__restrict__ label,
+                                                   int B, const float *__restrict__ h, const float *__restrict__ w1,
+                                                   const float *__restrict__ w2, const u16 *__restrict__ a5, int npix,
+                                                   float *__restrict__ ds_out, float *__restrict__ dh_out,
+                                                   u16 *__restrict__ dy5) {
+    __shared__ float s_dh[kHidden], s_dg[kFeat];
+    const int t = threadIdx.x, b = blockIdx.x;
+    const float ds = 2.f * (score[b] - label[b]) / (float)B;
+    if (t == 0) ds_out[b] = ds;
+    if (t < kHidden) {
+        const float v = h[(int64_t)b * kHidden + t] > 0.f ? ds * w2[t] : 0.f;
+        s_dh[t] = v;
+        dh_out[(int64_t)b * kHidden + t] = v;
+    }
+    __syncthreads();
+    if (t < kFeat) {
+        float v = 0.f;
+        for (int o = 0; o < kHidden; ++o) v += s_dh[o] * w1[o * kFeat + t];
+        s_dg[t] = v / (float)npix;
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)b * npix * kFeat;
+    for (int e = t; e < npix * kFeat; e += blockDim.x) {
+        const bool on = from_bf16(a5[base + e]) > 0.f;
+        dy5[base + e] = to_bf16(on ? s_dg[e & (kFeat - 1)] : 0.f);
+    }
+}
+
+// Gradients of the linear layers and the loss, summed over the batch in order:
+//   dW1[o][i] = sum_b dh[b][o] g[b][i], db1[o] = sum_b dh[b][o],
+//   dw2[i] = sum_b ds[b] h[b][i], db2 = sum_b ds[b], loss = mean (score - label)^2.
+__global__ void k_head_grads(const float *__restrict__ ds, const float *__restrict__ dh, const float *__restrict__ g,
+                             const float *__restrict__ h, const float *__restrict__ score,
+                             const float *__restrict__ label, int B, float *__restrict__ gw1,
+                             float *__restrict__ gb1, float *__restrict__ gw2, float *__restrict__ gb2,
+                             float *__restrict__ loss) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    float s = 0.f;
+    if (e < kHidden * kFeat) {
+        const int o = e / kFeat, i = e - o * kFeat;
+        for (int b = 0; b < B; ++b) s += dh[(int64_t)b * kHidden + o] * g[(int64_t)b * kFeat + i];
+        gw1[e] = s;
+    } else if (e < kHidden * kFeat + kHidden) {
+        const int o = e - kHidden * kFeat;
+        for (int b = 0; b < B; ++b) s += dh[(int64_t)b * kHidden + o];
+        gb1[o] = s;
+    } else if (e < kHidden * kFeat + 2 * kHidden) {
+        const int i = e - kHidden * kFeat - kHidden;
+        for (int b = 0; b < B; ++b) s += ds[b] * h[(int64_t)b * kHidden + i];
+        gw2[i] = s;
+    } else if (e == kHidden * kFeat + 2 * kHidden) {
+        for (int b = 0; b < B; ++b) s += ds[b];
+        gb2[0] = s;
+    } else if (e == kHidden * kFeat + 2 * kHidden + 1 && loss) {
+        for (int b = 0; b < B; ++b) {
+            const float r = score[b] - label[b];
+            s += r * r;
+        }
+        loss[0] = s / (float)B;
+    }
+}
+
+// ---- parameters ----
+
+// AdamW on the flat float32 parameters: m, v moments; bc1 = 1 - beta1^t,
+// bc2 = 1 - beta2^t; decoupled weight decay on entries with decay[i] != 0.
+__global__ void k_adamw(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                        float *__restrict__ v, const uint8_t *__restrict__ decay, int64_t n, float lr, float b1,
+                        float b2, float eps, float wd, float bc1, float bc2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / bc1, vh = vi / bc2;
+    float pi = p[i];
+    if (decay[i]) pi -= lr * wd * pi;
+    p[i] = pi - lr * mh / (sqrtf(vh) + eps);
+}
+
+// bf16 copies of the convolution weights: wt in the parameter layout
+// [co][tap][ci] and wd in [tap][ci][co], for layer l's slice.
+__global__ void k_conv_weights(const float *__restrict__ p, int64_t off, int CI, int CO, u16 *__restrict__ wt,
+                               u16 *__restrict__ wd) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= CO * 9 * CI) return;
+    const int co = e / (9 * CI), r = e - co * 9 * CI, tap = r / CI, ci = r - tap * CI;
+    const u16 h = to_bf16(p[off + e]);
+    wt[e] = h;
+    wd[((int64_t)tap * CI + ci) * CO + co] = h;
+}
+
+template <int CI, int CO, int S, int RM, int RN, int WGN>
+void fwd_layer(hipStream_t s, const u16 *x, ConvDims d, const u16 *wt, const float *bias, u16 *y) {
+    constexpr int BM = (4 / WGN) * RM * 32;
+    const int64_t M = (int64_t)d.n * d.Ho * d.Wo;
+    hipLaunchKernelGGL((k_conv_fwd<CI, CO, S, RM, RN, WGN>), dim3((unsigned)((M + BM - 1) / BM)), dim3(256), 0, s,
+                       x, d, wt, bias, y);
+}
+
+template <int CI, int CO, int S, int RM, int RN, int WGN>
+void bwd_data_layer(hipStream_t s, const u16 *dy, ConvDims d, const u16 *wd, const u16 *a_in, u16 *dx) {
+    constexpr int BM = (4 / WGN) * RM * 32;
+    const int64_t Hc = (d.H + S - 1) / S, Wc = (d.W + S - 1) / S;  // largest class
+    const int64_t M = (int64_t)d.n * Hc * Wc;
+    hipLaunchKernelGGL((k_conv_bwd_data<CI, CO, S, RM, RN, WGN>), dim3((unsigned)((M + BM - 1) / BM), S * S),
+                       dim3(256), 0, s, dy, d, wd, a_in, dx);
+}
+
+template <int CI, int CO, int S>
+void wgrad_layer(hipStream_t s, const u16 *x, const u16 *dy, ConvDims d, float *part_w, int64_t part_cap,
+                 float *grad_w, float *grad_b) {
+    constexpr int NCOL = 9 * CI;
+    const int colgroups = (NCOL / 32 + (NCOL % 32 ? 1 : 0) + 3) / 4;
+    const int coblocks = CO / 32;
+    const int R = d.n * d.Ho;
+    // about 2048 blocks, and no more splits than the partial buffer holds
+    int nsplit = std::max(1, 2048 / (colgroups * coblocks));
+    nsplit = (int)std::min<int64_t>(nsplit, std::min<int64_t>(R, part_cap / ((int64_t)CO * NCOL + CO)));
+    nsplit = std::max(1, nsplit);
+    const int rows = (R + nsplit - 1) / nsplit;
+    nsplit = (R + rows - 1) / rows;
+    hipLaunchKernelGGL((k_conv_wgrad<CI, CO, S>), dim3(colgroups, coblocks, nsplit), dim3(256), 0, s, x, dy, d, rows,
+                       part_w, part_w + (int64_t)nsplit * CO * NCOL);
+    const int nw = CO * NCOL;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((nw + CO + 255) / 256), dim3(256), 0, s, part_w,
+                       part_w + (int64_t)nsplit * CO * NCOL, nsplit, nw, CO, grad_w, grad_b);
+}
+
+}  // namespace
+
+// ---- launchers (declared in internal.h) ----
+
+void launch_pool_grey(hipStream_t s, const float *rgb, int P, int H, int W, int f, float *out) {
+    const int64_t n = (int64_t)P * (H / f) * (W / f);
+    hipLaunchKernelGGL(k_pool_grey, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rgb, P, H, W, f, out);
+}
+
+void launch_scorer_input(hipStream_t s, const float *rgb, int B, int h, int w, const float *q, float *qstats,
+                         uint16_t *x) {
+    hipLaunchKernelGGL(k_query_stats, dim3(1), dim3(1024), 0, s, q, h * w, qstats);
+    hipLaunchKernelGGL(k_scorer_input, dim3(B), dim3(1024), 0, s, rgb, h, w, q, qstats, x);
+}
+
+void scorer_dims(int H, int W, int dims[kScorerLayers + 1][2]) {
+    dims[0][0] = H;
+    dims[0][1] = W;
+    for (int l = 0; l < kScorerLayers; ++l) {
+        const int st = kScorerStride[l];
+        dims[l + 1][0] = (dims[l][0] - 1) / st + 1;
+        dims[l + 1][1] = (dims[l][1] - 1) / st + 1;
+    }
+}
+
+void launch_scorer_forward(hipStream_t s, const ScorerBufs &b, int B, float *score) {
+    int dm[kScorerLayers + 1][2];
+    scorer_dims(b.H, b.W, dm);
+    auto D = [&](int l) { return ConvDims{B, dm[l][0], dm[l][1], dm[l + 1][0], dm[l + 1][1]}; };
+    const float *p = b.params;
+    fwd_layer<2, 32, 2, 2, 1, 1>(s, b.x, D(0), b.wt + b.w_off[0], p + b.b_off[0], b.act[1]);
+    fwd_layer<32, 64, 1, 2, 2, 1>(s, b.act[1], D(1), b.wt + b.w_off[1], p + b.b_off[1], b.act[2]);
+    fwd_layer<64, 64, 2, 2, 2, 1>(s, b.act[2], D(2), b.wt + b.w_off[2], p + b.b_off[2], b.act[3]);
+    fwd_layer<64, 128, 1, 2, 2, 2>(s, b.act[3], D(3), b.wt + b.w_off[3], p + b.b_off[3], b.act[4]);
+    fwd_layer<128, 128, 2, 2, 2, 2>(s, b.act[4], D(4), b.wt + b.w_off[4], p + b.b_off[4], b.act[5]);
+    const int npix = dm[5][0] * dm[5][1];
+    hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(256), 0, s, b.act[5], npix, p + b.fc_off[0], p + b.fc_off[1],
+                       p + b.fc_off[2], p + b.fc_off[3], b.g, b.h, score);
+}
+
+void launch_scorer_backward(hipStream_t s, const ScorerBufs &b, int B, const float *score, const float *label,
+                            float *grad, float *loss) {
+    int dm[kScorerLayers + 1][2];
+    scorer_dims(b.H, b.W, dm);
+    auto D = [&](int l) { return ConvDims{B, dm[l][0], dm[l][1], dm[l + 1][0], dm[l + 1][1]}; };
+    const float *p = b.params;
+    const int npix = dm[5][0] * dm[5][1];
+    u16 *dA = b.dbuf[0], *dB = b.dbuf[1];
+    hipLaunchKernelGGL(k_head_bwd, dim3(B), dim3(256), 0, s, score, label, B, b.h, p + b.fc_off[0],
+                       p + b.fc_off[2], b.act[5], npix, b.ds, b.dh, dA);
+    const int nhead = kHidden * kFeat + 2 * kHidden + 2;
+    hipLaunchKernelGGL(k_head_grads, dim3((nhead + 255) / 256), dim3(256), 0, s, b.ds, b.dh, b.g, b.h, score, label,
+                       B, grad + b.fc_off[0], grad + b.fc_off[1], grad + b.fc_off[2], grad + b.fc_off[3], loss);
+    // layer 5: dy in dA
+    wgrad_layer<128, 128, 2>(s, b.act[4], dA, D(4), b.part, b.part_cap, grad + b.w_off[4], grad + b.b_off[4]);
+    bwd_data_layer<128, 128, 2, 2, 2, 2>(s, dA, D(4), b.wd + b.w_off[4], b.act[4], dB);
+    // layer 4: dy in dB
+    wgrad_layer<64, 128, 1>(s, b.act[3], dB, D(3), b.part, b.part_cap, grad + b.w_off[3], grad + b.b_off[3]);
+    bwd_data_layer<64, 128, 1, 2, 2, 1>(s, dB, D(3), b.wd + b.w_off[3], b.act[3], dA);
+    // layer 3: dy in dA
+    wgrad_layer<64, 64, 2>(s, b.act[2], dA, D(2), b.part, b.part_cap, grad + b.w_off[2], grad + b.b_off[2]);
+    bwd_data_layer<64, 64, 2, 2, 2, 1>(s, dA, D(2), b.wd + b.w_off[2], b.act[2], dB);
+    // layer 2: dy in dB
+    wgrad_layer<32, 64, 1>(s, b.act[1], dB, D(1), b.part, b.part_cap, grad + b.w_off[1], grad + b.b_off[1]);
+    bwd_data_layer<32, 64, 1, 2, 1, 1>(s, dB, D(1), b.wd + b.w_off[1], b.act[1], dA);
+    // layer 1: dy in dA
+    wgrad_layer<2, 32, 2>(s, b.x, dA, D(0), b.part, b.part_cap, grad + b.w_off[0], grad + b.b_off[0]);
+}
+
+void launch_scorer_weights(hipStream_t s, const ScorerBufs &b) {
+    for (int l = 0; l < kScorerLayers; ++l) {
+        const int ci = kScorerChannels[l], co = kScorerChannels[l + 1];
+        const int n = co * 9 * ci;
+        hipLaunchKernelGGL(k_conv_weights, dim3((n + 255) / 256), dim3(256), 0, s, b.params, b.w_off[l], ci, co,
+                           b.wt + b.w_off[l], b.wd + b.w_off[l]);
+    }
+}
+
+void launch_adamw(hipStream_t s, float *p, const float *g, float *m, float *v, const uint8_t *decay, int64_t n,
+                  float lr, float b1, float b2, float eps, float wd, float bc1, float bc2) {
+    hipLaunchKernelGGL(k_adamw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, decay, n, lr, b1, b2,
+                       eps, wd, bc1, bc2);
+}
+
+}  // namespace gsr

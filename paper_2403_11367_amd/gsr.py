@@ -1,4 +1,4 @@
-"""ctypes binding of libgsr (include/gsr.h): argument marshalling only.
+"""ctypes binding of libgsr (include/gsr.h, include/gsr_scorer.h): argument marshalling only.
 
 Every computation runs in the HIP library; this module checks tensor
 devices, dtypes and shapes, passes ``data_ptr()`` and the current torch
@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes as C
 import dataclasses
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -24,12 +25,15 @@ STATUS = {0: "GSR_OK", -1: "GSR_EINVAL", -2: "GSR_ENOMEM", -3: "GSR_EHIP", -4: "
 BUF_RECORDS, BUF_NTILES, BUF_OFFSETS, BUF_PAIRS = 0, 1, 2, 3
 RENDER_COUNT_EVALS = 1
 
-# every symbol declared in include/gsr.h
+# every symbol declared in include/gsr.h and include/gsr_scorer.h
 EXPORTS = [
     "gsr_create", "gsr_destroy", "gsr_set_stream", "gsr_set_profiling", "gsr_default_cfg",
     "gsr_submap_load", "gsr_submap_free", "gsr_submap_size", "gsr_render", "gsr_ncc", "gsr_topk", "gsr_search",
     "gsr_sync", "gsr_get_stats", "gsr_debug_size", "gsr_debug_copy", "gsr_crop",
     "gsr_status_string", "gsr_last_error",
+    "gsr_scorer_param_count", "gsr_scorer_create", "gsr_scorer_destroy", "gsr_scorer_set_params",
+    "gsr_scorer_get_params", "gsr_pool_grey", "gsr_scorer_inputs", "gsr_scorer_forward", "gsr_scorer_backward",
+    "gsr_scorer_adamw", "gsr_scorer_train_step",
 ]
 
 
@@ -64,6 +68,11 @@ class Stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class AdamW(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("weight_decay", C.c_float)]
+
+
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2403_11367_amd.build`")
@@ -90,6 +99,17 @@ def _load() -> C.CDLL:
         "gsr_crop": (I, [P, I64, D, D, D, D, D, P, I64, C.POINTER(I64)]),
         "gsr_status_string": (C.c_char_p, [I]),
         "gsr_last_error": (C.c_char_p, [P]),
+        "gsr_scorer_param_count": (I64, []),
+        "gsr_scorer_create": (I, [P, I32, I32, I32, C.POINTER(P)]),
+        "gsr_scorer_destroy": (I, [P]),
+        "gsr_scorer_set_params": (I, [P, P]),
+        "gsr_scorer_get_params": (I, [P, P]),
+        "gsr_pool_grey": (I, [P, P, I32, I32, I32, I32, P]),
+        "gsr_scorer_inputs": (I, [P, P, I32, P, P]),
+        "gsr_scorer_forward": (I, [P, P, I32, P]),
+        "gsr_scorer_backward": (I, [P, P, P, I32, P, P]),
+        "gsr_scorer_adamw": (I, [P, P, C.POINTER(AdamW)]),
+        "gsr_scorer_train_step": (I, [P, P, P, I32, C.POINTER(AdamW), P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -187,6 +207,7 @@ class Context:
         rc = LIB.gsr_create(C.byref(self.handle), self.device, C.c_void_p(stream))
         if rc != GSR_OK:
             raise GsrError(rc, "gsr_create")
+        self._scorers = weakref.WeakSet()  # destroyed before the context
 
     def _check(self, rc: int, what: str):
         if rc != GSR_OK:
@@ -199,6 +220,8 @@ class Context:
 
     def close(self):
         if self.handle:
+            for sc in list(getattr(self, "_scorers", ())):
+                sc.close()
             LIB.gsr_destroy(self.handle)
             self.handle = C.c_void_p()
 
@@ -330,3 +353,129 @@ class Context:
         if out.size:
             self._check(LIB.gsr_debug_copy(self.handle, which, out.ctypes.data, nb.value), "gsr_debug_copy")
         return out
+
+    def pool_grey(self, rgb, factor: int, out=None):
+        """factor x factor mean pool of the grey of rgb [n, 3, H, W] -> [n, H/f, W/f]."""
+        torch = _torch()
+        n, _, H, W = rgb.shape
+        _dev_f32(rgb, "rgb", (n, 3, H, W))
+        if out is None:
+            out = torch.empty((n, H // factor, W // factor), dtype=torch.float32, device=rgb.device)
+        _dev_f32(out, "out", (n, H // factor, W // factor))
+        self._bind_stream()
+        self._check(LIB.gsr_pool_grey(self.handle, rgb.data_ptr(), n, H, W, factor, out.data_ptr()), "gsr_pool_grey")
+        return out
+
+
+def _dev_bf16_bits(t, name, shape):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype not in (torch.int16, torch.bfloat16):
+        raise TypeError(f"{name} must be a CUDA int16 or bfloat16 tensor (bfloat16 bits)")
+    if not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be contiguous with shape {tuple(shape)}")
+    return t
+
+
+class Scorer:
+    """Learned candidate scorer (include/gsr_scorer.h) on a context: inputs of
+    height x width, batches of up to max_batch candidates."""
+
+    def __init__(self, ctx: Context, height: int, width: int, max_batch: int):
+        self.ctx = ctx
+        self.height, self.width, self.max_batch = int(height), int(width), int(max_batch)
+        self.handle = C.c_void_p()
+        ctx._bind_stream()
+        ctx._check(LIB.gsr_scorer_create(ctx.handle, self.height, self.width, self.max_batch,
+                                         C.byref(self.handle)), "gsr_scorer_create")
+        self.n_params = int(LIB.gsr_scorer_param_count())
+        ctx._scorers.add(self)
+
+    def close(self):
+        if self.handle:
+            LIB.gsr_scorer_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _x(self, x):
+        n = x.shape[0]
+        return _dev_bf16_bits(x, "x", (n, self.height, self.width, 2)), n
+
+    def set_params(self, params):
+        _dev_f32(params, "params", (self.n_params,))
+        self.ctx._bind_stream()
+        self.ctx._check(LIB.gsr_scorer_set_params(self.handle, params.data_ptr()), "gsr_scorer_set_params")
+
+    def get_params(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.n_params,), dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        _dev_f32(out, "out", (self.n_params,))
+        self.ctx._bind_stream()
+        self.ctx._check(LIB.gsr_scorer_get_params(self.handle, out.data_ptr()), "gsr_scorer_get_params")
+        return out
+
+    def inputs(self, renders, query_grey, out=None):
+        """Network inputs [n, h, w, 2] (bfloat16) from renders [n, 3, h, w] and the pooled query [h, w]."""
+        torch = _torch()
+        n = renders.shape[0]
+        _dev_f32(renders, "renders", (n, 3, self.height, self.width))
+        _dev_f32(query_grey, "query_grey", (self.height, self.width))
+        if out is None:
+            out = torch.empty((n, self.height, self.width, 2), dtype=torch.bfloat16, device=renders.device)
+        _dev_bf16_bits(out, "out", (n, self.height, self.width, 2))
+        self.ctx._bind_stream()
+        self.ctx._check(LIB.gsr_scorer_inputs(self.handle, renders.data_ptr(), n, query_grey.data_ptr(),
+                                              out.data_ptr()), "gsr_scorer_inputs")
+        return out
+
+    def forward(self, x, scores=None):
+        torch = _torch()
+        x, n = self._x(x)
+        if scores is None:
+            scores = torch.empty((n,), dtype=torch.float32, device=x.device)
+        _dev_f32(scores, "scores", (n,))
+        self.ctx._bind_stream()
+        self.ctx._check(LIB.gsr_scorer_forward(self.handle, x.data_ptr(), n, scores.data_ptr()), "gsr_scorer_forward")
+        return scores
+
+    def backward(self, x, labels, grads=None, loss=None):
+        """(loss [1], gradient [n_params]) of the mean squared error at the current parameters."""
+        torch = _torch()
+        x, n = self._x(x)
+        _dev_f32(labels, "labels", (n,))
+        if grads is None:
+            grads = torch.empty((self.n_params,), dtype=torch.float32, device=x.device)
+        if loss is None:
+            loss = torch.empty((1,), dtype=torch.float32, device=x.device)
+        _dev_f32(grads, "grads", (self.n_params,))
+        _dev_f32(loss, "loss", (1,))
+        self.ctx._bind_stream()
+        self.ctx._check(LIB.gsr_scorer_backward(self.handle, x.data_ptr(), labels.data_ptr(), n, loss.data_ptr(),
+                                                grads.data_ptr()), "gsr_scorer_backward")
+        return loss, grads
+
+    @staticmethod
+    def adamw_cfg(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4) -> AdamW:
+        return AdamW(lr, beta1, beta2, eps, weight_decay)
+
+    def adamw(self, grads, opt: AdamW):
+        _dev_f32(grads, "grads", (self.n_params,))
+        self.ctx._bind_stream()
+        self.ctx._check(LIB.gsr_scorer_adamw(self.handle, grads.data_ptr(), C.byref(opt)), "gsr_scorer_adamw")
+
+    def train_step(self, x, labels, opt: AdamW, loss=None):
+        torch = _torch()
+        x, n = self._x(x)
+        _dev_f32(labels, "labels", (n,))
+        if loss is None:
+            loss = torch.empty((1,), dtype=torch.float32, device=x.device)
+        _dev_f32(loss, "loss", (1,))
+        self.ctx._bind_stream()
+        self.ctx._check(LIB.gsr_scorer_train_step(self.handle, x.data_ptr(), labels.data_ptr(), n, C.byref(opt),
+                                                  loss.data_ptr()), "gsr_scorer_train_step")
+        return loss

@@ -1,4 +1,4 @@
-"""The C ABI library loads and exports every symbol include/gsr.h declares;
+"""The C ABI library loads and exports every symbol include/*.h declares;
 host-only entry points and argument checks work without a GPU."""
 import ctypes as C
 import os
@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "gsr.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("gsr.h", "gsr_scorer.h")]
 
 
 def _lib():
@@ -28,14 +28,17 @@ def gsr():
 
 
 def _declared():
-    src = open(HEADER).read()
+    import glob
+    assert sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))) == sorted(HEADERS)
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(gsr_[a-z_]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for must in ["gsr_create", "gsr_submap_load", "gsr_render", "gsr_ncc", "gsr_topk", "gsr_crop"]:
+    for must in ["gsr_create", "gsr_submap_load", "gsr_render", "gsr_ncc", "gsr_topk", "gsr_crop",
+                 "gsr_scorer_create", "gsr_scorer_forward", "gsr_scorer_backward", "gsr_scorer_train_step"]:
         assert must in names
 
 

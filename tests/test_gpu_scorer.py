@@ -1,0 +1,176 @@
+"""GPU parity of the learned scorer's kernels (through the C ABI) against the
+float64 oracle with bfloat16 emulation at the same storage points.
+
+Bars (derived in the design notes): the GPU sums in float32 where the oracle
+sums in float64, so a stored bfloat16 value can round the other way when its
+exact value lies within float32 error of a rounding midpoint; such flips are
+one bfloat16 step (|bit difference| = 1) and rare. Network inputs: bit-exact
+except for flips, at most 1e-3 of the values. Scores: |gpu - oracle| <= 2e-3 (1 + |oracle|).
+Gradients: per parameter block, ||gpu - oracle|| <= 1e-2 ||oracle||. Loss: 1e-3
+relative. AdamW (float32 against float64): |dp| <= 4 ulp(p) + 1e-5 lr.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import say
+from oracle import scorer as S
+
+pytestmark = pytest.mark.gpu
+
+TOL_SCORE = 2e-3
+TOL_GRAD = 1e-2
+TOL_LOSS = 1e-3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2403_11367_amd import Context
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _params(seed):
+    """He-initialised weights with small random biases, float32."""
+    p = W.scorer_params(seed).astype(np.float64)
+    rng = np.random.default_rng(seed + 1000)
+    for part, shape in zip(S.unflatten(p), S.param_shapes()):
+        if len(shape) == 1:
+            part += rng.normal(0, 0.05, shape)
+    return p.astype(np.float32)
+
+
+def _inputs(seed, B, h, w):
+    """Standard-normal network inputs as bfloat16 (torch tensor on the GPU) and
+    their exact values (float64)."""
+    import torch
+    x32 = np.random.default_rng(seed).normal(size=(B, h, w, 2)).astype(np.float32)
+    xb = torch.from_numpy(x32).to(torch.bfloat16)
+    return xb.cuda(), xb.to(torch.float64).numpy()
+
+
+def _scorer(ctx, h, w, B, params):
+    import torch
+    from paper_2403_11367_amd import Scorer
+    sc = Scorer(ctx, h, w, B)
+    sc.set_params(torch.from_numpy(params).cuda())
+    return sc
+
+
+def _check_scores(got, ref, what):
+    err = np.abs(got - ref) / (1 + np.abs(ref))
+    say(f"{what}: max score error {err.max():.2e} (scores {np.abs(ref).max():.3f})")
+    assert np.all(err <= TOL_SCORE), (what, got, ref)
+
+
+@pytest.mark.parametrize("B,h,w", [(2, 94, 352), (5, 13, 37), (3, 2, 3), (2, 1, 1)])
+def test_forward_matches_oracle(ctx, B, h, w):
+    say(f"scorer forward: B {B}, {h}x{w}")
+    params = _params(7)
+    sc = _scorer(ctx, h, w, B, params)
+    xg, x = _inputs(100 + h, B, h, w)
+    got = sc.forward(xg).cpu().numpy()
+    ref, _ = S.forward(params.astype(np.float64), x, bf16=True)
+    _check_scores(got, ref, f"{h}x{w}")
+    sc.close()
+
+
+def test_forward_full_batch_sampled(ctx):
+    """1024 candidates at 94x352 in one call (the size the pruning step runs);
+    three of them are checked one by one against the oracle."""
+    say("scorer forward: B 1024, 94x352, sampled")
+    B, h, w = 1024, 94, 352
+    params = _params(8)
+    sc = _scorer(ctx, h, w, B, params)
+    xg, x = _inputs(5, B, h, w)
+    got = sc.forward(xg).cpu().numpy()
+    for i in (0, 517, 1023):
+        ref, _ = S.forward(params.astype(np.float64), x[i:i + 1], bf16=True)
+        _check_scores(got[i:i + 1], ref, f"candidate {i}")
+    sc.close()
+
+
+@pytest.mark.parametrize("B,h,w", [(3, 94, 352), (4, 13, 37), (2, 5, 6)])
+def test_backward_matches_oracle(ctx, B, h, w):
+    import torch
+    say(f"scorer backward: B {B}, {h}x{w}")
+    params = _params(9)
+    sc = _scorer(ctx, h, w, B, params)
+    xg, x = _inputs(200 + h, B, h, w)
+    labels = np.random.default_rng(h).uniform(-1, 1, B).astype(np.float32)
+    loss, grads = sc.backward(xg, torch.from_numpy(labels).cuda())
+    loss, grads = float(loss.cpu()[0]), grads.cpu().numpy().astype(np.float64)
+    ref_loss, ref_g = S.loss_and_grads(params.astype(np.float64), x, labels.astype(np.float64), bf16=True)
+    say(f"  loss {loss:.6f} oracle {ref_loss:.6f}")
+    assert abs(loss - ref_loss) <= TOL_LOSS * abs(ref_loss)
+    names = ["conv1.w", "conv1.b", "conv2.w", "conv2.b", "conv3.w", "conv3.b", "conv4.w", "conv4.b",
+             "conv5.w", "conv5.b", "fc1.w", "fc1.b", "fc2.w", "fc2.b"]
+    for name, g, r in zip(names, S.unflatten(grads), S.unflatten(ref_g)):
+        nr = np.linalg.norm(r)
+        rel = np.linalg.norm(g - r) / nr if nr > 0 else np.linalg.norm(g)
+        say(f"  {name}: |g| {nr:.3e}, relative error {rel:.2e}")
+        assert rel <= TOL_GRAD or (nr == 0 and rel == 0), name
+    sc.close()
+
+
+def test_adamw_matches_oracle(ctx):
+    import torch
+    say("scorer AdamW: two steps")
+    params = _params(10)
+    sc = _scorer(ctx, 4, 4, 1, params)
+    rng = np.random.default_rng(3)
+    n = S.n_params()
+    g1, g2 = rng.normal(0, 1e-2, n).astype(np.float32), rng.normal(0, 1e-2, n).astype(np.float32)
+    opt = sc.adamw_cfg(lr=1e-3, beta1=0.9, beta2=0.99, eps=1e-8, weight_decay=0.05)
+    sc.adamw(torch.from_numpy(g1).cuda(), opt)
+    sc.adamw(torch.from_numpy(g2).cuda(), opt)
+    got = sc.get_params().cpu().numpy().astype(np.float64)
+    p, m, v = params.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t, g in ((1, g1), (2, g2)):
+        p, m, v = S.adamw_step(p, g.astype(np.float64), m, v, t, 1e-3, 0.9, 0.99, 1e-8, 0.05)
+    tol = 4 * np.spacing(np.abs(p).astype(np.float32)).astype(np.float64) + 1e-5 * 1e-3
+    assert np.all(np.abs(got - p) <= tol)
+    sc.close()
+
+
+def test_inputs_and_pooling_match_oracle(ctx):
+    import torch
+    from paper_2403_11367_amd import Scorer
+    say("scorer inputs: pool grey 376x1408 -> 94x352, standardise 3 renders (one constant)")
+    rng = np.random.default_rng(4)
+    q = rng.uniform(0, 1, (1, 3, 376, 1408)).astype(np.float32)
+    pooled = ctx.pool_grey(torch.from_numpy(q).cuda(), 4).cpu().numpy()[0]
+    ref_pool = S.pool_grey(q[0].astype(np.float64), 4)
+    assert np.max(np.abs(pooled - ref_pool)) <= 1e-5
+    renders = rng.uniform(0, 1, (3, 3, 94, 352)).astype(np.float32)
+    renders[1] = 0.25  # constant image: standardises to zeros
+    sc = Scorer(ctx, 94, 352, 3)
+    x = sc.inputs(torch.from_numpy(renders).cuda(), torch.from_numpy(pooled).cuda())
+    got = x.view(torch.int16).cpu().numpy().astype(np.int32)
+    ref = S.bf16_round(S.inputs(renders.astype(np.float64), pooled.astype(np.float64)))
+    ref_bits = torch.from_numpy(ref.astype(np.float32)).to(torch.bfloat16).view(torch.int16).numpy().astype(np.int32)
+    diff = np.abs(got - ref_bits)
+    say(f"  flips {np.count_nonzero(diff)} of {diff.size}")
+    assert diff.max() <= 1 and np.count_nonzero(diff) <= 1e-3 * diff.size
+    assert np.all(got[1, :, :, 0] == 0)
+    sc.close()
+
+
+def test_training_reduces_the_loss(ctx):
+    """A few AdamW steps on one batch fit its labels: the loss falls below a
+    fifth of its starting value."""
+    import torch
+    say("scorer training: 60 steps on one batch of 16 at 47x88")
+    B, h, w = 16, 47, 88
+    sc = _scorer(ctx, h, w, B, _params(11))
+    xg, _ = _inputs(6, B, h, w)
+    labels = torch.from_numpy(np.random.default_rng(6).uniform(-0.5, 0.5, B).astype(np.float32)).cuda()
+    opt = sc.adamw_cfg(lr=1e-3, weight_decay=0.0)
+    losses = [float(sc.train_step(xg, labels, opt).cpu()[0]) for _ in range(60)]
+    say(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.2 * losses[0]
+    sc.close()

@@ -109,6 +109,8 @@ def test_standardise_pool_and_inputs():
     z = S.standardise(img)
     assert abs(z.mean()) < 1e-12 and abs((z * z).mean() - 1) < 1e-12
     assert np.all(S.standardise(np.full((4, 4), 7.0)) == 0)
+    # grey of a constant colour has a full 53-bit mantissa; its rounded mean differs from it
+    assert np.all(S.standardise(S.grey(np.full((3, 94, 352), 0.25, np.float32))) == 0)
     rgb = rng.uniform(0, 1, (3, 8, 12))
     g = 0.299 * rgb[0] + 0.587 * rgb[1] + 0.114 * rgb[2]
     assert np.allclose(S.pool_grey(rgb, 4)[1, 2], g[4:8, 8:12].mean())
@@ -122,3 +124,48 @@ def test_forward_shapes_and_pooling():
     score, (acts, g, h) = S.forward(W.scorer_params(1), x)
     assert [a.shape[1:3] for a in acts] == [(94, 352), (47, 176), (47, 176), (24, 88), (24, 88), (12, 44)]
     assert score.shape == (2,) and np.allclose(g, acts[-1].mean(axis=(1, 2)))
+
+
+def test_adamw_first_step_closed_form_and_constant_gradient():
+    rng = np.random.default_rng(12)
+    n = S.n_params()
+    p = rng.normal(size=n)
+    g = rng.normal(size=n)
+    lr, eps = 1e-3, 1e-8
+    m = v = np.zeros(n)
+    step = lr * g / (np.abs(g) + eps)  # bias-corrected moments are g and g^2
+    for t in (1, 2, 3):  # a constant gradient gives the same step every time
+        p_new, m, v = S.adamw_step(p, g, m, v, t, lr, 0.9, 0.999, eps, 0.0)
+        assert np.allclose(p - p_new, step, rtol=1e-9, atol=1e-15)
+        p = p_new
+
+
+def test_adamw_weight_decay_only_on_weights():
+    n = S.n_params()
+    p = np.full(n, 2.0)
+    p_new, _, _ = S.adamw_step(p, np.zeros(n), np.zeros(n), np.zeros(n), 1, 0.1, 0.9, 0.999, 1e-8, 0.5)
+    parts = S.unflatten(p_new)
+    for i, q in enumerate(parts):
+        bias = i % 2 == 1 and i != 12  # conv biases, b1, b2 (index 12 is the fc2 weight vector)
+        assert np.all(q == (2.0 if bias else 2.0 * (1 - 0.1 * 0.5))), i
+
+
+def test_adamw_matches_torch():
+    import torch
+    rng = np.random.default_rng(13)
+    n = S.n_params()
+    p0 = rng.normal(size=n)
+    grads = [rng.normal(size=n) for _ in range(3)]
+    mask = S.decay_mask().astype(bool)
+    tw = torch.tensor(p0[mask], dtype=torch.float64, requires_grad=True)
+    tb = torch.tensor(p0[~mask], dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.AdamW([{"params": [tw], "weight_decay": 0.01}, {"params": [tb], "weight_decay": 0.0}],
+                            lr=3e-3, betas=(0.8, 0.95), eps=1e-6)
+    p, m, v = p0, np.zeros(n), np.zeros(n)
+    for t, g in enumerate(grads, 1):
+        tw.grad = torch.tensor(g[mask])
+        tb.grad = torch.tensor(g[~mask])
+        opt.step()
+        p, m, v = S.adamw_step(p, g, m, v, t, 3e-3, 0.8, 0.95, 1e-6, 0.01)
+    assert np.allclose(p[mask], tw.detach().numpy(), rtol=0, atol=1e-12)
+    assert np.allclose(p[~mask], tb.detach().numpy(), rtol=0, atol=1e-12)
