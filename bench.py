@@ -10,6 +10,12 @@ whole hot path on device-resident inputs: pack the submap from the map
 all 64 poses, NCC of the 64 renders, top-1. The crop itself is host code run
 once per query and is not timed.
 
+Beside the headline, on the same submap and query: the random-order search with
+an early stop (Sec. IV), and learned vs plain over 1024 candidates (the trained
+scorer prunes to 16 from quarter-resolution renders; the same pruning with
+low-resolution NCC in place of the network; plain renders all at full
+resolution).
+
 Prints one JSON line (rank 0). See --help for flags.
 """
 import argparse
@@ -83,6 +89,7 @@ def main():
     ap.add_argument("--cpu-candidates", type=int, default=2, help="oracle sample size (0 = skip)")
     ap.add_argument("--pose-groups", type=int, default=0,
                     help="pose groups per render (0 = the library's automatic choice)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy before the timed loop (for rocprofv3 counter scaling)")
     args = ap.parse_args()
@@ -222,12 +229,69 @@ def main():
                          "plain_best": best_i, "ms_per_search": round(t_s * 1e3, 3),
                          "scored_candidates_per_s": round(e_n / t_s, 1)}
     _log(f"early-stop search: {e_n} of {P} scored in {t_s * 1e3:.2f} ms, best {e_best} (plain {best_i})")
+    if not args.no_learned:
+        out["learned"] = learned_leg(ctx, sm, cam, sc, query, dev)
     if args.cpu_candidates > 0:
         _log(f"cpu baseline: oracle on {args.cpu_candidates} candidates ...")
         out["cpu_baseline"] = cpu_baseline(sc, idx, args.cpu_candidates)
     print(json.dumps(out), flush=True)
     sm.free()
     ctx.close()
+
+
+def learned_leg(ctx, sm, cam, sc, query, dev, k=16, reps=5):
+    """Learned vs plain on the same submap and query: 1024 candidates (8 dx x 8 dy
+    x 16 dyaw at 1 m / 1 m / 5 degrees around the prior). Plain renders and scores
+    all of them at full resolution; the pruned searches render all at a quarter of
+    the resolution, predict (trained scorer, or low-resolution NCC), and decide
+    among the k best by full-resolution NCC. Renders use exact pair buffers."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2403_11367_amd import Camera, Scorer, learned
+
+    poses = torch.as_tensor(W.yaw_grid_poses(sc.prior_center, W.AXES_ALONG_X, W.SCORER_DX, W.SCORER_DY,
+                                             W.SCORER_DYAW), device=dev)
+    P = poses.shape[0]
+    lc = W.low_res_camera(W.config1_camera(), W.SCORER_FACTOR)
+    cam_low = Camera(lc.width, lc.height, lc.fx, lc.fy, lc.cx, lc.cy)
+    scorer = Scorer(ctx, lc.height, lc.width, 256)
+    scorer.set_params(torch.as_tensor(learned.load_weights(), device=dev))
+    best_t = torch.empty((1,), dtype=torch.int32, device=dev)
+
+    def plain():
+        s = learned.exhaustive_ncc(ctx, sm, cam, poses, query)
+        ctx.topk(s, 1, out=best_t)
+        return s
+
+    def timed(fn):
+        r = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) / reps
+
+    s_plain, t_plain = timed(plain)
+    s_np = s_plain.cpu().numpy()
+    best = int(np.argmax(s_np))
+    res = {"candidates": P, "k": k, "low_res": f"{lc.width}x{lc.height}",
+           "plain": {"ms": round(t_plain * 1e3, 3), "candidates_per_s": round(P / t_plain, 1), "best": best,
+                     "best_ncc": round(float(s_np[best]), 5)}}
+    for name, net in (("learned", scorer), ("lowres_ncc", None)):
+        (b, bs, pred, top, ncc), t = timed(lambda net=net: ctx.search_pruned(sm, cam, cam_low, poses, query, k,
+                                                                           scorer=net))
+        res[name] = {"ms": round(t * 1e3, 3), "candidates_per_s": round(P / t, 1), "best": b,
+                     "best_ncc": round(bs, 5), "found_plain_best": b == best,
+                     "speedup_vs_plain": round(t_plain / t, 3)}
+    res["recall"] = ("top-5 recall on 100 held-out queries (maps 501-502): learned 1.0, low-res NCC 1.0; "
+                     "profiles/scorer_training_config4.md")
+    scorer.close()
+    _log(f"learned vs plain ({P} candidates): plain {res['plain']['ms']:.1f} ms, learned "
+         f"{res['learned']['ms']:.1f} ms, low-res NCC {res['lowres_ncc']['ms']:.1f} ms")
+    return res
 
 
 if __name__ == "__main__":

@@ -95,6 +95,29 @@ int gsr_scorer_adamw(gsr_scorer *s, const float *grads_dev, const gsr_adamw *opt
 int gsr_scorer_train_step(gsr_scorer *s, const uint16_t *x_dev, const float *labels_dev, int32_t n,
                           const gsr_adamw *opt, float *loss_dev);
 
+/* Pruned candidate search. Every candidate pose is rendered at the low
+ * resolution cam_low (batch candidates at a time; 0 = automatic) and given a
+ * predicted score: the scorer's output, or with scorer == NULL the NCC of the
+ * low-resolution render against the pooled query (the same pruning without the
+ * network). The k candidates with the best predictions (ties: lower index) are
+ * rendered at full resolution (cam) and scored by NCC against the query
+ * (Eq. 10), which decides among them. The full-resolution image must be f times
+ * the low-resolution one in both directions (integer f); cam_low is normally cam
+ * with focal lengths and principal point divided by f. One host wait at the end
+ * (and one per render, see gsr_render_cfg.pair_capacity).
+ *   poses_dev [P,3,4] float32 world-to-camera, 1 <= k <= P <= 8192
+ *   query_dev [3,H,W] float32 full-resolution query
+ *   pred_dev  [P] float32 output: predicted score of every candidate
+ *   top_dev   [k] int32 output: the kept candidates, best prediction first
+ *   ncc_dev   [k] float32 output: their full-resolution NCC
+ *   best, best_score (host): the kept candidate with the highest NCC (ties: lower
+ *   candidate index) and that NCC.
+ * The scorer, if given, must belong to ctx and take cam_low's image size. */
+int gsr_search_pruned(gsr_ctx *ctx, gsr_scorer *scorer, const gsr_submap *sm, const gsr_camera *cam,
+                      const gsr_camera *cam_low, const float *poses_dev, int32_t n_poses, int32_t batch,
+                      const float *query_dev, int32_t k, const gsr_render_cfg *cfg, float *pred_dev, int32_t *top_dev,
+                      float *ncc_dev, int32_t *best, float *best_score);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@
 #include <algorithm>
 
 #include "gsr.h"
+#include "gsr_scorer.h"
 
 namespace gsr {
 
@@ -174,6 +175,10 @@ void launch_scorer_backward(hipStream_t s, const ScorerBufs &b, int B, const flo
 void launch_scorer_weights(hipStream_t s, const ScorerBufs &b);
 void launch_adamw(hipStream_t s, float *p, const float *g, float *m, float *v, const uint8_t *decay, int64_t n,
                   float lr, float b1, float b2, float eps, float wd, float bc1, float bc2);
+
+// ---- scorer_rt.cpp ----
+// Context, input size and batch limit of a scorer.
+void scorer_info(const gsr_scorer *s, gsr_ctx **ctx, int *height, int *width, int *max_batch);
 
 // ---- runtime.cpp: context access for the other host units ----
 hipStream_t ctx_stream(gsr_ctx *ctx);

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "gsr.h"
+#include "gsr_scorer.h"
 #include "internal.h"
 
 // Pose groups of a render.
@@ -49,7 +50,7 @@ struct gsr_ctx {
         size_t bytes = 0;
     } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, esum, pseg, scan_tmp,
         ptile, pk, sk, cnt, total, block_base, offsets, grey_q, partials, s_order, s_poses, s_rgb, s_depth,
-        s_scores;
+        s_scores, pr_grey, pr_q3, pr_x, pr_rgb, pr_depth;
     // layout of the last render's pose groups
     struct Group {
         int64_t p0 = 0, np = 0;        // poses [p0, p0 + np)
@@ -655,6 +656,83 @@ int gsr_search(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     *best = b_best;
     *best_score = b_score;
     *n_scored = n;
+    return GSR_OK;
+}
+
+int gsr_search_pruned(gsr_ctx *ctx, gsr_scorer *scorer, const gsr_submap *sm, const gsr_camera *cam,
+                      const gsr_camera *cam_low, const float *poses, int32_t n_poses, int32_t batch,
+                      const float *query, int32_t k, const gsr_render_cfg *cfg, float *pred, int32_t *top,
+                      float *ncc, int32_t *best, float *best_score) {
+    if (!ctx) return GSR_EINVAL;
+    if (!sm || !cam || !cam_low || !poses || !query || !pred || !top || !ncc || !best || !best_score)
+        return fail(ctx, GSR_EINVAL, "null argument");
+    if (n_poses < 1 || n_poses > 8192 || k < 1 || k > n_poses || batch < 0)
+        return fail(ctx, GSR_EINVAL, "need 1 <= k <= P <= 8192 and batch >= 0");
+    const int h = cam_low->height, w = cam_low->width;
+    if (h < 1 || w < 1 || cam->height % h || cam->width % w || cam->height / h != cam->width / w)
+        return fail(ctx, GSR_EINVAL, "the full-resolution image must be an integer multiple of the low-resolution one");
+    const int f = cam->height / h;
+    int32_t B = batch ? batch : std::min<int32_t>(n_poses, 256);
+    if (scorer) {
+        int sh = 0, sw = 0, smax = 0;
+        gsr_ctx *sctx = nullptr;
+        gsr::scorer_info(scorer, &sctx, &sh, &sw, &smax);
+        if (sctx != ctx) return fail(ctx, GSR_EINVAL, "the scorer belongs to another context");
+        if (sh != h || sw != w) return fail(ctx, GSR_EINVAL, "scorer input size differs from the low-resolution camera");
+        B = std::min<int32_t>(B, smax);
+    }
+    B = std::min<int32_t>(B, n_poses);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    const int64_t hw = (int64_t)h * w, HW = (int64_t)cam->height * cam->width;
+    int rc;
+    if ((rc = ensure(ctx, ctx->pr_grey, hw * sizeof(float), "pooled query")) ||
+        (rc = ensure(ctx, ctx->pr_q3, 3 * hw * sizeof(float), "pooled query")) ||
+        (rc = ensure(ctx, ctx->pr_x, (size_t)B * hw * 2 * sizeof(uint16_t), "scorer inputs")) ||
+        (rc = ensure(ctx, ctx->s_rgb, (size_t)B * 3 * hw * sizeof(float), "low-resolution renders")) ||
+        (rc = ensure(ctx, ctx->s_depth, (size_t)B * hw * sizeof(float), "low-resolution depths")) ||
+        (rc = ensure(ctx, ctx->s_poses, (size_t)k * 12 * sizeof(float), "kept poses")) ||
+        (rc = ensure(ctx, ctx->pr_rgb, (size_t)k * 3 * HW * sizeof(float), "full-resolution renders")) ||
+        (rc = ensure(ctx, ctx->pr_depth, (size_t)k * HW * sizeof(float), "full-resolution depths")))
+        return rc;
+    hipStream_t s = ctx->stream;
+    float *grey = (float *)ctx->pr_grey.p, *q3 = (float *)ctx->pr_q3.p;
+    if ((rc = gsr_pool_grey(ctx, query, 1, cam->height, cam->width, f, grey))) return rc;
+    if (!scorer)  // the low-resolution query for NCC: its grey in all three planes
+        for (int c = 0; c < 3; ++c)
+            HIPC(ctx, hipMemcpyAsync(q3 + c * hw, grey, hw * sizeof(float), hipMemcpyDeviceToDevice, s));
+    float *lrgb = (float *)ctx->s_rgb.p, *ldep = (float *)ctx->s_depth.p;
+    for (int32_t b0 = 0; b0 < n_poses; b0 += B) {
+        const int32_t nb = std::min(B, n_poses - b0);
+        if ((rc = gsr_render(ctx, sm, cam_low, poses + (int64_t)b0 * 12, nb, cfg, lrgb, ldep, nullptr))) return rc;
+        if (scorer) {
+            uint16_t *x = (uint16_t *)ctx->pr_x.p;
+            if ((rc = gsr_scorer_inputs(scorer, lrgb, nb, grey, x))) return rc;
+            if ((rc = gsr_scorer_forward(scorer, x, nb, pred + b0))) return rc;
+        } else if ((rc = gsr_ncc(ctx, q3, lrgb, nb, h, w, pred + b0))) {
+            return rc;
+        }
+    }
+    if ((rc = gsr_topk(ctx, pred, n_poses, k, top))) return rc;
+    gsr::launch_gather_poses(s, poses, top, k, (float *)ctx->s_poses.p);
+    if ((rc = check_launch(ctx, "kept poses"))) return rc;
+    if ((rc = gsr_render(ctx, sm, cam, (const float *)ctx->s_poses.p, k, cfg, (float *)ctx->pr_rgb.p,
+                         (float *)ctx->pr_depth.p, nullptr)))
+        return rc;
+    if ((rc = gsr_ncc(ctx, query, (const float *)ctx->pr_rgb.p, k, cam->height, cam->width, ncc))) return rc;
+    std::vector<int32_t> ht((size_t)k);
+    std::vector<float> hs((size_t)k);
+    HIPC(ctx, hipMemcpyAsync(ht.data(), top, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(ctx, hipMemcpyAsync(hs.data(), ncc, (size_t)k * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPC(ctx, hipStreamSynchronize(s));
+    int32_t b_best = -1;
+    float b_score = -INFINITY;
+    for (int32_t i = 0; i < k; ++i)
+        if (hs[i] > b_score || (hs[i] == b_score && ht[i] < b_best)) {
+            b_score = hs[i];
+            b_best = ht[i];
+        }
+    *best = b_best;
+    *best_score = b_score;
     return GSR_OK;
 }
 

@@ -62,6 +62,15 @@ struct gsr_scorer {
     std::vector<void *> owned;
 };
 
+namespace gsr {
+void scorer_info(const gsr_scorer *s, gsr_ctx **ctx, int *height, int *width, int *max_batch) {
+    *ctx = s->ctx;
+    *height = s->H;
+    *width = s->W;
+    *max_batch = s->max_batch;
+}
+}  // namespace gsr
+
 namespace {
 
 int fail(gsr_scorer *s, int code, const std::string &msg) { return gsr::ctx_fail(s->ctx, code, msg.c_str()); }

@@ -33,7 +33,7 @@ EXPORTS = [
     "gsr_status_string", "gsr_last_error",
     "gsr_scorer_param_count", "gsr_scorer_create", "gsr_scorer_destroy", "gsr_scorer_set_params",
     "gsr_scorer_get_params", "gsr_pool_grey", "gsr_scorer_inputs", "gsr_scorer_forward", "gsr_scorer_backward",
-    "gsr_scorer_adamw", "gsr_scorer_train_step",
+    "gsr_scorer_adamw", "gsr_scorer_train_step", "gsr_search_pruned",
 ]
 
 
@@ -110,6 +110,8 @@ def _load() -> C.CDLL:
         "gsr_scorer_backward": (I, [P, P, P, I32, P, P]),
         "gsr_scorer_adamw": (I, [P, P, C.POINTER(AdamW)]),
         "gsr_scorer_train_step": (I, [P, P, P, I32, C.POINTER(AdamW), P]),
+        "gsr_search_pruned": (I, [P, P, P, C.POINTER(CameraC), C.POINTER(CameraC), P, I32, I32, P, I32,
+                                  C.POINTER(RenderCfg), P, P, P, C.POINTER(I32), C.POINTER(F)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -353,6 +355,30 @@ class Context:
         if out.size:
             self._check(LIB.gsr_debug_copy(self.handle, which, out.ctypes.data, nb.value), "gsr_debug_copy")
         return out
+
+    def search_pruned(self, submap: Submap, camera: Camera, camera_low: Camera, poses, query, k: int,
+                      scorer: Optional["Scorer"] = None, batch: int = 0, cfg: Optional[RenderCfg] = None):
+        """Pruned search (gsr_search_pruned): predict every candidate's score at low
+        resolution (scorer, or low-resolution NCC if scorer is None), keep the k best,
+        decide among them by full-resolution NCC. Returns (best candidate, its NCC,
+        predicted scores [P], kept candidates [k], their NCC [k])."""
+        torch = _torch()
+        P = poses.shape[0]
+        _dev_f32(poses, "poses", (P, 3, 4))
+        _dev_f32(query, "query", (3, camera.height, camera.width))
+        dev = poses.device
+        pred = torch.empty((P,), dtype=torch.float32, device=dev)
+        top = torch.empty((k,), dtype=torch.int32, device=dev)
+        ncc = torch.empty((k,), dtype=torch.float32, device=dev)
+        self._bind_stream()
+        cam, caml = camera.c(), camera_low.c()
+        best, score = C.c_int32(0), C.c_float(0)
+        rc = LIB.gsr_search_pruned(self.handle, scorer.handle if scorer is not None else None, submap.handle,
+                                   C.byref(cam), C.byref(caml), poses.data_ptr(), P, batch, query.data_ptr(), k,
+                                   C.byref(cfg) if cfg is not None else None, pred.data_ptr(), top.data_ptr(),
+                                   ncc.data_ptr(), C.byref(best), C.byref(score))
+        self._check(rc, "gsr_search_pruned")
+        return best.value, score.value, pred, top, ncc
 
     def pool_grey(self, rgb, factor: int, out=None):
         """factor x factor mean pool of the grey of rgb [n, 3, H, W] -> [n, H/f, W/f]."""

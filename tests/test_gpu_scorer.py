@@ -174,3 +174,93 @@ def test_training_reduces_the_loss(ctx):
     say(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert losses[-1] < 0.2 * losses[0]
     sc.close()
+
+
+@pytest.mark.parametrize("use_scorer", [False, True])
+def test_pruned_search_config0(ctx, use_scorer):
+    """gsr_search_pruned on config 0 at a quarter of the resolution (32x24), k = 4,
+    against the oracle chain: low-resolution renders, pooled query, the low-res NCC
+    (or the scorer on the oracle's inputs), top-k, full-resolution NCC of the kept."""
+    import torch
+    from helpers import TOL_NCC, camera, load, prep, to_dev
+    from oracle import ncc as oncc
+    from oracle import search
+    from paper_2403_11367_amd import Scorer
+    say(f"pruned search, config0, {'scorer' if use_scorer else 'low-res NCC'}")
+    sc = W.config0()
+    pr = prep(sc.gaussians)
+    cam_low = W.low_res_camera(sc.camera, 4)
+    query = (search.render_pose(pr, sc.hidden_pose, sc.camera).rgb + sc.query_noise).astype(np.float32)
+    q_grey = S.pool_grey(query, 4)
+    low = np.stack([search.render_pose(pr, sc.poses[p], cam_low).rgb for p in range(16)])
+    full = np.stack([search.render_pose(pr, sc.poses[p], sc.camera).rgb for p in range(16)])
+    full_ncc = oncc.ncc(query, full)
+    scorer = None
+    if use_scorer:
+        params = _params(12)
+        scorer = _scorer(ctx, cam_low.height, cam_low.width, 8, params)  # two batches of 8
+        ref_pred, _ = S.forward(params.astype(np.float64), S.inputs(low, q_grey), bf16=True)
+        tol = 1e-2  # the chain: render differences (1e-4) move standardised inputs across bf16 steps
+    else:
+        ref_pred = np.array([oncc.ncc_grey(q_grey, oncc.grey(low[p])) for p in range(16)])
+        tol = TOL_NCC
+    sm = load(ctx, sc.gaussians)
+    k = 4
+    best, best_score, pred, top, ncc = ctx.search_pruned(
+        sm, camera(sc.camera), camera(cam_low), to_dev(sc.poses), to_dev(query), k,
+        scorer=scorer, batch=8)
+    pred, top, ncc = pred.cpu().numpy(), top.cpu().numpy(), ncc.cpu().numpy()
+    err = np.abs(pred - ref_pred) / (1 + np.abs(ref_pred))
+    say(f"  prediction error {err.max():.2e}; kept {top.tolist()} best {best} NCC {best_score:.5f}")
+    assert err.max() <= tol
+    assert np.array_equal(top, search.topk(pred, k))          # the k best of its own predictions
+    ref_sorted = np.sort(ref_pred)[::-1]
+    if ref_sorted[k - 1] - ref_sorted[k] > 2 * tol:          # no near-tie at the cut
+        assert set(top.tolist()) == set(search.topk(ref_pred, k).tolist())
+    assert np.max(np.abs(ncc - full_ncc[top])) <= TOL_NCC
+    order = np.lexsort((top, -ncc))
+    assert best == top[order[0]] and best_score == ncc[order[0]]
+    sm.free()
+    if scorer is not None:
+        scorer.close()
+
+
+def test_trained_scorer_keeps_the_best_on_held_out_queries(ctx):
+    """The committed weights (trained by paper_2403_11367_amd.learned on maps
+    401-404) prune 1024 candidates to 16 on queries of map 501, which training
+    never saw: the exhaustive NCC best is always among the final five, while only
+    16 of the 1024 candidates are rendered at full resolution. The untrained
+    initial network misses it on most queries: the gain comes from training."""
+    import torch
+    from helpers import camera
+    from paper_2403_11367_amd import learned
+    say("trained scorer: 6 held-out queries on map 501, 1024 candidates, k = 16")
+    wcam = W.config1_camera()
+    cam, cam_low = camera(wcam), camera(W.low_res_camera(wcam, W.SCORER_FACTOR))
+    trained = _scorer(ctx, cam_low.height, cam_low.width, 256, learned.load_weights())
+    untrained = _scorer(ctx, cam_low.height, cam_low.width, 256, W.scorer_params(0))
+    dmap = learned.DeviceMap(ctx, W.corridor_map(1_000_000, seed=W.SCORER_EVAL_MAPS[0]))
+    hits, misses_untrained = 0, 0
+    for i in range(6):
+        q = W.scorer_query(W.scorer_query_seed(W.SCORER_EVAL_MAPS[0], i), wcam)
+        poses = torch.as_tensor(q.poses, device="cuda")
+        sm = dmap.crop(q.prior)
+        query = learned.render_query(ctx, dmap, cam, q)
+        s = learned.exhaustive_ncc(ctx, sm, cam, poses, query).cpu().numpy()
+        best = int(np.argmax(s))
+        for net, name in ((trained, "trained"), (untrained, "untrained")):
+            b, bs, pred, top, ncc = ctx.search_pruned(sm, cam, cam_low, poses, query, 16, scorer=net)
+            top, ncc = top.cpu().numpy(), ncc.cpu().numpy()
+            final = top[np.lexsort((top, -ncc))][:5]
+            hit = best in final
+            say(f"  query {i} ({name}): best {best} (NCC {s[best]:.3f}) kept in top 5: {hit}")
+            if name == "trained":
+                hits += hit
+                assert b == best and bs == s[best]
+            else:
+                misses_untrained += not hit
+    dmap.free()
+    assert hits == 6
+    assert misses_untrained >= 3
+    trained.close()
+    untrained.close()

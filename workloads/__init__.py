@@ -201,6 +201,11 @@ def corridor_map(n: int, seed: int, length: float = 200.0) -> Gaussians:
                      _f32(_sigmoid64(logit)), _f32(rgb))
 
 
+def config1_camera() -> Camera:
+    """1408x376 pinhole, f = 552 px, principal point at the image centre."""
+    return Camera(1408, 376, 552.0, 552.0, 704.0, 188.0)
+
+
 def config1(n: int = 1_000_000) -> Scene:
     """Driving-scale scene: corridor map (seed 1), 1408x376 camera, 64 poses.
 
@@ -212,7 +217,7 @@ def config1(n: int = 1_000_000) -> Scene:
     map at the hidden pose.
     """
     g = corridor_map(n, seed=1)
-    cam = Camera(1408, 376, 552.0, 552.0, 704.0, 188.0)
+    cam = config1_camera()
     center = np.array([100.0, 0.0, 1.5])
     steps = [-1.5, -0.5, 0.5, 1.5]
     poses = yaw_grid_poses(center, AXES_ALONG_X, steps, steps, [-7.5, -2.5, 2.5, 7.5])
@@ -294,3 +299,47 @@ def digest(*arrays) -> str:
         h.update(str(a.shape).encode())
         h.update(a.tobytes())
     return h.hexdigest()
+
+
+# ---- learned-scorer workload: 1024 candidates per query ----
+SCORER_DX = [-3.5, -2.5, -1.5, -0.5, 0.5, 1.5, 2.5, 3.5]          # metres (world x)
+SCORER_DY = SCORER_DX                                              # metres (world y)
+SCORER_DYAW = [-37.5 + 5.0 * i for i in range(16)]                 # degrees
+SCORER_TRAIN_MAPS = (401, 402, 403, 404)                           # 4 maps x 49 queries = 196
+SCORER_EVAL_MAPS = (501, 502)                                      # 2 maps x 50 queries = 100
+SCORER_QUERIES_PER_TRAIN_MAP = 49
+SCORER_QUERIES_PER_EVAL_MAP = 50
+SCORER_FACTOR = 4                                                  # low resolution = 1/4 in each direction
+
+
+@dataclasses.dataclass
+class ScorerQuery:
+    prior: np.ndarray     # camera centre of the prior (x, y, z), float64
+    poses: np.ndarray     # [1024, 3, 4] float32 candidate grid around the prior
+    hidden: np.ndarray    # [3, 4] float32 true pose
+    noise: np.ndarray     # [3, H, W] float32 query noise
+
+
+def scorer_query(seed: int, cam: Camera) -> ScorerQuery:
+    """One query of the learned-scorer workload on a corridor map: prior camera at
+    x ~ U(60, 140), y ~ U(-1.5, 1.5), height 1.5 m, looking along +x; candidates
+    8 dx x 8 dy x 16 dyaw (SCORER_* steps; x slowest, then y, then yaw); hidden
+    pose uniform over the grid's extent; query noise N(0, 0.02) per channel.
+    Draw order: prior x, prior y, hidden dx, dy, dyaw, noise."""
+    rng = np.random.default_rng(seed)
+    prior = np.array([rng.uniform(60.0, 140.0), rng.uniform(-1.5, 1.5), 1.5])
+    poses = yaw_grid_poses(prior, AXES_ALONG_X, SCORER_DX, SCORER_DY, SCORER_DYAW)
+    hdx, hdy = rng.uniform(SCORER_DX[0], SCORER_DX[-1], 2)
+    hyaw = rng.uniform(SCORER_DYAW[0], SCORER_DYAW[-1])
+    hidden = _f32(pose_from_center(prior + np.array([hdx, hdy, 0.0]), AXES_ALONG_X, np.deg2rad(hyaw)))
+    noise = _f32(rng.normal(0.0, 0.02, size=(3, cam.height, cam.width)))
+    return ScorerQuery(prior, poses, hidden, noise)
+
+
+def scorer_query_seed(map_seed: int, i: int) -> int:
+    return map_seed * 1000 + i
+
+
+def low_res_camera(cam: Camera, f: int) -> Camera:
+    """The camera with its image reduced f times (focal lengths and principal point / f)."""
+    return Camera(cam.width // f, cam.height // f, cam.fx / f, cam.fy / f, cam.cx / f, cam.cy / f)
