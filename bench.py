@@ -14,7 +14,9 @@ Beside the headline, on the same submap and query: the random-order search with
 an early stop (Sec. IV), and learned vs plain over 1024 candidates (the trained
 scorer prunes to 16 from quarter-resolution renders; the same pruning with
 low-resolution NCC in place of the network; plain renders all at full
-resolution).
+resolution), and batched queries: 8 maps of uneven size x 32 candidates in one
+batched render per stage (autotuned launch) and as a HIP-graph replay, against
+8 separate renders.
 
 Prints one JSON line (rank 0). See --help for flags.
 """
@@ -90,6 +92,7 @@ def main():
     ap.add_argument("--pose-groups", type=int, default=0,
                     help="pose groups per render (0 = the library's automatic choice)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-queries leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy before the timed loop (for rocprofv3 counter scaling)")
     args = ap.parse_args()
@@ -231,12 +234,122 @@ def main():
     _log(f"early-stop search: {e_n} of {P} scored in {t_s * 1e3:.2f} ms, best {e_best} (plain {best_i})")
     if not args.no_learned:
         out["learned"] = learned_leg(ctx, sm, cam, sc, query, dev)
+    if not args.no_batched:
+        out["batched"] = batched_leg(ctx, cam, dev)
     if args.cpu_candidates > 0:
         _log(f"cpu baseline: oracle on {args.cpu_candidates} candidates ...")
         out["cpu_baseline"] = cpu_baseline(sc, idx, args.cpu_candidates)
     print(json.dumps(out), flush=True)
     sm.free()
     ctx.close()
+
+
+def batched_leg(ctx, cam, dev, reps=5):
+    """Batched queries: 8 corridor maps of uneven size (batch_query seeds 200-207,
+    cropped like config 1), 32 candidates each, full-resolution NCC and top-1 per
+    query. Times 8 separate renders against one batched render (launch variant
+    picked by the autotuner) and its HIP-graph replay; all three must give the
+    same images."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2403_11367_amd import autotune, crop, default_cfg
+
+    t_setup = time.perf_counter()
+    qs = [W.batch_query(s, W.config1_camera()) for s in W.BATCH_MAP_SEEDS]
+    sms, queries = [], []
+    for q in qs:
+        arrs = [torch.as_tensor(a, device=dev) for a in q.gaussians.arrays()]
+        full = ctx.load_submap(*arrs)
+        img, _ = ctx.render(full, cam, torch.as_tensor(q.hidden[None], device=dev))
+        queries.append((img[0] + torch.as_tensor(q.noise, device=dev)).contiguous())
+        full.free()
+        idx = crop(q.gaussians.means, 10.0, (100.0, 0.0), 50.0, 1.0)
+        sms.append(ctx.load_submap(*arrs, index=torch.as_tensor(idx, device=dev)))
+        del arrs
+    counts = [q.poses.shape[0] for q in qs]
+    P = sum(counts)
+    poses = torch.as_tensor(np.concatenate([q.poses for q in qs]), device=dev)
+    starts = np.concatenate([[0], np.cumsum(counts)])
+    H, Wd = cam.height, cam.width
+    rgb = torch.empty((P, 3, H, Wd), device=dev)
+    depth = torch.empty((P, H, Wd), device=dev)
+    scores = torch.empty((P,), device=dev)
+    best = torch.empty((len(qs),), dtype=torch.int32, device=dev)
+    # fixed pair capacities from one exact render per query (no host wait when timed)
+    caps = []
+    for i, sm in enumerate(sms):
+        ctx.render(sm, cam, poses[starts[i]:starts[i + 1]].contiguous())
+        caps.append(int(ctx.stats()["n_pairs"] * 1.05) + 4096)
+    _log(f"batched: {len(qs)} queries, maps {[q.n for q in qs]}, crops {[sm.n for sm in sms]}, "
+         f"setup {time.perf_counter() - t_setup:.1f} s")
+
+    def scored(i):
+        a, b = int(starts[i]), int(starts[i + 1])
+        ctx.ncc(queries[i], rgb[a:b], scores[a:b])
+        ctx.topk(scores[a:b], 1, out=best[i:i + 1])
+
+    def separate():
+        for i, sm in enumerate(sms):
+            a, b = int(starts[i]), int(starts[i + 1])
+            ctx.render(sm, cam, poses[a:b].contiguous(), default_cfg(pair_capacity=caps[i]), rgb=rgb[a:b],
+                       depth=depth[a:b])
+            scored(i)
+
+    base = default_cfg(pair_capacity=sum(caps))
+    key = autotune.workload_key(torch.cuda.get_device_name(dev), Wd, H, P, max(sm.n for sm in sms))
+    tuned, record = autotune.tune(key, base, lambda cfg: ctx.render_multi(sms, counts, cam, poses, cfg,
+                                                                          rgb=rgb, depth=depth))
+
+    def batched():
+        ctx.render_multi(sms, counts, cam, poses, tuned, rgb=rgb, depth=depth)
+        for i in range(len(qs)):
+            scored(i)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_sep = timed(separate)
+    ref = (rgb.clone(), depth.clone(), scores.clone(), best.clone())
+    t_bat = timed(batched)
+    same_batched = all(torch.equal(a, b) for a, b in zip((rgb, depth, scores, best), ref))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        batched()
+        stream.synchronize()
+        ctx.capture_begin()
+        batched()
+        graph = ctx.capture_end()
+        rgb.zero_()
+        graph.launch()
+        stream.synchronize()
+        same_graph = all(torch.equal(a, b) for a, b in zip((rgb, depth, scores, best), ref))
+        t_graph = timed(graph.launch)
+        graph.close()
+    ctx.sync()
+    res = {"queries": len(qs), "poses_per_query": counts[0], "renders": P,
+           "map_gaussians": [q.n for q in qs], "submap_gaussians": [sm.n for sm in sms],
+           "separate": {"ms": round(t_sep * 1e3, 3), "renders_per_s": round(P / t_sep, 1)},
+           "batched": {"ms": round(t_bat * 1e3, 3), "renders_per_s": round(P / t_bat, 1),
+                       "identical_to_separate": bool(same_batched)},
+           "graph": {"ms": round(t_graph * 1e3, 3), "renders_per_s": round(P / t_graph, 1),
+                     "identical_to_separate": bool(same_graph)},
+           "autotune": {"key": key, "chosen": {f: getattr(tuned, f) for f in
+                                               ("blend_chunk", "blend_blocks_per_cu", "pose_groups")},
+                        "variants_ms": record.get("variants", "cached")},
+           "best_per_query": best.cpu().tolist()}
+    for sm in sms:
+        sm.free()
+    _log(f"batched: separate {res['separate']['ms']:.2f} ms, batched {res['batched']['ms']:.2f} ms, graph "
+         f"{res['graph']['ms']:.2f} ms for {P} renders; chosen {res['autotune']['chosen']}")
+    return res
 
 
 def learned_leg(ctx, sm, cam, sc, query, dev, k=16, reps=5):

@@ -64,6 +64,7 @@ extern "C" {
 
 typedef struct gsr_ctx gsr_ctx;
 typedef struct gsr_submap gsr_submap;
+typedef struct gsr_graph gsr_graph;
 
 /* Pinhole intrinsics K (Sec. III-A): image width x height in pixels, focal
  * lengths and principal point in pixels. 1 <= width, height <= 32768. */
@@ -93,6 +94,13 @@ typedef struct {
                               * then composites on a stream of its own (the context's
                               * stream for the first), concurrently with the other groups;
                               * the images do not depend on the grouping */
+    int32_t blend_blocks_per_cu; /* compositing launch: 0 = one block per (pose, tile) [0];
+                              * 1..64 = persistent: this many blocks per compute unit take
+                              * (pose, tile) items from a work queue until it is empty.
+                              * The images do not depend on it */
+    int32_t blend_chunk;     /* records staged in LDS per compositing step: 0 = 252 [0];
+                              * 252, 124 or 60 (shorter steps stop sooner on short lists).
+                              * The images do not depend on it */
 } gsr_render_cfg;
 
 /* gsr_render_cfg.flags: count compositing work into gsr_stats (evals_*), for
@@ -169,6 +177,33 @@ int64_t gsr_submap_size(const gsr_submap *sm);
 int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const float *poses_dev,
                int32_t n_poses, const gsr_render_cfg *cfg, float *rgb_dev, float *depth_dev,
                float *tfinal_dev);
+
+/* A batch of queries in one render: submap q is rendered at poses_per_submap[q]
+ * consecutive poses (Sec. III-C1 for several queries at once, each with its own
+ * submap), with one launch per stage for all of them. 1 <= n_submaps <= 16,
+ * poses_per_submap[q] >= 1, total P <= 65535; poses_dev [P,3,4] in submap order;
+ * rgb_dev / depth_dev / tfinal_dev as for gsr_render with P images. The images
+ * are those of separate gsr_render calls, bit for bit. Record slots are laid out
+ * per pose for the largest submap (P x max n < 2^32); gsr_debug_* then report
+ * that layout. */
+int gsr_render_multi(gsr_ctx *ctx, const gsr_submap *const *submaps, const int32_t *poses_per_submap,
+                     int32_t n_submaps, const gsr_camera *cam, const float *poses_dev, const gsr_render_cfg *cfg,
+                     float *rgb_dev, float *depth_dev, float *tfinal_dev);
+
+/* HIP graph capture of the context's stream. Between gsr_capture_begin and
+ * gsr_capture_end the calls of this context are recorded, not run; the graph
+ * then replays them with one launch. Rules: the stream must not be the null
+ * stream; renders need a fixed pair_capacity (no host wait); every workspace
+ * must already be large enough (run the same calls once before capturing),
+ * else the call fails with GSR_EINVAL; profiling is off; the library records no
+ * memset into the graph. A replay reads the inputs and writes the outputs at the
+ * addresses given during capture. gsr_graph_launch enqueues on the context's
+ * current stream. */
+int gsr_capture_begin(gsr_ctx *ctx);
+int gsr_capture_end(gsr_ctx *ctx, gsr_graph **out);
+int gsr_graph_launch(gsr_graph *graph);
+/* Waits for the context's stream and frees the graph. */
+int gsr_graph_destroy(gsr_graph *graph);
 
 /* NCC (Eq. 10) of the query against each of P renders, on grey images.
  *   query_dev   [3,H,W]   float32 planar RGB

@@ -1,0 +1,91 @@
+"""Autotuner of the compositing launch (gsr_render_cfg knobs that leave the
+images unchanged): records staged per LDS step (`blend_chunk`), grid or
+persistent work-queue launch (`blend_blocks_per_cu`), and pose groups.
+
+For a workload key (device, image size, pose count and largest submap size,
+both rounded to powers of two) every variant renders the caller's workload a
+few times; the fastest is kept in a JSON cache (``$GSR_AUTOTUNE_CACHE``, else
+``~/.cache/gsr/autotune.json``) and reused for the same key. Every variant's
+images are compared with the default variant's: they must be identical.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+import time
+from typing import Callable, Dict, List, Optional
+
+CHUNKS = (252, 124, 60)
+BLOCKS_PER_CU = (0, 4, 8)
+POSE_GROUPS = (1, 2)
+
+
+def cache_path() -> str:
+    return os.environ.get("GSR_AUTOTUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "gsr",
+                                                                "autotune.json")
+
+
+def workload_key(device_name: str, width: int, height: int, n_poses: int, n_max: int) -> str:
+    p2 = lambda x: 1 << max(0, math.ceil(math.log2(max(1, x))))  # noqa: E731
+    return f"{device_name}|{width}x{height}|P{p2(n_poses)}|N{p2(n_max)}"
+
+
+def variants() -> List[Dict[str, int]]:
+    return [dict(blend_chunk=c, blend_blocks_per_cu=b, pose_groups=g)
+            for c, b, g in itertools.product(CHUNKS, BLOCKS_PER_CU, POSE_GROUPS)]
+
+
+def _load(path: str) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def tune(key: str, base_cfg, render: Callable[[object], tuple], reps: int = 3, path: Optional[str] = None,
+         retune: bool = False):
+    """Pick the fastest variant for `key`. render(cfg) renders the workload into
+    fixed output tensors and returns them. Returns (cfg, record) where record
+    holds every variant's mean milliseconds (empty when the cache answered)."""
+    import torch
+    from .gsr import default_cfg
+    path = path or cache_path()
+    cache = _load(path)
+    fields = {f: getattr(base_cfg, f) for f, _ in base_cfg._fields_}
+
+    def make(v):
+        cfg = default_cfg(**fields)
+        for k, val in v.items():
+            setattr(cfg, k, val)
+        return cfg
+
+    if not retune and key in cache:
+        return make(cache[key]["best"]), {}
+    ref = [t.clone() for t in render(make(dict(blend_chunk=0, blend_blocks_per_cu=0, pose_groups=1)))]
+    timings = []
+    for v in variants():
+        cfg = make(v)
+        out = render(cfg)
+        torch.cuda.synchronize()
+        for a, b in zip(out, ref):
+            if not torch.equal(a, b):
+                raise RuntimeError(f"autotune: variant {v} changed the images")
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            render(cfg)
+        torch.cuda.synchronize()
+        timings.append((1e3 * (time.perf_counter() - t0) / reps, v))
+    timings.sort(key=lambda t: t[0])
+    best_ms, best = timings[0]
+    record = {"best": best, "best_ms": round(best_ms, 4),
+              "variants": [dict(ms=round(ms, 4), **v) for ms, v in timings]}
+    cache[key] = record
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1)
+    os.replace(tmp, path)
+    return make(best), record

@@ -27,8 +27,8 @@ namespace gsr {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kStage = 63;              // records staged per wave and chunk (lane 63 idle)
-constexpr int kChunk = 4 * kStage;      // records per chunk
+// Records staged per wave and chunk: 63 (lane 63 idle; a chunk of 252), 31 or 15
+// (chunks of 124 or 60, for earlier exits on short lists). A template parameter.
 constexpr int kDummy = 255;             // LDS slot (wave 3, lane 63) of a record that never contributes
 constexpr float kLog2e = 1.4426950408889634f;
 
@@ -41,19 +41,18 @@ struct BlendConsts {
     float t_min;
 };
 
-template <bool kCount>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_blend(const float4 *__restrict__ records, int64_t n,
-                                                    const uint32_t *__restrict__ pairs,
-                                                    const uint64_t *__restrict__ offsets, uint64_t capacity,
-                                                    int width, int height, int tiles_x, int n_tiles,
-                                                    BlendConsts k, float *__restrict__ out_rgb,
-                                                    float *__restrict__ out_depth, float *__restrict__ out_t,
-                                                    unsigned long long *__restrict__ counters) {
+// The compositing of one (tile, pose) by the whole block.
+template <bool kCount, int kStage>
+__device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__restrict__ records, int64_t n,
+                                           const uint32_t *__restrict__ pairs,
+                                           const uint64_t *__restrict__ offsets, uint64_t capacity, int width,
+                                           int height, int tiles_x, int n_tiles, const BlendConsts &k,
+                                           float *__restrict__ out_rgb, float *__restrict__ out_depth,
+                                           float *__restrict__ out_t, unsigned long long *__restrict__ counters) {
     __shared__ float4 s_rec[kThreads * 3];  // slot = staging thread
     __shared__ uint64_t s_mask[4][4][4];  // [band][quarter][64-record group]
     __shared__ uint32_t s_words[4][256];  // per wave: slot of every quarter, one byte each, per step
 
-    const int tile = blockIdx.x, pose = blockIdx.y;
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int quarter = lane >> 4;
@@ -82,7 +81,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     const uint32_t lane_sh = 8u * quarter;  // the lane's byte of a slot word
     const char *s_rec_bytes = reinterpret_cast<const char *>(s_rec);
 
-    for (uint64_t c0 = beg; c0 < end; c0 += kChunk) {
+    for (uint64_t c0 = beg; c0 < end; c0 += 4 * kStage) {
         // stage one record per thread (lanes 0..62 of every wave)
         const uint64_t kk = c0 + (uint64_t)wave * kStage + lane;
         uint32_t cells = 0;  // bit 4 * band + quarter
@@ -266,12 +265,65 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     }
 }
 
+template <bool kCount, int kStage>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_blend(
+    const float4 *__restrict__ records, int64_t n, const uint32_t *__restrict__ pairs,
+    const uint64_t *__restrict__ offsets, uint64_t capacity, int width, int height, int tiles_x, int n_tiles,
+    BlendConsts k, float *__restrict__ out_rgb, float *__restrict__ out_depth, float *__restrict__ out_t,
+    unsigned long long *__restrict__ counters) {
+    blend_tile<kCount, kStage>(blockIdx.x, blockIdx.y, records, n, pairs, offsets, capacity, width, height, tiles_x, n_tiles,
+                       k, out_rgb, out_depth, out_t, counters);
+}
+
+// Persistent variant: a fixed number of blocks take (pose, tile) items, pose
+// major, from a work queue (*queue starts at 0) until it passes n_items; every
+// block leaves once it draws an item past the end.
+template <bool kCount, int kStage>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_blend_queue(
+    const float4 *__restrict__ records, int64_t n, const uint32_t *__restrict__ pairs,
+    const uint64_t *__restrict__ offsets, uint64_t capacity, int width, int height, int tiles_x, int n_tiles,
+    BlendConsts k, float *__restrict__ out_rgb, float *__restrict__ out_depth, float *__restrict__ out_t,
+    unsigned long long *__restrict__ counters, unsigned int n_items, unsigned int *__restrict__ queue) {
+    __shared__ unsigned int s_item;
+    for (;;) {
+        __syncthreads();  // the previous item is done with LDS and with s_item
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
+        __syncthreads();
+        const unsigned int item = s_item;
+        if (item >= n_items) break;
+        blend_tile<kCount, kStage>((int)(item % (unsigned)n_tiles), (int)(item / (unsigned)n_tiles), records, n, pairs,
+                           offsets, capacity, width, height, tiles_x, n_tiles, k, out_rgb, out_depth, out_t,
+                           counters);
+    }
+}
+
+template <bool kCount, int kStage>
+void launch_blend_t(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
+                    const uint64_t *offsets, uint64_t capacity, const Camera &cam, const TileGrid &tg,
+                    const BlendConsts &bc, float *rgb, float *depth, float *tfinal, unsigned long long *counters,
+                    int persistent_blocks, unsigned int *queue) {
+    if (persistent_blocks > 0) {
+        const unsigned n_items = (unsigned)tg.n_tiles * (unsigned)n_poses;
+        const unsigned blocks = std::min<unsigned>((unsigned)persistent_blocks, n_items);
+        launch_fill_u32(s, queue, 1, 0u);
+        hipLaunchKernelGGL((k_blend_queue<kCount, kStage>), dim3(blocks), dim3(kThreads), 0, s, records, n, pairs,
+                           offsets, capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, bc, rgb, depth, tfinal,
+                           counters, n_items, queue);
+        return;
+    }
+    hipLaunchKernelGGL((k_blend<kCount, kStage>), dim3((unsigned)tg.n_tiles, (unsigned)n_poses), dim3(kThreads), 0, s,
+                       records, n, pairs, offsets, capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, bc, rgb,
+                       depth, tfinal, counters);
+}
+
 }  // namespace
+
+bool blend_chunk_supported(int chunk) { return chunk == 0 || chunk == 252 || chunk == 124 || chunk == 60; }
 
 void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
                   const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
                   const TileGrid &tg, float *rgb, float *depth, float *tfinal, bool count_evals,
-                  unsigned long long *counters) {
+                  unsigned long long *counters, int persistent_blocks, unsigned int *queue, int chunk) {
     BlendConsts bc;
     bc.cull_r2 = k.cutoff_d2 * 1.001f + 1e-3f;
     bc.sqrt_half_log2e = sqrtf(0.5f * kLog2e);
@@ -279,13 +331,17 @@ void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, 
     bc.log2_amin = log2f(k.alpha_min);
     bc.alpha_max = k.alpha_max;
     bc.t_min = k.t_min;
-    const dim3 grid((unsigned)tg.n_tiles, (unsigned)n_poses);
-    if (count_evals)
-        hipLaunchKernelGGL(k_blend<true>, grid, dim3(kThreads), 0, s, records, n, pairs, offsets, capacity,
-                           cam.width, cam.height, tg.tiles_x, tg.n_tiles, bc, rgb, depth, tfinal, counters);
-    else
-        hipLaunchKernelGGL(k_blend<false>, grid, dim3(kThreads), 0, s, records, n, pairs, offsets, capacity,
-                           cam.width, cam.height, tg.tiles_x, tg.n_tiles, bc, rgb, depth, tfinal, counters);
+#define GSR_BLEND(C, S)                                                                                              \
+    launch_blend_t<C, S>(s, records, n, n_poses, pairs, offsets, capacity, cam, tg, bc, rgb, depth, tfinal, counters, \
+                         persistent_blocks, queue)
+    if (chunk == 124) {
+        if (count_evals) GSR_BLEND(true, 31); else GSR_BLEND(false, 31);
+    } else if (chunk == 60) {
+        if (count_evals) GSR_BLEND(true, 15); else GSR_BLEND(false, 15);
+    } else {
+        if (count_evals) GSR_BLEND(true, 63); else GSR_BLEND(false, 63);
+    }
+#undef GSR_BLEND
 }
 
 }  // namespace gsr

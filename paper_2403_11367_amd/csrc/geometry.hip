@@ -74,41 +74,58 @@ __global__ __launch_bounds__(kThreads) void k_pack(int64_t n_map, const float *_
     out[3] = make_float4(rgb[src * 3 + 2], 0.f, 0.f, 0.f);
 }
 
-// S1. One thread per Gaussian, looping over a chunk of poses (blockIdx.y), so
-// the packed record is read once per chunk. For each pose the screen record is
+// S1. One thread per Gaussian slot, looping over a chunk of poses (blockIdx.y),
+// so the packed record is read once per chunk (again where the chunk crosses
+// into the next submap of a batch; slot g of a pose whose submap has no
+// Gaussian g is culled). For each pose the screen record is
 // written, the number of tiles its 3-sigma rectangle touches is stored (0 =
 // culled) with the tile rectangle, and each wave packs the (depth bits, record
 // slot = pose * n + index) of its visible Gaussians, in index order, at the
 // front of its 64-slot region of vz / vg, with their number in
 // vcount[pose * n_regions + region]: the input of the per-pose depth sort.
 __global__ __launch_bounds__(kThreads) void k_preprocess(
-    const float4 *__restrict__ packed, int64_t n, const float *__restrict__ poses, int n_poses, Camera cam,
+    const SubmapTable tab, int64_t n, const float *__restrict__ poses, int n_poses, Camera cam,
     Consts k, TileGrid tg, float4 *__restrict__ records, uint32_t *__restrict__ ntiles, uint2 *__restrict__ rect,
     uint32_t *__restrict__ vz, uint32_t *__restrict__ vg, uint32_t *__restrict__ vcount) {
     const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int p0 = blockIdx.y * kPosesPerThread;
     const int p1 = min(p0 + kPosesPerThread, n_poses);
-    const bool in = g < n;
     const int lane = threadIdx.x & 63;
     const int64_t region = g >> 6;  // the same for the whole wave
     const int64_t n_regions = (n + 63) >> 6;
     const bool region_in = (region << 6) < n;
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0, q3 = q0;
-    if (in) {
-        const float4 *src = packed + g * kPackedQuads;
-        q0 = src[0];
-        q1 = src[1];
-        q2 = src[2];
-        q3 = src[3];
-    }
-    const float mx = q0.x, my = q0.y, mz = q0.z;
-    const float s00 = q1.x, s01 = q1.y, s02 = q1.z, s11 = q1.w, s12 = q2.x, s22 = q2.y;
+    // submap of the chunk's first pose (uniform across the block)
+    int q = 0;
+    while (q + 1 < tab.count && p0 >= tab.pose_end[q]) ++q;
+    bool in = false;
+    float4 q0, q1, q2, q3;
+    auto load = [&](int sq) {
+        in = g < tab.n[sq];
+        q0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        q1 = q0;
+        q2 = q0;
+        q3 = q0;
+        if (in) {
+            const float4 *src = tab.packed[sq] + g * kPackedQuads;
+            q0 = src[0];
+            q1 = src[1];
+            q2 = src[2];
+            q3 = src[3];
+        }
+    };
+    load(q);
     // Jacobian clamp limits: 1.3 x tan(half field of view)
     const float lim_x = k.jac_clamp * ((0.5f * (float)cam.width) / cam.fx);
     const float lim_y = k.jac_clamp * ((0.5f * (float)cam.height) / cam.fy);
     const float wmax = (float)(cam.width - 1), hmax = (float)(cam.height - 1);
     for (int p = p0; p < p1; ++p) {
+        if (p >= tab.pose_end[q]) {
+            while (p >= tab.pose_end[q]) ++q;
+            load(q);
+        }
+        const float mx = q0.x, my = q0.y, mz = q0.z;
+        const float s00 = q1.x, s01 = q1.y, s02 = q1.z, s11 = q1.w, s12 = q2.x, s22 = q2.y;
         const float *P = poses + p * 12;  // [R | t] row-major, uniform across the block
         const float R00 = P[0], R01 = P[1], R02 = P[2], T0 = P[3];
         const float R10 = P[4], R11 = P[5], R12 = P[6], T1 = P[7];
@@ -350,12 +367,12 @@ void launch_pack(hipStream_t s, int64_t n_map, const float *means, const float *
 
 int64_t preprocess_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }
 
-void launch_preprocess(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
+void launch_preprocess(hipStream_t s, const SubmapTable &tab, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
                        uint32_t *ntiles, uint2 *rect, uint32_t *vz, uint32_t *vg, uint32_t *vcount) {
     if (n <= 0) return;
     const dim3 grid((unsigned)preprocess_blocks(n), (unsigned)((n_poses + kPosesPerThread - 1) / kPosesPerThread));
-    hipLaunchKernelGGL(k_preprocess, grid, dim3(kThreads), 0, s, packed, n, poses, n_poses, cam, k, tg, records,
+    hipLaunchKernelGGL(k_preprocess, grid, dim3(kThreads), 0, s, tab, n, poses, n_poses, cam, k, tg, records,
                        ntiles, rect, vz, vg, vcount);
 }
 

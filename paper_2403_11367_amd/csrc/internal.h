@@ -60,6 +60,17 @@ struct TileGrid {
 void launch_pack(hipStream_t s, int64_t n_map, const float *means, const float *scales,
                  const float *quats, const float *opacity, const float *rgb, const int64_t *index,
                  int64_t n_sel, float4 *packed, int *flags);
+// The submaps of one render: poses [pose_end[q-1], pose_end[q]) see submap q
+// (n[q] Gaussians, packed records). One entry for an ordinary render; up to
+// kMaxBatchSubmaps for a batch of queries. Record slots are pose * n_slot + g
+// with n_slot = the largest n[q]; slots g >= n[q] of a pose are culled.
+constexpr int kMaxBatchSubmaps = 16;
+struct SubmapTable {
+    int count;
+    int pose_end[kMaxBatchSubmaps];
+    int64_t n[kMaxBatchSubmaps];
+    const float4 *packed[kMaxBatchSubmaps];
+};
 // Blocks of the preprocess grid along the Gaussians.
 int64_t preprocess_blocks(int64_t n);
 // Screen records, tile counts ntiles[p][g] (0 = culled) and tile rectangles
@@ -67,7 +78,7 @@ int64_t preprocess_blocks(int64_t n);
 // region, the (depth bits, record slot p * n + g) of the visible Gaussians
 // packed at the front of the region's slots of vz / vg (P * n each) and their
 // count in vcount[p * ceil(n / 64) + region].
-void launch_preprocess(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
+void launch_preprocess(hipStream_t s, const SubmapTable &tab, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
                        uint32_t *ntiles, uint2 *rect, uint32_t *vz, uint32_t *vg, uint32_t *vcount);
 // Pair emission in front-to-back order. The depth-sorted visible Gaussians
@@ -123,7 +134,9 @@ void launch_bucket(hipStream_t s, const uint16_t *ptile, const uint32_t *pk, con
 void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
                   const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
                   const TileGrid &tg, float *rgb, float *depth, float *tfinal, bool count_evals,
-                  unsigned long long *counters);
+                  unsigned long long *counters, int persistent_blocks, unsigned int *queue, int chunk);
+// Records per compositing chunk the blend is built for (0 = the default, 252).
+bool blend_chunk_supported(int chunk);
 
 // ---- ncc.hip ----
 int ncc_pixels_per_block();

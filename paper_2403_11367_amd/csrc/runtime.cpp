@@ -30,8 +30,12 @@ constexpr int kMaxGroups = 8;
 
 struct gsr_ctx {
     int device = 0;
+    int n_cu = 0;                  // compute units of the device
     hipStream_t stream = nullptr;
     bool profile = false;
+    bool capturing = false;        // between gsr_capture_begin and gsr_capture_end
+    hipStream_t capture_stream = nullptr;
+    unsigned int *d_queue = nullptr;  // work-queue counters of persistent blends, one per pose group
     std::string err;
     // device flags (int32) and counters (uint64)
     int *d_flags = nullptr;
@@ -80,6 +84,12 @@ struct gsr_ctx {
     size_t n_ev_render = 0, n_ev_ncc = 0;
 };
 
+struct gsr_graph {
+    gsr_ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct gsr_submap {
     gsr_ctx *ctx = nullptr;
     int device = 0;
@@ -109,6 +119,9 @@ int hip_fail(gsr_ctx *ctx, hipError_t e, const char *what) {
 // streams of an earlier render may still read the old buffer.
 int ensure(gsr_ctx *ctx, gsr_ctx::Buf &b, size_t bytes, const char *name) {
     if (bytes <= b.bytes) return GSR_OK;
+    if (ctx->capturing)
+        return fail(ctx, GSR_EINVAL, std::string("workspace ") + name +
+                                         " would grow under graph capture; run the same call once before capturing");
     if (b.p) {
         HIPC(ctx, hipDeviceSynchronize());
         HIPC(ctx, hipFree(b.p));
@@ -199,6 +212,8 @@ int gsr_default_cfg(gsr_render_cfg *out) {
     out->flags = 0;
     out->pair_capacity = 0;
     out->pose_groups = 0;
+    out->blend_blocks_per_cu = 0;
+    out->blend_chunk = 0;
     return GSR_OK;
 }
 
@@ -231,6 +246,9 @@ int gsr_create(gsr_ctx **out, int device, void *hip_stream) {
         if (rc != GSR_OK) break;
         if (hipMemset(ctx->d_flags, 0, gsr::FLAG_COUNT * sizeof(int)) != hipSuccess) { rc = GSR_EHIP; break; }
         if (hipMemset(ctx->d_counters, 0, gsr::CNT_COUNT * sizeof(unsigned long long)) != hipSuccess) { rc = GSR_EHIP; break; }
+        if (hipMalloc(&ctx->d_queue, kMaxGroups * sizeof(unsigned int)) != hipSuccess) { rc = GSR_ENOMEM; break; }
+        if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+            ctx->n_cu < 1) { rc = GSR_EHIP; break; }
     } while (0);
     if (rc != GSR_OK) {
         (void)hipGetLastError();
@@ -264,6 +282,7 @@ int gsr_destroy(gsr_ctx *ctx) {
         if (b->p) (void)hipFree(b->p);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     if (ctx->d_counters) (void)hipFree(ctx->d_counters);
+    if (ctx->d_queue) (void)hipFree(ctx->d_queue);
     if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
     if (ctx->h_scores) (void)hipHostFree(ctx->h_scores);
     for (auto &r : ctx->ev_render)
@@ -332,11 +351,13 @@ int gsr_submap_free(gsr_submap *sm) {
 
 int64_t gsr_submap_size(const gsr_submap *sm) { return sm ? sm->n : -1; }
 
-int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const float *poses, int32_t n_poses,
-               const gsr_render_cfg *cfg_in, float *rgb, float *depth, float *tfinal) {
-    if (!ctx) return GSR_EINVAL;
-    if (!sm || !cam || !poses || !rgb || !depth) return fail(ctx, GSR_EINVAL, "null argument");
-    if (sm->ctx != ctx) return fail(ctx, GSR_EINVAL, "submap belongs to another context");
+namespace {
+
+// The render of gsr_render and gsr_render_multi: the poses see the submaps of
+// `tab`; n_slot = the largest submap (record slots pose * n_slot + index).
+int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const gsr_camera *cam, const float *poses,
+                int32_t n_poses, const gsr_render_cfg *cfg_in, float *rgb, float *depth, float *tfinal) {
+    if (!cam || !poses || !rgb || !depth) return fail(ctx, GSR_EINVAL, "null argument");
     if (n_poses < 1 || n_poses > 65535) return fail(ctx, GSR_EINVAL, "pose count out of [1, 65535]");
     if (cam->width < 1 || cam->height < 1 || cam->width > 32768 || cam->height > 32768)
         return fail(ctx, GSR_EINVAL, "image size out of [1, 32768]");
@@ -367,7 +388,7 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     tg.tiles_y = (cam->height + cfg.tile_h - 1) / cfg.tile_h;
     tg.n_tiles = tg.tiles_x * tg.tiles_y;
 
-    const int64_t n = sm->n;
+    const int64_t n = n_slot;
     const int64_t P = n_poses;
     const uint64_t T = (uint64_t)tg.n_tiles;
     const uint64_t n_lists = (uint64_t)P * T;
@@ -381,6 +402,12 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     const uint64_t nvc = std::max<uint64_t>(1, (uint64_t)P * n_regions);  // visible-count entries
     const uint64_t n_rc = gsr::radix_count_elems(n, n_poses);
     const bool exact = cfg.pair_capacity == 0;
+    if (exact && ctx->capturing)
+        return fail(ctx, GSR_EINVAL, "a render under graph capture needs a fixed pair_capacity (no host wait)");
+    if (cfg.blend_blocks_per_cu < 0 || cfg.blend_blocks_per_cu > 64)
+        return fail(ctx, GSR_EINVAL, "blend_blocks_per_cu out of [0, 64]");
+    if (!gsr::blend_chunk_supported(cfg.blend_chunk))
+        return fail(ctx, GSR_EUNSUPPORTED, "blend_chunk must be 0, 252, 124 or 60");
 
     // pose groups: automatic = one. Splitting a render of 64 poses at 1408x376 into
     // 2, 4 or 8 concurrent groups measured 1-13% slower: the ordering of a group
@@ -461,13 +488,13 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     const int64_t hw = (int64_t)cam->width * cam->height;
 
     gsr_ctx::RenderEv *ev = nullptr;
-    if (ctx->profile) {
+    if (ctx->profile && !ctx->capturing) {
         if ((rc = next_events(ctx, ctx->ev_render, ctx->n_ev_render, &ev))) return rc;
         ev->n_groups = G;
         HIPC(ctx, hipEventRecord(ev->e[0], s));
     }
     gsr::launch_fill_u64(s, ctx->d_counters, gsr::CNT_COUNT, 0ull);
-    gsr::launch_preprocess(s, sm->packed, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p, ntiles,
+    gsr::launch_preprocess(s, tab, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p, ntiles,
                            (uint2 *)ctx->rect.p, sort_kb, sort_vb, (uint32_t *)ctx->vcount.p);
     if ((rc = check_launch(ctx, "preprocess"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[1], s));
@@ -505,7 +532,8 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
         gsr::launch_blend(st, records + (uint64_t)gr.p0 * n * gsr::kRecordQuads, n, (int)gr.np,
                           (const uint32_t *)ctx->sk.p + gr.pairs, (const uint64_t *)ctx->offsets.p + gr.off, gr.cap, c,
                           k, tg, rgb + gr.p0 * 3 * hw, depth + gr.p0 * hw, tfinal ? tfinal + gr.p0 * hw : nullptr,
-                          (cfg.flags & GSR_RENDER_COUNT_EVALS) != 0, ctx->d_counters);
+                          (cfg.flags & GSR_RENDER_COUNT_EVALS) != 0, ctx->d_counters,
+                          cfg.blend_blocks_per_cu * ctx->n_cu, ctx->d_queue + g, cfg.blend_chunk);
     };
 
     if (exact) {
@@ -527,7 +555,7 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     // groups) is done; the groups' ordering kernels, which are bound by latency,
     // then run side by side, and a group's compositing overlaps what is left of
     // the others' ordering
-    HIPC(ctx, hipEventRecord(ctx->chain[0], s));
+    if (G > 1) HIPC(ctx, hipEventRecord(ctx->chain[0], s));
     for (int g = 0; g < G; ++g) {
         hipStream_t st = stream_of(g);
         if (g > 0) HIPC(ctx, hipStreamWaitEvent(st, ctx->chain[0], 0));
@@ -551,6 +579,46 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     ctx->last_tiles = tg.n_tiles;
     ctx->last_capacity = exact ? 0 : (uint64_t)cfg.pair_capacity;
     return GSR_OK;
+}
+
+}  // namespace
+
+int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const float *poses, int32_t n_poses,
+               const gsr_render_cfg *cfg, float *rgb, float *depth, float *tfinal) {
+    if (!ctx) return GSR_EINVAL;
+    if (!sm) return fail(ctx, GSR_EINVAL, "null argument");
+    if (sm->ctx != ctx) return fail(ctx, GSR_EINVAL, "submap belongs to another context");
+    gsr::SubmapTable tab{};
+    tab.count = 1;
+    tab.pose_end[0] = n_poses;
+    tab.n[0] = sm->n;
+    tab.packed[0] = sm->packed;
+    return render_impl(ctx, tab, sm->n, cam, poses, n_poses, cfg, rgb, depth, tfinal);
+}
+
+int gsr_render_multi(gsr_ctx *ctx, const gsr_submap *const *submaps, const int32_t *poses_per_submap,
+                     int32_t n_submaps, const gsr_camera *cam, const float *poses, const gsr_render_cfg *cfg, float *rgb,
+                     float *depth, float *tfinal) {
+    if (!ctx) return GSR_EINVAL;
+    if (!submaps || !poses_per_submap) return fail(ctx, GSR_EINVAL, "null argument");
+    if (n_submaps < 1 || n_submaps > gsr::kMaxBatchSubmaps)
+        return fail(ctx, GSR_EINVAL, "submap count out of [1, 16]");
+    gsr::SubmapTable tab{};
+    tab.count = n_submaps;
+    int64_t P = 0, n_slot = 0;
+    for (int q = 0; q < n_submaps; ++q) {
+        const gsr_submap *sm = submaps[q];
+        if (!sm) return fail(ctx, GSR_EINVAL, "null submap");
+        if (sm->ctx != ctx) return fail(ctx, GSR_EINVAL, "submap belongs to another context");
+        if (poses_per_submap[q] < 1) return fail(ctx, GSR_EINVAL, "every submap needs at least one pose");
+        P += poses_per_submap[q];
+        if (P > 65535) return fail(ctx, GSR_EINVAL, "pose count out of [1, 65535]");
+        tab.pose_end[q] = (int)P;
+        tab.n[q] = sm->n;
+        tab.packed[q] = sm->packed;
+        n_slot = std::max<int64_t>(n_slot, sm->n);
+    }
+    return render_impl(ctx, tab, n_slot, cam, poses, (int32_t)P, cfg, rgb, depth, tfinal);
 }
 
 int gsr_ncc(gsr_ctx *ctx, const float *query, const float *renders, int32_t n_poses, int32_t height, int32_t width,
@@ -733,6 +801,63 @@ int gsr_search_pruned(gsr_ctx *ctx, gsr_scorer *scorer, const gsr_submap *sm, co
         }
     *best = b_best;
     *best_score = b_score;
+    return GSR_OK;
+}
+
+int gsr_capture_begin(gsr_ctx *ctx) {
+    if (!ctx) return GSR_EINVAL;
+    if (ctx->capturing) return fail(ctx, GSR_EINVAL, "already capturing");
+    if (!ctx->stream) return fail(ctx, GSR_EINVAL, "graph capture needs a stream other than the null stream");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    HIPC(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
+    ctx->capture_stream = ctx->stream;
+    return GSR_OK;
+}
+
+int gsr_capture_end(gsr_ctx *ctx, gsr_graph **out) {
+    if (!ctx || !out) return GSR_EINVAL;
+    *out = nullptr;
+    if (!ctx->capturing) return fail(ctx, GSR_EINVAL, "not capturing");
+    ctx->capturing = false;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    hipGraph_t graph = nullptr;
+    HIPC(ctx, hipStreamEndCapture(ctx->capture_stream, &graph));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(ctx, e, "hipGraphInstantiate");
+    }
+    gsr_graph *g = new (std::nothrow) gsr_graph;
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return GSR_ENOMEM;
+    }
+    g->ctx = ctx;
+    g->graph = graph;
+    g->exec = exec;
+    *out = g;
+    return GSR_OK;
+}
+
+int gsr_graph_launch(gsr_graph *g) {
+    if (!g) return GSR_EINVAL;
+    gsr_ctx *ctx = g->ctx;
+    if (ctx->capturing) return fail(ctx, GSR_EINVAL, "cannot launch a graph while capturing");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    HIPC(ctx, hipGraphLaunch(g->exec, ctx->stream));
+    return GSR_OK;
+}
+
+int gsr_graph_destroy(gsr_graph *g) {
+    if (!g) return GSR_EINVAL;
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
     return GSR_OK;
 }
 

@@ -28,7 +28,8 @@ RENDER_COUNT_EVALS = 1
 # every symbol declared in include/gsr.h and include/gsr_scorer.h
 EXPORTS = [
     "gsr_create", "gsr_destroy", "gsr_set_stream", "gsr_set_profiling", "gsr_default_cfg",
-    "gsr_submap_load", "gsr_submap_free", "gsr_submap_size", "gsr_render", "gsr_ncc", "gsr_topk", "gsr_search",
+    "gsr_submap_load", "gsr_submap_free", "gsr_submap_size", "gsr_render", "gsr_render_multi", "gsr_ncc",
+    "gsr_topk", "gsr_search", "gsr_capture_begin", "gsr_capture_end", "gsr_graph_launch", "gsr_graph_destroy",
     "gsr_sync", "gsr_get_stats", "gsr_debug_size", "gsr_debug_copy", "gsr_crop",
     "gsr_status_string", "gsr_last_error",
     "gsr_scorer_param_count", "gsr_scorer_create", "gsr_scorer_destroy", "gsr_scorer_set_params",
@@ -52,7 +53,8 @@ class RenderCfg(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("eps_dilate", C.c_float),
                 ("z_near", C.c_float), ("jac_clamp", C.c_float), ("cutoff_d2", C.c_float),
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float),
-                ("flags", C.c_int32), ("pair_capacity", C.c_int64), ("pose_groups", C.c_int32)]
+                ("flags", C.c_int32), ("pair_capacity", C.c_int64), ("pose_groups", C.c_int32),
+                ("blend_blocks_per_cu", C.c_int32), ("blend_chunk", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -88,6 +90,11 @@ def _load() -> C.CDLL:
         "gsr_submap_free": (I, [P]),
         "gsr_submap_size": (I64, [P]),
         "gsr_render": (I, [P, P, C.POINTER(CameraC), P, I32, C.POINTER(RenderCfg), P, P, P]),
+        "gsr_render_multi": (I, [P, P, P, I32, C.POINTER(CameraC), P, C.POINTER(RenderCfg), P, P, P]),
+        "gsr_capture_begin": (I, [P]),
+        "gsr_capture_end": (I, [P, C.POINTER(P)]),
+        "gsr_graph_launch": (I, [P]),
+        "gsr_graph_destroy": (I, [P]),
         "gsr_ncc": (I, [P, P, P, I32, I32, I32, P]),
         "gsr_topk": (I, [P, P, I32, I32, P]),
         "gsr_search": (I, [P, P, C.POINTER(CameraC), P, I32, P, I32, I32, F, P, C.POINTER(RenderCfg), P,
@@ -198,6 +205,30 @@ class Submap:
             pass
 
 
+class Graph:
+    """A captured sequence of library calls (gsr_graph); launch() replays it on the
+    context's current torch stream."""
+
+    def __init__(self, ctx: "Context", handle: C.c_void_p):
+        self.ctx = ctx
+        self.handle = handle
+
+    def launch(self):
+        self.ctx._bind_stream()
+        self.ctx._check(LIB.gsr_graph_launch(self.handle), "gsr_graph_launch")
+
+    def close(self):
+        if self.handle:
+            LIB.gsr_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """One GPU context; every call enqueues on the current torch stream of its device."""
 
@@ -209,7 +240,7 @@ class Context:
         rc = LIB.gsr_create(C.byref(self.handle), self.device, C.c_void_p(stream))
         if rc != GSR_OK:
             raise GsrError(rc, "gsr_create")
-        self._scorers = weakref.WeakSet()  # destroyed before the context
+        self._children = weakref.WeakSet()  # scorers and graphs: destroyed before the context
 
     def _check(self, rc: int, what: str):
         if rc != GSR_OK:
@@ -222,8 +253,8 @@ class Context:
 
     def close(self):
         if self.handle:
-            for sc in list(getattr(self, "_scorers", ())):
-                sc.close()
+            for child in list(getattr(self, "_children", ())):
+                child.close()
             LIB.gsr_destroy(self.handle)
             self.handle = C.c_void_p()
 
@@ -288,6 +319,51 @@ class Context:
                             tfinal.data_ptr() if tfinal is not None else None)
         self._check(rc, "gsr_render")
         return (rgb, depth, tfinal) if tfinal is not None else (rgb, depth)
+
+    def render_multi(self, submaps: Sequence[Submap], poses_per_submap: Sequence[int], camera: Camera, poses,
+                     cfg: Optional[RenderCfg] = None, rgb=None, depth=None, tfinal=None, with_tfinal: bool = False):
+        """One render of several queries (gsr_render_multi): submap q at poses_per_submap[q]
+        consecutive poses of `poses`. Same outputs as gsr_render per submap."""
+        torch = _torch()
+        P = poses.shape[0]
+        counts = np.ascontiguousarray(poses_per_submap, dtype=np.int32)
+        if counts.ndim != 1 or counts.size != len(submaps) or int(counts.sum()) != P:
+            raise ValueError("poses_per_submap must give one count per submap, summing to the pose count")
+        _dev_f32(poses, "poses", (P, 3, 4))
+        H, W = camera.height, camera.width
+        dev = poses.device
+        if rgb is None:
+            rgb = torch.empty((P, 3, H, W), dtype=torch.float32, device=dev)
+        if depth is None:
+            depth = torch.empty((P, H, W), dtype=torch.float32, device=dev)
+        if with_tfinal and tfinal is None:
+            tfinal = torch.empty((P, H, W), dtype=torch.float32, device=dev)
+        _dev_f32(rgb, "rgb", (P, 3, H, W))
+        _dev_f32(depth, "depth", (P, H, W))
+        if tfinal is not None:
+            _dev_f32(tfinal, "tfinal", (P, H, W))
+        handles = (C.c_void_p * len(submaps))(*[sm.handle.value if isinstance(sm.handle, C.c_void_p) else sm.handle
+                                                for sm in submaps])
+        self._bind_stream()
+        cam = camera.c()
+        rc = LIB.gsr_render_multi(self.handle, handles, counts.ctypes.data, len(submaps), C.byref(cam),
+                                  poses.data_ptr(), C.byref(cfg) if cfg is not None else None, rgb.data_ptr(),
+                                  depth.data_ptr(), tfinal.data_ptr() if tfinal is not None else None)
+        self._check(rc, "gsr_render_multi")
+        return (rgb, depth, tfinal) if tfinal is not None else (rgb, depth)
+
+    def capture_begin(self):
+        """Start recording this context's calls into a HIP graph (gsr_capture_begin).
+        The current torch stream must not be the default stream."""
+        self._bind_stream()
+        self._check(LIB.gsr_capture_begin(self.handle), "gsr_capture_begin")
+
+    def capture_end(self) -> "Graph":
+        g = C.c_void_p()
+        self._check(LIB.gsr_capture_end(self.handle, C.byref(g)), "gsr_capture_end")
+        graph = Graph(self, g)
+        self._children.add(graph)
+        return graph
 
     def ncc(self, query, renders, scores=None):
         torch = _torch()
@@ -414,7 +490,7 @@ class Scorer:
         ctx._check(LIB.gsr_scorer_create(ctx.handle, self.height, self.width, self.max_batch,
                                          C.byref(self.handle)), "gsr_scorer_create")
         self.n_params = int(LIB.gsr_scorer_param_count())
-        ctx._scorers.add(self)
+        ctx._children.add(self)
 
     def close(self):
         if self.handle:

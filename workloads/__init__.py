@@ -343,3 +343,37 @@ def scorer_query_seed(map_seed: int, i: int) -> int:
 def low_res_camera(cam: Camera, f: int) -> Camera:
     """The camera with its image reduced f times (focal lengths and principal point / f)."""
     return Camera(cam.width // f, cam.height // f, cam.fx / f, cam.fy / f, cam.cx / f, cam.cy / f)
+
+
+# ---- batched queries: 8 corridor maps of uneven size, 32 candidates each ----
+BATCH_MAP_SEEDS = tuple(range(200, 208))
+BATCH_DX = [-1.5, -0.5, 0.5, 1.5]
+BATCH_DYAW = [-2.5, 2.5]
+
+
+@dataclasses.dataclass
+class BatchQuery:
+    seed: int
+    n: int                # Gaussians of the map
+    gaussians: Gaussians
+    poses: np.ndarray     # [32, 3, 4] float32
+    hidden: np.ndarray    # [3, 4] float32
+    noise: np.ndarray     # [3, H, W] float32
+
+
+def batch_query(seed: int, cam: Camera) -> BatchQuery:
+    """One query of the batched workload: a corridor map (config-1 layout) of
+    N = round(exp(U(ln 2e5, ln 2e6))) Gaussians (drawn from seed * 10), its own
+    map seed, the prior of config 1 at (100, 0, 1.5) looking along +x, candidates
+    4 dx x 4 dy x 2 dyaw (BATCH_* steps), hidden pose uniform over the grid's
+    extent (seed * 10 + 1), query noise N(0, 0.02) (seed * 10 + 2)."""
+    n = int(round(np.exp(np.random.default_rng(seed * 10).uniform(np.log(2e5), np.log(2e6)))))
+    g = corridor_map(n, seed=seed)
+    center = np.array([100.0, 0.0, 1.5])
+    poses = yaw_grid_poses(center, AXES_ALONG_X, BATCH_DX, BATCH_DX, BATCH_DYAW)
+    hr = np.random.default_rng(seed * 10 + 1)
+    hdx, hdy = hr.uniform(BATCH_DX[0], BATCH_DX[-1], 2)
+    hyaw = hr.uniform(BATCH_DYAW[0], BATCH_DYAW[-1])
+    hidden = _f32(pose_from_center(center + np.array([hdx, hdy, 0.0]), AXES_ALONG_X, np.deg2rad(hyaw)))
+    noise = _f32(np.random.default_rng(seed * 10 + 2).normal(0.0, 0.02, size=(3, cam.height, cam.width)))
+    return BatchQuery(seed, n, g, poses, hidden, noise)
