@@ -130,6 +130,8 @@ typedef struct {
     float ms_ncc;            /* whole gsr_ncc */
     float ms_render;         /* whole gsr_render, first launch to the join */
     int32_t n_groups;        /* pose groups of the last render */
+    int64_t render_serial;   /* renders made on this context so far (gsr_render_backward
+                              * differentiates the latest) */
 } gsr_stats;
 
 /* Create a context on GPU `device`, enqueueing on `hip_stream` (a hipStream_t;
@@ -177,6 +179,27 @@ int64_t gsr_submap_size(const gsr_submap *sm);
 int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const float *poses_dev,
                int32_t n_poses, const gsr_render_cfg *cfg, float *rgb_dev, float *depth_dev,
                float *tfinal_dev);
+
+/* Gradient of a loss through the most recent render of this context, given the
+ * gradients of its images (Sec. III-A, Eq. 1-5, differentiated; the map-training
+ * side of the paper). That render must be a gsr_render of `sm` at these poses, with
+ * no render and no reload of sm since; sm must be loaded without an index, so that
+ * submap entry g is input Gaussian g. The contributing set of every pixel (support
+ * cutoff, alpha floor, stop after t_min) is taken as fixed; where alpha is clamped at
+ * alpha_max it is constant. Per-pixel transmittance is recomputed front to back
+ * with the forward's arithmetic, not stored.
+ *   scales_dev [n,3], quats_dev [n,4]: the arrays sm was loaded from
+ *   poses_dev  [P,3,4]: the render's poses
+ *   rgb_dev, depth_dev: the render's images [P,3,H,W], [P,H,W]
+ *   grad_rgb_dev, grad_depth_dev: dL/d images, same shapes
+ *   outputs dL/d means [n,3], scales [n,3] (linear), quats [n,4] (raw, before
+ *   normalisation), opacity [n] (after the sigmoid), rgb [n,3].
+ * Gradients are summed with float atomics across pixels: the last bits vary from
+ * run to run. */
+int gsr_render_backward(gsr_ctx *ctx, const gsr_submap *sm, const float *scales_dev, const float *quats_dev,
+                        const float *poses_dev, int32_t n_poses, const float *rgb_dev, const float *depth_dev,
+                        const float *grad_rgb_dev, const float *grad_depth_dev, float *grad_means_dev,
+                        float *grad_scales_dev, float *grad_quats_dev, float *grad_opacity_dev, float *grad_rgb_out_dev);
 
 /* A batch of queries in one render: submap q is rendered at poses_per_submap[q]
  * consecutive poses (Sec. III-C1 for several queries at once, each with its own

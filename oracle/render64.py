@@ -29,8 +29,12 @@ CUTOFF = 9.0
 ALPHA_MIN = float(np.float32(1.0 / 255.0))
 ALPHA_MAX = 0.99
 T_MIN = 1e-4
-# decision margins within which a float32 evaluation may flip (relative / absolute)
-M_D2 = 1e-4        # |d^2 - cutoff| / cutoff
+# decision margins within which a float32 evaluation may flip (relative / absolute).
+# The float32 conic carries a relative error of about 6e-8 times the condition
+# number of the screen covariance; footprints worse conditioned than 1 / M_COND are
+# flagged, and for the rest d^2 is good to well within M_D2.
+M_COND = 1.0 / 300.0  # flag det < M_COND a c
+M_D2 = 2e-5        # |d^2 - cutoff| / cutoff
 M_ALPHA = 1e-5     # |alpha - alpha_min| / alpha_min, |o G - alpha_max| / alpha_max
 M_T = 1e-6         # |T - t_min| / t_min
 M_RECT = 1e-4      # pixel centre within this of the 3-sigma rectangle edge (pixels)
@@ -82,6 +86,7 @@ class Screen:
     rgb: np.ndarray      # [N, 3]
     rect: np.ndarray     # [N, 4] (x_lo, x_hi, y_lo, y_hi) support box in pixel-centre coordinates
     margin: np.ndarray   # [N] bool: a culling decision is within its margin
+    cond: np.ndarray     # [N] a c / det of the screen covariance (>= 1)
 
 
 def project(p: Params, pose, cam) -> Screen:
@@ -113,9 +118,11 @@ def project(p: Params, pose, cam) -> Screen:
     rect = np.stack([u - rx, u + rx, v - ry, v + ry], 1)
     margin = np.abs(tz - Z_NEAR) < 1e-6 * Z_NEAR
     with np.errstate(invalid="ignore"):
-        margin |= np.abs(det) < 1e-6 * np.abs(a * c)
+        margin |= det < M_COND * np.abs(a * c)
     op = 1.0 / (1.0 + np.exp(-p.logits))
-    return Screen(vis, u, v, tz, conic, op, p.rgb, rect, margin)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        cond = np.where(det > 0, a * c / det, np.inf)
+    return Screen(vis, u, v, tz, conic, op, p.rgb, rect, margin, cond)
 
 
 def _pixel(scr: Screen, cand: np.ndarray, px: float, py: float):
@@ -130,7 +137,9 @@ def _pixel(scr: Screen, cand: np.ndarray, px: float, py: float):
     g = scr.opacity[order] * np.exp(-0.5 * d2)
     alpha = np.minimum(ALPHA_MAX, g)
     take = (d2 <= CUTOFF) & (alpha >= ALPHA_MIN)
-    margin = bool(np.any(np.abs(d2 - CUTOFF) < M_D2 * CUTOFF)
+    # float32 d^2 is good to about 2e-7 a c / det (relative); never less than M_D2
+    m_d2 = CUTOFF * np.maximum(M_D2, 2e-7 * scr.cond[order])
+    margin = bool(np.any(np.abs(d2 - CUTOFF) < m_d2)
                   | np.any(take & (np.abs(alpha - ALPHA_MIN) < M_ALPHA * ALPHA_MIN))
                   | np.any(take & (np.abs(g - ALPHA_MAX) < M_ALPHA * ALPHA_MAX)))
     a = np.where(take, alpha, 0.0)

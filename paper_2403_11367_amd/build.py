@@ -34,6 +34,7 @@ SOURCES = [
     ("geometry.hip", "hip", STRICT_FP),
     ("sort.hip", "hip", []),
     ("blend.hip", "hip", []),
+    ("backward.hip", "hip", []),
     ("ncc.hip", "hip", []),
     ("scorer.hip", "hip", []),
     ("scorer_rt.cpp", "hip", ["-x", "hip"]),

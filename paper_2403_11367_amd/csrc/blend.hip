@@ -20,7 +20,7 @@
 // longest of the four walks rather than their union. Each pixel still sees its
 // records in list order. A wave stops when all of its pixels have stopped; the
 // block stops loading when all waves have.
-#include "internal.h"
+#include "blend_common.h"
 
 namespace gsr {
 
@@ -30,16 +30,6 @@ constexpr int kThreads = 256;
 // Records staged per wave and chunk: 63 (lane 63 idle; a chunk of 252), 31 or 15
 // (chunks of 124 or 60, for earlier exits on short lists). A template parameter.
 constexpr int kDummy = 255;             // LDS slot (wave 3, lane 63) of a record that never contributes
-constexpr float kLog2e = 1.4426950408889634f;
-
-struct BlendConsts {
-    float cull_r2;         // cutoff with a margin, for the (band, quarter) overlap test
-    float sqrt_half_log2e;  // sqrt(log2(e)/2): scales the conic factors
-    float cut_p2;          // -log2(e)/2 * cutoff_d2
-    float log2_amin;       // log2(alpha_min)
-    float alpha_max;
-    float t_min;
-};
 
 // The compositing of one (tile, pose) by the whole block.
 template <bool kCount, int kStage>
@@ -101,23 +91,11 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             // peak or the chord at the nearer band edge. R2 carries a margin that
             // covers float32 rounding, so the test never drops a contributing cell.
             const float A = q0.z, B = q0.w, C = q1.x;
-            // products of floats are exact in double, so det keeps its accuracy for
-            // thin, tilted ellipses where A C and B^2 nearly cancel
-            const float det = (float)((double)A * (double)C - (double)B * (double)B);
-            // d^2 = A dx^2 + 2 B dx dy + C dy^2 = (m11 dx + m12 dy)^2 + (m22 dy)^2 with
-            // m11 = sqrt(A), m12 = B / m11, m22 = sqrt(det / A): a sum of squares, so a
-            // needle-thin footprint loses about sqrt(A C / det) times less to rounding
-            // than the expanded form. Scaled by sqrt(log2(e) / 2), the exponent of
-            // o exp(-d^2 / 2) in base 2 is log2(o) - t1^2 - t2^2.
+            // d^2 as a sum of squares (stage_record): a needle-thin footprint loses
+            // about sqrt(A C / det) times less to rounding than the expanded form
+            const float det = conic_det(A, B, C);
             const float iA = __builtin_amdgcn_rcpf(A), idet = __builtin_amdgcn_rcpf(det);
-            const float m11 = sqrtf(A);
-            const float m12 = B / m11;
-            const float m22 = sqrtf(fmaxf(det, 0.f) / A);  // 0: the limit of a degenerate streak
-            const float lo = __log2f(q1.y);
-            const float thr = fmaxf(k.cut_p2 + lo, k.log2_amin);
-            s_rec[tid * 3 + 0] = make_float4(q0.x, q0.y, m11 * k.sqrt_half_log2e, m12 * k.sqrt_half_log2e);
-            s_rec[tid * 3 + 1] = make_float4(m22 * k.sqrt_half_log2e, thr, lo, q2.y);
-            s_rec[tid * 3 + 2] = make_float4(q1.z, q1.w, q2.x, 0.f);
+            stage_record(q0, q1, q2, det, k, s_rec[tid * 3 + 0], s_rec[tid * 3 + 1], s_rec[tid * 3 + 2]);
             const float R2 = k.cull_r2;
             // hardware reciprocal and square root (about 1 ulp) for the overlap test:
             // the margin in R2 covers them
@@ -195,9 +173,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             };
             // one step on a staged record; false when the wave is done with the chunk
             auto step = [&](uint32_t o, const float4 &ra, const float4 &rb) -> bool {
-                const float dx = px - ra.x, dy = py - ra.y;
-                const float t1 = ra.z * dx + ra.w * dy, t2 = rb.x * dy;
-                const float p2 = (rb.z - t1 * t1) - t2 * t2;
+                const float p2 = footprint_p2(ra, rb, px, py);
                 const bool ok = __builtin_amdgcn_inverse_ballot_w64(lm) && p2 >= rb.y;
                 if (kCount) {
                     n_contrib += ok;
@@ -207,10 +183,10 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                     const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
                     const float al = fminf(k.alpha_max, __builtin_amdgcn_exp2f(p2));
                     const float w = al * T;
-                    cr += c.x * w;
-                    cg += c.y * w;
-                    cb += c.z * w;
-                    dep += rb.w * w;
+                    cr = __builtin_fmaf(c.x, w, cr);
+                    cg = __builtin_fmaf(c.y, w, cg);
+                    cb = __builtin_fmaf(c.z, w, cb);
+                    dep = __builtin_fmaf(rb.w, w, dep);
                     T -= w;
                 }
                 const uint64_t lm_next = __ballot(!(T < k.t_min));
@@ -324,13 +300,7 @@ void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, 
                   const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
                   const TileGrid &tg, float *rgb, float *depth, float *tfinal, bool count_evals,
                   unsigned long long *counters, int persistent_blocks, unsigned int *queue, int chunk) {
-    BlendConsts bc;
-    bc.cull_r2 = k.cutoff_d2 * 1.001f + 1e-3f;
-    bc.sqrt_half_log2e = sqrtf(0.5f * kLog2e);
-    bc.cut_p2 = -0.5f * kLog2e * k.cutoff_d2;
-    bc.log2_amin = log2f(k.alpha_min);
-    bc.alpha_max = k.alpha_max;
-    bc.t_min = k.t_min;
+    const BlendConsts bc = blend_consts(k);
 #define GSR_BLEND(C, S)                                                                                              \
     launch_blend_t<C, S>(s, records, n, n_poses, pairs, offsets, capacity, cam, tg, bc, rgb, depth, tfinal, counters, \
                          persistent_blocks, queue)

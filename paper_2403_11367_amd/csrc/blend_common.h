@@ -1,0 +1,65 @@
+// Compositing arithmetic shared by the forward blend and its backward: the
+// staged form of a screen record and the footprint exponent, written with
+// explicit fused multiply-adds so that both kernels make the same decisions
+// and compute the same transmittance, bit for bit.
+#pragma once
+
+#include "internal.h"
+
+namespace gsr {
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+struct BlendConsts {
+    float cull_r2;          // cutoff with a margin, for the (band, quarter) overlap test
+    float sqrt_half_log2e;  // sqrt(log2(e)/2): scales the conic factors
+    float cut_p2;           // -log2(e)/2 * cutoff_d2
+    float log2_amin;        // log2(alpha_min)
+    float alpha_max;
+    float t_min;
+};
+
+inline BlendConsts blend_consts(const Consts &k) {
+    BlendConsts bc;
+    bc.cull_r2 = k.cutoff_d2 * 1.001f + 1e-3f;
+    bc.sqrt_half_log2e = sqrtf(0.5f * kLog2e);
+    bc.cut_p2 = -0.5f * kLog2e * k.cutoff_d2;
+    bc.log2_amin = log2f(k.alpha_min);
+    bc.alpha_max = k.alpha_max;
+    bc.t_min = k.t_min;
+    return bc;
+}
+
+// det of the conic [[A, B], [B, C]]: products of floats are exact in double, so
+// det keeps its accuracy for thin, tilted ellipses where A C and B^2 nearly cancel
+__device__ __forceinline__ float conic_det(float A, float B, float C) {
+    return (float)((double)A * (double)C - (double)B * (double)B);
+}
+
+// Staged record of screen record (q0, q1, q2) (see internal.h):
+//   s0 = (u, v, m11', m12'), s1 = (m22', threshold, log2 o, z), s2 = (r, g, b, 0)
+// with d^2 = (m11 dx + m12 dy)^2 + (m22 dy)^2, m11 = sqrt(A), m12 = B / m11,
+// m22 = sqrt(det / A), each scaled by sqrt(log2(e)/2); the exponent of
+// o exp(-d^2/2) in base 2 is then log2(o) - t1^2 - t2^2, and a pair contributes
+// when it is >= threshold = max(log2(o) - log2(e) cutoff / 2, log2(alpha_min)).
+__device__ __forceinline__ void stage_record(const float4 &q0, const float4 &q1, const float4 &q2, float det,
+                                             const BlendConsts &k, float4 &s0, float4 &s1, float4 &s2) {
+    const float A = q0.z, B = q0.w;
+    const float m11 = sqrtf(A);
+    const float m12 = B / m11;
+    const float m22 = sqrtf(fmaxf(det, 0.f) / A);  // 0: the limit of a degenerate streak
+    const float lo = __log2f(q1.y);
+    const float thr = fmaxf(k.cut_p2 + lo, k.log2_amin);
+    s0 = make_float4(q0.x, q0.y, m11 * k.sqrt_half_log2e, m12 * k.sqrt_half_log2e);
+    s1 = make_float4(m22 * k.sqrt_half_log2e, thr, lo, q2.y);
+    s2 = make_float4(q1.z, q1.w, q2.x, 0.f);
+}
+
+// Base-2 exponent of the footprint of staged record (s0, s1) at pixel centre (px, py).
+__device__ __forceinline__ float footprint_p2(const float4 &s0, const float4 &s1, float px, float py) {
+    const float dx = px - s0.x, dy = py - s0.y;
+    const float t1 = __builtin_fmaf(s0.z, dx, s0.w * dy), t2 = s1.x * dy;
+    return __builtin_fmaf(-t2, t2, __builtin_fmaf(-t1, t1, s1.z));
+}
+
+}  // namespace gsr

@@ -147,6 +147,23 @@ void launch_topk(hipStream_t s, const float *scores, int n, int k, int32_t *idx)
 void launch_gather_poses(hipStream_t s, const float *poses, const int32_t *order, int nb, float *out);
 void launch_scatter_scores(hipStream_t s, const float *batch_scores, const int32_t *order, int nb, float *scores);
 
+// ---- backward.hip ----
+// Gradients per (pose, Gaussian) in screen space (u, v, A, B, C, opacity, r, g, b,
+// z) and per (pose, Gaussian) in parameter space (mean 3, covariance entries 6,
+// opacity, r, g, b).
+int screen_grads_per_gaussian();
+int pose_grads_per_gaussian();
+void launch_blend_backward(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
+                           const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
+                           const TileGrid &tg, const float *img_rgb, const float *img_depth, const float *g_rgb,
+                           const float *g_depth, float *gscreen);
+void launch_project_backward(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
+                             const Camera &cam, const Consts &k, const uint32_t *ntiles, const float *gscreen,
+                             float *gpose);
+void launch_param_grads(hipStream_t s, const float *gpose, int64_t n, int n_poses, const float *scales,
+                        const float *quats, float *g_means, float *g_scales, float *g_quats, float *g_opacity,
+                        float *g_rgb);
+
 // ---- scorer.hip ----
 constexpr int kScorerLayers = 5;
 constexpr int kScorerChannels[kScorerLayers + 1] = {2, 32, 64, 64, 128, 128};

@@ -54,7 +54,7 @@ struct gsr_ctx {
         size_t bytes = 0;
     } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, esum, pseg, scan_tmp,
         ptile, pk, sk, cnt, total, block_base, offsets, grey_q, partials, s_order, s_poses, s_rgb, s_depth,
-        s_scores, pr_grey, pr_q3, pr_x, pr_rgb, pr_depth;
+        s_scores, pr_grey, pr_q3, pr_x, pr_rgb, pr_depth, bw_screen, bw_pose;
     // layout of the last render's pose groups
     struct Group {
         int64_t p0 = 0, np = 0;        // poses [p0, p0 + np)
@@ -68,6 +68,13 @@ struct gsr_ctx {
     Group groups[kMaxGroups];
     int n_groups = 0;
     int64_t last_n = 0, last_poses = 0, last_tiles = 0;
+    // what the backward needs of the last render
+    int64_t render_serial = 0;
+    const gsr_submap *last_sm = nullptr;  // single-submap render, else null
+    uint64_t last_sm_version = 0;
+    gsr::Camera last_cam{};
+    gsr::Consts last_consts{};
+    gsr::TileGrid last_tg{};
     uint64_t last_capacity = 0;  // per group
     // profiling: event sets of the renders / NCC calls profiled since the last gsr_get_stats
     struct RenderEv {
@@ -93,6 +100,8 @@ struct gsr_graph {
 struct gsr_submap {
     gsr_ctx *ctx = nullptr;
     int device = 0;
+    bool identity = false;  // loaded without an index: entry g is input Gaussian g
+    uint64_t version = 0;   // counts loads (a refill in place changes it)
     int64_t n = 0, cap = 0;
     float4 *packed = nullptr;  // [cap * kPackedQuads]
 };
@@ -336,6 +345,8 @@ int gsr_submap_load(gsr_ctx *ctx, int64_t n_map, const float *means, const float
         *out = sm;
     }
     sm->n = n_sel;
+    sm->identity = index == nullptr;
+    sm->version++;
     gsr::launch_pack(ctx->stream, n_map, means, scales, quats, opacity, rgb, index, n_sel, sm->packed, ctx->d_flags);
     return check_launch(ctx, "pack");
 }
@@ -356,7 +367,8 @@ namespace {
 // The render of gsr_render and gsr_render_multi: the poses see the submaps of
 // `tab`; n_slot = the largest submap (record slots pose * n_slot + index).
 int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const gsr_camera *cam, const float *poses,
-                int32_t n_poses, const gsr_render_cfg *cfg_in, float *rgb, float *depth, float *tfinal) {
+                int32_t n_poses, const gsr_render_cfg *cfg_in, float *rgb, float *depth, float *tfinal,
+                const gsr_submap *last_sm_hint) {
     if (!cam || !poses || !rgb || !depth) return fail(ctx, GSR_EINVAL, "null argument");
     if (n_poses < 1 || n_poses > 65535) return fail(ctx, GSR_EINVAL, "pose count out of [1, 65535]");
     if (cam->width < 1 || cam->height < 1 || cam->width > 32768 || cam->height > 32768)
@@ -578,6 +590,12 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
     ctx->last_poses = P;
     ctx->last_tiles = tg.n_tiles;
     ctx->last_capacity = exact ? 0 : (uint64_t)cfg.pair_capacity;
+    ctx->render_serial++;
+    ctx->last_sm = tab.count == 1 ? last_sm_hint : nullptr;
+    ctx->last_sm_version = last_sm_hint ? last_sm_hint->version : 0;
+    ctx->last_cam = c;
+    ctx->last_consts = k;
+    ctx->last_tg = tg;
     return GSR_OK;
 }
 
@@ -593,7 +611,52 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     tab.pose_end[0] = n_poses;
     tab.n[0] = sm->n;
     tab.packed[0] = sm->packed;
-    return render_impl(ctx, tab, sm->n, cam, poses, n_poses, cfg, rgb, depth, tfinal);
+    return render_impl(ctx, tab, sm->n, cam, poses, n_poses, cfg, rgb, depth, tfinal, sm);
+}
+
+int gsr_render_backward(gsr_ctx *ctx, const gsr_submap *sm, const float *scales, const float *quats,
+                        const float *poses, int32_t n_poses, const float *rgb, const float *depth,
+                        const float *grad_rgb, const float *grad_depth, float *g_means, float *g_scales,
+                        float *g_quats, float *g_opacity, float *g_rgb) {
+    if (!ctx) return GSR_EINVAL;
+    if (!sm || !scales || !quats || !poses || !rgb || !depth || !grad_rgb || !grad_depth || !g_means || !g_scales ||
+        !g_quats || !g_opacity || !g_rgb)
+        return fail(ctx, GSR_EINVAL, "null argument");
+    if (ctx->capturing) return fail(ctx, GSR_EINVAL, "the backward is not captured");
+    if (!sm->identity) return fail(ctx, GSR_EINVAL, "the submap must be loaded without an index");
+    if (ctx->last_sm != sm || ctx->last_sm_version != sm->version || ctx->last_poses != n_poses ||
+        ctx->last_n != sm->n)
+        return fail(ctx, GSR_EINVAL, "the last render of this context is not a render of this submap at these poses");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    const int64_t n = sm->n, P = n_poses;
+    const uint64_t pn = (uint64_t)std::max<int64_t>(1, P * n);
+    const int ns = gsr::screen_grads_per_gaussian(), np = gsr::pose_grads_per_gaussian();
+    int rc;
+    if ((rc = ensure(ctx, ctx->bw_screen, pn * ns * sizeof(float), "screen-space gradients")) ||
+        (rc = ensure(ctx, ctx->bw_pose, pn * np * sizeof(float), "per-pose gradients")))
+        return rc;
+    hipStream_t s = ctx->stream;
+    const gsr::TileGrid &tg = ctx->last_tg;
+    const uint64_t T = (uint64_t)tg.n_tiles;
+    const int64_t hw = (int64_t)ctx->last_cam.width * ctx->last_cam.height;
+    float *gscreen = (float *)ctx->bw_screen.p;
+    gsr::launch_fill_u32(s, (uint32_t *)gscreen, (uint64_t)P * n * ns, 0u);
+    const float4 *records = (const float4 *)ctx->records.p;
+    for (int g = 0; g < ctx->n_groups; ++g) {
+        const gsr_ctx::Group &gr = ctx->groups[g];
+        if (gr.np <= 0) continue;
+        gsr::launch_blend_backward(s, records + (uint64_t)gr.p0 * n * gsr::kRecordQuads, n, (int)gr.np,
+                                   (const uint32_t *)ctx->sk.p + gr.pairs, (const uint64_t *)ctx->offsets.p + gr.off,
+                                   gr.cap, ctx->last_cam, ctx->last_consts, tg, rgb + gr.p0 * 3 * hw,
+                                   depth + gr.p0 * hw, grad_rgb + gr.p0 * 3 * hw, grad_depth + gr.p0 * hw,
+                                   gscreen + (uint64_t)gr.p0 * n * ns);
+    }
+    (void)T;
+    gsr::launch_project_backward(s, sm->packed, n, poses, n_poses, ctx->last_cam, ctx->last_consts,
+                                 (const uint32_t *)ctx->ntiles.p, gscreen, (float *)ctx->bw_pose.p);
+    gsr::launch_param_grads(s, (const float *)ctx->bw_pose.p, n, n_poses, scales, quats, g_means, g_scales, g_quats,
+                            g_opacity, g_rgb);
+    return check_launch(ctx, "render backward");
 }
 
 int gsr_render_multi(gsr_ctx *ctx, const gsr_submap *const *submaps, const int32_t *poses_per_submap,
@@ -618,7 +681,7 @@ int gsr_render_multi(gsr_ctx *ctx, const gsr_submap *const *submaps, const int32
         tab.packed[q] = sm->packed;
         n_slot = std::max<int64_t>(n_slot, sm->n);
     }
-    return render_impl(ctx, tab, n_slot, cam, poses, (int32_t)P, cfg, rgb, depth, tfinal);
+    return render_impl(ctx, tab, n_slot, cam, poses, (int32_t)P, cfg, rgb, depth, tfinal, nullptr);
 }
 
 int gsr_ncc(gsr_ctx *ctx, const float *query, const float *renders, int32_t n_poses, int32_t height, int32_t width,
@@ -888,6 +951,7 @@ int gsr_get_stats(gsr_ctx *ctx, gsr_stats *out) {
     out->n_poses = ctx->last_poses;
     out->pair_capacity = (int64_t)ctx->last_capacity;
     out->n_groups = ctx->n_groups;
+    out->render_serial = ctx->render_serial;
     if (ctx->last_poses > 0) {
         for (int g = 0; g < ctx->n_groups; ++g) {
             const gsr_ctx::Group &gr = ctx->groups[g];

@@ -28,7 +28,8 @@ RENDER_COUNT_EVALS = 1
 # every symbol declared in include/gsr.h and include/gsr_scorer.h
 EXPORTS = [
     "gsr_create", "gsr_destroy", "gsr_set_stream", "gsr_set_profiling", "gsr_default_cfg",
-    "gsr_submap_load", "gsr_submap_free", "gsr_submap_size", "gsr_render", "gsr_render_multi", "gsr_ncc",
+    "gsr_submap_load", "gsr_submap_free", "gsr_submap_size", "gsr_render", "gsr_render_multi",
+    "gsr_render_backward", "gsr_ncc",
     "gsr_topk", "gsr_search", "gsr_capture_begin", "gsr_capture_end", "gsr_graph_launch", "gsr_graph_destroy",
     "gsr_sync", "gsr_get_stats", "gsr_debug_size", "gsr_debug_copy", "gsr_crop",
     "gsr_status_string", "gsr_last_error",
@@ -64,7 +65,8 @@ class Stats(C.Structure):
                 ("overflow", C.c_int32), ("bad_index", C.c_int32),
                 ("n_profiled_renders", C.c_int32), ("n_profiled_ncc", C.c_int32),
                 ("ms_preprocess", C.c_float), ("ms_sort", C.c_float), ("ms_blend", C.c_float),
-                ("ms_ncc", C.c_float), ("ms_render", C.c_float), ("n_groups", C.c_int32)]
+                ("ms_ncc", C.c_float), ("ms_render", C.c_float), ("n_groups", C.c_int32),
+                ("render_serial", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -91,6 +93,7 @@ def _load() -> C.CDLL:
         "gsr_submap_size": (I64, [P]),
         "gsr_render": (I, [P, P, C.POINTER(CameraC), P, I32, C.POINTER(RenderCfg), P, P, P]),
         "gsr_render_multi": (I, [P, P, P, I32, C.POINTER(CameraC), P, C.POINTER(RenderCfg), P, P, P]),
+        "gsr_render_backward": (I, [P, P, P, P, P, I32, P, P, P, P, P, P, P, P, P]),
         "gsr_capture_begin": (I, [P]),
         "gsr_capture_end": (I, [P, C.POINTER(P)]),
         "gsr_graph_launch": (I, [P]),
@@ -351,6 +354,28 @@ class Context:
                                   depth.data_ptr(), tfinal.data_ptr() if tfinal is not None else None)
         self._check(rc, "gsr_render_multi")
         return (rgb, depth, tfinal) if tfinal is not None else (rgb, depth)
+
+    def render_backward(self, submap: Submap, scales, quats, poses, rgb, depth, grad_rgb, grad_depth):
+        """Gradients (means, scales, quats, opacity, rgb) of a loss through the last
+        render of `submap` at `poses` (gsr_render_backward), given dL/drgb and dL/ddepth."""
+        torch = _torch()
+        n = submap.n
+        P = poses.shape[0]
+        _dev_f32(scales, "scales", (n, 3))
+        _dev_f32(quats, "quats", (n, 4))
+        _dev_f32(poses, "poses", (P, 3, 4))
+        H, W = rgb.shape[2], rgb.shape[3]
+        for t, nm, sh in ((rgb, "rgb", (P, 3, H, W)), (depth, "depth", (P, H, W)), (grad_rgb, "grad_rgb", (P, 3, H, W)),
+                          (grad_depth, "grad_depth", (P, H, W))):
+            _dev_f32(t, nm, sh)
+        dev = scales.device
+        out = [torch.empty(sh, dtype=torch.float32, device=dev) for sh in ((n, 3), (n, 3), (n, 4), (n,), (n, 3))]
+        self._bind_stream()
+        rc = LIB.gsr_render_backward(self.handle, submap.handle, scales.data_ptr(), quats.data_ptr(), poses.data_ptr(),
+                                     P, rgb.data_ptr(), depth.data_ptr(), grad_rgb.data_ptr(), grad_depth.data_ptr(),
+                                     *[o.data_ptr() for o in out])
+        self._check(rc, "gsr_render_backward")
+        return tuple(out)
 
     def capture_begin(self):
         """Start recording this context's calls into a HIP graph (gsr_capture_begin).

@@ -1,0 +1,127 @@
+"""GPU render backward (gsr_render_backward) against float64 central differences
+of the oracle renderer (oracle/render64.py) on the config-0 scene.
+
+The loss is a linear functional of the images, L = sum(w_rgb rgb) + sum(w_depth
+depth) with seeded random weights, so its gradient with respect to the images is
+(w_rgb, w_depth). Parameters are those of a map-training step: means, log-scales,
+raw quaternions, opacity logits, colours; the GPU's linear-scale and opacity
+gradients are chained through exp and the sigmoid here. Bar: |g - fd| <= 1e-3
+|fd| + 1e-3 x (median |fd| of the parameter group), over the parameters whose
+central-difference stencil is stable (no change of any pixel's contributing
+list, no decision within a float32 margin of its threshold).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import camera, say, to_dev
+from oracle import render64 as R
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = ["means", "log_scales", "quats", "logits", "rgb"]
+STEPS = {"means": 1e-5, "log_scales": 1e-6, "quats": 1e-6, "logits": 1e-6, "rgb": 1e-6}
+WIDTH = {"means": 3, "log_scales": 3, "quats": 4, "logits": 1, "rgb": 3}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2403_11367_amd import Context
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _gpu_grads(ctx, g, poses, cam, w_rgb, w_depth, cfg=None):
+    import torch
+    arrs = [to_dev(a.astype(np.float32)) for a in g.arrays()]
+    sm = ctx.load_submap(*arrs)
+    pt = to_dev(poses.astype(np.float32))
+    rgb, depth = ctx.render(sm, camera(cam), pt, cfg)
+    grads = ctx.render_backward(sm, arrs[1], arrs[2], pt, rgb, depth, to_dev(w_rgb.astype(np.float32)),
+                                to_dev(w_depth.astype(np.float32)))
+    torch.cuda.synchronize()
+    out = [t.cpu().numpy().astype(np.float64) for t in grads]
+    sm.free()
+    return out
+
+
+def test_backward_matches_central_differences_config0(ctx):
+    sc = W.config0()
+    cam = sc.camera
+    poses = sc.poses[[0, 9]]
+    rng = np.random.default_rng(77)
+    w_rgb = rng.normal(size=(2, 3, cam.height, cam.width)).astype(np.float32).astype(np.float64)
+    w_depth = (0.1 * rng.normal(size=(2, cam.height, cam.width))).astype(np.float32).astype(np.float64)
+    say("render backward: config0, 2 poses, 30 sampled Gaussians x 14 parameters vs float64 central differences")
+    gm, gs, gq, go, gc = _gpu_grads(ctx, sc.gaussians, poses, cam, w_rgb, w_depth)
+    p = R.as_params(sc.gaussians)
+    s = np.exp(p.log_scales)
+    o = 1.0 / (1.0 + np.exp(-p.logits))
+    gpu = {"means": gm, "log_scales": gs * s, "quats": gq, "logits": go * o * (1 - o), "rgb": gc}
+    # Gaussians with some footprint in the first pose
+    scr = R.project(p, poses[0], cam)
+    area = (scr.rect[:, 1] - scr.rect[:, 0]) * (scr.rect[:, 3] - scr.rect[:, 2])
+    inside = scr.visible & (scr.rect[:, 1] > 0) & (scr.rect[:, 0] < cam.width) & (scr.rect[:, 3] > 0) & \
+        (scr.rect[:, 2] < cam.height) & (area > 4.0)
+    pick = rng.choice(np.nonzero(inside)[0], 30, replace=False)
+    rows = {k: [] for k in GROUPS}
+    for gi in pick:
+        for k, name in enumerate(GROUPS):
+            for comp in range(WIDTH[name]):
+                fd, stable = R.fd_gradient(p, poses, cam, w_rgb, w_depth, int(gi), k, comp, STEPS[name])
+                got = gpu[name][gi] if gpu[name].ndim == 1 else gpu[name][gi, comp]
+                rows[name].append((fd, got, stable))
+    n_stable = 0
+    for name in GROUPS:
+        arr = np.array([(f, g) for f, g, st in rows[name] if st])
+        n_stable += len(arr)
+        assert len(arr) >= 0.5 * len(rows[name]), f"{name}: too few stable parameters"
+        scale = np.median(np.abs(arr[:, 0]))
+        err = np.abs(arr[:, 1] - arr[:, 0])
+        tol = 1e-3 * np.abs(arr[:, 0]) + 1e-3 * scale
+        rel = err / np.maximum(np.abs(arr[:, 0]), 1e-30)
+        say(f"  {name}: {len(arr)} stable of {len(rows[name])}, median |fd| {scale:.3e}, max relative error "
+            f"{np.max(rel[np.abs(arr[:, 0]) > scale]) if np.any(np.abs(arr[:, 0]) > scale) else 0:.2e}, "
+            f"worst err/tol {np.max(err / tol):.3f}")
+        assert np.all(err <= tol), name
+    assert n_stable >= 200
+
+
+def test_backward_is_independent_of_pose_groups(ctx):
+    """The same gradients (to float-atomic rounding) when the render ran in 2 pose groups."""
+    from paper_2403_11367_amd import default_cfg
+    sc = W.config0()
+    poses = sc.poses[:4]
+    rng = np.random.default_rng(5)
+    w_rgb = rng.normal(size=(4, 3, sc.camera.height, sc.camera.width))
+    w_depth = rng.normal(size=(4, sc.camera.height, sc.camera.width))
+    say("render backward: 1 vs 2 pose groups")
+    a = _gpu_grads(ctx, sc.gaussians, poses, sc.camera, w_rgb, w_depth)
+    b = _gpu_grads(ctx, sc.gaussians, poses, sc.camera, w_rgb, w_depth, default_cfg(pose_groups=2))
+    for x, y in zip(a, b):
+        assert np.allclose(x, y, rtol=1e-4, atol=1e-5 * np.abs(x).max())
+
+
+def test_backward_argument_checks(ctx):
+    import torch
+    from paper_2403_11367_amd import GsrError
+    sc = W.config0()
+    arrs = [to_dev(a.astype(np.float32)) for a in sc.gaussians.arrays()]
+    sm = ctx.load_submap(*arrs)
+    other = ctx.load_submap(*arrs)
+    pt = to_dev(sc.poses[:2].astype(np.float32))
+    rgb, depth = ctx.render(sm, camera(sc.camera), pt)
+    g = torch.zeros_like(rgb), torch.zeros_like(depth)
+    with pytest.raises(GsrError, match="EINVAL"):  # not the submap of the last render
+        ctx.render_backward(other, arrs[1], arrs[2], pt, rgb, depth, *g)
+    idx = to_dev(np.arange(100, dtype=np.int64))
+    sub = ctx.load_submap(*arrs, index=idx)
+    with pytest.raises(GsrError, match="EINVAL"):  # loaded with an index
+        ctx.render_backward(sub, arrs[1][:100].contiguous(), arrs[2][:100].contiguous(), pt, rgb, depth, *g)
+    torch.cuda.synchronize()
+    for s in (sm, other, sub):
+        s.free()
