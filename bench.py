@@ -16,7 +16,8 @@ scorer prunes to 16 from quarter-resolution renders; the same pruning with
 low-resolution NCC in place of the network; plain renders all at full
 resolution), and batched queries: 8 maps of uneven size x 32 candidates in one
 batched render per stage (autotuned launch) and as a HIP-graph replay, against
-8 separate renders.
+8 separate renders; and one map-training step (forward + backward of 4 views of a
+500,000-Gaussian map, Adam).
 
 Prints one JSON line (rank 0). See --help for flags.
 """
@@ -93,6 +94,7 @@ def main():
                     help="pose groups per render (0 = the library's automatic choice)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-queries leg")
+    ap.add_argument("--no-training", action="store_true", help="skip the map-training leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy before the timed loop (for rocprofv3 counter scaling)")
     args = ap.parse_args()
@@ -236,6 +238,8 @@ def main():
         out["learned"] = learned_leg(ctx, sm, cam, sc, query, dev)
     if not args.no_batched:
         out["batched"] = batched_leg(ctx, cam, dev)
+    if not args.no_training:
+        out["training"] = training_leg(ctx, cam, dev)
     if args.cpu_candidates > 0:
         _log(f"cpu baseline: oracle on {args.cpu_candidates} candidates ...")
         out["cpu_baseline"] = cpu_baseline(sc, idx, args.cpu_candidates)
@@ -349,6 +353,36 @@ def batched_leg(ctx, cam, dev, reps=5):
         sm.free()
     _log(f"batched: separate {res['separate']['ms']:.2f} ms, batched {res['batched']['ms']:.2f} ms, graph "
          f"{res['graph']['ms']:.2f} ms for {P} renders; chosen {res['autotune']['chosen']}")
+    return res
+
+
+def training_leg(ctx, cam, dev, steps=8, warmup=2):
+    """Map-training step (500,000-Gaussian corridor map, seed 3, perturbed; 4 views at
+    1408x376 per step; L1 on colour + 0.1 x L1 on 5%-valid LiDAR depth; Adam): the
+    library's forward and backward through torch.autograd, timed per step."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2403_11367_amd import train
+
+    tm = W.training_map(500_000)
+    data = train.make_training_data(ctx, tm.gt, cam, n_steps=steps + warmup, views=4, seed=33)
+    tr = train.MapTrainer(ctx, cam, tm.means, tm.log_scales, tm.quats, tm.logits, tm.rgb)
+    losses = []
+    for s in range(warmup):
+        losses.append(float(tr.step(data.poses[s], data.rgb[s], data.lidar[s], data.mask[s])))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = [tr.step(data.poses[s], data.rgb[s], data.lidar[s], data.mask[s]) for s in range(warmup, warmup + steps)]
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    losses += [float(x) for x in out]
+    tr.close()
+    res = {"gaussians": 500_000, "views_per_step": 4, "image": f"{cam.width}x{cam.height}",
+           "ms_per_step": round(t * 1e3, 3), "views_per_s": round(4 / t, 1),
+           "loss_first": round(losses[0], 5), "loss_last": round(losses[-1], 5)}
+    _log(f"training: {res['ms_per_step']:.2f} ms per step of 4 views, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     return res
 
 

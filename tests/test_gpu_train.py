@@ -1,0 +1,80 @@
+"""Map training through the differentiable render (torch.autograd.Function over
+gsr_render / gsr_render_backward): the autograd gradients equal the library's,
+and Adam steps on a perturbed map reduce the photometric + LiDAR loss and move
+the Gaussians back towards the ground truth."""
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import camera, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2403_11367_amd import Context
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def test_training_reduces_loss_and_error(ctx):
+    import torch
+    from paper_2403_11367_amd import train
+    say("map training: 60k Gaussians on a 40 m corridor, 352x94, 4 views x 40 steps")
+    cam = camera(W.low_res_camera(W.config1_camera(), 4))
+    tm = W.training_map(n=60_000, length=40.0)
+    data = train.make_training_data(ctx, tm.gt, cam, n_steps=40, views=4, seed=33, length=40.0)
+    tr = train.MapTrainer(ctx, cam, tm.means, tm.log_scales, tm.quats, tm.logits, tm.rgb)
+    gt_means = torch.as_tensor(tm.gt.means, device="cuda")
+    err0 = float((tr.means.detach() - gt_means).norm(dim=1).mean())
+    with torch.no_grad():
+        first = [float(tr.loss(data.poses[s], data.rgb[s], data.lidar[s], data.mask[s])) for s in range(40)]
+    for epoch in range(3):
+        for s in range(40):
+            tr.step(data.poses[s], data.rgb[s], data.lidar[s], data.mask[s])
+    with torch.no_grad():
+        last = [float(tr.loss(data.poses[s], data.rgb[s], data.lidar[s], data.mask[s])) for s in range(40)]
+    err1 = float((tr.means.detach() - gt_means).norm(dim=1).mean())
+    say(f"  loss {np.mean(first):.4f} -> {np.mean(last):.4f}; mean position error {err0:.4f} -> {err1:.4f} m")
+    assert np.mean(last) < 0.7 * np.mean(first)
+    assert err1 < err0
+    tr.close()
+
+
+def test_autograd_matches_the_library(ctx):
+    """loss.backward() through the Function gives the library's gradients chained
+    through exp and the sigmoid."""
+    import torch
+    from paper_2403_11367_amd import train
+    say("map training: autograd gradients vs gsr_render_backward")
+    sc = W.config0()
+    cam = camera(sc.camera)
+    g = sc.gaussians
+    dev = "cuda"
+    means = torch.tensor(g.means, device=dev, requires_grad=True)
+    log_s = torch.tensor(np.log(g.scales), device=dev, requires_grad=True)
+    quats = torch.tensor(g.quats, device=dev, requires_grad=True)
+    logit = torch.tensor(np.log(g.opacity / (1 - g.opacity)), device=dev, requires_grad=True)
+    rgb = torch.tensor(g.rgb, device=dev, requires_grad=True)
+    poses = torch.as_tensor(sc.poses[:3], device=dev)
+    slot = train._SubmapSlot()
+    img, depth = train.render(ctx, slot, means, torch.exp(log_s), quats, torch.sigmoid(logit), rgb, cam, poses)
+    w1 = torch.randn_like(img)
+    w2 = torch.randn_like(depth)
+    ((img * w1).sum() + (depth * w2).sum()).backward()
+    # the library directly, on the same render
+    s_lin, o_lin = torch.exp(log_s).detach(), torch.sigmoid(logit).detach()
+    sm = ctx.load_submap(means.detach(), s_lin, quats.detach(), o_lin, rgb.detach())
+    img2, depth2 = ctx.render(sm, cam, poses)
+    assert torch.equal(img, img2) and torch.equal(depth, depth2)
+    gm, gs, gq, go, gc = ctx.render_backward(sm, s_lin, quats.detach(), poses, img2, depth2, w1, w2)
+    for got, ref in ((means.grad, gm), (log_s.grad, gs * s_lin), (quats.grad, gq), (logit.grad, go * o_lin * (1 - o_lin)),
+                     (rgb.grad, gc)):
+        assert torch.allclose(got, ref, rtol=1e-4, atol=1e-6 * float(ref.abs().max()))
+    sm.free()
+    slot.sm.free()

@@ -377,3 +377,44 @@ def batch_query(seed: int, cam: Camera) -> BatchQuery:
     hidden = _f32(pose_from_center(center + np.array([hdx, hdy, 0.0]), AXES_ALONG_X, np.deg2rad(hyaw)))
     noise = _f32(np.random.default_rng(seed * 10 + 2).normal(0.0, 0.02, size=(3, cam.height, cam.width)))
     return BatchQuery(seed, n, g, poses, hidden, noise)
+
+
+# ---- map training: perturbed corridor map, views along the corridor ----
+def training_views(seed: int, n: int, length: float = 200.0) -> np.ndarray:
+    """n camera poses along a corridor of the given length: centre x ~ U(0.2 L,
+    0.8 L), y ~ U(-3, 3), height 1.5 m, looking along +x with yaw U(-15, 15)
+    degrees; float32 [n, 3, 4]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        c = np.array([rng.uniform(0.2 * length, 0.8 * length), rng.uniform(-3.0, 3.0), 1.5])
+        out.append(pose_from_center(c, AXES_ALONG_X, np.deg2rad(rng.uniform(-15.0, 15.0))))
+    return _f32(np.stack(out))
+
+
+@dataclasses.dataclass
+class TrainingMap:
+    gt: Gaussians          # ground truth (renders it are the targets)
+    means: np.ndarray      # initial parameters, float32
+    log_scales: np.ndarray
+    quats: np.ndarray
+    logits: np.ndarray
+    rgb: np.ndarray
+
+
+def training_map(n: int = 500_000, seed: int = 3, perturb_seed: int = 32, length: float = 200.0) -> TrainingMap:
+    """Ground-truth corridor map (seed 3) and the initial map of a training run: the
+    ground truth perturbed (perturb_seed) by N(0, 0.05) m on the means, N(0, 0.2) on
+    the log-scales, N(0, 0.05) on the quaternion components, N(0, 0.5) on the
+    opacity logits and N(0, 0.1) on the colours (clipped to [0, 1]). Draw order:
+    means, log-scales, quaternions, logits, colours."""
+    gt = corridor_map(n, seed=seed, length=length)
+    rng = np.random.default_rng(perturb_seed)
+    f = lambda a: np.asarray(a, np.float64)  # noqa: E731
+    op = f(gt.opacity)
+    means = f(gt.means) + rng.normal(0.0, 0.05, (n, 3))
+    log_s = np.log(f(gt.scales)) + rng.normal(0.0, 0.2, (n, 3))
+    quats = f(gt.quats) + rng.normal(0.0, 0.05, (n, 4))
+    logits = np.log(op / (1.0 - op)) + rng.normal(0.0, 0.5, n)
+    rgb = np.clip(f(gt.rgb) + rng.normal(0.0, 0.1, (n, 3)), 0.0, 1.0)
+    return TrainingMap(gt, _f32(means), _f32(log_s), _f32(quats), _f32(logits), _f32(rgb))
