@@ -15,10 +15,12 @@
 // walks the tile's list front to back again with the forward's arithmetic
 // (blend_common.h), so T_i and the colour in front of each layer are
 // recomputed rather than stored; the colour behind a layer is the forward's
-// final colour minus the colour up to and including it. Per-pixel gradients of
-// (u, v, conic A, B, C, opacity, r, g, b, z) are added atomically into a
-// per-(pose, Gaussian) buffer (float atomics: the summation order varies from
-// run to run).
+// final colour minus the colour up to and including it. A wave skips the
+// records whose pixel rows miss its 16x4 band, as the forward does. Per-pixel
+// gradients of (u, v, conic A, B, C, opacity, r, g, b, z) are added by global
+// float atomics into a per-(pose, Gaussian) buffer (the summation order varies
+// from run to run). Summing them across the wave first (lane shuffles) or in LDS
+// measured slower: the atomics are not what bounds this kernel.
 //
 // k_project_backward: per (pose, Gaussian), the chain through the conic
 // inverse, Sigma' = T Sigma T^T (Eq. 3), T = J R_w and the Jacobian of Eq. 4
@@ -43,12 +45,15 @@ __global__ __launch_bounds__(kThreads) void k_blend_backward(
     BlendConsts k, const float *__restrict__ img_rgb, const float *__restrict__ img_depth,
     const float *__restrict__ g_rgb, const float *__restrict__ g_depth, float *__restrict__ gscreen) {
     __shared__ float4 s_rec[kThreads * 4];  // staged record (3) + (A, B, C, opacity)
+    __shared__ uint32_t s_rows[kThreads];   // pixel rows j0 | j1 << 16 of the record
     __shared__ uint32_t s_idx[kThreads];
 
     const int tile = blockIdx.x, pose = blockIdx.y;
     const int tx = tile % tiles_x, ty = tile / tiles_x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    // thread = pixel, row-major in the tile: wave w owns rows 4w..4w+3 (a 16x4 band)
     const int pi = tx * 16 + (tid & 15), pj = ty * 16 + (tid >> 4);
+    const int band0 = ty * 16 + 4 * wave, band1 = band0 + 3;
     const bool in_image = pi < width && pj < height;
     const float px = (float)pi + 0.5f, py = (float)pj + 0.5f;
     const uint64_t list = (uint64_t)pose * n_tiles + tile;
@@ -76,12 +81,16 @@ __global__ __launch_bounds__(kThreads) void k_blend_backward(
             const float det = conic_det(q0.z, q0.w, q1.x);
             stage_record(q0, q1, q2, det, k, s_rec[tid * 4 + 0], s_rec[tid * 4 + 1], s_rec[tid * 4 + 2]);
             s_rec[tid * 4 + 3] = make_float4(q0.z, q0.w, q1.x, q1.y);
+            s_rows[tid] = __float_as_uint(q2.w);
             s_idx[tid] = g;
         }
         __syncthreads();
         const int nrec = (int)min<uint64_t>(kThreads, end - c0);
         for (int i = 0; i < nrec; ++i) {
             if (T < k.t_min) break;
+            // the forward visits a record only in the bands its pixel rows meet (uniform per wave)
+            const uint32_t rows = s_rows[i];
+            if ((int)(rows >> 16) < band0 || (int)(rows & 0xffffu) > band1) continue;
             const float4 a = s_rec[i * 4 + 0], b = s_rec[i * 4 + 1];
             const float p2 = footprint_p2(a, b, px, py);
             if (!(p2 >= b.y)) continue;
@@ -91,7 +100,7 @@ __global__ __launch_bounds__(kThreads) void k_blend_backward(
             const float w = al * T;
             const float n0 = __builtin_fmaf(c.x, w, cf0), n1 = __builtin_fmaf(c.y, w, cf1);
             const float n2 = __builtin_fmaf(c.z, w, cf2), nd = __builtin_fmaf(b.w, w, df);
-            const float inv = 1.f / (1.f - al);
+            const float inv = __builtin_amdgcn_rcpf(1.f - al);
             // dL/dalpha: this layer's own colour minus what it hides behind it
             const float dla = dc0 * (c.x * T - (cfin0 - n0) * inv) + dc1 * (c.y * T - (cfin1 - n1) * inv) +
                               dc2 * (c.z * T - (cfin2 - n2) * inv) + dd * (b.w * T - (dfin - nd) * inv);
@@ -105,7 +114,7 @@ __global__ __launch_bounds__(kThreads) void k_blend_backward(
                 atomicAdd(gq + 2, gd2 * dx * dx);
                 atomicAdd(gq + 3, 2.f * gd2 * dx * dy);
                 atomicAdd(gq + 4, gd2 * dy * dy);
-                atomicAdd(gq + 5, dla * al / e.w);
+                atomicAdd(gq + 5, dla * al * __builtin_amdgcn_rcpf(e.w));
             }
             atomicAdd(gq + 6, dc0 * w);
             atomicAdd(gq + 7, dc1 * w);
