@@ -264,6 +264,136 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ x, Con
     }
 }
 
+// Forward for c_in >= 32, LDS-staged: one block computes a TH x TW tile of output
+// pixels of one image for all output channels. Per chunk of 32 input channels
+// the block stages the tile's input halo ((TH-1) S + 3 rows x (TW-1) S + 3
+// columns) in LDS once, and all nine taps read their A fragments from it; per
+// tap it stages that tap's weights [c_out][32], prefetched into registers while
+// the previous tap computes. (Staging all nine taps' weights at once needs up to
+// 135 KB of LDS, one block per compute unit, and measured 1.5x slower.) Rows of
+// 32 channels are padded to 80 bytes, so the 16-byte fragment reads of 16
+// consecutive pixels (or channels) hit distinct banks; for stride 2 the halo is
+// stored as even and odd column planes, so that strided pixels are consecutive
+// in LDS as well.
+template <int CI, int CO, int S, int TH, int TW, int WGN>
+__global__ __launch_bounds__(256) void k_conv_fwd_lds(const u16 *__restrict__ x, ConvDims d,
+                                                       const u16 *__restrict__ wt, const float *__restrict__ bias,
+                                                       u16 *__restrict__ y) {
+    constexpr int WGM = 4 / WGN, BM = TH * TW;
+    constexpr int RM = BM / (WGM * 32), RN = CO / (WGN * 32);
+    static_assert(RM >= 1 && RN >= 1 && WGM * RM * 32 == BM && WGN * RN * 32 == CO, "tile and wave grid");
+    static_assert(CI % 32 == 0, "channel chunks of 32");
+    constexpr int HH = (TH - 1) * S + 3, HWD = (TW - 1) * S + 3;
+    constexpr int PW = S == 1 ? HWD : (HWD + 1) / 2;  // columns per plane
+    constexpr int SLOTS = S == 1 ? HH * HWD : HH * 2 * PW;
+    constexpr int ROW = 40;                              // bf16 per LDS row (32 + 8 padding)
+    __shared__ __align__(16) u16 s_halo[SLOTS * ROW];
+    __shared__ __align__(16) u16 s_b[CO * ROW];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WGM, wn = wave / WGM;
+    const int r32 = lane & 31, kq = lane >> 5;
+    const int n = blockIdx.z, oy0 = blockIdx.y * TH, ox0 = blockIdx.x * TW;
+    const int iy0 = oy0 * S - 1, ix0 = ox0 * S - 1;
+    const u16 *ximg = x + (int64_t)n * d.H * d.W * CI;
+    auto slot_of = [](int hy, int hx) { return S == 1 ? hy * HWD + hx : (hy * 2 + (hx & 1)) * PW + (hx >> 1); };
+
+    // this lane's output pixels (tile-local) for each of its row blocks
+    int ty[RM], tx[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const int m = wm * RM * 32 + 32 * r + r32;
+        ty[r] = m / TW;
+        tx[r] = m - ty[r] * TW;
+    }
+    f32x16 acc[RM][RN];
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int c = 0; c < RN; ++c)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[r][c][i] = 0.f;
+
+    constexpr int BPIECES = CO * 4;                      // 16-byte pieces of one tap's weights
+    constexpr int BPER = (BPIECES + 255) / 256;
+    u32x4 bpre[BPER];
+    auto fetch_b = [&](int tap, int ci0) {
+#pragma unroll
+        for (int j = 0; j < BPER; ++j) {
+            const int p = tid + 256 * j;
+            if (p < BPIECES) {
+                const int co = p >> 2, q = p & 3;
+                bpre[j] = *(const u32x4 *)(wt + ((int64_t)co * 9 + tap) * CI + ci0 + 8 * q);
+            }
+        }
+    };
+    auto store_b = [&]() {
+#pragma unroll
+        for (int j = 0; j < BPER; ++j) {
+            const int p = tid + 256 * j;
+            if (p < BPIECES) *(u32x4 *)(s_b + (p >> 2) * ROW + 8 * (p & 3)) = bpre[j];
+        }
+    };
+
+    for (int ci0 = 0; ci0 < CI; ci0 += 32) {
+        __syncthreads();  // the previous chunk is done with the LDS
+        for (int p = tid; p < HH * HWD * 4; p += 256) {
+            const int pix = p >> 2, q = p & 3;
+            const int hy = pix / HWD, hx = pix - hy * HWD;
+            const int iy = iy0 + hy, ix = ix0 + hx;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (iy >= 0 && iy < d.H && ix >= 0 && ix < d.W)
+                v = *(const u32x4 *)(ximg + ((int64_t)iy * d.W + ix) * CI + ci0 + 8 * q);
+            *(u32x4 *)(s_halo + slot_of(hy, hx) * ROW + 8 * q) = v;
+        }
+        fetch_b(0, ci0);
+        store_b();
+        __syncthreads();
+        for (int tap = 0; tap < 9; ++tap) {
+            const int kh = tap / 3, kw = tap - 3 * kh;
+            if (tap < 8) fetch_b(tap + 1, ci0);  // in flight while this tap computes
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                bf16x8 a[RM], b[RN];
+#pragma unroll
+                for (int r = 0; r < RM; ++r)
+                    a[r] = __builtin_bit_cast(
+                        bf16x8, *(const u32x4 *)(s_halo + slot_of(ty[r] * S + kh, tx[r] * S + kw) * ROW + 16 * kk +
+                                                 8 * kq));
+#pragma unroll
+                for (int c = 0; c < RN; ++c)
+                    b[c] = __builtin_bit_cast(
+                        bf16x8, *(const u32x4 *)(s_b + (wn * RN * 32 + 32 * c + r32) * ROW + 16 * kk + 8 * kq));
+#pragma unroll
+                for (int r = 0; r < RM; ++r)
+#pragma unroll
+                    for (int c = 0; c < RN; ++c) acc[r][c] = mfma(a[r], b[c], acc[r][c]);
+            }
+            if (tap < 8) {
+                __syncthreads();  // every wave is done with this tap's weights
+                store_b();
+                __syncthreads();
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < RN; ++c) {
+        const int co = wn * RN * 32 + 32 * c + r32;
+        const float bv = bias[co];
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = wm * RM * 32 + 32 * r + 8 * (i / 4) + 4 * kq + (i % 4);
+                const int oy = oy0 + m / TW, ox = ox0 + m % TW;
+                if (oy < d.Ho && ox < d.Wo) {
+                    const float v = acc[r][c][i] + bv;
+                    y[(((int64_t)n * d.Ho + oy) * d.Wo + ox) * CO + co] = to_bf16(v > 0.f ? v : 0.f);
+                }
+            }
+    }
+}
+
 // Backward data: dx = (conv^T(dy, W)) * (a_in > 0) in bf16, for the input
 // pixels of sub-pixel class blockIdx.y (stride 2: (y mod 2, x mod 2)).
 // wd is the weight in [tap][c_in][c_out] layout.
@@ -576,6 +706,12 @@ void fwd_layer(hipStream_t s, const u16 *x, ConvDims d, const u16 *wt, const flo
                        x, d, wt, bias, y);
 }
 
+template <int CI, int CO, int S, int TH, int TW, int WGN>
+void fwd_layer_lds(hipStream_t s, const u16 *x, ConvDims d, const u16 *wt, const float *bias, u16 *y) {
+    const dim3 grid((unsigned)((d.Wo + TW - 1) / TW), (unsigned)((d.Ho + TH - 1) / TH), (unsigned)d.n);
+    hipLaunchKernelGGL((k_conv_fwd_lds<CI, CO, S, TH, TW, WGN>), grid, dim3(256), 0, s, x, d, wt, bias, y);
+}
+
 template <int CI, int CO, int S, int RM, int RN, int WGN>
 void bwd_data_layer(hipStream_t s, const u16 *dy, ConvDims d, const u16 *wd, const u16 *a_in, u16 *dx) {
     constexpr int BM = (4 / WGN) * RM * 32;
@@ -636,10 +772,10 @@ void launch_scorer_forward(hipStream_t s, const ScorerBufs &b, int B, float *sco
     auto D = [&](int l) { return ConvDims{B, dm[l][0], dm[l][1], dm[l + 1][0], dm[l + 1][1]}; };
     const float *p = b.params;
     fwd_layer<2, 32, 2, 2, 1, 1>(s, b.x, D(0), b.wt + b.w_off[0], p + b.b_off[0], b.act[1]);
-    fwd_layer<32, 64, 1, 2, 2, 1>(s, b.act[1], D(1), b.wt + b.w_off[1], p + b.b_off[1], b.act[2]);
-    fwd_layer<64, 64, 2, 2, 2, 1>(s, b.act[2], D(2), b.wt + b.w_off[2], p + b.b_off[2], b.act[3]);
-    fwd_layer<64, 128, 1, 2, 2, 2>(s, b.act[3], D(3), b.wt + b.w_off[3], p + b.b_off[3], b.act[4]);
-    fwd_layer<128, 128, 2, 2, 2, 2>(s, b.act[4], D(4), b.wt + b.w_off[4], p + b.b_off[4], b.act[5]);
+    fwd_layer_lds<32, 64, 1, 16, 16, 1>(s, b.act[1], D(1), b.wt + b.w_off[1], p + b.b_off[1], b.act[2]);
+    fwd_layer_lds<64, 64, 2, 8, 16, 1>(s, b.act[2], D(2), b.wt + b.w_off[2], p + b.b_off[2], b.act[3]);
+    fwd_layer_lds<64, 128, 1, 8, 16, 2>(s, b.act[3], D(3), b.wt + b.w_off[3], p + b.b_off[3], b.act[4]);
+    fwd_layer_lds<128, 128, 2, 8, 16, 2>(s, b.act[4], D(4), b.wt + b.w_off[4], p + b.b_off[4], b.act[5]);
     const int npix = dm[5][0] * dm[5][1];
     hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(256), 0, s, b.act[5], npix, p + b.fc_off[0], p + b.fc_off[1],
                        p + b.fc_off[2], p + b.fc_off[3], b.g, b.h, score);
