@@ -36,12 +36,20 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 FP32_VECTOR_PEAK = 157.3     # TFLOP/s, MI355X published fp32 vector (packed FMA)
 FLOPS_PER_CONTRIB = 25       # flops of one (pixel, Gaussian) contribution, Eq. 1, 2, 5
-BLEND_SRC = os.path.join(ROOT, "paper_2403_11367_amd", "csrc", "blend.hip")
+# the compositing kernel's sources: the counters in TRAFFIC_FILE hold for this text
+BLEND_SRCS = [os.path.join(ROOT, "paper_2403_11367_amd", "csrc", f) for f in ("blend.hip", "blend_common.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blend_config1_traffic.md")
 
 
 def _log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def blend_source_sha256() -> str:
+    h = hashlib.sha256()
+    for f in BLEND_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def _blend_traffic(n_groups):
@@ -56,7 +64,7 @@ def _blend_traffic(n_groups):
     m_g = re.search(r"launches_per_render:\s*([0-9]+)", txt)
     if not (m_b and m_h and m_g) or int(m_g.group(1)) != n_groups:
         return None
-    cur = hashlib.sha256(open(BLEND_SRC, "rb").read()).hexdigest()
+    cur = blend_source_sha256()
     return float(m_b.group(1)) if m_h.group(1) == cur else None
 
 
