@@ -125,3 +125,46 @@ def test_backward_argument_checks(ctx):
     torch.cuda.synchronize()
     for s in (sm, other, sub):
         s.free()
+
+
+def test_backward_with_alpha_and_jacobian_clamps(ctx):
+    """Gaussians whose alpha is clamped at alpha_max near their centre (opacity
+    0.999) and a large one whose mean lies outside the Jacobian's clamp (1.3 x the
+    half field of view) but whose footprint reaches into the image: the clamped
+    branches of the backward against central differences."""
+    say("render backward: alpha clamp and Jacobian clamp, 64x48")
+    rng = np.random.default_rng(21)
+    cam = W.Camera(64, 48, 40.0, 40.0, 32.0, 24.0)
+    pose = W.pose_from_center(np.zeros(3), W.AXES_ALONG_Y)  # camera at the origin looking along +y
+    # Gaussian 0 projects onto the centre of pixel (32, 24), where its alpha is clamped
+    means = [[0.0625, 5.0, -0.0625], [0.8, 6.0, 0.3], [-5.5, 5.0, 0.2], [5.6, 5.2, -0.4]]
+    scales = [[0.25, 0.2, 0.3], [0.2, 0.3, 0.25], [1.5, 1.2, 1.4], [1.3, 1.6, 1.1]]
+    opac = [0.999, 0.995, 0.7, 0.6]
+    g = W.Gaussians(np.array(means, np.float32), np.array(scales, np.float32),
+                    rng.normal(size=(4, 4)).astype(np.float32), np.array(opac, np.float32),
+                    rng.uniform(0, 1, (4, 3)).astype(np.float32))
+    p = R.as_params(g)
+    scr = R.project(p, pose, cam)
+    lim = R.JAC_CLAMP * 0.5 * cam.width / cam.fx
+    xt = (scr.u - cam.cx) / cam.fx
+    assert abs(xt[2]) > lim and abs(xt[3]) > lim and scr.visible[2] and scr.visible[3]
+    assert abs(scr.u[0] - 32.5) < 1e-9 and abs(scr.v[0] - 24.5) < 1e-9 and scr.opacity[0] > R.ALPHA_MAX
+    poses = pose[None].astype(np.float32)
+    w_rgb = rng.normal(size=(1, 3, cam.height, cam.width))
+    w_depth = 0.1 * rng.normal(size=(1, cam.height, cam.width))
+    gm, gs, gq, go, gc = _gpu_grads(ctx, g, poses, cam, w_rgb, w_depth)
+    s = np.exp(p.log_scales)
+    o = 1.0 / (1.0 + np.exp(-p.logits))
+    gpu = {"means": gm, "log_scales": gs * s, "quats": gq, "logits": go * o * (1 - o), "rgb": gc}
+    n_checked = 0
+    for gi in range(4):
+        for k, name in enumerate(GROUPS):
+            for comp in range(WIDTH[name]):
+                fd, stable = R.fd_gradient(p, poses, cam, w_rgb, w_depth, gi, k, comp, STEPS[name])
+                if not stable:
+                    continue
+                got = gpu[name][gi] if gpu[name].ndim == 1 else gpu[name][gi, comp]
+                n_checked += 1
+                assert abs(got - fd) <= 1e-3 * abs(fd) + 1e-5, (gi, name, comp, got, fd)
+    say(f"  {n_checked} stable parameters checked")
+    assert n_checked >= 30

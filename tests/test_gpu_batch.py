@@ -156,3 +156,29 @@ def test_capture_rules(ctx, batch4):
         graph.launch()
         stream.synchronize()
         graph.close()
+
+
+def test_empty_submap(ctx):
+    """A submap with no Gaussians renders background (colour and depth 0, T = 1),
+    alone and inside a batch; its NCC against any query is 0."""
+    import torch
+    say("empty submap: render, batched render, NCC")
+    sc = W.tiny_scene(41, n=200, n_poses=2)
+    cam = camera(sc.camera)
+    empty = W.Gaussians(*(np.zeros((0,) + a.shape[1:], np.float32) for a in sc.gaussians.arrays()))
+    sm0 = load(ctx, empty)
+    sm1 = load(ctx, sc.gaussians)
+    assert sm0.n == 0
+    rgb, depth, tf = ctx.render(sm0, cam, to_dev(sc.poses), with_tfinal=True)
+    torch.cuda.synchronize()
+    assert float(rgb.abs().max()) == 0 and float(depth.abs().max()) == 0 and float(tf.min()) == 1
+    ref = ctx.render(sm1, cam, to_dev(sc.poses), with_tfinal=True)
+    got = ctx.render_multi([sm0, sm1], [2, 2], cam, to_dev(np.concatenate([sc.poses, sc.poses])), with_tfinal=True)
+    torch.cuda.synchronize()
+    for a, b in zip(got, ref):
+        assert torch.equal(a[2:], b)
+    assert float(got[0][:2].abs().max()) == 0
+    scores = ctx.ncc(torch.rand((3, cam.height, cam.width), device="cuda"), rgb)
+    assert float(scores.abs().max()) == 0
+    for sm in (sm0, sm1):
+        sm.free()
