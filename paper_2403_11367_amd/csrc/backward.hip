@@ -11,16 +11,9 @@
 // constant). The contributing set (support cutoff, alpha floor, the layer after
 // which the pixel stops) is piecewise constant and is taken as fixed.
 //
-// k_blend_backward: one 256-thread block per (tile, pose), one pixel per thread,
-// walks the tile's list front to back again with the forward's arithmetic
-// (blend_common.h), so T_i and the colour in front of each layer are
-// recomputed rather than stored; the colour behind a layer is the forward's
-// final colour minus the colour up to and including it. A wave skips the
-// records whose pixel rows miss its 16x4 band, as the forward does. Per-pixel
-// gradients of (u, v, conic A, B, C, opacity, r, g, b, z) are added by global
-// float atomics into a per-(pose, Gaussian) buffer (the summation order varies
-// from run to run). Summing them across the wave first (lane shuffles) or in LDS
-// measured slower: the atomics are not what bounds this kernel.
+// The compositing backward (screen-space gradients per (pose, Gaussian)) runs
+// the forward's tile walk and lives with it in blend.hip. This file chains them
+// to the parameters:
 //
 // k_project_backward: per (pose, Gaussian), the chain through the conic
 // inverse, Sigma' = T Sigma T^T (Eq. 3), T = J R_w and the Jacobian of Eq. 4
@@ -29,106 +22,14 @@
 //
 // k_param_grads: per Gaussian, sums the poses in order and chains
 // Sigma = M M^T, M = R(q) diag(s), and the quaternion normalisation.
-#include "blend_common.h"
+#include "internal.h"
 
 namespace gsr {
 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kScreenGrads = 10;  // u, v, A, B, C, opacity, r, g, b, z
 constexpr int kPoseGrads = 13;    // mean (3), Sigma unique entries (6), opacity, r, g, b
-
-__global__ __launch_bounds__(kThreads) void k_blend_backward(
-    const float4 *__restrict__ records, int64_t n, const uint32_t *__restrict__ pairs,
-    const uint64_t *__restrict__ offsets, uint64_t capacity, int width, int height, int tiles_x, int n_tiles,
-    BlendConsts k, const float *__restrict__ img_rgb, const float *__restrict__ img_depth,
-    const float *__restrict__ g_rgb, const float *__restrict__ g_depth, float *__restrict__ gscreen) {
-    __shared__ float4 s_rec[kThreads * 4];  // staged record (3) + (A, B, C, opacity)
-    __shared__ uint32_t s_rows[kThreads];   // pixel rows j0 | j1 << 16 of the record
-    __shared__ uint32_t s_idx[kThreads];
-
-    const int tile = blockIdx.x, pose = blockIdx.y;
-    const int tx = tile % tiles_x, ty = tile / tiles_x;
-    const int tid = threadIdx.x, wave = tid >> 6;
-    // thread = pixel, row-major in the tile: wave w owns rows 4w..4w+3 (a 16x4 band)
-    const int pi = tx * 16 + (tid & 15), pj = ty * 16 + (tid >> 4);
-    const int band0 = ty * 16 + 4 * wave, band1 = band0 + 3;
-    const bool in_image = pi < width && pj < height;
-    const float px = (float)pi + 0.5f, py = (float)pj + 0.5f;
-    const uint64_t list = (uint64_t)pose * n_tiles + tile;
-    const uint64_t beg = offsets[list];
-    const uint64_t end = min(offsets[list + 1], capacity);
-    const float4 *rec_pose = records + (int64_t)pose * n * 3;
-
-    const int64_t hw = (int64_t)width * height;
-    const int64_t pix = in_image ? (int64_t)pj * width + pi : 0;
-    const float *irgb = img_rgb + (int64_t)pose * 3 * hw;
-    const float *grgb = g_rgb + (int64_t)pose * 3 * hw;
-    const float cfin0 = irgb[pix], cfin1 = irgb[hw + pix], cfin2 = irgb[2 * hw + pix];
-    const float dfin = img_depth[(int64_t)pose * hw + pix];
-    const float dc0 = grgb[pix], dc1 = grgb[hw + pix], dc2 = grgb[2 * hw + pix];
-    const float dd = g_depth[(int64_t)pose * hw + pix];
-
-    float T = in_image ? 1.f : 0.f, cf0 = 0.f, cf1 = 0.f, cf2 = 0.f, df = 0.f;
-    float *gpose = gscreen + (int64_t)pose * n * kScreenGrads;
-    for (uint64_t c0 = beg; c0 < end; c0 += kThreads) {
-        const uint64_t kk = c0 + tid;
-        if (kk < end) {
-            const uint32_t g = pairs[kk];
-            const float4 *r = rec_pose + (int64_t)g * 3;
-            const float4 q0 = r[0], q1 = r[1], q2 = r[2];
-            const float det = conic_det(q0.z, q0.w, q1.x);
-            stage_record(q0, q1, q2, det, k, s_rec[tid * 4 + 0], s_rec[tid * 4 + 1], s_rec[tid * 4 + 2]);
-            s_rec[tid * 4 + 3] = make_float4(q0.z, q0.w, q1.x, q1.y);
-            s_rows[tid] = __float_as_uint(q2.w);
-            s_idx[tid] = g;
-        }
-        __syncthreads();
-        const int nrec = (int)min<uint64_t>(kThreads, end - c0);
-        for (int i = 0; i < nrec; ++i) {
-            if (T < k.t_min) break;
-            // the forward visits a record only in the bands its pixel rows meet (uniform per wave)
-            const uint32_t rows = s_rows[i];
-            if ((int)(rows >> 16) < band0 || (int)(rows & 0xffffu) > band1) continue;
-            const float4 a = s_rec[i * 4 + 0], b = s_rec[i * 4 + 1];
-            const float p2 = footprint_p2(a, b, px, py);
-            if (!(p2 >= b.y)) continue;
-            const float4 c = s_rec[i * 4 + 2], e = s_rec[i * 4 + 3];
-            const float gexp = __builtin_amdgcn_exp2f(p2);
-            const float al = fminf(k.alpha_max, gexp);
-            const float w = al * T;
-            const float n0 = __builtin_fmaf(c.x, w, cf0), n1 = __builtin_fmaf(c.y, w, cf1);
-            const float n2 = __builtin_fmaf(c.z, w, cf2), nd = __builtin_fmaf(b.w, w, df);
-            const float inv = __builtin_amdgcn_rcpf(1.f - al);
-            // dL/dalpha: this layer's own colour minus what it hides behind it
-            const float dla = dc0 * (c.x * T - (cfin0 - n0) * inv) + dc1 * (c.y * T - (cfin1 - n1) * inv) +
-                              dc2 * (c.z * T - (cfin2 - n2) * inv) + dd * (b.w * T - (dfin - nd) * inv);
-            float *gq = gpose + (int64_t)s_idx[i] * kScreenGrads;
-            if (gexp < k.alpha_max) {
-                // alpha = o exp(-d^2/2): dalpha/do = alpha / o, dalpha/d(d^2) = -alpha / 2
-                const float dx = px - a.x, dy = py - a.y;
-                const float gd2 = -0.5f * dla * al;
-                atomicAdd(gq + 0, -2.f * gd2 * (e.x * dx + e.y * dy));
-                atomicAdd(gq + 1, -2.f * gd2 * (e.y * dx + e.z * dy));
-                atomicAdd(gq + 2, gd2 * dx * dx);
-                atomicAdd(gq + 3, 2.f * gd2 * dx * dy);
-                atomicAdd(gq + 4, gd2 * dy * dy);
-                atomicAdd(gq + 5, dla * al * __builtin_amdgcn_rcpf(e.w));
-            }
-            atomicAdd(gq + 6, dc0 * w);
-            atomicAdd(gq + 7, dc1 * w);
-            atomicAdd(gq + 8, dc2 * w);
-            atomicAdd(gq + 9, dd * w);
-            T -= w;
-            cf0 = n0;
-            cf1 = n1;
-            cf2 = n2;
-            df = nd;
-        }
-        if (__syncthreads_count(!(T < k.t_min)) == 0) break;
-    }
-}
 
 // Per (pose, Gaussian): screen-space gradients -> mean and covariance entries.
 __global__ __launch_bounds__(kThreads) void k_project_backward(
@@ -278,17 +179,7 @@ __global__ __launch_bounds__(kThreads) void k_param_grads(const float *__restric
 
 }  // namespace
 
-int screen_grads_per_gaussian() { return kScreenGrads; }
 int pose_grads_per_gaussian() { return kPoseGrads; }
-
-void launch_blend_backward(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
-                           const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
-                           const TileGrid &tg, const float *img_rgb, const float *img_depth, const float *g_rgb,
-                           const float *g_depth, float *gscreen) {
-    hipLaunchKernelGGL(k_blend_backward, dim3((unsigned)tg.n_tiles, (unsigned)n_poses), dim3(kThreads), 0, s,
-                       records, n, pairs, offsets, capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles,
-                       blend_consts(k), img_rgb, img_depth, g_rgb, g_depth, gscreen);
-}
 
 void launch_project_backward(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
                              const Camera &cam, const Consts &k, const uint32_t *ntiles, const float *gscreen,

@@ -20,6 +20,13 @@
 // longest of the four walks rather than their union. Each pixel still sees its
 // records in list order. A wave stops when all of its pixels have stopped; the
 // block stops loading when all waves have.
+//
+// The backward of the compositing (k_blend_backward) runs the same walk: with
+// w_i = a_i T_i and S_i the colour behind layer i (the final colour minus the
+// colour up to and including it), dC/da_i = c_i T_i - S_i / (1 - a_i),
+// dC/dc_i = w_i, dD/dz_i = w_i. Each visit's gradients with respect to the
+// record's (u, v, conic, opacity, colour, depth) are summed over the quarter's
+// 16 lanes, which all visit the same record, and added once per quarter.
 #include "blend_common.h"
 
 namespace gsr {
@@ -31,15 +38,40 @@ constexpr int kThreads = 256;
 // (chunks of 124 or 60, for earlier exits on short lists). A template parameter.
 constexpr int kDummy = 255;             // LDS slot (wave 3, lane 63) of a record that never contributes
 
-// The compositing of one (tile, pose) by the whole block.
-template <bool kCount, int kStage>
+// Inputs and output of the backward walk, per launch (pose 0 = the launch's first).
+struct GradIo {
+    const float *img_rgb, *img_depth;  // the forward's images [P, 3, H, W], [P, H, W]
+    const float *g_rgb, *g_depth;      // dL/d(images), same layouts
+    float *gscreen;                    // [P, n, 10] screen-space gradients, accumulated
+};
+
+// Sum over the lane's 16-lane DPP row (one quarter): after rotations by 8, 4, 2
+// and 1 within the row every lane holds the row's total. All 64 lanes must be
+// active.
+__device__ __forceinline__ float quarter_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));  // row_ror:8
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false));  // row_ror:4
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x122, 0xf, 0xf, false));  // row_ror:2
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x121, 0xf, 0xf, false));  // row_ror:1
+    return v;
+}
+
+// The compositing of one (tile, pose) by the whole block, or (kGrad) its
+// backward: the same walk, so the same pixels visit the same records in the
+// same order and recompute the forward's T bit for bit.
+template <bool kCount, int kStage, bool kGrad = false>
 __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__restrict__ records, int64_t n,
                                            const uint32_t *__restrict__ pairs,
                                            const uint64_t *__restrict__ offsets, uint64_t capacity, int width,
                                            int height, int tiles_x, int n_tiles, const BlendConsts &k,
                                            float *__restrict__ out_rgb, float *__restrict__ out_depth,
-                                           float *__restrict__ out_t, unsigned long long *__restrict__ counters) {
-    __shared__ float4 s_rec[kThreads * 3];  // slot = staging thread
+                                           float *__restrict__ out_t, unsigned long long *__restrict__ counters,
+                                           const GradIo &gio = GradIo{}) {
+    // slot = staging thread; the backward adds a fourth quad (A, B, C, opacity)
+    // and keeps the Gaussian's index in the third quad's w
+    constexpr int kQuads = kGrad ? 4 : 3;
+    constexpr uint32_t kSlotBytes = 16u * kQuads;
+    __shared__ float4 s_rec[kThreads * kQuads];
     __shared__ uint64_t s_mask[4][4][4];  // [band][quarter][64-record group]
     __shared__ uint32_t s_words[4][256];  // per wave: slot of every quarter, one byte each, per step
 
@@ -59,9 +91,9 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
 
     if (tid == kDummy) {  // this thread never stages a record
         const float inf = __builtin_inff();
-        s_rec[kDummy * 3 + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
-        s_rec[kDummy * 3 + 1] = make_float4(0.f, inf, 0.f, 0.f);
-        s_rec[kDummy * 3 + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_rec[kDummy * kQuads + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_rec[kDummy * kQuads + 1] = make_float4(0.f, inf, 0.f, 0.f);
+        s_rec[kDummy * kQuads + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 
     // A pixel is live (still compositing) while T >= t_min: T never increases and
@@ -70,6 +102,24 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     unsigned n_contrib = 0, n_visits = 0;  // only with kCount
     const uint32_t lane_sh = 8u * quarter;  // the lane's byte of a slot word
     const char *s_rec_bytes = reinterpret_cast<const char *>(s_rec);
+
+    // backward: the pixel's final colour and depth and their loss gradients
+    float fin_r = 0.f, fin_g = 0.f, fin_b = 0.f, fin_d = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, gd = 0.f;
+    float *gpose = nullptr;
+    if constexpr (kGrad) {
+        const int64_t hw = (int64_t)width * height;
+        const int64_t pix = in_image ? (int64_t)pj * width + pi : 0;
+        const int64_t prgb = (int64_t)pose * 3 * hw + pix, pd = (int64_t)pose * hw + pix;
+        fin_r = gio.img_rgb[prgb];
+        fin_g = gio.img_rgb[prgb + hw];
+        fin_b = gio.img_rgb[prgb + 2 * hw];
+        fin_d = gio.img_depth[pd];
+        gr = gio.g_rgb[prgb];
+        gg = gio.g_rgb[prgb + hw];
+        gb = gio.g_rgb[prgb + 2 * hw];
+        gd = gio.g_depth[pd];
+        gpose = gio.gscreen + (int64_t)pose * n * kScreenGrads;
+    }
 
     for (uint64_t c0 = beg; c0 < end; c0 += 4 * kStage) {
         // stage one record per thread (lanes 0..62 of every wave)
@@ -95,7 +145,12 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             // about sqrt(A C / det) times less to rounding than the expanded form
             const float det = conic_det(A, B, C);
             const float iA = __builtin_amdgcn_rcpf(A), idet = __builtin_amdgcn_rcpf(det);
-            stage_record(q0, q1, q2, det, k, s_rec[tid * 3 + 0], s_rec[tid * 3 + 1], s_rec[tid * 3 + 2]);
+            stage_record(q0, q1, q2, det, k, s_rec[tid * kQuads + 0], s_rec[tid * kQuads + 1],
+                         s_rec[tid * kQuads + 2]);
+            if constexpr (kGrad) {
+                s_rec[tid * kQuads + 2].w = __uint_as_float(g);
+                s_rec[tid * kQuads + 3] = make_float4(A, B, C, q1.y);
+            }
             const float R2 = k.cull_r2;
             // hardware reciprocal and square root (about 1 ulp) for the overlap test:
             // the margin in R2 covers them
@@ -167,7 +222,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             // Software pipeline, unrolled twice so the two register sets alternate:
             // the slots and geometry of step i + 1 are read during step i.
             auto load = [&](uint32_t w, uint32_t &o, float4 &ra, float4 &rb) {
-                o = ((w >> lane_sh) & 0xffu) * 48u;
+                o = ((w >> lane_sh) & 0xffu) * kSlotBytes;
                 ra = *reinterpret_cast<const float4 *>(s_rec_bytes + o);
                 rb = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 16);
             };
@@ -179,15 +234,67 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                     n_contrib += ok;
                     ++n_visits;
                 }
-                if (ok) {
-                    const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
-                    const float al = fminf(k.alpha_max, __builtin_amdgcn_exp2f(p2));
-                    const float w = al * T;
-                    cr = __builtin_fmaf(c.x, w, cr);
-                    cg = __builtin_fmaf(c.y, w, cg);
-                    cb = __builtin_fmaf(c.z, w, cb);
-                    dep = __builtin_fmaf(rb.w, w, dep);
-                    T -= w;
+                if constexpr (!kGrad) {
+                    if (ok) {
+                        const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
+                        const float al = fminf(k.alpha_max, __builtin_amdgcn_exp2f(p2));
+                        const float w = al * T;
+                        cr = __builtin_fmaf(c.x, w, cr);
+                        cg = __builtin_fmaf(c.y, w, cg);
+                        cb = __builtin_fmaf(c.z, w, cb);
+                        dep = __builtin_fmaf(rb.w, w, dep);
+                        T -= w;
+                    }
+                } else {
+                    // Screen-space gradients of this pixel for this record (u, v,
+                    // A, B, C, opacity, r, g, b, z); zero where it does not contribute.
+                    float gv[kScreenGrads] = {};
+                    if (ok) {
+                        const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
+                        const float4 e = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 48);
+                        const float gexp = __builtin_amdgcn_exp2f(p2);
+                        const float al = fminf(k.alpha_max, gexp);
+                        const float w = al * T;
+                        // colour and depth up to and including this layer (the forward's sums)
+                        const float n_r = __builtin_fmaf(c.x, w, cr), n_g = __builtin_fmaf(c.y, w, cg);
+                        const float n_b = __builtin_fmaf(c.z, w, cb), n_d = __builtin_fmaf(rb.w, w, dep);
+                        const float inv = __builtin_amdgcn_rcpf(1.f - al);
+                        // dL/dalpha: the layer's own colour minus what it hides behind it
+                        const float dla = gr * (c.x * T - (fin_r - n_r) * inv) + gg * (c.y * T - (fin_g - n_g) * inv) +
+                                          gb * (c.z * T - (fin_b - n_b) * inv) + gd * (rb.w * T - (fin_d - n_d) * inv);
+                        if (gexp < k.alpha_max) {  // else alpha is clamped, constant
+                            // alpha = o exp(-d^2/2): dalpha/do = alpha / o, dalpha/d(d^2) = -alpha / 2
+                            const float dx = px - ra.x, dy = py - ra.y;
+                            const float gd2 = -0.5f * dla * al;
+                            gv[0] = -2.f * gd2 * (e.x * dx + e.y * dy);
+                            gv[1] = -2.f * gd2 * (e.y * dx + e.z * dy);
+                            gv[2] = gd2 * dx * dx;
+                            gv[3] = 2.f * gd2 * dx * dy;
+                            gv[4] = gd2 * dy * dy;
+                            gv[5] = dla * al * __builtin_amdgcn_rcpf(e.w);
+                        }
+                        gv[6] = gr * w;
+                        gv[7] = gg * w;
+                        gv[8] = gb * w;
+                        gv[9] = gd * w;
+                        T -= w;
+                        cr = n_r;
+                        cg = n_g;
+                        cb = n_b;
+                        dep = n_d;
+                    }
+                    const uint32_t gi = __float_as_uint(*reinterpret_cast<const float *>(s_rec_bytes + o + 44));
+                    // any lane of the quarter contributing (every lane of a quarter visits the same record)
+                    const uint64_t okm = __ballot(ok);
+                    if (okm != 0) {
+#pragma unroll
+                        for (int j = 0; j < kScreenGrads; ++j) gv[j] = quarter_sum(gv[j]);
+                        if ((lane & 15) == 0 && ((okm >> (16 * quarter)) & 0xffffull) != 0) {
+                            float *dst = gpose + (int64_t)gi * kScreenGrads;
+#pragma unroll
+                            for (int j = 0; j < kScreenGrads; ++j) atomicAdd(dst + j, gv[j]);
+                        }
+                    }
                 }
                 const uint64_t lm_next = __ballot(!(T < k.t_min));
                 if (lm_next != lm) {
@@ -229,7 +336,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
         }
     }
 
-    if (in_image) {
+    if (!kGrad && in_image) {
         const int64_t hw = (int64_t)width * height;
         const int64_t pix = (int64_t)pj * width + pi;
         float *rgb = out_rgb + (int64_t)pose * 3 * hw;
@@ -292,7 +399,26 @@ void launch_blend_t(hipStream_t s, const float4 *records, int64_t n, int n_poses
                        depth, tfinal, counters);
 }
 
+// Backward of the compositing: one 256-thread block per (tile, pose), the
+// forward's walk (chunks of 252 records).
+__global__ __launch_bounds__(kThreads) void k_blend_backward(
+    const float4 *__restrict__ records, int64_t n, const uint32_t *__restrict__ pairs,
+    const uint64_t *__restrict__ offsets, uint64_t capacity, int width, int height, int tiles_x, int n_tiles,
+    BlendConsts k, GradIo gio) {
+    blend_tile<false, 63, true>(blockIdx.x, blockIdx.y, records, n, pairs, offsets, capacity, width, height, tiles_x,
+                                 n_tiles, k, nullptr, nullptr, nullptr, nullptr, gio);
+}
+
 }  // namespace
+
+void launch_blend_backward(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
+                           const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
+                           const TileGrid &tg, const float *img_rgb, const float *img_depth, const float *g_rgb,
+                           const float *g_depth, float *gscreen) {
+    const GradIo gio{img_rgb, img_depth, g_rgb, g_depth, gscreen};
+    hipLaunchKernelGGL(k_blend_backward, dim3((unsigned)tg.n_tiles, (unsigned)n_poses), dim3(kThreads), 0, s, records,
+                       n, pairs, offsets, capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, blend_consts(k), gio);
+}
 
 bool blend_chunk_supported(int chunk) { return chunk == 0 || chunk == 252 || chunk == 124 || chunk == 60; }
 

@@ -137,6 +137,14 @@ void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, 
                   unsigned long long *counters, int persistent_blocks, unsigned int *queue, int chunk);
 // Records per compositing chunk the blend is built for (0 = the default, 252).
 bool blend_chunk_supported(int chunk);
+// Screen-space gradients per (pose, Gaussian): u, v, conic A, B, C, opacity, r, g, b, z.
+constexpr int kScreenGrads = 10;
+// Backward of the compositing: adds the screen-space gradients of every (pose,
+// Gaussian) pair into gscreen [n_poses, n, kScreenGrads] (which the caller zeroes).
+void launch_blend_backward(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
+                           const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
+                           const TileGrid &tg, const float *img_rgb, const float *img_depth, const float *g_rgb,
+                           const float *g_depth, float *gscreen);
 
 // ---- ncc.hip ----
 int ncc_pixels_per_block();
@@ -148,15 +156,9 @@ void launch_gather_poses(hipStream_t s, const float *poses, const int32_t *order
 void launch_scatter_scores(hipStream_t s, const float *batch_scores, const int32_t *order, int nb, float *scores);
 
 // ---- backward.hip ----
-// Gradients per (pose, Gaussian) in screen space (u, v, A, B, C, opacity, r, g, b,
-// z) and per (pose, Gaussian) in parameter space (mean 3, covariance entries 6,
+// Gradients per (pose, Gaussian) in parameter space (mean 3, covariance entries 6,
 // opacity, r, g, b).
-int screen_grads_per_gaussian();
 int pose_grads_per_gaussian();
-void launch_blend_backward(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
-                           const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
-                           const TileGrid &tg, const float *img_rgb, const float *img_depth, const float *g_rgb,
-                           const float *g_depth, float *gscreen);
 void launch_project_backward(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
                              const Camera &cam, const Consts &k, const uint32_t *ntiles, const float *gscreen,
                              float *gpose);

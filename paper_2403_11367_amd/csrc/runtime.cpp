@@ -630,14 +630,13 @@ int gsr_render_backward(gsr_ctx *ctx, const gsr_submap *sm, const float *scales,
     HIPC(ctx, hipSetDevice(ctx->device));
     const int64_t n = sm->n, P = n_poses;
     const uint64_t pn = (uint64_t)std::max<int64_t>(1, P * n);
-    const int ns = gsr::screen_grads_per_gaussian(), np = gsr::pose_grads_per_gaussian();
+    const int ns = gsr::kScreenGrads, np = gsr::pose_grads_per_gaussian();
     int rc;
     if ((rc = ensure(ctx, ctx->bw_screen, pn * ns * sizeof(float), "screen-space gradients")) ||
         (rc = ensure(ctx, ctx->bw_pose, pn * np * sizeof(float), "per-pose gradients")))
         return rc;
     hipStream_t s = ctx->stream;
     const gsr::TileGrid &tg = ctx->last_tg;
-    const uint64_t T = (uint64_t)tg.n_tiles;
     const int64_t hw = (int64_t)ctx->last_cam.width * ctx->last_cam.height;
     float *gscreen = (float *)ctx->bw_screen.p;
     gsr::launch_fill_u32(s, (uint32_t *)gscreen, (uint64_t)P * n * ns, 0u);
@@ -651,7 +650,6 @@ int gsr_render_backward(gsr_ctx *ctx, const gsr_submap *sm, const float *scales,
                                    depth + gr.p0 * hw, grad_rgb + gr.p0 * 3 * hw, grad_depth + gr.p0 * hw,
                                    gscreen + (uint64_t)gr.p0 * n * ns);
     }
-    (void)T;
     gsr::launch_project_backward(s, sm->packed, n, poses, n_poses, ctx->last_cam, ctx->last_consts,
                                  (const uint32_t *)ctx->ntiles.p, gscreen, (float *)ctx->bw_pose.p);
     gsr::launch_param_grads(s, (const float *)ctx->bw_pose.p, n, n_poses, scales, quats, g_means, g_scales, g_quats,
