@@ -101,12 +101,6 @@ void launch_emit(hipStream_t s, const uint32_t *snt, const uint32_t *sg, const u
 // ---- sort.hip ----
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t value);
 void launch_fill_u64(hipStream_t s, unsigned long long *p, uint64_t n, unsigned long long value);
-// Exclusive scan of count[0..n) into offsets[0..n), total into offsets[n]. With
-// d_n, only the first min(*d_n, n) counts are read and offsets written.
-// tmp must hold scan_tmp_elems(n) uint64.
-uint64_t scan_tmp_elems(uint64_t n);
-void launch_scan(hipStream_t s, const uint32_t *count, uint64_t n, uint64_t *offsets, uint64_t *tmp,
-                 const uint32_t *d_n);
 // Per-pose stable sort of the visible Gaussians by depth bits. Input: the
 // preprocess's regions in (kb, vb) with vcount. Output: vb[vbase[p] ..
 // vbase[p+1]) = pose p's record slots front to back, kb = their tile counts,
@@ -120,15 +114,18 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
 // Exclusive scan of sums[0 .. nb_max) in place (only the first *d_nb with d_nb),
 // total to *total. One block.
 void launch_block_scan(hipStream_t s, uint64_t *sums, uint64_t nb_max, const uint64_t *d_nb, uint64_t *total);
-// Stable counting sort of the emitted pairs by tile within each pose. Writes
-// the per-(pose, tile) list offsets [P*T + 1] and the bucketed indices sk.
-// cnt holds bucket_blocks_max(capacity, P) * T entries, total P * T,
-// block_base P + 1, scan_tmp scan_tmp_elems(P * T);
-// 1 <= tile_bits <= 14 with 2^tile_bits >= n_tiles (n_tiles <= kMaxTilesPerPose).
-uint64_t bucket_blocks_max(uint64_t capacity, int n_poses);
+// Stable sort of the emitted pairs by tile within each pose, in two stable
+// passes (coarse buckets of 64 tiles, then tiles within a bucket). Writes the
+// per-(pose, tile) list offsets [P*T + 1] and the bucketed indices sk.
+// Workspace: block_base P * bucket_coarse(T) + 1 entries, cnt
+// bucket_count_elems(capacity, P, T), cstart P * bucket_coarse(T) + 1, ctile and
+// cval capacity. n_poses >= 1 and n_tiles <= kMaxTilesPerPose.
+int bucket_coarse(int n_tiles);
+uint64_t bucket_blocks_max(uint64_t capacity, int n_poses, int n_tiles);
+uint64_t bucket_count_elems(uint64_t capacity, int n_poses, int n_tiles);
 void launch_bucket(hipStream_t s, const uint16_t *ptile, const uint32_t *pk, const uint64_t *pseg, int n_poses,
-                   uint64_t capacity, int n_tiles, int tile_bits, uint32_t *block_base, uint32_t *cnt,
-                   uint32_t *total, uint64_t *offsets, uint64_t *scan_tmp, uint32_t *sk);
+                   uint64_t capacity, int n_tiles, uint32_t *block_base, uint32_t *cnt, uint64_t *cstart,
+                   uint16_t *ctile, uint32_t *cval, uint64_t *offsets, uint32_t *sk);
 
 // ---- blend.hip ----
 void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,

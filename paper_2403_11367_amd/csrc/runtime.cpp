@@ -52,18 +52,19 @@ struct gsr_ctx {
     struct Buf {
         void *p = nullptr;
         size_t bytes = 0;
-    } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, esum, pseg, scan_tmp,
-        ptile, pk, sk, cnt, total, block_base, offsets, grey_q, partials, s_order, s_poses, s_rgb, s_depth,
+    } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, esum, pseg, ptile, pk,
+        sk, ccnt, cstart, ctile, cval, block_base, offsets, grey_q, partials, s_order, s_poses, s_rgb, s_depth,
         s_scores, pr_grey, pr_q3, pr_x, pr_rgb, pr_depth, bw_screen, bw_pose;
     // layout of the last render's pose groups
     struct Group {
         int64_t p0 = 0, np = 0;        // poses [p0, p0 + np)
-        uint64_t vb = 0;               // vbase / pseg / block_base: np + 1 entries from here
+        uint64_t vb = 0;               // vbase / pseg: np + 1 entries from here
         uint64_t es = 0, n_eb = 0;     // emission sums: n_eb + 1 entries from es
         uint64_t off = 0;              // list offsets: np * T + 1 entries from here
-        uint64_t tmp = 0;              // scan scratch
+        uint64_t cst = 0;              // coarse bucket starts and bucketing block bases: np * coarse + 1
+                                       // entries each from here
         uint64_t pairs = 0, cap = 0;   // pair buffers: cap entries from pairs
-        uint64_t cnt = 0;              // bucket counts
+        uint64_t cnt = 0;              // coarse bucket counts
     };
     Group groups[kMaxGroups];
     int n_groups = 0;
@@ -281,12 +282,14 @@ int gsr_destroy(gsr_ctx *ctx) {
         if (ctx->chain[g]) (void)hipEventDestroy(ctx->chain[g]);
         if (ctx->join[g]) (void)hipEventDestroy(ctx->join[g]);
     }
-    gsr_ctx::Buf *bufs[] = {&ctx->records, &ctx->ntiles,  &ctx->rect,     &ctx->vcount,  &ctx->sort_ka,
-                            &ctx->sort_va, &ctx->sort_kb, &ctx->sort_vb,  &ctx->rcnt,    &ctx->roff,    &ctx->nv,
-                            &ctx->vbase,   &ctx->esum,    &ctx->pseg,     &ctx->scan_tmp, &ctx->ptile,
-                            &ctx->pk,      &ctx->sk,      &ctx->cnt,      &ctx->total,   &ctx->block_base,
-                            &ctx->offsets, &ctx->grey_q,  &ctx->partials, &ctx->s_order, &ctx->s_poses,
-                            &ctx->s_rgb,   &ctx->s_depth, &ctx->s_scores};
+    gsr_ctx::Buf *bufs[] = {&ctx->records,   &ctx->ntiles,  &ctx->rect,      &ctx->vcount,    &ctx->sort_ka,
+                            &ctx->sort_va,   &ctx->sort_kb, &ctx->sort_vb,   &ctx->rcnt,      &ctx->roff,
+                            &ctx->nv,        &ctx->vbase,   &ctx->esum,      &ctx->pseg,      &ctx->ptile,
+                            &ctx->pk,        &ctx->sk,      &ctx->ccnt,      &ctx->cstart,    &ctx->ctile,
+                            &ctx->cval,      &ctx->block_base, &ctx->offsets, &ctx->grey_q,   &ctx->partials,
+                            &ctx->s_order,   &ctx->s_poses, &ctx->s_rgb,     &ctx->s_depth,   &ctx->s_scores,
+                            &ctx->pr_grey,   &ctx->pr_q3,   &ctx->pr_x,      &ctx->pr_rgb,    &ctx->pr_depth,
+                            &ctx->bw_screen, &ctx->bw_pose};
     for (auto *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
@@ -426,7 +429,8 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
     // costs about as much launch latency as the ordering of all poses at once.
     int G = cfg.pose_groups ? cfg.pose_groups : 1;
     G = (int)std::min<int64_t>(G, P);
-    uint64_t n_es = 0, n_tmp = 0;
+    const uint64_t NC = (uint64_t)gsr::bucket_coarse(tg.n_tiles);
+    uint64_t n_es = 0, n_cst = 0;
     for (int g = 0; g < G; ++g) {
         gsr_ctx::Group &gr = ctx->groups[g];
         gr.p0 = P * g / G;
@@ -436,8 +440,8 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         gr.es = n_es;
         n_es += gr.n_eb + 1;
         gr.off = (uint64_t)gr.p0 * T + g;
-        gr.tmp = n_tmp;
-        n_tmp += gsr::scan_tmp_elems((uint64_t)gr.np * T);
+        gr.cst = n_cst;
+        n_cst += (uint64_t)gr.np * NC + 1;
     }
     ctx->n_groups = G;
 
@@ -456,10 +460,9 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         (rc = ensure(ctx, ctx->vbase, ((uint64_t)P + G) * sizeof(uint32_t), "pose bases")) ||
         (rc = ensure(ctx, ctx->esum, n_es * sizeof(uint64_t), "emission sums")) ||
         (rc = ensure(ctx, ctx->pseg, ((uint64_t)P + G) * sizeof(uint64_t), "pair segments")) ||
-        (rc = ensure(ctx, ctx->scan_tmp, n_tmp * sizeof(uint64_t), "scan")) ||
+        (rc = ensure(ctx, ctx->cstart, n_cst * sizeof(uint64_t), "coarse bucket starts")) ||
         (rc = ensure(ctx, ctx->offsets, (n_lists + G) * sizeof(uint64_t), "offsets")) ||
-        (rc = ensure(ctx, ctx->total, n_lists * sizeof(uint32_t), "list totals")) ||
-        (rc = ensure(ctx, ctx->block_base, ((uint64_t)P + G) * sizeof(uint32_t), "block bases")))
+        (rc = ensure(ctx, ctx->block_base, n_cst * sizeof(uint32_t), "block bases")))
         return rc;
     // with a fixed capacity every buffer is sized now, before any launch
     auto size_pairs = [&](const uint64_t *caps) -> int {
@@ -470,13 +473,15 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
             gr.pairs = n_pairs;
             n_pairs += std::max<uint64_t>(1, gr.cap);
             gr.cnt = n_cnt;
-            n_cnt += gsr::bucket_blocks_max(gr.cap, (int)gr.np) * T;
+            n_cnt += gsr::bucket_count_elems(gr.cap, (int)gr.np, tg.n_tiles);
         }
         int r;
         if ((r = ensure(ctx, ctx->ptile, n_pairs * sizeof(uint16_t), "pair tiles")) ||
             (r = ensure(ctx, ctx->pk, n_pairs * sizeof(uint32_t), "pair indices")) ||
             (r = ensure(ctx, ctx->sk, n_pairs * sizeof(uint32_t), "list indices")) ||
-            (r = ensure(ctx, ctx->cnt, n_cnt * sizeof(uint32_t), "bucket counts")))
+            (r = ensure(ctx, ctx->ctile, n_pairs * sizeof(uint16_t), "bucketed pair tiles")) ||
+            (r = ensure(ctx, ctx->cval, n_pairs * sizeof(uint32_t), "bucketed pair indices")) ||
+            (r = ensure(ctx, ctx->ccnt, n_cnt * sizeof(uint32_t), "bucket counts")))
             return r;
         return GSR_OK;
     };
@@ -495,8 +500,6 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
     uint32_t *vbase = (uint32_t *)ctx->vbase.p;
     uint64_t *esum = (uint64_t *)ctx->esum.p;
     const float4 *records = (const float4 *)ctx->records.p;
-    int tile_bits = 1;
-    while ((1 << tile_bits) < tg.n_tiles) ++tile_bits;
     const int64_t hw = (int64_t)cam->width * cam->height;
 
     gsr_ctx::RenderEv *ev = nullptr;
@@ -534,10 +537,11 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
                                   (uint64_t *)ctx->pseg.p + gr.vb);
         gsr::launch_emit(st, sort_kb + so, sort_vb + so, vbase + gr.vb, (int)gr.np, (const uint2 *)ctx->rect.p, n, gpn,
                          esum + gr.es, tg, ptile, pk, gr.cap, ctx->d_flags);
-        gsr::launch_bucket(st, ptile, pk, (uint64_t *)ctx->pseg.p + gr.vb, (int)gr.np, gr.cap, tg.n_tiles, tile_bits,
-                           (uint32_t *)ctx->block_base.p + gr.vb, (uint32_t *)ctx->cnt.p + gr.cnt,
-                           (uint32_t *)ctx->total.p + (uint64_t)gr.p0 * T, (uint64_t *)ctx->offsets.p + gr.off,
-                           (uint64_t *)ctx->scan_tmp.p + gr.tmp, (uint32_t *)ctx->sk.p + gr.pairs);
+        gsr::launch_bucket(st, ptile, pk, (uint64_t *)ctx->pseg.p + gr.vb, (int)gr.np, gr.cap, tg.n_tiles,
+                           (uint32_t *)ctx->block_base.p + gr.cst, (uint32_t *)ctx->ccnt.p + gr.cnt,
+                           (uint64_t *)ctx->cstart.p + gr.cst, (uint16_t *)ctx->ctile.p + gr.pairs,
+                           (uint32_t *)ctx->cval.p + gr.pairs, (uint64_t *)ctx->offsets.p + gr.off,
+                           (uint32_t *)ctx->sk.p + gr.pairs);
     };
     auto composite = [&](int g, hipStream_t st) {
         const gsr_ctx::Group &gr = ctx->groups[g];

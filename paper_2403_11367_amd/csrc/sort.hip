@@ -8,9 +8,9 @@
 //   1. per pose, the visible Gaussians are sorted by their float32 depth bits
 //      with a stable LSD radix sort (four 8-bit digits). Its input is in index
 //      order, so equal depths stay in index order;
-//   2. the pairs are emitted in that order (geometry.hip) and a stable counting
-//      sort by tile buckets them into per-(pose, tile) lists, which keeps the
-//      depth order inside every list.
+//   2. the pairs are emitted in that order (geometry.hip) and a stable sort by
+//      tile (two passes: buckets of 64 tiles, then tiles) buckets them into
+//      per-(pose, tile) lists, which keeps the depth order inside every list.
 // Every rank is computed from counts and prefix sums (no ordering by atomics),
 // so the result does not depend on scheduling.
 #include "internal.h"
@@ -20,8 +20,6 @@ namespace gsr {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kScanItems = 8;  // per thread
-constexpr int kScanTile = kThreads * kScanItems;
 
 __global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
@@ -47,24 +45,6 @@ __device__ uint64_t block_inclusive_scan(uint64_t x, uint64_t *s_wave /*[4]*/) {
     for (int w = 0; w < wave; ++w) add += s_wave[w];
     __syncthreads();
     return x + add;
-}
-
-__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ count, uint64_t n_max,
-                                                          const uint32_t *__restrict__ d_n,
-                                                          uint64_t *__restrict__ block_sums) {
-    __shared__ uint64_t s_wave[4];
-    const uint64_t n = d_n ? min((uint64_t)*d_n, n_max) : n_max;
-    if ((uint64_t)blockIdx.x * kScanTile >= n) {  // whole block past the end
-        if (threadIdx.x == 0) block_sums[blockIdx.x] = 0;
-        return;
-    }
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
-    uint64_t sum = 0;
-#pragma unroll
-    for (int i = 0; i < kScanItems; ++i)
-        if (base + i < n) sum += count[base + i];
-    const uint64_t inc = block_inclusive_scan(sum, s_wave);
-    if (threadIdx.x == kThreads - 1) block_sums[blockIdx.x] = inc;
 }
 
 // Single block of kBigThreads: exclusive scan of the block sums in place (4 per
@@ -110,29 +90,6 @@ __global__ __launch_bounds__(kBigThreads) void k_scan_blocks(uint64_t *__restric
         __syncthreads();
     }
     if (threadIdx.x == 0) *out_total = s_carry;
-}
-
-__global__ __launch_bounds__(kThreads) void k_scan_apply(const uint32_t *__restrict__ count, uint64_t n_max,
-                                                         const uint32_t *__restrict__ d_n,
-                                                         const uint64_t *__restrict__ block_prefix,
-                                                         uint64_t *__restrict__ offsets) {
-    __shared__ uint64_t s_wave[4];
-    const uint64_t n = d_n ? min((uint64_t)*d_n, n_max) : n_max;
-    if ((uint64_t)blockIdx.x * kScanTile >= n) return;
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint64_t sum = 0;
-#pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        v[i] = base + i < n ? count[base + i] : 0u;
-        sum += v[i];
-    }
-    uint64_t run = block_inclusive_scan(sum, s_wave) - sum + block_prefix[blockIdx.x];
-#pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        if (base + i < n) offsets[base + i] = run;
-        run += v[i];
-    }
 }
 
 // ---- per-pose depth sort: stable LSD radix sort of the visible Gaussians ----
@@ -337,39 +294,78 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int 
     }
 }
 
-// ---- tile bucketing: a stable counting sort of the pairs by tile, per pose ----
+// ---- tile bucketing: a stable sort of the pairs by tile, per pose ----
 // The pairs of pose p occupy [pseg[p], pseg[p+1]) of the emission arrays, in
-// front-to-back order. They are cut into blocks of kBP pairs; each block
-// counts its pairs per tile, the counts are summed per (pose, tile) and
-// scanned into list offsets, and each block then writes its pairs to
-// offset(list) + (pairs of the list in earlier blocks) + (rank within the
-// block), which keeps the emission order inside every list.
-constexpr int kBP = 4096;
+// front-to-back order. They are sorted by tile in two stable passes of one
+// segmented counting sort:
+//   A. segments = poses, key = coarse bucket (tile >> 6: 64 consecutive tiles);
+//   B. segments = (pose, bucket) ranges of A's output, key = tile & 63.
+// A pass cuts every segment into blocks of kCB pairs. Each block counts its
+// pairs per key; one block per segment scans the counts in (key, block) order,
+// which gives every block the position of its first pair of each key and gives
+// the segment the start of each key's run (A: the buckets, B: the tile lists,
+// written as the list offsets); each block then writes its pairs in order.
+// Both passes keep the emission order among equal keys, so every list is in
+// front-to-back order. A block writes runs of about kCB / keys pairs (A: 33
+// buckets, B: 64 tiles at 1408x376), so the scattered stores fill whole cache
+// lines, and no block holds more than kCB pairs however skewed the lists are.
+constexpr int kFineBits = 6;
+constexpr int kFine = 1 << kFineBits;               // tiles per coarse bucket
+constexpr int kMaxKeys = 256;                       // keys per pass
+constexpr int kCBWaves = 8;
+constexpr int kCBThreads = 64 * kCBWaves;
+constexpr int kCBWave = 1024;                       // pairs per wave, contiguous
+constexpr int kCB = kCBWaves * kCBWave;             // pairs per block
+constexpr int kCBChunks = kCBWave / 64;
 
-// block_base[p] = sum over q < p of ceil(len(q) / kBP), for p in [0, P]. One block.
-__global__ __launch_bounds__(kThreads) void k_seg_blocks(const uint64_t *__restrict__ pseg, int P,
+// Lanes of the wave whose `key` (its low kBits bits) equals this lane's, among
+// the lanes with `valid`; 0 when not valid.
+template <int kBits>
+__device__ __forceinline__ uint64_t match_peers(uint32_t key, bool valid) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kBits; ++b) {
+        const bool bit = (key >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return valid ? peers : 0ull;
+}
+
+// A pass: segment i is [seg[i], seg[i+1]) of the input arrays; the key of a
+// pair is (tile >> shift) & mask, one of n_keys.
+struct SegPass {
+    const uint64_t *seg;
+    int n_seg;
+    int shift;
+    uint32_t mask;
+    int n_keys;
+};
+
+// block_base[i] = sum over j < i of ceil(len(j) / kCB), for i in [0, n_seg]. One block.
+__global__ __launch_bounds__(kThreads) void k_seg_blocks(const uint64_t *__restrict__ seg, int n_seg,
                                                          uint32_t *__restrict__ block_base) {
     __shared__ uint64_t s_wave[4];
     __shared__ uint64_t s_carry;
     if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
-    for (int c0 = 0; c0 <= P; c0 += kThreads) {
-        const int p = c0 + threadIdx.x;
+    for (int c0 = 0; c0 <= n_seg; c0 += kThreads) {
+        const int i = c0 + threadIdx.x;
         uint64_t nb = 0;
-        if (p < P) nb = (pseg[p + 1] - pseg[p] + kBP - 1) / kBP;
+        if (i < n_seg) nb = (seg[i + 1] - seg[i] + kCB - 1) / kCB;
         const uint64_t inc = block_inclusive_scan(nb, s_wave);
         const uint64_t carry = s_carry;
-        if (p <= P) block_base[p] = (uint32_t)(carry + inc - nb);
+        if (i <= n_seg) block_base[i] = (uint32_t)(carry + inc - nb);
         __syncthreads();
         if (threadIdx.x == kThreads - 1) s_carry = carry + inc;
         __syncthreads();
     }
 }
 
-// Pose of bucketing block gb (block_base is non-decreasing); -1 past the last block.
-__device__ __forceinline__ int block_pose(const uint32_t *block_base, int P, uint32_t gb) {
-    if (gb >= block_base[P]) return -1;
-    int lo = 0, hi = P - 1;  // largest p with block_base[p] <= gb
+// Segment of block gb (block_base is non-decreasing); -1 past the last block.
+__device__ __forceinline__ int block_segment(const uint32_t *block_base, int n_seg, uint32_t gb) {
+    if (gb >= block_base[n_seg]) return -1;
+    int lo = 0, hi = n_seg - 1;  // largest i with block_base[i] <= gb
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (block_base[mid] <= gb)
@@ -380,126 +376,156 @@ __device__ __forceinline__ int block_pose(const uint32_t *block_base, int P, uin
     return lo;
 }
 
-__global__ __launch_bounds__(kThreads) void k_tile_count(const uint16_t *__restrict__ ptile,
-                                                         const uint64_t *__restrict__ pseg, int P,
-                                                         const uint32_t *__restrict__ block_base, int n_tiles,
-                                                         uint32_t *__restrict__ cnt) {
-    extern __shared__ uint32_t s_hist[];
+// Loads block gb's pairs: wave w holds pairs w * kCBWave + 64 c + lane of the
+// block in tile[c] (0xffffffff past the segment's end) and, with vals, val[c].
+__device__ __forceinline__ void seg_load(const SegPass &ps, const uint32_t *block_base, int i, uint32_t gb,
+                                         const uint16_t *tiles, const uint32_t *vals, uint32_t *tile, uint32_t *val) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t b0 = ps.seg[i] + (uint64_t)(gb - block_base[i]) * kCB + (uint64_t)wave * kCBWave + lane;
+    const uint64_t end = ps.seg[i + 1];
+#pragma unroll
+    for (int c = 0; c < kCBChunks; ++c) {
+        const uint64_t j = b0 + (uint64_t)c * 64;
+        const bool valid = j < end;
+        tile[c] = valid ? (uint32_t)tiles[j] : 0xffffffffu;
+        if (vals) val[c] = valid ? vals[j] : 0u;
+    }
+}
+
+// cnt[gb * n_keys + k] = pairs of block gb with key k.
+template <int kBits>
+__global__ __launch_bounds__(kCBThreads) void k_seg_count(SegPass ps, const uint32_t *__restrict__ block_base,
+                                                          const uint16_t *__restrict__ tiles,
+                                                          uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t s_h[kMaxKeys];
     const uint32_t gb = blockIdx.x;
-    const int p = block_pose(block_base, P, gb);
-    if (p < 0) return;
-    for (int t = threadIdx.x; t < n_tiles; t += kThreads) s_hist[t] = 0;
+    const int i = block_segment(block_base, ps.n_seg, gb);
+    if (i < 0) return;
+    const int lane = threadIdx.x & 63;
+    for (int k = threadIdx.x; k < ps.n_keys; k += kCBThreads) s_h[k] = 0;
     __syncthreads();
-    const uint64_t beg = pseg[p] + (uint64_t)(gb - block_base[p]) * kBP;
-    const uint64_t end = min(beg + kBP, pseg[p + 1]);
-    for (uint64_t i = beg + threadIdx.x; i < end; i += kThreads) atomicAdd(&s_hist[ptile[i]], 1u);
-    __syncthreads();
-    for (int t = threadIdx.x; t < n_tiles; t += kThreads) cnt[(uint64_t)gb * n_tiles + t] = s_hist[t];
-}
-
-// total[p * T + t] = pairs of list (p, t), summed over the pose's blocks
-// (8 rows per step, so several loads are in flight per thread).
-__global__ void k_col_sum(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ block_base, int P,
-                          int n_tiles, uint32_t *__restrict__ total) {
-    const uint64_t l = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= (uint64_t)P * n_tiles) return;
-    const int p = (int)(l / n_tiles), t = (int)(l % n_tiles);
-    const uint32_t gb1 = block_base[p + 1];
-    uint32_t gb = block_base[p], sum = 0;
-    for (; gb + 8 <= gb1; gb += 8) {
-        uint32_t v[8];
+    uint32_t tile[kCBChunks];
+    seg_load(ps, block_base, i, gb, tiles, nullptr, tile, nullptr);
+    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = cnt[(uint64_t)(gb + u) * n_tiles + t];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) sum += v[u];
+    for (int c = 0; c < kCBChunks; ++c) {
+        const bool valid = tile[c] != 0xffffffffu;
+        const uint32_t key = valid ? (tile[c] >> ps.shift) & ps.mask : 0u;
+        const uint64_t peers = match_peers<kBits>(key, valid);
+        if (valid && (peers & lt_mask) == 0) atomicAdd(&s_h[key], (uint32_t)__popcll(peers));
     }
-    for (; gb < gb1; ++gb) sum += cnt[(uint64_t)gb * n_tiles + t];
-    total[l] = sum;
+    __syncthreads();
+    for (int k = threadIdx.x; k < ps.n_keys; k += kCBThreads) cnt[(uint64_t)gb * ps.n_keys + k] = s_h[k];
 }
 
-// cnt[gb][t] <- first output position of block gb's pairs of list (p, t). The
-// lists of a pose hold exactly the pose's pairs [pseg[p], pseg[p+1]), so the
-// exclusive scan of the totals over all P * T lists is the list start.
-__global__ void k_col_prefix(uint32_t *__restrict__ cnt, const uint32_t *__restrict__ block_base, int P, int n_tiles,
-                             const uint64_t *__restrict__ offsets) {
-    const uint64_t l = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= (uint64_t)P * n_tiles) return;
-    const int p = (int)(l / n_tiles), t = (int)(l % n_tiles);
-    const uint32_t gb1 = block_base[p + 1];
-    uint32_t gb = block_base[p];
-    uint32_t run = (uint32_t)offsets[l];
-    for (; gb + 8 <= gb1; gb += 8) {
-        uint32_t v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = cnt[(uint64_t)(gb + u) * n_tiles + t];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            cnt[(uint64_t)(gb + u) * n_tiles + t] = run;
-            run += v[u];
+// One block per segment, thread = key: cnt[gb][k] <- position, relative to the
+// segment's first pair, of block gb's first pair with key k (keys in order,
+// blocks in order within a key). The start of key k's run (absolute) goes to
+// starts[(i / per_row) * row + (i % per_row) * n_keys + k] where that column is
+// below `row`; the block of the last segment also writes
+// starts[(n_seg / per_row) * row] = seg[n_seg].
+__global__ __launch_bounds__(kThreads) void k_seg_offsets(SegPass ps, uint32_t *__restrict__ cnt,
+                                                          const uint32_t *__restrict__ block_base, int per_row,
+                                                          int row, uint64_t *__restrict__ starts) {
+    __shared__ uint32_t s_wave[4];
+    const int i = blockIdx.x, k = threadIdx.x;
+    const uint32_t g0 = block_base[i], g1 = block_base[i + 1];
+    uint32_t tot = 0;
+    if (k < ps.n_keys)
+        for (uint32_t g = g0; g < g1; ++g) tot += cnt[(uint64_t)g * ps.n_keys + k];
+    uint32_t all = 0;
+    uint32_t run = block_exclusive_scan_u32(tot, s_wave, &all);
+    const int col = (i % per_row) * ps.n_keys + k;
+    if (k < ps.n_keys) {
+        if (col < row) starts[(uint64_t)(i / per_row) * row + col] = ps.seg[i] + run;
+        for (uint32_t g = g0; g < g1; ++g) {
+            const uint64_t j = (uint64_t)g * ps.n_keys + k;
+            const uint32_t x = cnt[j];
+            cnt[j] = run;
+            run += x;
         }
     }
-    for (; gb < gb1; ++gb) {
-        const uint64_t i = (uint64_t)gb * n_tiles + t;
-        const uint32_t c = cnt[i];
-        cnt[i] = run;
-        run += c;
-    }
+    if (k == 0 && i == ps.n_seg - 1) starts[(uint64_t)(ps.n_seg / per_row) * row] = ps.seg[ps.n_seg];
 }
 
-// One wave per block walks its pairs in order, 64 at a time (loads issued
-// kAhead chunks ahead): lanes that name the same tile are matched with
-// tile_bits ballots, take consecutive slots in lane order, and the group's
-// leader advances that tile's cursor in LDS with an atomic whose return value
-// (the group's first slot) is broadcast to the group.
-constexpr int kAhead = 4;
-
-template <int kTileBits>
-__global__ __launch_bounds__(64) void k_tile_scatter(const uint16_t *__restrict__ ptile,
-                                                     const uint32_t *__restrict__ pk,
-                                                     const uint64_t *__restrict__ pseg, int P,
-                                                     const uint32_t *__restrict__ block_base,
-                                                     const uint32_t *__restrict__ cnt, int n_tiles,
-                                                     uint32_t *__restrict__ sk) {
-    extern __shared__ uint32_t s_run[];
+// Scatter of block gb. Each wave ranks its pairs 64 at a time: lanes with equal
+// keys are matched with ballots and ranked in lane order; the group's leader
+// adds the group size to a per-wave, per-key LDS counter, and the value it
+// returns (the wave's earlier pairs with that key) is broadcast to the group.
+// One wave's LDS operations complete in program order, so the counters carry
+// the order across chunks without a barrier. The block then turns the per-wave
+// counts into output positions. out_tiles may be null (the last pass).
+template <int kBits>
+__global__ __launch_bounds__(kCBThreads) void k_seg_scatter(SegPass ps, const uint32_t *__restrict__ block_base,
+                                                            const uint32_t *__restrict__ offs,
+                                                            const uint16_t *__restrict__ tiles,
+                                                            const uint32_t *__restrict__ vals,
+                                                            uint16_t *__restrict__ out_tiles,
+                                                            uint32_t *__restrict__ out_vals) {
+    __shared__ uint32_t s_cnt[kCBWaves][kMaxKeys];
     const uint32_t gb = blockIdx.x;
-    const int p = block_pose(block_base, P, gb);
-    if (p < 0) return;
-    const int lane = threadIdx.x;
-    for (int t = lane; t < n_tiles; t += 64) s_run[t] = cnt[(uint64_t)gb * n_tiles + t];
+    const int i = block_segment(block_base, ps.n_seg, gb);
+    if (i < 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = threadIdx.x; j < kCBWaves * kMaxKeys; j += kCBThreads) (&s_cnt[0][0])[j] = 0;
     __syncthreads();
-    const uint64_t beg = pseg[p] + (uint64_t)(gb - block_base[p]) * kBP;
-    const uint64_t end = min(beg + kBP, pseg[p + 1]);
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (uint64_t c0 = beg; c0 < end; c0 += 64 * kAhead) {
-        uint32_t tt[kAhead], kk[kAhead];
+    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint32_t tile[kCBChunks], val[kCBChunks], rnk[kCBChunks];
+    seg_load(ps, block_base, i, gb, tiles, vals, tile, val);
 #pragma unroll
-        for (int a = 0; a < kAhead; ++a) {
-            const uint64_t i = c0 + a * 64 + lane;
-            const bool valid = i < end;
-            tt[a] = valid ? (uint32_t)ptile[i] : 0xffffffffu;
-            kk[a] = valid ? pk[i] : 0u;
+    for (int c = 0; c < kCBChunks; ++c) {
+        const bool valid = tile[c] != 0xffffffffu;
+        const uint32_t key = valid ? (tile[c] >> ps.shift) & ps.mask : 0u;
+        const uint64_t peers = match_peers<kBits>(key, valid);
+        const uint32_t r = (uint32_t)__popcll(peers & lt_mask);
+        uint32_t old = 0;
+        if (valid && r == 0) old = atomicAdd(&s_cnt[wave][key], (uint32_t)__popcll(peers));
+        const int leader = (int)__builtin_ctzll(peers | (1ull << 63));
+        const uint32_t base = (uint32_t)__shfl((int)old, leader, 64);
+        rnk[c] = valid ? base + r : 0xffffffffu;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < ps.n_keys; k += kCBThreads) {
+        // s_cnt[w][k] <- output position (relative to the segment) of wave w's first pair with key k
+        uint32_t run = offs[(uint64_t)gb * ps.n_keys + k];
+#pragma unroll
+        for (int w = 0; w < kCBWaves; ++w) {
+            const uint32_t x = s_cnt[w][k];
+            s_cnt[w][k] = run;
+            run += x;
         }
+    }
+    __syncthreads();
+    const uint64_t base = ps.seg[i];
 #pragma unroll
-        for (int a = 0; a < kAhead; ++a) {
-            const uint32_t t = tt[a];
-            const bool valid = t != 0xffffffffu;
-            uint64_t peers = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < kTileBits; ++b) {
-                const bool bit = (t >> b) & 1u;
-                const uint64_t m = __ballot(bit);
-                peers &= bit ? m : ~m;
-            }
-            if (!valid) peers = 0;
-            const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-            // one wave: its LDS operations complete in program order, so no barrier
-            // (which would also wait for the scattered global stores)
-            uint32_t old = 0;
-            if (valid && rank == 0) old = atomicAdd(&s_run[t], (uint32_t)__popcll(peers));
-            const int leader = (int)__builtin_ctzll(peers | (1ull << 63));
-            const uint32_t base = (uint32_t)__shfl((int)old, leader, 64);
-            if (valid) sk[base + rank] = kk[a];
-        }
+    for (int c = 0; c < kCBChunks; ++c) {
+        if (rnk[c] == 0xffffffffu) continue;
+        const uint64_t pos = base + s_cnt[wave][(tile[c] >> ps.shift) & ps.mask] + rnk[c];
+        if (out_tiles) out_tiles[pos] = (uint16_t)tile[c];
+        out_vals[pos] = val[c];
+    }
+}
+
+// One segmented pass: counts, offsets (run starts to `starts`), scatter.
+void launch_seg_pass(hipStream_t s, const SegPass &ps, uint64_t n_blocks, uint32_t *block_base, uint32_t *cnt,
+                     int per_row, int row, uint64_t *starts, const uint16_t *tiles, const uint32_t *vals,
+                     uint16_t *out_tiles, uint32_t *out_vals) {
+    int bits = 0;
+    while ((1 << bits) < ps.n_keys) ++bits;
+    hipLaunchKernelGGL(k_seg_blocks, dim3(1), dim3(kThreads), 0, s, ps.seg, ps.n_seg, block_base);
+    switch (bits) {
+#define GSR_SEG(B)                                                                                                 \
+    case B:                                                                                                        \
+        hipLaunchKernelGGL(k_seg_count<B>, dim3((unsigned)n_blocks), dim3(kCBThreads), 0, s, ps, block_base, tiles, \
+                           cnt);                                                                                   \
+        hipLaunchKernelGGL(k_seg_offsets, dim3((unsigned)ps.n_seg), dim3(kThreads), 0, s, ps, cnt, block_base,      \
+                           per_row, row, starts);                                                                  \
+        hipLaunchKernelGGL(k_seg_scatter<B>, dim3((unsigned)n_blocks), dim3(kCBThreads), 0, s, ps, block_base, cnt, \
+                           tiles, vals, out_tiles, out_vals);                                                      \
+        break;
+        GSR_SEG(0) GSR_SEG(1) GSR_SEG(2) GSR_SEG(3) GSR_SEG(4) GSR_SEG(5) GSR_SEG(6) GSR_SEG(7) GSR_SEG(8)
+#undef GSR_SEG
+        default: break;  // at most kMaxKeys keys
     }
 }
 
@@ -515,20 +541,6 @@ void launch_fill_u64(hipStream_t s, unsigned long long *p, uint64_t n, unsigned 
     if (n == 0) return;
     const uint64_t blocks = std::min<uint64_t>((n + kThreads - 1) / kThreads, 4096);
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(kThreads), 0, s, p, n, value);
-}
-
-uint64_t scan_tmp_elems(uint64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
-
-void launch_scan(hipStream_t s, const uint32_t *count, uint64_t n, uint64_t *offsets, uint64_t *tmp,
-                 const uint32_t *d_n) {
-    const uint64_t nb = (n + kScanTile - 1) / kScanTile;
-    if (nb == 0) {
-        launch_fill_u64(s, reinterpret_cast<unsigned long long *>(offsets), 1, 0ull);
-        return;
-    }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, count, n, d_n, tmp);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBigThreads), 0, s, tmp, nb, nullptr, offsets + n);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, count, n, d_n, tmp, offsets);
 }
 
 void launch_block_scan(hipStream_t s, uint64_t *sums, uint64_t nb_max, const uint64_t *d_nb, uint64_t *total) {
@@ -567,34 +579,29 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
     }
 }
 
-uint64_t bucket_blocks_max(uint64_t capacity, int n_poses) { return (capacity + kBP - 1) / kBP + (uint64_t)n_poses; }
+int bucket_coarse(int n_tiles) { return (n_tiles + kFine - 1) / kFine; }
+
+uint64_t bucket_blocks_max(uint64_t capacity, int n_poses, int n_tiles) {
+    // pass B has the most segments (poses x buckets), each with one partial block at most
+    return (capacity + kCB - 1) / kCB + (uint64_t)n_poses * bucket_coarse(n_tiles);
+}
+
+uint64_t bucket_count_elems(uint64_t capacity, int n_poses, int n_tiles) {
+    return bucket_blocks_max(capacity, n_poses, n_tiles) * std::max(bucket_coarse(n_tiles), kFine);
+}
 
 void launch_bucket(hipStream_t s, const uint16_t *ptile, const uint32_t *pk, const uint64_t *pseg, int n_poses,
-                   uint64_t capacity, int n_tiles, int tile_bits, uint32_t *block_base, uint32_t *cnt,
-                   uint32_t *total, uint64_t *offsets, uint64_t *scan_tmp, uint32_t *sk) {
-    const uint64_t nbm = bucket_blocks_max(capacity, n_poses);
-    const size_t lds = (size_t)n_tiles * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_seg_blocks, dim3(1), dim3(kThreads), 0, s, pseg, n_poses, block_base);
-    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)nbm), dim3(kThreads), lds, s, ptile, pseg, n_poses, block_base,
-                       n_tiles, cnt);
-    const uint64_t n_lists = (uint64_t)n_poses * n_tiles;
-    const unsigned lblocks = (unsigned)((n_lists + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_col_sum, dim3(lblocks), dim3(kThreads), 0, s, cnt, block_base, n_poses, n_tiles, total);
-    launch_scan(s, total, n_lists, offsets, scan_tmp, nullptr);
-    hipLaunchKernelGGL(k_col_prefix, dim3(lblocks), dim3(kThreads), 0, s, cnt, block_base, n_poses, n_tiles, offsets);
-    const dim3 grid((unsigned)nbm), block(64);
-    switch (tile_bits) {
-#define GSR_SCATTER(B)                                                                                          \
-    case B:                                                                                                     \
-        hipLaunchKernelGGL(k_tile_scatter<B>, grid, block, lds, s, ptile, pk, pseg, n_poses, block_base, cnt,   \
-                           n_tiles, sk);                                                                        \
-        break;
-        GSR_SCATTER(1) GSR_SCATTER(2) GSR_SCATTER(3) GSR_SCATTER(4) GSR_SCATTER(5) GSR_SCATTER(6) GSR_SCATTER(7)
-        GSR_SCATTER(8) GSR_SCATTER(9) GSR_SCATTER(10) GSR_SCATTER(11) GSR_SCATTER(12) GSR_SCATTER(13)
-        GSR_SCATTER(14)
-#undef GSR_SCATTER
-        default: break;  // n_tiles <= kMaxTilesPerPose = 2^14 is checked by the caller
-    }
+                   uint64_t capacity, int n_tiles, uint32_t *block_base, uint32_t *cnt, uint64_t *cstart,
+                   uint16_t *ctile, uint32_t *cval, uint64_t *offsets, uint32_t *sk) {
+    if (n_poses <= 0) return;
+    const int n_coarse = bucket_coarse(n_tiles);
+    const uint64_t nbm = bucket_blocks_max(capacity, n_poses, n_tiles);
+    // A: poses -> buckets; cstart[p * n_coarse + b] = first pair of bucket (p, b), cstart[P * n_coarse] = pseg[P]
+    const SegPass a{pseg, n_poses, kFineBits, 0xffffu, n_coarse};
+    launch_seg_pass(s, a, nbm, block_base, cnt, 1, n_coarse, cstart, ptile, pk, ctile, cval);
+    // B: buckets -> tiles; offsets[p * n_tiles + t] = first pair of list (p, t), offsets[P * n_tiles] = pseg[P]
+    const SegPass b{cstart, n_poses * n_coarse, 0, (uint32_t)(kFine - 1), kFine};
+    launch_seg_pass(s, b, nbm, block_base, cnt, n_coarse, n_tiles, offsets, ctile, cval, nullptr, sk);
 }
 
 }  // namespace gsr
