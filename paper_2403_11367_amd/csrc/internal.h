@@ -117,15 +117,16 @@ void launch_block_scan(hipStream_t s, uint64_t *sums, uint64_t nb_max, const uin
 // Stable sort of the emitted pairs by tile within each pose, in two stable
 // passes (coarse buckets of 64 tiles, then tiles within a bucket). Writes the
 // per-(pose, tile) list offsets [P*T + 1] and the bucketed indices sk.
-// Workspace: block_base P * bucket_coarse(T) + 1 entries, cnt
-// bucket_count_elems(capacity, P, T), cstart P * bucket_coarse(T) + 1, ctile and
-// cval capacity. n_poses >= 1 and n_tiles <= kMaxTilesPerPose.
+// Workspace: block_base P * bucket_coarse(T) + 1 entries, bseg
+// bucket_blocks_max(capacity, P, T), cnt bucket_count_elems(capacity, P, T),
+// cstart P * bucket_coarse(T) + 1, ctile and cval capacity. n_poses >= 1 and
+// n_tiles <= kMaxTilesPerPose.
 int bucket_coarse(int n_tiles);
 uint64_t bucket_blocks_max(uint64_t capacity, int n_poses, int n_tiles);
 uint64_t bucket_count_elems(uint64_t capacity, int n_poses, int n_tiles);
 void launch_bucket(hipStream_t s, const uint16_t *ptile, const uint32_t *pk, const uint64_t *pseg, int n_poses,
-                   uint64_t capacity, int n_tiles, uint32_t *block_base, uint32_t *cnt, uint64_t *cstart,
-                   uint16_t *ctile, uint32_t *cval, uint64_t *offsets, uint32_t *sk);
+                   uint64_t capacity, int n_tiles, uint32_t *block_base, uint32_t *bseg, uint32_t *cnt,
+                   uint64_t *cstart, uint16_t *ctile, uint32_t *cval, uint64_t *offsets, uint32_t *sk);
 
 // ---- blend.hip ----
 void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,

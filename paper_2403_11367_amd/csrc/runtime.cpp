@@ -53,7 +53,7 @@ struct gsr_ctx {
         void *p = nullptr;
         size_t bytes = 0;
     } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, esum, pseg, ptile, pk,
-        sk, ccnt, cstart, ctile, cval, block_base, offsets, grey_q, partials, s_order, s_poses, s_rgb, s_depth,
+        sk, ccnt, cstart, ctile, cval, block_base, bseg, offsets, grey_q, partials, s_order, s_poses, s_rgb, s_depth,
         s_scores, pr_grey, pr_q3, pr_x, pr_rgb, pr_depth, bw_screen, bw_pose;
     // layout of the last render's pose groups
     struct Group {
@@ -64,7 +64,8 @@ struct gsr_ctx {
         uint64_t cst = 0;              // coarse bucket starts and bucketing block bases: np * coarse + 1
                                        // entries each from here
         uint64_t pairs = 0, cap = 0;   // pair buffers: cap entries from pairs
-        uint64_t cnt = 0;              // coarse bucket counts
+        uint64_t cnt = 0;              // bucketing counts
+        uint64_t bsg = 0;              // bucketing block -> segment map
     };
     Group groups[kMaxGroups];
     int n_groups = 0;
@@ -286,7 +287,7 @@ int gsr_destroy(gsr_ctx *ctx) {
                             &ctx->sort_va,   &ctx->sort_kb, &ctx->sort_vb,   &ctx->rcnt,      &ctx->roff,
                             &ctx->nv,        &ctx->vbase,   &ctx->esum,      &ctx->pseg,      &ctx->ptile,
                             &ctx->pk,        &ctx->sk,      &ctx->ccnt,      &ctx->cstart,    &ctx->ctile,
-                            &ctx->cval,      &ctx->block_base, &ctx->offsets, &ctx->grey_q,   &ctx->partials,
+                            &ctx->cval,      &ctx->block_base, &ctx->bseg, &ctx->offsets, &ctx->grey_q, &ctx->partials,
                             &ctx->s_order,   &ctx->s_poses, &ctx->s_rgb,     &ctx->s_depth,   &ctx->s_scores,
                             &ctx->pr_grey,   &ctx->pr_q3,   &ctx->pr_x,      &ctx->pr_rgb,    &ctx->pr_depth,
                             &ctx->bw_screen, &ctx->bw_pose};
@@ -466,7 +467,7 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         return rc;
     // with a fixed capacity every buffer is sized now, before any launch
     auto size_pairs = [&](const uint64_t *caps) -> int {
-        uint64_t n_pairs = 0, n_cnt = 0;
+        uint64_t n_pairs = 0, n_cnt = 0, n_bsg = 0;
         for (int g = 0; g < G; ++g) {
             gsr_ctx::Group &gr = ctx->groups[g];
             gr.cap = caps[g];
@@ -474,6 +475,8 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
             n_pairs += std::max<uint64_t>(1, gr.cap);
             gr.cnt = n_cnt;
             n_cnt += gsr::bucket_count_elems(gr.cap, (int)gr.np, tg.n_tiles);
+            gr.bsg = n_bsg;
+            n_bsg += gsr::bucket_blocks_max(gr.cap, (int)gr.np, tg.n_tiles);
         }
         int r;
         if ((r = ensure(ctx, ctx->ptile, n_pairs * sizeof(uint16_t), "pair tiles")) ||
@@ -481,7 +484,8 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
             (r = ensure(ctx, ctx->sk, n_pairs * sizeof(uint32_t), "list indices")) ||
             (r = ensure(ctx, ctx->ctile, n_pairs * sizeof(uint16_t), "bucketed pair tiles")) ||
             (r = ensure(ctx, ctx->cval, n_pairs * sizeof(uint32_t), "bucketed pair indices")) ||
-            (r = ensure(ctx, ctx->ccnt, n_cnt * sizeof(uint32_t), "bucket counts")))
+            (r = ensure(ctx, ctx->ccnt, n_cnt * sizeof(uint32_t), "bucket counts")) ||
+            (r = ensure(ctx, ctx->bseg, n_bsg * sizeof(uint32_t), "bucket block segments")))
             return r;
         return GSR_OK;
     };
@@ -538,7 +542,8 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         gsr::launch_emit(st, sort_kb + so, sort_vb + so, vbase + gr.vb, (int)gr.np, (const uint2 *)ctx->rect.p, n, gpn,
                          esum + gr.es, tg, ptile, pk, gr.cap, ctx->d_flags);
         gsr::launch_bucket(st, ptile, pk, (uint64_t *)ctx->pseg.p + gr.vb, (int)gr.np, gr.cap, tg.n_tiles,
-                           (uint32_t *)ctx->block_base.p + gr.cst, (uint32_t *)ctx->ccnt.p + gr.cnt,
+                           (uint32_t *)ctx->block_base.p + gr.cst, (uint32_t *)ctx->bseg.p + gr.bsg,
+                           (uint32_t *)ctx->ccnt.p + gr.cnt,
                            (uint64_t *)ctx->cstart.p + gr.cst, (uint16_t *)ctx->ctile.p + gr.pairs,
                            (uint32_t *)ctx->cval.p + gr.pairs, (uint64_t *)ctx->offsets.p + gr.off,
                            (uint32_t *)ctx->sk.p + gr.pairs);

@@ -182,12 +182,30 @@ __global__ __launch_bounds__(kThreads) void k_radix_offsets(const uint32_t *__re
     const int d = threadIdx.x;
     const uint32_t nb = nv ? nbp : (uint32_t)(((uint64_t)vbase[p + 1] - vbase[p] + kRB - 1) / kRB);
     const uint32_t *c = cnt + (uint64_t)p * nbp * kDigits + d;
-    uint32_t tot = 0;
-    for (uint32_t j = 0; j < nb; ++j) tot += c[(uint64_t)j * kDigits];
+    // 8 blocks per step, so several loads are in flight per thread
+    uint32_t tot = 0, j = 0;
+    for (; j + 8 <= nb; j += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = c[(uint64_t)(j + u) * kDigits];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tot += v[u];
+    }
+    for (; j < nb; ++j) tot += c[(uint64_t)j * kDigits];
     uint32_t all = 0;
     uint32_t run = block_exclusive_scan_u32(tot, s_wave, &all);
     uint32_t *o = off + (uint64_t)p * nbp * kDigits + d;
-    for (uint32_t j = 0; j < nb; ++j) {
+    for (j = 0; j + 8 <= nb; j += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = c[(uint64_t)(j + u) * kDigits];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            o[(uint64_t)(j + u) * kDigits] = run;
+            run += v[u];
+        }
+    }
+    for (; j < nb; ++j) {
         const uint32_t x = c[(uint64_t)j * kDigits];
         o[(uint64_t)j * kDigits] = run;
         run += x;
@@ -342,9 +360,11 @@ struct SegPass {
     int n_keys;
 };
 
-// block_base[i] = sum over j < i of ceil(len(j) / kCB), for i in [0, n_seg]. One block.
+// block_base[i] = sum over j < i of ceil(len(j) / kCB), for i in [0, n_seg], and
+// bseg[gb] = the segment of block gb for gb < block_base[n_seg]. One block.
 __global__ __launch_bounds__(kThreads) void k_seg_blocks(const uint64_t *__restrict__ seg, int n_seg,
-                                                         uint32_t *__restrict__ block_base) {
+                                                         uint32_t *__restrict__ block_base,
+                                                         uint32_t *__restrict__ bseg) {
     __shared__ uint64_t s_wave[4];
     __shared__ uint64_t s_carry;
     if (threadIdx.x == 0) s_carry = 0;
@@ -355,62 +375,61 @@ __global__ __launch_bounds__(kThreads) void k_seg_blocks(const uint64_t *__restr
         if (i < n_seg) nb = (seg[i + 1] - seg[i] + kCB - 1) / kCB;
         const uint64_t inc = block_inclusive_scan(nb, s_wave);
         const uint64_t carry = s_carry;
-        if (i <= n_seg) block_base[i] = (uint32_t)(carry + inc - nb);
+        const uint32_t first = (uint32_t)(carry + inc - nb);
+        if (i <= n_seg) block_base[i] = first;
+        for (uint64_t j = 0; j < nb; ++j) bseg[first + j] = (uint32_t)i;
         __syncthreads();
         if (threadIdx.x == kThreads - 1) s_carry = carry + inc;
         __syncthreads();
     }
 }
 
-// Segment of block gb (block_base is non-decreasing); -1 past the last block.
-__device__ __forceinline__ int block_segment(const uint32_t *block_base, int n_seg, uint32_t gb) {
-    if (gb >= block_base[n_seg]) return -1;
-    int lo = 0, hi = n_seg - 1;  // largest i with block_base[i] <= gb
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (block_base[mid] <= gb)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
+// Segment of block gb; -1 past the last block.
+__device__ __forceinline__ int block_segment(const uint32_t *block_base, const uint32_t *bseg, int n_seg,
+                                             uint32_t gb) {
+    return gb < block_base[n_seg] ? (int)bseg[gb] : -1;
 }
 
 // Loads block gb's pairs: wave w holds pairs w * kCBWave + 64 c + lane of the
-// block in tile[c] (0xffffffff past the segment's end) and, with vals, val[c].
+// block, the tile in the low 16 bits of tr[c] (0xffff past the segment's end,
+// tiles are below kMaxTilesPerPose) and, with vals, the index in val[c].
 __device__ __forceinline__ void seg_load(const SegPass &ps, const uint32_t *block_base, int i, uint32_t gb,
-                                         const uint16_t *tiles, const uint32_t *vals, uint32_t *tile, uint32_t *val) {
+                                         const uint16_t *tiles, const uint32_t *vals, uint32_t *tr, uint32_t *val) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t b0 = ps.seg[i] + (uint64_t)(gb - block_base[i]) * kCB + (uint64_t)wave * kCBWave + lane;
+    const uint64_t b0 = ps.seg[i] + (uint64_t)(gb - block_base[i]) * kCB + (uint64_t)wave * kCBWave;
     const uint64_t end = ps.seg[i + 1];
+    const uint32_t n = (uint32_t)min<uint64_t>(kCBWave, end > b0 ? end - b0 : 0);  // the wave's pairs
+    const uint16_t *t = tiles + b0;
+    const uint32_t *v = vals ? vals + b0 : nullptr;
 #pragma unroll
     for (int c = 0; c < kCBChunks; ++c) {
-        const uint64_t j = b0 + (uint64_t)c * 64;
-        const bool valid = j < end;
-        tile[c] = valid ? (uint32_t)tiles[j] : 0xffffffffu;
-        if (vals) val[c] = valid ? vals[j] : 0u;
+        const uint32_t j = (uint32_t)(c * 64 + lane);
+        const bool valid = j < n;
+        tr[c] = valid ? (uint32_t)t[j] : 0xffffu;
+        if (vals) val[c] = valid ? v[j] : 0u;
     }
 }
 
 // cnt[gb * n_keys + k] = pairs of block gb with key k.
 template <int kBits>
 __global__ __launch_bounds__(kCBThreads) void k_seg_count(SegPass ps, const uint32_t *__restrict__ block_base,
+                                                          const uint32_t *__restrict__ bseg,
                                                           const uint16_t *__restrict__ tiles,
                                                           uint32_t *__restrict__ cnt) {
     __shared__ uint32_t s_h[kMaxKeys];
     const uint32_t gb = blockIdx.x;
-    const int i = block_segment(block_base, ps.n_seg, gb);
+    const int i = block_segment(block_base, bseg, ps.n_seg, gb);
     if (i < 0) return;
     const int lane = threadIdx.x & 63;
     for (int k = threadIdx.x; k < ps.n_keys; k += kCBThreads) s_h[k] = 0;
     __syncthreads();
-    uint32_t tile[kCBChunks];
-    seg_load(ps, block_base, i, gb, tiles, nullptr, tile, nullptr);
+    uint32_t tr[kCBChunks];
+    seg_load(ps, block_base, i, gb, tiles, nullptr, tr, nullptr);
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
 #pragma unroll
     for (int c = 0; c < kCBChunks; ++c) {
-        const bool valid = tile[c] != 0xffffffffu;
-        const uint32_t key = valid ? (tile[c] >> ps.shift) & ps.mask : 0u;
+        const bool valid = tr[c] != 0xffffu;
+        const uint32_t key = valid ? (tr[c] >> ps.shift) & ps.mask : 0u;
         const uint64_t peers = match_peers<kBits>(key, valid);
         if (valid && (peers & lt_mask) == 0) atomicAdd(&s_h[key], (uint32_t)__popcll(peers));
     }
@@ -430,15 +449,36 @@ __global__ __launch_bounds__(kThreads) void k_seg_offsets(SegPass ps, uint32_t *
     __shared__ uint32_t s_wave[4];
     const int i = blockIdx.x, k = threadIdx.x;
     const uint32_t g0 = block_base[i], g1 = block_base[i + 1];
+    // 8 blocks per step, so several loads are in flight per thread
     uint32_t tot = 0;
-    if (k < ps.n_keys)
-        for (uint32_t g = g0; g < g1; ++g) tot += cnt[(uint64_t)g * ps.n_keys + k];
+    if (k < ps.n_keys) {
+        uint32_t g = g0;
+        for (; g + 8 <= g1; g += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = cnt[(uint64_t)(g + u) * ps.n_keys + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) tot += v[u];
+        }
+        for (; g < g1; ++g) tot += cnt[(uint64_t)g * ps.n_keys + k];
+    }
     uint32_t all = 0;
     uint32_t run = block_exclusive_scan_u32(tot, s_wave, &all);
     const int col = (i % per_row) * ps.n_keys + k;
     if (k < ps.n_keys) {
         if (col < row) starts[(uint64_t)(i / per_row) * row + col] = ps.seg[i] + run;
-        for (uint32_t g = g0; g < g1; ++g) {
+        uint32_t g = g0;
+        for (; g + 8 <= g1; g += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = cnt[(uint64_t)(g + u) * ps.n_keys + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                cnt[(uint64_t)(g + u) * ps.n_keys + k] = run;
+                run += v[u];
+            }
+        }
+        for (; g < g1; ++g) {
             const uint64_t j = (uint64_t)g * ps.n_keys + k;
             const uint32_t x = cnt[j];
             cnt[j] = run;
@@ -457,6 +497,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_offsets(SegPass ps, uint32_t *
 // counts into output positions. out_tiles may be null (the last pass).
 template <int kBits>
 __global__ __launch_bounds__(kCBThreads) void k_seg_scatter(SegPass ps, const uint32_t *__restrict__ block_base,
+                                                            const uint32_t *__restrict__ bseg,
                                                             const uint32_t *__restrict__ offs,
                                                             const uint16_t *__restrict__ tiles,
                                                             const uint32_t *__restrict__ vals,
@@ -464,25 +505,27 @@ __global__ __launch_bounds__(kCBThreads) void k_seg_scatter(SegPass ps, const ui
                                                             uint32_t *__restrict__ out_vals) {
     __shared__ uint32_t s_cnt[kCBWaves][kMaxKeys];
     const uint32_t gb = blockIdx.x;
-    const int i = block_segment(block_base, ps.n_seg, gb);
+    const int i = block_segment(block_base, bseg, ps.n_seg, gb);
     if (i < 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int j = threadIdx.x; j < kCBWaves * kMaxKeys; j += kCBThreads) (&s_cnt[0][0])[j] = 0;
     __syncthreads();
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-    uint32_t tile[kCBChunks], val[kCBChunks], rnk[kCBChunks];
-    seg_load(ps, block_base, i, gb, tiles, vals, tile, val);
+    // tr[c]: tile in the low 16 bits, then the pair's rank among the wave's pairs
+    // with its key in the high 16 (below kCBWave)
+    uint32_t tr[kCBChunks], val[kCBChunks];
+    seg_load(ps, block_base, i, gb, tiles, vals, tr, val);
 #pragma unroll
     for (int c = 0; c < kCBChunks; ++c) {
-        const bool valid = tile[c] != 0xffffffffu;
-        const uint32_t key = valid ? (tile[c] >> ps.shift) & ps.mask : 0u;
+        const bool valid = tr[c] != 0xffffu;
+        const uint32_t key = valid ? (tr[c] >> ps.shift) & ps.mask : 0u;
         const uint64_t peers = match_peers<kBits>(key, valid);
         const uint32_t r = (uint32_t)__popcll(peers & lt_mask);
         uint32_t old = 0;
         if (valid && r == 0) old = atomicAdd(&s_cnt[wave][key], (uint32_t)__popcll(peers));
         const int leader = (int)__builtin_ctzll(peers | (1ull << 63));
         const uint32_t base = (uint32_t)__shfl((int)old, leader, 64);
-        rnk[c] = valid ? base + r : 0xffffffffu;
+        tr[c] |= (base + r) << 16;
     }
     __syncthreads();
     for (int k = threadIdx.x; k < ps.n_keys; k += kCBThreads) {
@@ -497,31 +540,34 @@ __global__ __launch_bounds__(kCBThreads) void k_seg_scatter(SegPass ps, const ui
     }
     __syncthreads();
     const uint64_t base = ps.seg[i];
+    uint32_t *ov = out_vals + base;
+    uint16_t *ot = out_tiles ? out_tiles + base : nullptr;
 #pragma unroll
     for (int c = 0; c < kCBChunks; ++c) {
-        if (rnk[c] == 0xffffffffu) continue;
-        const uint64_t pos = base + s_cnt[wave][(tile[c] >> ps.shift) & ps.mask] + rnk[c];
-        if (out_tiles) out_tiles[pos] = (uint16_t)tile[c];
-        out_vals[pos] = val[c];
+        const uint32_t tile = tr[c] & 0xffffu;
+        if (tile == 0xffffu) continue;
+        const uint32_t pos = s_cnt[wave][(tile >> ps.shift) & ps.mask] + (tr[c] >> 16);
+        if (ot) ot[pos] = (uint16_t)tile;
+        ov[pos] = val[c];
     }
 }
 
 // One segmented pass: counts, offsets (run starts to `starts`), scatter.
-void launch_seg_pass(hipStream_t s, const SegPass &ps, uint64_t n_blocks, uint32_t *block_base, uint32_t *cnt,
-                     int per_row, int row, uint64_t *starts, const uint16_t *tiles, const uint32_t *vals,
-                     uint16_t *out_tiles, uint32_t *out_vals) {
+void launch_seg_pass(hipStream_t s, const SegPass &ps, uint64_t n_blocks, uint32_t *block_base, uint32_t *bseg,
+                     uint32_t *cnt, int per_row, int row, uint64_t *starts, const uint16_t *tiles,
+                     const uint32_t *vals, uint16_t *out_tiles, uint32_t *out_vals) {
     int bits = 0;
     while ((1 << bits) < ps.n_keys) ++bits;
-    hipLaunchKernelGGL(k_seg_blocks, dim3(1), dim3(kThreads), 0, s, ps.seg, ps.n_seg, block_base);
+    hipLaunchKernelGGL(k_seg_blocks, dim3(1), dim3(kThreads), 0, s, ps.seg, ps.n_seg, block_base, bseg);
     switch (bits) {
 #define GSR_SEG(B)                                                                                                 \
     case B:                                                                                                        \
-        hipLaunchKernelGGL(k_seg_count<B>, dim3((unsigned)n_blocks), dim3(kCBThreads), 0, s, ps, block_base, tiles, \
-                           cnt);                                                                                   \
+        hipLaunchKernelGGL(k_seg_count<B>, dim3((unsigned)n_blocks), dim3(kCBThreads), 0, s, ps, block_base, bseg,  \
+                           tiles, cnt);                                                                            \
         hipLaunchKernelGGL(k_seg_offsets, dim3((unsigned)ps.n_seg), dim3(kThreads), 0, s, ps, cnt, block_base,      \
                            per_row, row, starts);                                                                  \
-        hipLaunchKernelGGL(k_seg_scatter<B>, dim3((unsigned)n_blocks), dim3(kCBThreads), 0, s, ps, block_base, cnt, \
-                           tiles, vals, out_tiles, out_vals);                                                      \
+        hipLaunchKernelGGL(k_seg_scatter<B>, dim3((unsigned)n_blocks), dim3(kCBThreads), 0, s, ps, block_base, bseg, \
+                           cnt, tiles, vals, out_tiles, out_vals);                                                 \
         break;
         GSR_SEG(0) GSR_SEG(1) GSR_SEG(2) GSR_SEG(3) GSR_SEG(4) GSR_SEG(5) GSR_SEG(6) GSR_SEG(7) GSR_SEG(8)
 #undef GSR_SEG
@@ -591,17 +637,17 @@ uint64_t bucket_count_elems(uint64_t capacity, int n_poses, int n_tiles) {
 }
 
 void launch_bucket(hipStream_t s, const uint16_t *ptile, const uint32_t *pk, const uint64_t *pseg, int n_poses,
-                   uint64_t capacity, int n_tiles, uint32_t *block_base, uint32_t *cnt, uint64_t *cstart,
-                   uint16_t *ctile, uint32_t *cval, uint64_t *offsets, uint32_t *sk) {
+                   uint64_t capacity, int n_tiles, uint32_t *block_base, uint32_t *bseg, uint32_t *cnt,
+                   uint64_t *cstart, uint16_t *ctile, uint32_t *cval, uint64_t *offsets, uint32_t *sk) {
     if (n_poses <= 0) return;
     const int n_coarse = bucket_coarse(n_tiles);
     const uint64_t nbm = bucket_blocks_max(capacity, n_poses, n_tiles);
     // A: poses -> buckets; cstart[p * n_coarse + b] = first pair of bucket (p, b), cstart[P * n_coarse] = pseg[P]
     const SegPass a{pseg, n_poses, kFineBits, 0xffffu, n_coarse};
-    launch_seg_pass(s, a, nbm, block_base, cnt, 1, n_coarse, cstart, ptile, pk, ctile, cval);
+    launch_seg_pass(s, a, nbm, block_base, bseg, cnt, 1, n_coarse, cstart, ptile, pk, ctile, cval);
     // B: buckets -> tiles; offsets[p * n_tiles + t] = first pair of list (p, t), offsets[P * n_tiles] = pseg[P]
     const SegPass b{cstart, n_poses * n_coarse, 0, (uint32_t)(kFine - 1), kFine};
-    launch_seg_pass(s, b, nbm, block_base, cnt, n_coarse, n_tiles, offsets, ctile, cval, nullptr, sk);
+    launch_seg_pass(s, b, nbm, block_base, bseg, cnt, n_coarse, n_tiles, offsets, ctile, cval, nullptr, sk);
 }
 
 }  // namespace gsr
