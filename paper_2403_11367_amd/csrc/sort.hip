@@ -109,6 +109,7 @@ constexpr int kRB = kRBWaves * kRBWave;    // elements per radix block
 constexpr int kRBChunks = kRBWave / 64;    // 64-element chunks per wave
 constexpr int kRegionsPerBlock = kRB / 64;
 constexpr int kDigits = 256;
+constexpr uint32_t kXcds = 8;  // accelerator complex dies of the part (workgroups are dealt to them round robin)
 
 struct RadixSrc {
     const uint32_t *keys, *vals;
@@ -244,13 +245,21 @@ __global__ __launch_bounds__(kThreads) void k_pose_bases(const uint32_t *__restr
 // keys are not written: vout gets the sorted record slots and kout their tile
 // counts, the input of the pair emission.
 template <bool kLast>
-__global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int shift, uint32_t nbp,
+__global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int shift, uint32_t nbp, int n_poses,
                                                             const uint32_t *__restrict__ off,
                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                             const uint32_t *__restrict__ ntiles, int64_t n) {
     __shared__ uint32_t s_cnt[kRBWaves][kDigits];
-    const int p = blockIdx.y;
-    const uint32_t j = blockIdx.x;
+    // Workgroups go to the XCDs round robin by linear id; the mapping below puts
+    // every block of pose p on XCD p % 8, in order, so the partial cache lines
+    // that neighbouring blocks write at the ends of a digit's runs meet in one
+    // L2 before they are written back. The grid has n_pose_slots = P rounded up
+    // to 8 rows of nbp blocks.
+    const uint32_t lin = blockIdx.y * nbp + blockIdx.x;
+    const uint32_t xcd = lin % kXcds, slot = lin / kXcds;
+    const int p = (int)(xcd + kXcds * (slot / nbp));
+    const uint32_t j = slot % nbp;
+    if (p >= n_poses) return;
     const uint32_t pose_base = src.vbase[p];
     if (!src.vcount && (uint64_t)pose_base + (uint64_t)j * kRB >= src.vbase[p + 1]) return;  // empty block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -604,6 +613,7 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
                        uint32_t *nv, uint32_t *vbase) {
     const uint32_t nbp = (uint32_t)radix_blocks_per_pose(n);
     const dim3 grid(nbp, (unsigned)n_poses);
+    const dim3 sgrid(nbp, (unsigned)((n_poses + kXcds - 1) / kXcds * kXcds));  // see k_radix_scatter
     // pass 0: regions in (kb, vb) -> dense (ka, va); passes 1, 2 ping-pong; pass 3 -> (kb = tile counts, vb = index)
     const uint32_t *kin = kb, *vin = vb;
     for (int pass = 0; pass < 4; ++pass) {
@@ -615,11 +625,11 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
         if (pass == 0) hipLaunchKernelGGL(k_pose_bases, dim3(1), dim3(kThreads), 0, s, nv, n_poses, vbase);
         uint32_t *ko = (pass & 1) ? kb : ka, *vo = (pass & 1) ? vb : va;
         if (pass == 3)
-            hipLaunchKernelGGL(k_radix_scatter<true>, grid, dim3(kRBThreads), 0, s, src, shift, nbp, roff, ko, vo, ntiles,
-                               n);
+            hipLaunchKernelGGL(k_radix_scatter<true>, sgrid, dim3(kRBThreads), 0, s, src, shift, nbp, n_poses, roff,
+                               ko, vo, ntiles, n);
         else
-            hipLaunchKernelGGL(k_radix_scatter<false>, grid, dim3(kRBThreads), 0, s, src, shift, nbp, roff, ko, vo,
-                               ntiles, n);
+            hipLaunchKernelGGL(k_radix_scatter<false>, sgrid, dim3(kRBThreads), 0, s, src, shift, nbp, n_poses, roff,
+                               ko, vo, ntiles, n);
         kin = ko;
         vin = vo;
     }
