@@ -234,6 +234,29 @@ __global__ __launch_bounds__(kThreads) void k_pose_bases(const uint32_t *__restr
     }
 }
 
+// Exclusive scan of one uint32 per thread across a kRBThreads block; *total gets the sum.
+__device__ uint32_t block_exclusive_scan_512(uint32_t x, uint32_t *s_wave /*[kRBWaves]*/, uint32_t *total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    uint32_t add = 0, sum = 0;
+#pragma unroll
+    for (int w = 0; w < kRBWaves; ++w) {
+        const uint32_t v = s_wave[w];
+        if (w < wave) add += v;
+        sum += v;
+    }
+    *total = sum;
+    __syncthreads();
+    return add + inc - x;
+}
+
 // Stable scatter of radix block (p, j). Each wave walks its share 64 elements at
 // a time: lanes with equal digits are matched with ballots and ranked in lane
 // order; the group's leader adds the group size to a per-wave, per-digit LDS
@@ -241,15 +264,21 @@ __global__ __launch_bounds__(kThreads) void k_pose_bases(const uint32_t *__restr
 // digit) is broadcast to the group. One wave's LDS operations complete in
 // program order, so the counters carry the order across chunks without a
 // barrier, and the chunks' atomics need not wait for each other. The block then
-// turns the per-wave counts into output positions from off[]. With kLast the
-// keys are not written: vout gets the sorted record slots and kout their tile
-// counts, the input of the pair emission.
+// lays its elements out in LDS in output order (digits in order, waves in order
+// within a digit) and writes them from there, so consecutive threads store
+// consecutive positions of a digit's run (whole cache lines where the runs are
+// long) instead of 64 lanes storing to 64 runs. With kLast the keys are not
+// written: vout gets the sorted record slots and kout their tile counts, the
+// input of the pair emission.
 template <bool kLast>
 __global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int shift, uint32_t nbp, int n_poses,
                                                             const uint32_t *__restrict__ off,
                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                             const uint32_t *__restrict__ ntiles, int64_t n) {
     __shared__ uint32_t s_cnt[kRBWaves][kDigits];
+    __shared__ uint32_t s_delta[kDigits];
+    __shared__ uint32_t s_key[kRB], s_val[kRB];  // the block's elements in output order
+    __shared__ uint32_t s_wave[kRBWaves];
     // Workgroups go to the XCDs round robin by linear id; the mapping below puts
     // every block of pose p on XCD p % 8, in order, so the partial cache lines
     // that neighbouring blocks write at the ends of a digit's runs meet in one
@@ -295,28 +324,46 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int 
         rnk[c] = valid ? base + r : 0xffffffffu;
     }
     __syncthreads();
+    // Block-local order: digit d's elements go to [ls[d], ls[d] + tot[d]) of the
+    // staging arrays, wave by wave; s_cnt[w][d] <- wave w's first slot there, and
+    // s_delta[d] = (output position of the block's first digit-d element) - ls[d].
+    uint32_t tot = 0;
     if (threadIdx.x < kDigits) {
-        // s_cnt[w][d] <- output position of wave w's first element with digit d
+#pragma unroll
+        for (int w = 0; w < kRBWaves; ++w) tot += s_cnt[w][threadIdx.x];
+    }
+    uint32_t all = 0;
+    const uint32_t ls = block_exclusive_scan_512(tot, s_wave, &all);
+    if (threadIdx.x < kDigits) {
         const int d = threadIdx.x;
-        uint32_t run = pose_base + off[((uint64_t)p * nbp + j) * kDigits + d];
+        uint32_t run = ls;
 #pragma unroll
         for (int w = 0; w < kRBWaves; ++w) {
             const uint32_t c = s_cnt[w][d];
             s_cnt[w][d] = run;
             run += c;
         }
+        s_delta[d] = pose_base + off[((uint64_t)p * nbp + j) * kDigits + d] - ls;
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < kRBChunks; ++c) {
         if (rnk[c] == 0xffffffffu) continue;
-        const uint32_t pos = s_cnt[wave][(key[c] >> shift) & 0xffu] + rnk[c];
+        const uint32_t slot = s_cnt[wave][(key[c] >> shift) & 0xffu] + rnk[c];
+        s_key[slot] = key[c];
+        s_val[slot] = val[c];
+    }
+    __syncthreads();
+    // consecutive threads write consecutive positions of each digit's run
+    for (uint32_t i = threadIdx.x; i < all; i += kRBThreads) {
+        const uint32_t k = s_key[i], v = s_val[i];
+        const uint32_t pos = s_delta[(k >> shift) & 0xffu] + i;
         if (kLast) {
-            vout[pos] = val[c];
-            kout[pos] = ntiles[val[c]];  // values are record slots (pose * n + index)
+            vout[pos] = v;
+            kout[pos] = ntiles[v];  // values are record slots (pose * n + index)
         } else {
-            kout[pos] = key[c];
-            vout[pos] = val[c];
+            kout[pos] = k;
+            vout[pos] = v;
         }
     }
 }
