@@ -549,8 +549,10 @@ __global__ __launch_bounds__(kThreads) void k_seg_offsets(SegPass ps, uint32_t *
 // adds the group size to a per-wave, per-key LDS counter, and the value it
 // returns (the wave's earlier pairs with that key) is broadcast to the group.
 // One wave's LDS operations complete in program order, so the counters carry
-// the order across chunks without a barrier. The block then turns the per-wave
-// counts into output positions. out_tiles may be null (the last pass).
+// the order across chunks without a barrier. The block then lays its pairs out
+// in LDS in output order and writes them from there, so consecutive threads
+// store consecutive positions of a key's run. out_tiles may be null (the last
+// pass).
 template <int kBits>
 __global__ __launch_bounds__(kCBThreads) void k_seg_scatter(SegPass ps, const uint32_t *__restrict__ block_base,
                                                             const uint32_t *__restrict__ bseg,
@@ -560,6 +562,10 @@ __global__ __launch_bounds__(kCBThreads) void k_seg_scatter(SegPass ps, const ui
                                                             uint16_t *__restrict__ out_tiles,
                                                             uint32_t *__restrict__ out_vals) {
     __shared__ uint32_t s_cnt[kCBWaves][kMaxKeys];
+    __shared__ uint32_t s_delta[kMaxKeys];
+    __shared__ uint16_t s_tile[kCB];  // the block's pairs in output order
+    __shared__ uint32_t s_val[kCB];
+    __shared__ uint32_t s_wave[kCBWaves];
     const uint32_t gb = blockIdx.x;
     const int i = block_segment(block_base, bseg, ps.n_seg, gb);
     if (i < 0) return;
@@ -584,27 +590,46 @@ __global__ __launch_bounds__(kCBThreads) void k_seg_scatter(SegPass ps, const ui
         tr[c] |= (base + r) << 16;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < ps.n_keys; k += kCBThreads) {
-        // s_cnt[w][k] <- output position (relative to the segment) of wave w's first pair with key k
-        uint32_t run = offs[(uint64_t)gb * ps.n_keys + k];
+    // Block-local order: key k's pairs go to [ls[k], ls[k] + tot[k]) of the
+    // staging arrays, wave by wave; s_cnt[w][k] <- wave w's first slot there, and
+    // s_delta[k] = (position of the block's first key-k pair in the segment) - ls[k].
+    const int k = threadIdx.x;
+    uint32_t tot = 0;
+    if (k < ps.n_keys) {
+#pragma unroll
+        for (int w = 0; w < kCBWaves; ++w) tot += s_cnt[w][k];
+    }
+    uint32_t all = 0;
+    const uint32_t ls = block_exclusive_scan_512(tot, s_wave, &all);
+    if (k < ps.n_keys) {
+        uint32_t run = ls;
 #pragma unroll
         for (int w = 0; w < kCBWaves; ++w) {
             const uint32_t x = s_cnt[w][k];
             s_cnt[w][k] = run;
             run += x;
         }
+        s_delta[k] = offs[(uint64_t)gb * ps.n_keys + k] - ls;
     }
     __syncthreads();
-    const uint64_t base = ps.seg[i];
-    uint32_t *ov = out_vals + base;
-    uint16_t *ot = out_tiles ? out_tiles + base : nullptr;
 #pragma unroll
     for (int c = 0; c < kCBChunks; ++c) {
         const uint32_t tile = tr[c] & 0xffffu;
         if (tile == 0xffffu) continue;
-        const uint32_t pos = s_cnt[wave][(tile >> ps.shift) & ps.mask] + (tr[c] >> 16);
+        const uint32_t slot = s_cnt[wave][(tile >> ps.shift) & ps.mask] + (tr[c] >> 16);
+        s_tile[slot] = (uint16_t)tile;
+        s_val[slot] = val[c];
+    }
+    __syncthreads();
+    // consecutive threads write consecutive positions of each key's run
+    const uint64_t base = ps.seg[i];
+    uint32_t *ov = out_vals + base;
+    uint16_t *ot = out_tiles ? out_tiles + base : nullptr;
+    for (uint32_t e = threadIdx.x; e < all; e += kCBThreads) {
+        const uint32_t tile = s_tile[e];
+        const uint32_t pos = s_delta[(tile >> ps.shift) & ps.mask] + e;
         if (ot) ot[pos] = (uint16_t)tile;
-        ov[pos] = val[c];
+        ov[pos] = s_val[e];
     }
 }
 
