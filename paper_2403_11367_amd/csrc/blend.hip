@@ -73,7 +73,8 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     constexpr uint32_t kSlotBytes = 16u * kQuads;
     __shared__ float4 s_rec[kThreads * kQuads];
     __shared__ uint64_t s_mask[4][4][4];  // [band][quarter][64-record group]
-    __shared__ uint32_t s_words[4][256];  // per wave: slot of every quarter, one byte each, per step
+    // per wave, quarter and step: slot of the record the quarter visits
+    __shared__ uint8_t s_slots[4][4][256];
 
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -100,7 +101,6 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     // stops changing once the pixel has stopped, so no separate flag is kept.
     float T = in_image ? 1.f : 0.f, cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f;
     unsigned n_contrib = 0, n_visits = 0;  // only with kCount
-    const uint32_t lane_sh = 8u * quarter;  // the lane's byte of a slot word
     const char *s_rec_bytes = reinterpret_cast<const char *>(s_rec);
 
     // backward: the pixel's final colour and depth and their loss gradients
@@ -197,10 +197,11 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             // Step i visits the i-th record (in list order) of every quarter that
             // overlaps it, or the dummy slot when the quarter has fewer. The record
             // in slot 64 g + l is entered by lane l at its rank in each quarter's
-            // walk. One wave: its LDS accesses complete in program order.
+            // walk; every lane then reads its own quarter's slots. One wave: its
+            // LDS accesses complete in program order.
+            uint32_t *slots32 = reinterpret_cast<uint32_t *>(&s_slots[wave][0][0]);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) s_words[wave][e * 64 + lane] = 0xffffffffu;
-            uint8_t *words = reinterpret_cast<uint8_t *>(&s_words[wave][0]);
+            for (int e = 0; e < 4; ++e) slots32[e * 64 + lane] = kDummy * 0x01010101u;
             uint32_t cnt[4], steps = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -212,7 +213,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                         const uint32_t mhi = __builtin_amdgcn_readfirstlane((uint32_t)(mv >> 32));
                         const uint64_t m = ((uint64_t)mhi << 32) | mlo;
                         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, 0u));
-                        if (__builtin_amdgcn_inverse_ballot_w64(m)) words[(run + rank) * 4 + q] = (uint8_t)(grp * 64 + lane);
+                        if (__builtin_amdgcn_inverse_ballot_w64(m)) s_slots[wave][q][run + rank] = (uint8_t)(grp * 64 + lane);
                         run += (uint32_t)__popcll(m);
                     }
                 }
@@ -221,8 +222,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             }
             // Software pipeline, unrolled twice so the two register sets alternate:
             // the slots and geometry of step i + 1 are read during step i.
-            auto load = [&](uint32_t w, uint32_t &o, float4 &ra, float4 &rb) {
-                o = ((w >> lane_sh) & 0xffu) * kSlotBytes;
+            auto load = [&](uint32_t o, float4 &ra, float4 &rb) {
                 ra = *reinterpret_cast<const float4 *>(s_rec_bytes + o);
                 rb = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 16);
             };
@@ -237,7 +237,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                 if constexpr (!kGrad) {
                     if (ok) {
                         const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
-                        const float al = fminf(k.alpha_max, __builtin_amdgcn_exp2f(p2));
+                        const float al = clamp_alpha(__builtin_amdgcn_exp2f(p2), k.alpha_max);
                         const float w = al * T;
                         cr = __builtin_fmaf(c.x, w, cr);
                         cg = __builtin_fmaf(c.y, w, cg);
@@ -253,7 +253,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                         const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
                         const float4 e = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 48);
                         const float gexp = __builtin_amdgcn_exp2f(p2);
-                        const float al = fminf(k.alpha_max, gexp);
+                        const float al = clamp_alpha(gexp, k.alpha_max);
                         const float w = al * T;
                         // colour and depth up to and including this layer (the forward's sums)
                         const float n_r = __builtin_fmaf(c.x, w, cr), n_g = __builtin_fmaf(c.y, w, cg);
@@ -309,16 +309,19 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                 }
                 return true;
             };
-            uint32_t o0, o1;
+            const uint8_t *my_slots = &s_slots[wave][quarter][0];  // this lane's quarter
             float4 a0, b0, a1, b1;
-            load(s_words[wave][0], o0, a0, b0);
-            uint32_t word = s_words[wave][1];
+            uint32_t o0 = my_slots[0] * kSlotBytes, o1;
+            load(o0, a0, b0);
+            uint32_t s_next = my_slots[1];
             for (uint32_t i = 0; i < steps; i += 2) {
-                load(word, o1, a1, b1);      // step i + 1 (slot index <= 252)
-                word = s_words[wave][i + 2];  // (<= 253)
+                o1 = s_next * kSlotBytes;  // step i + 1 (step index <= 252)
+                load(o1, a1, b1);
+                s_next = my_slots[i + 2];  // (<= 253)
                 if (!step(o0, a0, b0) || i + 1 >= steps) break;
-                load(word, o0, a0, b0);      // step i + 2
-                word = s_words[wave][i + 3];  // i + 1 < steps <= 252, so <= 253
+                o0 = s_next * kSlotBytes;  // step i + 2
+                load(o0, a0, b0);
+                s_next = my_slots[i + 3];  // i + 1 < steps <= 252, so <= 253
                 if (!step(o1, a1, b1)) break;
             }
         }

@@ -55,6 +55,12 @@ __device__ __forceinline__ void stage_record(const float4 &q0, const float4 &q1,
     s2 = make_float4(q1.z, q1.w, q2.x, 0.f);
 }
 
+// min(alpha_max, e) for e >= 0 (an exponential) in one instruction: the median
+// of (e, 0, alpha_max) equals it for every such e, bit for bit.
+__device__ __forceinline__ float clamp_alpha(float e, float alpha_max) {
+    return __builtin_amdgcn_fmed3f(e, 0.f, alpha_max);
+}
+
 // Base-2 exponent of the footprint of staged record (s0, s1) at pixel centre (px, py).
 __device__ __forceinline__ float footprint_p2(const float4 &s0, const float4 &s1, float px, float py) {
     const float dx = px - s0.x, dy = py - s0.y;
