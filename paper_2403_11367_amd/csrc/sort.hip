@@ -138,19 +138,33 @@ __device__ __forceinline__ bool radix_elem(const RadixSrc &src, int p, uint32_t 
 // cnt[(p * nbp + j) * 256 + digit] = elements of radix block (p, j) with that digit.
 __global__ __launch_bounds__(kRBThreads) void k_radix_count(RadixSrc src, int shift, uint32_t nbp,
                                                           uint32_t *__restrict__ cnt) {
-    __shared__ uint32_t s_h[kDigits];
+    __shared__ uint32_t s_h[kRBWaves][kDigits];  // per wave, so only a wave's own lanes meet at a counter
     const int p = blockIdx.y;
     const uint32_t j = blockIdx.x;
     if (!src.vcount && (uint64_t)src.vbase[p] + (uint64_t)j * kRB >= src.vbase[p + 1]) return;  // empty block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x < kDigits) s_h[threadIdx.x] = 0;
-    __syncthreads();
+    for (int i = threadIdx.x; i < kRBWaves * kDigits; i += kRBThreads) (&s_h[0][0])[i] = 0;
+    // every chunk's key is loaded before the first count, so the loads overlap
+    uint32_t key[kRBChunks];
+    uint32_t vmask = 0;
+#pragma unroll
     for (int c = 0; c < kRBChunks; ++c) {
         uint64_t idx = 0;
-        if (radix_elem(src, p, j, wave, c, lane, idx)) atomicAdd(&s_h[(src.keys[idx] >> shift) & 0xffu], 1u);
+        const bool valid = radix_elem(src, p, j, wave, c, lane, idx);
+        key[c] = valid ? src.keys[idx] : 0u;
+        vmask |= (uint32_t)valid << c;
     }
     __syncthreads();
-    if (threadIdx.x < kDigits) cnt[((uint64_t)p * nbp + j) * kDigits + threadIdx.x] = s_h[threadIdx.x];
+#pragma unroll
+    for (int c = 0; c < kRBChunks; ++c)
+        if ((vmask >> c) & 1u) atomicAdd(&s_h[wave][(key[c] >> shift) & 0xffu], 1u);
+    __syncthreads();
+    for (int d = threadIdx.x; d < kDigits; d += kRBThreads) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kRBWaves; ++w) t += s_h[w][d];
+        cnt[((uint64_t)p * nbp + j) * kDigits + d] = t;
+    }
 }
 
 // Exclusive scan of one uint32 per thread across a 256-thread block; *total gets the sum.
@@ -467,30 +481,29 @@ __device__ __forceinline__ void seg_load(const SegPass &ps, const uint32_t *bloc
 }
 
 // cnt[gb * n_keys + k] = pairs of block gb with key k.
-template <int kBits>
 __global__ __launch_bounds__(kCBThreads) void k_seg_count(SegPass ps, const uint32_t *__restrict__ block_base,
                                                           const uint32_t *__restrict__ bseg,
                                                           const uint16_t *__restrict__ tiles,
                                                           uint32_t *__restrict__ cnt) {
-    __shared__ uint32_t s_h[kMaxKeys];
+    __shared__ uint32_t s_h[kCBWaves][kMaxKeys];  // per wave, so only a wave's own lanes meet at a counter
     const uint32_t gb = blockIdx.x;
     const int i = block_segment(block_base, bseg, ps.n_seg, gb);
     if (i < 0) return;
-    const int lane = threadIdx.x & 63;
-    for (int k = threadIdx.x; k < ps.n_keys; k += kCBThreads) s_h[k] = 0;
-    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < kCBWaves * kMaxKeys; k += kCBThreads) (&s_h[0][0])[k] = 0;
     uint32_t tr[kCBChunks];
     seg_load(ps, block_base, i, gb, tiles, nullptr, tr, nullptr);
-    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-#pragma unroll
-    for (int c = 0; c < kCBChunks; ++c) {
-        const bool valid = tr[c] != 0xffffu;
-        const uint32_t key = valid ? (tr[c] >> ps.shift) & ps.mask : 0u;
-        const uint64_t peers = match_peers<kBits>(key, valid);
-        if (valid && (peers & lt_mask) == 0) atomicAdd(&s_h[key], (uint32_t)__popcll(peers));
-    }
     __syncthreads();
-    for (int k = threadIdx.x; k < ps.n_keys; k += kCBThreads) cnt[(uint64_t)gb * ps.n_keys + k] = s_h[k];
+#pragma unroll
+    for (int c = 0; c < kCBChunks; ++c)
+        if (tr[c] != 0xffffu) atomicAdd(&s_h[wave][(tr[c] >> ps.shift) & ps.mask], 1u);
+    __syncthreads();
+    for (int k = threadIdx.x; k < ps.n_keys; k += kCBThreads) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kCBWaves; ++w) t += s_h[w][k];
+        cnt[(uint64_t)gb * ps.n_keys + k] = t;
+    }
 }
 
 // One block per segment, thread = key: cnt[gb][k] <- position, relative to the
@@ -643,7 +656,7 @@ void launch_seg_pass(hipStream_t s, const SegPass &ps, uint64_t n_blocks, uint32
     switch (bits) {
 #define GSR_SEG(B)                                                                                                 \
     case B:                                                                                                        \
-        hipLaunchKernelGGL(k_seg_count<B>, dim3((unsigned)n_blocks), dim3(kCBThreads), 0, s, ps, block_base, bseg,  \
+        hipLaunchKernelGGL(k_seg_count, dim3((unsigned)n_blocks), dim3(kCBThreads), 0, s, ps, block_base, bseg,     \
                            tiles, cnt);                                                                            \
         hipLaunchKernelGGL(k_seg_offsets, dim3((unsigned)ps.n_seg), dim3(kThreads), 0, s, ps, cnt, block_base,      \
                            per_row, row, starts);                                                                  \
