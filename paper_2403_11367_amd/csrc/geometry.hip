@@ -287,8 +287,19 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
     __shared__ uint16_t s_tile[kEmitWin];
     __shared__ uint32_t s_key[kEmitWin];
     __shared__ uint32_t s_wave[4];
+    // Workgroups go to the 8 XCDs round robin by linear id; block b below takes
+    // emission block (b % 8) * per + b / 8 with per = ceil(nb / 8) for the nb
+    // blocks that hold elements, so each XCD walks one eighth of the elements in
+    // order (about one pose at a time), and the rectangles its blocks gather come
+    // through one L2 instead of eight. The grid (a multiple of 8, sized for every
+    // slot visible) has at least 8 * per blocks.
     const uint64_t nv = vbase[P];
-    const uint64_t e0 = (uint64_t)blockIdx.x * kEmitTile;
+    const uint64_t nb = (nv + kEmitTile - 1) / kEmitTile;
+    const uint64_t per = (nb + kXcdCount - 1) / kXcdCount;
+    const uint64_t slot = blockIdx.x / kXcdCount;
+    if (slot >= per) return;
+    const uint64_t eb = (uint64_t)(blockIdx.x % kXcdCount) * per + slot;
+    const uint64_t e0 = eb * kEmitTile;
     if (e0 >= nv) return;
     // this thread's elements: e0 + t * kEmitItems + k (consecutive, for the scan)
     const uint64_t et = e0 + (uint64_t)threadIdx.x * kEmitItems;
@@ -312,7 +323,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
             key[k] = slot - (uint32_t)((uint64_t)slot / (uint64_t)n) * (uint32_t)n;  // submap index
         }
     }
-    const uint64_t base = prefix[blockIdx.x];
+    const uint64_t base = prefix[eb];
     bool over = false;
     for (uint32_t w0 = 0; w0 < total; w0 += kEmitWin) {
         const uint32_t w1 = min(total, w0 + kEmitWin);
@@ -394,7 +405,8 @@ void launch_emit(hipStream_t s, const uint32_t *snt, const uint32_t *sg, const u
                  const uint2 *rect, int64_t n, uint64_t n_max, const uint64_t *prefix, const TileGrid &tg,
                  uint16_t *ptile, uint32_t *pk, uint64_t capacity, int *flags) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks(n_max)), dim3(kThreads), 0, s, snt, sg, vbase, n_poses,
+    const uint64_t grid = (emit_blocks(n_max) + kXcdCount - 1) / kXcdCount * kXcdCount;  // see k_emit
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(kThreads), 0, s, snt, sg, vbase, n_poses,
                        rect, n, prefix, tg, ptile, pk, capacity, flags);
 }
 

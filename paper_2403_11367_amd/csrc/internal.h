@@ -31,6 +31,10 @@ constexpr int kPackedQuads = 4;
 constexpr int kRecordQuads = 3;
 
 
+// XCDs (accelerator complex dies) of the part; workgroups are dealt to them
+// round robin by linear id, and each has its own L2.
+constexpr uint32_t kXcdCount = 8;
+
 // Tiles per pose the LDS bucketing handles (larger images are rejected).
 constexpr int kMaxTilesPerPose = 16384;
 

@@ -109,7 +109,6 @@ constexpr int kRB = kRBWaves * kRBWave;    // elements per radix block
 constexpr int kRBChunks = kRBWave / 64;    // 64-element chunks per wave
 constexpr int kRegionsPerBlock = kRB / 64;
 constexpr int kDigits = 256;
-constexpr uint32_t kXcds = 8;  // accelerator complex dies of the part (workgroups are dealt to them round robin)
 
 struct RadixSrc {
     const uint32_t *keys, *vals;
@@ -299,8 +298,8 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int 
     // L2 before they are written back. The grid has n_pose_slots = P rounded up
     // to 8 rows of nbp blocks.
     const uint32_t lin = blockIdx.y * nbp + blockIdx.x;
-    const uint32_t xcd = lin % kXcds, slot = lin / kXcds;
-    const int p = (int)(xcd + kXcds * (slot / nbp));
+    const uint32_t xcd = lin % kXcdCount, slot = lin / kXcdCount;
+    const int p = (int)(xcd + kXcdCount * (slot / nbp));
     const uint32_t j = slot % nbp;
     if (p >= n_poses) return;
     const uint32_t pose_base = src.vbase[p];
@@ -698,7 +697,7 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
                        uint32_t *nv, uint32_t *vbase) {
     const uint32_t nbp = (uint32_t)radix_blocks_per_pose(n);
     const dim3 grid(nbp, (unsigned)n_poses);
-    const dim3 sgrid(nbp, (unsigned)((n_poses + kXcds - 1) / kXcds * kXcds));  // see k_radix_scatter
+    const dim3 sgrid(nbp, (unsigned)((n_poses + kXcdCount - 1) / kXcdCount * kXcdCount));  // see k_radix_scatter
     // pass 0: regions in (kb, vb) -> dense (ka, va); passes 1, 2 ping-pong; pass 3 -> (kb = tile counts, vb = index)
     const uint32_t *kin = kb, *vin = vb;
     for (int pass = 0; pass < 4; ++pass) {
