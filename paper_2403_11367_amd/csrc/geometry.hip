@@ -296,33 +296,36 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
     const uint64_t nv = vbase[P];
     const uint64_t nb = (nv + kEmitTile - 1) / kEmitTile;
     const uint64_t per = (nb + kXcdCount - 1) / kXcdCount;
-    const uint64_t slot = blockIdx.x / kXcdCount;
-    if (slot >= per) return;
-    const uint64_t eb = (uint64_t)(blockIdx.x % kXcdCount) * per + slot;
+    const uint64_t turn = blockIdx.x / kXcdCount;  // this block's place in its XCD's walk
+    if (turn >= per) return;
+    const uint64_t eb = (uint64_t)(blockIdx.x % kXcdCount) * per + turn;
     const uint64_t e0 = eb * kEmitTile;
     if (e0 >= nv) return;
     // this thread's elements: e0 + t * kEmitItems + k (consecutive, for the scan)
     const uint64_t et = e0 + (uint64_t)threadIdx.x * kEmitItems;
-    uint32_t cnt[kEmitItems], sum = 0;
+    // tile counts and record slots together, then the rectangles (one round trip
+    // fewer than loading the slots after the scan)
+    uint32_t cnt[kEmitItems], slot[kEmitItems], sum = 0;
 #pragma unroll
     for (int k = 0; k < kEmitItems; ++k) {
-        cnt[k] = et + k < nv ? snt[et + k] : 0u;
-        sum += cnt[k];
+        const bool in = et + k < nv;
+        cnt[k] = in ? snt[et + k] : 0u;
+        slot[k] = in ? slots[et + k] : 0u;
     }
-    uint32_t total = 0;
-    const uint32_t first = emit_block_scan(sum, s_wave, &total);
     uint32_t key[kEmitItems];
     uint2 rc[kEmitItems];
 #pragma unroll
     for (int k = 0; k < kEmitItems; ++k) {
+        sum += cnt[k];
         key[k] = 0;
         rc[k] = make_uint2(0u, 0u);
         if (cnt[k]) {
-            const uint32_t slot = slots[et + k];
-            rc[k] = rect[slot];
-            key[k] = slot - (uint32_t)((uint64_t)slot / (uint64_t)n) * (uint32_t)n;  // submap index
+            rc[k] = rect[slot[k]];
+            key[k] = slot[k] - (uint32_t)((uint64_t)slot[k] / (uint64_t)n) * (uint32_t)n;  // submap index
         }
     }
+    uint32_t total = 0;
+    const uint32_t first = emit_block_scan(sum, s_wave, &total);
     const uint64_t base = prefix[eb];
     bool over = false;
     for (uint32_t w0 = 0; w0 < total; w0 += kEmitWin) {
