@@ -235,16 +235,17 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                     ++n_visits;
                 }
                 if constexpr (!kGrad) {
-                    if (ok) {
-                        const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
-                        const float al = clamp_alpha(__builtin_amdgcn_exp2f(p2), k.alpha_max);
-                        const float w = al * T;
-                        cr = __builtin_fmaf(c.x, w, cr);
-                        cg = __builtin_fmaf(c.y, w, cg);
-                        cb = __builtin_fmaf(c.z, w, cb);
-                        dep = __builtin_fmaf(rb.w, w, dep);
-                        T -= w;
-                    }
+                    // Without a branch: w = 0 where the pixel does not take this
+                    // record, and fma(c, 0, x) = x, T - 0 = T exactly (the sums are
+                    // finite and never -0), so every pixel's result is unchanged.
+                    const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
+                    const float al = clamp_alpha(__builtin_amdgcn_exp2f(p2), k.alpha_max);
+                    const float w = ok ? al * T : 0.f;
+                    cr = __builtin_fmaf(c.x, w, cr);
+                    cg = __builtin_fmaf(c.y, w, cg);
+                    cb = __builtin_fmaf(c.z, w, cb);
+                    dep = __builtin_fmaf(rb.w, w, dep);
+                    T -= w;
                 } else {
                     // Screen-space gradients of this pixel for this record (u, v,
                     // A, B, C, opacity, r, g, b, z); zero where it does not contribute.
