@@ -162,13 +162,14 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     if (!(j0 <= 4 * b + 3 && j1 >= 4 * b)) continue;
-                    const float ylo = fmaxf(((float)(4 * b) + 0.5f) - v_rel, -ryv);
-                    const float yhi = fminf(((float)(4 * b) + 3.5f) - v_rel, ryv);
+                    // (all finite here; the clamps are medians)
+                    const float ylo = max_finite(((float)(4 * b) + 0.5f) - v_rel, -ryv);
+                    const float yhi = min_finite(((float)(4 * b) + 3.5f) - v_rel, ryv);
                     if (!(ylo <= yhi)) continue;
-                    const float yr = fminf(fmaxf(dys, ylo), yhi);   // where the right end peaks in the band
-                    const float yl = fminf(fmaxf(-dys, ylo), yhi);  // where the left end bottoms
-                    const float xr = (-B * yr + __builtin_amdgcn_sqrtf(fmaxf(A * R2 - det * yr * yr, 0.f))) * iA;
-                    const float xl = (-B * yl - __builtin_amdgcn_sqrtf(fmaxf(A * R2 - det * yl * yl, 0.f))) * iA;
+                    const float yr = __builtin_amdgcn_fmed3f(dys, ylo, yhi);   // where the right end peaks in the band
+                    const float yl = __builtin_amdgcn_fmed3f(-dys, ylo, yhi);  // where the left end bottoms
+                    const float xr = (-B * yr + __builtin_amdgcn_sqrtf(max_finite(A * R2 - det * yr * yr, 0.f))) * iA;
+                    const float xl = (-B * yl - __builtin_amdgcn_sqrtf(max_finite(A * R2 - det * yl * yl, 0.f))) * iA;
                     const float x_hi = u_rel + xr + 1e-3f, x_lo = u_rel + xl - 1e-3f;  // tile-relative
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
@@ -310,19 +311,19 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                 }
                 return true;
             };
-            const uint8_t *my_slots = &s_slots[wave][quarter][0];  // this lane's quarter
+            const uint8_t *sp = &s_slots[wave][quarter][0];  // this lane's quarter; sp[j] = slot of step i + j
             float4 a0, b0, a1, b1;
-            uint32_t o0 = my_slots[0] * kSlotBytes, o1;
+            uint32_t o0 = sp[0] * kSlotBytes, o1;
             load(o0, a0, b0);
-            uint32_t s_next = my_slots[1];
-            for (uint32_t i = 0; i < steps; i += 2) {
+            uint32_t s_next = sp[1];
+            for (uint32_t i = 0; i < steps; i += 2, sp += 2) {
                 o1 = s_next * kSlotBytes;  // step i + 1 (step index <= 252)
                 load(o1, a1, b1);
-                s_next = my_slots[i + 2];  // (<= 253)
+                s_next = sp[2];  // step i + 2 (<= 253)
                 if (!step(o0, a0, b0) || i + 1 >= steps) break;
                 o0 = s_next * kSlotBytes;  // step i + 2
                 load(o0, a0, b0);
-                s_next = my_slots[i + 3];  // i + 1 < steps <= 252, so <= 253
+                s_next = sp[3];  // i + 1 < steps <= 252, so step i + 3 <= 253
                 if (!step(o1, a1, b1)) break;
             }
         }

@@ -36,18 +36,31 @@ __device__ __forceinline__ float conic_det(float A, float B, float C) {
     return (float)((double)A * (double)C - (double)B * (double)B);
 }
 
+// Max and min of two finite floats in one instruction: the median with an
+// infinite third operand (fmaxf and fminf also quiet signalling NaNs, which
+// costs an extra instruction per operand that is not known to be canonical).
+__device__ __forceinline__ float max_finite(float a, float b) {
+    return __builtin_amdgcn_fmed3f(a, b, __builtin_inff());
+}
+__device__ __forceinline__ float min_finite(float a, float b) {
+    return __builtin_amdgcn_fmed3f(a, b, -__builtin_inff());
+}
+
 // Staged record of screen record (q0, q1, q2) (see internal.h):
 //   s0 = (u, v, m11', m12'), s1 = (m22', threshold, log2 o, z), s2 = (r, g, b, 0)
 // with d^2 = (m11 dx + m12 dy)^2 + (m22 dy)^2, m11 = sqrt(A), m12 = B / m11,
 // m22 = sqrt(det / A), each scaled by sqrt(log2(e)/2); the exponent of
 // o exp(-d^2/2) in base 2 is then log2(o) - t1^2 - t2^2, and a pair contributes
 // when it is >= threshold = max(log2(o) - log2(e) cutoff / 2, log2(alpha_min)).
+// The factors come from the hardware reciprocal square root and square root
+// (about 1 ulp each), far inside the float32 margins of the contribution tests.
 __device__ __forceinline__ void stage_record(const float4 &q0, const float4 &q1, const float4 &q2, float det,
                                              const BlendConsts &k, float4 &s0, float4 &s1, float4 &s2) {
     const float A = q0.z, B = q0.w;
-    const float m11 = sqrtf(A);
-    const float m12 = B / m11;
-    const float m22 = sqrtf(fmaxf(det, 0.f) / A);  // 0: the limit of a degenerate streak
+    const float r = __builtin_amdgcn_rsqf(A);  // 1 / sqrt(A)
+    const float m11 = A * r;
+    const float m12 = B * r;
+    const float m22 = __builtin_amdgcn_sqrtf(max_finite(det, 0.f)) * r;  // 0: the limit of a degenerate streak
     const float lo = __log2f(q1.y);
     const float thr = fmaxf(k.cut_p2 + lo, k.log2_amin);
     s0 = make_float4(q0.x, q0.y, m11 * k.sqrt_half_log2e, m12 * k.sqrt_half_log2e);
