@@ -159,6 +159,28 @@ def test_long_tile_lists(ctx, n, label):
     compare_render(rgb[0], dep[0], tf[0], out, "pose 0")
 
 
+@pytest.mark.parametrize("w,h,n_poses", [(1000, 600, 2), (2048, 2048, 1)])
+def test_many_tiles_bucketing(ctx, w, h, n_poses):
+    """Tile bucketing with several 64-tile buckets: 2394 tiles (38 buckets, the last
+    holding 26 tiles) and the largest supported image, 16384 tiles (256 buckets).
+    Records, list offsets and lists bit for bit, images within tolerance."""
+    T = ((w + 15) // 16) * ((h + 15) // 16)
+    say(f"many tiles: {w}x{h} ({T} tiles), 3000 Gaussians, {n_poses} poses")
+    sc = W.tiny_scene(61, n=3000, width=w, height=h, n_poses=max(n_poses, 2), log_scale_mean=-3.0)
+    poses = sc.poses[:n_poses]
+    sm = load(ctx, sc.gaussians)
+    rgb, dep, tf = gpu_render(ctx, sm, sc.camera, poses)
+    recs, nts, offs, pairs = gpu_buffers(ctx)
+    pr = prep(sc.gaussians)
+    assert T == _tiles(sc.camera)
+    for p in range(n_poses):
+        out, rec, ks, vs, rng = oracle_pose(pr, poses[p], sc.camera)
+        check_records(recs, nts, rec, sc.gaussians.n, p)
+        check_pairs(offs, pairs, ks, vs, rng, p, T)
+        compare_render(rgb[p], dep[p], tf[p], out, f"pose {p}")
+    sm.free()
+
+
 def test_determinism_and_fixed_capacity(ctx):
     say("config0 twice (exact sizing) and once with a fixed pair capacity")
     from paper_2403_11367_amd import default_cfg
