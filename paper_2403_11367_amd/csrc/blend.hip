@@ -45,15 +45,59 @@ struct GradIo {
     float *gscreen;                    // [P, n, 10] screen-space gradients, accumulated
 };
 
-// Sum over the lane's 16-lane DPP row (one quarter): after rotations by 8, 4, 2
-// and 1 within the row every lane holds the row's total. All 64 lanes must be
-// active.
-__device__ __forceinline__ float quarter_sum(float v) {
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));  // row_ror:8
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false));  // row_ror:4
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x122, 0xf, 0xf, false));  // row_ror:2
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x121, 0xf, 0xf, false));  // row_ror:1
-    return v;
+// Sums of the 10 values over each lane's 16-lane DPP row (one quarter): after
+// rotations by 8, 4, 2 and 1 within the row (v += row_ror(v)) every lane holds
+// its row's totals. All 64 lanes must be active. Written out because the
+// compiler leaves a separate DPP move (and a zeroing move) in front of some of
+// the adds; stage by stage across the 10 values, every DPP read comes 9
+// instructions after the write it reads, and the leading s_nop covers the
+// two wait states a DPP read needs after the compiler's last VALU write.
+__device__ __forceinline__ void quarter_sums(float (&v)[kScreenGrads]) {
+    static_assert(kScreenGrads == 10, "one operand per value");
+    asm volatile(
+        "s_nop 1\n"
+        "v_add_f32_dpp %0, %0, %0 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %1, %1, %1 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %2, %2, %2 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %3, %3, %3 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %4, %4, %4 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %5, %5, %5 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %6, %6, %6 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %7, %7, %7 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %8, %8, %8 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %9, %9, %9 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %0, %0, %0 row_ror:4 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %1, %1, %1 row_ror:4 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %2, %2, %2 row_ror:4 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %3, %3, %3 row_ror:4 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %4, %4, %4 row_ror:4 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %5, %5, %5 row_ror:4 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %6, %6, %6 row_ror:4 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %7, %7, %7 row_ror:4 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %8, %8, %8 row_ror:4 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %9, %9, %9 row_ror:4 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %0, %0, %0 row_ror:2 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %1, %1, %1 row_ror:2 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %2, %2, %2 row_ror:2 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %3, %3, %3 row_ror:2 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %4, %4, %4 row_ror:2 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %5, %5, %5 row_ror:2 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %6, %6, %6 row_ror:2 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %7, %7, %7 row_ror:2 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %8, %8, %8 row_ror:2 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %9, %9, %9 row_ror:2 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %0, %0, %0 row_ror:1 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %1, %1, %1 row_ror:1 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %2, %2, %2 row_ror:1 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %3, %3, %3 row_ror:1 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %4, %4, %4 row_ror:1 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %5, %5, %5 row_ror:1 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %6, %6, %6 row_ror:1 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %7, %7, %7 row_ror:1 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %8, %8, %8 row_ror:1 row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %9, %9, %9 row_ror:1 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7]),
+          "+v"(v[8]), "+v"(v[9]));
 }
 
 // The compositing of one (tile, pose) by the whole block, or (kGrad) its
@@ -249,14 +293,18 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                     T -= w;
                 } else {
                     // Screen-space gradients of this pixel for this record (u, v,
-                    // A, B, C, opacity, r, g, b, z); zero where it does not contribute.
-                    float gv[kScreenGrads] = {};
-                    if (ok) {
+                    // A, B, C, opacity, r, g, b, z), without a branch: the weight and
+                    // dL/dalpha are zero where the pixel does not take the record (and
+                    // dL/dalpha where alpha is clamped at alpha_max, a constant), so
+                    // those lanes add zeros and keep T and the colour sums unchanged,
+                    // exactly as the forward does.
+                    float gv[kScreenGrads];
+                    {
                         const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
                         const float4 e = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 48);
                         const float gexp = __builtin_amdgcn_exp2f(p2);
                         const float al = clamp_alpha(gexp, k.alpha_max);
-                        const float w = al * T;
+                        const float w = ok ? al * T : 0.f;
                         // colour and depth up to and including this layer (the forward's sums)
                         const float n_r = __builtin_fmaf(c.x, w, cr), n_g = __builtin_fmaf(c.y, w, cg);
                         const float n_b = __builtin_fmaf(c.z, w, cb), n_d = __builtin_fmaf(rb.w, w, dep);
@@ -264,17 +312,16 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                         // dL/dalpha: the layer's own colour minus what it hides behind it
                         const float dla = gr * (c.x * T - (fin_r - n_r) * inv) + gg * (c.y * T - (fin_g - n_g) * inv) +
                                           gb * (c.z * T - (fin_b - n_b) * inv) + gd * (rb.w * T - (fin_d - n_d) * inv);
-                        if (gexp < k.alpha_max) {  // else alpha is clamped, constant
-                            // alpha = o exp(-d^2/2): dalpha/do = alpha / o, dalpha/d(d^2) = -alpha / 2
-                            const float dx = px - ra.x, dy = py - ra.y;
-                            const float gd2 = -0.5f * dla * al;
-                            gv[0] = -2.f * gd2 * (e.x * dx + e.y * dy);
-                            gv[1] = -2.f * gd2 * (e.y * dx + e.z * dy);
-                            gv[2] = gd2 * dx * dx;
-                            gv[3] = 2.f * gd2 * dx * dy;
-                            gv[4] = gd2 * dy * dy;
-                            gv[5] = dla * al * __builtin_amdgcn_rcpf(e.w);
-                        }
+                        // alpha = o exp(-d^2/2): dalpha/do = alpha / o, dalpha/d(d^2) = -alpha / 2
+                        const float dla_f = (ok && gexp < k.alpha_max) ? dla : 0.f;
+                        const float dx = px - ra.x, dy = py - ra.y;
+                        const float gd2 = -0.5f * dla_f * al;
+                        gv[0] = -2.f * gd2 * (e.x * dx + e.y * dy);
+                        gv[1] = -2.f * gd2 * (e.y * dx + e.z * dy);
+                        gv[2] = gd2 * dx * dx;
+                        gv[3] = 2.f * gd2 * dx * dy;
+                        gv[4] = gd2 * dy * dy;
+                        gv[5] = dla_f * al * __builtin_amdgcn_rcpf(e.w);
                         gv[6] = gr * w;
                         gv[7] = gg * w;
                         gv[8] = gb * w;
@@ -289,8 +336,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                     // any lane of the quarter contributing (every lane of a quarter visits the same record)
                     const uint64_t okm = __ballot(ok);
                     if (okm != 0) {
-#pragma unroll
-                        for (int j = 0; j < kScreenGrads; ++j) gv[j] = quarter_sum(gv[j]);
+                        quarter_sums(gv);
                         if ((lane & 15) == 0 && ((okm >> (16 * quarter)) & 0xffffull) != 0) {
                             float *dst = gpose + (int64_t)gi * kScreenGrads;
 #pragma unroll
