@@ -24,7 +24,8 @@
 // The backward of the compositing (k_blend_backward) runs the same walk: with
 // w_i = a_i T_i and S_i the colour behind layer i (the final colour minus the
 // colour up to and including it), dC/da_i = c_i T_i - S_i / (1 - a_i),
-// dC/dc_i = w_i, dD/dz_i = w_i. Each visit's gradients with respect to the
+// dC/dc_i = w_i, dD/dz_i = w_i; dL/da_i takes these dotted with the image
+// gradients, so one running sum of g.c w serves all four channels. Each visit's gradients with respect to the
 // record's (u, v, conic, opacity, colour, depth) are summed over the quarter's
 // 16 lanes, which all visit the same record, and added once per quarter.
 #include "blend_common.h"
@@ -147,21 +148,21 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     unsigned n_contrib = 0, n_visits = 0;  // only with kCount
     const char *s_rec_bytes = reinterpret_cast<const char *>(s_rec);
 
-    // backward: the pixel's final colour and depth and their loss gradients
-    float fin_r = 0.f, fin_g = 0.f, fin_b = 0.f, fin_d = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, gd = 0.f;
+    // backward: the loss gradients of the pixel's colour and depth (g), the
+    // g-weighted final colour and depth, and the g-weighted colour and depth up to
+    // the current layer (s_front, accumulated as the forward accumulates colour)
+    float gr = 0.f, gg = 0.f, gb = 0.f, gd = 0.f, g_fin = 0.f, s_front = 0.f;
     float *gpose = nullptr;
     if constexpr (kGrad) {
         const int64_t hw = (int64_t)width * height;
         const int64_t pix = in_image ? (int64_t)pj * width + pi : 0;
         const int64_t prgb = (int64_t)pose * 3 * hw + pix, pd = (int64_t)pose * hw + pix;
-        fin_r = gio.img_rgb[prgb];
-        fin_g = gio.img_rgb[prgb + hw];
-        fin_b = gio.img_rgb[prgb + 2 * hw];
-        fin_d = gio.img_depth[pd];
         gr = gio.g_rgb[prgb];
         gg = gio.g_rgb[prgb + hw];
         gb = gio.g_rgb[prgb + 2 * hw];
         gd = gio.g_depth[pd];
+        g_fin = gr * gio.img_rgb[prgb] + gg * gio.img_rgb[prgb + hw] + gb * gio.img_rgb[prgb + 2 * hw] +
+                gd * gio.img_depth[pd];
         gpose = gio.gscreen + (int64_t)pose * n * kScreenGrads;
     }
 
@@ -296,8 +297,8 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                     // A, B, C, opacity, r, g, b, z), without a branch: the weight and
                     // dL/dalpha are zero where the pixel does not take the record (and
                     // dL/dalpha where alpha is clamped at alpha_max, a constant), so
-                    // those lanes add zeros and keep T and the colour sums unchanged,
-                    // exactly as the forward does.
+                    // those lanes add zeros and keep T unchanged, exactly as the
+                    // forward does.
                     float gv[kScreenGrads];
                     {
                         const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
@@ -305,13 +306,12 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                         const float gexp = __builtin_amdgcn_exp2f(p2);
                         const float al = clamp_alpha(gexp, k.alpha_max);
                         const float w = ok ? al * T : 0.f;
-                        // colour and depth up to and including this layer (the forward's sums)
-                        const float n_r = __builtin_fmaf(c.x, w, cr), n_g = __builtin_fmaf(c.y, w, cg);
-                        const float n_b = __builtin_fmaf(c.z, w, cb), n_d = __builtin_fmaf(rb.w, w, dep);
+                        // dL/dalpha = g.c T - g.(what this layer hides) / (1 - alpha), with
+                        // g.(hidden) = g.(final) - g.(up to and including this layer)
+                        const float gc = gr * c.x + gg * c.y + gb * c.z + gd * rb.w;
+                        s_front = __builtin_fmaf(gc, w, s_front);
                         const float inv = __builtin_amdgcn_rcpf(1.f - al);
-                        // dL/dalpha: the layer's own colour minus what it hides behind it
-                        const float dla = gr * (c.x * T - (fin_r - n_r) * inv) + gg * (c.y * T - (fin_g - n_g) * inv) +
-                                          gb * (c.z * T - (fin_b - n_b) * inv) + gd * (rb.w * T - (fin_d - n_d) * inv);
+                        const float dla = gc * T - (g_fin - s_front) * inv;
                         // alpha = o exp(-d^2/2): dalpha/do = alpha / o, dalpha/d(d^2) = -alpha / 2
                         const float dla_f = (ok && gexp < k.alpha_max) ? dla : 0.f;
                         const float dx = px - ra.x, dy = py - ra.y;
@@ -327,10 +327,6 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                         gv[8] = gb * w;
                         gv[9] = gd * w;
                         T -= w;
-                        cr = n_r;
-                        cg = n_g;
-                        cb = n_b;
-                        dep = n_d;
                     }
                     const uint32_t gi = __float_as_uint(*reinterpret_cast<const float *>(s_rec_bytes + o + 44));
                     // any lane of the quarter contributing (every lane of a quarter visits the same record)
