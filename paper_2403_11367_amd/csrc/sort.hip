@@ -247,8 +247,9 @@ __global__ __launch_bounds__(kThreads) void k_pose_bases(const uint32_t *__restr
     }
 }
 
-// Exclusive scan of one uint32 per thread across a kRBThreads block; *total gets the sum.
-__device__ uint32_t block_exclusive_scan_512(uint32_t x, uint32_t *s_wave /*[kRBWaves]*/, uint32_t *total) {
+// Exclusive scan of one uint32 per thread across a block of kWaves waves; *total gets the sum.
+template <int kWaves>
+__device__ uint32_t block_exclusive_scan_waves(uint32_t x, uint32_t *s_wave /*[kWaves]*/, uint32_t *total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t inc = x;
 #pragma unroll
@@ -260,7 +261,7 @@ __device__ uint32_t block_exclusive_scan_512(uint32_t x, uint32_t *s_wave /*[kRB
     __syncthreads();
     uint32_t add = 0, sum = 0;
 #pragma unroll
-    for (int w = 0; w < kRBWaves; ++w) {
+    for (int w = 0; w < kWaves; ++w) {
         const uint32_t v = s_wave[w];
         if (w < wave) add += v;
         sum += v;
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int 
         for (int w = 0; w < kRBWaves; ++w) tot += s_cnt[w][threadIdx.x];
     }
     uint32_t all = 0;
-    const uint32_t ls = block_exclusive_scan_512(tot, s_wave, &all);
+    const uint32_t ls = block_exclusive_scan_waves<kRBWaves>(tot, s_wave, &all);
     if (threadIdx.x < kDigits) {
         const int d = threadIdx.x;
         uint32_t run = ls;
@@ -399,7 +400,7 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int 
 constexpr int kFineBits = 6;
 constexpr int kFine = 1 << kFineBits;               // tiles per coarse bucket
 constexpr int kMaxKeys = 256;                       // keys per pass
-constexpr int kCBWaves = 8;
+constexpr int kCBWaves = 4;
 constexpr int kCBThreads = 64 * kCBWaves;
 constexpr int kCBWave = 1024;                       // pairs per wave, contiguous
 constexpr int kCB = kCBWaves * kCBWave;             // pairs per block
@@ -446,10 +447,21 @@ __global__ __launch_bounds__(kThreads) void k_seg_blocks(const uint64_t *__restr
         const uint64_t carry = s_carry;
         const uint32_t first = (uint32_t)(carry + inc - nb);
         if (i <= n_seg) block_base[i] = first;
-        for (uint64_t j = 0; j < nb; ++j) bseg[first + j] = (uint32_t)i;
+        // many short segments: every thread maps its own segment's blocks
+        if (n_seg > kThreads)
+            for (uint64_t j = 0; j < nb; ++j) bseg[first + j] = (uint32_t)i;
         __syncthreads();
         if (threadIdx.x == kThreads - 1) s_carry = carry + inc;
         __syncthreads();
+    }
+    if (n_seg <= kThreads) {
+        // few long segments: a wave maps one segment at a time, 64 blocks per store
+        // (the block's own stores of block_base are visible after the barrier)
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int i = wave; i < n_seg; i += kThreads / 64) {
+            const uint32_t b0 = block_base[i], b1 = block_base[i + 1];
+            for (uint32_t gb = b0 + lane; gb < b1; gb += 64) bseg[gb] = (uint32_t)i;
+        }
     }
 }
 
@@ -612,7 +624,7 @@ __global__ __launch_bounds__(kCBThreads) void k_seg_scatter(SegPass ps, const ui
         for (int w = 0; w < kCBWaves; ++w) tot += s_cnt[w][k];
     }
     uint32_t all = 0;
-    const uint32_t ls = block_exclusive_scan_512(tot, s_wave, &all);
+    const uint32_t ls = block_exclusive_scan_waves<kCBWaves>(tot, s_wave, &all);
     if (k < ps.n_keys) {
         uint32_t run = ls;
 #pragma unroll
