@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kBigThreads) void k_scan_blocks(uint64_t *__restric
 // its elements there in order. The first pass reads the preprocess's 64-slot regions (visible
 // entries packed at the front of each), later passes the dense per-pose
 // segments [vbase[p], vbase[p+1]).
-constexpr int kRBWaves = 8;                // waves per radix block
+constexpr int kRBWaves = 4;                // waves per radix block
 constexpr int kRBThreads = 64 * kRBWaves;
 constexpr int kRBWave = 1024;              // elements per wave, contiguous
 constexpr int kRB = kRBWaves * kRBWave;    // elements per radix block
