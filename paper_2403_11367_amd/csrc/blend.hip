@@ -25,9 +25,11 @@
 // w_i = a_i T_i and S_i the colour behind layer i (the final colour minus the
 // colour up to and including it), dC/da_i = c_i T_i - S_i / (1 - a_i),
 // dC/dc_i = w_i, dD/dz_i = w_i; dL/da_i takes these dotted with the image
-// gradients, so one running sum of g.c w serves all four channels. Each visit's gradients with respect to the
-// record's (u, v, conic, opacity, colour, depth) are summed over the quarter's
-// 16 lanes, which all visit the same record, and added once per quarter.
+// gradients, so one running sum of g.c w serves all four channels. Each visit's
+// gradients with respect to the record's (u, v, conic, opacity, colour, depth)
+// are summed over the quarter's 16 lanes, which all visit the same record, and
+// added to the record's LDS accumulator; at the end of a chunk every staged
+// record's sums go to global memory with one atomic add per value.
 #include "blend_common.h"
 
 namespace gsr {
@@ -113,10 +115,12 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                                            float *__restrict__ out_t, unsigned long long *__restrict__ counters,
                                            const GradIo &gio = GradIo{}) {
     // slot = staging thread; the backward adds a fourth quad (A, B, C, opacity)
-    // and keeps the Gaussian's index in the third quad's w
     constexpr int kQuads = kGrad ? 4 : 3;
     constexpr uint32_t kSlotBytes = 16u * kQuads;
     __shared__ float4 s_rec[kThreads * kQuads];
+    // backward: the gradients of each staged record summed over the chunk's
+    // quarter visits, [value][slot], flushed to global memory once per chunk
+    __shared__ float s_acc[kGrad ? kScreenGrads : 1][kGrad ? kThreads : 1];
     __shared__ uint64_t s_mask[4][4][4];  // [band][quarter][64-record group]
     // per wave, quarter and step: slot of the record the quarter visits
     __shared__ uint8_t s_slots[4][4][256];
@@ -166,12 +170,19 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
         gpose = gio.gscreen + (int64_t)pose * n * kScreenGrads;
     }
 
+    if constexpr (kGrad) {
+#pragma unroll
+        for (int j = 0; j < kScreenGrads; ++j) s_acc[j][tid] = 0.f;
+    }
+    uint32_t staged_g = 0xffffffffu;  // backward: Gaussian this thread staged in the current chunk
+
     for (uint64_t c0 = beg; c0 < end; c0 += 4 * kStage) {
         // stage one record per thread (lanes 0..62 of every wave)
         const uint64_t kk = c0 + (uint64_t)wave * kStage + lane;
         uint32_t cells = 0;  // bit 4 * band + quarter
         if (lane < kStage && kk < end) {
             const uint32_t g = pairs[kk];
+            if constexpr (kGrad) staged_g = g;
             const float4 *r = rec_pose + (int64_t)g * 3;
             const float4 q0 = r[0], q1 = r[1], q2 = r[2];
             const uint32_t rx = __float_as_uint(q2.z), ry = __float_as_uint(q2.w);
@@ -192,10 +203,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             const float iA = __builtin_amdgcn_rcpf(A), idet = __builtin_amdgcn_rcpf(det);
             stage_record(q0, q1, q2, det, k, s_rec[tid * kQuads + 0], s_rec[tid * kQuads + 1],
                          s_rec[tid * kQuads + 2]);
-            if constexpr (kGrad) {
-                s_rec[tid * kQuads + 2].w = __uint_as_float(g);
-                s_rec[tid * kQuads + 3] = make_float4(A, B, C, q1.y);
-            }
+            if constexpr (kGrad) s_rec[tid * kQuads + 3] = make_float4(A, B, C, q1.y);
             const float R2 = k.cull_r2;
             // hardware reciprocal and square root (about 1 ulp) for the overlap test:
             // the margin in R2 covers them
@@ -328,15 +336,14 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                         gv[9] = gd * w;
                         T -= w;
                     }
-                    const uint32_t gi = __float_as_uint(*reinterpret_cast<const float *>(s_rec_bytes + o + 44));
                     // any lane of the quarter contributing (every lane of a quarter visits the same record)
                     const uint64_t okm = __ballot(ok);
                     if (okm != 0) {
                         quarter_sums(gv);
                         if ((lane & 15) == 0 && ((okm >> (16 * quarter)) & 0xffffull) != 0) {
-                            float *dst = gpose + (int64_t)gi * kScreenGrads;
+                            const uint32_t slot = o / kSlotBytes;
 #pragma unroll
-                            for (int j = 0; j < kScreenGrads; ++j) atomicAdd(dst + j, gv[j]);
+                            for (int j = 0; j < kScreenGrads; ++j) atomicAdd(&s_acc[j][slot], gv[j]);
                         }
                     }
                 }
@@ -369,7 +376,21 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                 if (!step(o1, a1, b1)) break;
             }
         }
-        if (__syncthreads_count(!(T < k.t_min)) == 0) break;
+        const int live = __syncthreads_count(!(T < k.t_min));
+        if constexpr (kGrad) {
+            // every wave is done with the chunk: add each staged record's sums once
+            if (staged_g != 0xffffffffu) {
+                float *dst = gpose + (int64_t)staged_g * kScreenGrads;
+#pragma unroll
+                for (int j = 0; j < kScreenGrads; ++j) {
+                    const float v = s_acc[j][tid];
+                    if (v != 0.f) atomicAdd(dst + j, v);
+                    s_acc[j][tid] = 0.f;
+                }
+                staged_g = 0xffffffffu;
+            }
+        }
+        if (live == 0) break;
     }
 
     if (kCount) {
