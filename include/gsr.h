@@ -106,6 +106,13 @@ typedef struct {
 /* gsr_render_cfg.flags: count compositing work into gsr_stats (evals_*), for
  * measurement; a slower kernel variant, same images. */
 #define GSR_RENDER_COUNT_EVALS 1
+/* gsr_render_cfg.flags: keep the compositing state of every tile list longer
+ * than 2016 records (each pixel's transmittance, colour and depth sums before
+ * list positions 2016, 4032, ...) for a following gsr_render_backward, which
+ * then walks such a list as independent segments instead of one serial walk.
+ * Same images. Not with GSR_RENDER_COUNT_EVALS; blend_chunk must be 0 or 252;
+ * blend_blocks_per_cu is not used (grid launch). */
+#define GSR_RENDER_KEEP_STATE 2
 
 /* Counters of the most recent gsr_render / gsr_ncc on the context. */
 typedef struct {
@@ -187,7 +194,8 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
  * submap entry g is input Gaussian g. The contributing set of every pixel (support
  * cutoff, alpha floor, stop after t_min) is taken as fixed; where alpha is clamped at
  * alpha_max it is constant. Per-pixel transmittance is recomputed front to back
- * with the forward's arithmetic, not stored.
+ * with the forward's arithmetic, not stored; if the render had
+ * GSR_RENDER_KEEP_STATE, long lists restart from the kept states, bit for bit.
  *   scales_dev [n,3], quats_dev [n,4]: the arrays sm was loaded from
  *   poses_dev  [P,3,4]: the render's poses
  *   rgb_dev, depth_dev: the render's images [P,3,H,W], [P,H,W]

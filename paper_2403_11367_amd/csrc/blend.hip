@@ -41,11 +41,28 @@ constexpr int kThreads = 256;
 // (chunks of 124 or 60, for earlier exits on short lists). A template parameter.
 constexpr int kDummy = 255;             // LDS slot (wave 3, lane 63) of a record that never contributes
 
+// Kept compositing state: for every tile list longer than kKeepRecords, each
+// pixel's T and colour and depth sums just before list positions kKeepRecords,
+// 2 kKeepRecords, ... (a multiple of the 252-record chunk). cp_off[list] is the
+// index of the list's first kept state (an exclusive prefix over the lists);
+// state [index][5][256]: T, r, g, b, depth per tile pixel (thread index).
+struct KeepIo {
+    const uint32_t *cp_off;
+    float *state;
+};
+
 // Inputs and output of the backward walk, per launch (pose 0 = the launch's first).
+// Block b walks segment s of list items[b] (s = b - list - cp_off[list]): the
+// records from s kKeepRecords to the next kept state or the list's end, starting
+// from kept state s (s > 0) or from T = 1 (s = 0).
 struct GradIo {
     const float *img_rgb, *img_depth;  // the forward's images [P, 3, H, W], [P, H, W]
     const float *g_rgb, *g_depth;      // dL/d(images), same layouts
     float *gscreen;                    // [P, n, 10] screen-space gradients, accumulated
+    const uint32_t *cp_off;            // kept states per list, as in KeepIo (all 0: none kept)
+    const float *state;
+    const uint32_t *items;             // list of each block
+    uint32_t n_lists;
 };
 
 // Sums of the 10 values over each lane's 16-lane DPP row (one quarter): after
@@ -106,14 +123,16 @@ __device__ __forceinline__ void quarter_sums(float (&v)[kScreenGrads]) {
 // The compositing of one (tile, pose) by the whole block, or (kGrad) its
 // backward: the same walk, so the same pixels visit the same records in the
 // same order and recompute the forward's T bit for bit.
-template <bool kCount, int kStage, bool kGrad = false>
+template <bool kCount, int kStage, bool kGrad = false, bool kKeep = false>
 __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__restrict__ records, int64_t n,
                                            const uint32_t *__restrict__ pairs,
                                            const uint64_t *__restrict__ offsets, uint64_t capacity, int width,
                                            int height, int tiles_x, int n_tiles, const BlendConsts &k,
                                            float *__restrict__ out_rgb, float *__restrict__ out_depth,
                                            float *__restrict__ out_t, unsigned long long *__restrict__ counters,
-                                           const GradIo &gio = GradIo{}) {
+                                           const GradIo &gio = GradIo{}, const KeepIo &keep = KeepIo{},
+                                           uint32_t seg = 0) {
+    static_assert(!kKeep || (kStage == 63 && !kGrad), "kept states are written by the 252-record forward");
     // slot = staging thread; the backward adds a fourth quad (A, B, C, opacity)
     constexpr int kQuads = kGrad ? 4 : 3;
     constexpr uint32_t kSlotBytes = 16u * kQuads;
@@ -137,6 +156,12 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     const uint64_t list = (uint64_t)pose * n_tiles + tile;
     const uint64_t beg = offsets[list];
     const uint64_t end = min(offsets[list + 1], capacity);
+    // the walk's range: the whole list, or (backward) one kept-state segment of it
+    uint64_t lbeg = beg, lend = end;
+    if constexpr (kGrad) {
+        lbeg = beg + (uint64_t)seg * kKeepRecords;
+        if (seg < gio.cp_off[list + 1] - gio.cp_off[list]) lend = lbeg + kKeepRecords;
+    }
     const float4 *rec_pose = records + (int64_t)pose * n * 3;
 
     if (tid == kDummy) {  // this thread never stages a record
@@ -168,7 +193,24 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
         g_fin = gr * gio.img_rgb[prgb] + gg * gio.img_rgb[prgb + hw] + gb * gio.img_rgb[prgb + 2 * hw] +
                 gd * gio.img_depth[pd];
         gpose = gio.gscreen + (int64_t)pose * n * kScreenGrads;
+        if (seg > 0) {
+            // the forward's state before this segment, bit for bit
+            const float *st = gio.state + (size_t)(gio.cp_off[list] + seg - 1) * 5 * kThreads;
+            T = st[tid];
+            s_front = gr * st[kThreads + tid] + gg * st[2 * kThreads + tid] + gb * st[3 * kThreads + tid] +
+                      gd * st[4 * kThreads + tid];
+        }
     }
+    // forward with kept states: writes state s (s >= 1) of this list
+    uint32_t kept = 0;  // states written
+    auto keep_state = [&](uint32_t s_index) {
+        float *st = keep.state + (size_t)(keep.cp_off[list] + s_index - 1) * 5 * kThreads;
+        st[tid] = T;
+        st[kThreads + tid] = cr;
+        st[2 * kThreads + tid] = cg;
+        st[3 * kThreads + tid] = cb;
+        st[4 * kThreads + tid] = dep;
+    };
 
     if constexpr (kGrad) {
 #pragma unroll
@@ -176,11 +218,15 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     }
     uint32_t staged_g = 0xffffffffu;  // backward: Gaussian this thread staged in the current chunk
 
-    for (uint64_t c0 = beg; c0 < end; c0 += 4 * kStage) {
+    for (uint64_t c0 = lbeg; c0 < lend; c0 += 4 * kStage) {
+        if constexpr (kKeep) {
+            // chunks are 252 records and kKeepRecords a multiple of that
+            if (c0 != beg && (c0 - beg) % kKeepRecords == 0) keep_state(++kept);
+        }
         // stage one record per thread (lanes 0..62 of every wave)
         const uint64_t kk = c0 + (uint64_t)wave * kStage + lane;
         uint32_t cells = 0;  // bit 4 * band + quarter
-        if (lane < kStage && kk < end) {
+        if (lane < kStage && kk < lend) {
             const uint32_t g = pairs[kk];
             if constexpr (kGrad) staged_g = g;
             const float4 *r = rec_pose + (int64_t)g * 3;
@@ -245,7 +291,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
         }
         __syncthreads();
 
-        const uint32_t n_groups = (uint32_t)min<uint64_t>(4, (end - c0 + kStage - 1) / kStage);
+        const uint32_t n_groups = (uint32_t)min<uint64_t>(4, (lend - c0 + kStage - 1) / kStage);
         uint64_t lm = __ballot(!(T < k.t_min));  // live lanes
         if (lm != 0) {
             // Step i visits the i-th record (in list order) of every quarter that
@@ -392,6 +438,11 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
         }
         if (live == 0) break;
     }
+    if constexpr (kKeep) {
+        // states past an early stop equal the final state (nothing changes after it)
+        const uint32_t n_kept = keep.cp_off[list + 1] - keep.cp_off[list];
+        while (kept < n_kept) keep_state(++kept);
+    }
 
     if (kCount) {
         // contributions summed over the wave; visits are per wave (64 lane slots each)
@@ -467,14 +518,29 @@ void launch_blend_t(hipStream_t s, const float4 *records, int64_t n, int n_poses
                        depth, tfinal, counters);
 }
 
-// Backward of the compositing: one 256-thread block per (tile, pose), the
-// forward's walk (chunks of 252 records).
+// The forward that also keeps the compositing state of long lists (chunks of 252).
+__global__ __launch_bounds__(kThreads) void k_blend_keep(
+    const float4 *__restrict__ records, int64_t n, const uint32_t *__restrict__ pairs,
+    const uint64_t *__restrict__ offsets, uint64_t capacity, int width, int height, int tiles_x, int n_tiles,
+    BlendConsts k, float *__restrict__ out_rgb, float *__restrict__ out_depth, float *__restrict__ out_t,
+    KeepIo keep) {
+    blend_tile<false, 63, false, true>(blockIdx.x, blockIdx.y, records, n, pairs, offsets, capacity, width, height,
+                                       tiles_x, n_tiles, k, out_rgb, out_depth, out_t, nullptr, GradIo{}, keep);
+}
+
+// Backward of the compositing: one 256-thread block per (list, kept-state
+// segment), the forward's walk (chunks of 252 records).
 __global__ __launch_bounds__(kThreads) void k_blend_backward(
     const float4 *__restrict__ records, int64_t n, const uint32_t *__restrict__ pairs,
     const uint64_t *__restrict__ offsets, uint64_t capacity, int width, int height, int tiles_x, int n_tiles,
     BlendConsts k, GradIo gio) {
-    blend_tile<false, 63, true>(blockIdx.x, blockIdx.y, records, n, pairs, offsets, capacity, width, height, tiles_x,
-                                 n_tiles, k, nullptr, nullptr, nullptr, nullptr, gio);
+    const uint32_t b = blockIdx.x;
+    if (b >= gio.n_lists + gio.cp_off[gio.n_lists]) return;  // the grid is an upper bound
+    const uint32_t list = gio.items[b];
+    const uint32_t seg = b - list - gio.cp_off[list];
+    blend_tile<false, 63, true>((int)(list % (uint32_t)n_tiles), (int)(list / (uint32_t)n_tiles), records, n, pairs,
+                                offsets, capacity, width, height, tiles_x, n_tiles, k, nullptr, nullptr, nullptr,
+                                nullptr, gio, KeepIo{}, seg);
 }
 
 }  // namespace
@@ -482,10 +548,13 @@ __global__ __launch_bounds__(kThreads) void k_blend_backward(
 void launch_blend_backward(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
                            const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
                            const TileGrid &tg, const float *img_rgb, const float *img_depth, const float *g_rgb,
-                           const float *g_depth, float *gscreen) {
-    const GradIo gio{img_rgb, img_depth, g_rgb, g_depth, gscreen};
-    hipLaunchKernelGGL(k_blend_backward, dim3((unsigned)tg.n_tiles, (unsigned)n_poses), dim3(kThreads), 0, s, records,
-                       n, pairs, offsets, capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, blend_consts(k), gio);
+                           const float *g_depth, float *gscreen, const uint32_t *keep_off, const float *keep_state,
+                           const uint32_t *items, uint64_t max_blocks) {
+    const uint32_t n_lists = (uint32_t)tg.n_tiles * (uint32_t)n_poses;
+    const GradIo gio{img_rgb, img_depth, g_rgb, g_depth, gscreen, keep_off, keep_state, items, n_lists};
+    if (max_blocks == 0) return;
+    hipLaunchKernelGGL(k_blend_backward, dim3((unsigned)max_blocks), dim3(kThreads), 0, s, records, n, pairs, offsets,
+                       capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, blend_consts(k), gio);
 }
 
 bool blend_chunk_supported(int chunk) { return chunk == 0 || chunk == 252 || chunk == 124 || chunk == 60; }
@@ -493,8 +562,15 @@ bool blend_chunk_supported(int chunk) { return chunk == 0 || chunk == 252 || chu
 void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
                   const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
                   const TileGrid &tg, float *rgb, float *depth, float *tfinal, bool count_evals,
-                  unsigned long long *counters, int persistent_blocks, unsigned int *queue, int chunk) {
+                  unsigned long long *counters, int persistent_blocks, unsigned int *queue, int chunk,
+                  const uint32_t *keep_off, float *keep_state) {
     const BlendConsts bc = blend_consts(k);
+    if (keep_off) {
+        hipLaunchKernelGGL(k_blend_keep, dim3((unsigned)tg.n_tiles, (unsigned)n_poses), dim3(kThreads), 0, s, records,
+                           n, pairs, offsets, capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, bc, rgb, depth,
+                           tfinal, KeepIo{keep_off, keep_state});
+        return;
+    }
 #define GSR_BLEND(C, S)                                                                                              \
     launch_blend_t<C, S>(s, records, n, n_poses, pairs, offsets, capacity, cam, tg, bc, rgb, depth, tfinal, counters, \
                          persistent_blocks, queue)

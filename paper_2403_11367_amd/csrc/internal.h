@@ -132,21 +132,42 @@ void launch_bucket(hipStream_t s, const uint16_t *ptile, const uint32_t *pk, con
                    uint64_t capacity, int n_tiles, uint32_t *block_base, uint32_t *bseg, uint32_t *cnt,
                    uint64_t *cstart, uint16_t *ctile, uint32_t *cval, uint64_t *offsets, uint32_t *sk);
 
+// Kept compositing states (see kKeepRecords): keep_off[l] = states of lists j < l,
+// l in [0, n_lists], from the list offsets clipped to the capacity. One block.
+void launch_keep_offsets(hipStream_t s, const uint64_t *offsets, uint64_t capacity, uint32_t n_lists,
+                         uint32_t *keep_off);
+// items[b] = list of backward block b: list l owns blocks l + keep_off[l] ..
+// l + keep_off[l + 1] (one per segment).
+void launch_keep_items(hipStream_t s, const uint32_t *keep_off, uint32_t n_lists, uint32_t *items);
+
 // ---- blend.hip ----
+// With keep_off (GSR_RENDER_KEEP_STATE): the 252-record grid launch that also
+// writes the kept compositing states of long lists (see kKeepRecords);
+// count_evals, persistent_blocks and chunk are then not used.
 void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
                   const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
                   const TileGrid &tg, float *rgb, float *depth, float *tfinal, bool count_evals,
-                  unsigned long long *counters, int persistent_blocks, unsigned int *queue, int chunk);
+                  unsigned long long *counters, int persistent_blocks, unsigned int *queue, int chunk,
+                  const uint32_t *keep_off, float *keep_state);
 // Records per compositing chunk the blend is built for (0 = the default, 252).
 bool blend_chunk_supported(int chunk);
 // Screen-space gradients per (pose, Gaussian): u, v, conic A, B, C, opacity, r, g, b, z.
 constexpr int kScreenGrads = 10;
+// Records between kept compositing states of a long tile list (8 chunks of 252):
+// the forward with GSR_RENDER_KEEP_STATE stores each pixel's T, colour and depth
+// sums [5][256] before list positions kKeepRecords, 2 kKeepRecords, ..., so that
+// the backward can walk a long list as several independent segments.
+constexpr uint64_t kKeepRecords = 2016;
 // Backward of the compositing: adds the screen-space gradients of every (pose,
 // Gaussian) pair into gscreen [n_poses, n, kScreenGrads] (which the caller zeroes).
+// One block per (list, segment): keep_off [lists + 1] the kept states per list
+// (all zero when none were kept), items [max_blocks] the list of each block
+// (launch_keep_items), max_blocks at least lists + kept states.
 void launch_blend_backward(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
                            const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
                            const TileGrid &tg, const float *img_rgb, const float *img_depth, const float *g_rgb,
-                           const float *g_depth, float *gscreen);
+                           const float *g_depth, float *gscreen, const uint32_t *keep_off, const float *keep_state,
+                           const uint32_t *items, uint64_t max_blocks);
 
 // ---- ncc.hip ----
 int ncc_pixels_per_block();

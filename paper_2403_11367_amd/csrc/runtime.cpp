@@ -53,7 +53,7 @@ struct gsr_ctx {
         void *p = nullptr;
         size_t bytes = 0;
     } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, esum, pseg, ptile, pk,
-        sk, ccnt, cstart, ctile, cval, block_base, bseg, offsets, grey_q, partials, s_order, s_poses, s_rgb, s_depth,
+        sk, ccnt, cstart, ctile, cval, block_base, bseg, offsets, keep_off, keep_state, keep_items, grey_q, partials, s_order, s_poses, s_rgb, s_depth,
         s_scores, pr_grey, pr_q3, pr_x, pr_rgb, pr_depth, bw_screen, bw_pose;
     // layout of the last render's pose groups
     struct Group {
@@ -66,12 +66,14 @@ struct gsr_ctx {
         uint64_t pairs = 0, cap = 0;   // pair buffers: cap entries from pairs
         uint64_t cnt = 0;              // bucketing counts
         uint64_t bsg = 0;              // bucketing block -> segment map
+        uint64_t kst = 0, kit = 0;     // kept compositing states (floats) and backward items
     };
     Group groups[kMaxGroups];
     int n_groups = 0;
     int64_t last_n = 0, last_poses = 0, last_tiles = 0;
     // what the backward needs of the last render
     int64_t render_serial = 0;
+    bool last_keep = false;        // the last render kept its long lists' compositing states
     const gsr_submap *last_sm = nullptr;  // single-submap render, else null
     uint64_t last_sm_version = 0;
     gsr::Camera last_cam{};
@@ -290,7 +292,8 @@ int gsr_destroy(gsr_ctx *ctx) {
                             &ctx->cval,      &ctx->block_base, &ctx->bseg, &ctx->offsets, &ctx->grey_q, &ctx->partials,
                             &ctx->s_order,   &ctx->s_poses, &ctx->s_rgb,     &ctx->s_depth,   &ctx->s_scores,
                             &ctx->pr_grey,   &ctx->pr_q3,   &ctx->pr_x,      &ctx->pr_rgb,    &ctx->pr_depth,
-                            &ctx->bw_screen, &ctx->bw_pose};
+                            &ctx->bw_screen, &ctx->bw_pose, &ctx->keep_off, &ctx->keep_state,
+                            &ctx->keep_items};
     for (auto *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
@@ -384,7 +387,7 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         cfg = *cfg_in;
     else
         gsr_default_cfg(&cfg);
-    if (!pow2(cfg.tile_w) || !pow2(cfg.tile_h) || (cfg.flags & ~GSR_RENDER_COUNT_EVALS) != 0 ||
+    if (!pow2(cfg.tile_w) || !pow2(cfg.tile_h) || (cfg.flags & ~(GSR_RENDER_COUNT_EVALS | GSR_RENDER_KEEP_STATE)) != 0 ||
         cfg.pair_capacity < 0 || cfg.pose_groups < 0 || cfg.pose_groups > kMaxGroups)
         return fail(ctx, GSR_EINVAL, "bad render configuration");
     if (cfg.tile_w != 16 || cfg.tile_h != 16) return fail(ctx, GSR_EUNSUPPORTED, "this build renders 16x16 tiles");
@@ -424,6 +427,9 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         return fail(ctx, GSR_EINVAL, "blend_blocks_per_cu out of [0, 64]");
     if (!gsr::blend_chunk_supported(cfg.blend_chunk))
         return fail(ctx, GSR_EUNSUPPORTED, "blend_chunk must be 0, 252, 124 or 60");
+    const bool keep = (cfg.flags & GSR_RENDER_KEEP_STATE) != 0;
+    if (keep && ((cfg.flags & GSR_RENDER_COUNT_EVALS) || (cfg.blend_chunk != 0 && cfg.blend_chunk != 252)))
+        return fail(ctx, GSR_EUNSUPPORTED, "GSR_RENDER_KEEP_STATE needs 252-record chunks and no evaluation counting");
 
     // pose groups: automatic = one. Splitting a render of 64 poses at 1408x376 into
     // 2, 4 or 8 concurrent groups measured 1-13% slower: the ordering of a group
@@ -463,11 +469,12 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         (rc = ensure(ctx, ctx->pseg, ((uint64_t)P + G) * sizeof(uint64_t), "pair segments")) ||
         (rc = ensure(ctx, ctx->cstart, n_cst * sizeof(uint64_t), "coarse bucket starts")) ||
         (rc = ensure(ctx, ctx->offsets, (n_lists + G) * sizeof(uint64_t), "offsets")) ||
+        (rc = ensure(ctx, ctx->keep_off, (n_lists + G) * sizeof(uint32_t), "kept-state offsets")) ||
         (rc = ensure(ctx, ctx->block_base, n_cst * sizeof(uint32_t), "block bases")))
         return rc;
     // with a fixed capacity every buffer is sized now, before any launch
     auto size_pairs = [&](const uint64_t *caps) -> int {
-        uint64_t n_pairs = 0, n_cnt = 0, n_bsg = 0;
+        uint64_t n_pairs = 0, n_cnt = 0, n_bsg = 0, n_kst = 0;
         for (int g = 0; g < G; ++g) {
             gsr_ctx::Group &gr = ctx->groups[g];
             gr.cap = caps[g];
@@ -477,6 +484,8 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
             n_cnt += gsr::bucket_count_elems(gr.cap, (int)gr.np, tg.n_tiles);
             gr.bsg = n_bsg;
             n_bsg += gsr::bucket_blocks_max(gr.cap, (int)gr.np, tg.n_tiles);
+            gr.kst = n_kst;
+            if (keep) n_kst += gr.cap / gsr::kKeepRecords * 5 * 256;  // at most one state per kKeepRecords pairs
         }
         int r;
         if ((r = ensure(ctx, ctx->ptile, n_pairs * sizeof(uint16_t), "pair tiles")) ||
@@ -485,7 +494,8 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
             (r = ensure(ctx, ctx->ctile, n_pairs * sizeof(uint16_t), "bucketed pair tiles")) ||
             (r = ensure(ctx, ctx->cval, n_pairs * sizeof(uint32_t), "bucketed pair indices")) ||
             (r = ensure(ctx, ctx->ccnt, n_cnt * sizeof(uint32_t), "bucket counts")) ||
-            (r = ensure(ctx, ctx->bseg, n_bsg * sizeof(uint32_t), "bucket block segments")))
+            (r = ensure(ctx, ctx->bseg, n_bsg * sizeof(uint32_t), "bucket block segments")) ||
+            (keep && (r = ensure(ctx, ctx->keep_state, std::max<uint64_t>(1, n_kst) * sizeof(float), "kept states"))))
             return r;
         return GSR_OK;
     };
@@ -547,6 +557,9 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
                            (uint64_t *)ctx->cstart.p + gr.cst, (uint16_t *)ctx->ctile.p + gr.pairs,
                            (uint32_t *)ctx->cval.p + gr.pairs, (uint64_t *)ctx->offsets.p + gr.off,
                            (uint32_t *)ctx->sk.p + gr.pairs);
+        if (keep)
+            gsr::launch_keep_offsets(st, (const uint64_t *)ctx->offsets.p + gr.off, gr.cap, (uint32_t)(gr.np * T),
+                                     (uint32_t *)ctx->keep_off.p + gr.off);
     };
     auto composite = [&](int g, hipStream_t st) {
         const gsr_ctx::Group &gr = ctx->groups[g];
@@ -554,7 +567,9 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
                           (const uint32_t *)ctx->sk.p + gr.pairs, (const uint64_t *)ctx->offsets.p + gr.off, gr.cap, c,
                           k, tg, rgb + gr.p0 * 3 * hw, depth + gr.p0 * hw, tfinal ? tfinal + gr.p0 * hw : nullptr,
                           (cfg.flags & GSR_RENDER_COUNT_EVALS) != 0, ctx->d_counters,
-                          cfg.blend_blocks_per_cu * ctx->n_cu, ctx->d_queue + g, cfg.blend_chunk);
+                          cfg.blend_blocks_per_cu * ctx->n_cu, ctx->d_queue + g, cfg.blend_chunk,
+                          keep ? (const uint32_t *)ctx->keep_off.p + gr.off : nullptr,
+                          keep ? (float *)ctx->keep_state.p + gr.kst : nullptr);
     };
 
     if (exact) {
@@ -603,6 +618,7 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
     ctx->last_sm = tab.count == 1 ? last_sm_hint : nullptr;
     ctx->last_sm_version = last_sm_hint ? last_sm_hint->version : 0;
     ctx->last_cam = c;
+    ctx->last_keep = keep;
     ctx->last_consts = k;
     ctx->last_tg = tg;
     return GSR_OK;
@@ -650,14 +666,33 @@ int gsr_render_backward(gsr_ctx *ctx, const gsr_submap *sm, const float *scales,
     float *gscreen = (float *)ctx->bw_screen.p;
     gsr::launch_fill_u32(s, (uint32_t *)gscreen, (uint64_t)P * n * ns, 0u);
     const float4 *records = (const float4 *)ctx->records.p;
+    // one backward block per (list, kept-state segment); without kept states one per list
+    const uint64_t T = (uint64_t)tg.n_tiles;
+    uint64_t blocks[kMaxGroups] = {}, n_items = 0;
+    for (int g = 0; g < ctx->n_groups; ++g) {
+        const gsr_ctx::Group &gr = ctx->groups[g];
+        blocks[g] = (uint64_t)gr.np * T + (ctx->last_keep ? gr.cap / gsr::kKeepRecords : 0);
+        n_items += blocks[g];
+    }
+    if ((rc = ensure(ctx, ctx->keep_items, std::max<uint64_t>(1, n_items) * sizeof(uint32_t), "backward blocks")))
+        return rc;
+    uint64_t item0 = 0;
     for (int g = 0; g < ctx->n_groups; ++g) {
         const gsr_ctx::Group &gr = ctx->groups[g];
         if (gr.np <= 0) continue;
+        const uint32_t n_lists = (uint32_t)(gr.np * T);
+        uint32_t *keep_off = (uint32_t *)ctx->keep_off.p + gr.off;
+        if (!ctx->last_keep) gsr::launch_fill_u32(s, keep_off, (uint64_t)n_lists + 1, 0u);
+        uint32_t *items = (uint32_t *)ctx->keep_items.p + item0;
+        gsr::launch_keep_items(s, keep_off, n_lists, items);
         gsr::launch_blend_backward(s, records + (uint64_t)gr.p0 * n * gsr::kRecordQuads, n, (int)gr.np,
                                    (const uint32_t *)ctx->sk.p + gr.pairs, (const uint64_t *)ctx->offsets.p + gr.off,
                                    gr.cap, ctx->last_cam, ctx->last_consts, tg, rgb + gr.p0 * 3 * hw,
                                    depth + gr.p0 * hw, grad_rgb + gr.p0 * 3 * hw, grad_depth + gr.p0 * hw,
-                                   gscreen + (uint64_t)gr.p0 * n * ns);
+                                   gscreen + (uint64_t)gr.p0 * n * ns, keep_off,
+                                   ctx->last_keep ? (const float *)ctx->keep_state.p + gr.kst : nullptr, items,
+                                   blocks[g]);
+        item0 += blocks[g];
     }
     gsr::launch_project_backward(s, sm->packed, n, poses, n_poses, ctx->last_cam, ctx->last_consts,
                                  (const uint32_t *)ctx->ntiles.p, gscreen, (float *)ctx->bw_pose.p);

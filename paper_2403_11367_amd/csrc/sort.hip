@@ -680,7 +680,50 @@ void launch_seg_pass(hipStream_t s, const SegPass &ps, uint64_t n_blocks, uint32
     }
 }
 
+// keep_off[l] = kept states of lists j < l (one per kKeepRecords records beyond
+// the first kKeepRecords of a list), l in [0, n_lists]. One block.
+__global__ __launch_bounds__(kThreads) void k_keep_offsets(const uint64_t *__restrict__ offsets, uint64_t capacity,
+                                                           uint32_t n_lists, uint32_t *__restrict__ keep_off) {
+    __shared__ uint64_t s_wave[4];
+    __shared__ uint64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 <= n_lists; c0 += kThreads) {
+        const uint32_t l = c0 + threadIdx.x;
+        uint64_t nk = 0;
+        if (l < n_lists) {
+            const uint64_t b = min(offsets[l], capacity), e = min(offsets[l + 1], capacity);
+            if (e > b + kKeepRecords) nk = (e - b - 1) / kKeepRecords;
+        }
+        const uint64_t inc = block_inclusive_scan(nk, s_wave);
+        const uint64_t carry = s_carry;
+        if (l <= n_lists) keep_off[l] = (uint32_t)(carry + inc - nk);
+        __syncthreads();
+        if (threadIdx.x == kThreads - 1) s_carry = carry + inc;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_keep_items(const uint32_t *__restrict__ keep_off, uint32_t n_lists,
+                                                         uint32_t *__restrict__ items) {
+    const uint32_t l = blockIdx.x * kThreads + threadIdx.x;
+    if (l >= n_lists) return;
+    const uint32_t first = l + keep_off[l], count = 1 + keep_off[l + 1] - keep_off[l];
+    for (uint32_t j = 0; j < count; ++j) items[first + j] = l;
+}
+
 }  // namespace
+
+void launch_keep_offsets(hipStream_t s, const uint64_t *offsets, uint64_t capacity, uint32_t n_lists,
+                         uint32_t *keep_off) {
+    hipLaunchKernelGGL(k_keep_offsets, dim3(1), dim3(kThreads), 0, s, offsets, capacity, n_lists, keep_off);
+}
+
+void launch_keep_items(hipStream_t s, const uint32_t *keep_off, uint32_t n_lists, uint32_t *items) {
+    if (n_lists == 0) return;
+    hipLaunchKernelGGL(k_keep_items, dim3((n_lists + kThreads - 1) / kThreads), dim3(kThreads), 0, s, keep_off,
+                       n_lists, items);
+}
 
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t value) {
     if (n == 0) return;

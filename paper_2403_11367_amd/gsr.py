@@ -24,6 +24,7 @@ STATUS = {0: "GSR_OK", -1: "GSR_EINVAL", -2: "GSR_ENOMEM", -3: "GSR_EHIP", -4: "
           -5: "GSR_EOVERFLOW", -6: "GSR_EUNSUPPORTED", -7: "GSR_EDEVICE"}
 BUF_RECORDS, BUF_NTILES, BUF_OFFSETS, BUF_PAIRS = 0, 1, 2, 3
 RENDER_COUNT_EVALS = 1
+RENDER_KEEP_STATE = 2  # keep long lists' compositing states for gsr_render_backward
 
 # every symbol declared in include/gsr.h and include/gsr_scorer.h
 EXPORTS = [

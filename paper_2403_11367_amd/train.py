@@ -10,7 +10,9 @@ differentiates; torch holds the tensors, computes the loss and runs Adam.
 """
 from __future__ import annotations
 
+import copy
 import dataclasses
+
 import numpy as np
 
 
@@ -34,8 +36,12 @@ def _render_function():
 
         @staticmethod
         def forward(fctx, means, scales, quats, opacity, colours, ctx, slot, camera, poses, cfg):
+            from .gsr import RENDER_KEEP_STATE, default_cfg
             args = [t.detach().contiguous() for t in (means, scales, quats, opacity, colours)]
             slot.sm = ctx.load_submap(*args, into=slot.sm)
+            # keep the long lists' compositing states, so that the backward walks them in segments
+            cfg = default_cfg() if cfg is None else copy.copy(cfg)
+            cfg.flags |= RENDER_KEEP_STATE
             img, depth = ctx.render(slot.sm, camera, poses, cfg)
             fctx.ctx, fctx.sm = ctx, slot.sm
             fctx.serial = ctx.stats()["render_serial"]

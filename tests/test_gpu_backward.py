@@ -168,3 +168,98 @@ def test_backward_with_alpha_and_jacobian_clamps(ctx):
                 assert abs(got - fd) <= 1e-3 * abs(fd) + 1e-5, (gi, name, comp, got, fd)
     say(f"  {n_checked} stable parameters checked")
     assert n_checked >= 30
+
+
+def _stacked_scene(n, seed):
+    """n small, faint, anisotropic Gaussians stacked over the two tiles at the centre
+    of a 64x48 image: tile lists of about 0.6 n records, whose pixels never reach
+    t_min."""
+    rng = np.random.default_rng(seed)
+    y = rng.uniform(3.0, 30.0, n)
+    x = rng.uniform(-0.02, 0.02, n) * y
+    z = rng.uniform(-0.02, 0.02, n) * y
+    scales = 0.002 * y[:, None] * rng.uniform(0.6, 1.2, (n, 3))
+    g = W.Gaussians(np.stack([x, y, z], 1).astype(np.float32), scales.astype(np.float32),
+                    rng.normal(size=(n, 4)).astype(np.float32), np.full(n, 0.015, np.float32),
+                    rng.uniform(0, 1, (n, 3)).astype(np.float32))
+    cam = W.Camera(64, 48, 400.0, 400.0, 32.0, 24.0)
+    poses = W.yaw_grid_poses(np.zeros(3), W.AXES_ALONG_Y, [0.0], [0.0], [0.0]).astype(np.float32)
+    return g, cam, poses
+
+
+def test_backward_splits_long_lists_at_kept_states(ctx):
+    """Tile lists of about 5000 records: with GSR_RENDER_KEEP_STATE the forward keeps
+    each pixel's state at records 2016 and 4032 (images unchanged, bit for bit) and
+    the backward walks the list as three segments. Its gradients equal those of the
+    one serial walk (to float-atomic rounding) and, for Gaussians in the later
+    segments, float64 central differences."""
+    import torch
+    from paper_2403_11367_amd import default_cfg
+    from paper_2403_11367_amd.gsr import RENDER_KEEP_STATE
+    g, cam, poses = _stacked_scene(8000, 9)
+    p = R.as_params(g)
+    scr = R.project(p, poses[0], cam)
+    rng = np.random.default_rng(3)
+    w_rgb = rng.normal(size=(1, 3, cam.height, cam.width))
+    w_depth = 0.1 * rng.normal(size=(1, cam.height, cam.width))
+    say("render backward: tile lists of about 5000 records, kept states vs one serial walk")
+    arrs = [to_dev(a.astype(np.float32)) for a in g.arrays()]
+    sm = ctx.load_submap(*arrs)
+    pt = to_dev(poses)
+    res = []
+    for cfg in (None, default_cfg(flags=RENDER_KEEP_STATE)):
+        rgb, depth = ctx.render(sm, camera(cam), pt, cfg)
+        grads = ctx.render_backward(sm, arrs[1], arrs[2], pt, rgb, depth, to_dev(w_rgb.astype(np.float32)),
+                                    to_dev(w_depth.astype(np.float32)))
+        torch.cuda.synchronize()
+        res.append(([rgb.cpu().numpy(), depth.cpu().numpy()], [t.cpu().numpy().astype(np.float64) for t in grads]))
+    from paper_2403_11367_amd import BUF_OFFSETS
+    offs = ctx.debug_buffer(BUF_OFFSETS)
+    longest = int(np.max(np.diff(offs.astype(np.int64))))
+    say(f"  longest list {longest}")
+    assert longest > 2 * 2016
+    for a, b in zip(res[0][0], res[1][0]):
+        assert np.array_equal(a, b)
+    for a, b in zip(res[0][1], res[1][1]):
+        assert np.allclose(a, b, rtol=1e-4, atol=1e-5 * np.abs(a).max())
+    gm, gs, gq, go, gc = res[1][1]
+    s = np.exp(p.log_scales)
+    o = 1.0 / (1.0 + np.exp(-p.logits))
+    gpu = {"means": gm, "log_scales": gs * s, "quats": gq, "logits": go * o * (1 - o), "rgb": gc}
+    # the farther half by depth: about 2400 or more records into their tiles' lists
+    vis = np.nonzero(scr.visible)[0]
+    deep = vis[np.argsort(scr.z[vis], kind="stable")][4000:]
+    rows = {k: [] for k in GROUPS}
+    for gi in rng.choice(deep, 24, replace=False):
+        for k, name in enumerate(GROUPS):
+            for comp in range(WIDTH[name]):
+                fd, stable = R.fd_gradient(p, poses, cam, w_rgb, w_depth, int(gi), k, comp, STEPS[name])
+                if stable:
+                    rows[name].append((fd, gpu[name][gi] if gpu[name].ndim == 1 else gpu[name][gi, comp]))
+    n_checked = 0
+    for name in GROUPS:
+        arr = np.array(rows[name]).reshape(-1, 2)
+        n_checked += len(arr)
+        scale = np.median(np.abs(arr[:, 0]))
+        err = np.abs(arr[:, 1] - arr[:, 0])
+        tol = 1e-3 * np.abs(arr[:, 0]) + 1e-3 * scale
+        say(f"  {name}: {len(arr)} stable, median |fd| {scale:.3e}, worst err/tol {np.max(err / tol):.3f}")
+        assert np.all(err <= tol), name
+    assert n_checked >= 100
+    sm.free()
+
+
+def test_keep_state_rejects_count_evals_and_other_chunks(ctx):
+    """Kept states are taken at 2016-record boundaries of the 252-record chunk walk
+    without evaluation counting: other combinations are refused."""
+    from paper_2403_11367_amd import GsrError, default_cfg
+    from paper_2403_11367_amd.gsr import RENDER_COUNT_EVALS, RENDER_KEEP_STATE
+    sc = W.config0()
+    arrs = [to_dev(a.astype(np.float32)) for a in sc.gaussians.arrays()]
+    sm = ctx.load_submap(*arrs)
+    pt = to_dev(sc.poses[:2].astype(np.float32))
+    for cfg in (default_cfg(flags=RENDER_KEEP_STATE | RENDER_COUNT_EVALS),
+                default_cfg(flags=RENDER_KEEP_STATE, blend_chunk=124)):
+        with pytest.raises(GsrError, match="EUNSUPPORTED"):
+            ctx.render(sm, camera(sc.camera), pt, cfg)
+    sm.free()
