@@ -110,7 +110,9 @@ typedef struct {
  * than 2016 records (each pixel's transmittance, colour and depth sums before
  * list positions 2016, 4032, ...) for a following gsr_render_backward, which
  * then walks such a list as independent segments instead of one serial walk.
- * Same images. Not with GSR_RENDER_COUNT_EVALS; blend_chunk must be 0 or 252;
+ * Same images. The states take 5 KB per 2016 records of pair capacity (context
+ * memory, kept until the next render). Not with GSR_RENDER_COUNT_EVALS (else
+ * GSR_EUNSUPPORTED); blend_chunk must be 0 or 252 (else GSR_EUNSUPPORTED);
  * blend_blocks_per_cu is not used (grid launch). */
 #define GSR_RENDER_KEEP_STATE 2
 
@@ -195,7 +197,8 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
  * cutoff, alpha floor, stop after t_min) is taken as fixed; where alpha is clamped at
  * alpha_max it is constant. Per-pixel transmittance is recomputed front to back
  * with the forward's arithmetic, not stored; if the render had
- * GSR_RENDER_KEEP_STATE, long lists restart from the kept states, bit for bit.
+ * GSR_RENDER_KEEP_STATE, each 2016-record segment of a long list starts from the
+ * state the forward kept there (equal, bit for bit, to the serial walk's state).
  *   scales_dev [n,3], quats_dev [n,4]: the arrays sm was loaded from
  *   poses_dev  [P,3,4]: the render's poses
  *   rgb_dev, depth_dev: the render's images [P,3,H,W], [P,H,W]
