@@ -133,7 +133,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                                            const GradIo &gio = GradIo{}, const KeepIo &keep = KeepIo{},
                                            uint32_t seg = 0) {
     static_assert(!kKeep || (kStage == 63 && !kGrad), "kept states are written by the 252-record forward");
-    // slot = staging thread; the backward adds a fourth quad (A, B, C, opacity)
+    // slot = staging thread; the backward adds a fourth quad (A, B, C, u - tile centre x)
     constexpr int kQuads = kGrad ? 4 : 3;
     constexpr uint32_t kSlotBytes = 16u * kQuads;
     __shared__ float4 s_rec[kThreads * kQuads];
@@ -149,9 +149,10 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     const int quarter = lane >> 4;
     const int pi = tx * 16 + quarter * 4 + (lane & 3);
     const int pj = ty * 16 + wave * 4 + ((lane >> 2) & 3);
-    const float px = (float)pi + 0.5f, py = (float)pj + 0.5f;
     const bool in_image = pi < width && pj < height;
     const int row0 = ty * 16, col0 = tx * 16;
+    // pixel centre relative to the tile centre (col0 + 8, row0 + 8), exact
+    const float xc = (float)(pi - col0) - 7.5f, yc = (float)(pj - row0) - 7.5f;
 
     const uint64_t list = (uint64_t)pose * n_tiles + tile;
     const uint64_t beg = offsets[list];
@@ -247,16 +248,17 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             // about sqrt(A C / det) times less to rounding than the expanded form
             const float det = conic_det(A, B, C);
             const float iA = __builtin_amdgcn_rcpf(A), idet = __builtin_amdgcn_rcpf(det);
-            stage_record(q0, q1, q2, det, k, s_rec[tid * kQuads + 0], s_rec[tid * kQuads + 1],
+            const float u_rel = q0.x - (float)col0, v_rel = q0.y - (float)row0;
+            const float uc = q0.x - (float)(col0 + 8), vc = q0.y - (float)(row0 + 8);  // from the tile centre
+            stage_record(q0, q1, q2, det, uc, vc, k, s_rec[tid * kQuads + 0], s_rec[tid * kQuads + 1],
                          s_rec[tid * kQuads + 2]);
-            if constexpr (kGrad) s_rec[tid * kQuads + 3] = make_float4(A, B, C, q1.y);
+            if constexpr (kGrad) s_rec[tid * kQuads + 3] = make_float4(A, B, C, uc);
             const float R2 = k.cull_r2;
             // hardware reciprocal and square root (about 1 ulp) for the overlap test:
             // the margin in R2 covers them
             const float ryv = __builtin_amdgcn_sqrtf(R2 * A * idet);
             const float dxm = __builtin_amdgcn_sqrtf(R2 * C * idet);
             const float dys = -B * __builtin_amdgcn_rcpf(C) * dxm;  // dy of the rightmost point of E
-            const float u_rel = q0.x - (float)col0, v_rel = q0.y - (float)row0;
             if (det > 0.f && __builtin_isfinite(ryv) && __builtin_isfinite(dxm) && __builtin_isfinite(dys)) {
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
@@ -326,9 +328,9 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                 ra = *reinterpret_cast<const float4 *>(s_rec_bytes + o);
                 rb = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 16);
             };
-            // one step on a staged record; false when the wave is done with the chunk
-            auto step = [&](uint32_t o, const float4 &ra, const float4 &rb) -> bool {
-                const float p2 = footprint_p2(ra, rb, px, py);
+            // one step on a staged record: lanes outside the live mask lm take nothing
+            auto step = [&](uint32_t o, const float4 &ra, const float4 &rb) {
+                const float p2 = footprint_p2(ra, rb, xc, yc);
                 const bool ok = __builtin_amdgcn_inverse_ballot_w64(lm) && p2 >= rb.y;
                 if (kCount) {
                     n_contrib += ok;
@@ -368,14 +370,15 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                         const float dla = gc * T - (g_fin - s_front) * inv;
                         // alpha = o exp(-d^2/2): dalpha/do = alpha / o, dalpha/d(d^2) = -alpha / 2
                         const float dla_f = (ok && gexp < k.alpha_max) ? dla : 0.f;
-                        const float dx = px - ra.x, dy = py - ra.y;
+                        // (u - xc, v - yc) of the record: e.w and c.w
+                        const float dx = xc - e.w, dy = yc - c.w;
                         const float gd2 = -0.5f * dla_f * al;
                         gv[0] = -2.f * gd2 * (e.x * dx + e.y * dy);
                         gv[1] = -2.f * gd2 * (e.y * dx + e.z * dy);
                         gv[2] = gd2 * dx * dx;
                         gv[3] = 2.f * gd2 * dx * dy;
                         gv[4] = gd2 * dy * dy;
-                        gv[5] = dla_f * al * __builtin_amdgcn_rcpf(e.w);
+                        gv[5] = dla_f * al * __builtin_amdgcn_exp2f(-rb.z);  // 1 / o = 2^-log2(o)
                         gv[6] = gr * w;
                         gv[7] = gg * w;
                         gv[8] = gb * w;
@@ -393,10 +396,35 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                         }
                     }
                 }
-                const uint64_t lm_next = __ballot(!(T < k.t_min));
-                if (lm_next != lm) {
-                    lm = lm_next;
-                    if (lm == 0) return false;
+                lm = __ballot(!(T < k.t_min));
+            };
+            const uint8_t *sp = &s_slots[wave][quarter][0];  // this lane's quarter; sp[j] = slot of step i + j
+            float4 a0, b0, a1, b1;
+            uint32_t o0 = sp[0] * kSlotBytes, o1;
+            load(o0, a0, b0);
+            uint32_t s_next = sp[1];
+            // Steps go in pairs, and the live mask is checked after each pair: a
+            // pixel that stops in the first step of a pair is masked in the second
+            // (lm is updated every step), and a step past a quarter's walk reads the
+            // dummy record (every slot list is dummy-filled to 256), so the extra
+            // step of an odd count changes nothing. Checking per pair keeps the
+            // loop's scalar bookkeeping off every other step. (Groups of 4 steps
+            // measured slower: the forward then spills registers.)
+            uint64_t lm_seen = lm;
+            // i < steps <= 252 with i even, so every slot read, at most i + 3,
+            // stays below 256
+            for (uint32_t i = 0; i < steps; i += 2, sp += 2) {
+                o1 = s_next * kSlotBytes;  // step i + 1
+                load(o1, a1, b1);
+                s_next = sp[2];  // step i + 2
+                step(o0, a0, b0);
+                o0 = s_next * kSlotBytes;  // step i + 2
+                load(o0, a0, b0);
+                s_next = sp[3];  // step i + 3
+                step(o1, a1, b1);
+                if (lm != lm_seen) {
+                    if (lm == 0) break;
+                    lm_seen = lm;
                     // steps still needed by the quarters that have live pixels
                     uint32_t need = 0;
 #pragma unroll
@@ -404,22 +432,6 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                         if (((lm >> (16 * q)) & 0xffffull) != 0) need = max(need, cnt[q]);
                     steps = __builtin_amdgcn_readfirstlane(need);
                 }
-                return true;
-            };
-            const uint8_t *sp = &s_slots[wave][quarter][0];  // this lane's quarter; sp[j] = slot of step i + j
-            float4 a0, b0, a1, b1;
-            uint32_t o0 = sp[0] * kSlotBytes, o1;
-            load(o0, a0, b0);
-            uint32_t s_next = sp[1];
-            for (uint32_t i = 0; i < steps; i += 2, sp += 2) {
-                o1 = s_next * kSlotBytes;  // step i + 1 (step index <= 252)
-                load(o1, a1, b1);
-                s_next = sp[2];  // step i + 2 (<= 253)
-                if (!step(o0, a0, b0) || i + 1 >= steps) break;
-                o0 = s_next * kSlotBytes;  // step i + 2
-                load(o0, a0, b0);
-                s_next = sp[3];  // i + 1 < steps <= 252, so step i + 3 <= 253
-                if (!step(o1, a1, b1)) break;
             }
         }
         const int live = __syncthreads_count(!(T < k.t_min));
