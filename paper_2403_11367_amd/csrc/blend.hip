@@ -142,7 +142,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     __shared__ float s_acc[kGrad ? kScreenGrads : 1][kGrad ? kThreads : 1];
     __shared__ uint64_t s_mask[4][4][4];  // [band][quarter][64-record group]
     // per wave, quarter and step: slot of the record the quarter visits
-    __shared__ uint8_t s_slots[4][4][256];
+    __shared__ __attribute__((aligned(4))) uint8_t s_slots[4][4][256];
 
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -304,7 +304,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             uint32_t *slots32 = reinterpret_cast<uint32_t *>(&s_slots[wave][0][0]);
 #pragma unroll
             for (int e = 0; e < 4; ++e) slots32[e * 64 + lane] = kDummy * 0x01010101u;
-            uint32_t cnt[4], steps = 0;
+            uint32_t steps = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 uint32_t run = 0;
@@ -319,7 +319,6 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                         run += (uint32_t)__popcll(m);
                     }
                 }
-                cnt[q] = run;
                 steps = max(steps, run);
             }
             // Software pipeline, unrolled twice so the two register sets alternate:
@@ -403,35 +402,27 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             uint32_t o0 = sp[0] * kSlotBytes, o1;
             load(o0, a0, b0);
             uint32_t s_next = sp[1];
-            // Steps go in pairs, and the live mask is checked after each pair: a
+            // Steps go in pairs, and the wave's exit is checked after each pair: a
             // pixel that stops in the first step of a pair is masked in the second
             // (lm is updated every step), and a step past a quarter's walk reads the
             // dummy record (every slot list is dummy-filled to 256), so the extra
-            // step of an odd count changes nothing. Checking per pair keeps the
-            // loop's scalar bookkeeping off every other step. (Groups of 4 steps
-            // measured slower: the forward then spills registers.)
-            uint64_t lm_seen = lm;
+            // step of an odd count changes nothing. The walk ends at the longest
+            // quarter's count, or when no pixel of the wave is live. (Checking every
+            // step, and shortening the walk when a quarter's pixels have all
+            // stopped, cost more in scalar instructions than they saved.) The two
+            // slots of the next pair are one 16-bit read: pairs start at even steps.
             // i < steps <= 252 with i even, so every slot read, at most i + 3,
             // stays below 256
             for (uint32_t i = 0; i < steps; i += 2, sp += 2) {
                 o1 = s_next * kSlotBytes;  // step i + 1
                 load(o1, a1, b1);
-                s_next = sp[2];  // step i + 2
+                const uint32_t pr = *reinterpret_cast<const uint16_t *>(sp + 2);  // steps i + 2, i + 3
                 step(o0, a0, b0);
-                o0 = s_next * kSlotBytes;  // step i + 2
+                o0 = (pr & 0xffu) * kSlotBytes;  // step i + 2
                 load(o0, a0, b0);
-                s_next = sp[3];  // step i + 3
+                s_next = pr >> 8;  // step i + 3
                 step(o1, a1, b1);
-                if (lm != lm_seen) {
-                    if (lm == 0) break;
-                    lm_seen = lm;
-                    // steps still needed by the quarters that have live pixels
-                    uint32_t need = 0;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (((lm >> (16 * q)) & 0xffffull) != 0) need = max(need, cnt[q]);
-                    steps = __builtin_amdgcn_readfirstlane(need);
-                }
+                if (lm == 0) break;
             }
         }
         const int live = __syncthreads_count(!(T < k.t_min));
