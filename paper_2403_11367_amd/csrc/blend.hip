@@ -11,9 +11,9 @@
 // quarters (lanes 16q..16q+15). The block walks the tile's list in chunks of
 // 252 records: every thread but the last of each wave stages one record in LDS
 // (the conic as two scaled square-root factors, log2 of the opacity, and one
-// log2 threshold that folds the cutoff and the alpha floor) and marks which
-// (band, quarter) cells its support ellipse overlaps; ballots turn the marks
-// into one 64-bit mask per (band, quarter, 64-record group). A wave then walks
+// log2 threshold that folds the cutoff and the alpha floor) and writes which
+// (band, quarter) cells its support ellipse overlaps; each wave ballots its
+// band's marks into one 64-bit mask per (quarter, 64-record group). A wave walks
 // its four quarters side by side: step i takes the i-th record of every
 // quarter (a quarter with fewer reads a record that cannot contribute; the
 // per-step slots are laid out in LDS once per chunk), so a chunk costs the
@@ -140,7 +140,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     // backward: the gradients of each staged record summed over the chunk's
     // quarter visits, [value][slot], flushed to global memory once per chunk
     __shared__ float s_acc[kGrad ? kScreenGrads : 1][kGrad ? kThreads : 1];
-    __shared__ uint64_t s_mask[4][4][4];  // [band][quarter][64-record group]
+    __shared__ uint16_t s_cells[kThreads];  // (band, quarter) cells of the record in each slot
     // per wave, quarter and step: slot of the record the quarter visits
     __shared__ __attribute__((aligned(4))) uint8_t s_slots[4][4][256];
 
@@ -286,14 +286,11 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                         if (j0 <= 4 * b + 3 && j1 >= 4 * b && i0 <= 4 * q + 3 && i1 >= 4 * q) cells |= 1u << (4 * b + q);
             }
         }
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            const uint64_t m = __ballot((cells >> c) & 1u);
-            if (lane == 0) s_mask[c >> 2][c & 3][wave] = m;
-        }
+        s_cells[tid] = (uint16_t)cells;  // 0 for a thread without a record
         __syncthreads();
 
-        const uint32_t n_groups = (uint32_t)min<uint64_t>(4, (lend - c0 + kStage - 1) / kStage);
+        const uint32_t n_left = (uint32_t)min<uint64_t>(lend - c0, 4 * kStage);
+        const uint32_t n_groups = (n_left + kStage - 1) / kStage;  // 64-record groups staged
         uint64_t lm = __ballot(!(T < k.t_min));  // live lanes
         if (lm != 0) {
             // Step i visits the i-th record (in list order) of every quarter that
@@ -304,23 +301,22 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             uint32_t *slots32 = reinterpret_cast<uint32_t *>(&s_slots[wave][0][0]);
 #pragma unroll
             for (int e = 0; e < 4; ++e) slots32[e * 64 + lane] = kDummy * 0x01010101u;
-            uint32_t steps = 0;
+            // Group by group (lane l: the record in slot 64 g + l), each quarter's
+            // walk grows by the group's records that overlap the quarter's cell.
+            uint32_t run[4] = {0u, 0u, 0u, 0u};
+            for (uint32_t grp = 0; grp < n_groups; ++grp) {
+                const uint32_t cw = s_cells[grp * 64 + lane] >> (4 * wave);  // this band's 4 marks
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint32_t run = 0;
-                if (((lm >> (16 * q)) & 0xffffull) != 0) {
-                    for (uint32_t grp = 0; grp < n_groups; ++grp) {
-                        const uint64_t mv = s_mask[wave][q][grp];
-                        const uint32_t mlo = __builtin_amdgcn_readfirstlane((uint32_t)mv);
-                        const uint32_t mhi = __builtin_amdgcn_readfirstlane((uint32_t)(mv >> 32));
-                        const uint64_t m = ((uint64_t)mhi << 32) | mlo;
-                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, 0u));
-                        if (__builtin_amdgcn_inverse_ballot_w64(m)) s_slots[wave][q][run + rank] = (uint8_t)(grp * 64 + lane);
-                        run += (uint32_t)__popcll(m);
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    if (((lm >> (16 * q)) & 0xffffull) == 0) continue;  // no live pixel in the quarter
+                    const uint64_t m = __ballot((cw >> q) & 1u);
+                    const uint32_t rank =
+                        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    if (__builtin_amdgcn_inverse_ballot_w64(m)) s_slots[wave][q][run[q] + rank] = (uint8_t)(grp * 64 + lane);
+                    run[q] += (uint32_t)__popcll(m);
                 }
-                steps = max(steps, run);
             }
+            const uint32_t steps = max(max(run[0], run[1]), max(run[2], run[3]));
             // Software pipeline, unrolled twice so the two register sets alternate:
             // the slots and geometry of step i + 1 are read during step i.
             auto load = [&](uint32_t o, float4 &ra, float4 &rb) {
