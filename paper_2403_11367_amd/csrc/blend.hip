@@ -140,9 +140,15 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     // backward: the gradients of each staged record summed over the chunk's
     // quarter visits, [value][slot], flushed to global memory once per chunk
     __shared__ float s_acc[kGrad ? kScreenGrads : 1][kGrad ? kThreads : 1];
-    __shared__ uint16_t s_cells[kThreads];  // (band, quarter) cells of the record in each slot
+    // (band, quarter) cells of the record in each slot: the forward keeps them in
+    // the unused last word of the colour quad (s2.w), the backward here
+    __shared__ uint16_t s_cells[kGrad ? kThreads : 1];
     // per wave, quarter and step: slot of the record the quarter visits
-    __shared__ __attribute__((aligned(4))) uint8_t s_slots[4][4][256];
+    // per wave, quarter and step: LDS byte offset of the record the quarter
+    // visits (steps 0..253: a walk has at most 252 steps and reads 2 ahead)
+    constexpr int kSlotCap = 254;
+    __shared__ __attribute__((aligned(4))) uint16_t s_slots[4][4][kSlotCap];
+    __shared__ uint32_t s_live[4];  // per wave: any pixel still live after the chunk
 
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -286,7 +292,11 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                         if (j0 <= 4 * b + 3 && j1 >= 4 * b && i0 <= 4 * q + 3 && i1 >= 4 * q) cells |= 1u << (4 * b + q);
             }
         }
-        s_cells[tid] = (uint16_t)cells;  // 0 for a thread without a record
+        // 0 for a thread without a record (the dummy's colour quad is all 0)
+        if constexpr (kGrad)
+            s_cells[tid] = (uint16_t)cells;
+        else
+            reinterpret_cast<uint32_t *>(&s_rec[tid * kQuads + 2])[3] = cells;
         __syncthreads();
 
         const uint32_t n_left = (uint32_t)min<uint64_t>(lend - c0, 4 * kStage);
@@ -299,24 +309,34 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             // walk; every lane then reads its own quarter's slots. One wave: its
             // LDS accesses complete in program order.
             uint32_t *slots32 = reinterpret_cast<uint32_t *>(&s_slots[wave][0][0]);
+            constexpr uint32_t kDummyPair = kDummy * kSlotBytes * 0x00010001u;
+            static_assert(kDummy * kSlotBytes < 65536u && (4 * kSlotCap) % 2 == 0, "16-bit offsets, whole words");
 #pragma unroll
-            for (int e = 0; e < 4; ++e) slots32[e * 64 + lane] = kDummy * 0x01010101u;
+            for (int e = 0; e < (4 * kSlotCap / 2 + 63) / 64; ++e)
+                if (e * 64 + lane < 4 * kSlotCap / 2) slots32[e * 64 + lane] = kDummyPair;
             // Group by group (lane l: the record in slot 64 g + l), each quarter's
             // walk grows by the group's records that overlap the quarter's cell.
             uint32_t run[4] = {0u, 0u, 0u, 0u};
             for (uint32_t grp = 0; grp < n_groups; ++grp) {
-                const uint32_t cw = s_cells[grp * 64 + lane] >> (4 * wave);  // this band's 4 marks
+                uint32_t cw;  // this band's 4 marks
+                if constexpr (kGrad)
+                    cw = s_cells[grp * 64 + lane];
+                else
+                    cw = reinterpret_cast<const uint32_t *>(&s_rec[(grp * 64 + lane) * kQuads + 2])[3];
+                cw >>= 4 * wave;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (((lm >> (16 * q)) & 0xffffull) == 0) continue;  // no live pixel in the quarter
                     const uint64_t m = __ballot((cw >> q) & 1u);
                     const uint32_t rank =
                         __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    if (__builtin_amdgcn_inverse_ballot_w64(m)) s_slots[wave][q][run[q] + rank] = (uint8_t)(grp * 64 + lane);
+                    if (__builtin_amdgcn_inverse_ballot_w64(m))
+                        s_slots[wave][q][run[q] + rank] = (uint16_t)((grp * 64 + lane) * kSlotBytes);
                     run[q] += (uint32_t)__popcll(m);
                 }
             }
-            const uint32_t steps = max(max(run[0], run[1]), max(run[2], run[3]));
+            // (uniform: every run is a sum of ballot counts)
+            const uint32_t steps = __builtin_amdgcn_readfirstlane(max(max(run[0], run[1]), max(run[2], run[3])));
             // Software pipeline, unrolled twice so the two register sets alternate:
             // the slots and geometry of step i + 1 are read during step i.
             auto load = [&](uint32_t o, float4 &ra, float4 &rb) {
@@ -393,35 +413,41 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                 }
                 lm = __ballot(!(T < k.t_min));
             };
-            const uint8_t *sp = &s_slots[wave][quarter][0];  // this lane's quarter; sp[j] = slot of step i + j
+            const uint16_t *sp = &s_slots[wave][quarter][0];  // this lane's quarter; sp[j]: step i + j
             float4 a0, b0, a1, b1;
-            uint32_t o0 = sp[0] * kSlotBytes, o1;
+            uint32_t o0 = sp[0], o1;
             load(o0, a0, b0);
-            uint32_t s_next = sp[1];
+            uint32_t o_next = sp[1];
             // Steps go in pairs, and the wave's exit is checked after each pair: a
             // pixel that stops in the first step of a pair is masked in the second
             // (lm is updated every step), and a step past a quarter's walk reads the
-            // dummy record (every slot list is dummy-filled to 256), so the extra
-            // step of an odd count changes nothing. The walk ends at the longest
-            // quarter's count, or when no pixel of the wave is live. (Checking every
-            // step, and shortening the walk when a quarter's pixels have all
-            // stopped, cost more in scalar instructions than they saved.) The two
-            // slots of the next pair are one 16-bit read: pairs start at even steps.
+            // dummy record (every slot list is dummy-filled), so the extra step of an
+            // odd count changes nothing. The walk ends at the longest quarter's
+            // count, or when no pixel of the wave is live. (Checking every step, and
+            // shortening the walk when a quarter's pixels have all stopped, cost more
+            // in scalar instructions than they saved.)
             // i < steps <= 252 with i even, so every slot read, at most i + 3,
-            // stays below 256
+            // stays below kSlotCap
             for (uint32_t i = 0; i < steps; i += 2, sp += 2) {
-                o1 = s_next * kSlotBytes;  // step i + 1
+                o1 = o_next;  // step i + 1
                 load(o1, a1, b1);
-                const uint32_t pr = *reinterpret_cast<const uint16_t *>(sp + 2);  // steps i + 2, i + 3
+                const uint32_t oa = sp[2], ob = sp[3];  // steps i + 2, i + 3
                 step(o0, a0, b0);
-                o0 = (pr & 0xffu) * kSlotBytes;  // step i + 2
+                o0 = oa;
                 load(o0, a0, b0);
-                s_next = pr >> 8;  // step i + 3
+                o_next = ob;
                 step(o1, a1, b1);
                 if (lm == 0) break;
             }
         }
-        const int live = __syncthreads_count(!(T < k.t_min));
+        // any live pixel in the block (each wave's flag is read after the barrier and
+        // rewritten only after the next chunk's barrier)
+        {
+            const bool wave_live = __ballot(!(T < k.t_min)) != 0;
+            if (lane == 0) s_live[wave] = wave_live;
+        }
+        __syncthreads();
+        const bool live = (s_live[0] | s_live[1] | s_live[2] | s_live[3]) != 0;
         if constexpr (kGrad) {
             // every wave is done with the chunk: add each staged record's sums once
             if (staged_g != 0xffffffffu) {
@@ -435,7 +461,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                 staged_g = 0xffffffffu;
             }
         }
-        if (live == 0) break;
+        if (!live) break;
     }
     if constexpr (kKeep) {
         // states past an early stop equal the final state (nothing changes after it)
