@@ -39,6 +39,10 @@ namespace {
 constexpr int kThreads = 256;
 // Records staged per wave and chunk: 63 (lane 63 idle; a chunk of 252), 31 or 15
 // (chunks of 124 or 60, for earlier exits on short lists). A template parameter.
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
+};
 constexpr int kDummy = 255;             // LDS slot (wave 3, lane 63) of a record that never contributes
 
 // Kept compositing state: for every tile list longer than kKeepRecords, each
@@ -148,7 +152,8 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     // visits (steps 0..253: a walk has at most 252 steps and reads 2 ahead)
     constexpr int kSlotCap = 254;
     __shared__ __attribute__((aligned(4))) uint16_t s_slots[4][4][kSlotCap];
-    __shared__ uint32_t s_live[4];  // per wave: any pixel still live after the chunk
+    __shared__ uint32_t s_live[4];   // per wave: any pixel still live after the chunk
+    __shared__ uint32_t s_clamp[4];  // per wave: a staged record whose alpha may reach alpha_max
 
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -233,11 +238,15 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
         // stage one record per thread (lanes 0..62 of every wave)
         const uint64_t kk = c0 + (uint64_t)wave * kStage + lane;
         uint32_t cells = 0;  // bit 4 * band + quarter
+        bool may_clamp = false;  // o exp(-d^2/2) can reach alpha_max (o near or above it)
         if (lane < kStage && kk < lend) {
             const uint32_t g = pairs[kk];
             if constexpr (kGrad) staged_g = g;
             const float4 *r = rec_pose + (int64_t)g * 3;
             const float4 q0 = r[0], q1 = r[1], q2 = r[2];
+            // 2^p2 <= 2^log2(o) ~ o (hardware log2 and exp2: a few ulp), so below this
+            // bound the clamp at alpha_max never acts
+            may_clamp = q1.y > k.alpha_max * 0.9999f;
             const uint32_t rx = __float_as_uint(q2.z), ry = __float_as_uint(q2.w);
             const int j0 = (int)(ry & 0xffffu) - row0, j1 = (int)(ry >> 16) - row0;
             // Cells are (band, quarter) pixel blocks. The support ellipse
@@ -297,7 +306,13 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             s_cells[tid] = (uint16_t)cells;
         else
             reinterpret_cast<uint32_t *>(&s_rec[tid * kQuads + 2])[3] = cells;
+        {
+            const bool wave_clamp = __ballot(may_clamp) != 0;
+            if (lane == 0) s_clamp[wave] = wave_clamp;
+        }
         __syncthreads();
+        // read here, rewritten only after the end-of-chunk barrier
+        const bool clamp_chunk = kGrad || (s_clamp[0] | s_clamp[1] | s_clamp[2] | s_clamp[3]) != 0;
 
         const uint32_t n_left = (uint32_t)min<uint64_t>(lend - c0, 4 * kStage);
         const uint32_t n_groups = (n_left + kStage - 1) / kStage;  // 64-record groups staged
@@ -343,102 +358,113 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                 ra = *reinterpret_cast<const float4 *>(s_rec_bytes + o);
                 rb = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 16);
             };
-            // one step on a staged record: lanes outside the live mask lm take nothing
-            auto step = [&](uint32_t o, const float4 &ra, const float4 &rb) {
-                const float p2 = footprint_p2(ra, rb, xc, yc);
-                const bool ok = __builtin_amdgcn_inverse_ballot_w64(lm) && p2 >= rb.y;
-                if (kCount) {
-                    n_contrib += ok;
-                    ++n_visits;
-                }
-                if constexpr (!kGrad) {
-                    // Without a branch: w = 0 where the pixel does not take this
-                    // record, and fma(c, 0, x) = x, T - 0 = T exactly (the sums are
-                    // finite and never -0), so every pixel's result is unchanged.
-                    const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
-                    const float al = clamp_alpha(__builtin_amdgcn_exp2f(p2), k.alpha_max);
-                    const float w = ok ? al * T : 0.f;
-                    cr = __builtin_fmaf(c.x, w, cr);
-                    cg = __builtin_fmaf(c.y, w, cg);
-                    cb = __builtin_fmaf(c.z, w, cb);
-                    dep = __builtin_fmaf(rb.w, w, dep);
-                    T -= w;
-                } else {
-                    // Screen-space gradients of this pixel for this record (u, v,
-                    // A, B, C, opacity, r, g, b, z), without a branch: the weight and
-                    // dL/dalpha are zero where the pixel does not take the record (and
-                    // dL/dalpha where alpha is clamped at alpha_max, a constant), so
-                    // those lanes add zeros and keep T unchanged, exactly as the
-                    // forward does.
-                    float gv[kScreenGrads];
-                    {
-                        const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
-                        const float4 e = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 48);
-                        const float gexp = __builtin_amdgcn_exp2f(p2);
-                        const float al = clamp_alpha(gexp, k.alpha_max);
-                        const float w = ok ? al * T : 0.f;
-                        // dL/dalpha = g.c T - g.(what this layer hides) / (1 - alpha), with
-                        // g.(hidden) = g.(final) - g.(up to and including this layer)
-                        const float gc = gr * c.x + gg * c.y + gb * c.z + gd * rb.w;
-                        s_front = __builtin_fmaf(gc, w, s_front);
-                        const float inv = __builtin_amdgcn_rcpf(1.f - al);
-                        const float dla = gc * T - (g_fin - s_front) * inv;
-                        // alpha = o exp(-d^2/2): dalpha/do = alpha / o, dalpha/d(d^2) = -alpha / 2
-                        const float dla_f = (ok && gexp < k.alpha_max) ? dla : 0.f;
-                        // (u - xc, v - yc) of the record: e.w and c.w
-                        const float dx = xc - e.w, dy = yc - c.w;
-                        const float gd2 = -0.5f * dla_f * al;
-                        gv[0] = -2.f * gd2 * (e.x * dx + e.y * dy);
-                        gv[1] = -2.f * gd2 * (e.y * dx + e.z * dy);
-                        gv[2] = gd2 * dx * dx;
-                        gv[3] = 2.f * gd2 * dx * dy;
-                        gv[4] = gd2 * dy * dy;
-                        gv[5] = dla_f * al * __builtin_amdgcn_exp2f(-rb.z);  // 1 / o = 2^-log2(o)
-                        gv[6] = gr * w;
-                        gv[7] = gg * w;
-                        gv[8] = gb * w;
-                        gv[9] = gd * w;
-                        T -= w;
+            // The walk, with (kClamp) or without the clamp of alpha at alpha_max: a
+            // chunk none of whose records can reach alpha_max skips it (exactly: the
+            // clamp is then the identity).
+            auto walk = [&](auto clamp_tag) {
+                constexpr bool kClamp = decltype(clamp_tag)::value;
+                // one step on a staged record: lanes outside the live mask lm take nothing
+                auto step = [&](uint32_t o, const float4 &ra, const float4 &rb) {
+                    const float p2 = footprint_p2(ra, rb, xc, yc);
+                    const bool ok = __builtin_amdgcn_inverse_ballot_w64(lm) && p2 >= rb.y;
+                    if (kCount) {
+                        n_contrib += ok;
+                        ++n_visits;
                     }
-                    // any lane of the quarter contributing (every lane of a quarter visits the same record)
-                    const uint64_t okm = __ballot(ok);
-                    if (okm != 0) {
-                        quarter_sums(gv);
-                        if ((lane & 15) == 0 && ((okm >> (16 * quarter)) & 0xffffull) != 0) {
-                            const uint32_t slot = o / kSlotBytes;
+                    if constexpr (!kGrad) {
+                        // Without a branch: w = 0 where the pixel does not take this
+                        // record, and fma(c, 0, x) = x, T - 0 = T exactly (the sums are
+                        // finite and never -0), so every pixel's result is unchanged.
+                        const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
+                        const float e = __builtin_amdgcn_exp2f(p2);
+                        const float al = kClamp ? clamp_alpha(e, k.alpha_max) : e;
+                        const float w = ok ? al * T : 0.f;
+                        cr = __builtin_fmaf(c.x, w, cr);
+                        cg = __builtin_fmaf(c.y, w, cg);
+                        cb = __builtin_fmaf(c.z, w, cb);
+                        dep = __builtin_fmaf(rb.w, w, dep);
+                        T -= w;
+                    } else {
+                        // Screen-space gradients of this pixel for this record (u, v,
+                        // A, B, C, opacity, r, g, b, z), without a branch: the weight and
+                        // dL/dalpha are zero where the pixel does not take the record (and
+                        // dL/dalpha where alpha is clamped at alpha_max, a constant), so
+                        // those lanes add zeros and keep T unchanged, exactly as the
+                        // forward does.
+                        float gv[kScreenGrads];
+                        {
+                            const float4 c = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 32);
+                            const float4 e = *reinterpret_cast<const float4 *>(s_rec_bytes + o + 48);
+                            const float gexp = __builtin_amdgcn_exp2f(p2);
+                            const float al = clamp_alpha(gexp, k.alpha_max);
+                            const float w = ok ? al * T : 0.f;
+                            // dL/dalpha = g.c T - g.(what this layer hides) / (1 - alpha), with
+                            // g.(hidden) = g.(final) - g.(up to and including this layer)
+                            const float gc = gr * c.x + gg * c.y + gb * c.z + gd * rb.w;
+                            s_front = __builtin_fmaf(gc, w, s_front);
+                            const float inv = __builtin_amdgcn_rcpf(1.f - al);
+                            const float dla = gc * T - (g_fin - s_front) * inv;
+                            // alpha = o exp(-d^2/2): dalpha/do = alpha / o, dalpha/d(d^2) = -alpha / 2
+                            const float dla_f = (ok && gexp < k.alpha_max) ? dla : 0.f;
+                            // (u - xc, v - yc) of the record: e.w and c.w
+                            const float dx = xc - e.w, dy = yc - c.w;
+                            const float gd2 = -0.5f * dla_f * al;
+                            gv[0] = -2.f * gd2 * (e.x * dx + e.y * dy);
+                            gv[1] = -2.f * gd2 * (e.y * dx + e.z * dy);
+                            gv[2] = gd2 * dx * dx;
+                            gv[3] = 2.f * gd2 * dx * dy;
+                            gv[4] = gd2 * dy * dy;
+                            gv[5] = dla_f * al * __builtin_amdgcn_exp2f(-rb.z);  // 1 / o = 2^-log2(o)
+                            gv[6] = gr * w;
+                            gv[7] = gg * w;
+                            gv[8] = gb * w;
+                            gv[9] = gd * w;
+                            T -= w;
+                        }
+                        // any lane of the quarter contributing (every lane of a quarter visits the same record)
+                        const uint64_t okm = __ballot(ok);
+                        if (okm != 0) {
+                            quarter_sums(gv);
+                            if ((lane & 15) == 0 && ((okm >> (16 * quarter)) & 0xffffull) != 0) {
+                                const uint32_t slot = o / kSlotBytes;
 #pragma unroll
-                            for (int j = 0; j < kScreenGrads; ++j) atomicAdd(&s_acc[j][slot], gv[j]);
+                                for (int j = 0; j < kScreenGrads; ++j) atomicAdd(&s_acc[j][slot], gv[j]);
+                            }
                         }
                     }
-                }
-                lm = __ballot(!(T < k.t_min));
-            };
-            const uint16_t *sp = &s_slots[wave][quarter][0];  // this lane's quarter; sp[j]: step i + j
-            float4 a0, b0, a1, b1;
-            uint32_t o0 = sp[0], o1;
-            load(o0, a0, b0);
-            uint32_t o_next = sp[1];
-            // Steps go in pairs, and the wave's exit is checked after each pair: a
-            // pixel that stops in the first step of a pair is masked in the second
-            // (lm is updated every step), and a step past a quarter's walk reads the
-            // dummy record (every slot list is dummy-filled), so the extra step of an
-            // odd count changes nothing. The walk ends at the longest quarter's
-            // count, or when no pixel of the wave is live. (Checking every step, and
-            // shortening the walk when a quarter's pixels have all stopped, cost more
-            // in scalar instructions than they saved.)
-            // i < steps <= 252 with i even, so every slot read, at most i + 3,
-            // stays below kSlotCap
-            for (uint32_t i = 0; i < steps; i += 2, sp += 2) {
-                o1 = o_next;  // step i + 1
-                load(o1, a1, b1);
-                const uint32_t oa = sp[2], ob = sp[3];  // steps i + 2, i + 3
-                step(o0, a0, b0);
-                o0 = oa;
+                    lm = __ballot(!(T < k.t_min));
+                };
+                const uint16_t *sp = &s_slots[wave][quarter][0];  // this lane's quarter; sp[j]: step i + j
+                float4 a0, b0, a1, b1;
+                uint32_t o0 = sp[0], o1;
                 load(o0, a0, b0);
-                o_next = ob;
-                step(o1, a1, b1);
-                if (lm == 0) break;
-            }
+                uint32_t o_next = sp[1];
+                // Steps go in pairs, and the wave's exit is checked after each pair: a
+                // pixel that stops in the first step of a pair is masked in the second
+                // (lm is updated every step), and a step past a quarter's walk reads the
+                // dummy record (every slot list is dummy-filled), so the extra step of an
+                // odd count changes nothing. The walk ends at the longest quarter's
+                // count, or when no pixel of the wave is live. (Checking every step, and
+                // shortening the walk when a quarter's pixels have all stopped, cost more
+                // in scalar instructions than they saved.)
+                // i < steps <= 252 with i even, so every slot read, at most i + 3,
+                // stays below kSlotCap
+                for (uint32_t i = 0; i < steps; i += 2, sp += 2) {
+                    o1 = o_next;  // step i + 1
+                    load(o1, a1, b1);
+                    const uint32_t oa = sp[2], ob = sp[3];  // steps i + 2, i + 3
+                    step(o0, a0, b0);
+                    o0 = oa;
+                    load(o0, a0, b0);
+                    o_next = ob;
+                    step(o1, a1, b1);
+                    if (lm == 0) break;
+                }
+            };
+            if (clamp_chunk)
+                walk(BoolTag<true>{});
+            else if constexpr (!kGrad)
+                walk(BoolTag<false>{});
         }
         // any live pixel in the block (each wave's flag is read after the barrier and
         // rewritten only after the next chunk's barrier)

@@ -63,6 +63,33 @@ def test_tiny_scenes_ragged_sizes(ctx, seed, n, w, h):
         compare_render(rgb[p], dep[p], tf[p], out, f"pose {p}")
 
 
+def test_alpha_clamp_in_some_chunks(ctx):
+    """Every 500th Gaussian at opacity 0.9995, so that alpha is clamped at alpha_max
+    near those centres: about half of the 252-record chunks hold such a record and
+    composite with the clamp, the others without it, and both must match the
+    oracle."""
+    say("alpha clamp mixed into some chunks: 3000 Gaussians, 64x48, 3 poses")
+    sc = W.tiny_scene(71, n=3000, width=64, height=48, n_poses=3)
+    g = sc.gaussians
+    op = g.opacity.copy()
+    op[::500] = np.float32(0.9995)
+    g = W.Gaussians(g.means, g.scales, g.quats, op, g.rgb)
+    sm = load(ctx, g)
+    rgb, dep, tf = gpu_render(ctx, sm, sc.camera, sc.poses)
+    recs, nts, offs, pairs = gpu_buffers(ctx)
+    pr = prep(g)
+    T = _tiles(sc.camera)
+    n_clamped = 0
+    for p in range(3):
+        out, rec, ks, vs, rng = oracle_pose(pr, sc.poses[p], sc.camera)
+        check_records(recs, nts, rec, g.n, p)
+        check_pairs(offs, pairs, ks, vs, rng, p, T)
+        compare_render(rgb[p], dep[p], tf[p], out, f"pose {p}")
+        n_clamped += int((rec.opacity[rec.visible] > 0.99).sum())
+    assert n_clamped > 0
+    sm.free()
+
+
 @pytest.mark.parametrize("seed", [41, 42])
 def test_thin_tilted_and_huge_gaussians(ctx, seed):
     """Needle-thin tilted footprints and a few that cover the whole image: the
