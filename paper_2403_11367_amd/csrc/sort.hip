@@ -135,6 +135,10 @@ __device__ __forceinline__ bool radix_elem(const RadixSrc &src, int p, uint32_t 
 }
 
 // cnt[(p * nbp + j) * 256 + digit] = elements of radix block (p, j) with that digit.
+// kGroup (for a digit with few distinct values, such as the exponent byte of a
+// positive depth): lanes with the same digit are grouped by 8 ballots and one of
+// them adds the group's count, instead of up to 64 same-address LDS atomics.
+template <bool kGroup>
 __global__ __launch_bounds__(kRBThreads) void k_radix_count(RadixSrc src, int shift, uint32_t nbp,
                                                           uint32_t *__restrict__ cnt) {
     __shared__ uint32_t s_h[kRBWaves][kDigits];  // per wave, so only a wave's own lanes meet at a counter
@@ -155,8 +159,23 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_count(RadixSrc src, int sh
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < kRBChunks; ++c)
-        if ((vmask >> c) & 1u) atomicAdd(&s_h[wave][(key[c] >> shift) & 0xffu], 1u);
+    for (int c = 0; c < kRBChunks; ++c) {
+        const bool valid = (vmask >> c) & 1u;
+        const uint32_t d = (key[c] >> shift) & 0xffu;
+        if constexpr (kGroup) {
+            uint64_t same = __ballot(valid);  // valid lanes whose digit equals this lane's
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                same &= bit ? m : ~m;
+            }
+            // the group's lowest lane adds its size
+            if (valid && (same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&s_h[wave][d], (uint32_t)__popcll(same));
+        } else {
+            if (valid) atomicAdd(&s_h[wave][d], 1u);
+        }
+    }
     __syncthreads();
     for (int d = threadIdx.x; d < kDigits; d += kRBThreads) {
         uint32_t t = 0;
@@ -758,7 +777,12 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
     for (int pass = 0; pass < 4; ++pass) {
         RadixSrc src{kin, vin, pass == 0 ? vcount : nullptr, n, vbase};
         const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_radix_count, grid, dim3(kRBThreads), 0, s, src, shift, nbp, rcnt);
+        // the top byte of a positive float depth (sign and high exponent bits) takes
+        // few values, so its counts are grouped per wave
+        if (pass == 3)
+            hipLaunchKernelGGL(k_radix_count<true>, grid, dim3(kRBThreads), 0, s, src, shift, nbp, rcnt);
+        else
+            hipLaunchKernelGGL(k_radix_count<false>, grid, dim3(kRBThreads), 0, s, src, shift, nbp, rcnt);
         hipLaunchKernelGGL(k_radix_offsets, dim3((unsigned)n_poses), dim3(kThreads), 0, s, rcnt, nbp, vbase, roff,
                            pass == 0 ? nv : nullptr);
         if (pass == 0) hipLaunchKernelGGL(k_pose_bases, dim3(1), dim3(kThreads), 0, s, nv, n_poses, vbase);
