@@ -106,8 +106,8 @@ void launch_emit(hipStream_t s, const uint32_t *snt, const uint32_t *sg, const u
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t value);
 void launch_fill_u64(hipStream_t s, unsigned long long *p, uint64_t n, unsigned long long value);
 // Per-pose stable sort of the visible Gaussians by depth bits. Input: the
-// preprocess's regions in (kb, vb) with vcount. Output: vb[vbase[p] ..
-// vbase[p+1]) = pose p's record slots front to back, kb = their tile counts,
+// preprocess's regions in (kb, vb) with vcount. Output: va[vbase[p] ..
+// vbase[p+1]) = pose p's record slots front to back, ka = their tile counts,
 // vbase[P] = visible total; nv[p] = pose p's visible count.
 // ka, va, kb, vb hold P * n entries; rcnt and roff radix_count_elems each.
 uint64_t radix_blocks_per_pose(int64_t n);

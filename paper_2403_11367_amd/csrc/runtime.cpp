@@ -537,7 +537,7 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         gsr::launch_depth_sort(st, n, (int)gr.np, (const uint32_t *)ctx->vcount.p + (uint64_t)gr.p0 * n_regions, ntiles,
                                sort_ka + so, sort_va + so, sort_kb + so, sort_vb + so, (uint32_t *)ctx->rcnt.p + ro,
                                (uint32_t *)ctx->roff.p + ro, (uint32_t *)ctx->nv.p + gr.p0, vbase + gr.vb);
-        gsr::launch_emit_sums(st, sort_kb + so, vbase + gr.vb, (int)gr.np, gpn, esum + gr.es);
+        gsr::launch_emit_sums(st, sort_ka + so, vbase + gr.vb, (int)gr.np, gpn, esum + gr.es);
         gsr::launch_block_scan(st, esum + gr.es, gr.n_eb, nullptr, esum + gr.es + gr.n_eb);
     };
     // ordering, part 2 (pair emission and stable bucketing by tile), then compositing
@@ -547,9 +547,9 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         const uint64_t gpn = (uint64_t)std::max<int64_t>(1, gr.np * n);
         uint16_t *ptile = (uint16_t *)ctx->ptile.p + gr.pairs;
         uint32_t *pk = (uint32_t *)ctx->pk.p + gr.pairs;
-        gsr::launch_pair_segments(st, sort_kb + so, vbase + gr.vb, (int)gr.np, esum + gr.es, gpn, gr.cap,
+        gsr::launch_pair_segments(st, sort_ka + so, vbase + gr.vb, (int)gr.np, esum + gr.es, gpn, gr.cap,
                                   (uint64_t *)ctx->pseg.p + gr.vb);
-        gsr::launch_emit(st, sort_kb + so, sort_vb + so, vbase + gr.vb, (int)gr.np, (const uint2 *)ctx->rect.p, n, gpn,
+        gsr::launch_emit(st, sort_ka + so, sort_va + so, vbase + gr.vb, (int)gr.np, (const uint2 *)ctx->rect.p, n, gpn,
                          esum + gr.es, tg, ptile, pk, gr.cap, ctx->d_flags);
         gsr::launch_bucket(st, ptile, pk, (uint64_t *)ctx->pseg.p + gr.vb, (int)gr.np, gr.cap, tg.n_tiles,
                            (uint32_t *)ctx->block_base.p + gr.cst, (uint32_t *)ctx->bseg.p + gr.bsg,

@@ -99,36 +99,27 @@ __global__ __launch_bounds__(kBigThreads) void k_scan_blocks(uint64_t *__restric
 // cut into radix blocks of kRB; per pass every block counts its digits, one
 // block per pose scans the counts in (digit, block) order into each block's
 // output position for its first element of every digit, and the block writes
-// its elements there in order. The first pass reads the preprocess's 64-slot regions (visible
-// entries packed at the front of each), later passes the dense per-pose
-// segments [vbase[p], vbase[p+1]).
+// its elements there in order. The passes read dense per-pose segments
+// [vbase[p], vbase[p+1]): the preprocess's 64-slot regions (visible entries
+// packed at the front of each) are compacted into them first, in slot order.
+// (Passes over the sparse regions themselves cost 2.4x the blocks of a dense
+// pass; the compaction is cheaper than that difference.)
 constexpr int kRBWaves = 4;                // waves per radix block
 constexpr int kRBThreads = 64 * kRBWaves;
 constexpr int kRBWave = 1024;              // elements per wave, contiguous
 constexpr int kRB = kRBWaves * kRBWave;    // elements per radix block
 constexpr int kRBChunks = kRBWave / 64;    // 64-element chunks per wave
-constexpr int kRegionsPerBlock = kRB / 64;
 constexpr int kDigits = 256;
 
 struct RadixSrc {
     const uint32_t *keys, *vals;
-    const uint32_t *vcount;  // non-null: region layout (first pass)
-    int64_t n;               // Gaussians per pose (region layout)
-    const uint32_t *vbase;   // dense layout: segment starts, P + 1 entries
+    const uint32_t *vbase;  // segment starts, P + 1 entries
 };
 
 // Element `c * 64 + lane` of wave `wave`'s share of radix block (p, j): returns
 // whether it exists and sets its position in keys / vals.
 __device__ __forceinline__ bool radix_elem(const RadixSrc &src, int p, uint32_t j, int wave, int c, int lane,
                                            uint64_t &idx) {
-    if (src.vcount) {
-        const int64_t n_regions = (src.n + 63) >> 6;
-        const int64_t reg = (int64_t)j * kRegionsPerBlock + wave * kRBChunks + c;
-        if (reg >= n_regions) return false;
-        const uint32_t cnt = src.vcount[(int64_t)p * n_regions + reg];
-        idx = (uint64_t)p * (uint64_t)src.n + ((uint64_t)reg << 6) + (uint64_t)lane;
-        return (uint32_t)lane < cnt;
-    }
     const uint64_t i = (uint64_t)src.vbase[p] + (uint64_t)j * kRB + (uint64_t)wave * kRBWave + (uint64_t)c * 64 + lane;
     idx = i;
     return i < (uint64_t)src.vbase[p + 1];
@@ -144,7 +135,7 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_count(RadixSrc src, int sh
     __shared__ uint32_t s_h[kRBWaves][kDigits];  // per wave, so only a wave's own lanes meet at a counter
     const int p = blockIdx.y;
     const uint32_t j = blockIdx.x;
-    if (!src.vcount && (uint64_t)src.vbase[p] + (uint64_t)j * kRB >= src.vbase[p + 1]) return;  // empty block
+    if ((uint64_t)src.vbase[p] + (uint64_t)j * kRB >= src.vbase[p + 1]) return;  // empty block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < kRBWaves * kDigits; i += kRBThreads) (&s_h[0][0])[i] = 0;
     // every chunk's key is loaded before the first count, so the loads overlap
@@ -205,15 +196,14 @@ __device__ uint32_t block_exclusive_scan_u32(uint32_t x, uint32_t *s_wave /*[4]*
 
 // Per pose (one block, thread = digit): off[(p * nbp + j) * 256 + d] = position,
 // relative to the pose's first element, of radix block j's first element with
-// digit d (digits in order, blocks in order within a digit). With nv non-null
-// (first pass) the pose's element count is stored there.
+// digit d (digits in order, blocks in order within a digit).
 __global__ __launch_bounds__(kThreads) void k_radix_offsets(const uint32_t *__restrict__ cnt, uint32_t nbp,
                                                             const uint32_t *__restrict__ vbase,
-                                                            uint32_t *__restrict__ off, uint32_t *__restrict__ nv) {
+                                                            uint32_t *__restrict__ off) {
     __shared__ uint32_t s_wave[4];
     const int p = blockIdx.x;
     const int d = threadIdx.x;
-    const uint32_t nb = nv ? nbp : (uint32_t)(((uint64_t)vbase[p + 1] - vbase[p] + kRB - 1) / kRB);
+    const uint32_t nb = (uint32_t)(((uint64_t)vbase[p + 1] - vbase[p] + kRB - 1) / kRB);
     const uint32_t *c = cnt + (uint64_t)p * nbp * kDigits + d;
     // 8 blocks per step, so several loads are in flight per thread
     uint32_t tot = 0, j = 0;
@@ -243,7 +233,6 @@ __global__ __launch_bounds__(kThreads) void k_radix_offsets(const uint32_t *__re
         o[(uint64_t)j * kDigits] = run;
         run += x;
     }
-    if (nv && d == 0) nv[p] = all;
 }
 
 // vbase[p] = sum of nv[q] over q < p, for p in [0, P]. One block.
@@ -263,6 +252,67 @@ __global__ __launch_bounds__(kThreads) void k_pose_bases(const uint32_t *__restr
         __syncthreads();
         if (threadIdx.x == 0) s_carry = carry + all;
         __syncthreads();
+    }
+}
+
+// Compaction of the preprocess's region layout (per pose, regions of 64 slots,
+// each holding its visible entries at the front, vcount of them) into one dense
+// run per pose, in slot order, so that every radix pass works on dense blocks.
+// Per pose (one block): reg_off[p * n_regions + r] = entries of the pose's
+// regions before r; nv[p] = the pose's total.
+__global__ __launch_bounds__(kThreads) void k_region_offsets(const uint32_t *__restrict__ vcount, int64_t n_regions,
+                                                             uint32_t *__restrict__ reg_off,
+                                                             uint32_t *__restrict__ nv) {
+    __shared__ uint32_t s_wave[4];
+    const int p = blockIdx.x;
+    const uint32_t *vc = vcount + (int64_t)p * n_regions;
+    uint32_t *ro = reg_off + (int64_t)p * n_regions;
+    const int64_t per = (n_regions + kThreads - 1) / kThreads;  // consecutive regions per thread
+    const int64_t r0 = (int64_t)threadIdx.x * per, r1 = min(r0 + per, n_regions);
+    uint32_t sum = 0;
+    for (int64_t r = r0; r < r1; ++r) sum += vc[r];
+    uint32_t all = 0;
+    uint32_t run = block_exclusive_scan_u32(sum, s_wave, &all);
+    for (int64_t r = r0; r < r1; ++r) {
+        ro[r] = run;
+        run += vc[r];
+    }
+    if (threadIdx.x == 0) nv[p] = all;
+}
+
+// Each wave takes kCompactRegions consecutive (pose, region) pairs; a region's
+// entries go to vbase[p] + reg_off[..] onward. Lane i first loads region i's
+// count and destination, so that the wave's copies do not wait on each other.
+constexpr int kCompactRegions = 16;
+__global__ __launch_bounds__(kThreads) void k_compact(const uint32_t *__restrict__ vcount, int64_t n, int P,
+                                                      const uint32_t *__restrict__ reg_off,
+                                                      const uint32_t *__restrict__ vbase,
+                                                      const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                      uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+    const int64_t n_regions = (n + 63) >> 6;
+    const int64_t total = (int64_t)P * n_regions;
+    const int64_t w0 = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * kCompactRegions;
+    const int lane = threadIdx.x & 63;
+    // lane i < kCompactRegions: region w0 + i's count, source and destination
+    uint32_t my_cnt = 0;
+    uint64_t my_src = 0, my_dst = 0;
+    if (lane < kCompactRegions && w0 + lane < total) {
+        const int64_t w = w0 + lane;
+        const int p = (int)(w / n_regions);
+        const int64_t r = w - (int64_t)p * n_regions;
+        my_cnt = vcount[w];
+        my_src = (uint64_t)p * (uint64_t)n + ((uint64_t)r << 6);
+        my_dst = (uint64_t)vbase[p] + reg_off[w];
+    }
+#pragma unroll
+    for (int i = 0; i < kCompactRegions; ++i) {
+        const uint32_t cnt = (uint32_t)__shfl((int)my_cnt, i, 64);
+        const uint64_t src = (uint64_t)__shfl((long long)my_src, i, 64);
+        const uint64_t dst = (uint64_t)__shfl((long long)my_dst, i, 64);
+        if ((uint32_t)lane < cnt) {
+            kout[dst + lane] = kin[src + lane];
+            vout[dst + lane] = vin[src + lane];
+        }
     }
 }
 
@@ -323,7 +373,7 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int 
     const uint32_t j = slot % nbp;
     if (p >= n_poses) return;
     const uint32_t pose_base = src.vbase[p];
-    if (!src.vcount && (uint64_t)pose_base + (uint64_t)j * kRB >= src.vbase[p + 1]) return;  // empty block
+    if ((uint64_t)pose_base + (uint64_t)j * kRB >= src.vbase[p + 1]) return;  // empty block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < kRBWaves * kDigits; i += kRBThreads) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
@@ -770,12 +820,24 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
                        uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t *rcnt, uint32_t *roff,
                        uint32_t *nv, uint32_t *vbase) {
     const uint32_t nbp = (uint32_t)radix_blocks_per_pose(n);
+    const int64_t n_regions = (n + 63) >> 6;
     const dim3 grid(nbp, (unsigned)n_poses);
     const dim3 sgrid(nbp, (unsigned)((n_poses + kXcdCount - 1) / kXcdCount * kXcdCount));  // see k_radix_scatter
-    // pass 0: regions in (kb, vb) -> dense (ka, va); passes 1, 2 ping-pong; pass 3 -> (kb = tile counts, vb = index)
-    const uint32_t *kin = kb, *vin = vb;
+    // Compaction: regions in (kb, vb) -> dense (ka, va), in slot order. roff holds
+    // the region offsets (P * n_regions <= radix_count_elems) until pass 0 writes
+    // its digit offsets there.
+    hipLaunchKernelGGL(k_region_offsets, dim3((unsigned)n_poses), dim3(kThreads), 0, s, vcount, n_regions, roff, nv);
+    hipLaunchKernelGGL(k_pose_bases, dim3(1), dim3(kThreads), 0, s, nv, n_poses, vbase);
+    const uint64_t n_waves = (uint64_t)n_poses * (uint64_t)n_regions;  // 0 for an empty submap
+    if (n_waves > 0)
+        hipLaunchKernelGGL(k_compact,
+                           dim3((unsigned)((n_waves + kCompactRegions * (kThreads / 64) - 1) /
+                                           (kCompactRegions * (kThreads / 64)))),
+                           dim3(kThreads), 0, s, vcount, n, n_poses, roff, vbase, kb, vb, ka, va);
+    // four dense passes: (ka, va) -> (kb, vb) -> (ka, va) -> (kb, vb) -> (ka = tile counts, va = slots)
+    const uint32_t *kin = ka, *vin = va;
     for (int pass = 0; pass < 4; ++pass) {
-        RadixSrc src{kin, vin, pass == 0 ? vcount : nullptr, n, vbase};
+        RadixSrc src{kin, vin, vbase};
         const int shift = 8 * pass;
         // the top byte of a positive float depth (sign and high exponent bits) takes
         // few values, so its counts are grouped per wave
@@ -783,10 +845,8 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
             hipLaunchKernelGGL(k_radix_count<true>, grid, dim3(kRBThreads), 0, s, src, shift, nbp, rcnt);
         else
             hipLaunchKernelGGL(k_radix_count<false>, grid, dim3(kRBThreads), 0, s, src, shift, nbp, rcnt);
-        hipLaunchKernelGGL(k_radix_offsets, dim3((unsigned)n_poses), dim3(kThreads), 0, s, rcnt, nbp, vbase, roff,
-                           pass == 0 ? nv : nullptr);
-        if (pass == 0) hipLaunchKernelGGL(k_pose_bases, dim3(1), dim3(kThreads), 0, s, nv, n_poses, vbase);
-        uint32_t *ko = (pass & 1) ? kb : ka, *vo = (pass & 1) ? vb : va;
+        hipLaunchKernelGGL(k_radix_offsets, dim3((unsigned)n_poses), dim3(kThreads), 0, s, rcnt, nbp, vbase, roff);
+        uint32_t *ko = (pass & 1) ? ka : kb, *vo = (pass & 1) ? va : vb;
         if (pass == 3)
             hipLaunchKernelGGL(k_radix_scatter<true>, sgrid, dim3(kRBThreads), 0, s, src, shift, nbp, n_poses, roff,
                                ko, vo, ntiles, n);
