@@ -754,22 +754,23 @@ void launch_seg_pass(hipStream_t s, const SegPass &ps, uint64_t n_blocks, uint32
 __global__ __launch_bounds__(kThreads) void k_keep_offsets(const uint64_t *__restrict__ offsets, uint64_t capacity,
                                                            uint32_t n_lists, uint32_t *__restrict__ keep_off) {
     __shared__ uint64_t s_wave[4];
-    __shared__ uint64_t s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (uint32_t c0 = 0; c0 <= n_lists; c0 += kThreads) {
-        const uint32_t l = c0 + threadIdx.x;
-        uint64_t nk = 0;
-        if (l < n_lists) {
-            const uint64_t b = min(offsets[l], capacity), e = min(offsets[l + 1], capacity);
-            if (e > b + kKeepRecords) nk = (e - b - 1) / kKeepRecords;
-        }
-        const uint64_t inc = block_inclusive_scan(nk, s_wave);
-        const uint64_t carry = s_carry;
-        if (l <= n_lists) keep_off[l] = (uint32_t)(carry + inc - nk);
-        __syncthreads();
-        if (threadIdx.x == kThreads - 1) s_carry = carry + inc;
-        __syncthreads();
+    // kept states of list l: one per whole kKeepRecords before its last record
+    auto kept = [&](uint32_t l) -> uint64_t {
+        if (l >= n_lists) return 0;
+        const uint64_t b = min(offsets[l], capacity), e = min(offsets[l + 1], capacity);
+        return e > b + kKeepRecords ? (e - b - 1) / kKeepRecords : 0;
+    };
+    // thread t: consecutive entries [l0, l1) of keep_off[0 .. n_lists]
+    const uint32_t per = (n_lists + 1 + kThreads - 1) / kThreads;
+    const uint32_t l0 = threadIdx.x * per, l1 = min(l0 + per, n_lists + 1);
+    uint64_t sum = 0;
+#pragma unroll 8
+    for (uint32_t l = l0; l < l1; ++l) sum += kept(l);
+    uint64_t run = block_inclusive_scan(sum, s_wave) - sum;
+#pragma unroll 8
+    for (uint32_t l = l0; l < l1; ++l) {
+        keep_off[l] = (uint32_t)run;
+        run += kept(l);
     }
 }
 
