@@ -6,7 +6,7 @@
 // brute-force search keeps the most similar render.
 //
 // Grey = 0.299 R + 0.587 G + 0.114 B. Each block reads 4096 pixels of one render
-// once (12 B/px, coalesced) plus the query's grey image (4 B/px, shared by all
+// once (12 B/px, coalesced, 16 B per lane and load where the layout allows) plus the query's grey image (4 B/px, shared by all
 // renders and so mostly served from cache), computes the block's counts,
 // means, centred sums of squares and co-moment by a two-pass reduction about a
 // shift (the block's first pixel, so a constant block gives exactly zero
@@ -52,6 +52,10 @@ __device__ void block_sum3(float &a, float &b, float &c, float *s /*[3][4]*/) {
     __syncthreads();
 }
 
+// kVec (4 | hw and 16-byte aligned planes): each thread reads 4 consecutive
+// pixels per load (float4), 16 pixels in 4 loads per plane; otherwise one pixel
+// per load, 256 apart.
+template <bool kVec>
 __global__ __launch_bounds__(kThreads) void k_ncc_partial(const float *__restrict__ qgrey,
                                                           const float *__restrict__ renders, int64_t hw,
                                                           int n_blocks, double *__restrict__ partials) {
@@ -60,22 +64,63 @@ __global__ __launch_bounds__(kThreads) void k_ncc_partial(const float *__restric
     const float *rgb = renders + (int64_t)pose * 3 * hw;
     const int64_t base = (int64_t)blk * kPix;
     const int64_t nvalid = min((int64_t)kPix, hw - base);
+    // block-relative position of this thread's item i (kVec: 4 | nvalid, so a group
+    // of 4 is valid or not as a whole)
+    auto item_loc = [&](int i) -> int64_t {
+        if constexpr (kVec)
+            return ((int64_t)(i >> 2) * kThreads + threadIdx.x) * 4 + (i & 3);
+        else
+            return (int64_t)i * kThreads + threadIdx.x;
+    };
     float q[kItems], g[kItems];
     const float sq = qgrey[base];
     const float sg = grey(rgb[base], rgb[hw + base], rgb[2 * hw + base]);
     float aq = 0.f, ag = 0.f, dummy = 0.f;
+    if constexpr (kVec) {
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-        const int64_t loc = (int64_t)i * kThreads + threadIdx.x;
-        const int64_t pix = base + loc;
-        if (loc < nvalid) {
-            q[i] = qgrey[pix] - sq;
-            g[i] = grey(rgb[pix], rgb[hw + pix], rgb[2 * hw + pix]) - sg;
-            aq += q[i];
-            ag += g[i];
-        } else {
-            q[i] = 0.f;
-            g[i] = 0.f;
+        for (int i = 0; i < kItems / 4; ++i) {
+            const int64_t loc = item_loc(4 * i);
+            if (loc < nvalid) {
+                const int64_t pix = base + loc;
+                const float4 qv = *reinterpret_cast<const float4 *>(qgrey + pix);
+                const float4 rv = *reinterpret_cast<const float4 *>(rgb + pix);
+                const float4 gv = *reinterpret_cast<const float4 *>(rgb + hw + pix);
+                const float4 bv = *reinterpret_cast<const float4 *>(rgb + 2 * hw + pix);
+                q[4 * i + 0] = qv.x - sq;
+                q[4 * i + 1] = qv.y - sq;
+                q[4 * i + 2] = qv.z - sq;
+                q[4 * i + 3] = qv.w - sq;
+                g[4 * i + 0] = grey(rv.x, gv.x, bv.x) - sg;
+                g[4 * i + 1] = grey(rv.y, gv.y, bv.y) - sg;
+                g[4 * i + 2] = grey(rv.z, gv.z, bv.z) - sg;
+                g[4 * i + 3] = grey(rv.w, gv.w, bv.w) - sg;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    aq += q[4 * i + k];
+                    ag += g[4 * i + k];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    q[4 * i + k] = 0.f;
+                    g[4 * i + k] = 0.f;
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const int64_t loc = item_loc(i);
+            const int64_t pix = base + loc;
+            if (loc < nvalid) {
+                q[i] = qgrey[pix] - sq;
+                g[i] = grey(rgb[pix], rgb[hw + pix], rgb[2 * hw + pix]) - sg;
+                aq += q[i];
+                ag += g[i];
+            } else {
+                q[i] = 0.f;
+                g[i] = 0.f;
+            }
         }
     }
     block_sum3(aq, ag, dummy, s_red);
@@ -84,8 +129,7 @@ __global__ __launch_bounds__(kThreads) void k_ncc_partial(const float *__restric
     float m2q = 0.f, m2g = 0.f, cqg = 0.f;
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
-        const int64_t loc = (int64_t)i * kThreads + threadIdx.x;
-        if (loc < nvalid) {
+        if (item_loc(i) < nvalid) {
             const float dq = q[i] - mq, dg = g[i] - mg;
             m2q += dq * dq;
             m2g += dg * dg;
@@ -205,8 +249,16 @@ void launch_ncc(hipStream_t s, const float *query, const float *renders, int n_p
     const int nb = (int)((hw + kPix - 1) / kPix);
     const unsigned gblocks = (unsigned)std::min<int64_t>((hw + kThreads - 1) / kThreads, 2048);
     hipLaunchKernelGGL(k_grey, dim3(gblocks), dim3(kThreads), 0, s, query, hw, grey_q);
-    hipLaunchKernelGGL(k_ncc_partial, dim3((unsigned)nb, (unsigned)n_poses), dim3(kThreads), 0, s, grey_q, renders,
-                       hw, nb, partials);
+    // whole float4 groups: 4 | hw (so every block's pixel count and every plane's
+    // start are multiples of 4) and 16-byte aligned bases
+    const bool vec = hw % 4 == 0 && reinterpret_cast<uintptr_t>(renders) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(grey_q) % 16 == 0;
+    if (vec)
+        hipLaunchKernelGGL(k_ncc_partial<true>, dim3((unsigned)nb, (unsigned)n_poses), dim3(kThreads), 0, s, grey_q,
+                           renders, hw, nb, partials);
+    else
+        hipLaunchKernelGGL(k_ncc_partial<false>, dim3((unsigned)nb, (unsigned)n_poses), dim3(kThreads), 0, s, grey_q,
+                           renders, hw, nb, partials);
     hipLaunchKernelGGL(k_ncc_final, dim3((unsigned)n_poses), dim3(kThreads), 0, s, partials, nb, scores);
 }
 
