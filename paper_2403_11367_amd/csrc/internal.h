@@ -112,9 +112,11 @@ void launch_fill_u64(hipStream_t s, unsigned long long *p, uint64_t n, unsigned 
 // ka, va, kb, vb hold P * n entries; rcnt and roff radix_count_elems each.
 uint64_t radix_blocks_per_pose(int64_t n);
 uint64_t radix_count_elems(int64_t n, int n_poses);
+// slot0: the first pose's first record slot (record slots are pose * n + index
+// over all poses of the render); n_tiles: tiles per image.
 void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vcount, const uint32_t *ntiles,
-                       uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t *rcnt, uint32_t *roff,
-                       uint32_t *nv, uint32_t *vbase);
+                       uint32_t slot0, int n_tiles, uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
+                       uint32_t *rcnt, uint32_t *roff, uint32_t *nv, uint32_t *vbase);
 // Exclusive scan of sums[0 .. nb_max) in place (only the first *d_nb with d_nb),
 // total to *total. One block.
 void launch_block_scan(hipStream_t s, uint64_t *sums, uint64_t nb_max, const uint64_t *d_nb, uint64_t *total);

@@ -90,6 +90,30 @@ def test_alpha_clamp_in_some_chunks(ctx):
     sm.free()
 
 
+@pytest.mark.parametrize("n", [1 << 19, 600_000])
+def test_depth_sort_either_side_of_value_packing(ctx, n):
+    """Submaps of up to 2^19 Gaussians carry each visible Gaussian's tile count
+    with its index in the depth sort's value; larger ones gather the counts in
+    the sort's last pass. Either way the records and the sorted pairs match the
+    oracle bit for bit."""
+    from oracle import keys, project
+    say(f"depth sort with {n} Gaussians (value packing {'on' if n <= 1 << 19 else 'off'}), 64x48, 1 pose")
+    sc = W.tiny_scene(81, n=n, width=64, height=48, n_poses=1, log_scale_mean=-3.0)
+    cam = sc.camera
+    sm = load(ctx, sc.gaussians)
+    gpu_render(ctx, sm, cam, sc.poses)
+    recs, nts, offs, pairs = gpu_buffers(ctx)
+    mu, cov6, op, rgb = prep(sc.gaussians)
+    rec = project.preprocess(mu, cov6, op, rgb, sc.poses[0], cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy)
+    T = _tiles(cam)
+    k, v = keys.make_pairs_fast(rec, cam.width, cam.height, 16, 16)
+    ks, vs = keys.sort_pairs(k, v)
+    rng = keys.tile_ranges(ks, T)
+    check_records(recs, nts, rec, n, 0)
+    check_pairs(offs, pairs, ks, vs, rng, 0, T)
+    sm.free()
+
+
 @pytest.mark.parametrize("seed", [41, 42])
 def test_thin_tilted_and_huge_gaussians(ctx, seed):
     """Needle-thin tilted footprints and a few that cover the whole image: the
