@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kThreads) void k_pack(int64_t n_map, const float *_
 __global__ __launch_bounds__(kThreads) void k_preprocess(
     const SubmapTable tab, int64_t n, const float *__restrict__ poses, int n_poses, Camera cam,
     Consts k, TileGrid tg, float4 *__restrict__ records, uint32_t *__restrict__ ntiles, uint2 *__restrict__ rect,
-    uint32_t *__restrict__ vz, uint32_t *__restrict__ vg, uint32_t *__restrict__ vcount) {
+    uint32_t *__restrict__ vz, uint32_t *__restrict__ vg, uint32_t *__restrict__ vcount, bool pack) {
     const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int p0 = blockIdx.y * kPosesPerThread;
     const int p1 = min(p0 + kPosesPerThread, n_poses);
@@ -195,7 +195,8 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
             if (nt != 0) {
                 const int64_t slot = (int64_t)p * n + (region << 6) + __popcll(vis & lt_mask);
                 vz[slot] = zb;
-                vg[slot] = (uint32_t)((int64_t)p * n + g);  // the record slot of (pose, Gaussian)
+                // the record slot of (pose, Gaussian), or its index and tile count
+                vg[slot] = pack ? (uint32_t)g | (nt << kPackIndexBits) : (uint32_t)((int64_t)p * n + g);
             }
         }
     }
@@ -383,11 +384,11 @@ int64_t preprocess_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }
 
 void launch_preprocess(hipStream_t s, const SubmapTable &tab, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
-                       uint32_t *ntiles, uint2 *rect, uint32_t *vz, uint32_t *vg, uint32_t *vcount) {
+                       uint32_t *ntiles, uint2 *rect, uint32_t *vz, uint32_t *vg, uint32_t *vcount, bool pack) {
     if (n <= 0) return;
     const dim3 grid((unsigned)preprocess_blocks(n), (unsigned)((n_poses + kPosesPerThread - 1) / kPosesPerThread));
     hipLaunchKernelGGL(k_preprocess, grid, dim3(kThreads), 0, s, tab, n, poses, n_poses, cam, k, tg, records,
-                       ntiles, rect, vz, vg, vcount);
+                       ntiles, rect, vz, vg, vcount, pack);
 }
 
 uint64_t emit_blocks(uint64_t n_max) { return std::max<uint64_t>(1, (n_max + kEmitTile - 1) / kEmitTile); }

@@ -82,9 +82,16 @@ int64_t preprocess_blocks(int64_t n);
 // region, the (depth bits, record slot p * n + g) of the visible Gaussians
 // packed at the front of the region's slots of vz / vg (P * n each) and their
 // count in vcount[p * ceil(n / 64) + region].
+// Sort values: the record slot (pose * n + index) of each visible Gaussian, or,
+// where pack_sort_values(n, n_tiles), (index) | (tile count << kPackIndexBits),
+// which the depth sort's last pass turns back into the slot and the count.
+constexpr int kPackIndexBits = 19;
+inline bool pack_sort_values(int64_t n, int n_tiles) {
+    return n <= (int64_t(1) << kPackIndexBits) && n_tiles < (1 << (32 - kPackIndexBits));
+}
 void launch_preprocess(hipStream_t s, const SubmapTable &tab, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
-                       uint32_t *ntiles, uint2 *rect, uint32_t *vz, uint32_t *vg, uint32_t *vcount);
+                       uint32_t *ntiles, uint2 *rect, uint32_t *vz, uint32_t *vg, uint32_t *vcount, bool pack);
 // Pair emission in front-to-back order. The depth-sorted visible Gaussians
 // (snt: tile counts, sg: record slots p * n + g; pose p owns [vbase[p],
 // vbase[p+1]), at most n_max = P * n of them) are cut into emit_blocks(n_max)
@@ -113,9 +120,10 @@ void launch_fill_u64(hipStream_t s, unsigned long long *p, uint64_t n, unsigned 
 uint64_t radix_blocks_per_pose(int64_t n);
 uint64_t radix_count_elems(int64_t n, int n_poses);
 // slot0: the first pose's first record slot (record slots are pose * n + index
-// over all poses of the render); n_tiles: tiles per image.
+// over all poses of the render); pack: the values are packed (as the preprocess
+// wrote them).
 void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vcount, const uint32_t *ntiles,
-                       uint32_t slot0, int n_tiles, uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
+                       uint32_t slot0, bool pack, uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
                        uint32_t *rcnt, uint32_t *roff, uint32_t *nv, uint32_t *vbase);
 // Exclusive scan of sums[0 .. nb_max) in place (only the first *d_nb with d_nb),
 // total to *total. One block.

@@ -523,8 +523,9 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         HIPC(ctx, hipEventRecord(ev->e[0], s));
     }
     gsr::launch_fill_u64(s, ctx->d_counters, gsr::CNT_COUNT, 0ull);
+    const bool pack = gsr::pack_sort_values(n, tg.n_tiles);  // tile counts ride in the sort values
     gsr::launch_preprocess(s, tab, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p, ntiles,
-                           (uint2 *)ctx->rect.p, sort_kb, sort_vb, (uint32_t *)ctx->vcount.p);
+                           (uint2 *)ctx->rect.p, sort_kb, sort_vb, (uint32_t *)ctx->vcount.p, pack);
     if ((rc = check_launch(ctx, "preprocess"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[1], s));
 
@@ -535,7 +536,7 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         const uint64_t so = (uint64_t)gr.p0 * n, ro = gsr::radix_count_elems(n, (int)gr.p0);
         const uint64_t gpn = (uint64_t)std::max<int64_t>(1, gr.np * n);
         gsr::launch_depth_sort(st, n, (int)gr.np, (const uint32_t *)ctx->vcount.p + (uint64_t)gr.p0 * n_regions, ntiles,
-                               (uint32_t)so, tg.n_tiles, sort_ka + so, sort_va + so, sort_kb + so, sort_vb + so, (uint32_t *)ctx->rcnt.p + ro,
+                               (uint32_t)so, pack, sort_ka + so, sort_va + so, sort_kb + so, sort_vb + so, (uint32_t *)ctx->rcnt.p + ro,
                                (uint32_t *)ctx->roff.p + ro, (uint32_t *)ctx->nv.p + gr.p0, vbase + gr.vb);
         gsr::launch_emit_sums(st, sort_ka + so, vbase + gr.vb, (int)gr.np, gpn, esum + gr.es);
         gsr::launch_block_scan(st, esum + gr.es, gr.n_eb, nullptr, esum + gr.es + gr.n_eb);

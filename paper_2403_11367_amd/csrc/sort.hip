@@ -283,23 +283,18 @@ __global__ __launch_bounds__(kThreads) void k_region_offsets(const uint32_t *__r
 // Each wave takes kCompactRegions consecutive (pose, region) pairs; a region's
 // entries go to vbase[p] + reg_off[..] onward. Lane i first loads region i's
 // count and destination, so that the wave's copies do not wait on each other.
-// With ntiles (n <= 2^kPackIndexBits and fewer than 2^(32 - kPackIndexBits)
-// tiles), a value becomes (index within the pose) | (tile count << kPackIndexBits),
-// read here almost in order, so that the last pass needs no gather.
 constexpr int kCompactRegions = 16;
-constexpr int kPackIndexBits = 19;
 __global__ __launch_bounds__(kThreads) void k_compact(const uint32_t *__restrict__ vcount, int64_t n, int P,
                                                       const uint32_t *__restrict__ reg_off,
                                                       const uint32_t *__restrict__ vbase,
                                                       const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-                                                      const uint32_t *__restrict__ ntiles, uint32_t slot0,
                                                       uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
     const int64_t n_regions = (n + 63) >> 6;
     const int64_t total = (int64_t)P * n_regions;
     const int64_t w0 = ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * kCompactRegions;
     const int lane = threadIdx.x & 63;
     // lane i < kCompactRegions: region w0 + i's count, source and destination
-    uint32_t my_cnt = 0, my_pose_base = 0;
+    uint32_t my_cnt = 0;
     uint64_t my_src = 0, my_dst = 0;
     if (lane < kCompactRegions && w0 + lane < total) {
         const int64_t w = w0 + lane;
@@ -308,19 +303,15 @@ __global__ __launch_bounds__(kThreads) void k_compact(const uint32_t *__restrict
         my_cnt = vcount[w];
         my_src = (uint64_t)p * (uint64_t)n + ((uint64_t)r << 6);
         my_dst = (uint64_t)vbase[p] + reg_off[w];
-        my_pose_base = slot0 + (uint32_t)((uint64_t)p * (uint64_t)n);  // the pose's first record slot
     }
 #pragma unroll
     for (int i = 0; i < kCompactRegions; ++i) {
         const uint32_t cnt = (uint32_t)__shfl((int)my_cnt, i, 64);
         const uint64_t src = (uint64_t)__shfl((long long)my_src, i, 64);
         const uint64_t dst = (uint64_t)__shfl((long long)my_dst, i, 64);
-        const uint32_t pose_base = (uint32_t)__shfl((int)my_pose_base, i, 64);
         if ((uint32_t)lane < cnt) {
-            const uint32_t v = vin[src + lane];
             kout[dst + lane] = kin[src + lane];
-            // (a region's tile counts, read by slot within its 64-slot window)
-            vout[dst + lane] = ntiles ? (v - pose_base) | (ntiles[v] << kPackIndexBits) : v;
+            vout[dst + lane] = vin[src + lane];
         }
     }
 }
@@ -833,10 +824,8 @@ uint64_t radix_count_elems(int64_t n, int n_poses) {
 }
 
 void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vcount, const uint32_t *ntiles,
-                       uint32_t slot0, int n_tiles, uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
+                       uint32_t slot0, bool packed, uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
                        uint32_t *rcnt, uint32_t *roff, uint32_t *nv, uint32_t *vbase) {
-    // tile counts travel in the values when index and count fit 32 bits
-    const bool packed = n <= (int64_t(1) << kPackIndexBits) && n_tiles < (1 << (32 - kPackIndexBits));
     const uint32_t nbp = (uint32_t)radix_blocks_per_pose(n);
     const int64_t n_regions = (n + 63) >> 6;
     const dim3 grid(nbp, (unsigned)n_poses);
@@ -851,8 +840,7 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
         hipLaunchKernelGGL(k_compact,
                            dim3((unsigned)((n_waves + kCompactRegions * (kThreads / 64) - 1) /
                                            (kCompactRegions * (kThreads / 64)))),
-                           dim3(kThreads), 0, s, vcount, n, n_poses, roff, vbase, kb, vb, packed ? ntiles : nullptr, slot0,
-                           ka, va);
+                           dim3(kThreads), 0, s, vcount, n, n_poses, roff, vbase, kb, vb, ka, va);
     // four dense passes: (ka, va) -> (kb, vb) -> (ka, va) -> (kb, vb) -> (ka = tile counts, va = slots)
     const uint32_t *kin = ka, *vin = va;
     for (int pass = 0; pass < 4; ++pass) {
