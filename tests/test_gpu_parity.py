@@ -325,6 +325,14 @@ def test_ncc_matches_oracle_full_size(ctx):
     s = ctx.ncc(to_dev(small[0]), to_dev(small)).cpu().numpy()
     assert abs(s[0] - 1.0) <= TOL_NCC
     assert np.abs(s - oncc.ncc(small[0], small)).max() <= TOL_NCC
+    # 4 | H x W but renders not 16-byte aligned (a view one float into a buffer):
+    # the per-pixel loads instead of the 4-pixel ones
+    even = W.random_images(9, 4, 32, 48)
+    flat = torch.zeros(1 + even[1:].size, dtype=torch.float32, device="cuda")
+    view = flat[1:].view(3, 3, 32, 48)
+    view.copy_(to_dev(even[1:]))
+    e = ctx.ncc(to_dev(even[0]), view).cpu().numpy()
+    assert np.abs(e - oncc.ncc(even[0], even[1:])).max() <= TOL_NCC
     torch.cuda.synchronize()
 
 
