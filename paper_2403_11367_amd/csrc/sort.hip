@@ -260,19 +260,23 @@ __global__ __launch_bounds__(kThreads) void k_pose_bases(const uint32_t *__restr
 // run per pose, in slot order, so that every radix pass works on dense blocks.
 // Per pose (one block): reg_off[p * n_regions + r] = entries of the pose's
 // regions before r; nv[p] = the pose's total.
-__global__ __launch_bounds__(kThreads) void k_region_offsets(const uint32_t *__restrict__ vcount, int64_t n_regions,
-                                                             uint32_t *__restrict__ reg_off,
-                                                             uint32_t *__restrict__ nv) {
-    __shared__ uint32_t s_wave[4];
+template <int kWaves>
+__device__ uint32_t block_exclusive_scan_waves(uint32_t x, uint32_t *s_wave, uint32_t *total);
+
+constexpr int kRegionThreads = 1024;  // about 8 regions per thread at 500k Gaussians
+__global__ __launch_bounds__(kRegionThreads) void k_region_offsets(const uint32_t *__restrict__ vcount,
+                                                                   int64_t n_regions, uint32_t *__restrict__ reg_off,
+                                                                   uint32_t *__restrict__ nv) {
+    __shared__ uint32_t s_wave[kRegionThreads / 64];
     const int p = blockIdx.x;
     const uint32_t *vc = vcount + (int64_t)p * n_regions;
     uint32_t *ro = reg_off + (int64_t)p * n_regions;
-    const int64_t per = (n_regions + kThreads - 1) / kThreads;  // consecutive regions per thread
+    const int64_t per = (n_regions + kRegionThreads - 1) / kRegionThreads;  // consecutive regions per thread
     const int64_t r0 = (int64_t)threadIdx.x * per, r1 = min(r0 + per, n_regions);
     uint32_t sum = 0;
     for (int64_t r = r0; r < r1; ++r) sum += vc[r];
     uint32_t all = 0;
-    uint32_t run = block_exclusive_scan_u32(sum, s_wave, &all);
+    uint32_t run = block_exclusive_scan_waves<kRegionThreads / 64>(sum, s_wave, &all);
     for (int64_t r = r0; r < r1; ++r) {
         ro[r] = run;
         run += vc[r];
@@ -833,7 +837,8 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
     // Compaction: regions in (kb, vb) -> dense (ka, va), in slot order. roff holds
     // the region offsets (P * n_regions <= radix_count_elems) until pass 0 writes
     // its digit offsets there.
-    hipLaunchKernelGGL(k_region_offsets, dim3((unsigned)n_poses), dim3(kThreads), 0, s, vcount, n_regions, roff, nv);
+    hipLaunchKernelGGL(k_region_offsets, dim3((unsigned)n_poses), dim3(kRegionThreads), 0, s, vcount, n_regions, roff,
+                       nv);
     hipLaunchKernelGGL(k_pose_bases, dim3(1), dim3(kThreads), 0, s, nv, n_poses, vbase);
     const uint64_t n_waves = (uint64_t)n_poses * (uint64_t)n_regions;  // 0 for an empty submap
     if (n_waves > 0)
