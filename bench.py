@@ -109,8 +109,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (the path shards by candidate pose, "
-              "see DESIGN.md); run with --gpus 1", file=sys.stderr, flush=True)
+        print("bench.py: measures one GPU only (the path would shard by candidate pose, each GPU "
+              "rendering and scoring its own slice); run with --gpus 1", file=sys.stderr, flush=True)
         sys.exit(2)
 
     import numpy as np

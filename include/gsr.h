@@ -59,7 +59,7 @@ extern "C" {
 #define GSR_EHIP (-3)         /* a HIP runtime call failed; see gsr_last_error */
 #define GSR_ENODEV (-4)       /* no usable GPU / bad device ordinal */
 #define GSR_EOVERFLOW (-5)    /* fixed pair capacity exceeded in a render */
-#define GSR_EUNSUPPORTED (-6) /* valid request this build does not implement */
+#define GSR_EUNSUPPORTED (-6) /* valid request this library does not implement */
 #define GSR_EDEVICE (-7)      /* device-side check failed (e.g. index out of range) */
 
 typedef struct gsr_ctx gsr_ctx;
@@ -75,7 +75,7 @@ typedef struct {
 
 /* Render constants. gsr_default_cfg fills the defaults given in brackets. */
 typedef struct {
-    int32_t tile_w, tile_h;  /* screen tile in pixels [16, 16]; this build: 16 x 16 */
+    int32_t tile_w, tile_h;  /* screen tile in pixels [16, 16]; this library: 16 x 16 */
     float eps_dilate;        /* screen-covariance dilation, px^2 [0.3] */
     float z_near;            /* near plane, metres; cull unless t_z > z_near [0.2] */
     float jac_clamp;         /* Jacobian point clamp, x of half field of view [1.3] */

@@ -7,7 +7,7 @@
  * the full-resolution comparison: a small convolutional network maps a
  * low-resolution render of a candidate and the equally pooled query to a
  * predicted NCC, so that only the best-predicted candidates are rendered at full
- * resolution and scored by the exact NCC (which stays the judge). It is trained
+ * resolution and scored by the exact NCC (which keeps the final say). It is trained
  * on pairs that the renderer itself produces, labelled with their full-resolution
  * NCC, by the kernels below (forward, backward, AdamW) on the GPU.
  *

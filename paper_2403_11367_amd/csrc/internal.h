@@ -54,7 +54,7 @@ struct Consts {
 };
 
 struct TileGrid {
-    int tile_w, tile_h;    // 16 x 16 in this build
+    int tile_w, tile_h;    // 16 x 16 in this library
     int log2_w, log2_h;
     int tiles_x, tiles_y;  // tiles per image row / column
     int n_tiles;           // tiles per pose

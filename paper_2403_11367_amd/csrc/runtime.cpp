@@ -202,7 +202,7 @@ const char *gsr_status_string(int status) {
         case GSR_EHIP: return "HIP runtime error";
         case GSR_ENODEV: return "no such device";
         case GSR_EOVERFLOW: return "pair buffer overflow";
-        case GSR_EUNSUPPORTED: return "unsupported by this build";
+        case GSR_EUNSUPPORTED: return "unsupported by this library";
         case GSR_EDEVICE: return "device-side check failed";
         default: return "unknown status";
     }
@@ -390,7 +390,7 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
     if (!pow2(cfg.tile_w) || !pow2(cfg.tile_h) || (cfg.flags & ~(GSR_RENDER_COUNT_EVALS | GSR_RENDER_KEEP_STATE)) != 0 ||
         cfg.pair_capacity < 0 || cfg.pose_groups < 0 || cfg.pose_groups > kMaxGroups)
         return fail(ctx, GSR_EINVAL, "bad render configuration");
-    if (cfg.tile_w != 16 || cfg.tile_h != 16) return fail(ctx, GSR_EUNSUPPORTED, "this build renders 16x16 tiles");
+    if (cfg.tile_w != 16 || cfg.tile_h != 16) return fail(ctx, GSR_EUNSUPPORTED, "this library renders 16x16 tiles");
     if (!(cfg.alpha_min > 0.f) || !(cfg.alpha_max <= 1.f) || !(cfg.alpha_min < cfg.alpha_max) ||
         !(cfg.t_min > 0.f) || !(cfg.cutoff_d2 > 0.f) || !(cfg.eps_dilate >= 0.f))
         return fail(ctx, GSR_EINVAL, "bad render constants");

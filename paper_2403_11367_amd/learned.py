@@ -78,7 +78,7 @@ def render_query(ctx, dmap: DeviceMap, cam, q):
 
 
 def exhaustive_ncc(ctx, sm, cam, poses_t, query, batch=128, out=None):
-    """NCC of every candidate at full resolution (the labels and the judge)."""
+    """NCC of every candidate at full resolution (the labels and the final ranking)."""
     import torch
     P = poses_t.shape[0]
     if out is None:
