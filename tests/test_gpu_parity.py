@@ -1,7 +1,9 @@
 """GPU parity of the HIP path (through the C ABI) against the CPU oracle.
 
 Bars: screen records, tile counts, keys and per-tile order bit-exact;
-renders within 1e-4 abs on pixels the oracle does not flag; NCC within 1e-4.
+renders within 1e-4 abs on every pixel, of the oracle's result or, where the
+oracle flags a decision within float32 error of its threshold, of one of the
+pixel's outcomes with those decisions taken either way; NCC within 1e-4.
 """
 import numpy as np
 import pytest
@@ -413,8 +415,10 @@ def cfg1():
     return sc, idx
 
 
-def test_config1_full_size_sampled(ctx, cfg1):
-    """Headline shape: 500,143-Gaussian crop, 64 poses, 1408x376 (the bench launch)."""
+def test_config1_full_size_frames(ctx, cfg1):
+    """Headline shape: 500,143-Gaussian crop, 64 poses, 1408x376 (the bench launch);
+    records, keys and order of 4 poses bit-exact, and those 4 frames compared
+    with the oracle on every pixel (depth bar 1e-4 x max(1, depth))."""
     sc, idx = cfg1
     say(f"config1: crop {idx.size} of {sc.gaussians.n}, 64 poses, 1408x376")
     sm = load(ctx, sc.gaussians, index=idx)
@@ -425,27 +429,11 @@ def test_config1_full_size_sampled(ctx, cfg1):
     sub = sc.gaussians.take(idx)
     pr = prep(sub)
     T = _tiles(sc.camera)
-    rng_px = np.random.default_rng(5)
     for p in (0, 21, 42, 63):
-        out_rec = search.project.preprocess(pr[0], pr[1], pr[2], pr[3], sc.poses[p], sc.camera.width,
-                                            sc.camera.height, sc.camera.fx, sc.camera.fy, sc.camera.cx,
-                                            sc.camera.cy)
-        check_records(recs, nts, out_rec, idx.size, p)
-        k, v = search.keys.make_pairs_fast(out_rec, sc.camera.width, sc.camera.height, 16, 16)
-        ks, vs = search.keys.sort_pairs(k, v)
-        rng = search.keys.tile_ranges(ks, T)
+        out, rec, ks, vs, rng = oracle_pose(pr, sc.poses[p], sc.camera)
+        check_records(recs, nts, rec, idx.size, p)
         check_pairs(offs, pairs, ks, vs, rng, p, T)
-        pi = rng_px.integers(0, sc.camera.width, 3000)
-        pj = rng_px.integers(0, sc.camera.height, 3000)
-        c, d, t, f = search.blend.render_pixels(out_rec, vs, rng, sc.camera.width, pi, pj)
-        ok = ~f
-        e_rgb = np.abs(rgb[p][:, pj, pi] - c)[:, ok].max()
-        e_dep = np.abs(dep[p][pj, pi] - d)[ok].max()
-        e_t = np.abs(tf[p][pj, pi] - t)[ok].max()
-        say(f"  pose {p}: sampled 3000 px, max|drgb| {e_rgb:.2e} max|ddepth| {e_dep:.2e} "
-            f"max|dT| {e_t:.2e} flagged {int(f.sum())}")
-        assert e_rgb <= 1e-4 and e_t <= 1e-4
-        assert e_dep <= 1e-4 * max(1.0, float(np.abs(d).max()))
+        compare_render(rgb[p], dep[p], tf[p], out, f"pose {p}", depth_rel=True)
     # properties at full size: T in [0, 1], colours in [0, 1] (all inputs are)
     assert tf.min() >= 0 and tf.max() <= 1
     assert rgb.min() >= 0 and rgb.max() <= 1 + 1e-5

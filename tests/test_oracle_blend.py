@@ -189,3 +189,154 @@ def test_render_pixels_matches_full_render():
     np.testing.assert_allclose(rgb, out.rgb[:, pj, pi], atol=1e-12)
     np.testing.assert_allclose(dep, out.depth[pj, pi], atol=1e-10)
     assert np.array_equal(fl, out.flag[pj, pi])
+
+
+# ---- margin flag and outcomes: decisions within float32 error of a threshold ----
+
+def _one_pixel(rec, w=16, h=16, tile=(16, 16)):
+    return _render(rec, w, h, *tile)
+
+
+def test_flag_cutoff_both_sides():
+    # one Gaussian, pixel (8, 8) at dx = 3 from the mean, isotropic conic a: d^2 = 9 a
+    base = dict(u=[5.5], v=[8.5], z=[2.0], op=[0.9], rgb=[[1.0, 0.5, 0.25]], rect=[[0, 15, 0, 15]])
+    d2, p, m_cut, _ = blend._exponent_margins(np.array(3.0), np.array(0.0), 1.0, 0.0, 1.0, 0.9, 16, 16)
+    margin_d2 = float(m_cut) / blend.S2
+    assert 1e-6 < margin_d2 < 1e-4          # float32 error of d^2 near 9 at this geometry
+    for a, flagged, inside in ((1.0 + 0.2 * margin_d2 / 9, True, False), (1.0 - 0.2 * margin_d2 / 9, True, True),
+                               (1.0 + 3.0 * margin_d2 / 9, False, False), (1.0 - 3.0 * margin_d2 / 9, False, True)):
+        rec = _records(conic=[[a, 0.0, a]], **base)
+        out = _one_pixel(rec)
+        assert bool(out.flag[8, 8]) == flagged, a
+        expect_in = float(np.float32(0.9)) * np.exp(-0.5 * 9.0 * float(np.float32(a)))
+        assert (out.t_final[8, 8] < 1.0) == inside
+        outs = blend.outcomes(out, 8, 8)
+        got = sorted(float(x) for x in outs[:, 4])
+        if flagged:   # both decisions, with their closed-form results
+            np.testing.assert_allclose(got, [1.0 - expect_in, 1.0], rtol=1e-12)
+            np.testing.assert_allclose(sorted(outs[:, 0]), [0.0, expect_in], rtol=1e-12)
+        else:
+            assert len(got) == 1
+        # pixels away from the threshold are never flagged
+        assert not out.flag[8, 5] and not out.flag[3, 12]
+
+
+def test_flag_alpha_floor_both_sides():
+    amin = blend.ALPHA_MIN
+    for rel, flagged in ((1e-6, True), (-1e-6, True), (3e-5, False), (-3e-5, False)):
+        o = np.float32(amin * (1.0 + rel))
+        rec = _records(u=[8.5], v=[8.5], conic=[[0.5, 0.0, 0.5]], z=[2.0], op=[o], rgb=[[1.0, 1.0, 1.0]],
+                       rect=[[0, 15, 0, 15]])
+        out = _one_pixel(rec)
+        assert bool(out.flag[8, 8]) == flagged, rel
+        takes = float(o) >= amin
+        assert (out.rgb[0, 8, 8] > 0) == takes
+        outs = blend.outcomes(out, 8, 8)
+        if flagged:
+            np.testing.assert_allclose(sorted(outs[:, 0]), [0.0, float(o)], rtol=1e-12)
+        else:
+            assert outs.shape[0] == 1
+
+
+def test_flag_termination_both_sides():
+    # three equal layers take T to 1e-4 (1 + rel); a fourth (blue) lies behind
+    for rel, flagged in ((1e-6, True), (-1e-6, True), (3e-3, False), (-3e-3, False)):
+        a = np.float32(1.0 - (1e-4 * (1.0 + rel)) ** (1.0 / 3.0))
+        t3 = (1.0 - float(a)) ** 3
+        rec = _records(u=[8.5] * 4, v=[8.5] * 4, conic=[[0.5, 0.0, 0.5]] * 4, z=[1.0, 2.0, 3.0, 4.0],
+                       op=[a, a, a, 0.5], rgb=[[1.0, 0.0, 0.0]] * 3 + [[0.0, 0.0, 1.0]], rect=[[0, 15, 0, 15]] * 4)
+        out = _one_pixel(rec)
+        assert bool(out.flag[8, 8]) == flagged, rel
+        stops = t3 < blend.T_MIN
+        assert (out.rgb[2, 8, 8] == 0.0) == stops
+        outs = blend.outcomes(out, 8, 8)
+        blues = sorted(float(x) for x in outs[:, 2])
+        if flagged:  # stop after the third layer, or take the fourth too
+            np.testing.assert_allclose(blues, [0.0, 0.5 * t3], rtol=1e-12)
+        else:
+            assert len(blues) == 1
+
+
+def _fma32(a, b, c):
+    return np.float32(np.float64(a) * np.float64(b) + np.float64(c))
+
+
+def test_margin_bounds_a_float32_evaluation():
+    """The exponent margins bound the error of the float32 evaluation they
+    describe: sum of squares of factors from a 1-ulp reciprocal square root and
+    square root, expanded about the tile centre, with fused adds; on random
+    geometry up to condition number 1e4, pixels of the tile, centres within the
+    3-sigma reach."""
+    r = np.random.default_rng(7)
+    f = np.float32
+    s = f(np.sqrt(f(0.5) * f(1.4426950408889634)))
+    cut_p2 = f(f(-0.5) * f(1.4426950408889634) * f(9.0))
+    worst = 0.0
+    for _ in range(4000):
+        sig = np.exp(r.uniform(np.log(0.3), np.log(60.0)))
+        cond = np.exp(r.uniform(0.0, np.log(1e4)))
+        th = r.uniform(0, np.pi)
+        R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+        cov = R @ np.diag([sig ** 2, sig ** 2 / cond]) @ R.T + 0.3 * np.eye(2)
+        inv = np.linalg.inv(cov)
+        A, B, C = f(inv[0, 0]), f(inv[0, 1]), f(inv[1, 1])
+        o = f(r.uniform(0.01, 0.99))
+        xc, yc = f(r.integers(0, 80) * 16 + 8), f(r.integers(0, 20) * 16 + 8)
+        x, y = f(r.integers(0, 16) - 7.5), f(r.integers(0, 16) - 7.5)
+        reach = 3.0 * np.sqrt(np.diag(cov)) + 1.0
+        u = f(xc + x + r.uniform(-reach[0], reach[0]))
+        v = f(yc + y + r.uniform(-reach[1], reach[1]))
+        ulp = lambda t: np.spacing(np.float32(t))
+        rr = f(f(1.0 / np.sqrt(np.float64(A))) + r.integers(-1, 2) * ulp(1.0 / np.sqrt(A)))
+        m11, m12 = f(A * rr), f(B * rr)
+        det = f(np.float64(A) * np.float64(C) - np.float64(B) * np.float64(B))
+        sq = f(f(np.sqrt(np.float64(max(det, 0)))) + r.integers(-1, 2) * ulp(np.sqrt(max(det, 0))))
+        m22 = f(sq * rr)
+        a11, a12, a22 = f(m11 * s), f(m12 * s), f(m22 * s)
+        lo = f(f(np.log2(np.float64(o))) + r.integers(-1, 2) * ulp(np.log2(o)))
+        uc, vc = f(u - xc), f(v - yc)
+        k1 = -_fma32(a11, uc, f(a12 * vc))
+        k2 = -f(a22 * vc)
+        t1 = _fma32(a11, x, _fma32(a12, y, k1))
+        t2 = _fma32(a22, y, k2)
+        p2 = _fma32(-t2, t2, _fma32(-t1, t1, lo))
+        thr = f(cut_p2 + lo)
+        dx, dy = np.float64(xc + x) - np.float64(u), np.float64(yc + y) - np.float64(v)
+        d2, p, m_cut, m_amin = blend._exponent_margins(dx, dy, np.float64(A), np.float64(B), np.float64(C),
+                                                       np.float64(o), 16, 16)
+        err_cut = abs((np.float64(p2) - np.float64(thr)) - blend.S2 * (9.0 - d2))
+        err_amin = abs((np.float64(p2) - np.float64(np.float32(np.log2(np.float32(1 / 255))))) -
+                       (p - blend.LOG2_AMIN))
+        assert err_cut <= m_cut and err_amin <= m_amin, (err_cut, m_cut, err_amin, m_amin)
+        worst = max(worst, err_cut / m_cut, err_amin / m_amin)
+    assert worst > 0.01  # the bound is not vacuous
+
+
+def test_outcomes_hold_the_result_and_unflagged_are_unique():
+    sc = W.config0()
+    prep = search.prepare(sc.gaussians)
+    n_flag = 0
+    for p in (0, 5, 10, 15):
+        out = search.render_pose(prep, sc.poses[p], sc.camera)
+        res = np.concatenate([out.rgb, out.depth[None], out.t_final[None]])
+        for j, i in np.argwhere(out.flag):
+            o = blend.outcomes(out, int(i), int(j))
+            assert np.abs(o - res[:, j, i]).max(axis=1).min() < 1e-12
+            n_flag += 1
+        r = np.random.default_rng(p)
+        for j, i in zip(r.integers(0, 96, 300), r.integers(0, 128, 300)):
+            if not out.flag[j, i]:
+                o = blend.outcomes(out, int(i), int(j))
+                assert o.shape[0] == 1
+                np.testing.assert_allclose(o[0], res[:, j, i], rtol=1e-12, atol=1e-15)
+    assert n_flag > 0
+
+
+@pytest.mark.parametrize("seed,n", [(10, 40), (12, 256)])
+def test_tiled_and_bruteforce_within_each_others_outcomes(seed, n):
+    rec, tiled, brute = _scene_render_pair(seed, n, (16, 16))
+    for a, b in ((tiled, brute), (brute, tiled)):
+        for j, i in np.argwhere(b.flag & ~a.flag):
+            o = blend.outcomes(b, int(i), int(j))
+            res = np.array([*a.rgb[:, j, i], a.depth[j, i], a.t_final[j, i]])
+            assert np.abs(o - res).max(axis=1).min() < 1e-10
