@@ -141,6 +141,9 @@ typedef struct {
     int32_t n_groups;        /* pose groups of the last render */
     int64_t render_serial;   /* renders made on this context so far (gsr_render_backward
                               * differentiates the latest) */
+    int64_t n_culled_nonfinite; /* Gaussians of the rendered submap(s), as last loaded, with a
+                              * non-finite mean, covariance, opacity or colour entry: culled
+                              * at every pose (summed over the submaps of a batched render) */
 } gsr_stats;
 
 /* Create a context on GPU `device`, enqueueing on `hip_stream` (a hipStream_t;

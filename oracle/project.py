@@ -12,6 +12,7 @@ then the inverse (the conic used by the footprint of Eq. 2), the 3-sigma
 pixel rectangle and the tile rectangle.
 
 Float32, fixed operation order (written out term by term below):
+  cull a Gaussian with any non-finite mean, covariance, opacity or colour entry
   t_k  = ((Rw[k,0]*mu_x + Rw[k,1]*mu_y) + Rw[k,2]*mu_z) + tw[k]; cull unless t_z > 0.2
   xt   = t_x / t_z, yt = t_y / t_z; lim_x = 1.3 * ((0.5*W) / fx), lim_y alike;
   xc   = clamp(xt, -lim_x, lim_x), yc alike (used in J only)
@@ -68,6 +69,15 @@ class ScreenRecords:
         return np.where(self.visible, n, 0)
 
 
+def nonfinite(mu: np.ndarray, cov6: np.ndarray, opacity: np.ndarray, rgb: np.ndarray) -> np.ndarray:
+    """[N] bool: Gaussians with a non-finite mean, covariance entry, opacity or
+    colour channel. Such a Gaussian is culled at every pose (and counted)."""
+    with np.errstate(all="ignore"):
+        ok = (np.isfinite(np.asarray(mu, F)).all(1) & np.isfinite(np.asarray(cov6, F)).all(1)
+              & np.isfinite(np.asarray(opacity, F)) & np.isfinite(np.asarray(rgb, F)).all(1))
+    return ~ok
+
+
 def preprocess(mu: np.ndarray, cov6: np.ndarray, opacity: np.ndarray, rgb: np.ndarray,
                pose: np.ndarray, width: int, height: int, fx: float, fy: float,
                cx: float, cy: float, tile_w: int = 16, tile_h: int = 16,
@@ -89,6 +99,7 @@ def preprocess(mu: np.ndarray, cov6: np.ndarray, opacity: np.ndarray, rgb: np.nd
     tx, ty, tz = tcomp(0), tcomp(1), tcomp(2)
     with np.errstate(all="ignore"):
         vis = tz > z_near
+        vis &= ~nonfinite(mu, s, opacity, rgb)
         xt = tx / tz
         yt = ty / tz
         lim_x = jac_clamp * ((F(0.5) * F(width)) / fx)

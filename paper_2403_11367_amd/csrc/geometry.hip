@@ -28,7 +28,8 @@ __global__ __launch_bounds__(kThreads) void k_pack(int64_t n_map, const float *_
                                                    const float *__restrict__ opacity,
                                                    const float *__restrict__ rgb,
                                                    const int64_t *__restrict__ index, int64_t n_sel,
-                                                   float4 *__restrict__ packed, int *__restrict__ flags) {
+                                                   float4 *__restrict__ packed, int *__restrict__ flags,
+                                                   unsigned long long *__restrict__ nonfinite) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n_sel) return;
     const int64_t src = index ? index[i] : i;
@@ -68,10 +69,28 @@ __global__ __launch_bounds__(kThreads) void k_pack(int64_t n_map, const float *_
     const float s11 = (m10 * m10 + m11 * m11) + m12 * m12;
     const float s12 = (m10 * m20 + m11 * m21) + m12 * m22;
     const float s22 = (m20 * m20 + m21 * m21) + m22 * m22;
-    out[0] = make_float4(means[src * 3 + 0], means[src * 3 + 1], means[src * 3 + 2], opacity[src]);
+    float mx = means[src * 3 + 0], my = means[src * 3 + 1], mz = means[src * 3 + 2];
+    const float o = opacity[src], cr = rgb[src * 3 + 0], cg = rgb[src * 3 + 1], cb = rgb[src * 3 + 2];
+    // a Gaussian with any non-finite entry is counted and culled at every pose (NaN mean)
+    const bool finite = __builtin_isfinite(mx) && __builtin_isfinite(my) && __builtin_isfinite(mz) &&
+                        __builtin_isfinite(s00) && __builtin_isfinite(s01) && __builtin_isfinite(s02) &&
+                        __builtin_isfinite(s11) && __builtin_isfinite(s12) && __builtin_isfinite(s22) &&
+                        __builtin_isfinite(o) && __builtin_isfinite(cr) && __builtin_isfinite(cg) &&
+                        __builtin_isfinite(cb);
+    if (!finite) {
+        mx = my = mz = __builtin_nanf("");
+        atomicAdd(nonfinite, 1ull);
+    }
+    out[0] = make_float4(mx, my, mz, o);
     out[1] = make_float4(s00, s01, s02, s11);
-    out[2] = make_float4(s12, s22, rgb[src * 3 + 0], rgb[src * 3 + 1]);
-    out[3] = make_float4(rgb[src * 3 + 2], 0.f, 0.f, 0.f);
+    out[2] = make_float4(s12, s22, cr, cg);
+    out[3] = make_float4(cb, 0.f, 0.f, 0.f);
+}
+
+// Adds each submap's count of non-finite Gaussians to *total.
+__global__ void k_sum_nonfinite(const SubmapTable tab, unsigned long long *__restrict__ total) {
+    const int q = threadIdx.x;
+    if (q < tab.count) atomicAdd(total, *tab.nonfinite[q]);
 }
 
 // S1. One thread per Gaussian slot, looping over a chunk of poses (blockIdx.y),
@@ -373,11 +392,17 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
 
 void launch_pack(hipStream_t s, int64_t n_map, const float *means, const float *scales, const float *quats,
                  const float *opacity, const float *rgb, const int64_t *index, int64_t n_sel, float4 *packed,
-                 int *flags) {
+                 int *flags, unsigned long long *nonfinite) {
+    launch_fill_u64(s, nonfinite, 1, 0ull);
     if (n_sel <= 0) return;
     const unsigned blocks = (unsigned)((n_sel + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(kThreads), 0, s, n_map, means, scales, quats, opacity, rgb,
-                       index, n_sel, packed, flags);
+                       index, n_sel, packed, flags, nonfinite);
+}
+
+void launch_sum_nonfinite(hipStream_t s, const SubmapTable &tab, unsigned long long *total) {
+    static_assert(kMaxBatchSubmaps <= 64, "one lane per submap");
+    hipLaunchKernelGGL(k_sum_nonfinite, dim3(1), dim3(64), 0, s, tab, total);
 }
 
 int64_t preprocess_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }

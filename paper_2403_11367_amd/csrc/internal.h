@@ -15,7 +15,7 @@ namespace gsr {
 // Device flag slots (int32 each), raised by kernels, read and cleared by gsr_sync.
 enum : int { FLAG_OVERFLOW = 0, FLAG_BAD_INDEX = 1, FLAG_COUNT = 4 };
 // Device counter slots (uint64 each), reset at the start of a render.
-enum : int { CNT_EVALS_CONTRIB = 0, CNT_EVALS_LANES = 1, CNT_COUNT = 8 };
+enum : int { CNT_EVALS_CONTRIB = 0, CNT_EVALS_LANES = 1, CNT_NONFINITE = 2, CNT_COUNT = 8 };
 
 // Packed submap record: 4 float4 (64 B) per Gaussian.
 //   q0 = (mu_x, mu_y, mu_z, opacity)
@@ -63,7 +63,7 @@ struct TileGrid {
 // ---- geometry.hip (strict float32, no contraction) ----
 void launch_pack(hipStream_t s, int64_t n_map, const float *means, const float *scales,
                  const float *quats, const float *opacity, const float *rgb, const int64_t *index,
-                 int64_t n_sel, float4 *packed, int *flags);
+                 int64_t n_sel, float4 *packed, int *flags, unsigned long long *nonfinite);
 // The submaps of one render: poses [pose_end[q-1], pose_end[q]) see submap q
 // (n[q] Gaussians, packed records). One entry for an ordinary render; up to
 // kMaxBatchSubmaps for a batch of queries. Record slots are pose * n_slot + g
@@ -74,7 +74,10 @@ struct SubmapTable {
     int pose_end[kMaxBatchSubmaps];
     int64_t n[kMaxBatchSubmaps];
     const float4 *packed[kMaxBatchSubmaps];
+    const unsigned long long *nonfinite[kMaxBatchSubmaps];  // per submap: Gaussians culled as non-finite
 };
+// Adds the non-finite counts of the table's submaps to *total (one launch).
+void launch_sum_nonfinite(hipStream_t s, const SubmapTable &tab, unsigned long long *total);
 // Blocks of the preprocess grid along the Gaussians.
 int64_t preprocess_blocks(int64_t n);
 // Screen records, tile counts ntiles[p][g] (0 = culled) and tile rectangles

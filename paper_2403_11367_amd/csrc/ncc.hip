@@ -191,8 +191,10 @@ __global__ __launch_bounds__(kThreads) void k_ncc_final(const double *__restrict
     }
 }
 
-// Ascending order of the key = descending score, then ascending index.
+// Ascending order of the key = descending score, then ascending index; a NaN
+// score ranks after every number (-inf included).
 __device__ __forceinline__ uint64_t rank_key(float score, uint32_t idx) {
+    if (__builtin_isnan(score)) return (0xffffffffull << 32) | idx;
     uint32_t b = __float_as_uint(score);
     b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);  // ascending in score
     return ((uint64_t)(~b) << 32) | idx;

@@ -108,6 +108,7 @@ struct gsr_submap {
     uint64_t version = 0;   // counts loads (a refill in place changes it)
     int64_t n = 0, cap = 0;
     float4 *packed = nullptr;  // [cap * kPackedQuads]
+    unsigned long long *nonfinite = nullptr;  // Gaussians of the last load culled as non-finite
 };
 
 namespace {
@@ -342,8 +343,10 @@ int gsr_submap_load(gsr_ctx *ctx, int64_t n_map, const float *means, const float
         nsm->device = ctx->device;
         nsm->cap = n_sel > 0 ? n_sel : 1;
         hipError_t e = hipMalloc(&nsm->packed, (size_t)nsm->cap * gsr::kPackedQuads * sizeof(float4));
+        if (e == hipSuccess) e = hipMalloc(&nsm->nonfinite, sizeof(unsigned long long));
         if (e != hipSuccess) {
             (void)hipGetLastError();
+            if (nsm->packed) (void)hipFree(nsm->packed);
             delete nsm;
             return fail(ctx, GSR_ENOMEM, "submap allocation failed");
         }
@@ -354,7 +357,8 @@ int gsr_submap_load(gsr_ctx *ctx, int64_t n_map, const float *means, const float
     sm->n = n_sel;
     sm->identity = index == nullptr;
     sm->version++;
-    gsr::launch_pack(ctx->stream, n_map, means, scales, quats, opacity, rgb, index, n_sel, sm->packed, ctx->d_flags);
+    gsr::launch_pack(ctx->stream, n_map, means, scales, quats, opacity, rgb, index, n_sel, sm->packed, ctx->d_flags,
+                     sm->nonfinite);
     return check_launch(ctx, "pack");
 }
 
@@ -363,6 +367,7 @@ int gsr_submap_free(gsr_submap *sm) {
     // hipFree waits for work on the device that may still read the submap
     (void)hipSetDevice(sm->device);
     if (sm->packed) (void)hipFree(sm->packed);
+    if (sm->nonfinite) (void)hipFree(sm->nonfinite);
     delete sm;
     return GSR_OK;
 }
@@ -523,6 +528,7 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         HIPC(ctx, hipEventRecord(ev->e[0], s));
     }
     gsr::launch_fill_u64(s, ctx->d_counters, gsr::CNT_COUNT, 0ull);
+    gsr::launch_sum_nonfinite(s, tab, ctx->d_counters + gsr::CNT_NONFINITE);
     const bool pack = gsr::pack_sort_values(n, tg.n_tiles);  // tile counts ride in the sort values
     gsr::launch_preprocess(s, tab, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p, ntiles,
                            (uint2 *)ctx->rect.p, sort_kb, sort_vb, (uint32_t *)ctx->vcount.p, pack);
@@ -637,6 +643,7 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     tab.pose_end[0] = n_poses;
     tab.n[0] = sm->n;
     tab.packed[0] = sm->packed;
+    tab.nonfinite[0] = sm->nonfinite;
     return render_impl(ctx, tab, sm->n, cam, poses, n_poses, cfg, rgb, depth, tfinal, sm);
 }
 
@@ -722,6 +729,7 @@ int gsr_render_multi(gsr_ctx *ctx, const gsr_submap *const *submaps, const int32
         tab.pose_end[q] = (int)P;
         tab.n[q] = sm->n;
         tab.packed[q] = sm->packed;
+        tab.nonfinite[q] = sm->nonfinite;
         n_slot = std::max<int64_t>(n_slot, sm->n);
     }
     return render_impl(ctx, tab, n_slot, cam, poses, (int32_t)P, cfg, rgb, depth, tfinal, nullptr);
@@ -1010,6 +1018,7 @@ int gsr_get_stats(gsr_ctx *ctx, gsr_stats *out) {
     out->bad_index = flags[gsr::FLAG_BAD_INDEX];
     out->evals_contrib = (int64_t)cnt[gsr::CNT_EVALS_CONTRIB];
     out->evals_lanes = (int64_t)cnt[gsr::CNT_EVALS_LANES];
+    out->n_culled_nonfinite = (int64_t)cnt[gsr::CNT_NONFINITE];
     double pre = 0, sort = 0, blend = 0, whole = 0;
     size_t n_group_runs = 0;
     for (size_t i = 0; i < ctx->n_ev_render; ++i) {

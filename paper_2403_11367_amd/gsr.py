@@ -67,7 +67,7 @@ class Stats(C.Structure):
                 ("n_profiled_renders", C.c_int32), ("n_profiled_ncc", C.c_int32),
                 ("ms_preprocess", C.c_float), ("ms_sort", C.c_float), ("ms_blend", C.c_float),
                 ("ms_ncc", C.c_float), ("ms_render", C.c_float), ("n_groups", C.c_int32),
-                ("render_serial", C.c_int64)]
+                ("render_serial", C.c_int64), ("n_culled_nonfinite", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -157,26 +157,48 @@ def test_empty_and_all_culled(ctx):
 
 
 def test_nan_and_degenerate_inputs_are_culled(ctx):
-    say("NaN means, zero scales, zero quaternion")
+    say("NaN / Inf means, scales, opacities and colours, zero scales, zero quaternion")
     sc = W.tiny_scene(31, n=200)
     g = sc.gaussians
     means = g.means.copy()
     means[5] = np.nan
+    means[11, 1] = np.inf
     scales = g.scales.copy()
     scales[7] = 0.0
+    scales[13, 2] = np.inf
     quats = g.quats.copy()
     quats[9] = 0.0
-    bad = W.Gaussians(means, scales, quats, g.opacity, g.rgb)
+    op = g.opacity.copy()
+    op[[20, 21]] = [np.nan, np.inf]
+    rgb_in = g.rgb.copy()
+    rgb_in[30, 0] = np.nan
+    rgb_in[31, 2] = -np.inf
+    bad = W.Gaussians(means, scales, quats, op, rgb_in)
     sm = load(ctx, bad)
     rgb, dep, tf = gpu_render(ctx, sm, sc.camera, sc.poses)
+    st = ctx.stats()
     recs, nts, offs, pairs = gpu_buffers(ctx)
     pr = prep(bad)
+    n_bad = int(search.project.nonfinite(*pr).sum())
+    say(f"  non-finite: gpu {st['n_culled_nonfinite']} oracle {n_bad}")
+    assert st["n_culled_nonfinite"] == n_bad >= 7
     for p in range(sc.poses.shape[0]):
         out, rec, ks, vs, rng = oracle_pose(pr, sc.poses[p], sc.camera)
-        assert not rec.visible[5] and not rec.visible[9]
+        assert not rec.visible[[5, 9, 11, 13, 20, 21, 30, 31]].any()
         check_records(recs, nts, rec, g.n, p)
         check_pairs(offs, pairs, ks, vs, rng, p, _tiles(sc.camera))
         compare_render(rgb[p], dep[p], tf[p], out, f"pose {p}")
+        assert np.isfinite(rgb[p]).all() and np.isfinite(dep[p]).all()
+
+
+def test_topk_ranks_nan_scores_last(ctx):
+    """Scores with NaN and infinities: the order equals the oracle's (NaN after -inf)."""
+    import torch
+    say("top-k over scores with NaN, +-inf and ties")
+    s = np.array([0.5, np.nan, -np.inf, 0.5, np.inf, np.nan, -0.25, 0.9, -np.inf, 0.0], np.float32)
+    got = ctx.topk(to_dev(s), s.size).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(got, search.topk(s, s.size)), (got, search.topk(s, s.size))
 
 
 def _stack_scene(n, spread, seed):

@@ -199,6 +199,27 @@ def test_culling_rules():
     assert rec.visible.tolist() == [False, False, True, False, False, False, True]
 
 
+def test_non_finite_parameters_are_culled_and_counted():
+    # the same on-axis Gaussian 7 times, then one non-finite entry in each of
+    # opacity, a colour channel, a covariance entry and the mean (the first copy
+    # stays clean)
+    pose = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0]], np.float32)
+    n = 7
+    mu = np.tile(np.array([[0.0, 0.0, 5.0]], np.float32), (n, 1))
+    cov6 = np.tile(np.array([[0.01, 0, 0, 0.01, 0, 0.01]], np.float32), (n, 1))
+    op = np.full(n, 0.5, np.float32)
+    rgb = np.full((n, 3), 0.5, np.float32)
+    op[1], op[2] = np.nan, np.inf
+    rgb[3, 1] = -np.inf
+    cov6[4, 3] = np.inf
+    mu[5, 0] = np.nan
+    rgb[6, 2] = np.nan
+    bad = project.nonfinite(mu, cov6, op, rgb)
+    assert bad.tolist() == [False] + [True] * 6
+    rec = project.preprocess(mu, cov6, op, rgb, pose, 64, 48, 50.0, 50.0, 32.0, 24.0)
+    assert rec.visible.tolist() == [True] + [False] * 6
+
+
 def test_jacobian_clamp_outside_fov():
     """A Gaussian far to the side: J uses x/z clamped to 1.3 * (W/2)/fx, u does not."""
     pose = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0]], np.float32)
