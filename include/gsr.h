@@ -249,6 +249,19 @@ int gsr_graph_destroy(gsr_graph *graph);
 int gsr_ncc(gsr_ctx *ctx, const float *query_dev, const float *renders_dev, int32_t n_poses,
             int32_t height, int32_t width, float *scores_dev);
 
+/* gsr_ncc without any allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and scores, with the grey query and the per-block partial sums in
+ * a static device array of 8 MiB per device (each device holds its copy until the
+ * process ends) instead of the context's workspace. It calls no hipMalloc or
+ * hipFree and records no profiling events. Sizes whose scratch,
+ * 4 H W (rounded up to 256 B) + 48 P ceil(H W / 4096) bytes, exceeds 8 MiB are
+ * refused with GSR_EINVAL (1408 x 376 fits up to about 1000 renders per call).
+ * Every call on a device shares that device's array: calls that overlap on one
+ * device, from any context or stream, race. Arguments as gsr_ncc. */
+int gsr_ncc_noalloc(gsr_ctx *ctx, const float *query_dev, const float *renders_dev, int32_t n_poses,
+                    int32_t height, int32_t width, float *scores_dev);
+
 /* Indices of the k best scores, best first; ties go to the lower index
  * (Sec. III-C1 keeps the most similar render). 1 <= k <= P <= 8192.
  *   scores_dev [P] float32, idx_dev [k] int32 output. */

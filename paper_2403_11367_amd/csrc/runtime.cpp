@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -231,6 +232,38 @@ int gsr_default_cfg(gsr_render_cfg *out) {
     return GSR_OK;
 }
 
+// Scratch of gsr_ncc_noalloc: a static device array (one copy per device, held
+// until the process ends) in place of the context workspace. Host code uses the
+// device address taken once per device at gsr_create, never the array's name.
+namespace {
+constexpr size_t kNccScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kNccScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch[kMaxScratchDevices] = {};
+
+// With `device` current: record the device address of its copy of `scratch`.
+int scratch_setup(gsr_ctx *ctx, int device) {
+    if (device >= kMaxScratchDevices) return GSR_OK;  // gsr_ncc_noalloc then reports GSR_EUNSUPPORTED
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[device]) return GSR_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(ctx, GSR_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch[device] = static_cast<unsigned char *>(p);
+    return GSR_OK;
+}
+
+unsigned char *scratch_of(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[device];
+}
+}  // namespace
+
 int gsr_create(gsr_ctx **out, int device, void *hip_stream) {
     if (!out) return GSR_EINVAL;
     *out = nullptr;
@@ -263,6 +296,7 @@ int gsr_create(gsr_ctx **out, int device, void *hip_stream) {
         if (hipMalloc(&ctx->d_queue, kMaxGroups * sizeof(unsigned int)) != hipSuccess) { rc = GSR_ENOMEM; break; }
         if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
             ctx->n_cu < 1) { rc = GSR_EHIP; break; }
+        if ((rc = scratch_setup(ctx, device)) != GSR_OK) break;
     } while (0);
     if (rc != GSR_OK) {
         (void)hipGetLastError();
@@ -758,6 +792,29 @@ int gsr_ncc(gsr_ctx *ctx, const float *query, const float *renders, int32_t n_po
     if ((rc = check_launch(ctx, "ncc"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[1], ctx->stream));
     return GSR_OK;
+}
+
+int gsr_ncc_noalloc(gsr_ctx *ctx, const float *query, const float *renders, int32_t n_poses, int32_t height,
+                    int32_t width, float *scores) {
+    if (!ctx) return GSR_EINVAL;
+    if (!query || !renders || !scores) return fail(ctx, GSR_EINVAL, "null argument");
+    if (n_poses < 1 || n_poses > 65535 || height < 1 || width < 1 || (int64_t)height * width > ((int64_t)1 << 31))
+        return fail(ctx, GSR_EINVAL, "size out of range");
+    const int64_t hw = (int64_t)height * width;
+    const int64_t nb = (hw + gsr::ncc_pixels_per_block() - 1) / gsr::ncc_pixels_per_block();
+    // grey query, then the per-block partial moments (6 doubles each); both are
+    // written in full before they are read, so nothing is cleared
+    const size_t grey_bytes = ((size_t)hw * sizeof(float) + 255) & ~(size_t)255;
+    const size_t need = grey_bytes + (size_t)n_poses * (size_t)nb * 6 * sizeof(double);
+    if (need > kNccScratchBytes)
+        return fail(ctx, GSR_EINVAL, "gsr_ncc_noalloc: " + std::to_string(need) + " bytes of scratch needed, more than the " +
+                                         std::to_string(kNccScratchBytes) + " of the static scratch (use gsr_ncc)");
+    unsigned char *base = scratch_of(ctx->device);
+    if (!base) return fail(ctx, GSR_EUNSUPPORTED, "gsr_ncc_noalloc: no static scratch on this device");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    gsr::launch_ncc(ctx->stream, query, renders, n_poses, height, width, reinterpret_cast<float *>(base),
+                    reinterpret_cast<double *>(base + grey_bytes), scores);
+    return check_launch(ctx, "ncc_noalloc");
 }
 
 int gsr_topk(gsr_ctx *ctx, const float *scores, int32_t n_poses, int32_t k, int32_t *idx) {

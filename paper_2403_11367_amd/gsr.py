@@ -30,7 +30,7 @@ RENDER_KEEP_STATE = 2  # keep long lists' compositing states for gsr_render_back
 EXPORTS = [
     "gsr_create", "gsr_destroy", "gsr_set_stream", "gsr_set_profiling", "gsr_default_cfg",
     "gsr_submap_load", "gsr_submap_free", "gsr_submap_size", "gsr_render", "gsr_render_multi",
-    "gsr_render_backward", "gsr_ncc",
+    "gsr_render_backward", "gsr_ncc", "gsr_ncc_noalloc",
     "gsr_topk", "gsr_search", "gsr_capture_begin", "gsr_capture_end", "gsr_graph_launch", "gsr_graph_destroy",
     "gsr_sync", "gsr_get_stats", "gsr_debug_size", "gsr_debug_copy", "gsr_crop",
     "gsr_status_string", "gsr_last_error",
@@ -100,6 +100,7 @@ def _load() -> C.CDLL:
         "gsr_graph_launch": (I, [P]),
         "gsr_graph_destroy": (I, [P]),
         "gsr_ncc": (I, [P, P, P, I32, I32, I32, P]),
+        "gsr_ncc_noalloc": (I, [P, P, P, I32, I32, I32, P]),
         "gsr_topk": (I, [P, P, I32, I32, P]),
         "gsr_search": (I, [P, P, C.POINTER(CameraC), P, I32, P, I32, I32, F, P, C.POINTER(RenderCfg), P,
                            C.POINTER(I32), C.POINTER(F), C.POINTER(I32)]),
@@ -402,6 +403,18 @@ class Context:
         self._bind_stream()
         self._check(LIB.gsr_ncc(self.handle, query.data_ptr(), renders.data_ptr(), P, H, W,
                                 scores.data_ptr()), "gsr_ncc")
+        return scores
+
+    def ncc_noalloc(self, query, renders, scores):
+        """gsr_ncc_noalloc: NCC into the caller's `scores` [P] with the library's
+        static scratch (no allocation anywhere in the call)."""
+        P, _, H, W = renders.shape
+        _dev_f32(query, "query", (3, H, W))
+        _dev_f32(renders, "renders", (P, 3, H, W))
+        _dev_f32(scores, "scores", (P,))
+        self._bind_stream()
+        self._check(LIB.gsr_ncc_noalloc(self.handle, query.data_ptr(), renders.data_ptr(), P, H, W,
+                                        scores.data_ptr()), "gsr_ncc_noalloc")
         return scores
 
     def topk(self, scores, k: int = 1, out=None):
