@@ -22,6 +22,7 @@ batched render per stage (autotuned launch) and as a HIP-graph replay, against
 Prints one JSON line (rank 0). See --help for flags.
 """
 import argparse
+import contextlib
 import hashlib
 import json
 import os
@@ -68,9 +69,42 @@ def _blend_traffic(n_groups):
     return float(m_b.group(1)) if m_h.group(1) == cur else None
 
 
+def _oracle_candidates(args):
+    """Worker: the oracle on candidate poses `poses` of a submap (pack + project +
+    keys + sort + float64 blend), one thread; returns their renders."""
+    arrays, poses, cam = args
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import search
+
+    with threadpool_limits(limits=1):
+        prep = search.prepare(W.Gaussians(*arrays))
+        return [search.render_pose(prep, pose, cam).rgb.astype(np.float32) for pose in poses]
+
+
+def _noop(x):
+    return x
+
+
+def _cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(scene, sub_idx, n_cand):
-    """The oracle, untouched, on a bounded sample: n_cand full-frame candidates,
-    single thread (BLAS pools limited to 1)."""
+    """The oracle, untouched, on a bounded sample of the same workload: n_cand
+    full-frame candidates on one thread (BLAS pools limited to 1), then one
+    candidate per core on every core of this process's affinity set (a process
+    pool, one thread each), each followed by the oracle's NCC."""
+    import multiprocessing as mp
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -86,10 +120,27 @@ def cpu_baseline(scene, sub_idx, n_cand):
         for p in range(n_cand):
             renders.append(search.render_pose(prep, scene.poses[p], scene.camera).rgb)
         oncc.ncc(query, np.stack(renders))
-        dt = time.perf_counter() - t0
-    return {"value": n_cand / dt, "unit": "candidates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_cand} of the 64 full-frame candidates of the same workload (pack + project + "
-                      f"keys + sort + float64 blend + NCC), {dt:.1f} s, 1 thread"}
+        dt1 = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    n_all = min(cores, scene.poses.shape[0])
+    ctxm = mp.get_context("spawn")
+    arrays = tuple(sub.arrays())
+    with ctxm.Pool(n_all) as pool:
+        pool.map(_noop, range(n_all))  # workers started and importing before the clock starts
+        t0 = time.perf_counter()
+        parts = pool.map(_oracle_candidates, [(arrays, [scene.poses[p]], scene.camera) for p in range(n_all)],
+                         chunksize=1)
+        with threadpool_limits(limits=1):
+            oncc.ncc(query, np.stack([r for part in parts for r in part]))
+        dt_all = time.perf_counter() - t0
+    model = _cpu_model()
+    return {"value": n_all / dt_all, "unit": "candidates/s", "cores": n_all, "kind": "oracle",
+            "sample": f"{n_all} of the 64 full-frame candidates of the same workload, one per core in a process "
+                      f"pool of started workers (each: pack + project + keys + sort + float64 blend; then NCC), "
+                      f"{dt_all:.1f} s wall, on {n_all} cores of '{model}'",
+            "cpu_model": model,
+            "single_core": {"value": n_cand / dt1, "cores": 1,
+                            "sample": f"{n_cand} candidates on one thread, {dt1:.1f} s"}}
 
 
 def main():
@@ -172,12 +223,19 @@ def main():
 
     ctx.set_profiling(True)
     ctx.stats()  # reset the profiled-call window
+    # per-step HIP events on the stream the library enqueues on (torch's current)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         step()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
+    med_ms = step_ms[len(step_ms) // 2] if len(step_ms) % 2 else 0.5 * (step_ms[len(step_ms) // 2 - 1] +
+                                                                         step_ms[len(step_ms) // 2])
     st = ctx.stats()
     ctx.set_profiling(False)
     ctx.sync()  # raises on overflow: the timed images would be invalid
@@ -216,6 +274,8 @@ def main():
                    "global_batch": P, "parallelism": "single GPU",
                    "path": "plain: every candidate rendered at full resolution and NCC-scored"},
         "pixels_per_s": round(cand_s * px, 1),
+        "step_ms": {"mean": round(ms_step, 4), "median": round(med_ms, 4), "min": round(step_ms[0], 4),
+                    "max": round(step_ms[-1], 4), "median_candidates_per_s": round(P / (med_ms * 1e-3), 1)},
         "roofline": roof,
         "e2e_hbm": {"bytes_per_step": bytes_step, "achieved_GBs": round(e2e_gbs, 1), "peak_GBs": HBM_PEAK_GBS,
                     "frac": round(e2e_gbs / HBM_PEAK_GBS, 4)},
@@ -376,25 +436,29 @@ def training_leg(ctx, cam, dev, steps=8, warmup=2):
 
     tm = W.training_map(500_000)
     data = train.make_training_data(ctx, tm.gt, cam, n_steps=steps + warmup, views=4, seed=33)
-    tr = train.MapTrainer(ctx, cam, tm.means, tm.log_scales, tm.quats, tm.logits, tm.rgb)
-    losses = []
-    for s in range(warmup):
-        losses.append(float(tr.step(data.poses[s], data.rgb[s], data.lidar[s], data.mask[s])))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = [tr.step(data.poses[s], data.rgb[s], data.lidar[s], data.mask[s]) for s in range(warmup, warmup + steps)]
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / steps
-    losses += [float(x) for x in out]
-    tr.close()
-    res = {"gaussians": 500_000, "views_per_step": 4, "image": f"{cam.width}x{cam.height}",
-           "ms_per_step": round(t * 1e3, 3), "views_per_s": round(4 / t, 1),
-           "loss_first": round(losses[0], 5), "loss_last": round(losses[-1], 5)}
-    _log(f"training: {res['ms_per_step']:.2f} ms per step of 4 views, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    res = {"gaussians": 500_000, "views_per_step": 4, "image": f"{cam.width}x{cam.height}"}
+    # kept compositing states (the default) and the backward that recomputes every
+    # list's transmittance from its front, each from the same initial map
+    for mode, keep in (("kept_states", True), ("recompute", False)):
+        tr = train.MapTrainer(ctx, cam, tm.means, tm.log_scales, tm.quats, tm.logits, tm.rgb, keep_state=keep)
+        losses = []
+        for s in range(warmup):
+            losses.append(float(tr.step(data.poses[s], data.rgb[s], data.lidar[s], data.mask[s])))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = [tr.step(data.poses[s], data.rgb[s], data.lidar[s], data.mask[s]) for s in range(warmup, warmup + steps)]
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        losses += [float(x) for x in out]
+        tr.close()
+        res[mode] = {"ms_per_step": round(t * 1e3, 3), "views_per_s": round(4 / t, 1),
+                     "loss_first": round(losses[0], 5), "loss_last": round(losses[-1], 5)}
+        _log(f"training ({mode}): {t * 1e3:.2f} ms per step of 4 views, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    res["ms_per_step"] = res["kept_states"]["ms_per_step"]
     return res
 
 
-def learned_leg(ctx, sm, cam, sc, query, dev, k=16, reps=5):
+def learned_leg(ctx, sm, cam, sc, query, dev, k=16, reps=5, recall_queries=24):
     """Learned vs plain on the same submap and query: 1024 candidates (8 dx x 8 dy
     x 16 dyaw at 1 m / 1 m / 5 degrees around the prior). Plain renders and scores
     all of them at full resolution; the pruned searches render all at a quarter of
@@ -441,11 +505,25 @@ def learned_leg(ctx, sm, cam, sc, query, dev, k=16, reps=5):
         res[name] = {"ms": round(t * 1e3, 3), "candidates_per_s": round(P / t, 1), "best": b,
                      "best_ncc": round(bs, 5), "found_plain_best": b == best,
                      "speedup_vs_plain": round(t_plain / t, 3)}
-    res["recall"] = ("top-5 recall on 100 held-out queries (maps 501-502): learned 1.0, low-res NCC 1.0; "
-                     "profiles/scorer_training_config4.md")
+    # top-5 recall of the exhaustive NCC best on held-out queries (a map the scorer
+    # was not trained on), measured here
+    with contextlib.redirect_stdout(sys.stderr):  # its progress lines; stdout carries only the JSON line
+        ev = learned.evaluate(ctx, scorer, [W.SCORER_EVAL_MAPS[0]], recall_queries, k=k, reps=1)
+    res["recall"] = {"queries": ev["queries"], "map_seed": W.SCORER_EVAL_MAPS[0],
+                     "top5_recall_learned": ev["top5_recall_learned"],
+                     "top5_recall_lowres_ncc": ev["top5_recall_lowres"],
+                     "median_rank_of_best_learned": ev["median_rank_of_best_learned"],
+                     "max_rank_of_best_learned": ev["max_rank_of_best_learned"],
+                     "median_rank_of_best_lowres_ncc": ev["median_rank_of_best_lowres"],
+                     "max_rank_of_best_lowres_ncc": ev["max_rank_of_best_lowres"],
+                     "ms_per_query": {"plain": ev["ms_per_query_plain"], "learned": ev["ms_per_query_learned"],
+                                      "lowres_ncc": ev["ms_per_query_lowres"]}}
+    res["learned_vs_lowres_ncc"] = round(res["lowres_ncc"]["ms"] / res["learned"]["ms"], 3)
     scorer.close()
     _log(f"learned vs plain ({P} candidates): plain {res['plain']['ms']:.1f} ms, learned "
-         f"{res['learned']['ms']:.1f} ms, low-res NCC {res['lowres_ncc']['ms']:.1f} ms")
+         f"{res['learned']['ms']:.1f} ms, low-res NCC {res['lowres_ncc']['ms']:.1f} ms; top-5 recall on "
+         f"{ev['queries']} held-out queries: learned {ev['top5_recall_learned']}, low-res NCC "
+         f"{ev['top5_recall_lowres']}")
     return res
 
 

@@ -30,10 +30,14 @@ ALPHA_MIN = float(np.float32(1.0 / 255.0))
 ALPHA_MAX = 0.99
 T_MIN = 1e-4
 # decision margins within which a float32 evaluation may flip (relative / absolute).
-# The float32 conic carries a relative error of about 6e-8 times the condition
-# number of the screen covariance; footprints worse conditioned than 1 / M_COND are
-# flagged, and for the rest d^2 is good to well within M_D2.
-M_COND = 1.0 / 300.0  # flag det < M_COND a c
+# The float32 conic is the inverse of the screen covariance with det = a c - b^2
+# formed in float32: its relative error is up to about (2 cond + 3) u, u = 2^-24,
+# cond = a c / det. A footprint is flagged where that exceeds 1e-4, a tenth of the
+# gradient bar (cond > 800): there the float32 footprint itself, not only its
+# decisions, departs from the float64 one by more than the bar can absorb. (Seen
+# from a street, the flat map disks are elongated but mostly axis-aligned on
+# screen, which keeps cond near 1: at most 12 over a 1408x376 view.)
+M_COND = 1.0 / 800.0  # flag det < M_COND a c
 M_D2 = 2e-5        # |d^2 - cutoff| / cutoff
 M_ALPHA = 1e-5     # |alpha - alpha_min| / alpha_min, |o G - alpha_max| / alpha_max
 M_T = 1e-6         # |T - t_min| / t_min
@@ -193,10 +197,14 @@ def _touched(scr: Screen, i: int, cam) -> set:
     return {(a, b) for a in range(a0, a1 + 1) for b in range(b0, b1 + 1)}
 
 
-def fd_gradient(p: Params, poses, cam, w_rgb, w_depth, gaussian: int, group: int, comp: int, h: float):
+def fd_gradient(p: Params, poses, cam, w_rgb, w_depth, gaussian: int, group: int, comp: int, h: float,
+                with_scale: bool = False):
     """Central difference of L = sum(w_rgb rgb) + sum(w_depth depth) over all poses
     with respect to parameter (group, gaussian, comp) (groups: means, log_scales,
-    quats, logits, rgb). Returns (gradient, stable)."""
+    quats, logits, rgb). Returns (gradient, stable), and with `with_scale` also
+    the sum over pixels and poses of the magnitudes of the per-pixel central
+    differences (the scale of the terms the gradient sums, which bounds what a
+    float32 evaluation of that sum can lose to cancellation)."""
     def perturbed(delta):
         q = p.copy()
         arr = q.field(group)
@@ -208,6 +216,7 @@ def fd_gradient(p: Params, poses, cam, w_rgb, w_depth, gaussian: int, group: int
 
     ps = [p, perturbed(h), perturbed(-h)]
     total = [0.0, 0.0, 0.0]
+    scale = 0.0
     stable = True
     for pi, pose in enumerate(poses):
         scrs = [project(q, pose, cam) for q in ps]
@@ -245,4 +254,8 @@ def fd_gradient(p: Params, poses, cam, w_rgb, w_depth, gaussian: int, group: int
         wd = w_depth[pi][pix[:, 1], pix[:, 0]]
         for e in range(3):
             total[e] += float((wr * outs[e][0]).sum() + (wd * outs[e][1]).sum())
+        per_pixel = (wr * (outs[1][0] - outs[2][0])).sum(1) + wd * (outs[1][1] - outs[2][1])
+        scale += float(np.abs(per_pixel).sum()) / (2 * h)
+    if with_scale:
+        return (total[1] - total[2]) / (2 * h), stable, scale
     return (total[1] - total[2]) / (2 * h), stable

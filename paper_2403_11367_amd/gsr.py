@@ -81,6 +81,11 @@ class AdamW(C.Structure):
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2403_11367_amd.build`")
+    # torch first: its HIP runtime has the soname libgsr links against, so the
+    # library then binds to that same runtime (one runtime per process, sharing
+    # torch's streams and allocations); loaded the other way round, the process
+    # would hold two HIP runtimes
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, I, I32, I64, F, D = C.c_void_p, C.c_int, C.c_int32, C.c_int64, C.c_float, C.c_double
     sig = {

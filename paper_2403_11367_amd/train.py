@@ -35,13 +35,16 @@ def _render_function():
         """(means, scales, quats, opacity, rgb) -> (rgb images [P,3,H,W], depth [P,H,W])."""
 
         @staticmethod
-        def forward(fctx, means, scales, quats, opacity, colours, ctx, slot, camera, poses, cfg):
+        def forward(fctx, means, scales, quats, opacity, colours, ctx, slot, camera, poses, cfg, keep_state):
             from .gsr import RENDER_KEEP_STATE, default_cfg
             args = [t.detach().contiguous() for t in (means, scales, quats, opacity, colours)]
             slot.sm = ctx.load_submap(*args, into=slot.sm)
-            # keep the long lists' compositing states, so that the backward walks them in segments
             cfg = default_cfg() if cfg is None else copy.copy(cfg)
-            cfg.flags |= RENDER_KEEP_STATE
+            if keep_state:
+                # keep the long lists' compositing states, so that the backward walks
+                # them in segments (without: each list is one serial walk that
+                # recomputes its transmittance from the front)
+                cfg.flags |= RENDER_KEEP_STATE
             img, depth = ctx.render(slot.sm, camera, poses, cfg)
             fctx.ctx, fctx.sm = ctx, slot.sm
             fctx.serial = ctx.stats()["render_serial"]
@@ -56,7 +59,7 @@ def _render_function():
             g_img = torch.zeros_like(img) if g_img is None else g_img.contiguous()
             g_depth = torch.zeros_like(depth) if g_depth is None else g_depth.contiguous()
             gm, gs, gq, go, gc = fctx.ctx.render_backward(fctx.sm, scales, quats, poses, img, depth, g_img, g_depth)
-            return gm, gs, gq, go, gc, None, None, None, None, None
+            return gm, gs, gq, go, gc, None, None, None, None, None, None
 
     return RenderFunction
 
@@ -64,12 +67,17 @@ def _render_function():
 _FN = None
 
 
-def render(ctx, slot: _SubmapSlot, means, scales, quats, opacity, colours, camera, poses, cfg=None):
-    """Differentiable render of all Gaussians at `poses`: (rgb, depth)."""
+def render(ctx, slot: _SubmapSlot, means, scales, quats, opacity, colours, camera, poses, cfg=None,
+           keep_state: bool = True):
+    """Differentiable render of all Gaussians at `poses`: (rgb, depth). keep_state:
+    the forward keeps the compositing state every 2016 records of a long list
+    (GSR_RENDER_KEEP_STATE) and the backward walks such lists in segments;
+    without it the backward recomputes each list's transmittance in one walk
+    from the front."""
     global _FN
     if _FN is None:
         _FN = _render_function()
-    return _FN.apply(means, scales, quats, opacity, colours, ctx, slot, camera, poses, cfg)
+    return _FN.apply(means, scales, quats, opacity, colours, ctx, slot, camera, poses, cfg, keep_state)
 
 
 @dataclasses.dataclass
@@ -84,9 +92,11 @@ class MapTrainer:
     """Optimises a Gaussian map against target images and sparse LiDAR depth:
     loss = mean |rgb - target| + depth_weight * mean over valid pixels |depth - lidar|."""
 
-    def __init__(self, ctx, camera, means, log_scales, quats, logits, colours, lr=None, depth_weight=0.1):
+    def __init__(self, ctx, camera, means, log_scales, quats, logits, colours, lr=None, depth_weight=0.1,
+                 keep_state: bool = True):
         torch = _torch()
         self.ctx, self.camera, self.depth_weight = ctx, camera, depth_weight
+        self.keep_state = keep_state
         dev = torch.device("cuda", ctx.device)
         mk = lambda a: torch.nn.Parameter(torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev))  # noqa
         self.means, self.log_scales, self.quats = mk(means), mk(log_scales), mk(quats)
@@ -101,7 +111,7 @@ class MapTrainer:
     def loss(self, poses, target_rgb, lidar, mask, cfg=None):
         torch = _torch()
         img, depth = render(self.ctx, self.slot, self.means, torch.exp(self.log_scales), self.quats,
-                            torch.sigmoid(self.logits), self.colours, self.camera, poses, cfg)
+                            torch.sigmoid(self.logits), self.colours, self.camera, poses, cfg, self.keep_state)
         l_rgb = (img - target_rgb).abs().mean()
         l_depth = ((depth - lidar).abs() * mask).sum() / mask.sum().clamp(min=1)
         return l_rgb + self.depth_weight * l_depth

@@ -1,14 +1,24 @@
 """GPU render backward (gsr_render_backward) against float64 central differences
-of the oracle renderer (oracle/render64.py) on the config-0 scene.
+of the oracle renderer (oracle/render64.py).
 
 The loss is a linear functional of the images, L = sum(w_rgb rgb) + sum(w_depth
 depth) with seeded random weights, so its gradient with respect to the images is
 (w_rgb, w_depth). Parameters are those of a map-training step: means, log-scales,
 raw quaternions, opacity logits, colours; the GPU's linear-scale and opacity
-gradients are chained through exp and the sigmoid here. Bar: |g - fd| <= 1e-3
-|fd| + 1e-3 x (median |fd| of the parameter group), over the parameters whose
-central-difference stencil is stable (no change of any pixel's contributing
-list, no decision within a float32 margin of its threshold).
+gradients are chained through exp and the sigmoid here.
+
+Bar, per parameter: |g - fd| <= 1e-3 |fd| + 512 u (1 + cond) S, with u = 2^-24,
+S the sum over pixels of the magnitudes of the parameter's per-pixel central
+differences and cond = a c / det of the Gaussian's screen covariance (largest
+over the poses). The second term is what a float32 evaluation can lose where the
+per-pixel terms cancel (|fd| much smaller than S): each term carries a relative
+error of some hundred u (recomputed transmittance, the colour behind a layer
+taken as a difference of sums, hardware exp2), growing with cond through the
+float32 conic, and the terms are summed in float32. Measured on MI355X the
+largest error is 260 u S (config 0 and oblique disks); where there is no
+cancellation the first term governs. Only parameters whose central-difference
+stencil is stable are checked (no change of any pixel's contributing list, no
+decision within a float32 margin of its threshold).
 """
 import numpy as np
 import pytest
@@ -18,6 +28,50 @@ from helpers import camera, say, to_dev
 from oracle import render64 as R
 
 pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _bar(fd, scale, cond):
+    return 1e-3 * np.abs(fd) + 512.0 * U32 * (1.0 + cond) * scale
+
+
+def _check_rows(rows, label, min_stable=0.5):
+    """rows[name] = [(fd, gpu, stable, scale, cond)]: every stable one within the
+    bar; at least min_stable of each group stable. Returns the stable count."""
+    n = 0
+    for name in GROUPS:
+        if not rows[name]:
+            continue
+        arr = np.array(rows[name], dtype=float)
+        st = arr[:, 2] > 0
+        assert st.mean() >= min_stable, f"{label} {name}: too few stable parameters ({st.sum()}/{len(arr)})"
+        a = arr[st]
+        err = np.abs(a[:, 1] - a[:, 0])
+        tol = _bar(a[:, 0], a[:, 3], a[:, 4])
+        rel = err / np.maximum(np.abs(a[:, 0]), 1e-300)
+        say(f"  {label} {name}: {len(a)} stable of {len(arr)}, max rel error {rel.max():.2e}, max err / (u S) "
+            f"{np.max(err / (U32 * np.maximum(a[:, 3], 1e-300))):.0f}, worst err/bar {np.max(err / tol):.3f}")
+        bad = np.nonzero(err > tol)[0]
+        assert bad.size == 0, f"{label} {name}: {a[bad[:3]]}"
+        n += len(a)
+    return n
+
+
+def _fd_rows(p, poses, cam, w_rgb, w_depth, gpu, gaussians, rows=None):
+    from oracle import render64 as R_
+    rows = rows if rows is not None else {k: [] for k in GROUPS}
+    conds = {}
+    for gi in gaussians:
+        gi = int(gi)
+        conds[gi] = max(float(R_.project(p, ps, cam).cond[gi]) for ps in poses)
+        for k, name in enumerate(GROUPS):
+            for comp in range(WIDTH[name]):
+                fd, stable, scale = R_.fd_gradient(p, poses, cam, w_rgb, w_depth, gi, k, comp, STEPS[name],
+                                                   with_scale=True)
+                got = gpu[name][gi] if gpu[name].ndim == 1 else gpu[name][gi, comp]
+                rows[name].append((fd, got, stable, scale, conds[gi]))
+    return rows
 
 GROUPS = ["means", "log_scales", "quats", "logits", "rgb"]
 STEPS = {"means": 1e-5, "log_scales": 1e-6, "quats": 1e-6, "logits": 1e-6, "rgb": 1e-6}
@@ -68,27 +122,48 @@ def test_backward_matches_central_differences_config0(ctx):
     inside = scr.visible & (scr.rect[:, 1] > 0) & (scr.rect[:, 0] < cam.width) & (scr.rect[:, 3] > 0) & \
         (scr.rect[:, 2] < cam.height) & (area > 4.0)
     pick = rng.choice(np.nonzero(inside)[0], 30, replace=False)
-    rows = {k: [] for k in GROUPS}
-    for gi in pick:
-        for k, name in enumerate(GROUPS):
-            for comp in range(WIDTH[name]):
-                fd, stable = R.fd_gradient(p, poses, cam, w_rgb, w_depth, int(gi), k, comp, STEPS[name])
-                got = gpu[name][gi] if gpu[name].ndim == 1 else gpu[name][gi, comp]
-                rows[name].append((fd, got, stable))
-    n_stable = 0
-    for name in GROUPS:
-        arr = np.array([(f, g) for f, g, st in rows[name] if st])
-        n_stable += len(arr)
-        assert len(arr) >= 0.5 * len(rows[name]), f"{name}: too few stable parameters"
-        scale = np.median(np.abs(arr[:, 0]))
-        err = np.abs(arr[:, 1] - arr[:, 0])
-        tol = 1e-3 * np.abs(arr[:, 0]) + 1e-3 * scale
-        rel = err / np.maximum(np.abs(arr[:, 0]), 1e-30)
-        say(f"  {name}: {len(arr)} stable of {len(rows[name])}, median |fd| {scale:.3e}, max relative error "
-            f"{np.max(rel[np.abs(arr[:, 0]) > scale]) if np.any(np.abs(arr[:, 0]) > scale) else 0:.2e}, "
-            f"worst err/tol {np.max(err / tol):.3f}")
-        assert np.all(err <= tol), name
-    assert n_stable >= 200
+    rows = _fd_rows(p, poses, cam, w_rgb, w_depth, gpu, pick)
+    assert _check_rows(rows, "config0") >= 200
+
+
+def test_backward_oblique_thin_disks(ctx):
+    """Map-training layout: flat disks (in-plane log-scale N(-2.5, 0.4), normal
+    N(-4, 0.3)) on the ground and two facades of a 30 m corridor, seen from 1.5 m
+    above the ground along it (ground disks at grazing angles: thin, elongated
+    footprints), 2 poses at 160x64."""
+    g = W.corridor_map(6000, seed=3, length=30.0)
+    cam = W.Camera(160, 64, 70.0, 70.0, 80.0, 32.0)
+    poses = np.stack([W.pose_from_center(np.array([1.0, 0.5, 1.5]), W.AXES_ALONG_X, 0.0),
+                      W.pose_from_center(np.array([2.0, -0.5, 1.4]), W.AXES_ALONG_X, np.deg2rad(4.0))]
+                     ).astype(np.float32)
+    rng = np.random.default_rng(78)
+    w_rgb = rng.normal(size=(2, 3, cam.height, cam.width)).astype(np.float32).astype(np.float64)
+    w_depth = (0.1 * rng.normal(size=(2, cam.height, cam.width))).astype(np.float32).astype(np.float64)
+    say("render backward: oblique thin disks (corridor layout), 2 poses, 30 sampled Gaussians")
+    gm, gs, gq, go, gc = _gpu_grads(ctx, g, poses, cam, w_rgb, w_depth)
+    p = R.as_params(g)
+    s = np.exp(p.log_scales)
+    o = 1.0 / (1.0 + np.exp(-p.logits))
+    gpu = {"means": gm, "log_scales": gs * s, "quats": gq, "logits": go * o * (1 - o), "rgb": gc}
+    scr = R.project(p, poses[0], cam)
+    area = (scr.rect[:, 1] - scr.rect[:, 0]) * (scr.rect[:, 3] - scr.rect[:, 2])
+    inside = scr.visible & (scr.rect[:, 1] > 0) & (scr.rect[:, 0] < cam.width) & (scr.rect[:, 3] > 0) & \
+        (scr.rect[:, 2] < cam.height) & (area > 4.0)
+    # footprints: elongated (eigenvalue ratio of the screen covariance)
+    det_c = scr.conic[:, 0] * scr.conic[:, 2] - scr.conic[:, 1] ** 2
+    cov = np.stack([scr.conic[:, 2], -scr.conic[:, 1], scr.conic[:, 0]], 1) / det_c[:, None]
+    tr, dt = cov[:, 0] + cov[:, 2], cov[:, 0] * cov[:, 2] - cov[:, 1] ** 2
+    disc = np.sqrt(np.maximum(tr * tr / 4 - dt, 0))
+    ratio = (tr / 2 + disc) / np.maximum(tr / 2 - disc, 1e-30)
+    cand = np.nonzero(inside)[0]
+    say(f"  {cand.size} footprints in view; eigenvalue ratio median {np.median(ratio[cand]):.1f}, 90% "
+        f"{np.percentile(ratio[cand], 90):.1f}; a c / det max {scr.cond[cand].max():.2f}")
+    # half the sample among the most elongated footprints
+    elong = cand[np.argsort(-ratio[cand])][:200]
+    pick = np.concatenate([rng.choice(elong, 15, replace=False),
+                           rng.choice(np.setdiff1d(cand, elong), 15, replace=False)])
+    rows = _fd_rows(p, poses, cam, w_rgb, w_depth, gpu, pick)
+    assert _check_rows(rows, "oblique disks") >= 200
 
 
 def test_backward_is_independent_of_pose_groups(ctx):
@@ -156,16 +231,8 @@ def test_backward_with_alpha_and_jacobian_clamps(ctx):
     s = np.exp(p.log_scales)
     o = 1.0 / (1.0 + np.exp(-p.logits))
     gpu = {"means": gm, "log_scales": gs * s, "quats": gq, "logits": go * o * (1 - o), "rgb": gc}
-    n_checked = 0
-    for gi in range(4):
-        for k, name in enumerate(GROUPS):
-            for comp in range(WIDTH[name]):
-                fd, stable = R.fd_gradient(p, poses, cam, w_rgb, w_depth, gi, k, comp, STEPS[name])
-                if not stable:
-                    continue
-                got = gpu[name][gi] if gpu[name].ndim == 1 else gpu[name][gi, comp]
-                n_checked += 1
-                assert abs(got - fd) <= 1e-3 * abs(fd) + 1e-5, (gi, name, comp, got, fd)
+    rows = _fd_rows(p, poses, cam, w_rgb, w_depth, gpu, range(4))
+    n_checked = _check_rows(rows, "clamps", min_stable=0.0)
     say(f"  {n_checked} stable parameters checked")
     assert n_checked >= 30
 
@@ -229,22 +296,8 @@ def test_backward_splits_long_lists_at_kept_states(ctx):
     # the farther half by depth: about 2400 or more records into their tiles' lists
     vis = np.nonzero(scr.visible)[0]
     deep = vis[np.argsort(scr.z[vis], kind="stable")][4000:]
-    rows = {k: [] for k in GROUPS}
-    for gi in rng.choice(deep, 24, replace=False):
-        for k, name in enumerate(GROUPS):
-            for comp in range(WIDTH[name]):
-                fd, stable = R.fd_gradient(p, poses, cam, w_rgb, w_depth, int(gi), k, comp, STEPS[name])
-                if stable:
-                    rows[name].append((fd, gpu[name][gi] if gpu[name].ndim == 1 else gpu[name][gi, comp]))
-    n_checked = 0
-    for name in GROUPS:
-        arr = np.array(rows[name]).reshape(-1, 2)
-        n_checked += len(arr)
-        scale = np.median(np.abs(arr[:, 0]))
-        err = np.abs(arr[:, 1] - arr[:, 0])
-        tol = 1e-3 * np.abs(arr[:, 0]) + 1e-3 * scale
-        say(f"  {name}: {len(arr)} stable, median |fd| {scale:.3e}, worst err/tol {np.max(err / tol):.3f}")
-        assert np.all(err <= tol), name
+    rows = _fd_rows(p, poses, cam, w_rgb, w_depth, gpu, rng.choice(deep, 24, replace=False))
+    n_checked = _check_rows(rows, "long lists", min_stable=0.0)
     assert n_checked >= 100
     sm.free()
 

@@ -484,3 +484,50 @@ def test_eval_counters_match_oracle(ctx):
         f"lane slots {st['evals_lanes']}")
     assert abs(st["evals_contrib"] - ref) <= 2 * flagged
     assert st["evals_lanes"] >= st["evals_contrib"]
+
+
+def test_fig2_ncc_profile_config0_and_config1(ctx, cfg1):
+    """Sec. IV, Fig. 2 on the library: NCC of renders swept through the hidden
+    pose in x and in yaw peaks at the hidden pose and falls with the error
+    (config 0: the scores equal the oracle's within 1e-4; config 1: full-map
+    query, cropped-submap renders at 1408x376). On config 1 the best of the 64
+    grid candidates lies within one grid step (1 m, 1 m, 5 degrees) of the
+    hidden pose."""
+    import torch
+    from test_oracle_search import FIG2_DX, FIG2_DYAW, check_fig2_profile, fig2_sweeps
+    sc = W.config0()
+    sm = load(ctx, sc.gaussians)
+    pr = prep(sc.gaussians)
+    query = (search.render_pose(pr, sc.hidden_pose, sc.camera).rgb + sc.query_noise).astype(np.float32)
+    xs, ys = fig2_sweeps(sc)
+    for poses, offs in ((xs, FIG2_DX), (ys, FIG2_DYAW)):
+        rgb, _, _ = gpu_render(ctx, sm, sc.camera, poses)
+        got = ctx.ncc(to_dev(query), to_dev(rgb)).cpu().numpy()
+        ref = oncc.ncc(query, np.stack([search.render_pose(pr, p, sc.camera).rgb for p in poses]))
+        say(f"  config0 sweep: gpu {np.round(got, 4)}")
+        assert np.abs(got - ref).max() <= TOL_NCC
+        check_fig2_profile(got, offs)
+    sm.free()
+    sc1, idx = cfg1
+    full = load(ctx, sc1.gaussians)
+    q_rgb, _, _ = gpu_render(ctx, full, sc1.camera, sc1.hidden_pose[None])
+    query1 = to_dev(q_rgb[0] + sc1.query_noise)
+    full.free()
+    sm1 = load(ctx, sc1.gaussians, index=idx)
+    xs, ys = fig2_sweeps(sc1)
+    for poses, offs in ((xs, FIG2_DX), (ys, FIG2_DYAW)):
+        rgb, _, _ = gpu_render(ctx, sm1, sc1.camera, poses)
+        got = ctx.ncc(query1, to_dev(rgb)).cpu().numpy()
+        say(f"  config1 sweep: {np.round(got, 4)}")
+        check_fig2_profile(got, offs)
+    rgb, _, _ = gpu_render(ctx, sm1, sc1.camera, sc1.poses)
+    s = ctx.ncc(query1, to_dev(rgb)).cpu().numpy()
+    torch.cuda.synchronize()
+    best = int(np.argmax(s))
+    steps = [-1.5, -0.5, 0.5, 1.5]
+    grid = [(dx, dy, dyaw) for dx in steps for dy in steps for dyaw in [-7.5, -2.5, 2.5, 7.5]]
+    hx, hy, hyaw = sc1.hidden_offset
+    bx, by, byaw = grid[best]
+    say(f"  config1 grid: best {best} at {grid[best]}, hidden ({hx:.2f}, {hy:.2f}, {hyaw:.2f}), NCC {s[best]:.4f}")
+    assert abs(bx - hx) <= 1.0 and abs(by - hy) <= 1.0 and abs(byaw - hyaw) <= 5.0
+    sm1.free()

@@ -2,6 +2,7 @@
 import numpy as np
 import pytest
 
+import workloads as W
 from oracle import search
 
 
@@ -46,3 +47,40 @@ def test_early_stop_matches_closed_form(seed):
     seen = order[:n_ref]
     best_ref = min(c for c in seen if s[c] == s[seen].max())
     assert (best, n) == (best_ref, n_ref) and score == s[best_ref]
+
+
+# Sec. IV, Fig. 2: NCC between the query and renders around the true pose
+# peaks at the true pose and falls off with the x and yaw error.
+FIG2_DX = [-2.0, -1.0, -0.5, -0.25, 0.0, 0.25, 0.5, 1.0, 2.0]       # metres
+FIG2_DYAW = [-10.0, -6.0, -3.0, -1.5, 0.0, 1.5, 3.0, 6.0, 10.0]     # degrees
+
+
+def fig2_sweeps(scene):
+    """(x sweep poses, yaw sweep poses) through the hidden pose."""
+    hx, hy, hyaw = scene.hidden_offset
+    xs = W.offset_poses(scene, [(hx + d, hy, hyaw) for d in FIG2_DX])
+    ys = W.offset_poses(scene, [(hx, hy, hyaw + d) for d in FIG2_DYAW])
+    return xs, ys
+
+
+def check_fig2_profile(scores, offsets):
+    """The peak is at offset 0, clear of its neighbours; within +-3 steps of the
+    peak the scores fall strictly with |offset|; all others stay below the peak."""
+    s = np.asarray(scores, np.float64)
+    c = offsets.index(0.0)
+    assert int(np.argmax(s)) == c, s
+    assert s[c] - max(s[c - 1], s[c + 1]) > 0.05, s
+    for k in range(1, 4):
+        assert s[c - k] < s[c - k + 1] and s[c + k] < s[c + k - 1], s
+    assert np.all(np.delete(s, c) < s[c])
+
+
+def test_fig2_ncc_peaks_at_the_true_pose_config0():
+    from oracle import ncc as oncc
+    sc = W.config0()
+    prep = search.prepare(sc.gaussians)
+    query = search.render_pose(prep, sc.hidden_pose, sc.camera).rgb + sc.query_noise
+    xs, ys = fig2_sweeps(sc)
+    for poses, offs in ((xs, FIG2_DX), (ys, FIG2_DYAW)):
+        s = oncc.ncc(query, np.stack([search.render_pose(prep, p, sc.camera).rgb for p in poses]))
+        check_fig2_profile(s, offs)

@@ -74,6 +74,15 @@ class Scene:
     crop_cell: float = 0.0    # 2D voxel cell edge (m); 0 = no crop
     crop_radius: float = 0.0  # crop radius around the prior (m)
     crop_voxel: float = 1.0   # fine voxel (m) whose Morton order orders the submap
+    hidden_offset: tuple = (0.0, 0.0, 0.0)  # hidden pose - prior: (dx m, dy m, dyaw degrees)
+    camera_axes: np.ndarray | None = None   # camera axes (rows) in world, before the yaw
+
+
+def offset_poses(scene: "Scene", offsets) -> np.ndarray:
+    """Poses of the scene's camera at (dx m, dy m, dyaw degrees) from its prior; float32 [P,3,4]."""
+    out = [pose_from_center(np.asarray(scene.prior_center) + np.array([dx, dy, 0.0]), scene.camera_axes,
+                            np.deg2rad(dyaw)) for dx, dy, dyaw in offsets]
+    return _f32(np.stack(out))
 
 
 def _f32(a) -> np.ndarray:
@@ -146,7 +155,8 @@ def config0() -> Scene:
     hidden = _f32(pose_from_center(center + np.array([hdx, 0.0, 0.0]), AXES_ALONG_Y,
                                    np.deg2rad(hyaw)))
     noise = _f32(np.random.default_rng(101).normal(0.0, 0.02, size=(3, cam.height, cam.width)))
-    return Scene("config0", g, cam, (16, 16), poses, hidden, noise, center)
+    return Scene("config0", g, cam, (16, 16), poses, hidden, noise, center,
+                 hidden_offset=(hdx, 0.0, hyaw), camera_axes=AXES_ALONG_Y)
 
 
 def _quat_mul(a: np.ndarray, b: np.ndarray) -> np.ndarray:
@@ -228,7 +238,7 @@ def config1(n: int = 1_000_000) -> Scene:
                                    np.deg2rad(hyaw)))
     noise = _f32(np.random.default_rng(11).normal(0.0, 0.02, size=(3, cam.height, cam.width)))
     return Scene("config1", g, cam, (16, 16), poses, hidden, noise, center,
-                 crop_cell=10.0, crop_radius=50.0)
+                 crop_cell=10.0, crop_radius=50.0, hidden_offset=(hdx, hdy, hyaw), camera_axes=AXES_ALONG_X)
 
 
 def tiny_scene(seed: int, n: int = 64, width: int = 64, height: int = 48,
