@@ -50,11 +50,36 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found; install ROCm or set HIPCC")
 
 
-def _compile(src: str, kind: str, extra: list) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+# Host AddressSanitizer build (libgsr_asan.so, for the CPU tests of the host code):
+# the HIP sources instrument their host pass only, and the host-only source is
+# built with the same clang so that one ASan runtime serves the library.
+ASAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+BUILD_ASAN = os.path.join(PKG, "_build_asan")
+LIB_ASAN = os.path.join(PKG, "libgsr_asan.so")
+
+
+def _clangxx() -> str:
+    return os.path.join(os.path.dirname(os.path.realpath(_hipcc())), "..", "lib", "llvm", "bin", "clang++")
+
+
+def asan_runtime() -> str:
+    """Path of the clang ASan runtime that libgsr_asan.so needs preloaded."""
+    import glob
+    llvm = os.path.realpath(os.path.join(os.path.dirname(os.path.realpath(_hipcc())), "..", "lib", "llvm"))
+    hits = sorted(glob.glob(os.path.join(llvm, "lib", "clang", "*", "lib", "linux", "libclang_rt.asan-x86_64.so")))
+    if not hits:
+        raise RuntimeError("clang ASan runtime not found")
+    return hits[-1]
+
+
+def _compile(src: str, kind: str, extra: list, asan: bool = False) -> str:
+    obj = os.path.join(BUILD_ASAN if asan else BUILD, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
     if kind == "hip":
-        cmd = [_hipcc(), *HIP_FLAGS, *extra, "-c", path, "-o", obj]
+        cmd = [_hipcc(), *HIP_FLAGS, *extra, *(ASAN_HOST if asan else []), "-c", path, "-o", obj]
+    elif asan:
+        cmd = [os.path.realpath(_clangxx()), "-O1", "-g", "-std=c++17", "-fPIC", "-Wall", "-fsanitize=address",
+               "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "include"), "-c", path, "-o", obj]
     else:
         cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"),
                "-c", path, "-o", obj]
@@ -68,20 +93,22 @@ def _compile(src: str, kind: str, extra: list) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, asan: bool = False) -> str:
+    """Build libgsr.so, or with asan the host-instrumented libgsr_asan.so."""
+    out_dir, lib = (BUILD_ASAN, LIB_ASAN) if asan else (BUILD, LIB)
+    os.makedirs(out_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(lambda s: _compile(*s), SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+        objs = list(ex.map(lambda s: _compile(*s, asan=asan), SOURCES))
+    tmp = lib + ".tmp"
+    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, *(ASAN_HOST if asan else []), "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, asan="--asan" in sys.argv)

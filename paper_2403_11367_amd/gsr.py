@@ -17,7 +17,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgsr.so")
+# GSR_LIB selects another build of the library (the host-sanitised one in the CPU tests)
+LIB_PATH = os.environ.get("GSR_LIB") or os.path.join(_HERE, "libgsr.so")
 
 GSR_OK = 0
 STATUS = {0: "GSR_OK", -1: "GSR_EINVAL", -2: "GSR_ENOMEM", -3: "GSR_EHIP", -4: "GSR_ENODEV",
