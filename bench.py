@@ -151,6 +151,8 @@ def main():
     ap.add_argument("--cpu-candidates", type=int, default=2, help="oracle sample size (0 = skip)")
     ap.add_argument("--pose-groups", type=int, default=0,
                     help="pose groups per render (0 = the library's automatic choice)")
+    ap.add_argument("--tile", type=int, nargs=2, default=(16, 16), metavar=("W", "H"),
+                    help="screen tile of the headline renders: 16 16, 32 8 or 8 32")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-queries leg")
     ap.add_argument("--no-training", action="store_true", help="skip the map-training leg")
@@ -192,11 +194,13 @@ def main():
 
     # one counting render (untimed): exact pair total and evaluation counts of this workload
     sm = ctx.load_submap(*gmap, index=idx_t)
-    ctx.render(sm, cam, poses_t, default_cfg(flags=RENDER_COUNT_EVALS, pose_groups=args.pose_groups))
+    tw, th = args.tile
+    ctx.render(sm, cam, poses_t, default_cfg(flags=RENDER_COUNT_EVALS, pose_groups=args.pose_groups, tile_w=tw,
+                                             tile_h=th))
     st0 = ctx.stats()
     n_pairs, n_vis, n_groups = st0["n_pairs"], st0["n_visible"], st0["n_groups"]
     # fixed capacity (it bounds each pose group): no host wait per step
-    cfg = default_cfg(pair_capacity=int(n_pairs * 1.05) + 4096, pose_groups=args.pose_groups)
+    cfg = default_cfg(pair_capacity=int(n_pairs * 1.05) + 4096, pose_groups=args.pose_groups, tile_w=tw, tile_h=th)
     rgb = torch.empty((P, 3, H, Wd), dtype=torch.float32, device=dev)
     depth = torch.empty((P, H, Wd), dtype=torch.float32, device=dev)
     scores = torch.empty((P,), dtype=torch.float32, device=dev)
@@ -271,7 +275,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "config1: 1M-Gaussian street-corridor map, 10 m voxel / 50 m crop "
                                f"({n_c} Gaussians), {P} candidate poses, {Wd}x{H}, full-res NCC, top-1",
-                   "global_batch": P, "parallelism": "single GPU",
+                   "global_batch": P, "parallelism": "single GPU", "tile": f"{tw}x{th}",
                    "path": "plain: every candidate rendered at full resolution and NCC-scored"},
         "pixels_per_s": round(cand_s * px, 1),
         "step_ms": {"mean": round(ms_step, 4), "median": round(med_ms, 4), "min": round(step_ms[0], 4),
@@ -316,12 +320,25 @@ def main():
     ctx.close()
 
 
+def _with(cfg, **over):
+    """A copy of a render configuration with some fields replaced."""
+    from paper_2403_11367_amd import default_cfg
+    c = default_cfg(**{f: getattr(cfg, f) for f, _ in cfg._fields_})
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c
+
+
 def batched_leg(ctx, cam, dev, reps=5):
     """Batched queries: 8 corridor maps of uneven size (batch_query seeds 200-207,
     cropped like config 1), 32 candidates each, full-resolution NCC and top-1 per
-    query. Times 8 separate renders against one batched render (launch variant
-    picked by the autotuner) and its HIP-graph replay; all three must give the
-    same images."""
+    query. The queries are grouped by submap-size bucket (powers of two); the
+    autotuner picks tile shape, LDS chunk, grid or persistent launch and pose
+    groups per bucket, and each bucket renders as one batched render. Times 8
+    separate default renders, the per-bucket batched renders and their HIP-graph
+    replay. The batched images equal separate renders with the same settings bit
+    for bit; against the default 16x16 renders they differ within float32
+    rounding where a bucket chose another tile shape (reported)."""
     import numpy as np
     import torch
 
@@ -340,6 +357,10 @@ def batched_leg(ctx, cam, dev, reps=5):
         idx = crop(q.gaussians.means, 10.0, (100.0, 0.0), 50.0, 1.0)
         sms.append(ctx.load_submap(*arrs, index=torch.as_tensor(idx, device=dev)))
         del arrs
+    # queries ordered by submap-size bucket (stable), so each bucket's poses are contiguous
+    bucket_of = [autotune.size_bucket(sm.n) for sm in sms]
+    order = sorted(range(len(qs)), key=lambda i: bucket_of[i])
+    qs, sms, queries, bucket_of = ([x[i] for i in order] for x in (qs, sms, queries, bucket_of))
     counts = [q.poses.shape[0] for q in qs]
     P = sum(counts)
     poses = torch.as_tensor(np.concatenate([q.poses for q in qs]), device=dev)
@@ -349,33 +370,61 @@ def batched_leg(ctx, cam, dev, reps=5):
     depth = torch.empty((P, H, Wd), device=dev)
     scores = torch.empty((P,), device=dev)
     best = torch.empty((len(qs),), dtype=torch.int32, device=dev)
-    # fixed pair capacities from one exact render per query (no host wait when timed)
+    # fixed pair capacities (no host wait when timed): the largest exact count over
+    # the tile shapes the autotuner tries
     caps = []
     for i, sm in enumerate(sms):
-        ctx.render(sm, cam, poses[starts[i]:starts[i + 1]].contiguous())
-        caps.append(int(ctx.stats()["n_pairs"] * 1.05) + 4096)
-    _log(f"batched: {len(qs)} queries, maps {[q.n for q in qs]}, crops {[sm.n for sm in sms]}, "
-         f"setup {time.perf_counter() - t_setup:.1f} s")
+        n_max = 0
+        for tw, th in autotune.TILES:
+            ctx.render(sm, cam, poses[starts[i]:starts[i + 1]].contiguous(), default_cfg(tile_w=tw, tile_h=th))
+            n_max = max(n_max, ctx.stats()["n_pairs"])
+        caps.append(int(n_max * 1.05) + 4096)
+    buckets = sorted(set(bucket_of))
+    groups = [[i for i in range(len(qs)) if bucket_of[i] == b] for b in buckets]
+    _log(f"batched: {len(qs)} queries, maps {[q.n for q in qs]}, crops {[sm.n for sm in sms]}, buckets "
+         f"{[(b, len(g)) for b, g in zip(buckets, groups)]}, setup {time.perf_counter() - t_setup:.1f} s")
 
     def scored(i):
         a, b = int(starts[i]), int(starts[i + 1])
         ctx.ncc(queries[i], rgb[a:b], scores[a:b])
         ctx.topk(scores[a:b], 1, out=best[i:i + 1])
 
-    def separate():
+    def separate(cfg_of=None):
         for i, sm in enumerate(sms):
             a, b = int(starts[i]), int(starts[i + 1])
-            ctx.render(sm, cam, poses[a:b].contiguous(), default_cfg(pair_capacity=caps[i]), rgb=rgb[a:b],
-                       depth=depth[a:b])
+            cfg = default_cfg(pair_capacity=caps[i]) if cfg_of is None else cfg_of(i)
+            ctx.render(sm, cam, poses[a:b].contiguous(), cfg, rgb=rgb[a:b], depth=depth[a:b])
             scored(i)
 
-    base = default_cfg(pair_capacity=sum(caps))
-    key = autotune.workload_key(torch.cuda.get_device_name(dev), Wd, H, P, max(sm.n for sm in sms))
-    tuned, record = autotune.tune(key, base, lambda cfg: ctx.render_multi(sms, counts, cam, poses, cfg,
-                                                                          rgb=rgb, depth=depth))
+    def span(g):
+        return int(starts[g[0]]), int(starts[g[-1] + 1])
+
+    tuned, records, keys = [], [], []
+    for b, g in zip(buckets, groups):
+        a0, a1 = span(g)
+        key = autotune.workload_key(torch.cuda.get_device_name(dev), Wd, H, a1 - a0, b)
+        base = default_cfg(pair_capacity=sum(caps[i] for i in g))
+        cfg, record = autotune.tune(key, base, lambda cfg, g=g, a0=a0, a1=a1: ctx.render_multi(
+            [sms[i] for i in g], [counts[i] for i in g], cam, poses[a0:a1], cfg, rgb=rgb[a0:a1], depth=depth[a0:a1]))
+        tuned.append(cfg)
+        records.append(record)
+        keys.append(key)
+
+    # for comparison: the whole batch as one render with one tuned setting (key: largest submap)
+    key_one = autotune.workload_key(torch.cuda.get_device_name(dev), Wd, H, P, max(sm.n for sm in sms))
+    tuned_one, record_one = autotune.tune(key_one, default_cfg(pair_capacity=sum(caps)), lambda cfg: ctx.render_multi(
+        sms, counts, cam, poses, cfg, rgb=rgb, depth=depth))
+
+    def batched_one():
+        ctx.render_multi(sms, counts, cam, poses, tuned_one, rgb=rgb, depth=depth)
+        for i in range(len(qs)):
+            scored(i)
 
     def batched():
-        ctx.render_multi(sms, counts, cam, poses, tuned, rgb=rgb, depth=depth)
+        for g, cfg in zip(groups, tuned):
+            a0, a1 = span(g)
+            ctx.render_multi([sms[i] for i in g], [counts[i] for i in g], cam, poses[a0:a1], cfg, rgb=rgb[a0:a1],
+                             depth=depth[a0:a1])
         for i in range(len(qs)):
             scored(i)
 
@@ -389,9 +438,20 @@ def batched_leg(ctx, cam, dev, reps=5):
         return (time.perf_counter() - t0) / reps
 
     t_sep = timed(separate)
+    ref_default = (rgb.clone(), depth.clone(), scores.clone(), best.clone())
+    group_of = {i: k for k, g in enumerate(groups) for i in g}
+
+    def cfg_same(i):  # query i rendered alone with its bucket's tuned settings
+        return _with(tuned[group_of[i]], pair_capacity=caps[i], pose_groups=1)
+
+    separate(cfg_same)
+    torch.cuda.synchronize()
     ref = (rgb.clone(), depth.clone(), scores.clone(), best.clone())
     t_bat = timed(batched)
     same_batched = all(torch.equal(a, b) for a, b in zip((rgb, depth, scores, best), ref))
+    diff_default = {"max_abs_rgb": float((rgb - ref_default[0]).abs().max()),
+                    "max_abs_score": float((scores - ref_default[2]).abs().max()),
+                    "same_best": bool(torch.equal(best, ref_default[3]))}
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         batched()
@@ -405,22 +465,49 @@ def batched_leg(ctx, cam, dev, reps=5):
         same_graph = all(torch.equal(a, b) for a, b in zip((rgb, depth, scores, best), ref))
         t_graph = timed(graph.launch)
         graph.close()
+        # the single-setting batch and its graph
+        separate(lambda i: _with(tuned_one, pair_capacity=caps[i], pose_groups=1))
+        stream.synchronize()
+        ref_one = (rgb.clone(), depth.clone(), scores.clone(), best.clone())
+        t_one = timed(batched_one)
+        same_one = all(torch.equal(a, b) for a, b in zip((rgb, depth, scores, best), ref_one))
+        ctx.capture_begin()
+        batched_one()
+        graph = ctx.capture_end()
+        rgb.zero_()
+        graph.launch()
+        stream.synchronize()
+        same_one_graph = all(torch.equal(a, b) for a, b in zip((rgb, depth, scores, best), ref_one))
+        t_one_graph = timed(graph.launch)
+        graph.close()
     ctx.sync()
+    knobs = ("tile_w", "tile_h", "blend_chunk", "blend_blocks_per_cu", "pose_groups")
     res = {"queries": len(qs), "poses_per_query": counts[0], "renders": P,
            "map_gaussians": [q.n for q in qs], "submap_gaussians": [sm.n for sm in sms],
            "separate": {"ms": round(t_sep * 1e3, 3), "renders_per_s": round(P / t_sep, 1)},
            "batched": {"ms": round(t_bat * 1e3, 3), "renders_per_s": round(P / t_bat, 1),
-                       "identical_to_separate": bool(same_batched)},
+                       "identical_to_separate_same_settings": bool(same_batched),
+                       "against_default_separate": diff_default},
            "graph": {"ms": round(t_graph * 1e3, 3), "renders_per_s": round(P / t_graph, 1),
-                     "identical_to_separate": bool(same_graph)},
-           "autotune": {"key": key, "chosen": {f: getattr(tuned, f) for f in
-                                               ("blend_chunk", "blend_blocks_per_cu", "pose_groups")},
-                        "variants_ms": record.get("variants", "cached")},
+                     "identical_to_separate_same_settings": bool(same_graph)},
+           "one_batch_one_setting": {
+               "key": key_one, "chosen": {f: getattr(tuned_one, f) for f in knobs},
+               "ms": round(t_one * 1e3, 3), "renders_per_s": round(P / t_one, 1),
+               "graph_ms": round(t_one_graph * 1e3, 3), "graph_renders_per_s": round(P / t_one_graph, 1),
+               "identical_to_separate_same_settings": bool(same_one and same_one_graph)},
+           "autotune": [{"key": k, "bucket": b, "queries": len(g),
+                         "chosen": {f: getattr(c, f) for f in knobs},
+                         "launch": "persistent queue" if c.blend_blocks_per_cu > 0 else "grid",
+                         "variants_ms": r.get("variants", "cached")[:6] if r else "cached"}
+                        for k, b, g, c, r in zip(keys, buckets, groups, tuned, records)],
            "best_per_query": best.cpu().tolist()}
     for sm in sms:
         sm.free()
-    _log(f"batched: separate {res['separate']['ms']:.2f} ms, batched {res['batched']['ms']:.2f} ms, graph "
-         f"{res['graph']['ms']:.2f} ms for {P} renders; chosen {res['autotune']['chosen']}")
+    _log(f"batched: separate {res['separate']['ms']:.2f} ms, per-bucket batched {res['batched']['ms']:.2f} ms, "
+         f"graph {res['graph']['ms']:.2f} ms for {P} renders; chosen per bucket "
+         f"{[(a['bucket'], a['chosen']) for a in res['autotune']]}; one batch, one setting "
+         f"{res['one_batch_one_setting']['ms']:.2f} ms, graph {res['one_batch_one_setting']['graph_ms']:.2f} ms, "
+         f"chosen {res['one_batch_one_setting']['chosen']}")
     return res
 
 

@@ -75,7 +75,9 @@ typedef struct {
 
 /* Render constants. gsr_default_cfg fills the defaults given in brackets. */
 typedef struct {
-    int32_t tile_w, tile_h;  /* screen tile in pixels [16, 16]; this library: 16 x 16 */
+    int32_t tile_w, tile_h;  /* screen tile in pixels [16, 16]: 16 x 16, 32 x 8 or 8 x 32 (else
+                              * GSR_EUNSUPPORTED); the tile lists and so the images depend on it
+                              * within float32 rounding of the compositing */
     float eps_dilate;        /* screen-covariance dilation, px^2 [0.3] */
     float z_near;            /* near plane, metres; cull unless t_z > z_near [0.2] */
     float jac_clamp;         /* Jacobian point clamp, x of half field of view [1.3] */

@@ -1,4 +1,5 @@
-// Front-to-back compositing of colour and depth per 16x16 tile (S5).
+// Front-to-back compositing of colour and depth per tile (S5): 16x16 tiles by
+// default, 32x8 and 8x32 as options.
 //
 // Paper: Sec. III-A, Eq. 1 and Eq. 5 with the footprint of Eq. 2:
 //   C(x) = sum_i c_i a_i T_i,  D(x) = sum_i z_i a_i T_i,  T_i = prod_{j<i} (1 - a_j),
@@ -127,7 +128,7 @@ __device__ __forceinline__ void quarter_sums(float (&v)[kScreenGrads]) {
 // The compositing of one (tile, pose) by the whole block, or (kGrad) its
 // backward: the same walk, so the same pixels visit the same records in the
 // same order and recompute the forward's T bit for bit.
-template <bool kCount, int kStage, bool kGrad = false, bool kKeep = false>
+template <int kTW, bool kCount, int kStage, bool kGrad = false, bool kKeep = false>
 __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__restrict__ records, int64_t n,
                                            const uint32_t *__restrict__ pairs,
                                            const uint64_t *__restrict__ offsets, uint64_t capacity, int width,
@@ -158,12 +159,17 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int quarter = lane >> 4;
-    const int pi = tx * 16 + quarter * 4 + (lane & 3);
-    const int pj = ty * 16 + wave * 4 + ((lane >> 2) & 3);
+    // tile of kTW x kTH pixels; wave w owns rows kBH w .. kBH w + kBH - 1 (a band of 64
+    // pixels), split into four cells of kCW x kBH (16 lanes each, row-major inside)
+    constexpr int kTH = kThreads / kTW, kBH = 64 / kTW, kCW = kTW / 4;
+    static_assert(kTW == 8 || kTW == 16 || kTW == 32, "8x32, 16x16 or 32x8 tiles");
+    const int pi = tx * kTW + quarter * kCW + ((lane & 15) % kCW);
+    const int pj = ty * kTH + wave * kBH + ((lane & 15) / kCW);
     const bool in_image = pi < width && pj < height;
-    const int row0 = ty * 16, col0 = tx * 16;
-    // pixel centre relative to the tile centre (col0 + 8, row0 + 8), exact
-    const float xc = (float)(pi - col0) - 7.5f, yc = (float)(pj - row0) - 7.5f;
+    const int row0 = ty * kTH, col0 = tx * kTW;
+    // pixel centre relative to the tile centre (col0 + kTW / 2, row0 + kTH / 2), exact
+    const float xc = (float)(pi - col0) - (0.5f * (float)kTW - 0.5f);
+    const float yc = (float)(pj - row0) - (0.5f * (float)kTH - 0.5f);
 
     const uint64_t list = (uint64_t)pose * n_tiles + tile;
     const uint64_t beg = offsets[list];
@@ -264,7 +270,8 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             const float det = conic_det(A, B, C);
             const float iA = __builtin_amdgcn_rcpf(A), idet = __builtin_amdgcn_rcpf(det);
             const float u_rel = q0.x - (float)col0, v_rel = q0.y - (float)row0;
-            const float uc = q0.x - (float)(col0 + 8), vc = q0.y - (float)(row0 + 8);  // from the tile centre
+            // from the tile centre
+            const float uc = q0.x - (float)(col0 + kTW / 2), vc = q0.y - (float)(row0 + kTH / 2);
             stage_record(q0, q1, q2, det, uc, vc, k, s_rec[tid * kQuads + 0], s_rec[tid * kQuads + 1],
                          s_rec[tid * kQuads + 2]);
             if constexpr (kGrad) s_rec[tid * kQuads + 3] = make_float4(A, B, C, uc);
@@ -277,10 +284,10 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             if (det > 0.f && __builtin_isfinite(ryv) && __builtin_isfinite(dxm) && __builtin_isfinite(dys)) {
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    if (!(j0 <= 4 * b + 3 && j1 >= 4 * b)) continue;
+                    if (!(j0 <= kBH * b + kBH - 1 && j1 >= kBH * b)) continue;
                     // (all finite here; the clamps are medians)
-                    const float ylo = max_finite(((float)(4 * b) + 0.5f) - v_rel, -ryv);
-                    const float yhi = min_finite(((float)(4 * b) + 3.5f) - v_rel, ryv);
+                    const float ylo = max_finite(((float)(kBH * b) + 0.5f) - v_rel, -ryv);
+                    const float yhi = min_finite(((float)(kBH * b + kBH) - 0.5f) - v_rel, ryv);
                     if (!(ylo <= yhi)) continue;
                     const float yr = __builtin_amdgcn_fmed3f(dys, ylo, yhi);   // where the right end peaks in the band
                     const float yl = __builtin_amdgcn_fmed3f(-dys, ylo, yhi);  // where the left end bottoms
@@ -289,7 +296,8 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                     const float x_hi = u_rel + xr + 1e-3f, x_lo = u_rel + xl - 1e-3f;  // tile-relative
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (x_hi >= (float)(4 * q) + 0.5f && x_lo <= (float)(4 * q) + 3.5f) cells |= 1u << (4 * b + q);
+                        if (x_hi >= (float)(kCW * q) + 0.5f && x_lo <= (float)(kCW * q + kCW) - 0.5f)
+                            cells |= 1u << (4 * b + q);
                 }
             } else {
                 // fall back to the pixel rectangle
@@ -298,7 +306,8 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
                 for (int b = 0; b < 4; ++b)
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (j0 <= 4 * b + 3 && j1 >= 4 * b && i0 <= 4 * q + 3 && i1 >= 4 * q) cells |= 1u << (4 * b + q);
+                        if (j0 <= kBH * b + kBH - 1 && j1 >= kBH * b && i0 <= kCW * q + kCW - 1 && i1 >= kCW * q)
+                            cells |= 1u << (4 * b + q);
             }
         }
         // 0 for a thread without a record (the dummy's colour quad is all 0)
@@ -518,20 +527,20 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     }
 }
 
-template <bool kCount, int kStage>
+template <int kTW, bool kCount, int kStage>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_blend(
     const float4 *__restrict__ records, int64_t n, const uint32_t *__restrict__ pairs,
     const uint64_t *__restrict__ offsets, uint64_t capacity, int width, int height, int tiles_x, int n_tiles,
     BlendConsts k, float *__restrict__ out_rgb, float *__restrict__ out_depth, float *__restrict__ out_t,
     unsigned long long *__restrict__ counters) {
-    blend_tile<kCount, kStage>(blockIdx.x, blockIdx.y, records, n, pairs, offsets, capacity, width, height, tiles_x, n_tiles,
-                       k, out_rgb, out_depth, out_t, counters);
+    blend_tile<kTW, kCount, kStage>(blockIdx.x, blockIdx.y, records, n, pairs, offsets, capacity, width, height,
+                                    tiles_x, n_tiles, k, out_rgb, out_depth, out_t, counters);
 }
 
 // Persistent variant: a fixed number of blocks take (pose, tile) items, pose
 // major, from a work queue (*queue starts at 0) until it passes n_items; every
 // block leaves once it draws an item past the end.
-template <bool kCount, int kStage>
+template <int kTW, bool kCount, int kStage>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_blend_queue(
     const float4 *__restrict__ records, int64_t n, const uint32_t *__restrict__ pairs,
     const uint64_t *__restrict__ offsets, uint64_t capacity, int width, int height, int tiles_x, int n_tiles,
@@ -544,13 +553,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
         __syncthreads();
         const unsigned int item = s_item;
         if (item >= n_items) break;
-        blend_tile<kCount, kStage>((int)(item % (unsigned)n_tiles), (int)(item / (unsigned)n_tiles), records, n, pairs,
-                           offsets, capacity, width, height, tiles_x, n_tiles, k, out_rgb, out_depth, out_t,
-                           counters);
+        blend_tile<kTW, kCount, kStage>((int)(item % (unsigned)n_tiles), (int)(item / (unsigned)n_tiles), records, n,
+                                        pairs, offsets, capacity, width, height, tiles_x, n_tiles, k, out_rgb,
+                                        out_depth, out_t, counters);
     }
 }
 
-template <bool kCount, int kStage>
+template <int kTW, bool kCount, int kStage>
 void launch_blend_t(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
                     const uint64_t *offsets, uint64_t capacity, const Camera &cam, const TileGrid &tg,
                     const BlendConsts &bc, float *rgb, float *depth, float *tfinal, unsigned long long *counters,
@@ -559,28 +568,31 @@ void launch_blend_t(hipStream_t s, const float4 *records, int64_t n, int n_poses
         const unsigned n_items = (unsigned)tg.n_tiles * (unsigned)n_poses;
         const unsigned blocks = std::min<unsigned>((unsigned)persistent_blocks, n_items);
         launch_fill_u32(s, queue, 1, 0u);
-        hipLaunchKernelGGL((k_blend_queue<kCount, kStage>), dim3(blocks), dim3(kThreads), 0, s, records, n, pairs,
+        hipLaunchKernelGGL((k_blend_queue<kTW, kCount, kStage>), dim3(blocks), dim3(kThreads), 0, s, records, n, pairs,
                            offsets, capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, bc, rgb, depth, tfinal,
                            counters, n_items, queue);
         return;
     }
-    hipLaunchKernelGGL((k_blend<kCount, kStage>), dim3((unsigned)tg.n_tiles, (unsigned)n_poses), dim3(kThreads), 0, s,
-                       records, n, pairs, offsets, capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, bc, rgb,
-                       depth, tfinal, counters);
+    hipLaunchKernelGGL((k_blend<kTW, kCount, kStage>), dim3((unsigned)tg.n_tiles, (unsigned)n_poses), dim3(kThreads),
+                       0, s, records, n, pairs, offsets, capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, bc,
+                       rgb, depth, tfinal, counters);
 }
 
 // The forward that also keeps the compositing state of long lists (chunks of 252).
+template <int kTW>
 __global__ __launch_bounds__(kThreads) void k_blend_keep(
     const float4 *__restrict__ records, int64_t n, const uint32_t *__restrict__ pairs,
     const uint64_t *__restrict__ offsets, uint64_t capacity, int width, int height, int tiles_x, int n_tiles,
     BlendConsts k, float *__restrict__ out_rgb, float *__restrict__ out_depth, float *__restrict__ out_t,
     KeepIo keep) {
-    blend_tile<false, 63, false, true>(blockIdx.x, blockIdx.y, records, n, pairs, offsets, capacity, width, height,
-                                       tiles_x, n_tiles, k, out_rgb, out_depth, out_t, nullptr, GradIo{}, keep);
+    blend_tile<kTW, false, 63, false, true>(blockIdx.x, blockIdx.y, records, n, pairs, offsets, capacity, width,
+                                            height, tiles_x, n_tiles, k, out_rgb, out_depth, out_t, nullptr, GradIo{},
+                                            keep);
 }
 
 // Backward of the compositing: one 256-thread block per (list, kept-state
 // segment), the forward's walk (chunks of 252 records).
+template <int kTW>
 __global__ __launch_bounds__(kThreads) void k_blend_backward(
     const float4 *__restrict__ records, int64_t n, const uint32_t *__restrict__ pairs,
     const uint64_t *__restrict__ offsets, uint64_t capacity, int width, int height, int tiles_x, int n_tiles,
@@ -589,12 +601,41 @@ __global__ __launch_bounds__(kThreads) void k_blend_backward(
     if (b >= gio.n_lists + gio.cp_off[gio.n_lists]) return;  // the grid is an upper bound
     const uint32_t list = gio.items[b];
     const uint32_t seg = b - list - gio.cp_off[list];
-    blend_tile<false, 63, true>((int)(list % (uint32_t)n_tiles), (int)(list / (uint32_t)n_tiles), records, n, pairs,
-                                offsets, capacity, width, height, tiles_x, n_tiles, k, nullptr, nullptr, nullptr,
-                                nullptr, gio, KeepIo{}, seg);
+    blend_tile<kTW, false, 63, true>((int)(list % (uint32_t)n_tiles), (int)(list / (uint32_t)n_tiles), records, n,
+                                     pairs, offsets, capacity, width, height, tiles_x, n_tiles, k, nullptr, nullptr,
+                                     nullptr, nullptr, gio, KeepIo{}, seg);
+}
+
+template <int kTW>
+void launch_blend_w(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
+                    const uint64_t *offsets, uint64_t capacity, const Camera &cam, const BlendConsts &bc,
+                    const TileGrid &tg, float *rgb, float *depth, float *tfinal, bool count_evals,
+                    unsigned long long *counters, int persistent_blocks, unsigned int *queue, int chunk,
+                    const uint32_t *keep_off, float *keep_state) {
+    if (keep_off) {
+        hipLaunchKernelGGL(k_blend_keep<kTW>, dim3((unsigned)tg.n_tiles, (unsigned)n_poses), dim3(kThreads), 0, s,
+                           records, n, pairs, offsets, capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, bc,
+                           rgb, depth, tfinal, KeepIo{keep_off, keep_state});
+        return;
+    }
+#define GSR_BLEND(C, S)                                                                                             \
+    launch_blend_t<kTW, C, S>(s, records, n, n_poses, pairs, offsets, capacity, cam, tg, bc, rgb, depth, tfinal,    \
+                              counters, persistent_blocks, queue)
+    if (chunk == 124) {
+        if (count_evals) GSR_BLEND(true, 31); else GSR_BLEND(false, 31);
+    } else if (chunk == 60) {
+        if (count_evals) GSR_BLEND(true, 15); else GSR_BLEND(false, 15);
+    } else {
+        if (count_evals) GSR_BLEND(true, 63); else GSR_BLEND(false, 63);
+    }
+#undef GSR_BLEND
 }
 
 }  // namespace
+
+bool blend_tile_supported(int tile_w, int tile_h) {
+    return (tile_w == 16 && tile_h == 16) || (tile_w == 32 && tile_h == 8) || (tile_w == 8 && tile_h == 32);
+}
 
 void launch_blend_backward(hipStream_t s, const float4 *records, int64_t n, int n_poses, const uint32_t *pairs,
                            const uint64_t *offsets, uint64_t capacity, const Camera &cam, const Consts &k,
@@ -604,8 +645,16 @@ void launch_blend_backward(hipStream_t s, const float4 *records, int64_t n, int 
     const uint32_t n_lists = (uint32_t)tg.n_tiles * (uint32_t)n_poses;
     const GradIo gio{img_rgb, img_depth, g_rgb, g_depth, gscreen, keep_off, keep_state, items, n_lists};
     if (max_blocks == 0) return;
-    hipLaunchKernelGGL(k_blend_backward, dim3((unsigned)max_blocks), dim3(kThreads), 0, s, records, n, pairs, offsets,
-                       capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, blend_consts(k), gio);
+#define GSR_BWD(W)                                                                                                  \
+    hipLaunchKernelGGL(k_blend_backward<W>, dim3((unsigned)max_blocks), dim3(kThreads), 0, s, records, n, pairs,     \
+                       offsets, capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, blend_consts(k), gio)
+    if (tg.tile_w == 32)
+        GSR_BWD(32);
+    else if (tg.tile_w == 8)
+        GSR_BWD(8);
+    else
+        GSR_BWD(16);
+#undef GSR_BWD
 }
 
 bool blend_chunk_supported(int chunk) { return chunk == 0 || chunk == 252 || chunk == 124 || chunk == 60; }
@@ -616,23 +665,16 @@ void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, 
                   unsigned long long *counters, int persistent_blocks, unsigned int *queue, int chunk,
                   const uint32_t *keep_off, float *keep_state) {
     const BlendConsts bc = blend_consts(k);
-    if (keep_off) {
-        hipLaunchKernelGGL(k_blend_keep, dim3((unsigned)tg.n_tiles, (unsigned)n_poses), dim3(kThreads), 0, s, records,
-                           n, pairs, offsets, capacity, cam.width, cam.height, tg.tiles_x, tg.n_tiles, bc, rgb, depth,
-                           tfinal, KeepIo{keep_off, keep_state});
-        return;
-    }
-#define GSR_BLEND(C, S)                                                                                              \
-    launch_blend_t<C, S>(s, records, n, n_poses, pairs, offsets, capacity, cam, tg, bc, rgb, depth, tfinal, counters, \
-                         persistent_blocks, queue)
-    if (chunk == 124) {
-        if (count_evals) GSR_BLEND(true, 31); else GSR_BLEND(false, 31);
-    } else if (chunk == 60) {
-        if (count_evals) GSR_BLEND(true, 15); else GSR_BLEND(false, 15);
-    } else {
-        if (count_evals) GSR_BLEND(true, 63); else GSR_BLEND(false, 63);
-    }
-#undef GSR_BLEND
+#define GSR_BLEND_W(W)                                                                                              \
+    launch_blend_w<W>(s, records, n, n_poses, pairs, offsets, capacity, cam, bc, tg, rgb, depth, tfinal, count_evals, \
+                      counters, persistent_blocks, queue, chunk, keep_off, keep_state)
+    if (tg.tile_w == 32)
+        GSR_BLEND_W(32);
+    else if (tg.tile_w == 8)
+        GSR_BLEND_W(8);
+    else
+        GSR_BLEND_W(16);
+#undef GSR_BLEND_W
 }
 
 }  // namespace gsr

@@ -54,7 +54,7 @@ struct Consts {
 };
 
 struct TileGrid {
-    int tile_w, tile_h;    // 16 x 16 in this library
+    int tile_w, tile_h;    // 16 x 16, 32 x 8 or 8 x 32
     int log2_w, log2_h;
     int tiles_x, tiles_y;  // tiles per image row / column
     int n_tiles;           // tiles per pose
@@ -164,6 +164,8 @@ void launch_blend(hipStream_t s, const float4 *records, int64_t n, int n_poses, 
                   const uint32_t *keep_off, float *keep_state);
 // Records per compositing chunk the blend is built for (0 = the default, 252).
 bool blend_chunk_supported(int chunk);
+// Tile shapes the compositing kernels implement: 16x16, 32x8, 8x32.
+bool blend_tile_supported(int tile_w, int tile_h);
 // Screen-space gradients per (pose, Gaussian): u, v, conic A, B, C, opacity, r, g, b, z.
 constexpr int kScreenGrads = 10;
 // Records between kept compositing states of a long tile list (8 chunks of 252):

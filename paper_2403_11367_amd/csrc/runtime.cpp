@@ -429,7 +429,8 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
     if (!pow2(cfg.tile_w) || !pow2(cfg.tile_h) || (cfg.flags & ~(GSR_RENDER_COUNT_EVALS | GSR_RENDER_KEEP_STATE)) != 0 ||
         cfg.pair_capacity < 0 || cfg.pose_groups < 0 || cfg.pose_groups > kMaxGroups)
         return fail(ctx, GSR_EINVAL, "bad render configuration");
-    if (cfg.tile_w != 16 || cfg.tile_h != 16) return fail(ctx, GSR_EUNSUPPORTED, "this library renders 16x16 tiles");
+    if (!gsr::blend_tile_supported(cfg.tile_w, cfg.tile_h))
+        return fail(ctx, GSR_EUNSUPPORTED, "this library renders 16x16, 32x8 or 8x32 tiles");
     if (!(cfg.alpha_min > 0.f) || !(cfg.alpha_max <= 1.f) || !(cfg.alpha_min < cfg.alpha_max) ||
         !(cfg.t_min > 0.f) || !(cfg.cutoff_d2 > 0.f) || !(cfg.eps_dilate >= 0.f))
         return fail(ctx, GSR_EINVAL, "bad render constants");

@@ -126,6 +126,31 @@ def test_backward_matches_central_differences_config0(ctx):
     assert _check_rows(rows, "config0") >= 200
 
 
+@pytest.mark.parametrize("tw,th", [(32, 8), (8, 32)])
+def test_backward_other_tile_shapes(ctx, tw, th):
+    """The backward walks the forward's tiles: with 32x8 and 8x32 tiles, config 0
+    (2 poses, 12 sampled Gaussians) against float64 central differences."""
+    from paper_2403_11367_amd import default_cfg
+    sc = W.config0()
+    cam = sc.camera
+    poses = sc.poses[[0, 9]]
+    rng = np.random.default_rng(177)
+    w_rgb = rng.normal(size=(2, 3, cam.height, cam.width)).astype(np.float32).astype(np.float64)
+    w_depth = (0.1 * rng.normal(size=(2, cam.height, cam.width))).astype(np.float32).astype(np.float64)
+    say(f"render backward: config0 with {tw}x{th} tiles, 12 sampled Gaussians")
+    gm, gs, gq, go, gc = _gpu_grads(ctx, sc.gaussians, poses, cam, w_rgb, w_depth, default_cfg(tile_w=tw, tile_h=th))
+    p = R.as_params(sc.gaussians)
+    s = np.exp(p.log_scales)
+    o = 1.0 / (1.0 + np.exp(-p.logits))
+    gpu = {"means": gm, "log_scales": gs * s, "quats": gq, "logits": go * o * (1 - o), "rgb": gc}
+    scr = R.project(p, poses[0], cam)
+    area = (scr.rect[:, 1] - scr.rect[:, 0]) * (scr.rect[:, 3] - scr.rect[:, 2])
+    inside = scr.visible & (scr.rect[:, 1] > 0) & (scr.rect[:, 0] < cam.width) & (scr.rect[:, 3] > 0) & \
+        (scr.rect[:, 2] < cam.height) & (area > 4.0)
+    rows = _fd_rows(p, poses, cam, w_rgb, w_depth, gpu, rng.choice(np.nonzero(inside)[0], 12, replace=False))
+    assert _check_rows(rows, f"{tw}x{th}") >= 80
+
+
 def test_backward_oblique_thin_disks(ctx):
     """Map-training layout: flat disks (in-plane log-scale N(-2.5, 0.4), normal
     N(-4, 0.3)) on the ground and two facades of a 30 m corridor, seen from 1.5 m

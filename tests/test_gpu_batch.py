@@ -182,3 +182,46 @@ def test_empty_submap(ctx):
     assert float(scores.abs().max()) == 0
     for sm in (sm0, sm1):
         sm.free()
+
+
+@pytest.mark.parametrize("tw,th", [(32, 8), (8, 32)])
+def test_multi_tile_shapes_equal_separate(ctx, batch4, tw, th):
+    """With 32x8 and 8x32 tiles the batched render equals separate renders of the
+    same tile shape bit for bit, for grid and persistent launches."""
+    import torch
+    from paper_2403_11367_amd import default_cfg
+    cam, qs, sms, poses = batch4
+    say(f"render_multi with {tw}x{th} tiles: 4 queries x 32 poses")
+    outs = [ctx.render(sm, cam, to_dev(q.poses), default_cfg(tile_w=tw, tile_h=th), with_tfinal=True)
+            for sm, q in zip(sms, qs)]
+    ref = [torch.cat([o[i] for o in outs]) for i in range(3)]
+    for chunk, blocks in [(0, 0), (124, 8)]:
+        cfg = default_cfg(tile_w=tw, tile_h=th, blend_chunk=chunk, blend_blocks_per_cu=blocks)
+        got = ctx.render_multi(sms, [32] * 4, cam, poses, cfg, with_tfinal=True)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(got, ref)), (chunk, blocks)
+
+
+def test_autotune_per_bucket_and_cache(ctx, tmp_path):
+    """The autotuner tries every tile shape, chunk, launch and grouping on a
+    workload, keeps the fastest under its submap-size bucket key and answers the
+    same key from its cache."""
+    from paper_2403_11367_amd import autotune, default_cfg
+    scenes = [W.tiny_scene(31, n=300, n_poses=2), W.tiny_scene(33, n=1000, n_poses=2)]
+    cam = camera(scenes[0].camera)
+    path = str(tmp_path / "tune.json")
+    keys = set()
+    for sc in scenes:
+        sm = load(ctx, sc.gaussians)
+        key = autotune.workload_key("test", cam.width, cam.height, 2, autotune.size_bucket(sm.n))
+        keys.add(key)
+        cfg, record = autotune.tune(key, default_cfg(), lambda c: ctx.render(sm, cam, to_dev(sc.poses), c),
+                                    reps=1, path=path)
+        assert len(record["variants"]) == len(autotune.variants())
+        assert {(v["tile_w"], v["tile_h"]) for v in record["variants"]} == set(autotune.TILES)
+        assert (cfg.tile_w, cfg.tile_h) in autotune.TILES
+        cfg2, record2 = autotune.tune(key, default_cfg(), lambda c: ctx.render(sm, cam, to_dev(sc.poses), c),
+                                      path=path)
+        assert record2 == {} and (cfg2.tile_w, cfg2.blend_chunk) == (cfg.tile_w, cfg.blend_chunk)
+        sm.free()
+    assert len(keys) == 2  # 300 and 1000 Gaussians fall in different buckets

@@ -531,3 +531,76 @@ def test_fig2_ncc_profile_config0_and_config1(ctx, cfg1):
     say(f"  config1 grid: best {best} at {grid[best]}, hidden ({hx:.2f}, {hy:.2f}, {hyaw:.2f}), NCC {s[best]:.4f}")
     assert abs(bx - hx) <= 1.0 and abs(by - hy) <= 1.0 and abs(byaw - hyaw) <= 5.0
     sm1.free()
+
+
+TILE_SHAPES = [(32, 8), (8, 32)]
+
+
+def _tiles_of(cam, tw, th):
+    return ((cam.width + tw - 1) // tw) * ((cam.height + th - 1) // th)
+
+
+def _shape_case(ctx, g, cam, poses, tw, th, label, depth_rel=False):
+    from paper_2403_11367_amd import default_cfg
+    sm = load(ctx, g)
+    rgb, dep, tf = gpu_render(ctx, sm, cam, poses, default_cfg(tile_w=tw, tile_h=th))
+    recs, nts, offs, pairs = gpu_buffers(ctx)
+    pr = prep(g)
+    T = _tiles_of(cam, tw, th)
+    for p in range(poses.shape[0]):
+        out, rec, ks, vs, rng = oracle_pose(pr, poses[p], cam, tile=(tw, th))
+        check_records(recs, nts, rec, g.n, p)
+        check_pairs(offs, pairs, ks, vs, rng, p, T)
+        compare_render(rgb[p], dep[p], tf[p], out, f"{label} {tw}x{th} pose {p}", depth_rel=depth_rel)
+    sm.free()
+
+
+@pytest.mark.parametrize("tw,th", TILE_SHAPES)
+def test_tile_shapes_config0_and_ragged(ctx, tw, th):
+    """32x8 and 8x32 tiles (the compositing's other wave bands and cells): records,
+    tile counts, keys, per-tile order bit for bit and images against the oracle
+    rendering the same tiles, on config 0 and on ragged tiny scenes."""
+    say(f"tile shape {tw}x{th}: config0 and ragged scenes")
+    sc = W.config0()
+    _shape_case(ctx, sc.gaussians, sc.camera, sc.poses[::3], tw, th, "config0")
+    for seed, n, w, h in [(22, 500, 37, 21), (24, 1000, 200, 9), (23, 64, 16, 16)]:
+        t = W.tiny_scene(seed, n=n, width=w, height=h, n_poses=2)
+        _shape_case(ctx, t.gaussians, t.camera, t.poses, tw, th, f"tiny {seed}")
+
+
+@pytest.mark.parametrize("tw,th", TILE_SHAPES)
+def test_tile_shapes_thin_huge_and_long_lists(ctx, tw, th):
+    """The same for needle-thin tilted and image-covering footprints, and for tile
+    lists of a few thousand records."""
+    say(f"tile shape {tw}x{th}: anisotropic scene and long lists")
+    sc = W.tiny_scene(41, n=400, width=96, height=64, n_poses=2)
+    g = sc.gaussians
+    rng = np.random.default_rng(1041)
+    s = np.exp(np.stack([rng.normal(-0.3, 0.8, g.n), rng.normal(-5.0, 0.5, g.n), rng.normal(-4.0, 1.0, g.n)], 1))
+    s[:6] = np.exp(rng.normal(0.8, 0.2, (6, 3)))
+    thin = W.Gaussians(g.means, s.astype(np.float32), g.quats, g.opacity, g.rgb)
+    _shape_case(ctx, thin, sc.camera, sc.poses, tw, th, "anisotropic")
+    g2, cam2, poses2 = _stack_scene(3500, 0.01, 3540)
+    _shape_case(ctx, g2, cam2, poses2, tw, th, "long lists")
+
+
+def test_tile_shapes_config1_frame(ctx, cfg1):
+    """The headline submap at full size with 32x8 and 8x32 tiles: two whole
+    frames each against the oracle (depth bar relative to max(1, depth))."""
+    from paper_2403_11367_amd import default_cfg
+    sc, idx = cfg1
+    sub = sc.gaussians.take(idx)
+    pr = prep(sub)
+    for tw, th in TILE_SHAPES:
+        say(f"config1 with {tw}x{th} tiles")
+        sm = load(ctx, sc.gaussians, index=idx)
+        poses = sc.poses[[5, 50]]
+        rgb, dep, tf = gpu_render(ctx, sm, sc.camera, poses, default_cfg(tile_w=tw, tile_h=th))
+        recs, nts, offs, pairs = gpu_buffers(ctx)
+        T = _tiles_of(sc.camera, tw, th)
+        for p in range(2):
+            out, rec, ks, vs, rng = oracle_pose(pr, poses[p], sc.camera, tile=(tw, th))
+            check_records(recs, nts, rec, idx.size, p)
+            check_pairs(offs, pairs, ks, vs, rng, p, T)
+            compare_render(rgb[p], dep[p], tf[p], out, f"config1 {tw}x{th} pose {p}", depth_rel=True)
+        sm.free()

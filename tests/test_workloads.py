@@ -39,3 +39,12 @@ def test_generators_are_deterministic():
     assert W.digest(*a.gaussians.arrays()) == DIGEST0
 
     assert W.digest(*W.config1().gaussians.arrays()) == DIGEST1
+
+
+def test_autotune_buckets_and_variants():
+    from paper_2403_11367_amd import autotune
+    assert [autotune.size_bucket(n) for n in (1, 2, 3, 175195, 262144, 262145, 956309)] == \
+        [1, 2, 4, 262144, 262144, 524288, 1048576]
+    v = autotune.variants()
+    assert len(v) == len(autotune.TILES) * len(autotune.CHUNKS) * len(autotune.BLOCKS_PER_CU) * len(autotune.POSE_GROUPS)
+    assert {(x["tile_w"], x["tile_h"]) for x in v} == {(16, 16), (32, 8), (8, 32)}
