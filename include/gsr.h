@@ -117,6 +117,13 @@ typedef struct {
  * GSR_EUNSUPPORTED); blend_chunk must be 0 or 252 (else GSR_EUNSUPPORTED);
  * blend_blocks_per_cu is not used (grid launch). */
 #define GSR_RENDER_KEEP_STATE 2
+/* gsr_render_cfg.flags: with a fixed pair_capacity, wait after the render for
+ * the device's overflow flag and, if the capacity was exceeded, render again with
+ * the pair buffers sized exactly (gsr_stats.overflow_retried = 1); the images are
+ * then those of an exact render. Two host waits per render; refused under graph
+ * capture (GSR_EUNSUPPORTED). An overflow of an earlier render that gsr_sync has
+ * not yet reported makes the call fail with GSR_EOVERFLOW. */
+#define GSR_RENDER_RETRY_OVERFLOW 4
 
 /* Counters of the most recent gsr_render / gsr_ncc on the context. */
 typedef struct {
@@ -146,6 +153,9 @@ typedef struct {
     int64_t n_culled_nonfinite; /* Gaussians of the rendered submap(s), as last loaded, with a
                               * non-finite mean, covariance, opacity or colour entry: culled
                               * at every pose (summed over the submaps of a batched render) */
+    int64_t workspace_bytes; /* device memory the context's workspace holds */
+    int32_t overflow_retried; /* 1 if the last render overflowed its fixed capacity and was
+                              * rendered again (GSR_RENDER_RETRY_OVERFLOW) */
 } gsr_stats;
 
 /* Create a context on GPU `device`, enqueueing on `hip_stream` (a hipStream_t;
@@ -156,6 +166,10 @@ int gsr_create(gsr_ctx **out, int device, void *hip_stream);
 int gsr_destroy(gsr_ctx *ctx);
 /* Switch the stream later calls enqueue on. */
 int gsr_set_stream(gsr_ctx *ctx, void *hip_stream);
+/* Limit the device memory the context's grow-only workspace may hold, in bytes
+ * (0 = no limit, the default). A call whose workspace would pass it fails with
+ * GSR_ENOMEM and allocates nothing; submaps and static scratch are not counted. */
+int gsr_set_workspace_limit(gsr_ctx *ctx, int64_t bytes);
 /* 1 = record HIP events around the stages of gsr_render / gsr_ncc. */
 int gsr_set_profiling(gsr_ctx *ctx, int on);
 /* Fill `out` with the default constants (see gsr_render_cfg). */
@@ -181,6 +195,14 @@ int gsr_default_cfg(gsr_render_cfg *out);
 int gsr_submap_load(gsr_ctx *ctx, int64_t n_map, const float *means_dev, const float *scales_dev,
                     const float *quats_dev, const float *opacity_dev, const float *rgb_dev,
                     const int64_t *index_dev, int64_t n_sel, gsr_submap **out);
+/* gsr_submap_load from host memory (Sec. III-B2: the submap retrieved around the
+ * prior is uploaded once per query): the same arguments, with every array in host
+ * memory, copied into a context staging buffer and packed. Waits until the
+ * packing is done, so the caller may free or reuse the inputs on return. Refused
+ * under graph capture (GSR_EUNSUPPORTED). */
+int gsr_submap_load_host(gsr_ctx *ctx, int64_t n_map, const float *means_host, const float *scales_host,
+                         const float *quats_host, const float *opacity_host, const float *rgb_host,
+                         const int64_t *index_host, int64_t n_sel, gsr_submap **out);
 int gsr_submap_free(gsr_submap *sm);
 int64_t gsr_submap_size(const gsr_submap *sm);
 

@@ -55,7 +55,10 @@ struct gsr_ctx {
         size_t bytes = 0;
     } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, esum, pseg, ptile, pk,
         sk, ccnt, cstart, ctile, cval, block_base, bseg, offsets, keep_off, keep_state, keep_items, grey_q, partials, s_order, s_poses, s_rgb, s_depth,
-        s_scores, pr_grey, pr_q3, pr_x, pr_rgb, pr_depth, bw_screen, bw_pose;
+        s_scores, pr_grey, pr_q3, pr_x, pr_rgb, pr_depth, bw_screen, bw_pose, h2d;
+    size_t ws_limit = 0;  // bytes the workspace may hold in all (0 = no limit)
+    size_t ws_bytes = 0;  // bytes it holds
+    int32_t overflow_retried = 0;  // the last render overflowed its fixed capacity and was rendered again
     // layout of the last render's pose groups
     struct Group {
         int64_t p0 = 0, np = 0;        // poses [p0, p0 + np)
@@ -137,13 +140,19 @@ int ensure(gsr_ctx *ctx, gsr_ctx::Buf &b, size_t bytes, const char *name) {
     if (ctx->capturing)
         return fail(ctx, GSR_EINVAL, std::string("workspace ") + name +
                                          " would grow under graph capture; run the same call once before capturing");
+    if (ctx->ws_limit && ctx->ws_bytes - b.bytes + bytes > ctx->ws_limit)
+        return fail(ctx, GSR_ENOMEM, std::string("workspace ") + name + " of " + std::to_string(bytes) +
+                                         " bytes would pass the workspace limit of " + std::to_string(ctx->ws_limit) +
+                                         " bytes (" + std::to_string(ctx->ws_bytes - b.bytes) + " held elsewhere)");
     if (b.p) {
         HIPC(ctx, hipDeviceSynchronize());
         HIPC(ctx, hipFree(b.p));
+        ctx->ws_bytes -= b.bytes;
         b.p = nullptr;
         b.bytes = 0;
     }
     size_t want = bytes + bytes / 4 + 256;
+    if (ctx->ws_limit && ctx->ws_bytes + want > ctx->ws_limit) want = bytes;  // no headroom past the limit
     hipError_t e = hipMalloc(&b.p, want);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -157,6 +166,7 @@ int ensure(gsr_ctx *ctx, gsr_ctx::Buf &b, size_t bytes, const char *name) {
                                          std::to_string(bytes) + " bytes)");
     }
     b.bytes = want;
+    ctx->ws_bytes += want;
     return GSR_OK;
 }
 
@@ -396,6 +406,40 @@ int gsr_submap_load(gsr_ctx *ctx, int64_t n_map, const float *means, const float
     return check_launch(ctx, "pack");
 }
 
+int gsr_submap_load_host(gsr_ctx *ctx, int64_t n_map, const float *means, const float *scales, const float *quats,
+                         const float *opacity, const float *rgb, const int64_t *index, int64_t n_sel,
+                         gsr_submap **out) {
+    if (!ctx || !out) return GSR_EINVAL;
+    if (n_map < 0 || n_sel < 0) return fail(ctx, GSR_EINVAL, "negative size");
+    if (n_map > 0 && (!means || !scales || !quats || !opacity || !rgb)) return fail(ctx, GSR_EINVAL, "null input array");
+    if (ctx->capturing) return fail(ctx, GSR_EUNSUPPORTED, "host-input load copies and waits: not under graph capture");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    // staging: means, scales, quats, opacity, colours, then the index
+    const size_t nf = (size_t)n_map * 14, bytes = nf * sizeof(float) + (index ? (size_t)n_sel * sizeof(int64_t) : 0);
+    int rc;
+    if ((rc = ensure(ctx, ctx->h2d, bytes + 64, "host-input staging"))) return rc;
+    float *d = (float *)ctx->h2d.p;
+    float *dm = d, *ds = dm + 3 * n_map, *dq = ds + 3 * n_map, *dopa = dq + 4 * n_map, *dc = dopa + n_map;
+    int64_t *di = index ? reinterpret_cast<int64_t *>(d + nf + (nf & 1)) : nullptr;  // 8-byte aligned
+    if (index && (size_t)((char *)(di + n_sel) - (char *)d) > ctx->h2d.bytes)
+        return fail(ctx, GSR_EINVAL, "staging layout");
+    const hipStream_t st = ctx->stream;
+    if (n_map > 0) {
+        HIPC(ctx, hipMemcpyAsync(dm, means, (size_t)n_map * 3 * sizeof(float), hipMemcpyHostToDevice, st));
+        HIPC(ctx, hipMemcpyAsync(ds, scales, (size_t)n_map * 3 * sizeof(float), hipMemcpyHostToDevice, st));
+        HIPC(ctx, hipMemcpyAsync(dq, quats, (size_t)n_map * 4 * sizeof(float), hipMemcpyHostToDevice, st));
+        HIPC(ctx, hipMemcpyAsync(dopa, opacity, (size_t)n_map * sizeof(float), hipMemcpyHostToDevice, st));
+        HIPC(ctx, hipMemcpyAsync(dc, rgb, (size_t)n_map * 3 * sizeof(float), hipMemcpyHostToDevice, st));
+    }
+    if (index && n_sel > 0)
+        HIPC(ctx, hipMemcpyAsync(di, index, (size_t)n_sel * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    rc = gsr_submap_load(ctx, n_map, dm, ds, dq, dopa, dc, di, index ? n_sel : n_map, out);
+    if (rc != GSR_OK) return rc;
+    // the staging buffer is reused by the next call: wait for the pack here
+    HIPC(ctx, hipStreamSynchronize(st));
+    return GSR_OK;
+}
+
 int gsr_submap_free(gsr_submap *sm) {
     if (!sm) return GSR_EINVAL;
     // hipFree waits for work on the device that may still read the submap
@@ -426,7 +470,7 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         cfg = *cfg_in;
     else
         gsr_default_cfg(&cfg);
-    if (!pow2(cfg.tile_w) || !pow2(cfg.tile_h) || (cfg.flags & ~(GSR_RENDER_COUNT_EVALS | GSR_RENDER_KEEP_STATE)) != 0 ||
+    if (!pow2(cfg.tile_w) || !pow2(cfg.tile_h) || (cfg.flags & ~(GSR_RENDER_COUNT_EVALS | GSR_RENDER_KEEP_STATE | GSR_RENDER_RETRY_OVERFLOW)) != 0 ||
         cfg.pair_capacity < 0 || cfg.pose_groups < 0 || cfg.pose_groups > kMaxGroups)
         return fail(ctx, GSR_EINVAL, "bad render configuration");
     if (!gsr::blend_tile_supported(cfg.tile_w, cfg.tile_h))
@@ -668,6 +712,47 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
 
 }  // namespace
 
+namespace {
+
+// render_impl, and with GSR_RENDER_RETRY_OVERFLOW and a fixed pair capacity: wait
+// for the device's overflow flag and, if the capacity was exceeded, render again
+// with the pair buffers sized exactly.
+int render_retry(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const gsr_camera *cam, const float *poses,
+                 int32_t n_poses, const gsr_render_cfg *cfg_in, float *rgb, float *depth, float *tfinal,
+                 const gsr_submap *hint) {
+    ctx->overflow_retried = 0;
+    if (!cfg_in || !(cfg_in->flags & GSR_RENDER_RETRY_OVERFLOW))
+        return render_impl(ctx, tab, n_slot, cam, poses, n_poses, cfg_in, rgb, depth, tfinal, hint);
+    if (ctx->capturing)
+        return fail(ctx, GSR_EUNSUPPORTED, "GSR_RENDER_RETRY_OVERFLOW waits on the host: not under graph capture");
+    gsr_render_cfg cfg = *cfg_in;
+    cfg.flags &= ~GSR_RENDER_RETRY_OVERFLOW;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    int flags[gsr::FLAG_COUNT];
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    HIPC(ctx, hipMemcpy(flags, ctx->d_flags, sizeof(flags), hipMemcpyDeviceToHost));
+    if (flags[gsr::FLAG_OVERFLOW]) return fail(ctx, GSR_EOVERFLOW, "an earlier render overflowed (not yet reported)");
+    int rc = render_impl(ctx, tab, n_slot, cam, poses, n_poses, &cfg, rgb, depth, tfinal, hint);
+    if (rc != GSR_OK || cfg.pair_capacity == 0) return rc;
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    HIPC(ctx, hipMemcpy(flags, ctx->d_flags, sizeof(flags), hipMemcpyDeviceToHost));
+    if (!flags[gsr::FLAG_OVERFLOW]) return GSR_OK;
+    flags[gsr::FLAG_OVERFLOW] = 0;
+    HIPC(ctx, hipMemcpy(ctx->d_flags, flags, sizeof(flags), hipMemcpyHostToDevice));
+    cfg.pair_capacity = 0;
+    rc = render_impl(ctx, tab, n_slot, cam, poses, n_poses, &cfg, rgb, depth, tfinal, hint);
+    ctx->overflow_retried = 1;
+    return rc;
+}
+
+}  // namespace
+
+int gsr_set_workspace_limit(gsr_ctx *ctx, int64_t bytes) {
+    if (!ctx || bytes < 0) return GSR_EINVAL;
+    ctx->ws_limit = (size_t)bytes;
+    return GSR_OK;
+}
+
 int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const float *poses, int32_t n_poses,
                const gsr_render_cfg *cfg, float *rgb, float *depth, float *tfinal) {
     if (!ctx) return GSR_EINVAL;
@@ -679,7 +764,7 @@ int gsr_render(gsr_ctx *ctx, const gsr_submap *sm, const gsr_camera *cam, const 
     tab.n[0] = sm->n;
     tab.packed[0] = sm->packed;
     tab.nonfinite[0] = sm->nonfinite;
-    return render_impl(ctx, tab, sm->n, cam, poses, n_poses, cfg, rgb, depth, tfinal, sm);
+    return render_retry(ctx, tab, sm->n, cam, poses, n_poses, cfg, rgb, depth, tfinal, sm);
 }
 
 int gsr_render_backward(gsr_ctx *ctx, const gsr_submap *sm, const float *scales, const float *quats,
@@ -767,7 +852,7 @@ int gsr_render_multi(gsr_ctx *ctx, const gsr_submap *const *submaps, const int32
         tab.nonfinite[q] = sm->nonfinite;
         n_slot = std::max<int64_t>(n_slot, sm->n);
     }
-    return render_impl(ctx, tab, n_slot, cam, poses, (int32_t)P, cfg, rgb, depth, tfinal, nullptr);
+    return render_retry(ctx, tab, n_slot, cam, poses, (int32_t)P, cfg, rgb, depth, tfinal, nullptr);
 }
 
 int gsr_ncc(gsr_ctx *ctx, const float *query, const float *renders, int32_t n_poses, int32_t height, int32_t width,
@@ -1077,6 +1162,8 @@ int gsr_get_stats(gsr_ctx *ctx, gsr_stats *out) {
     out->evals_contrib = (int64_t)cnt[gsr::CNT_EVALS_CONTRIB];
     out->evals_lanes = (int64_t)cnt[gsr::CNT_EVALS_LANES];
     out->n_culled_nonfinite = (int64_t)cnt[gsr::CNT_NONFINITE];
+    out->workspace_bytes = (int64_t)ctx->ws_bytes;
+    out->overflow_retried = ctx->overflow_retried;
     double pre = 0, sort = 0, blend = 0, whole = 0;
     size_t n_group_runs = 0;
     for (size_t i = 0; i < ctx->n_ev_render; ++i) {

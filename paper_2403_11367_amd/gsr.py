@@ -26,11 +26,12 @@ STATUS = {0: "GSR_OK", -1: "GSR_EINVAL", -2: "GSR_ENOMEM", -3: "GSR_EHIP", -4: "
 BUF_RECORDS, BUF_NTILES, BUF_OFFSETS, BUF_PAIRS = 0, 1, 2, 3
 RENDER_COUNT_EVALS = 1
 RENDER_KEEP_STATE = 2  # keep long lists' compositing states for gsr_render_backward
+RENDER_RETRY_OVERFLOW = 4  # with a fixed capacity: re-render exactly after an overflow
 
 # every symbol declared in include/gsr.h and include/gsr_scorer.h
 EXPORTS = [
     "gsr_create", "gsr_destroy", "gsr_set_stream", "gsr_set_profiling", "gsr_default_cfg",
-    "gsr_submap_load", "gsr_submap_free", "gsr_submap_size", "gsr_render", "gsr_render_multi",
+    "gsr_submap_load", "gsr_submap_load_host", "gsr_submap_free", "gsr_submap_size", "gsr_set_workspace_limit", "gsr_render", "gsr_render_multi",
     "gsr_render_backward", "gsr_ncc", "gsr_ncc_noalloc",
     "gsr_topk", "gsr_search", "gsr_capture_begin", "gsr_capture_end", "gsr_graph_launch", "gsr_graph_destroy",
     "gsr_sync", "gsr_get_stats", "gsr_debug_size", "gsr_debug_copy", "gsr_crop",
@@ -68,7 +69,8 @@ class Stats(C.Structure):
                 ("n_profiled_renders", C.c_int32), ("n_profiled_ncc", C.c_int32),
                 ("ms_preprocess", C.c_float), ("ms_sort", C.c_float), ("ms_blend", C.c_float),
                 ("ms_ncc", C.c_float), ("ms_render", C.c_float), ("n_groups", C.c_int32),
-                ("render_serial", C.c_int64), ("n_culled_nonfinite", C.c_int64)]
+                ("render_serial", C.c_int64), ("n_culled_nonfinite", C.c_int64), ("workspace_bytes", C.c_int64),
+                ("overflow_retried", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -96,6 +98,8 @@ def _load() -> C.CDLL:
         "gsr_set_profiling": (I, [P, I]),
         "gsr_default_cfg": (I, [C.POINTER(RenderCfg)]),
         "gsr_submap_load": (I, [P, I64, P, P, P, P, P, P, I64, C.POINTER(P)]),
+        "gsr_submap_load_host": (I, [P, I64, P, P, P, P, P, P, I64, C.POINTER(P)]),
+        "gsr_set_workspace_limit": (I, [P, I64]),
         "gsr_submap_free": (I, [P]),
         "gsr_submap_size": (I64, [P]),
         "gsr_render": (I, [P, P, C.POINTER(CameraC), P, I32, C.POINTER(RenderCfg), P, P, P]),
@@ -305,6 +309,32 @@ class Context:
         if reuse:
             into.handle = None  # the library freed it when it allocated a larger one
         return Submap(self, h)
+
+    def load_submap_host(self, means, scales, quats, opacity, rgb, index=None,
+                         into: Optional[Submap] = None) -> Submap:
+        """gsr_submap_load_host: the same from host (numpy) arrays; returns once packed."""
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (means, scales, quats, opacity, rgb)]
+        n = arrs[0].shape[0]
+        for a, w, name in zip(arrs, (3, 3, 4, None, 3), ("means", "scales", "quats", "opacity", "rgb")):
+            if a.shape != ((n, w) if w else (n,)):
+                raise ValueError(f"{name} has shape {a.shape}")
+        idx = None if index is None else np.ascontiguousarray(index, dtype=np.int64)
+        n_sel = n if idx is None else idx.shape[0]
+        reuse = into is not None and bool(into.handle)
+        h = C.c_void_p(into.handle.value) if reuse else C.c_void_p()
+        self._bind_stream()
+        rc = LIB.gsr_submap_load_host(self.handle, n, *[a.ctypes.data for a in arrs],
+                                      None if idx is None else idx.ctypes.data, n_sel, C.byref(h))
+        self._check(rc, "gsr_submap_load_host")
+        if reuse and h.value == into.handle.value:
+            return into
+        if reuse:
+            into.handle = None
+        return Submap(self, h)
+
+    def set_workspace_limit(self, nbytes: int):
+        """gsr_set_workspace_limit: cap the context workspace (0 = no cap)."""
+        self._check(LIB.gsr_set_workspace_limit(self.handle, int(nbytes)), "gsr_set_workspace_limit")
 
     def render(self, submap: Submap, camera: Camera, poses, cfg: Optional[RenderCfg] = None,
                rgb=None, depth=None, tfinal=None, with_tfinal: bool = False):

@@ -604,3 +604,60 @@ def test_tile_shapes_config1_frame(ctx, cfg1):
             check_pairs(offs, pairs, ks, vs, rng, p, T)
             compare_render(rgb[p], dep[p], tf[p], out, f"config1 {tw}x{th} pose {p}", depth_rel=True)
         sm.free()
+
+
+def test_host_input_load_equals_device_load(ctx):
+    """gsr_submap_load_host (host arrays, with and without an index) gives the
+    records and images of gsr_submap_load on the same data, bit for bit."""
+    import torch
+    say("host-input submap load")
+    sc = W.tiny_scene(21, n=300, width=64, height=48, n_poses=3)
+    g = sc.gaussians
+    idx = np.random.default_rng(2).permutation(g.n)[:200].astype(np.int64)
+    for index in (None, idx):
+        a = load(ctx, g, index)
+        ra = gpu_render(ctx, a, sc.camera, sc.poses)
+        recs_a = ctx.debug_buffer(__import__("paper_2403_11367_amd").BUF_RECORDS)
+        b = ctx.load_submap_host(*g.arrays(), index=index)
+        assert b.n == (g.n if index is None else idx.size)
+        rb = gpu_render(ctx, b, sc.camera, sc.poses)
+        recs_b = ctx.debug_buffer(__import__("paper_2403_11367_amd").BUF_RECORDS)
+        torch.cuda.synchronize()
+        assert np.array_equal(recs_a.view(np.uint32), recs_b.view(np.uint32))
+        for x, y in zip(ra, rb):
+            assert np.array_equal(x, y)
+        a.free()
+        b.free()
+
+
+def test_workspace_limit_and_overflow_retry(ctx):
+    """A workspace limit below what a render needs fails with GSR_ENOMEM and the
+    context keeps working once the limit is lifted; a fixed pair capacity that is
+    too small, with GSR_RENDER_RETRY_OVERFLOW, renders again exactly and gives the
+    exact render's images, while without it gsr_sync reports the overflow."""
+    from paper_2403_11367_amd import Context, GsrError, default_cfg
+    from paper_2403_11367_amd.gsr import RENDER_RETRY_OVERFLOW
+    say("workspace limit and overflow retry")
+    sc = W.config0()
+    c2 = Context(0)
+    sm = load(c2, sc.gaussians)
+    c2.set_workspace_limit(1 << 20)
+    with pytest.raises(GsrError) as e:
+        gpu_render(c2, sm, sc.camera, sc.poses)
+    assert e.value.status == -2 and "workspace limit" in str(e.value)
+    c2.set_workspace_limit(0)
+    exact = gpu_render(c2, sm, sc.camera, sc.poses)
+    st = c2.stats()
+    assert st["workspace_bytes"] > (1 << 20) and st["overflow_retried"] == 0
+    small = default_cfg(pair_capacity=1000, flags=RENDER_RETRY_OVERFLOW)
+    got = gpu_render(c2, sm, sc.camera, sc.poses, small)
+    assert c2.stats()["overflow_retried"] == 1
+    for x, y in zip(exact, got):
+        assert np.array_equal(x, y)
+    c2.sync()  # nothing left to report
+    gpu_render(c2, sm, sc.camera, sc.poses, default_cfg(pair_capacity=1000))
+    with pytest.raises(GsrError) as e:
+        c2.sync()
+    assert e.value.status == -5
+    sm.free()
+    c2.close()
