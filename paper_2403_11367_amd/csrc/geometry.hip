@@ -292,6 +292,18 @@ __global__ __launch_bounds__(kThreads) void k_pair_segments(const uint32_t *__re
     if (threadIdx.x == 0) pseg[p] = min(prefix[b] + total, capacity);
 }
 
+// The submap index of record slot x = pose * n + index (n >= 1): the quotient
+// x / n is the pose, below 65536, so the float product (relative error a few
+// 2^-24) is within 0.02 of it and its truncation off by at most one; the
+// remainder is then corrected into [0, n) exactly.
+__device__ __forceinline__ uint32_t slot_index(uint32_t x, uint32_t n, float inv_n) {
+    const int64_t q = (int64_t)((float)x * inv_n);
+    int64_t r = (int64_t)x - q * (int64_t)n;
+    if (r < 0) r += n;
+    if (r >= (int64_t)n) r -= n;
+    return (uint32_t)r;
+}
+
 // One block per emission block. The block scans its elements' tile counts, then
 // lays the pairs out window by window in LDS: every thread expands its own
 // elements' rectangles (row-major) into the window slots given by the scan, and
@@ -321,6 +333,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
     const uint64_t eb = (uint64_t)(blockIdx.x % kXcdCount) * per + turn;
     const uint64_t e0 = eb * kEmitTile;
     if (e0 >= nv) return;
+    const float inv_n = 1.0f / (float)n;
     // this thread's elements: e0 + t * kEmitItems + k (consecutive, for the scan)
     const uint64_t et = e0 + (uint64_t)threadIdx.x * kEmitItems;
     // tile counts and record slots together, then the rectangles (one round trip
@@ -341,7 +354,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
         rc[k] = make_uint2(0u, 0u);
         if (cnt[k]) {
             rc[k] = rect[slot[k]];
-            key[k] = slot[k] - (uint32_t)((uint64_t)slot[k] / (uint64_t)n) * (uint32_t)n;  // submap index
+            key[k] = slot_index(slot[k], (uint32_t)n, inv_n);  // submap index
         }
     }
     uint32_t total = 0;

@@ -308,14 +308,27 @@ __global__ __launch_bounds__(kThreads) void k_compact(const uint32_t *__restrict
         my_src = (uint64_t)p * (uint64_t)n + ((uint64_t)r << 6);
         my_dst = (uint64_t)vbase[p] + reg_off[w];
     }
+    // every region's entries are loaded before the first store, so the wave's 16
+    // loads are in flight together instead of one memory latency per region
+    uint32_t kv[kCompactRegions], vv[kCompactRegions];
 #pragma unroll
     for (int i = 0; i < kCompactRegions; ++i) {
         const uint32_t cnt = (uint32_t)__shfl((int)my_cnt, i, 64);
         const uint64_t src = (uint64_t)__shfl((long long)my_src, i, 64);
+        kv[i] = 0u;
+        vv[i] = 0u;
+        if ((uint32_t)lane < cnt) {
+            kv[i] = kin[src + lane];
+            vv[i] = vin[src + lane];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kCompactRegions; ++i) {
+        const uint32_t cnt = (uint32_t)__shfl((int)my_cnt, i, 64);
         const uint64_t dst = (uint64_t)__shfl((long long)my_dst, i, 64);
         if ((uint32_t)lane < cnt) {
-            kout[dst + lane] = kin[src + lane];
-            vout[dst + lane] = vin[src + lane];
+            kout[dst + lane] = kv[i];
+            vout[dst + lane] = vv[i];
         }
     }
 }
@@ -584,9 +597,23 @@ __global__ __launch_bounds__(kCBThreads) void k_seg_count(SegPass ps, const uint
     uint32_t tr[kCBChunks];
     seg_load(ps, block_base, i, gb, tiles, nullptr, tr, nullptr);
     __syncthreads();
+    // Runs of equal keys in lane order (a Gaussian's tiles of one row mostly share
+    // a bucket) are counted by their first lane, which adds the run's length: far
+    // fewer lanes meet at one LDS counter than with one atomic per pair.
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int c = 0; c < kCBChunks; ++c)
-        if (tr[c] != 0xffffu) atomicAdd(&s_h[wave][(tr[c] >> ps.shift) & ps.mask], 1u);
+    for (int c = 0; c < kCBChunks; ++c) {
+        const bool valid = tr[c] != 0xffffu;
+        const uint32_t key = valid ? (tr[c] >> ps.shift) & ps.mask : 0xffffffffu;
+        const uint32_t prev = (uint32_t)__shfl_up((int)key, 1, 64);
+        const bool head = valid && (lane == 0 || prev != key);
+        const uint64_t heads = __ballot(head) | __ballot(!valid);  // a run also ends before an invalid lane
+        if (head) {
+            const uint64_t after = lane == 63 ? 0ull : heads >> (lane + 1);
+            const uint32_t len = after ? (uint32_t)__builtin_ctzll(after) + 1u : (uint32_t)(64 - lane);
+            atomicAdd(&s_h[wave][key], len);
+        }
+    }
     __syncthreads();
     for (int k = threadIdx.x; k < ps.n_keys; k += kCBThreads) {
         uint32_t t = 0;
