@@ -223,12 +223,22 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
 
 // S2, pair emission in front-to-back order. The depth-sorted visible Gaussians of
 // all poses are cut into emission blocks of kEmitTile elements (pose p owns
-// [vbase[p], vbase[p+1]); snt holds their tile counts, sg their indices). Block
-// sums of the tile counts are scanned (sort.hip), and each block then lays its
-// pairs out contiguously from its prefix: element i writes one pair per tile of
-// its rectangle (row-major): the tile id within the pose and the submap index.
-constexpr int kEmitItems = 8;
+// [vbase[p], vbase[p+1]); snt holds their tile counts, sg their indices). The
+// tile counts are summed per block, the block sums prefixed in two levels (within
+// spans of kSumSpan blocks, then across spans by a scan in sort.hip), and each
+// block then lays its pairs out contiguously from its prefix: element i writes
+// one pair per tile of its rectangle (row-major): the tile id within the pose and
+// the submap index.
+constexpr int kEmitItems = 2;
 constexpr int kEmitTile = kThreads * kEmitItems;
+constexpr int kSumSpan = 8;
+
+// First pair of emission block b: its span's prefix plus its prefix within the span
+// (the layout of the emission sums is in internal.h).
+__device__ __forceinline__ uint64_t emit_block_prefix(const uint64_t *__restrict__ es, uint64_t n_blocks,
+                                                      uint64_t b) {
+    return es[n_blocks + 2 + b / kSumSpan] + es[b];
+}
 
 // Exclusive scan of one uint32 per thread across a kThreads block; *total = sum.
 __device__ uint32_t emit_block_scan(uint32_t x, uint32_t *s_wave /*[4]*/, uint32_t *total) {
@@ -248,40 +258,69 @@ __device__ uint32_t emit_block_scan(uint32_t x, uint32_t *s_wave /*[4]*/, uint32
     return add + inc - x;
 }
 
-// sums[b] = tile counts of emission block b (0 past the visible total vbase[P]).
+// The emission sums, before the scan of the span sums: one workgroup per span of
+// kSumSpan emission blocks, wave w summing blocks 2w and 2w + 1 (lane l takes
+// elements k * 64 + l of a block, coalesced). Spans past the visible total
+// write nothing.
+static_assert(kSumSpan == 2 * (kThreads / 64), "two emission blocks per wave");
 __global__ __launch_bounds__(kThreads) void k_emit_sums(const uint32_t *__restrict__ snt,
                                                         const uint32_t *__restrict__ vbase, int P,
-                                                        uint64_t *__restrict__ sums) {
-    __shared__ uint32_t s_wave[4];
+                                                        uint64_t n_blocks, uint64_t *__restrict__ es) {
+    __shared__ uint32_t s_sum[kSumSpan];
     const uint64_t nv = vbase[P];
-    const uint64_t e0 = (uint64_t)blockIdx.x * kEmitTile;
-    if (e0 >= nv) {
-        if (threadIdx.x == 0) sums[blockIdx.x] = 0;
-        return;
-    }
-    uint64_t sum = 0;
+    const uint64_t blocks_used = (nv + kEmitTile - 1) / kEmitTile;
+    if (blockIdx.x == 0 && threadIdx.x == 0) es[n_blocks + 1] = (blocks_used + kSumSpan - 1) / kSumSpan;
+    const uint64_t span = blockIdx.x, b0 = span * kSumSpan;
+    if (b0 >= blocks_used) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // unconditional loads (an element past the end reads element 0 and adds
+    // nothing), so that all of them are in flight at once
+    uint32_t sum[2] = {0u, 0u};
 #pragma unroll
-    for (int k = 0; k < kEmitItems; ++k) {
-        const uint64_t e = e0 + (uint64_t)k * kThreads + threadIdx.x;
-        if (e < nv) sum += snt[e];
+    for (int h = 0; h < 2; ++h) {
+        const uint64_t e0 = (b0 + 2 * wave + h) * kEmitTile;
+#pragma unroll
+        for (int k = 0; k < kEmitTile / 64; ++k) {
+            const uint64_t e = e0 + (uint64_t)k * 64 + lane;
+            const uint32_t c = snt[e < nv ? e : 0];
+            sum[h] += e < nv ? c : 0u;
+        }
     }
-    // tile counts per element are < 2^15 and a block has 2048 elements: fits 32 bits
-    uint32_t total = 0;
-    (void)emit_block_scan((uint32_t)sum, s_wave, &total);
-    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+    // tile counts per element are < 2^15 and a span has 4096 elements: fits 32 bits
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sum[h] += __shfl_xor(sum[h], o, 64);
+    }
+    if (lane == 0) {
+        s_sum[2 * wave] = sum[0];
+        s_sum[2 * wave + 1] = sum[1];
+    }
+    __syncthreads();
+    if (threadIdx.x < kSumSpan) {
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int i = 0; i < kSumSpan; ++i) {
+            const uint32_t x = s_sum[i];
+            if (i < (int)threadIdx.x) before += x;
+            all += x;
+        }
+        if (b0 + threadIdx.x < n_blocks) es[b0 + threadIdx.x] = before;
+        if (threadIdx.x == 0) es[n_blocks + 2 + span] = all;
+    }
 }
 
-// pseg[p] = min(first pair of pose p, capacity) for p in [0, P]; prefix holds the
-// scanned block sums and prefix[n_blocks] the pair total.
+// pseg[p] = min(first pair of pose p, capacity) for p in [0, P], from the
+// scanned emission sums es (es[n_blocks]: the pair total).
 __global__ __launch_bounds__(kThreads) void k_pair_segments(const uint32_t *__restrict__ snt,
                                                             const uint32_t *__restrict__ vbase, int P,
-                                                            const uint64_t *__restrict__ prefix, uint64_t n_blocks,
+                                                            const uint64_t *__restrict__ es, uint64_t n_blocks,
                                                             uint64_t capacity, uint64_t *__restrict__ pseg) {
     __shared__ uint32_t s_wave[4];
     const int p = blockIdx.x;
     const uint64_t e = vbase[p], nv = vbase[P];
     if (e >= nv) {
-        if (threadIdx.x == 0) pseg[p] = min(prefix[n_blocks], capacity);
+        if (threadIdx.x == 0) pseg[p] = min(es[n_blocks], capacity);
         return;
     }
     const uint64_t b = e / kEmitTile, e0 = b * kEmitTile;
@@ -289,7 +328,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_segments(const uint32_t *__re
     for (uint64_t i = e0 + threadIdx.x; i < e; i += kThreads) part += snt[i];
     uint32_t total = 0;
     (void)emit_block_scan(part, s_wave, &total);
-    if (threadIdx.x == 0) pseg[p] = min(prefix[b] + total, capacity);
+    if (threadIdx.x == 0) pseg[p] = min(emit_block_prefix(es, n_blocks, b) + total, capacity);
 }
 
 // The submap index of record slot x = pose * n + index (n >= 1): the quotient
@@ -308,12 +347,12 @@ __device__ __forceinline__ uint32_t slot_index(uint32_t x, uint32_t n, float inv
 // lays the pairs out window by window in LDS: every thread expands its own
 // elements' rectangles (row-major) into the window slots given by the scan, and
 // the block copies the window to the output with coalesced stores.
-constexpr int kEmitWin = 8192;  // pairs per LDS window
+constexpr int kEmitWin = 4096;  // pairs per LDS window
 
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ snt, const uint32_t *__restrict__ slots,
                                                    const uint32_t *__restrict__ vbase, int P,
                                                    const uint2 *__restrict__ rect, int64_t n,
-                                                   const uint64_t *__restrict__ prefix, TileGrid tg,
+                                                   const uint64_t *__restrict__ es, uint64_t n_blocks, TileGrid tg,
                                                    uint16_t *__restrict__ ptile, uint32_t *__restrict__ pk,
                                                    uint64_t capacity, int *__restrict__ flags) {
     __shared__ uint16_t s_tile[kEmitWin];
@@ -337,29 +376,30 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
     // this thread's elements: e0 + t * kEmitItems + k (consecutive, for the scan)
     const uint64_t et = e0 + (uint64_t)threadIdx.x * kEmitItems;
     // tile counts and record slots together, then the rectangles (one round trip
-    // fewer than loading the slots after the scan)
+    // fewer than loading the slots after the scan). No load is conditional: an
+    // element past the end reads the block's first element and counts nothing, so
+    // the loads of all items are in flight at once (a load under a branch is
+    // waited for where the branches join, one item at a time).
     uint32_t cnt[kEmitItems], slot[kEmitItems], sum = 0;
 #pragma unroll
     for (int k = 0; k < kEmitItems; ++k) {
         const bool in = et + k < nv;
-        cnt[k] = in ? snt[et + k] : 0u;
-        slot[k] = in ? slots[et + k] : 0u;
+        const uint64_t e = in ? et + k : e0;
+        const uint32_t c = snt[e];
+        cnt[k] = in ? c : 0u;
+        slot[k] = slots[e];
     }
     uint32_t key[kEmitItems];
     uint2 rc[kEmitItems];
 #pragma unroll
     for (int k = 0; k < kEmitItems; ++k) {
         sum += cnt[k];
-        key[k] = 0;
-        rc[k] = make_uint2(0u, 0u);
-        if (cnt[k]) {
-            rc[k] = rect[slot[k]];
-            key[k] = slot_index(slot[k], (uint32_t)n, inv_n);  // submap index
-        }
+        rc[k] = rect[slot[k]];
+        key[k] = slot_index(slot[k], (uint32_t)n, inv_n);  // submap index
     }
     uint32_t total = 0;
     const uint32_t first = emit_block_scan(sum, s_wave, &total);
-    const uint64_t base = prefix[eb];
+    const uint64_t base = emit_block_prefix(es, n_blocks, eb);
     bool over = false;
     for (uint32_t w0 = 0; w0 < total; w0 += kEmitWin) {
         const uint32_t w1 = min(total, w0 + kEmitWin);
@@ -431,25 +471,32 @@ void launch_preprocess(hipStream_t s, const SubmapTable &tab, int64_t n, const f
 
 uint64_t emit_blocks(uint64_t n_max) { return std::max<uint64_t>(1, (n_max + kEmitTile - 1) / kEmitTile); }
 
+uint64_t emit_sums_size(uint64_t n_max) {
+    const uint64_t nb = emit_blocks(n_max);
+    return nb + 2 + (nb + kSumSpan - 1) / kSumSpan;
+}
+
 void launch_emit_sums(hipStream_t s, const uint32_t *snt, const uint32_t *vbase, int n_poses, uint64_t n_max,
-                      uint64_t *sums) {
-    hipLaunchKernelGGL(k_emit_sums, dim3((unsigned)emit_blocks(n_max)), dim3(kThreads), 0, s, snt, vbase, n_poses,
-                       sums);
+                      uint64_t *es) {
+    const uint64_t nb = emit_blocks(n_max), spans = (nb + kSumSpan - 1) / kSumSpan;
+    hipLaunchKernelGGL(k_emit_sums, dim3((unsigned)spans), dim3(kThreads), 0, s, snt, vbase, n_poses, nb, es);
+    // the span sums, scanned in place (only the spans in use); the pair total to es[nb]
+    launch_block_scan(s, es + nb + 2, spans, es + nb + 1, es + nb);
 }
 
 void launch_pair_segments(hipStream_t s, const uint32_t *snt, const uint32_t *vbase, int n_poses,
-                          const uint64_t *prefix, uint64_t n_max, uint64_t capacity, uint64_t *pseg) {
+                          const uint64_t *es, uint64_t n_max, uint64_t capacity, uint64_t *pseg) {
     hipLaunchKernelGGL(k_pair_segments, dim3((unsigned)n_poses + 1), dim3(kThreads), 0, s, snt, vbase, n_poses,
-                       prefix, emit_blocks(n_max), capacity, pseg);
+                       es, emit_blocks(n_max), capacity, pseg);
 }
 
 void launch_emit(hipStream_t s, const uint32_t *snt, const uint32_t *sg, const uint32_t *vbase, int n_poses,
-                 const uint2 *rect, int64_t n, uint64_t n_max, const uint64_t *prefix, const TileGrid &tg,
+                 const uint2 *rect, int64_t n, uint64_t n_max, const uint64_t *es, const TileGrid &tg,
                  uint16_t *ptile, uint32_t *pk, uint64_t capacity, int *flags) {
     if (n <= 0) return;
     const uint64_t grid = (emit_blocks(n_max) + kXcdCount - 1) / kXcdCount * kXcdCount;  // see k_emit
     hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(kThreads), 0, s, snt, sg, vbase, n_poses,
-                       rect, n, prefix, tg, ptile, pk, capacity, flags);
+                       rect, n, es, emit_blocks(n_max), tg, ptile, pk, capacity, flags);
 }
 
 }  // namespace gsr

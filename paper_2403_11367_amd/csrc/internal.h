@@ -97,19 +97,23 @@ void launch_preprocess(hipStream_t s, const SubmapTable &tab, int64_t n, const f
                        uint32_t *ntiles, uint2 *rect, uint32_t *vz, uint32_t *vg, uint32_t *vcount, bool pack);
 // Pair emission in front-to-back order. The depth-sorted visible Gaussians
 // (snt: tile counts, sg: record slots p * n + g; pose p owns [vbase[p],
-// vbase[p+1]), at most n_max = P * n of them) are cut into emit_blocks(n_max)
-// blocks.
-//   launch_emit_sums:     sums[b] = tile counts of block b
-//   (launch_block_scan:   sums -> exclusive prefix, pair total in sums[emit_blocks])
+// vbase[p+1]), at most n_max = P * n of them) are cut into nb = emit_blocks(n_max)
+// blocks, grouped in spans. The emission sums es (emit_sums_size(n_max) entries):
+//   es[b], b < nb:          tile counts of the blocks of b's span before b
+//   es[nb]:                 the pair total
+//   es[nb + 1]:             the number of spans that hold elements
+//   es[nb + 2 + s]:         first pair of span s
+//   launch_emit_sums:     all of es (the span sums scanned by launch_block_scan)
 //   launch_pair_segments: pseg[p] = min(first pair of pose p, capacity), p in [0, P]
 //   launch_emit:          ptile / pk = tile id within the pose / submap index per pair
 uint64_t emit_blocks(uint64_t n_max);
+uint64_t emit_sums_size(uint64_t n_max);
 void launch_emit_sums(hipStream_t s, const uint32_t *snt, const uint32_t *vbase, int n_poses, uint64_t n_max,
-                      uint64_t *sums);
+                      uint64_t *es);
 void launch_pair_segments(hipStream_t s, const uint32_t *snt, const uint32_t *vbase, int n_poses,
-                          const uint64_t *prefix, uint64_t n_max, uint64_t capacity, uint64_t *pseg);
+                          const uint64_t *es, uint64_t n_max, uint64_t capacity, uint64_t *pseg);
 void launch_emit(hipStream_t s, const uint32_t *snt, const uint32_t *sg, const uint32_t *vbase, int n_poses,
-                 const uint2 *rect, int64_t n, uint64_t n_max, const uint64_t *prefix, const TileGrid &tg,
+                 const uint2 *rect, int64_t n, uint64_t n_max, const uint64_t *es, const TileGrid &tg,
                  uint16_t *ptile, uint32_t *pk, uint64_t capacity, int *flags);
 
 // ---- sort.hip ----

@@ -63,7 +63,7 @@ struct gsr_ctx {
     struct Group {
         int64_t p0 = 0, np = 0;        // poses [p0, p0 + np)
         uint64_t vb = 0;               // vbase / pseg: np + 1 entries from here
-        uint64_t es = 0, n_eb = 0;     // emission sums: n_eb + 1 entries from es
+        uint64_t es = 0, n_eb = 0;     // emission sums from es (pair total at es + n_eb)
         uint64_t off = 0;              // list offsets: np * T + 1 entries from here
         uint64_t cst = 0;              // coarse bucket starts and bucketing block bases: np * coarse + 1
                                        // entries each from here
@@ -529,7 +529,7 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         gr.vb = (uint64_t)gr.p0 + g;
         gr.n_eb = gsr::emit_blocks((uint64_t)std::max<int64_t>(1, gr.np * n));
         gr.es = n_es;
-        n_es += gr.n_eb + 1;
+        n_es += gsr::emit_sums_size((uint64_t)std::max<int64_t>(1, gr.np * n));
         gr.off = (uint64_t)gr.p0 * T + g;
         gr.cst = n_cst;
         n_cst += (uint64_t)gr.np * NC + 1;
@@ -624,7 +624,6 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
                                (uint32_t)so, pack, sort_ka + so, sort_va + so, sort_kb + so, sort_vb + so, (uint32_t *)ctx->rcnt.p + ro,
                                (uint32_t *)ctx->roff.p + ro, (uint32_t *)ctx->nv.p + gr.p0, vbase + gr.vb);
         gsr::launch_emit_sums(st, sort_ka + so, vbase + gr.vb, (int)gr.np, gpn, esum + gr.es);
-        gsr::launch_block_scan(st, esum + gr.es, gr.n_eb, nullptr, esum + gr.es + gr.n_eb);
     };
     // ordering, part 2 (pair emission and stable bucketing by tile), then compositing
     auto order_part2 = [&](int g, hipStream_t st) {

@@ -47,9 +47,9 @@ __device__ uint64_t block_inclusive_scan(uint64_t x, uint64_t *s_wave /*[4]*/) {
     return x + add;
 }
 
-// Single block of kBigThreads: exclusive scan of the block sums in place (4 per
-// thread per round); total to out_total. With d_nb only the first *d_nb sums are
-// scanned (the rest are zero and left alone).
+// Exclusive scan of block_sums[0 .. nb) in place, nb = min(*d_nb, nb_max) (nb_max
+// without d_nb), total to *out_total. One block of kBigThreads, kBigItems
+// consecutive entries per thread per round.
 constexpr int kBigThreads = 1024;
 constexpr int kBigItems = 4;
 
@@ -64,10 +64,13 @@ __global__ __launch_bounds__(kBigThreads) void k_scan_blocks(uint64_t *__restric
     __syncthreads();
     for (uint64_t c0 = 0; c0 < nb; c0 += (uint64_t)kBigThreads * kBigItems) {
         const uint64_t i0 = c0 + (uint64_t)threadIdx.x * kBigItems;
+        // loads clamped into range rather than under a branch, so that all of a
+        // thread's loads are in flight at once
         uint64_t v[kBigItems], sum = 0;
 #pragma unroll
         for (int k = 0; k < kBigItems; ++k) {
-            v[k] = i0 + k < nb ? block_sums[i0 + k] : 0;
+            const uint64_t x = block_sums[min(i0 + k, nb - 1)];
+            v[k] = i0 + k < nb ? x : 0;
             sum += v[k];
         }
         uint64_t inc = sum;
