@@ -95,6 +95,25 @@ __global__ __launch_bounds__(kBigThreads) void k_scan_blocks(uint64_t *__restric
     if (threadIdx.x == 0) *out_total = s_carry;
 }
 
+// Lanes of the wave whose `key` (its low kBits bits) equals this lane's, among
+// the lanes with `valid`; 0 when not valid. Per bit: the ballot of the bit, and
+// this lane's bit as a 0 / all-ones word s, so that the lanes agreeing with it
+// are ~(ballot ^ s) in each 32-bit half (a few VALU operations per bit instead
+// of 64-bit selects).
+template <int kBits>
+__device__ __forceinline__ uint64_t match_peers(uint32_t key, bool valid) {
+    const uint64_t v = __ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+    for (int b = 0; b < kBits; ++b) {
+        const uint32_t s = (uint32_t)((int32_t)(key << (31 - b)) >> 31);
+        const uint64_t m = __ballot(s != 0u);
+        lo &= ~((uint32_t)m ^ s);
+        hi &= ~((uint32_t)(m >> 32) ^ s);
+    }
+    return valid ? ((uint64_t)hi << 32 | lo) : 0ull;
+}
+
 // ---- per-pose depth sort: stable LSD radix sort of the visible Gaussians ----
 // Keys are float32 depth bits (depths are above the near plane, so positive,
 // and order like their bits); values are record slots (pose * n + submap
@@ -157,13 +176,7 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_count(RadixSrc src, int sh
         const bool valid = (vmask >> c) & 1u;
         const uint32_t d = (key[c] >> shift) & 0xffu;
         if constexpr (kGroup) {
-            uint64_t same = __ballot(valid);  // valid lanes whose digit equals this lane's
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const uint64_t m = __ballot(bit);
-                same &= bit ? m : ~m;
-            }
+            const uint64_t same = match_peers<8>(d, valid);  // valid lanes whose digit equals this lane's
             // the group's lowest lane adds its size
             if (valid && (same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&s_h[wave][d], (uint32_t)__popcll(same));
         } else {
@@ -413,13 +426,7 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int 
     for (int c = 0; c < kRBChunks; ++c) {
         const bool valid = (vmask >> c) & 1u;
         const uint32_t d = (key[c] >> shift) & 0xffu;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
+        const uint64_t peers = match_peers<8>(d, valid);
         const uint32_t r = (uint32_t)__popcll(peers & lt_mask);
         uint32_t old = 0;
         if (valid && r == 0) old = atomicAdd(&s_cnt[wave][d], (uint32_t)__popcll(peers));
@@ -500,20 +507,6 @@ constexpr int kCBThreads = 64 * kCBWaves;
 constexpr int kCBWave = 1024;                       // pairs per wave, contiguous
 constexpr int kCB = kCBWaves * kCBWave;             // pairs per block
 constexpr int kCBChunks = kCBWave / 64;
-
-// Lanes of the wave whose `key` (its low kBits bits) equals this lane's, among
-// the lanes with `valid`; 0 when not valid.
-template <int kBits>
-__device__ __forceinline__ uint64_t match_peers(uint32_t key, bool valid) {
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < kBits; ++b) {
-        const bool bit = (key >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
-    }
-    return valid ? peers : 0ull;
-}
 
 // A pass: segment i is [seg[i], seg[i+1]) of the input arrays; the key of a
 // pair is (tile >> shift) & mask, one of n_keys.
