@@ -11,7 +11,9 @@
 // the two linear layers, the loss and AdamW are float32 on the vector ALUs.
 //
 // The three convolution products are implicit GEMMs:
-//   forward        rows = output pixels, cols = output channels, K = (tap, c_in)
+//   forward        rows = output channels, cols = output pixels, K = (tap, c_in)
+//                  (so a lane's accumulators hold four consecutive channels of
+//                  one pixel at a time, which leave in one 8-byte store)
 //   backward data  rows = input pixels of one sub-pixel class (for stride 2 the
 //                  four (y mod 2, x mod 2) classes each see a fixed set of taps,
 //                  so no MFMA is spent on taps that skip the pixel),
@@ -54,6 +56,46 @@ __device__ inline bf16x8 pack8(const uint32_t (&w)[4]) {
 }
 __device__ inline f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// relu(acc + bias) of four consecutive output channels as bfloat16 (round to
+// nearest even, as to_bf16: the hardware conversion of finite and infinite
+// values), packed for one 8-byte store.
+__device__ inline uint2 relu_bf16x4(float a0, float a1, float a2, float a3, float4 b) {
+    const f32x2 lo = {fmaxf(a0 + b.x, 0.f), fmaxf(a1 + b.y, 0.f)};
+    const f32x2 hi = {fmaxf(a2 + b.z, 0.f), fmaxf(a3 + b.w, 0.f)};
+    return make_uint2(__builtin_bit_cast(uint32_t, __builtin_convertvector(lo, bf16x2)),
+                      __builtin_bit_cast(uint32_t, __builtin_convertvector(hi, bf16x2)));
+}
+
+// Forward epilogue of a wave whose accumulators hold D[c_out][pixel] (the
+// weights are the MFMA's A operand, the pixels its B operand): lane l holds the
+// pixel in column l % 32 of each pixel block r and, for g = 0..3, the output
+// channels 32 c + 8 g + 4 (l / 32) .. + 3 of each channel block c, which leave as
+// one 8-byte store each. dst[r]: the lane's pixel's first output channel of the
+// wave's channel range (null: the pixel is outside the output).
+template <int RM, int RN>
+__device__ inline void store_relu_bf16(const f32x16 (&acc)[RM][RN], u16 *const (&dst)[RM], const float *bias) {
+    const int kq = (threadIdx.x & 63) >> 5;
+    float4 bv[RN][4];
+#pragma unroll
+    for (int c = 0; c < RN; ++c)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) bv[c][g] = *(const float4 *)(bias + 32 * c + 8 * g + 4 * kq);
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        if (!dst[r]) continue;
+#pragma unroll
+        for (int c = 0; c < RN; ++c)
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                *(uint2 *)(dst[r] + 32 * c + 8 * g + 4 * kq) =
+                    relu_bf16x4(acc[r][c][4 * g], acc[r][c][4 * g + 1], acc[r][c][4 * g + 2], acc[r][c][4 * g + 3],
+                                bv[c][g]);
+    }
 }
 
 template <typename T>
@@ -219,7 +261,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ x, Con
 #pragma unroll
             for (int r = 0; r < RM; ++r)
 #pragma unroll
-                for (int c = 0; c < RN; ++c) acc[r][c] = mfma(a[r], b[c], acc[r][c]);
+                for (int c = 0; c < RN; ++c) acc[r][c] = mfma(b[c], a[r], acc[r][c]);  // D[c_out][pixel]
         }
     } else {
         for (int tap = 0; tap < 9; ++tap) {
@@ -243,34 +285,24 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ x, Con
 #pragma unroll
                 for (int r = 0; r < RM; ++r)
 #pragma unroll
-                    for (int c = 0; c < RN; ++c) acc[r][c] = mfma(a[r], b[c], acc[r][c]);
+                    for (int c = 0; c < RN; ++c) acc[r][c] = mfma(b[c], a[r], acc[r][c]);  // D[c_out][pixel]
             }
         }
     }
+    u16 *dst[RM];
 #pragma unroll
-    for (int c = 0; c < RN; ++c) {
-        const int co = cob + 32 * c + r32;
-        const float bv = bias[co];
-#pragma unroll
-        for (int r = 0; r < RM; ++r)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int64_t m = m0 + 32 * r + 8 * (i / 4) + 4 * kq + (i % 4);
-                if (m < M) {
-                    const float v = acc[r][c][i] + bv;
-                    y[m * CO + co] = to_bf16(v > 0.f ? v : 0.f);
-                }
-            }
-    }
+    for (int r = 0; r < RM; ++r) dst[r] = live[r] ? y + (m0 + 32 * r + r32) * CO + cob : nullptr;
+    store_relu_bf16<RM, RN>(acc, dst, bias + cob);
 }
 
 // Forward for c_in >= 32, LDS-staged: one block computes a TH x TW tile of output
 // pixels of one image for all output channels. Per chunk of 32 input channels
 // the block stages the tile's input halo ((TH-1) S + 3 rows x (TW-1) S + 3
-// columns) in LDS once, and all nine taps read their A fragments from it; per
-// tap it stages that tap's weights [c_out][32], prefetched into registers while
-// the previous tap computes. (Staging all nine taps' weights at once needs up to
-// 135 KB of LDS, one block per compute unit, and measured 1.5x slower.) Rows of
+// columns) in LDS once, and all nine taps read their B fragments from it; the
+// taps' weights [c_out][32] go through two LDS buffers, each tap's fetched into
+// registers two taps ahead, with one barrier per tap. (Staging all nine taps'
+// weights at once needs up to 135 KB of LDS, one block per compute unit, and
+// measured 1.5x slower.) Rows of
 // 32 channels are padded to 80 bytes, so the 16-byte fragment reads of 16
 // consecutive pixels (or channels) hit distinct banks; for stride 2 the halo is
 // stored as even and odd column planes, so that strided pixels are consecutive
@@ -288,7 +320,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const u16 *__restrict__ x,
     constexpr int SLOTS = S == 1 ? HH * HWD : HH * 2 * PW;
     constexpr int ROW = 40;                              // bf16 per LDS row (32 + 8 padding)
     __shared__ __align__(16) u16 s_halo[SLOTS * ROW];
-    __shared__ __align__(16) u16 s_b[CO * ROW];
+    __shared__ __align__(16) u16 s_b[2][CO * ROW];  // the weights of taps t (t & 1) and t + 1
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
@@ -327,31 +359,54 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const u16 *__restrict__ x,
             }
         }
     };
-    auto store_b = [&]() {
+    auto store_b = [&](int buf) {
 #pragma unroll
         for (int j = 0; j < BPER; ++j) {
             const int p = tid + 256 * j;
-            if (p < BPIECES) *(u32x4 *)(s_b + (p >> 2) * ROW + 8 * (p & 3)) = bpre[j];
+            if (p < BPIECES) *(u32x4 *)(s_b[buf] + (p >> 2) * ROW + 8 * (p & 3)) = bpre[j];
         }
     };
 
     for (int ci0 = 0; ci0 < CI; ci0 += 32) {
-        __syncthreads();  // the previous chunk is done with the LDS
-        for (int p = tid; p < HH * HWD * 4; p += 256) {
+        // the halo's 16-byte pieces: all of a thread's loads are issued before its
+        // first LDS store (unconditional, from a clamped address, so that none waits
+        // for another), and land in LDS after the barrier
+        constexpr int HPIECES = HH * HWD * 4, HPER = (HPIECES + 255) / 256;
+        u32x4 hv[HPER];
+#pragma unroll
+        for (int j = 0; j < HPER; ++j) {
+            const int p = min(tid + 256 * j, HPIECES - 1);
             const int pix = p >> 2, q = p & 3;
             const int hy = pix / HWD, hx = pix - hy * HWD;
             const int iy = iy0 + hy, ix = ix0 + hx;
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (iy >= 0 && iy < d.H && ix >= 0 && ix < d.W)
-                v = *(const u32x4 *)(ximg + ((int64_t)iy * d.W + ix) * CI + ci0 + 8 * q);
-            *(u32x4 *)(s_halo + slot_of(hy, hx) * ROW + 8 * q) = v;
+            const bool in = iy >= 0 && iy < d.H && ix >= 0 && ix < d.W;
+            const u32x4 v = *(const u32x4 *)(ximg + ((int64_t)(in ? iy : 0) * d.W + (in ? ix : 0)) * CI + ci0 + 8 * q);
+            const u32x4 z = {0u, 0u, 0u, 0u};
+            hv[j] = in ? v : z;
+        }
+        __syncthreads();  // the previous chunk is done with the LDS
+#pragma unroll
+        for (int j = 0; j < HPER; ++j) {
+            const int p = tid + 256 * j;
+            if (p < HPIECES) {
+                const int pix = p >> 2, q = p & 3;
+                const int hy = pix / HWD, hx = pix - hy * HWD;
+                *(u32x4 *)(s_halo + slot_of(hy, hx) * ROW + 8 * q) = hv[j];
+            }
         }
         fetch_b(0, ci0);
-        store_b();
+        store_b(0);
+        fetch_b(1, ci0);
         __syncthreads();
         for (int tap = 0; tap < 9; ++tap) {
             const int kh = tap / 3, kw = tap - 3 * kh;
-            if (tap < 8) fetch_b(tap + 1, ci0);  // in flight while this tap computes
+            // The weights of tap + 1 (fetched during the previous tap) go to the other
+            // buffer, whose readers (tap - 1) are past the last barrier; those of
+            // tap + 2 are fetched while this tap computes. One barrier per tap.
+            if (tap < 8) {
+                store_b((tap + 1) & 1);
+                if (tap < 7) fetch_b(tap + 2, ci0);
+            }
 #pragma unroll
             for (int kk = 0; kk < 2; ++kk) {
                 bf16x8 a[RM], b[RN];
@@ -362,35 +417,149 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const u16 *__restrict__ x,
                                                  8 * kq));
 #pragma unroll
                 for (int c = 0; c < RN; ++c)
-                    b[c] = __builtin_bit_cast(
-                        bf16x8, *(const u32x4 *)(s_b + (wn * RN * 32 + 32 * c + r32) * ROW + 16 * kk + 8 * kq));
+                    b[c] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(s_b[tap & 1] + (wn * RN * 32 + 32 * c + r32) * ROW +
+                                                                        16 * kk + 8 * kq));
 #pragma unroll
                 for (int r = 0; r < RM; ++r)
 #pragma unroll
-                    for (int c = 0; c < RN; ++c) acc[r][c] = mfma(a[r], b[c], acc[r][c]);
+                    for (int c = 0; c < RN; ++c) acc[r][c] = mfma(b[c], a[r], acc[r][c]);  // D[c_out][pixel]
             }
-            if (tap < 8) {
-                __syncthreads();  // every wave is done with this tap's weights
-                store_b();
-                __syncthreads();
-            }
+            if (tap < 8) __syncthreads();  // tap + 1's weights are in LDS, and this tap's buffer is free
         }
     }
+    u16 *dst[RM];
 #pragma unroll
-    for (int c = 0; c < RN; ++c) {
-        const int co = wn * RN * 32 + 32 * c + r32;
-        const float bv = bias[co];
+    for (int r = 0; r < RM; ++r) {
+        const int oy = oy0 + ty[r], ox = ox0 + tx[r];
+        dst[r] = oy < d.Ho && ox < d.Wo ? y + (((int64_t)n * d.Ho + oy) * d.Wo + ox) * CO + wn * RN * 32 : nullptr;
+    }
+    store_relu_bf16<RM, RN>(acc, dst, bias + wn * RN * 32);
+}
+
+// Forward, persistent: each block stages the nine taps' weights for its COG
+// output channels and all c_in in LDS once, then takes TH x TW output tiles t =
+// blockIdx.x, blockIdx.x + gridDim.x, ... (channel group blockIdx.y). The next
+// tile's input halo (all c_in, in chunks of 32 channels) is loaded into
+// registers while the current tile computes and goes to LDS between two
+// barriers; the taps run with no barrier in between. Halo layout and row padding
+// as in k_conv_fwd_lds.
+template <int CI, int CO, int S, int TH, int TW, int COG, int WGN>
+__global__ __launch_bounds__(256) void k_conv_fwd_pers(const u16 *__restrict__ x, ConvDims d,
+                                                        const u16 *__restrict__ wt, const float *__restrict__ bias,
+                                                        u16 *__restrict__ y, int tiles_x, int tiles_y) {
+    constexpr int WGM = 4 / WGN, BM = TH * TW, NCH = CI / 32;
+    constexpr int RM = BM / (WGM * 32), RN = COG / (WGN * 32);
+    static_assert(RM >= 1 && RN >= 1 && WGM * RM * 32 == BM && WGN * RN * 32 == COG && CO % COG == 0,
+                  "tile, channel group and wave grid");
+    static_assert(CI % 32 == 0, "channel chunks of 32");
+    constexpr int HH = (TH - 1) * S + 3, HWD = (TW - 1) * S + 3;
+    constexpr int PW = S == 1 ? HWD : (HWD + 1) / 2;  // columns per plane
+    constexpr int SLOTS = S == 1 ? HH * HWD : HH * 2 * PW;
+    constexpr int ROW = 40;                              // bf16 per LDS row (32 + 8 padding)
+    __shared__ __align__(16) u16 s_halo[NCH * SLOTS * ROW];  // [chunk][slot][32 + 8]
+    __shared__ __align__(16) u16 s_w[9 * NCH * COG * ROW];   // [tap][chunk][c_out][32 + 8]
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WGM, wn = wave / WGM;
+    const int r32 = lane & 31, kq = lane >> 5;
+    const int co0 = blockIdx.y * COG;
+    const int n_tiles = d.n * tiles_y * tiles_x;
+    auto slot_of = [](int hy, int hx) { return S == 1 ? hy * HWD + hx : (hy * 2 + (hx & 1)) * PW + (hx >> 1); };
+
+    int ty[RM], tx[RM];  // this lane's output pixels (tile-local)
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const int m = wm * RM * 32 + 32 * r + r32;
+        ty[r] = m / TW;
+        tx[r] = m - ty[r] * TW;
+    }
+
+    // the weights, once: piece p = ((tap NCH + chunk) COG + c_out) 4 + quarter
+    constexpr int WPIECES = 9 * NCH * COG * 4;
+    for (int p = tid; p < WPIECES; p += 256) {
+        const int row = p >> 2, co = row % COG, tc = row / COG, tap = tc / NCH, ch = tc - tap * NCH;
+        *(u32x4 *)(s_w + row * ROW + 8 * (p & 3)) =
+            *(const u32x4 *)(wt + ((int64_t)(co0 + co) * 9 + tap) * CI + 32 * ch + 8 * (p & 3));
+    }
+
+    // a tile's halo, piece p = (chunk HH HWD + pixel) 4 + quarter, loaded from
+    // clamped addresses (none under a branch)
+    constexpr int HPIX = HH * HWD, HPIECES = NCH * HPIX * 4, HPER = (HPIECES + 255) / 256;
+    u32x4 hv[HPER];
+    auto load_halo = [&](int t) {
+        const int txi = t % tiles_x, rest = t / tiles_x, tyi = rest % tiles_y, n = rest / tiles_y;
+        const int iy0 = tyi * TH * S - 1, ix0 = txi * TW * S - 1;
+        const u16 *ximg = x + (int64_t)n * d.H * d.W * CI;
+#pragma unroll
+        for (int j = 0; j < HPER; ++j) {
+            const int p = min(tid + 256 * j, HPIECES - 1);
+            const int ch = (p >> 2) / HPIX, pix = (p >> 2) - ch * HPIX, q = p & 3;
+            const int hy = pix / HWD, hx = pix - hy * HWD;
+            const int iy = iy0 + hy, ix = ix0 + hx;
+            const bool in = iy >= 0 && iy < d.H && ix >= 0 && ix < d.W;
+            const u32x4 v =
+                *(const u32x4 *)(ximg + ((int64_t)(in ? iy : 0) * d.W + (in ? ix : 0)) * CI + 32 * ch + 8 * q);
+            const u32x4 z = {0u, 0u, 0u, 0u};
+            hv[j] = in ? v : z;
+        }
+    };
+    int t = blockIdx.x;
+    if (t < n_tiles) load_halo(t);
+    for (; t < n_tiles; t += gridDim.x) {
+        __syncthreads();  // the previous tile is done with the halo (and the weights are stored)
+#pragma unroll
+        for (int j = 0; j < HPER; ++j) {
+            const int p = tid + 256 * j;
+            if (p < HPIECES) {
+                const int ch = (p >> 2) / HPIX, pix = (p >> 2) - ch * HPIX, q = p & 3;
+                const int hy = pix / HWD, hx = pix - hy * HWD;
+                *(u32x4 *)(s_halo + (ch * SLOTS + slot_of(hy, hx)) * ROW + 8 * q) = hv[j];
+            }
+        }
+        __syncthreads();
+        if (t + (int)gridDim.x < n_tiles) load_halo(t + gridDim.x);  // in flight during this tile
+        f32x16 acc[RM][RN];
 #pragma unroll
         for (int r = 0; r < RM; ++r)
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int m = wm * RM * 32 + 32 * r + 8 * (i / 4) + 4 * kq + (i % 4);
-                const int oy = oy0 + m / TW, ox = ox0 + m % TW;
-                if (oy < d.Ho && ox < d.Wo) {
-                    const float v = acc[r][c][i] + bv;
-                    y[(((int64_t)n * d.Ho + oy) * d.Wo + ox) * CO + co] = to_bf16(v > 0.f ? v : 0.f);
+            for (int c = 0; c < RN; ++c)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[r][c][i] = 0.f;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int kh = tap / 3, kw = tap - 3 * kh;
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) {
+                    bf16x8 a[RN], b[RM];
+#pragma unroll
+                    for (int c = 0; c < RN; ++c)
+                        a[c] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(s_w +
+                                                                          ((tap * NCH + ch) * COG + wn * RN * 32 +
+                                                                           32 * c + r32) * ROW +
+                                                                          16 * kk + 8 * kq));
+#pragma unroll
+                    for (int r = 0; r < RM; ++r)
+                        b[r] = __builtin_bit_cast(
+                            bf16x8, *(const u32x4 *)(s_halo + (ch * SLOTS + slot_of(ty[r] * S + kh, tx[r] * S + kw)) *
+                                                                  ROW +
+                                                     16 * kk + 8 * kq));
+#pragma unroll
+                    for (int r = 0; r < RM; ++r)
+#pragma unroll
+                        for (int c = 0; c < RN; ++c) acc[r][c] = mfma(a[c], b[r], acc[r][c]);  // D[c_out][pixel]
                 }
-            }
+        }
+        const int txi = t % tiles_x, rest = t / tiles_x, tyi = rest % tiles_y, n = rest / tiles_y;
+        u16 *dst[RM];
+#pragma unroll
+        for (int r = 0; r < RM; ++r) {
+            const int oy = tyi * TH + ty[r], ox = txi * TW + tx[r];
+            dst[r] = oy < d.Ho && ox < d.Wo ? y + (((int64_t)n * d.Ho + oy) * d.Wo + ox) * CO + co0 + wn * RN * 32
+                                           : nullptr;
+        }
+        store_relu_bf16<RM, RN>(acc, dst, bias + co0 + wn * RN * 32);
     }
 }
 
@@ -712,6 +881,19 @@ void fwd_layer_lds(hipStream_t s, const u16 *x, ConvDims d, const u16 *wt, const
     hipLaunchKernelGGL((k_conv_fwd_lds<CI, CO, S, TH, TW, WGN>), grid, dim3(256), 0, s, x, d, wt, bias, y);
 }
 
+template <int CI, int CO, int S, int TH, int TW, int COG, int WGN>
+void fwd_layer_pers(hipStream_t s, const u16 *x, ConvDims d, const u16 *wt, const float *bias, u16 *y,
+                    int blocks_per_cu) {
+    const int tiles_x = (d.Wo + TW - 1) / TW, tiles_y = (d.Ho + TH - 1) / TH;
+    const int n_tiles = d.n * tiles_x * tiles_y;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // as many blocks as fit on the device at once (their LDS), each taking tiles in turn
+    const int blocks = std::max(1, std::min(n_tiles, blocks_per_cu * cus));
+    hipLaunchKernelGGL((k_conv_fwd_pers<CI, CO, S, TH, TW, COG, WGN>), dim3((unsigned)blocks, CO / COG), dim3(256), 0,
+                       s, x, d, wt, bias, y, tiles_x, tiles_y);
+}
+
 template <int CI, int CO, int S, int RM, int RN, int WGN>
 void bwd_data_layer(hipStream_t s, const u16 *dy, ConvDims d, const u16 *wd, const u16 *a_in, u16 *dx) {
     constexpr int BM = (4 / WGN) * RM * 32;
@@ -772,8 +954,8 @@ void launch_scorer_forward(hipStream_t s, const ScorerBufs &b, int B, float *sco
     auto D = [&](int l) { return ConvDims{B, dm[l][0], dm[l][1], dm[l + 1][0], dm[l + 1][1]}; };
     const float *p = b.params;
     fwd_layer<2, 32, 2, 2, 1, 1>(s, b.x, D(0), b.wt + b.w_off[0], p + b.b_off[0], b.act[1]);
-    fwd_layer_lds<32, 64, 1, 16, 16, 1>(s, b.act[1], D(1), b.wt + b.w_off[1], p + b.b_off[1], b.act[2]);
-    fwd_layer_lds<64, 64, 2, 8, 16, 1>(s, b.act[2], D(2), b.wt + b.w_off[2], p + b.b_off[2], b.act[3]);
+    fwd_layer_pers<32, 64, 1, 16, 16, 64, 1>(s, b.act[1], D(1), b.wt + b.w_off[1], p + b.b_off[1], b.act[2], 2);
+    fwd_layer_pers<64, 64, 2, 8, 8, 64, 2>(s, b.act[2], D(2), b.wt + b.w_off[2], p + b.b_off[2], b.act[3], 1);
     fwd_layer_lds<64, 128, 1, 8, 16, 2>(s, b.act[3], D(3), b.wt + b.w_off[3], p + b.b_off[3], b.act[4]);
     fwd_layer_lds<128, 128, 2, 8, 16, 2>(s, b.act[4], D(4), b.wt + b.w_off[4], p + b.b_off[4], b.act[5]);
     const int npix = dm[5][0] * dm[5][1];
