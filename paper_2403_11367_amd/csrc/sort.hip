@@ -210,45 +210,97 @@ __device__ uint32_t block_exclusive_scan_u32(uint32_t x, uint32_t *s_wave /*[4]*
     return add + inc - x;
 }
 
-// Per pose (one block, thread = digit): off[(p * nbp + j) * 256 + d] = position,
-// relative to the pose's first element, of radix block j's first element with
-// digit d (digits in order, blocks in order within a digit).
-__global__ __launch_bounds__(kThreads) void k_radix_offsets(const uint32_t *__restrict__ cnt, uint32_t nbp,
-                                                            const uint32_t *__restrict__ vbase,
-                                                            uint32_t *__restrict__ off) {
-    __shared__ uint32_t s_wave[4];
-    const int p = blockIdx.x;
-    const int d = threadIdx.x;
-    const uint32_t nb = (uint32_t)(((uint64_t)vbase[p + 1] - vbase[p] + kRB - 1) / kRB);
-    const uint32_t *c = cnt + (uint64_t)p * nbp * kDigits + d;
-    // 8 blocks per step, so several loads are in flight per thread
-    uint32_t tot = 0, j = 0;
-    for (; j + 8 <= nb; j += 8) {
-        uint32_t v[8];
+// Offsets of one segment's blocks per key, by a block of 256 kGroups threads: cnt[j * K +
+// k] (block j < nb of the segment, key k < K <= 256) are its blocks' key counts;
+// off[j * K + k] <- the position, relative to the segment's first element, of
+// block j's first element with key k (keys in order, blocks in order within a
+// key); off may be cnt. Returns to thread k < K of the first group the start of
+// key k's run (relative), and to every thread the segment's total in *all. The
+// blocks are split over the kGroups groups of 256 threads (thread = key), which
+// sum their share, 8 blocks per step with the loads in flight together, and
+// then write it from their prefix: a chain of nb / (8 kGroups) dependent loads
+// instead of nb / 8 (for segments of many blocks).
+template <int kGroups>
+__device__ uint32_t seg_key_offsets(const uint32_t *cnt, uint32_t *off, uint32_t nb, int K,
+                                    uint32_t (*s_part)[256] /*[kGroups][256]*/, uint32_t *s_wave /*[4]*/,
+                                    uint32_t *all) {
+    const int g = threadIdx.x >> 8, k = threadIdx.x & 255;
+    const uint32_t per = (nb + kGroups - 1) / kGroups;
+    const uint32_t j0 = min(nb, g * per), j1 = min(nb, j0 + per);
+    uint32_t tot = 0;
+    if (k < K) {
+        for (uint32_t j = j0; j < j1; j += 8) {
+            uint32_t v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = c[(uint64_t)(j + u) * kDigits];
+            for (int u = 0; u < 8; ++u) v[u] = cnt[(uint64_t)min(j + u, j1 - 1) * K + k];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) tot += v[u];
-    }
-    for (; j < nb; ++j) tot += c[(uint64_t)j * kDigits];
-    uint32_t all = 0;
-    uint32_t run = block_exclusive_scan_u32(tot, s_wave, &all);
-    uint32_t *o = off + (uint64_t)p * nbp * kDigits + d;
-    for (j = 0; j + 8 <= nb; j += 8) {
-        uint32_t v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = c[(uint64_t)(j + u) * kDigits];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            o[(uint64_t)(j + u) * kDigits] = run;
-            run += v[u];
+            for (int u = 0; u < 8; ++u) tot += j + u < j1 ? v[u] : 0u;
         }
     }
-    for (; j < nb; ++j) {
-        const uint32_t x = c[(uint64_t)j * kDigits];
-        o[(uint64_t)j * kDigits] = run;
-        run += x;
+    s_part[g][k] = tot;
+    __syncthreads();
+    // key totals, scanned over the keys by the first 256 threads
+    uint32_t key_tot = 0;
+    if (g == 0) {
+#pragma unroll
+        for (int h = 0; h < kGroups; ++h) key_tot += s_part[h][k];
     }
+    uint32_t inc = key_tot;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (g == 0 && lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    const uint32_t total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    uint32_t start = 0;
+    if (g == 0) {
+        start = inc - key_tot;
+        for (int w = 0; w < wave; ++w) start += s_wave[w];
+        // each group's first position per key
+        uint32_t run = start;
+#pragma unroll
+        for (int h = 0; h < kGroups; ++h) {
+            const uint32_t x = s_part[h][k];
+            s_part[h][k] = run;
+            run += x;
+        }
+    }
+    __syncthreads();
+    if (k < K) {
+        uint32_t run = s_part[g][k];
+        for (uint32_t j = j0; j < j1; j += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = cnt[(uint64_t)min(j + u, j1 - 1) * K + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (j + u < j1) {
+                    off[(uint64_t)(j + u) * K + k] = run;
+                    run += v[u];
+                }
+        }
+    }
+    *all = total;
+    return start;
+}
+
+// Per pose (one block): off[(p * nbp + j) * 256 + d] = position, relative to the
+// pose's first element, of radix block j's first element with digit d (digits in
+// order, blocks in order within a digit).
+constexpr int kOffGroups = 4;  // radix blocks per pose: tens to hundreds
+__global__ __launch_bounds__(256 * kOffGroups) void k_radix_offsets(const uint32_t *__restrict__ cnt, uint32_t nbp,
+                                                                   const uint32_t *__restrict__ vbase,
+                                                                   uint32_t *__restrict__ off) {
+    __shared__ uint32_t s_part[kOffGroups][256];
+    __shared__ uint32_t s_wave[4];
+    const int p = blockIdx.x;
+    const uint32_t nb = (uint32_t)(((uint64_t)vbase[p + 1] - vbase[p] + kRB - 1) / kRB);
+    uint32_t all = 0;
+    (void)seg_key_offsets<kOffGroups>(cnt + (uint64_t)p * nbp * kDigits, off + (uint64_t)p * nbp * kDigits, nb, kDigits, s_part,
+                          s_wave, &all);
 }
 
 // vbase[p] = sum of nv[q] over q < p, for p in [0, P]. One block.
@@ -289,13 +341,27 @@ __global__ __launch_bounds__(kRegionThreads) void k_region_offsets(const uint32_
     uint32_t *ro = reg_off + (int64_t)p * n_regions;
     const int64_t per = (n_regions + kRegionThreads - 1) / kRegionThreads;  // consecutive regions per thread
     const int64_t r0 = (int64_t)threadIdx.x * per, r1 = min(r0 + per, n_regions);
+    // 8 regions per step, the loads in flight together (clamped, not under a branch)
     uint32_t sum = 0;
-    for (int64_t r = r0; r < r1; ++r) sum += vc[r];
+    for (int64_t r = r0; r < r1; r += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = vc[min(r + u, r1 - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sum += r + u < r1 ? v[u] : 0u;
+    }
     uint32_t all = 0;
     uint32_t run = block_exclusive_scan_waves<kRegionThreads / 64>(sum, s_wave, &all);
-    for (int64_t r = r0; r < r1; ++r) {
-        ro[r] = run;
-        run += vc[r];
+    for (int64_t r = r0; r < r1; r += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = vc[min(r + u, r1 - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (r + u < r1) {
+                ro[r + u] = run;
+                run += v[u];
+            }
     }
     if (threadIdx.x == 0) nv[p] = all;
 }
@@ -519,34 +585,49 @@ struct SegPass {
 };
 
 // block_base[i] = sum over j < i of ceil(len(j) / kCB), for i in [0, n_seg], and
-// bseg[gb] = the segment of block gb for gb < block_base[n_seg]. One block.
-__global__ __launch_bounds__(kThreads) void k_seg_blocks(const uint64_t *__restrict__ seg, int n_seg,
-                                                         uint32_t *__restrict__ block_base,
-                                                         uint32_t *__restrict__ bseg) {
-    __shared__ uint64_t s_wave[4];
-    __shared__ uint64_t s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (int c0 = 0; c0 <= n_seg; c0 += kThreads) {
-        const int i = c0 + threadIdx.x;
-        uint64_t nb = 0;
-        if (i < n_seg) nb = (seg[i + 1] - seg[i] + kCB - 1) / kCB;
-        const uint64_t inc = block_inclusive_scan(nb, s_wave);
-        const uint64_t carry = s_carry;
-        const uint32_t first = (uint32_t)(carry + inc - nb);
-        if (i <= n_seg) block_base[i] = first;
-        // many short segments: every thread maps its own segment's blocks
-        if (n_seg > kThreads)
-            for (uint64_t j = 0; j < nb; ++j) bseg[first + j] = (uint32_t)i;
-        __syncthreads();
-        if (threadIdx.x == kThreads - 1) s_carry = carry + inc;
-        __syncthreads();
+// bseg[gb] = the segment of block gb for gb < block_base[n_seg]. One block; each
+// thread takes a run of consecutive segments, 8 at a time with the loads in
+// flight together.
+constexpr int kSegBlkThreads = 1024;
+__global__ __launch_bounds__(kSegBlkThreads) void k_seg_blocks(const uint64_t *__restrict__ seg, int n_seg,
+                                                               uint32_t *__restrict__ block_base,
+                                                               uint32_t *__restrict__ bseg) {
+    __shared__ uint32_t s_wave[kSegBlkThreads / 64];
+    const int per = (n_seg + kSegBlkThreads - 1) / kSegBlkThreads;
+    const int i0 = min(n_seg, (int)threadIdx.x * per), i1 = min(n_seg, i0 + per);
+    uint32_t sum = 0;
+    for (int c = i0; c < i1; c += 8) {
+        uint64_t a[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) a[u] = seg[min(c + u, n_seg)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (c + u < i1) sum += (uint32_t)((a[u + 1] - a[u] + kCB - 1) / kCB);
     }
-    if (n_seg <= kThreads) {
+    uint32_t all = 0;
+    uint32_t run = block_exclusive_scan_waves<kSegBlkThreads / 64>(sum, s_wave, &all);
+    for (int c = i0; c < i1; c += 8) {
+        uint64_t a[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) a[u] = seg[min(c + u, n_seg)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (c + u < i1) {
+                const uint32_t nb = (uint32_t)((a[u + 1] - a[u] + kCB - 1) / kCB);
+                block_base[c + u] = run;
+                // many short segments: every thread maps its own segments' blocks
+                if (n_seg > kSegBlkThreads / 4)
+                    for (uint32_t j = 0; j < nb; ++j) bseg[run + j] = (uint32_t)(c + u);
+                run += nb;
+            }
+    }
+    if (threadIdx.x == 0) block_base[n_seg] = all;
+    if (n_seg <= kSegBlkThreads / 4) {
         // few long segments: a wave maps one segment at a time, 64 blocks per store
         // (the block's own stores of block_base are visible after the barrier)
+        __syncthreads();
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        for (int i = wave; i < n_seg; i += kThreads / 64) {
+        for (int i = wave; i < n_seg; i += kSegBlkThreads / 64) {
             const uint32_t b0 = block_base[i], b1 = block_base[i + 1];
             for (uint32_t gb = b0 + lane; gb < b1; gb += 64) bseg[gb] = (uint32_t)i;
         }
@@ -619,54 +700,26 @@ __global__ __launch_bounds__(kCBThreads) void k_seg_count(SegPass ps, const uint
     }
 }
 
-// One block per segment, thread = key: cnt[gb][k] <- position, relative to the
-// segment's first pair, of block gb's first pair with key k (keys in order,
-// blocks in order within a key). The start of key k's run (absolute) goes to
+// One block per segment: cnt[gb][k] <- position, relative to the segment's first
+// pair, of block gb's first pair with key k (keys in order, blocks in order within
+// a key). The start of key k's run (absolute) goes to
 // starts[(i / per_row) * row + (i % per_row) * n_keys + k] where that column is
 // below `row`; the block of the last segment also writes
 // starts[(n_seg / per_row) * row] = seg[n_seg].
-__global__ __launch_bounds__(kThreads) void k_seg_offsets(SegPass ps, uint32_t *__restrict__ cnt,
-                                                          const uint32_t *__restrict__ block_base, int per_row,
-                                                          int row, uint64_t *__restrict__ starts) {
+template <int kGroups>
+__global__ __launch_bounds__(256 * kGroups) void k_seg_offsets(SegPass ps, uint32_t *__restrict__ cnt,
+                                                               const uint32_t *__restrict__ block_base, int per_row,
+                                                               int row, uint64_t *__restrict__ starts) {
+    __shared__ uint32_t s_part[kGroups][256];
     __shared__ uint32_t s_wave[4];
-    const int i = blockIdx.x, k = threadIdx.x;
+    const int i = blockIdx.x;
     const uint32_t g0 = block_base[i], g1 = block_base[i + 1];
-    // 8 blocks per step, so several loads are in flight per thread
-    uint32_t tot = 0;
-    if (k < ps.n_keys) {
-        uint32_t g = g0;
-        for (; g + 8 <= g1; g += 8) {
-            uint32_t v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = cnt[(uint64_t)(g + u) * ps.n_keys + k];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) tot += v[u];
-        }
-        for (; g < g1; ++g) tot += cnt[(uint64_t)g * ps.n_keys + k];
-    }
     uint32_t all = 0;
-    uint32_t run = block_exclusive_scan_u32(tot, s_wave, &all);
+    uint32_t *c = cnt + (uint64_t)g0 * ps.n_keys;
+    const uint32_t start = seg_key_offsets<kGroups>(c, c, g1 - g0, ps.n_keys, s_part, s_wave, &all);
+    const int k = threadIdx.x;  // (first group: thread = key)
     const int col = (i % per_row) * ps.n_keys + k;
-    if (k < ps.n_keys) {
-        if (col < row) starts[(uint64_t)(i / per_row) * row + col] = ps.seg[i] + run;
-        uint32_t g = g0;
-        for (; g + 8 <= g1; g += 8) {
-            uint32_t v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = cnt[(uint64_t)(g + u) * ps.n_keys + k];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                cnt[(uint64_t)(g + u) * ps.n_keys + k] = run;
-                run += v[u];
-            }
-        }
-        for (; g < g1; ++g) {
-            const uint64_t j = (uint64_t)g * ps.n_keys + k;
-            const uint32_t x = cnt[j];
-            cnt[j] = run;
-            run += x;
-        }
-    }
+    if (k < ps.n_keys && col < row) starts[(uint64_t)(i / per_row) * row + col] = ps.seg[i] + start;
     if (k == 0 && i == ps.n_seg - 1) starts[(uint64_t)(ps.n_seg / per_row) * row] = ps.seg[ps.n_seg];
 }
 
@@ -765,14 +818,21 @@ void launch_seg_pass(hipStream_t s, const SegPass &ps, uint64_t n_blocks, uint32
                      const uint32_t *vals, uint16_t *out_tiles, uint32_t *out_vals) {
     int bits = 0;
     while ((1 << bits) < ps.n_keys) ++bits;
-    hipLaunchKernelGGL(k_seg_blocks, dim3(1), dim3(kThreads), 0, s, ps.seg, ps.n_seg, block_base, bseg);
+    hipLaunchKernelGGL(k_seg_blocks, dim3(1), dim3(kSegBlkThreads), 0, s, ps.seg, ps.n_seg, block_base, bseg);
+    // few segments (the poses) of many blocks each: the offsets split each segment's
+    // blocks over four thread groups
+    const bool few_long = ps.n_seg <= 256;
     switch (bits) {
 #define GSR_SEG(B)                                                                                                 \
     case B:                                                                                                        \
         hipLaunchKernelGGL(k_seg_count, dim3((unsigned)n_blocks), dim3(kCBThreads), 0, s, ps, block_base, bseg,     \
                            tiles, cnt);                                                                            \
-        hipLaunchKernelGGL(k_seg_offsets, dim3((unsigned)ps.n_seg), dim3(kThreads), 0, s, ps, cnt, block_base,      \
-                           per_row, row, starts);                                                                  \
+        if (few_long)                                                                                              \
+            hipLaunchKernelGGL(k_seg_offsets<4>, dim3((unsigned)ps.n_seg), dim3(1024), 0, s, ps, cnt, block_base,   \
+                               per_row, row, starts);                                                              \
+        else                                                                                                       \
+            hipLaunchKernelGGL(k_seg_offsets<1>, dim3((unsigned)ps.n_seg), dim3(256), 0, s, ps, cnt, block_base,    \
+                               per_row, row, starts);                                                              \
         hipLaunchKernelGGL(k_seg_scatter<B>, dim3((unsigned)n_blocks), dim3(kCBThreads), 0, s, ps, block_base, bseg, \
                            cnt, tiles, vals, out_tiles, out_vals);                                                 \
         break;
@@ -880,7 +940,8 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
             hipLaunchKernelGGL(k_radix_count<true>, grid, dim3(kRBThreads), 0, s, src, shift, nbp, rcnt);
         else
             hipLaunchKernelGGL(k_radix_count<false>, grid, dim3(kRBThreads), 0, s, src, shift, nbp, rcnt);
-        hipLaunchKernelGGL(k_radix_offsets, dim3((unsigned)n_poses), dim3(kThreads), 0, s, rcnt, nbp, vbase, roff);
+        hipLaunchKernelGGL(k_radix_offsets, dim3((unsigned)n_poses), dim3(256 * kOffGroups), 0, s, rcnt, nbp, vbase,
+                           roff);
         uint32_t *ko = (pass & 1) ? ka : kb, *vo = (pass & 1) ? va : vb;
         if (pass == 3)
             hipLaunchKernelGGL(k_radix_scatter<true>, sgrid, dim3(kRBThreads), 0, s, src, shift, nbp, n_poses, roff,
