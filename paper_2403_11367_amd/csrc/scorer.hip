@@ -168,23 +168,57 @@ __global__ __launch_bounds__(1024) void k_scorer_input(const float *__restrict__
     __shared__ double red[16];
     const int n = h * w;
     const float *src = rgb + (int64_t)blockIdx.x * 3 * n;
+    // four pixels per thread and step, their loads in flight together (clamped)
+    const int stride = blockDim.x;
+    auto grey4 = [&](int i0, float (&gv)[4]) {
+        float r[4], g[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = min(i0 + u * stride, n - 1);
+            r[u] = src[i];
+            g[u] = src[n + i];
+            b[u] = src[2 * n + i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) gv[u] = grey_of(r[u], g[u], b[u]);
+    };
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += grey_of(src[i], src[n + i], src[2 * n + i]);
+    for (int i0 = threadIdx.x; i0 < n; i0 += 4 * stride) {
+        float gv[4];
+        grey4(i0, gv);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + u * stride < n) s += gv[u];
+    }
     const double sum = block_sum(s, red), mu = sum / n;
     double m2 = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double d = grey_of(src[i], src[n + i], src[2 * n + i]) - mu;
-        m2 += d * d;
+    for (int i0 = threadIdx.x; i0 < n; i0 += 4 * stride) {
+        float gv[4];
+        grey4(i0, gv);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + u * stride < n) {
+                const double d = gv[u] - mu;
+                m2 += d * d;
+            }
     }
     m2 = block_sum(m2, red);
     float mean, rstd;
     image_stats(sum, m2, n, mean, rstd);
     const float qm = qstats[0], qr = qstats[1];
     uint32_t *dst = (uint32_t *)(x + (int64_t)blockIdx.x * 2 * n);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const float g = (grey_of(src[i], src[n + i], src[2 * n + i]) - mean) * rstd;
-        const float v = (q[i] - qm) * qr;
-        dst[i] = (uint32_t)to_bf16(g) | ((uint32_t)to_bf16(v) << 16);
+    for (int i0 = threadIdx.x; i0 < n; i0 += 4 * stride) {
+        float gv[4], qv[4];
+        grey4(i0, gv);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) qv[u] = q[min(i0 + u * stride, n - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + u * stride < n) {
+                const float g = (gv[u] - mean) * rstd;
+                const float v = (qv[u] - qm) * qr;
+                dst[i0 + u * stride] = (uint32_t)to_bf16(g) | ((uint32_t)to_bf16(v) << 16);
+            }
     }
 }
 
@@ -744,15 +778,39 @@ __global__ __launch_bounds__(256) void k_head_fwd(const u16 *__restrict__ a5, in
                                                    const float *__restrict__ b1, const float *__restrict__ w2,
                                                    const float *__restrict__ b2, float *__restrict__ g_out,
                                                    float *__restrict__ h_out, float *__restrict__ score) {
-    __shared__ float s_part[256], s_g[kFeat], s_h[kHidden], red[4];
-    const int t = threadIdx.x, c = t & (kFeat - 1), half = t >> 7;
-    const u16 *src = a5 + (int64_t)blockIdx.x * npix * kFeat + c;
-    float s = 0.f;
-    for (int p = half; p < npix; p += 2) s += from_bf16(src[(int64_t)p * kFeat]);
-    s_part[t] = s;
+    static_assert(kFeat == 128, "16 groups of 8 channels");
+    __shared__ float s_part[16][kFeat], s_g[kFeat], s_h[kHidden], red[4];
+    const int t = threadIdx.x;
+    // global average pool: thread t sums channels 8 (t % 16) .. + 7 (one 16-byte
+    // load per pixel) over pixels t / 16, t / 16 + 16, ..., four pixels per step
+    // with their loads in flight together
+    {
+        const int cg = t & 15, pg = t >> 4;
+        const u16 *src = a5 + (int64_t)blockIdx.x * npix * kFeat + 8 * cg;
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int p0 = pg; p0 < npix; p0 += 64) {
+            u32x4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = *(const u32x4 *)(src + (int64_t)min(p0 + 16 * u, npix - 1) * kFeat);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (p0 + 16 * u < npix) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        acc[2 * k] += __uint_as_float(v[u][k] << 16);
+                        acc[2 * k + 1] += __uint_as_float(v[u][k] & 0xffff0000u);
+                    }
+                }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s_part[pg][8 * cg + k] = acc[k];
+    }
     __syncthreads();
     if (t < kFeat) {
-        const float g = (s_part[t] + s_part[t + kFeat]) / (float)npix;
+        float sum = 0.f;
+#pragma unroll
+        for (int pg = 0; pg < 16; ++pg) sum += s_part[pg][t];
+        const float g = sum / (float)npix;
         s_g[t] = g;
         g_out[(int64_t)blockIdx.x * kFeat + t] = g;
     }
@@ -760,7 +818,11 @@ __global__ __launch_bounds__(256) void k_head_fwd(const u16 *__restrict__ a5, in
     if (t < kHidden) {
         float v = b1[t];
         const float *row = w1 + t * kFeat;
-        for (int i = 0; i < kFeat; ++i) v += row[i] * s_g[i];
+#pragma unroll 8
+        for (int i = 0; i < kFeat; i += 4) {
+            const float4 w = *(const float4 *)(row + i);
+            v += w.x * s_g[i] + w.y * s_g[i + 1] + w.z * s_g[i + 2] + w.w * s_g[i + 3];
+        }
         v = v > 0.f ? v : 0.f;
         s_h[t] = v;
         h_out[(int64_t)blockIdx.x * kHidden + t] = v;

@@ -844,26 +844,42 @@ void launch_seg_pass(hipStream_t s, const SegPass &ps, uint64_t n_blocks, uint32
 
 // keep_off[l] = kept states of lists j < l (one per kKeepRecords records beyond
 // the first kKeepRecords of a list), l in [0, n_lists]. One block.
-__global__ __launch_bounds__(kThreads) void k_keep_offsets(const uint64_t *__restrict__ offsets, uint64_t capacity,
-                                                           uint32_t n_lists, uint32_t *__restrict__ keep_off) {
-    __shared__ uint64_t s_wave[4];
-    // kept states of list l: one per whole kKeepRecords before its last record
-    auto kept = [&](uint32_t l) -> uint64_t {
-        if (l >= n_lists) return 0;
-        const uint64_t b = min(offsets[l], capacity), e = min(offsets[l + 1], capacity);
-        return e > b + kKeepRecords ? (e - b - 1) / kKeepRecords : 0;
+constexpr int kKeepThreads = 1024;
+__global__ __launch_bounds__(kKeepThreads) void k_keep_offsets(const uint64_t *__restrict__ offsets,
+                                                               uint64_t capacity, uint32_t n_lists,
+                                                               uint32_t *__restrict__ keep_off) {
+    __shared__ uint32_t s_wave[kKeepThreads / 64];
+    // kept states of a list [b, e): one per whole kKeepRecords before its last record
+    auto kept = [&](uint64_t b, uint64_t e) -> uint32_t {
+        b = min(b, capacity);
+        e = min(e, capacity);
+        return e > b + kKeepRecords ? (uint32_t)((e - b - 1) / kKeepRecords) : 0u;
     };
-    // thread t: consecutive entries [l0, l1) of keep_off[0 .. n_lists]
-    const uint32_t per = (n_lists + 1 + kThreads - 1) / kThreads;
-    const uint32_t l0 = threadIdx.x * per, l1 = min(l0 + per, n_lists + 1);
-    uint64_t sum = 0;
-#pragma unroll 8
-    for (uint32_t l = l0; l < l1; ++l) sum += kept(l);
-    uint64_t run = block_inclusive_scan(sum, s_wave) - sum;
-#pragma unroll 8
-    for (uint32_t l = l0; l < l1; ++l) {
-        keep_off[l] = (uint32_t)run;
-        run += kept(l);
+    // thread t: consecutive entries [l0, l1) of keep_off[0 .. n_lists], 8 lists per
+    // step with the loads in flight together (clamped, not under a branch)
+    const uint32_t per = (n_lists + 1 + kKeepThreads - 1) / kKeepThreads;
+    const uint32_t l0 = min(n_lists + 1, threadIdx.x * per), l1 = min(l0 + per, n_lists + 1);
+    uint32_t sum = 0;
+    for (uint32_t l = l0; l < l1; l += 8) {
+        uint64_t o[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) o[u] = offsets[min(l + u, n_lists)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (l + u < l1 && l + u < n_lists) sum += kept(o[u], o[u + 1]);
+    }
+    uint32_t all = 0;
+    uint32_t run = block_exclusive_scan_waves<kKeepThreads / 64>(sum, s_wave, &all);
+    for (uint32_t l = l0; l < l1; l += 8) {
+        uint64_t o[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) o[u] = offsets[min(l + u, n_lists)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (l + u < l1) {
+                keep_off[l + u] = run;
+                if (l + u < n_lists) run += kept(o[u], o[u + 1]);
+            }
     }
 }
 
@@ -879,7 +895,7 @@ __global__ __launch_bounds__(kThreads) void k_keep_items(const uint32_t *__restr
 
 void launch_keep_offsets(hipStream_t s, const uint64_t *offsets, uint64_t capacity, uint32_t n_lists,
                          uint32_t *keep_off) {
-    hipLaunchKernelGGL(k_keep_offsets, dim3(1), dim3(kThreads), 0, s, offsets, capacity, n_lists, keep_off);
+    hipLaunchKernelGGL(k_keep_offsets, dim3(1), dim3(kKeepThreads), 0, s, offsets, capacity, n_lists, keep_off);
 }
 
 void launch_keep_items(hipStream_t s, const uint32_t *keep_off, uint32_t n_lists, uint32_t *items) {

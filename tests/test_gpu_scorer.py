@@ -161,16 +161,18 @@ def test_inputs_and_pooling_match_oracle(ctx):
 
 
 def test_training_reduces_the_loss(ctx):
-    """A few AdamW steps on one batch fit its labels: the loss falls below a
-    fifth of its starting value."""
+    """AdamW steps on one batch fit its labels: the loss falls below a fifth of
+    its starting value. (At 60 steps the loss sits at 0.20 of the start, so the
+    summation order of the float32 kernels decided the outcome; by 100 it is
+    below 0.003 of it.)"""
     import torch
-    say("scorer training: 60 steps on one batch of 16 at 47x88")
+    say("scorer training: 100 steps on one batch of 16 at 47x88")
     B, h, w = 16, 47, 88
     sc = _scorer(ctx, h, w, B, _params(11))
     xg, _ = _inputs(6, B, h, w)
     labels = torch.from_numpy(np.random.default_rng(6).uniform(-0.5, 0.5, B).astype(np.float32)).cuda()
     opt = sc.adamw_cfg(lr=1e-3, weight_decay=0.0)
-    losses = [float(sc.train_step(xg, labels, opt).cpu()[0]) for _ in range(60)]
+    losses = [float(sc.train_step(xg, labels, opt).cpu()[0]) for _ in range(100)]
     say(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert losses[-1] < 0.2 * losses[0]
     sc.close()
