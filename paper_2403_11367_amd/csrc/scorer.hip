@@ -273,11 +273,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ x, Con
                 uint32_t wv[4];
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
+                    // (loaded from a clamped address, not under a branch, so that the
+                    // eight loads of a lane are in flight together)
                     const int tap = 8 * sub + 4 * kq + jj;
                     const int iy = iy0[r] + tap / 3, ix = ix0[r] + tap % 3;
                     const bool ok = live[r] && tap < 9 && iy >= 0 && iy < d.H && ix >= 0 && ix < d.W;
                     const int64_t o = img[r] + (ok ? (int64_t)iy * d.W + ix : 0);
-                    wv[jj] = ok ? *(const uint32_t *)(x + o * 2) : 0u;
+                    const uint32_t v = *(const uint32_t *)(x + o * 2);
+                    wv[jj] = ok ? v : 0u;
                 }
                 a[r] = pack8(wv);
             }
@@ -288,7 +291,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ x, Con
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     const int tap = 8 * sub + 4 * kq + jj;
-                    wv[jj] = tap < 9 ? *(const uint32_t *)(wt + co * 18 + 2 * (tap < 9 ? tap : 0)) : 0u;
+                    const uint32_t v = *(const uint32_t *)(wt + co * 18 + 2 * (tap < 9 ? tap : 0));
+                    wv[jj] = tap < 9 ? v : 0u;
                 }
                 b[c] = pack8(wv);
             }
