@@ -77,14 +77,27 @@ __device__ inline uint2 relu_bf16x4(float a0, float a1, float a2, float a3, floa
 // channels 32 c + 8 g + 4 (l / 32) .. + 3 of each channel block c, which leave as
 // one 8-byte store each. dst[r]: the lane's pixel's first output channel of the
 // wave's channel range (null: the pixel is outside the output).
-template <int RM, int RN>
-__device__ inline void store_relu_bf16(const f32x16 (&acc)[RM][RN], u16 *const (&dst)[RM], const float *bias) {
+// The biases a lane's accumulators need (its RN channel blocks from `bias`), for
+// store_relu_bf16: loaded ahead of the main loop, so that their latency is not
+// waited out in the epilogue.
+template <int RN>
+struct LaneBias {
+    float4 v[RN][4];
+};
+template <int RN>
+__device__ inline LaneBias<RN> load_lane_bias(const float *bias) {
     const int kq = (threadIdx.x & 63) >> 5;
-    float4 bv[RN][4];
+    LaneBias<RN> b;
 #pragma unroll
     for (int c = 0; c < RN; ++c)
 #pragma unroll
-        for (int g = 0; g < 4; ++g) bv[c][g] = *(const float4 *)(bias + 32 * c + 8 * g + 4 * kq);
+        for (int g = 0; g < 4; ++g) b.v[c][g] = *(const float4 *)(bias + 32 * c + 8 * g + 4 * kq);
+    return b;
+}
+
+template <int RM, int RN>
+__device__ inline void store_relu_bf16(const f32x16 (&acc)[RM][RN], u16 *const (&dst)[RM], const LaneBias<RN> &bv) {
+    const int kq = (threadIdx.x & 63) >> 5;
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
         if (!dst[r]) continue;
@@ -94,7 +107,7 @@ __device__ inline void store_relu_bf16(const f32x16 (&acc)[RM][RN], u16 *const (
             for (int g = 0; g < 4; ++g)
                 *(uint2 *)(dst[r] + 32 * c + 8 * g + 4 * kq) =
                     relu_bf16x4(acc[r][c][4 * g], acc[r][c][4 * g + 1], acc[r][c][4 * g + 2], acc[r][c][4 * g + 3],
-                                bv[c][g]);
+                                bv.v[c][g]);
     }
 }
 
@@ -229,7 +242,8 @@ struct ConvDims {
 };
 
 // Forward: y = relu(conv(x, W) + b) in bf16. Block = 4 waves in a WGM x WGN
-// grid; each wave owns RM x RN accumulator tiles of 32 x 32.
+// grid; each wave owns RM x RN accumulator tiles of 32 x 32; block (x, n) takes
+// output pixels [BM x, BM x + BM) of image n.
 template <int CI, int CO, int S, int RM, int RN, int WGN>
 __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ x, ConvDims d, const u16 *__restrict__ wt,
                                                    const float *__restrict__ bias, u16 *__restrict__ y) {
@@ -238,19 +252,18 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ x, Con
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
     const int r32 = lane & 31, kq = lane >> 5;
-    const int64_t M = (int64_t)d.n * d.Ho * d.Wo;
-    const int64_t m0 = (int64_t)blockIdx.x * BM + wm * RM * 32;
     const int hw = d.Ho * d.Wo;
+    const int n = blockIdx.y;
+    const int m0 = blockIdx.x * BM + wm * RM * 32;  // within image n
     int iy0[RM], ix0[RM];
     int64_t img[RM];
     bool live[RM];
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
-        const int64_t m = m0 + 32 * r + r32;
-        live[r] = m < M;
-        const int64_t mm = live[r] ? m : 0;
-        const int n = (int)(mm / hw), rem = (int)(mm - (int64_t)n * hw);
-        const int oy = rem / d.Wo, ox = rem - oy * d.Wo;
+        const int m = m0 + 32 * r + r32;
+        live[r] = m < hw;
+        const int mm = live[r] ? m : 0;
+        const int oy = mm / d.Wo, ox = mm - oy * d.Wo;
         iy0[r] = oy * S - 1;
         ix0[r] = ox * S - 1;
         img[r] = (int64_t)n * d.H * d.W;
@@ -329,8 +342,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ x, Con
     }
     u16 *dst[RM];
 #pragma unroll
-    for (int r = 0; r < RM; ++r) dst[r] = live[r] ? y + (m0 + 32 * r + r32) * CO + cob : nullptr;
-    store_relu_bf16<RM, RN>(acc, dst, bias + cob);
+    for (int r = 0; r < RM; ++r)
+        dst[r] = live[r] ? y + ((int64_t)n * hw + m0 + 32 * r + r32) * CO + cob : nullptr;
+    store_relu_bf16<RM, RN>(acc, dst, load_lane_bias<RN>(bias + cob));
 }
 
 // Forward for c_in >= 32, LDS-staged: one block computes a TH x TW tile of output
@@ -344,8 +358,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ x, Con
 // 32 channels are padded to 80 bytes, so the 16-byte fragment reads of 16
 // consecutive pixels (or channels) hit distinct banks; for stride 2 the halo is
 // stored as even and odd column planes, so that strided pixels are consecutive
-// in LDS as well.
-template <int CI, int CO, int S, int TH, int TW, int WGN>
+// in LDS as well. PIPE: the taps of all chunks form one pipeline (the next
+// chunk's halo is loaded into registers while this chunk's taps compute);
+// otherwise each chunk loads its halo and first weights before its taps.
+template <int CI, int CO, int S, int TH, int TW, int WGN, bool PIPE>
 __global__ __launch_bounds__(256) void k_conv_fwd_lds(const u16 *__restrict__ x, ConvDims d,
                                                        const u16 *__restrict__ wt, const float *__restrict__ bias,
                                                        u16 *__restrict__ y) {
@@ -405,45 +421,58 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const u16 *__restrict__ x,
         }
     };
 
-    for (int ci0 = 0; ci0 < CI; ci0 += 32) {
-        // the halo's 16-byte pieces: all of a thread's loads are issued before its
-        // first LDS store (unconditional, from a clamped address, so that none waits
-        // for another), and land in LDS after the barrier
-        constexpr int HPIECES = HH * HWD * 4, HPER = (HPIECES + 255) / 256;
+    if constexpr (PIPE) {
+        // the halo's 16-byte pieces of one chunk of 32 input channels, loaded from
+        // clamped addresses (none under a branch, so that a thread's loads are in
+        // flight together)
+        constexpr int NCH = CI / 32, HPIECES = HH * HWD * 4, HPER = (HPIECES + 255) / 256;
+        static_assert(HPER <= 32, "one mask bit per piece");
         u32x4 hv[HPER];
+        uint32_t hin = 0;  // bit j: piece j lies inside the image (else it goes to LDS as zeros)
+        auto load_halo = [&](int ci0) {
+            hin = 0;
 #pragma unroll
-        for (int j = 0; j < HPER; ++j) {
-            const int p = min(tid + 256 * j, HPIECES - 1);
-            const int pix = p >> 2, q = p & 3;
-            const int hy = pix / HWD, hx = pix - hy * HWD;
-            const int iy = iy0 + hy, ix = ix0 + hx;
-            const bool in = iy >= 0 && iy < d.H && ix >= 0 && ix < d.W;
-            const u32x4 v = *(const u32x4 *)(ximg + ((int64_t)(in ? iy : 0) * d.W + (in ? ix : 0)) * CI + ci0 + 8 * q);
-            const u32x4 z = {0u, 0u, 0u, 0u};
-            hv[j] = in ? v : z;
-        }
-        __syncthreads();  // the previous chunk is done with the LDS
-#pragma unroll
-        for (int j = 0; j < HPER; ++j) {
-            const int p = tid + 256 * j;
-            if (p < HPIECES) {
+            for (int j = 0; j < HPER; ++j) {
+                const int p = min(tid + 256 * j, HPIECES - 1);
                 const int pix = p >> 2, q = p & 3;
                 const int hy = pix / HWD, hx = pix - hy * HWD;
-                *(u32x4 *)(s_halo + slot_of(hy, hx) * ROW + 8 * q) = hv[j];
+                const int iy = iy0 + hy, ix = ix0 + hx;
+                const bool in = iy >= 0 && iy < d.H && ix >= 0 && ix < d.W;
+                // (kept as loaded: a select here would wait for the load at once)
+                hv[j] = *(const u32x4 *)(ximg + ((int64_t)(in ? iy : 0) * d.W + (in ? ix : 0)) * CI + ci0 + 8 * q);
+                hin |= (uint32_t)in << j;
             }
-        }
-        fetch_b(0, ci0);
+        };
+        auto store_halo = [&]() {
+#pragma unroll
+            for (int j = 0; j < HPER; ++j) {
+                const int p = tid + 256 * j;
+                if (p < HPIECES) {
+                    const int pix = p >> 2, q = p & 3;
+                    const int hy = pix / HWD, hx = pix - hy * HWD;
+                    const u32x4 z = {0u, 0u, 0u, 0u};
+                    *(u32x4 *)(s_halo + slot_of(hy, hx) * ROW + 8 * q) = ((hin >> j) & 1u) ? hv[j] : z;
+                }
+            }
+        };
+        // Steps st = 9 chunk + tap over all chunks: the weights of step st + 1 (fetched
+        // during step st - 1) go to the buffer that step st - 1 read, past the last
+        // barrier, and those of st + 2 are fetched while st computes; the next
+        // chunk's halo is loaded into registers while this chunk's taps compute.
+        constexpr int STEPS = 9 * NCH;
+        load_halo(0);
+        store_halo();
+        fetch_b(0, 0);
         store_b(0);
-        fetch_b(1, ci0);
+        fetch_b(1, 0);
+        if (NCH > 1) load_halo(32);
         __syncthreads();
-        for (int tap = 0; tap < 9; ++tap) {
+        for (int st = 0; st < STEPS; ++st) {
+            const int ch = st / 9, tap = st - 9 * ch;
             const int kh = tap / 3, kw = tap - 3 * kh;
-            // The weights of tap + 1 (fetched during the previous tap) go to the other
-            // buffer, whose readers (tap - 1) are past the last barrier; those of
-            // tap + 2 are fetched while this tap computes. One barrier per tap.
-            if (tap < 8) {
-                store_b((tap + 1) & 1);
-                if (tap < 7) fetch_b(tap + 2, ci0);
+            if (st + 1 < STEPS) {
+                store_b((st + 1) & 1);
+                if (st + 2 < STEPS) fetch_b((st + 2) % 9, 32 * ((st + 2) / 9));
             }
 #pragma unroll
             for (int kk = 0; kk < 2; ++kk) {
@@ -451,18 +480,89 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const u16 *__restrict__ x,
 #pragma unroll
                 for (int r = 0; r < RM; ++r)
                     a[r] = __builtin_bit_cast(
-                        bf16x8, *(const u32x4 *)(s_halo + slot_of(ty[r] * S + kh, tx[r] * S + kw) * ROW + 16 * kk +
-                                                 8 * kq));
+                        bf16x8, *(const u32x4 *)(s_halo + slot_of(ty[r] * S + kh, tx[r] * S + kw) * ROW + 16 * kk + 8 * kq));
 #pragma unroll
                 for (int c = 0; c < RN; ++c)
-                    b[c] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(s_b[tap & 1] + (wn * RN * 32 + 32 * c + r32) * ROW +
-                                                                        16 * kk + 8 * kq));
+                    b[c] = __builtin_bit_cast(
+                        bf16x8, *(const u32x4 *)(s_b[st & 1] + (wn * RN * 32 + 32 * c + r32) * ROW + 16 * kk + 8 * kq));
 #pragma unroll
                 for (int r = 0; r < RM; ++r)
 #pragma unroll
                     for (int c = 0; c < RN; ++c) acc[r][c] = mfma(b[c], a[r], acc[r][c]);  // D[c_out][pixel]
             }
-            if (tap < 8) __syncthreads();  // tap + 1's weights are in LDS, and this tap's buffer is free
+            if (st + 1 < STEPS) {
+                __syncthreads();  // step st + 1's weights are in LDS, and step st's buffer is free
+                if (tap == 8) {
+                    // every wave is done with this chunk's halo: the next one replaces it
+                    store_halo();
+                    if (ch + 2 < NCH) load_halo(32 * (ch + 2));
+                    __syncthreads();
+                }
+            }
+        }
+    } else {
+        for (int ci0 = 0; ci0 < CI; ci0 += 32) {
+            // the halo's 16-byte pieces: all of a thread's loads are issued before its
+            // first LDS store (unconditional, from a clamped address, so that none waits
+            // for another), and land in LDS after the barrier
+            constexpr int HPIECES = HH * HWD * 4, HPER = (HPIECES + 255) / 256;
+            static_assert(HPER <= 32, "one mask bit per piece");
+            u32x4 hv[HPER];
+            uint32_t hin = 0;  // bit j: piece j lies inside the image (else it goes to LDS as zeros)
+#pragma unroll
+            for (int j = 0; j < HPER; ++j) {
+                const int p = min(tid + 256 * j, HPIECES - 1);
+                const int pix = p >> 2, q = p & 3;
+                const int hy = pix / HWD, hx = pix - hy * HWD;
+                const int iy = iy0 + hy, ix = ix0 + hx;
+                const bool in = iy >= 0 && iy < d.H && ix >= 0 && ix < d.W;
+                // (kept as loaded: a select here would wait for the load before the barrier)
+                hv[j] = *(const u32x4 *)(ximg + ((int64_t)(in ? iy : 0) * d.W + (in ? ix : 0)) * CI + ci0 + 8 * q);
+                hin |= (uint32_t)in << j;
+            }
+            __syncthreads();  // the previous chunk is done with the LDS
+#pragma unroll
+            for (int j = 0; j < HPER; ++j) {
+                const int p = tid + 256 * j;
+                if (p < HPIECES) {
+                    const int pix = p >> 2, q = p & 3;
+                    const int hy = pix / HWD, hx = pix - hy * HWD;
+                    const u32x4 z = {0u, 0u, 0u, 0u};
+                    *(u32x4 *)(s_halo + slot_of(hy, hx) * ROW + 8 * q) = ((hin >> j) & 1u) ? hv[j] : z;
+                }
+            }
+            fetch_b(0, ci0);
+            store_b(0);
+            fetch_b(1, ci0);
+            __syncthreads();
+            for (int tap = 0; tap < 9; ++tap) {
+                const int kh = tap / 3, kw = tap - 3 * kh;
+                // The weights of tap + 1 (fetched during the previous tap) go to the other
+                // buffer, whose readers (tap - 1) are past the last barrier; those of
+                // tap + 2 are fetched while this tap computes. One barrier per tap.
+                if (tap < 8) {
+                    store_b((tap + 1) & 1);
+                    if (tap < 7) fetch_b(tap + 2, ci0);
+                }
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) {
+                    bf16x8 a[RM], b[RN];
+#pragma unroll
+                    for (int r = 0; r < RM; ++r)
+                        a[r] = __builtin_bit_cast(
+                            bf16x8, *(const u32x4 *)(s_halo + slot_of(ty[r] * S + kh, tx[r] * S + kw) * ROW + 16 * kk +
+                                                     8 * kq));
+#pragma unroll
+                    for (int c = 0; c < RN; ++c)
+                        b[c] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(s_b[tap & 1] + (wn * RN * 32 + 32 * c + r32) * ROW +
+                                                                            16 * kk + 8 * kq));
+#pragma unroll
+                    for (int r = 0; r < RM; ++r)
+#pragma unroll
+                        for (int c = 0; c < RN; ++c) acc[r][c] = mfma(b[c], a[r], acc[r][c]);  // D[c_out][pixel]
+                }
+                if (tap < 8) __syncthreads();  // tap + 1's weights are in LDS, and this tap's buffer is free
+            }
         }
     }
     u16 *dst[RM];
@@ -471,7 +571,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const u16 *__restrict__ x,
         const int oy = oy0 + ty[r], ox = ox0 + tx[r];
         dst[r] = oy < d.Ho && ox < d.Wo ? y + (((int64_t)n * d.Ho + oy) * d.Wo + ox) * CO + wn * RN * 32 : nullptr;
     }
-    store_relu_bf16<RM, RN>(acc, dst, bias + wn * RN * 32);
+    store_relu_bf16<RM, RN>(acc, dst, load_lane_bias<RN>(bias + wn * RN * 32));
 }
 
 // Forward, persistent: each block stages the nine taps' weights for its COG
@@ -479,12 +579,15 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(const u16 *__restrict__ x,
 // blockIdx.x, blockIdx.x + gridDim.x, ... (channel group blockIdx.y). The next
 // tile's input halo (all c_in, in chunks of 32 channels) is loaded into
 // registers while the current tile computes and goes to LDS between two
-// barriers; the taps run with no barrier in between. Halo layout and row padding
-// as in k_conv_fwd_lds.
-template <int CI, int CO, int S, int TH, int TW, int COG, int WGN>
-__global__ __launch_bounds__(256) void k_conv_fwd_pers(const u16 *__restrict__ x, ConvDims d,
-                                                        const u16 *__restrict__ wt, const float *__restrict__ bias,
-                                                        u16 *__restrict__ y, int tiles_x, int tiles_y) {
+// barriers; the taps run with no barrier in between. Halo layout and row
+// padding as in k_conv_fwd_lds. BPC blocks share a compute unit (their LDS), so
+// each wave keeps to 512 / BPC registers. (Two or three tiles' halos in flight,
+// and fragment reads pipelined up to six K steps ahead of the multiplies,
+// measured no faster.)
+template <int CI, int CO, int S, int TH, int TW, int COG, int WGN, int BPC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BPC))) void k_conv_fwd_pers(
+    const u16 *__restrict__ x, ConvDims d, const u16 *__restrict__ wt, const float *__restrict__ bias,
+    u16 *__restrict__ y, int tiles_x, int tiles_y) {
     constexpr int WGM = 4 / WGN, BM = TH * TW, NCH = CI / 32;
     constexpr int RM = BM / (WGM * 32), RN = COG / (WGN * 32);
     static_assert(RM >= 1 && RN >= 1 && WGM * RM * 32 == BM && WGN * RN * 32 == COG && CO % COG == 0,
@@ -512,6 +615,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd_pers(const u16 *__restrict__ x
         tx[r] = m - ty[r] * TW;
     }
 
+    // loaded once, so that no tile's epilogue waits for them
+    const LaneBias<RN> lane_bias = load_lane_bias<RN>(bias + co0 + wn * RN * 32);
     // the weights, once: piece p = ((tap NCH + chunk) COG + c_out) 4 + quarter
     constexpr int WPIECES = 9 * NCH * COG * 4;
     for (int p = tid; p < WPIECES; p += 256) {
@@ -521,10 +626,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd_pers(const u16 *__restrict__ x
     }
 
     // a tile's halo, piece p = (chunk HH HWD + pixel) 4 + quarter, loaded from
-    // clamped addresses (none under a branch)
+    // clamped addresses (none under a branch) and kept as loaded until its LDS
+    // store: a select right after the load would wait for it there
     constexpr int HPIX = HH * HWD, HPIECES = NCH * HPIX * 4, HPER = (HPIECES + 255) / 256;
+    static_assert(HPER <= 32, "one mask bit per piece");
     u32x4 hv[HPER];
+    uint32_t hin = 0;  // bit j: piece j lies inside the image (else zeros go to LDS)
     auto load_halo = [&](int t) {
+        hin = 0;
         const int txi = t % tiles_x, rest = t / tiles_x, tyi = rest % tiles_y, n = rest / tiles_y;
         const int iy0 = tyi * TH * S - 1, ix0 = txi * TW * S - 1;
         const u16 *ximg = x + (int64_t)n * d.H * d.W * CI;
@@ -535,10 +644,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd_pers(const u16 *__restrict__ x
             const int hy = pix / HWD, hx = pix - hy * HWD;
             const int iy = iy0 + hy, ix = ix0 + hx;
             const bool in = iy >= 0 && iy < d.H && ix >= 0 && ix < d.W;
-            const u32x4 v =
-                *(const u32x4 *)(ximg + ((int64_t)(in ? iy : 0) * d.W + (in ? ix : 0)) * CI + 32 * ch + 8 * q);
-            const u32x4 z = {0u, 0u, 0u, 0u};
-            hv[j] = in ? v : z;
+            hv[j] = *(const u32x4 *)(ximg + ((int64_t)(in ? iy : 0) * d.W + (in ? ix : 0)) * CI + 32 * ch + 8 * q);
+            hin |= (uint32_t)in << j;
         }
     };
     int t = blockIdx.x;
@@ -551,7 +658,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd_pers(const u16 *__restrict__ x
             if (p < HPIECES) {
                 const int ch = (p >> 2) / HPIX, pix = (p >> 2) - ch * HPIX, q = p & 3;
                 const int hy = pix / HWD, hx = pix - hy * HWD;
-                *(u32x4 *)(s_halo + (ch * SLOTS + slot_of(hy, hx)) * ROW + 8 * q) = hv[j];
+                const u32x4 z = {0u, 0u, 0u, 0u};
+                *(u32x4 *)(s_halo + (ch * SLOTS + slot_of(hy, hx)) * ROW + 8 * q) = ((hin >> j) & 1u) ? hv[j] : z;
             }
         }
         __syncthreads();
@@ -597,7 +705,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_pers(const u16 *__restrict__ x
             dst[r] = oy < d.Ho && ox < d.Wo ? y + (((int64_t)n * d.Ho + oy) * d.Wo + ox) * CO + co0 + wn * RN * 32
                                            : nullptr;
         }
-        store_relu_bf16<RM, RN>(acc, dst, bias + co0 + wn * RN * 32);
+        store_relu_bf16<RM, RN>(acc, dst, lane_bias);
     }
 }
 
@@ -936,27 +1044,26 @@ __global__ void k_conv_weights(const float *__restrict__ p, int64_t off, int CI,
 template <int CI, int CO, int S, int RM, int RN, int WGN>
 void fwd_layer(hipStream_t s, const u16 *x, ConvDims d, const u16 *wt, const float *bias, u16 *y) {
     constexpr int BM = (4 / WGN) * RM * 32;
-    const int64_t M = (int64_t)d.n * d.Ho * d.Wo;
-    hipLaunchKernelGGL((k_conv_fwd<CI, CO, S, RM, RN, WGN>), dim3((unsigned)((M + BM - 1) / BM)), dim3(256), 0, s,
-                       x, d, wt, bias, y);
+    const int hw = d.Ho * d.Wo;
+    hipLaunchKernelGGL((k_conv_fwd<CI, CO, S, RM, RN, WGN>), dim3((unsigned)((hw + BM - 1) / BM), (unsigned)d.n),
+                       dim3(256), 0, s, x, d, wt, bias, y);
 }
 
-template <int CI, int CO, int S, int TH, int TW, int WGN>
+template <int CI, int CO, int S, int TH, int TW, int WGN, bool PIPE>
 void fwd_layer_lds(hipStream_t s, const u16 *x, ConvDims d, const u16 *wt, const float *bias, u16 *y) {
     const dim3 grid((unsigned)((d.Wo + TW - 1) / TW), (unsigned)((d.Ho + TH - 1) / TH), (unsigned)d.n);
-    hipLaunchKernelGGL((k_conv_fwd_lds<CI, CO, S, TH, TW, WGN>), grid, dim3(256), 0, s, x, d, wt, bias, y);
+    hipLaunchKernelGGL((k_conv_fwd_lds<CI, CO, S, TH, TW, WGN, PIPE>), grid, dim3(256), 0, s, x, d, wt, bias, y);
 }
 
-template <int CI, int CO, int S, int TH, int TW, int COG, int WGN>
-void fwd_layer_pers(hipStream_t s, const u16 *x, ConvDims d, const u16 *wt, const float *bias, u16 *y,
-                    int blocks_per_cu) {
+template <int CI, int CO, int S, int TH, int TW, int COG, int WGN, int BPC>
+void fwd_layer_pers(hipStream_t s, const u16 *x, ConvDims d, const u16 *wt, const float *bias, u16 *y) {
     const int tiles_x = (d.Wo + TW - 1) / TW, tiles_y = (d.Ho + TH - 1) / TH;
     const int n_tiles = d.n * tiles_x * tiles_y;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     // as many blocks as fit on the device at once (their LDS), each taking tiles in turn
-    const int blocks = std::max(1, std::min(n_tiles, blocks_per_cu * cus));
-    hipLaunchKernelGGL((k_conv_fwd_pers<CI, CO, S, TH, TW, COG, WGN>), dim3((unsigned)blocks, CO / COG), dim3(256), 0,
+    const int blocks = std::max(1, std::min(n_tiles, BPC * cus));
+    hipLaunchKernelGGL((k_conv_fwd_pers<CI, CO, S, TH, TW, COG, WGN, BPC>), dim3((unsigned)blocks, CO / COG), dim3(256), 0,
                        s, x, d, wt, bias, y, tiles_x, tiles_y);
 }
 
@@ -1020,10 +1127,13 @@ void launch_scorer_forward(hipStream_t s, const ScorerBufs &b, int B, float *sco
     auto D = [&](int l) { return ConvDims{B, dm[l][0], dm[l][1], dm[l + 1][0], dm[l + 1][1]}; };
     const float *p = b.params;
     fwd_layer<2, 32, 2, 2, 1, 1>(s, b.x, D(0), b.wt + b.w_off[0], p + b.b_off[0], b.act[1]);
-    fwd_layer_pers<32, 64, 1, 16, 16, 64, 1>(s, b.act[1], D(1), b.wt + b.w_off[1], p + b.b_off[1], b.act[2], 2);
-    fwd_layer_pers<64, 64, 2, 8, 8, 64, 2>(s, b.act[2], D(2), b.wt + b.w_off[2], p + b.b_off[2], b.act[3], 1);
-    fwd_layer_lds<64, 128, 1, 8, 16, 2>(s, b.act[3], D(3), b.wt + b.w_off[3], p + b.b_off[3], b.act[4]);
-    fwd_layer_lds<128, 128, 2, 8, 16, 2>(s, b.act[4], D(4), b.wt + b.w_off[4], p + b.b_off[4], b.act[5]);
+    fwd_layer_pers<32, 64, 1, 16, 16, 64, 1, 2>(s, b.act[1], D(1), b.wt + b.w_off[1], p + b.b_off[1], b.act[2]);
+    fwd_layer_pers<64, 64, 2, 8, 8, 64, 2, 1>(s, b.act[2], D(2), b.wt + b.w_off[2], p + b.b_off[2], b.act[3]);
+    // (the continuous tap pipeline measured 11% faster on the 64->128 layer and 5%
+    // slower on the 128->128 one; 12 x 8 tiles fit that layer's 12-row output,
+    // where 8 x 16 tiles computed 45% padding)
+    fwd_layer_lds<64, 128, 1, 8, 16, 2, true>(s, b.act[3], D(3), b.wt + b.w_off[3], p + b.b_off[3], b.act[4]);
+    fwd_layer_lds<128, 128, 2, 12, 8, 4, false>(s, b.act[4], D(4), b.wt + b.w_off[4], p + b.b_off[4], b.act[5]);
     const int npix = dm[5][0] * dm[5][1];
     hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(256), 0, s, b.act[5], npix, p + b.fc_off[0], p + b.fc_off[1],
                        p + b.fc_off[2], p + b.fc_off[3], b.g, b.h, score);
