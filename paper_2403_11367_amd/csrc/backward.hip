@@ -34,13 +34,14 @@ constexpr int kPoseGrads = 13;    // mean (3), Sigma unique entries (6), opacity
 // Per (pose, Gaussian): screen-space gradients -> mean and covariance entries.
 __global__ __launch_bounds__(kThreads) void k_project_backward(
     const float4 *__restrict__ packed, int64_t n, const float *__restrict__ poses, int n_poses, Camera cam,
-    Consts kc, const uint32_t *__restrict__ ntiles, const float *__restrict__ gscreen, float *__restrict__ gout) {
+    Consts kc, const uint64_t *__restrict__ vmask, const float *__restrict__ gscreen, float *__restrict__ gout) {
     const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= (int64_t)n_poses * n) return;
     const int p = (int)(idx / n);
     const int64_t g = idx - (int64_t)p * n;
     float *out = gout + idx * kPoseGrads;
-    if (ntiles[idx] == 0) {
+    // culled in the forward (bit g % 64 of the pose's region g / 64)
+    if (((vmask[(int64_t)p * ((n + 63) >> 6) + (g >> 6)] >> (g & 63)) & 1ull) == 0) {
         for (int i = 0; i < kPoseGrads; ++i) out[i] = 0.f;
         return;
     }
@@ -182,12 +183,12 @@ __global__ __launch_bounds__(kThreads) void k_param_grads(const float *__restric
 int pose_grads_per_gaussian() { return kPoseGrads; }
 
 void launch_project_backward(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
-                             const Camera &cam, const Consts &k, const uint32_t *ntiles, const float *gscreen,
+                             const Camera &cam, const Consts &k, const uint64_t *vmask, const float *gscreen,
                              float *gpose) {
     const int64_t total = (int64_t)n_poses * n;
     if (total <= 0) return;
     hipLaunchKernelGGL(k_project_backward, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                       s, packed, n, poses, n_poses, cam, k, ntiles, gscreen, gpose);
+                       s, packed, n, poses, n_poses, cam, k, vmask, gscreen, gpose);
 }
 
 void launch_param_grads(hipStream_t s, const float *gpose, int64_t n, int n_poses, const float *scales,

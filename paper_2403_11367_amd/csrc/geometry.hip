@@ -96,16 +96,18 @@ __global__ void k_sum_nonfinite(const SubmapTable tab, unsigned long long *__res
 // S1. One thread per Gaussian slot, looping over a chunk of poses (blockIdx.y),
 // so the packed record is read once per chunk (again where the chunk crosses
 // into the next submap of a batch; slot g of a pose whose submap has no
-// Gaussian g is culled). For each pose the screen record is
-// written, the number of tiles its 3-sigma rectangle touches is stored (0 =
-// culled) with the tile rectangle, and each wave packs the (depth bits, record
-// slot = pose * n + index) of its visible Gaussians, in index order, at the
-// front of its 64-slot region of vz / vg, with their number in
-// vcount[pose * n_regions + region]: the input of the per-pose depth sort.
+// Gaussian g is culled). For each pose the screen record and the tile
+// rectangle of a visible Gaussian are written, and each wave packs the (depth
+// bits, sort value) of its visible Gaussians, in index order, at the front of
+// its 64-slot region of vz / vg, with the region's visibility mask (bit l: slot
+// 64 region + l is visible) in vmask[pose * n_regions + region]: the input of
+// the per-pose depth sort. (The mask replaces a 4-byte tile count per pose and
+// Gaussian: 8 bytes per 64 slots; the count is in the sort value and follows
+// from the tile rectangle.)
 __global__ __launch_bounds__(kThreads) void k_preprocess(
     const SubmapTable tab, int64_t n, const float *__restrict__ poses, int n_poses, Camera cam,
-    Consts k, TileGrid tg, float4 *__restrict__ records, uint32_t *__restrict__ ntiles, uint2 *__restrict__ rect,
-    uint32_t *__restrict__ vz, uint32_t *__restrict__ vg, uint32_t *__restrict__ vcount, bool pack) {
+    Consts k, TileGrid tg, float4 *__restrict__ records, uint2 *__restrict__ rect, uint32_t *__restrict__ vz,
+    uint32_t *__restrict__ vg, uint64_t *__restrict__ vmask, bool pack) {
     const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int p0 = blockIdx.y * kPosesPerThread;
     const int p1 = min(p0 + kPosesPerThread, n_poses);
@@ -206,11 +208,10 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
                     }
                 }
             }
-            ntiles[(int64_t)p * n + g] = nt;
         }
         const uint64_t vis = __ballot(nt != 0);
         if (region_in) {
-            if (lane == 0) vcount[(int64_t)p * n_regions + region] = (uint32_t)__popcll(vis);
+            if (lane == 0) vmask[(int64_t)p * n_regions + region] = vis;
             if (nt != 0) {
                 const int64_t slot = (int64_t)p * n + (region << 6) + __popcll(vis & lt_mask);
                 vz[slot] = zb;
@@ -461,12 +462,12 @@ void launch_sum_nonfinite(hipStream_t s, const SubmapTable &tab, unsigned long l
 int64_t preprocess_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }
 
 void launch_preprocess(hipStream_t s, const SubmapTable &tab, int64_t n, const float *poses, int n_poses,
-                       const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
-                       uint32_t *ntiles, uint2 *rect, uint32_t *vz, uint32_t *vg, uint32_t *vcount, bool pack) {
+                       const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records, uint2 *rect,
+                       uint32_t *vz, uint32_t *vg, uint64_t *vmask, bool pack) {
     if (n <= 0) return;
     const dim3 grid((unsigned)preprocess_blocks(n), (unsigned)((n_poses + kPosesPerThread - 1) / kPosesPerThread));
     hipLaunchKernelGGL(k_preprocess, grid, dim3(kThreads), 0, s, tab, n, poses, n_poses, cam, k, tg, records,
-                       ntiles, rect, vz, vg, vcount, pack);
+                       rect, vz, vg, vmask, pack);
 }
 
 uint64_t emit_blocks(uint64_t n_max) { return std::max<uint64_t>(1, (n_max + kEmitTile - 1) / kEmitTile); }

@@ -80,11 +80,12 @@ struct SubmapTable {
 void launch_sum_nonfinite(hipStream_t s, const SubmapTable &tab, unsigned long long *total);
 // Blocks of the preprocess grid along the Gaussians.
 int64_t preprocess_blocks(int64_t n);
-// Screen records, tile counts ntiles[p][g] (0 = culled) and tile rectangles
-// rect[p][g] = (tx0 | tx1 << 16, ty0 | ty1 << 16); per pose and 64-Gaussian
-// region, the (depth bits, record slot p * n + g) of the visible Gaussians
-// packed at the front of the region's slots of vz / vg (P * n each) and their
-// count in vcount[p * ceil(n / 64) + region].
+// Screen records and tile rectangles rect[p][g] = (tx0 | tx1 << 16, ty0 | ty1
+// << 16) of the visible Gaussians (entries of culled ones are left as they
+// were); per pose and 64-Gaussian region, the visibility mask (bit l: Gaussian
+// 64 region + l) in vmask[p * ceil(n / 64) + region], and the (depth bits, sort
+// value) of the visible Gaussians packed at the front of the region's slots of
+// vz / vg (P * n each).
 // Sort values: the record slot (pose * n + index) of each visible Gaussian, or,
 // where pack_sort_values(n, n_tiles), (index) | (tile count << kPackIndexBits),
 // which the depth sort's last pass turns back into the slot and the count.
@@ -94,7 +95,7 @@ inline bool pack_sort_values(int64_t n, int n_tiles) {
 }
 void launch_preprocess(hipStream_t s, const SubmapTable &tab, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
-                       uint32_t *ntiles, uint2 *rect, uint32_t *vz, uint32_t *vg, uint32_t *vcount, bool pack);
+                       uint2 *rect, uint32_t *vz, uint32_t *vg, uint64_t *vmask, bool pack);
 // Pair emission in front-to-back order. The depth-sorted visible Gaussians
 // (snt: tile counts, sg: record slots p * n + g; pose p owns [vbase[p],
 // vbase[p+1]), at most n_max = P * n of them) are cut into nb = emit_blocks(n_max)
@@ -120,7 +121,7 @@ void launch_emit(hipStream_t s, const uint32_t *snt, const uint32_t *sg, const u
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t value);
 void launch_fill_u64(hipStream_t s, unsigned long long *p, uint64_t n, unsigned long long value);
 // Per-pose stable sort of the visible Gaussians by depth bits. Input: the
-// preprocess's regions in (kb, vb) with vcount. Output: va[vbase[p] ..
+// preprocess's regions in (kb, vb) with vmask. Output: va[vbase[p] ..
 // vbase[p+1]) = pose p's record slots front to back, ka = their tile counts,
 // vbase[P] = visible total; nv[p] = pose p's visible count.
 // ka, va, kb, vb hold P * n entries; rcnt and roff radix_count_elems each.
@@ -129,7 +130,7 @@ uint64_t radix_count_elems(int64_t n, int n_poses);
 // slot0: the first pose's first record slot (record slots are pose * n + index
 // over all poses of the render); pack: the values are packed (as the preprocess
 // wrote them).
-void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vcount, const uint32_t *ntiles,
+void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint64_t *vmask, const uint2 *rect,
                        uint32_t slot0, bool pack, uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
                        uint32_t *rcnt, uint32_t *roff, uint32_t *nv, uint32_t *vbase);
 // Exclusive scan of sums[0 .. nb_max) in place (only the first *d_nb with d_nb),
@@ -202,7 +203,7 @@ void launch_scatter_scores(hipStream_t s, const float *batch_scores, const int32
 // opacity, r, g, b).
 int pose_grads_per_gaussian();
 void launch_project_backward(hipStream_t s, const float4 *packed, int64_t n, const float *poses, int n_poses,
-                             const Camera &cam, const Consts &k, const uint32_t *ntiles, const float *gscreen,
+                             const Camera &cam, const Consts &k, const uint64_t *vmask, const float *gscreen,
                              float *gpose);
 void launch_param_grads(hipStream_t s, const float *gpose, int64_t n, int n_poses, const float *scales,
                         const float *quats, float *g_means, float *g_scales, float *g_quats, float *g_opacity,

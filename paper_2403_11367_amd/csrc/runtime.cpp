@@ -53,7 +53,7 @@ struct gsr_ctx {
     struct Buf {
         void *p = nullptr;
         size_t bytes = 0;
-    } records, ntiles, rect, vcount, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, esum, pseg, ptile, pk,
+    } records, rect, vmask, sort_ka, sort_va, sort_kb, sort_vb, rcnt, roff, nv, vbase, esum, pseg, ptile, pk,
         sk, ccnt, cstart, ctile, cval, block_base, bseg, offsets, keep_off, keep_state, keep_items, grey_q, partials, s_order, s_poses, s_rgb, s_depth,
         s_scores, pr_grey, pr_q3, pr_x, pr_rgb, pr_depth, bw_screen, bw_pose, h2d;
     size_t ws_limit = 0;  // bytes the workspace may hold in all (0 = no limit)
@@ -330,7 +330,7 @@ int gsr_destroy(gsr_ctx *ctx) {
         if (ctx->chain[g]) (void)hipEventDestroy(ctx->chain[g]);
         if (ctx->join[g]) (void)hipEventDestroy(ctx->join[g]);
     }
-    gsr_ctx::Buf *bufs[] = {&ctx->records,   &ctx->ntiles,  &ctx->rect,      &ctx->vcount,    &ctx->sort_ka,
+    gsr_ctx::Buf *bufs[] = {&ctx->records,   &ctx->rect,      &ctx->vmask,    &ctx->sort_ka,
                             &ctx->sort_va,   &ctx->sort_kb, &ctx->sort_vb,   &ctx->rcnt,      &ctx->roff,
                             &ctx->nv,        &ctx->vbase,   &ctx->esum,      &ctx->pseg,      &ctx->ptile,
                             &ctx->pk,        &ctx->sk,      &ctx->ccnt,      &ctx->cstart,    &ctx->ctile,
@@ -502,7 +502,7 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         return fail(ctx, GSR_EINVAL, "poses x submap size must be below 2^32");
     const uint64_t pn = (uint64_t)std::max<int64_t>(1, P * n);
     const uint64_t n_regions = (uint64_t)(n + 63) / 64;
-    const uint64_t nvc = std::max<uint64_t>(1, (uint64_t)P * n_regions);  // visible-count entries
+    const uint64_t nvc = std::max<uint64_t>(1, (uint64_t)P * n_regions);  // visibility-mask entries
     const uint64_t n_rc = gsr::radix_count_elems(n, n_poses);
     const bool exact = cfg.pair_capacity == 0;
     if (exact && ctx->capturing)
@@ -538,9 +538,8 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
 
     int rc;
     if ((rc = ensure(ctx, ctx->records, pn * gsr::kRecordQuads * sizeof(float4), "records")) ||
-        (rc = ensure(ctx, ctx->ntiles, pn * sizeof(uint32_t), "ntiles")) ||
         (rc = ensure(ctx, ctx->rect, pn * sizeof(uint2), "tile rectangles")) ||
-        (rc = ensure(ctx, ctx->vcount, nvc * sizeof(uint32_t), "visible counts")) ||
+        (rc = ensure(ctx, ctx->vmask, nvc * sizeof(uint64_t), "visibility masks")) ||
         (rc = ensure(ctx, ctx->sort_ka, pn * sizeof(uint32_t), "depth sort")) ||
         (rc = ensure(ctx, ctx->sort_va, pn * sizeof(uint32_t), "depth sort")) ||
         (rc = ensure(ctx, ctx->sort_kb, pn * sizeof(uint32_t), "depth sort")) ||
@@ -592,7 +591,6 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
 
     hipStream_t s = ctx->stream;
     auto stream_of = [&](int g) { return g == 0 ? s : ctx->aux[g - 1]; };
-    uint32_t *ntiles = (uint32_t *)ctx->ntiles.p;
     uint32_t *sort_ka = (uint32_t *)ctx->sort_ka.p, *sort_va = (uint32_t *)ctx->sort_va.p;
     uint32_t *sort_kb = (uint32_t *)ctx->sort_kb.p, *sort_vb = (uint32_t *)ctx->sort_vb.p;
     uint32_t *vbase = (uint32_t *)ctx->vbase.p;
@@ -609,8 +607,8 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
     gsr::launch_fill_u64(s, ctx->d_counters, gsr::CNT_COUNT, 0ull);
     gsr::launch_sum_nonfinite(s, tab, ctx->d_counters + gsr::CNT_NONFINITE);
     const bool pack = gsr::pack_sort_values(n, tg.n_tiles);  // tile counts ride in the sort values
-    gsr::launch_preprocess(s, tab, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p, ntiles,
-                           (uint2 *)ctx->rect.p, sort_kb, sort_vb, (uint32_t *)ctx->vcount.p, pack);
+    gsr::launch_preprocess(s, tab, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p, (uint2 *)ctx->rect.p,
+                           sort_kb, sort_vb, (uint64_t *)ctx->vmask.p, pack);
     if ((rc = check_launch(ctx, "preprocess"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[1], s));
 
@@ -620,7 +618,8 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         const gsr_ctx::Group &gr = ctx->groups[g];
         const uint64_t so = (uint64_t)gr.p0 * n, ro = gsr::radix_count_elems(n, (int)gr.p0);
         const uint64_t gpn = (uint64_t)std::max<int64_t>(1, gr.np * n);
-        gsr::launch_depth_sort(st, n, (int)gr.np, (const uint32_t *)ctx->vcount.p + (uint64_t)gr.p0 * n_regions, ntiles,
+        gsr::launch_depth_sort(st, n, (int)gr.np, (const uint64_t *)ctx->vmask.p + (uint64_t)gr.p0 * n_regions,
+                               (const uint2 *)ctx->rect.p,
                                (uint32_t)so, pack, sort_ka + so, sort_va + so, sort_kb + so, sort_vb + so, (uint32_t *)ctx->rcnt.p + ro,
                                (uint32_t *)ctx->roff.p + ro, (uint32_t *)ctx->nv.p + gr.p0, vbase + gr.vb);
         gsr::launch_emit_sums(st, sort_ka + so, vbase + gr.vb, (int)gr.np, gpn, esum + gr.es);
@@ -822,7 +821,7 @@ int gsr_render_backward(gsr_ctx *ctx, const gsr_submap *sm, const float *scales,
         item0 += blocks[g];
     }
     gsr::launch_project_backward(s, sm->packed, n, poses, n_poses, ctx->last_cam, ctx->last_consts,
-                                 (const uint32_t *)ctx->ntiles.p, gscreen, (float *)ctx->bw_pose.p);
+                                 (const uint64_t *)ctx->vmask.p, gscreen, (float *)ctx->bw_pose.p);
     gsr::launch_param_grads(s, (const float *)ctx->bw_pose.p, n, n_poses, scales, quats, g_means, g_scales, g_quats,
                             g_opacity, g_rgb);
     return check_launch(ctx, "render backward");
@@ -1248,9 +1247,24 @@ int gsr_debug_copy(gsr_ctx *ctx, int which, void *dst, int64_t bytes) {
     if (bytes != want) return fail(ctx, GSR_EINVAL, "byte count differs from gsr_debug_size");
     if (bytes == 0) return GSR_OK;
     HIPC(ctx, hipDeviceSynchronize());
-    if (which == GSR_BUF_RECORDS || which == GSR_BUF_NTILES) {
-        const void *src = which == GSR_BUF_RECORDS ? ctx->records.p : ctx->ntiles.p;
-        HIPC(ctx, hipMemcpy(dst, src, (size_t)bytes, hipMemcpyDeviceToHost));
+    if (which == GSR_BUF_RECORDS) {
+        HIPC(ctx, hipMemcpy(dst, ctx->records.p, (size_t)bytes, hipMemcpyDeviceToHost));
+        return GSR_OK;
+    }
+    if (which == GSR_BUF_NTILES) {
+        // from the visibility masks and the tile rectangles of the visible entries
+        const int64_t n = ctx->last_n, P = ctx->last_poses, nr = (n + 63) / 64;
+        std::vector<uint64_t> mask((size_t)(P * nr));
+        std::vector<uint2> rect((size_t)(P * n));
+        HIPC(ctx, hipMemcpy(mask.data(), ctx->vmask.p, mask.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        HIPC(ctx, hipMemcpy(rect.data(), ctx->rect.p, rect.size() * sizeof(uint2), hipMemcpyDeviceToHost));
+        uint32_t *out = (uint32_t *)dst;
+        for (int64_t p = 0; p < P; ++p)
+            for (int64_t g = 0; g < n; ++g) {
+                const uint2 r = rect[(size_t)(p * n + g)];
+                const bool vis = (mask[(size_t)(p * nr + g / 64)] >> (g % 64)) & 1ull;
+                out[p * n + g] = vis ? ((r.x >> 16) - (r.x & 0xffffu) + 1u) * ((r.y >> 16) - (r.y & 0xffffu) + 1u) : 0u;
+            }
         return GSR_OK;
     }
     // the groups' pair lists laid end to end, and their list offsets shifted to match

@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_pose_bases(const uint32_t *__restr
 }
 
 // Compaction of the preprocess's region layout (per pose, regions of 64 slots,
-// each holding its visible entries at the front, vcount of them) into one dense
+// each holding its visible entries at the front, popcount(vmask) of them) into one dense
 // run per pose, in slot order, so that every radix pass works on dense blocks.
 // Per pose (one block): reg_off[p * n_regions + r] = entries of the pose's
 // regions before r; nv[p] = the pose's total.
@@ -332,12 +332,12 @@ template <int kWaves>
 __device__ uint32_t block_exclusive_scan_waves(uint32_t x, uint32_t *s_wave, uint32_t *total);
 
 constexpr int kRegionThreads = 1024;  // about 8 regions per thread at 500k Gaussians
-__global__ __launch_bounds__(kRegionThreads) void k_region_offsets(const uint32_t *__restrict__ vcount,
+__global__ __launch_bounds__(kRegionThreads) void k_region_offsets(const uint64_t *__restrict__ vmask,
                                                                    int64_t n_regions, uint32_t *__restrict__ reg_off,
                                                                    uint32_t *__restrict__ nv) {
     __shared__ uint32_t s_wave[kRegionThreads / 64];
     const int p = blockIdx.x;
-    const uint32_t *vc = vcount + (int64_t)p * n_regions;
+    const uint64_t *vc = vmask + (int64_t)p * n_regions;
     uint32_t *ro = reg_off + (int64_t)p * n_regions;
     const int64_t per = (n_regions + kRegionThreads - 1) / kRegionThreads;  // consecutive regions per thread
     const int64_t r0 = (int64_t)threadIdx.x * per, r1 = min(r0 + per, n_regions);
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kRegionThreads) void k_region_offsets(const uint32_
     for (int64_t r = r0; r < r1; r += 8) {
         uint32_t v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = vc[min(r + u, r1 - 1)];
+        for (int u = 0; u < 8; ++u) v[u] = (uint32_t)__popcll(vc[min(r + u, r1 - 1)]);
 #pragma unroll
         for (int u = 0; u < 8; ++u) sum += r + u < r1 ? v[u] : 0u;
     }
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(kRegionThreads) void k_region_offsets(const uint32_
     for (int64_t r = r0; r < r1; r += 8) {
         uint32_t v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = vc[min(r + u, r1 - 1)];
+        for (int u = 0; u < 8; ++u) v[u] = (uint32_t)__popcll(vc[min(r + u, r1 - 1)]);
 #pragma unroll
         for (int u = 0; u < 8; ++u)
             if (r + u < r1) {
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kRegionThreads) void k_region_offsets(const uint32_
 // entries go to vbase[p] + reg_off[..] onward. Lane i first loads region i's
 // count and destination, so that the wave's copies do not wait on each other.
 constexpr int kCompactRegions = 16;
-__global__ __launch_bounds__(kThreads) void k_compact(const uint32_t *__restrict__ vcount, int64_t n, int P,
+__global__ __launch_bounds__(kThreads) void k_compact(const uint64_t *__restrict__ vmask, int64_t n, int P,
                                                       const uint32_t *__restrict__ reg_off,
                                                       const uint32_t *__restrict__ vbase,
                                                       const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(const uint32_t *__restrict
         const int64_t w = w0 + lane;
         const int p = (int)(w / n_regions);
         const int64_t r = w - (int64_t)p * n_regions;
-        my_cnt = vcount[w];
+        my_cnt = (uint32_t)__popcll(vmask[w]);
         my_src = (uint64_t)p * (uint64_t)n + ((uint64_t)r << 6);
         my_dst = (uint64_t)vbase[p] + reg_off[w];
     }
@@ -456,7 +456,7 @@ template <bool kLast>
 __global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int shift, uint32_t nbp, int n_poses,
                                                             const uint32_t *__restrict__ off,
                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                            const uint32_t *__restrict__ ntiles, int64_t n,
+                                                            const uint2 *__restrict__ rect, int64_t n,
                                                             bool packed, uint32_t slot0) {
     __shared__ uint32_t s_cnt[kRBWaves][kDigits];
     __shared__ uint32_t s_delta[kDigits];
@@ -540,8 +540,10 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int 
                 vout[pos] = slot0 + (uint32_t)((uint64_t)p * (uint64_t)n) + (v & ((1u << kPackIndexBits) - 1u));
                 kout[pos] = v >> kPackIndexBits;
             } else {
+                // values are record slots (pose * n + index); the tile count from the rectangle
+                const uint2 r = rect[v];
                 vout[pos] = v;
-                kout[pos] = ntiles[v];  // values are record slots (pose * n + index)
+                kout[pos] = ((r.x >> 16) - (r.x & 0xffffu) + 1u) * ((r.y >> 16) - (r.y & 0xffffu) + 1u);
             }
         } else {
             kout[pos] = k;
@@ -926,7 +928,7 @@ uint64_t radix_count_elems(int64_t n, int n_poses) {
     return (uint64_t)n_poses * kDigits * radix_blocks_per_pose(n);
 }
 
-void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vcount, const uint32_t *ntiles,
+void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint64_t *vmask, const uint2 *rect,
                        uint32_t slot0, bool packed, uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
                        uint32_t *rcnt, uint32_t *roff, uint32_t *nv, uint32_t *vbase) {
     const uint32_t nbp = (uint32_t)radix_blocks_per_pose(n);
@@ -936,7 +938,7 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
     // Compaction: regions in (kb, vb) -> dense (ka, va), in slot order. roff holds
     // the region offsets (P * n_regions <= radix_count_elems) until pass 0 writes
     // its digit offsets there.
-    hipLaunchKernelGGL(k_region_offsets, dim3((unsigned)n_poses), dim3(kRegionThreads), 0, s, vcount, n_regions, roff,
+    hipLaunchKernelGGL(k_region_offsets, dim3((unsigned)n_poses), dim3(kRegionThreads), 0, s, vmask, n_regions, roff,
                        nv);
     hipLaunchKernelGGL(k_pose_bases, dim3(1), dim3(kThreads), 0, s, nv, n_poses, vbase);
     const uint64_t n_waves = (uint64_t)n_poses * (uint64_t)n_regions;  // 0 for an empty submap
@@ -944,7 +946,7 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
         hipLaunchKernelGGL(k_compact,
                            dim3((unsigned)((n_waves + kCompactRegions * (kThreads / 64) - 1) /
                                            (kCompactRegions * (kThreads / 64)))),
-                           dim3(kThreads), 0, s, vcount, n, n_poses, roff, vbase, kb, vb, ka, va);
+                           dim3(kThreads), 0, s, vmask, n, n_poses, roff, vbase, kb, vb, ka, va);
     // four dense passes: (ka, va) -> (kb, vb) -> (ka, va) -> (kb, vb) -> (ka = tile counts, va = slots)
     const uint32_t *kin = ka, *vin = va;
     for (int pass = 0; pass < 4; ++pass) {
@@ -961,10 +963,10 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint32_t *vc
         uint32_t *ko = (pass & 1) ? ka : kb, *vo = (pass & 1) ? va : vb;
         if (pass == 3)
             hipLaunchKernelGGL(k_radix_scatter<true>, sgrid, dim3(kRBThreads), 0, s, src, shift, nbp, n_poses, roff,
-                               ko, vo, ntiles, n, packed, slot0);
+                               ko, vo, rect, n, packed, slot0);
         else
             hipLaunchKernelGGL(k_radix_scatter<false>, sgrid, dim3(kRBThreads), 0, s, src, shift, nbp, n_poses, roff,
-                               ko, vo, ntiles, n, packed, slot0);
+                               ko, vo, rect, n, packed, slot0);
         kin = ko;
         vin = vo;
     }
