@@ -152,7 +152,7 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
     // per wave, quarter and step: LDS byte offset of the record the quarter
     // visits (steps 0..253: a walk has at most 252 steps and reads 2 ahead)
     constexpr int kSlotCap = 254;
-    __shared__ __attribute__((aligned(4))) uint16_t s_slots[4][4][kSlotCap];
+    __shared__ __attribute__((aligned(16))) uint16_t s_slots[4][4][kSlotCap];
     __shared__ uint32_t s_live[4];   // per wave: any pixel still live after the chunk
     __shared__ uint32_t s_clamp[4];  // per wave: a staged record whose alpha may reach alpha_max
 
@@ -332,12 +332,14 @@ __device__ __forceinline__ void blend_tile(int tile, int pose, const float4 *__r
             // in slot 64 g + l is entered by lane l at its rank in each quarter's
             // walk; every lane then reads its own quarter's slots. One wave: its
             // LDS accesses complete in program order.
-            uint32_t *slots32 = reinterpret_cast<uint32_t *>(&s_slots[wave][0][0]);
+            // (16-byte stores: a wave's four lists are 127 of them)
+            uint4 *slots128 = reinterpret_cast<uint4 *>(&s_slots[wave][0][0]);
             constexpr uint32_t kDummyPair = kDummy * kSlotBytes * 0x00010001u;
-            static_assert(kDummy * kSlotBytes < 65536u && (4 * kSlotCap) % 2 == 0, "16-bit offsets, whole words");
+            static_assert(kDummy * kSlotBytes < 65536u && (4 * kSlotCap * 2) % 16 == 0, "16-bit offsets, whole pieces");
+            const uint4 dummy4 = make_uint4(kDummyPair, kDummyPair, kDummyPair, kDummyPair);
 #pragma unroll
-            for (int e = 0; e < (4 * kSlotCap / 2 + 63) / 64; ++e)
-                if (e * 64 + lane < 4 * kSlotCap / 2) slots32[e * 64 + lane] = kDummyPair;
+            for (int e = 0; e < (4 * kSlotCap / 8 + 63) / 64; ++e)
+                if (e * 64 + lane < 4 * kSlotCap / 8) slots128[e * 64 + lane] = dummy4;
             // Group by group (lane l: the record in slot 64 g + l), each quarter's
             // walk grows by the group's records that overlap the quarter's cell.
             uint32_t run[4] = {0u, 0u, 0u, 0u};
