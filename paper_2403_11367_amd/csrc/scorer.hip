@@ -340,11 +340,39 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ x, Con
             }
         }
     }
-    u16 *dst[RM];
+    if constexpr (WGN == 1) {
+        // A wave's RM x 32 pixels are consecutive in the output and it holds all
+        // of their channels: the results go through LDS (rows padded by 16 bytes)
+        // and leave in 16-byte stores of consecutive addresses, instead of 8-byte
+        // stores a pixel row (CO x 2 bytes) apart.
+        constexpr int PXW = RM * 32, ROWB = CO * 2 + 16, PPP = CO * 2 / 16;  // pixels, row bytes, pieces per pixel
+        __shared__ __align__(16) unsigned char s_out[4][PXW * ROWB];
+        unsigned char *so = s_out[wave];
+        const LaneBias<RN> bv = load_lane_bias<RN>(bias);
 #pragma unroll
-    for (int r = 0; r < RM; ++r)
-        dst[r] = live[r] ? y + ((int64_t)n * hw + m0 + 32 * r + r32) * CO + cob : nullptr;
-    store_relu_bf16<RM, RN>(acc, dst, load_lane_bias<RN>(bias + cob));
+        for (int r = 0; r < RM; ++r)
+#pragma unroll
+            for (int c = 0; c < RN; ++c)
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    *(uint2 *)(so + (32 * r + r32) * ROWB + (32 * c + 8 * g + 4 * kq) * 2) =
+                        relu_bf16x4(acc[r][c][4 * g], acc[r][c][4 * g + 1], acc[r][c][4 * g + 2],
+                                    acc[r][c][4 * g + 3], bv.v[c][g]);
+        __builtin_amdgcn_wave_barrier();  // (one wave's LDS accesses complete in program order)
+#pragma unroll
+        for (int t = lane; t < PXW * PPP; t += 64) {
+            const int px = t / PPP, part = t - px * PPP;
+            if (m0 + px < hw)
+                *(uint4 *)(y + ((int64_t)n * hw + m0 + px) * CO + 8 * part) =
+                    *(const uint4 *)(so + px * ROWB + 16 * part);
+        }
+    } else {
+        u16 *dst[RM];
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+            dst[r] = live[r] ? y + ((int64_t)n * hw + m0 + 32 * r + r32) * CO + cob : nullptr;
+        store_relu_bf16<RM, RN>(acc, dst, load_lane_bias<RN>(bias + cob));
+    }
 }
 
 // Forward for c_in >= 32, LDS-staged: one block computes a TH x TW tile of output
