@@ -79,7 +79,7 @@ typedef struct {
                               * GSR_EUNSUPPORTED); the tile lists and so the images depend on it
                               * within float32 rounding of the compositing */
     float eps_dilate;        /* screen-covariance dilation, px^2 [0.3] */
-    float z_near;            /* near plane, metres; cull unless t_z > z_near [0.2] */
+    float z_near;            /* near plane, metres, >= 0; cull unless t_z > z_near [0.2] */
     float jac_clamp;         /* Jacobian point clamp, x of half field of view [1.3] */
     float cutoff_d2;         /* footprint support d^2 <= cutoff_d2 [9] */
     float alpha_min;         /* skip layers with alpha < alpha_min [float32(1/255)] */

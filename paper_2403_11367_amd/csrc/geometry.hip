@@ -98,16 +98,17 @@ __global__ void k_sum_nonfinite(const SubmapTable tab, unsigned long long *__res
 // into the next submap of a batch; slot g of a pose whose submap has no
 // Gaussian g is culled). For each pose the screen record and the tile
 // rectangle of a visible Gaussian are written, and each wave packs the (depth
-// bits, sort value) of its visible Gaussians, in index order, at the front of
+// key, sort value) of its visible Gaussians, in index order, at the front of
 // its 64-slot region of vz / vg, with the region's visibility mask (bit l: slot
 // 64 region + l is visible) in vmask[pose * n_regions + region]: the input of
 // the per-pose depth sort. (The mask replaces a 4-byte tile count per pose and
 // Gaussian: 8 bytes per 64 slots; the count is in the sort value and follows
-// from the tile rectangle.)
+// from the tile rectangle.) The depth key is the depth's float32 bits minus the
+// near plane's; a key of 2^kNarrowKeyBits or more raises *wide.
 __global__ __launch_bounds__(kThreads) void k_preprocess(
     const SubmapTable tab, int64_t n, const float *__restrict__ poses, int n_poses, Camera cam,
     Consts k, TileGrid tg, float4 *__restrict__ records, uint2 *__restrict__ rect, uint32_t *__restrict__ vz,
-    uint32_t *__restrict__ vg, uint64_t *__restrict__ vmask, bool pack) {
+    uint32_t *__restrict__ vg, uint64_t *__restrict__ vmask, bool pack, unsigned long long *__restrict__ wide) {
     const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int p0 = blockIdx.y * kPosesPerThread;
     const int p1 = min(p0 + kPosesPerThread, n_poses);
@@ -140,6 +141,8 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
     const float lim_x = k.jac_clamp * ((0.5f * (float)cam.width) / cam.fx);
     const float lim_y = k.jac_clamp * ((0.5f * (float)cam.height) / cam.fy);
     const float wmax = (float)(cam.width - 1), hmax = (float)(cam.height - 1);
+    // visible depths exceed z_near >= 0, so their bits exceed these
+    const uint32_t zoff = k.z_near > 0.f ? __float_as_uint(k.z_near) : 0u;
     for (int p = p0; p < p1; ++p) {
         if (p >= tab.pose_end[q]) {
             while (p >= tab.pose_end[q]) ++q;
@@ -203,13 +206,14 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
                                                __uint_as_float((uint32_t)j0 | ((uint32_t)j1 << 16)));
                             rect[(int64_t)p * n + g] = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16),
                                                                   (uint32_t)ty0 | ((uint32_t)ty1 << 16));
-                            zb = __float_as_uint(tz);
+                            zb = __float_as_uint(tz) - zoff;
                         }
                     }
                 }
             }
         }
         const uint64_t vis = __ballot(nt != 0);
+        if (__ballot(nt != 0 && zb >= (1u << kNarrowKeyBits)) != 0ull && lane == 0) atomicOr(wide, 1ull);
         if (region_in) {
             if (lane == 0) vmask[(int64_t)p * n_regions + region] = vis;
             if (nt != 0) {
@@ -224,7 +228,8 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
 
 // S2, pair emission in front-to-back order. The depth-sorted visible Gaussians of
 // all poses are cut into emission blocks of kEmitTile elements (pose p owns
-// [vbase[p], vbase[p+1]); snt holds their tile counts, sg their indices). The
+// [vbase[p], vbase[p+1]); the sorted run holds their tile counts and record
+// slots). The
 // tile counts are summed per block, the block sums prefixed in two levels (within
 // spans of kSumSpan blocks, then across spans by a scan in sort.hip), and each
 // block then lays its pairs out contiguously from its prefix: element i writes
@@ -264,10 +269,10 @@ __device__ uint32_t emit_block_scan(uint32_t x, uint32_t *s_wave /*[4]*/, uint32
 // elements k * 64 + l of a block, coalesced). Spans past the visible total
 // write nothing.
 static_assert(kSumSpan == 2 * (kThreads / 64), "two emission blocks per wave");
-__global__ __launch_bounds__(kThreads) void k_emit_sums(const uint32_t *__restrict__ snt,
-                                                        const uint32_t *__restrict__ vbase, int P,
-                                                        uint64_t n_blocks, uint64_t *__restrict__ es) {
+__global__ __launch_bounds__(kThreads) void k_emit_sums(const SortedRun run, const uint32_t *__restrict__ vbase,
+                                                        int P, uint64_t n_blocks, uint64_t *__restrict__ es) {
     __shared__ uint32_t s_sum[kSumSpan];
+    const uint32_t *__restrict__ snt = *run.wide ? run.cnt_a : run.cnt_b;
     const uint64_t nv = vbase[P];
     const uint64_t blocks_used = (nv + kEmitTile - 1) / kEmitTile;
     if (blockIdx.x == 0 && threadIdx.x == 0) es[n_blocks + 1] = (blocks_used + kSumSpan - 1) / kSumSpan;
@@ -313,11 +318,11 @@ __global__ __launch_bounds__(kThreads) void k_emit_sums(const uint32_t *__restri
 
 // pseg[p] = min(first pair of pose p, capacity) for p in [0, P], from the
 // scanned emission sums es (es[n_blocks]: the pair total).
-__global__ __launch_bounds__(kThreads) void k_pair_segments(const uint32_t *__restrict__ snt,
-                                                            const uint32_t *__restrict__ vbase, int P,
-                                                            const uint64_t *__restrict__ es, uint64_t n_blocks,
+__global__ __launch_bounds__(kThreads) void k_pair_segments(const SortedRun run, const uint32_t *__restrict__ vbase,
+                                                            int P, const uint64_t *__restrict__ es, uint64_t n_blocks,
                                                             uint64_t capacity, uint64_t *__restrict__ pseg) {
     __shared__ uint32_t s_wave[4];
+    const uint32_t *__restrict__ snt = *run.wide ? run.cnt_a : run.cnt_b;
     const int p = blockIdx.x;
     const uint64_t e = vbase[p], nv = vbase[P];
     if (e >= nv) {
@@ -350,8 +355,7 @@ __device__ __forceinline__ uint32_t slot_index(uint32_t x, uint32_t n, float inv
 // the block copies the window to the output with coalesced stores.
 constexpr int kEmitWin = 4096;  // pairs per LDS window
 
-__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ snt, const uint32_t *__restrict__ slots,
-                                                   const uint32_t *__restrict__ vbase, int P,
+__global__ __launch_bounds__(kThreads) void k_emit(const SortedRun run, const uint32_t *__restrict__ vbase, int P,
                                                    const uint2 *__restrict__ rect, int64_t n,
                                                    const uint64_t *__restrict__ es, uint64_t n_blocks, TileGrid tg,
                                                    uint16_t *__restrict__ ptile, uint32_t *__restrict__ pk,
@@ -359,6 +363,9 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *__restrict__ 
     __shared__ uint16_t s_tile[kEmitWin];
     __shared__ uint32_t s_key[kEmitWin];
     __shared__ uint32_t s_wave[4];
+    const bool wide = *run.wide != 0ull;
+    const uint32_t *__restrict__ snt = wide ? run.cnt_a : run.cnt_b;
+    const uint32_t *__restrict__ slots = wide ? run.slot_a : run.slot_b;
     // Workgroups go to the 8 XCDs round robin by linear id; block b below takes
     // emission block (b % 8) * per + b / 8 with per = ceil(nb / 8) for the nb
     // blocks that hold elements, so each XCD walks one eighth of the elements in
@@ -463,11 +470,11 @@ int64_t preprocess_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }
 
 void launch_preprocess(hipStream_t s, const SubmapTable &tab, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records, uint2 *rect,
-                       uint32_t *vz, uint32_t *vg, uint64_t *vmask, bool pack) {
+                       uint32_t *vz, uint32_t *vg, uint64_t *vmask, bool pack, unsigned long long *wide) {
     if (n <= 0) return;
     const dim3 grid((unsigned)preprocess_blocks(n), (unsigned)((n_poses + kPosesPerThread - 1) / kPosesPerThread));
     hipLaunchKernelGGL(k_preprocess, grid, dim3(kThreads), 0, s, tab, n, poses, n_poses, cam, k, tg, records,
-                       rect, vz, vg, vmask, pack);
+                       rect, vz, vg, vmask, pack, wide);
 }
 
 uint64_t emit_blocks(uint64_t n_max) { return std::max<uint64_t>(1, (n_max + kEmitTile - 1) / kEmitTile); }
@@ -477,26 +484,26 @@ uint64_t emit_sums_size(uint64_t n_max) {
     return nb + 2 + (nb + kSumSpan - 1) / kSumSpan;
 }
 
-void launch_emit_sums(hipStream_t s, const uint32_t *snt, const uint32_t *vbase, int n_poses, uint64_t n_max,
+void launch_emit_sums(hipStream_t s, const SortedRun &run, const uint32_t *vbase, int n_poses, uint64_t n_max,
                       uint64_t *es) {
     const uint64_t nb = emit_blocks(n_max), spans = (nb + kSumSpan - 1) / kSumSpan;
-    hipLaunchKernelGGL(k_emit_sums, dim3((unsigned)spans), dim3(kThreads), 0, s, snt, vbase, n_poses, nb, es);
+    hipLaunchKernelGGL(k_emit_sums, dim3((unsigned)spans), dim3(kThreads), 0, s, run, vbase, n_poses, nb, es);
     // the span sums, scanned in place (only the spans in use); the pair total to es[nb]
     launch_block_scan(s, es + nb + 2, spans, es + nb + 1, es + nb);
 }
 
-void launch_pair_segments(hipStream_t s, const uint32_t *snt, const uint32_t *vbase, int n_poses,
+void launch_pair_segments(hipStream_t s, const SortedRun &run, const uint32_t *vbase, int n_poses,
                           const uint64_t *es, uint64_t n_max, uint64_t capacity, uint64_t *pseg) {
-    hipLaunchKernelGGL(k_pair_segments, dim3((unsigned)n_poses + 1), dim3(kThreads), 0, s, snt, vbase, n_poses,
+    hipLaunchKernelGGL(k_pair_segments, dim3((unsigned)n_poses + 1), dim3(kThreads), 0, s, run, vbase, n_poses,
                        es, emit_blocks(n_max), capacity, pseg);
 }
 
-void launch_emit(hipStream_t s, const uint32_t *snt, const uint32_t *sg, const uint32_t *vbase, int n_poses,
+void launch_emit(hipStream_t s, const SortedRun &run, const uint32_t *vbase, int n_poses,
                  const uint2 *rect, int64_t n, uint64_t n_max, const uint64_t *es, const TileGrid &tg,
                  uint16_t *ptile, uint32_t *pk, uint64_t capacity, int *flags) {
     if (n <= 0) return;
     const uint64_t grid = (emit_blocks(n_max) + kXcdCount - 1) / kXcdCount * kXcdCount;  // see k_emit
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(kThreads), 0, s, snt, sg, vbase, n_poses,
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(kThreads), 0, s, run, vbase, n_poses,
                        rect, n, es, emit_blocks(n_max), tg, ptile, pk, capacity, flags);
 }
 

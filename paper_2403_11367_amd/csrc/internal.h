@@ -15,7 +15,15 @@ namespace gsr {
 // Device flag slots (int32 each), raised by kernels, read and cleared by gsr_sync.
 enum : int { FLAG_OVERFLOW = 0, FLAG_BAD_INDEX = 1, FLAG_COUNT = 4 };
 // Device counter slots (uint64 each), reset at the start of a render.
-enum : int { CNT_EVALS_CONTRIB = 0, CNT_EVALS_LANES = 1, CNT_NONFINITE = 2, CNT_COUNT = 8 };
+// CNT_WIDE_DEPTH: nonzero when some visible depth key reaches 2^kNarrowKeyBits.
+enum : int { CNT_EVALS_CONTRIB = 0, CNT_EVALS_LANES = 1, CNT_NONFINITE = 2, CNT_WIDE_DEPTH = 3, CNT_COUNT = 8 };
+
+// Depth keys: float32 depth bits minus the near plane's (the near plane is not
+// negative, so every visible depth is positive and keys order like depths).
+// Keys below 2^kNarrowKeyBits (depths up to about 2^16 times a positive near
+// plane) sort in three 9-bit radix passes; the preprocess flags any larger key
+// in CNT_WIDE_DEPTH, and a fourth pass then runs.
+constexpr int kNarrowKeyBits = 27;
 
 // Packed submap record: 4 float4 (64 B) per Gaussian.
 //   q0 = (mu_x, mu_y, mu_z, opacity)
@@ -83,9 +91,10 @@ int64_t preprocess_blocks(int64_t n);
 // Screen records and tile rectangles rect[p][g] = (tx0 | tx1 << 16, ty0 | ty1
 // << 16) of the visible Gaussians (entries of culled ones are left as they
 // were); per pose and 64-Gaussian region, the visibility mask (bit l: Gaussian
-// 64 region + l) in vmask[p * ceil(n / 64) + region], and the (depth bits, sort
+// 64 region + l) in vmask[p * ceil(n / 64) + region], and the (depth key, sort
 // value) of the visible Gaussians packed at the front of the region's slots of
-// vz / vg (P * n each).
+// vz / vg (P * n each); *wide (a CNT_WIDE_DEPTH counter) is raised when a depth
+// key reaches 2^kNarrowKeyBits.
 // Sort values: the record slot (pose * n + index) of each visible Gaussian, or,
 // where pack_sort_values(n, n_tiles), (index) | (tile count << kPackIndexBits),
 // which the depth sort's last pass turns back into the slot and the count.
@@ -95,7 +104,15 @@ inline bool pack_sort_values(int64_t n, int n_tiles) {
 }
 void launch_preprocess(hipStream_t s, const SubmapTable &tab, int64_t n, const float *poses, int n_poses,
                        const Camera &cam, const Consts &k, const TileGrid &tg, float4 *records,
-                       uint2 *rect, uint32_t *vz, uint32_t *vg, uint64_t *vmask, bool pack);
+                       uint2 *rect, uint32_t *vz, uint32_t *vg, uint64_t *vmask, bool pack,
+                       unsigned long long *wide);
+// The depth sort's output (tile counts and record slots, front to back): in the
+// "b" buffers after three radix passes, in the "a" buffers after four (when
+// *wide is raised).
+struct SortedRun {
+    const uint32_t *cnt_b, *slot_b, *cnt_a, *slot_a;
+    const unsigned long long *wide;
+};
 // Pair emission in front-to-back order. The depth-sorted visible Gaussians
 // (snt: tile counts, sg: record slots p * n + g; pose p owns [vbase[p],
 // vbase[p+1]), at most n_max = P * n of them) are cut into nb = emit_blocks(n_max)
@@ -109,21 +126,22 @@ void launch_preprocess(hipStream_t s, const SubmapTable &tab, int64_t n, const f
 //   launch_emit:          ptile / pk = tile id within the pose / submap index per pair
 uint64_t emit_blocks(uint64_t n_max);
 uint64_t emit_sums_size(uint64_t n_max);
-void launch_emit_sums(hipStream_t s, const uint32_t *snt, const uint32_t *vbase, int n_poses, uint64_t n_max,
+void launch_emit_sums(hipStream_t s, const SortedRun &run, const uint32_t *vbase, int n_poses, uint64_t n_max,
                       uint64_t *es);
-void launch_pair_segments(hipStream_t s, const uint32_t *snt, const uint32_t *vbase, int n_poses,
+void launch_pair_segments(hipStream_t s, const SortedRun &run, const uint32_t *vbase, int n_poses,
                           const uint64_t *es, uint64_t n_max, uint64_t capacity, uint64_t *pseg);
-void launch_emit(hipStream_t s, const uint32_t *snt, const uint32_t *sg, const uint32_t *vbase, int n_poses,
+void launch_emit(hipStream_t s, const SortedRun &run, const uint32_t *vbase, int n_poses,
                  const uint2 *rect, int64_t n, uint64_t n_max, const uint64_t *es, const TileGrid &tg,
                  uint16_t *ptile, uint32_t *pk, uint64_t capacity, int *flags);
 
 // ---- sort.hip ----
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t value);
 void launch_fill_u64(hipStream_t s, unsigned long long *p, uint64_t n, unsigned long long value);
-// Per-pose stable sort of the visible Gaussians by depth bits. Input: the
-// preprocess's regions in (kb, vb) with vmask. Output: va[vbase[p] ..
-// vbase[p+1]) = pose p's record slots front to back, ka = their tile counts,
-// vbase[P] = visible total; nv[p] = pose p's visible count.
+// Per-pose stable sort of the visible Gaussians by depth key. Input: the
+// preprocess's regions in (kb, vb) with vmask. Output: vb[vbase[p] ..
+// vbase[p+1]) = pose p's record slots front to back, kb = their tile counts, or
+// the same in (va, ka) when *wide is raised (see SortedRun); vbase[P] = visible
+// total; nv[p] = pose p's visible count.
 // ka, va, kb, vb hold P * n entries; rcnt and roff radix_count_elems each.
 uint64_t radix_blocks_per_pose(int64_t n);
 uint64_t radix_count_elems(int64_t n, int n_poses);
@@ -131,8 +149,8 @@ uint64_t radix_count_elems(int64_t n, int n_poses);
 // over all poses of the render); pack: the values are packed (as the preprocess
 // wrote them).
 void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint64_t *vmask, const uint2 *rect,
-                       uint32_t slot0, bool pack, uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
-                       uint32_t *rcnt, uint32_t *roff, uint32_t *nv, uint32_t *vbase);
+                       uint32_t slot0, bool pack, const unsigned long long *wide, uint32_t *ka, uint32_t *va,
+                       uint32_t *kb, uint32_t *vb, uint32_t *rcnt, uint32_t *roff, uint32_t *nv, uint32_t *vbase);
 // Exclusive scan of sums[0 .. nb_max) in place (only the first *d_nb with d_nb),
 // total to *total. One block.
 void launch_block_scan(hipStream_t s, uint64_t *sums, uint64_t nb_max, const uint64_t *d_nb, uint64_t *total);

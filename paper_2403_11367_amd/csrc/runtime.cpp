@@ -476,7 +476,7 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
     if (!gsr::blend_tile_supported(cfg.tile_w, cfg.tile_h))
         return fail(ctx, GSR_EUNSUPPORTED, "this library renders 16x16, 32x8 or 8x32 tiles");
     if (!(cfg.alpha_min > 0.f) || !(cfg.alpha_max <= 1.f) || !(cfg.alpha_min < cfg.alpha_max) ||
-        !(cfg.t_min > 0.f) || !(cfg.cutoff_d2 > 0.f) || !(cfg.eps_dilate >= 0.f))
+        !(cfg.t_min > 0.f) || !(cfg.cutoff_d2 > 0.f) || !(cfg.eps_dilate >= 0.f) || !(cfg.z_near >= 0.f))
         return fail(ctx, GSR_EINVAL, "bad render constants");
     HIPC(ctx, hipSetDevice(ctx->device));
 
@@ -608,10 +608,16 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
     gsr::launch_sum_nonfinite(s, tab, ctx->d_counters + gsr::CNT_NONFINITE);
     const bool pack = gsr::pack_sort_values(n, tg.n_tiles);  // tile counts ride in the sort values
     gsr::launch_preprocess(s, tab, n, poses, n_poses, c, k, tg, (float4 *)ctx->records.p, (uint2 *)ctx->rect.p,
-                           sort_kb, sort_vb, (uint64_t *)ctx->vmask.p, pack);
+                           sort_kb, sort_vb, (uint64_t *)ctx->vmask.p, pack, ctx->d_counters + gsr::CNT_WIDE_DEPTH);
     if ((rc = check_launch(ctx, "preprocess"))) return rc;
     if (ev) HIPC(ctx, hipEventRecord(ev->e[1], s));
 
+    // the depth sort's output of group g (three or four radix passes)
+    const unsigned long long *wide = ctx->d_counters + gsr::CNT_WIDE_DEPTH;
+    auto sorted_run = [&](int g) {
+        const uint64_t so = (uint64_t)ctx->groups[g].p0 * n;
+        return gsr::SortedRun{sort_kb + so, sort_vb + so, sort_ka + so, sort_va + so, wide};
+    };
     // ordering, part 1 of group g: per-pose depth order of its visible Gaussians
     // and the emission sums. Group slices: poses p0.., Gaussian slots p0 * n..
     auto order_part1 = [&](int g, hipStream_t st) {
@@ -619,21 +625,20 @@ int render_impl(gsr_ctx *ctx, const gsr::SubmapTable &tab, int64_t n_slot, const
         const uint64_t so = (uint64_t)gr.p0 * n, ro = gsr::radix_count_elems(n, (int)gr.p0);
         const uint64_t gpn = (uint64_t)std::max<int64_t>(1, gr.np * n);
         gsr::launch_depth_sort(st, n, (int)gr.np, (const uint64_t *)ctx->vmask.p + (uint64_t)gr.p0 * n_regions,
-                               (const uint2 *)ctx->rect.p,
-                               (uint32_t)so, pack, sort_ka + so, sort_va + so, sort_kb + so, sort_vb + so, (uint32_t *)ctx->rcnt.p + ro,
+                               (const uint2 *)ctx->rect.p, (uint32_t)so, pack, wide, sort_ka + so, sort_va + so,
+                               sort_kb + so, sort_vb + so, (uint32_t *)ctx->rcnt.p + ro,
                                (uint32_t *)ctx->roff.p + ro, (uint32_t *)ctx->nv.p + gr.p0, vbase + gr.vb);
-        gsr::launch_emit_sums(st, sort_ka + so, vbase + gr.vb, (int)gr.np, gpn, esum + gr.es);
+        gsr::launch_emit_sums(st, sorted_run(g), vbase + gr.vb, (int)gr.np, gpn, esum + gr.es);
     };
     // ordering, part 2 (pair emission and stable bucketing by tile), then compositing
     auto order_part2 = [&](int g, hipStream_t st) {
         const gsr_ctx::Group &gr = ctx->groups[g];
-        const uint64_t so = (uint64_t)gr.p0 * n;
         const uint64_t gpn = (uint64_t)std::max<int64_t>(1, gr.np * n);
         uint16_t *ptile = (uint16_t *)ctx->ptile.p + gr.pairs;
         uint32_t *pk = (uint32_t *)ctx->pk.p + gr.pairs;
-        gsr::launch_pair_segments(st, sort_ka + so, vbase + gr.vb, (int)gr.np, esum + gr.es, gpn, gr.cap,
+        gsr::launch_pair_segments(st, sorted_run(g), vbase + gr.vb, (int)gr.np, esum + gr.es, gpn, gr.cap,
                                   (uint64_t *)ctx->pseg.p + gr.vb);
-        gsr::launch_emit(st, sort_ka + so, sort_va + so, vbase + gr.vb, (int)gr.np, (const uint2 *)ctx->rect.p, n, gpn,
+        gsr::launch_emit(st, sorted_run(g), vbase + gr.vb, (int)gr.np, (const uint2 *)ctx->rect.p, n, gpn,
                          esum + gr.es, tg, ptile, pk, gr.cap, ctx->d_flags);
         gsr::launch_bucket(st, ptile, pk, (uint64_t *)ctx->pseg.p + gr.vb, (int)gr.np, gr.cap, tg.n_tiles,
                            (uint32_t *)ctx->block_base.p + gr.cst, (uint32_t *)ctx->bseg.p + gr.bsg,

@@ -5,9 +5,11 @@
 // equal depths in ascending submap index (a total order).
 //
 // Depth does not depend on the tile, so the order is built in two stable sorts:
-//   1. per pose, the visible Gaussians are sorted by their float32 depth bits
-//      with a stable LSD radix sort (four 8-bit digits). Its input is in index
-//      order, so equal depths stay in index order;
+//   1. per pose, the visible Gaussians are sorted by their depth keys (float32
+//      depth bits minus the near plane's, which order like the depths) with a
+//      stable LSD radix sort of 9-bit digits: three passes, and a fourth only
+//      when some key reaches 2^27 (a depth above about 13 km for a 0.2 m near
+//      plane). Its input is in index order, so equal depths stay in index order;
 //   2. the pairs are emitted in that order (geometry.hip) and a stable sort by
 //      tile (two passes: buckets of 64 tiles, then tiles) buckets them into
 //      per-(pose, tile) lists, which keeps the depth order inside every list.
@@ -115,9 +117,10 @@ __device__ __forceinline__ uint64_t match_peers(uint32_t key, bool valid) {
 }
 
 // ---- per-pose depth sort: stable LSD radix sort of the visible Gaussians ----
-// Keys are float32 depth bits (depths are above the near plane, so positive,
-// and order like their bits); values are record slots (pose * n + submap
-// index), which within a pose order like the indices. A pose's elements are
+// Keys are float32 depth bits minus the near plane's (depths are above a
+// non-negative near plane, so positive, and order like their bits); values are
+// record slots (pose * n + submap index), which within a pose order like the
+// indices. A pose's elements are
 // cut into radix blocks of kRB; per pass every block counts its digits, one
 // block per pose scans the counts in (digit, block) order into each block's
 // output position for its first element of every digit, and the block writes
@@ -131,7 +134,17 @@ constexpr int kRBThreads = 64 * kRBWaves;
 constexpr int kRBWave = 1024;              // elements per wave, contiguous
 constexpr int kRB = kRBWaves * kRBWave;    // elements per radix block
 constexpr int kRBChunks = kRBWave / 64;    // 64-element chunks per wave
-constexpr int kDigits = 256;
+constexpr int kDigitBits = 9;
+constexpr int kDigits = 1 << kDigitBits;
+constexpr int kKeyPasses = 4;              // 4 x 9 bits cover any 32-bit key
+constexpr int kNarrowPasses = kNarrowKeyBits / kDigitBits;  // enough when every key is below 2^27
+static_assert(kNarrowPasses * kDigitBits == kNarrowKeyBits && kKeyPasses * kDigitBits >= 32, "digit split");
+
+// Whether pass `pass` runs: the passes past the narrow ones only when the
+// preprocess flagged a key of 2^27 or more.
+__device__ __forceinline__ bool radix_pass_runs(int pass, const unsigned long long *wide) {
+    return pass < kNarrowPasses || *wide != 0ull;
+}
 
 struct RadixSrc {
     const uint32_t *keys, *vals;
@@ -147,18 +160,18 @@ __device__ __forceinline__ bool radix_elem(const RadixSrc &src, int p, uint32_t 
     return i < (uint64_t)src.vbase[p + 1];
 }
 
-// cnt[(p * nbp + j) * 256 + digit] = elements of radix block (p, j) with that digit.
-// kGroup (for a digit with few distinct values, such as the exponent byte of a
-// positive depth): lanes with the same digit are grouped by 8 ballots and one of
-// them adds the group's count, instead of up to 64 same-address LDS atomics.
-template <bool kGroup>
-__global__ __launch_bounds__(kRBThreads) void k_radix_count(RadixSrc src, int shift, uint32_t nbp,
+// cnt[(p * nbp + j) * kDigits + digit] = elements of radix block (p, j) with that
+// digit of pass `pass`.
+__global__ __launch_bounds__(kRBThreads) void k_radix_count(RadixSrc src, int pass, uint32_t nbp,
+                                                          const unsigned long long *__restrict__ wide,
                                                           uint32_t *__restrict__ cnt) {
     __shared__ uint32_t s_h[kRBWaves][kDigits];  // per wave, so only a wave's own lanes meet at a counter
+    if (!radix_pass_runs(pass, wide)) return;
     const int p = blockIdx.y;
     const uint32_t j = blockIdx.x;
     if ((uint64_t)src.vbase[p] + (uint64_t)j * kRB >= src.vbase[p + 1]) return;  // empty block
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int shift = kDigitBits * pass;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < kRBWaves * kDigits; i += kRBThreads) (&s_h[0][0])[i] = 0;
     // every chunk's key is loaded before the first count, so the loads overlap
     uint32_t key[kRBChunks];
@@ -172,17 +185,8 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_count(RadixSrc src, int sh
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < kRBChunks; ++c) {
-        const bool valid = (vmask >> c) & 1u;
-        const uint32_t d = (key[c] >> shift) & 0xffu;
-        if constexpr (kGroup) {
-            const uint64_t same = match_peers<8>(d, valid);  // valid lanes whose digit equals this lane's
-            // the group's lowest lane adds its size
-            if (valid && (same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&s_h[wave][d], (uint32_t)__popcll(same));
-        } else {
-            if (valid) atomicAdd(&s_h[wave][d], 1u);
-        }
-    }
+    for (int c = 0; c < kRBChunks; ++c)
+        if ((vmask >> c) & 1u) atomicAdd(&s_h[wave][(key[c] >> shift) & (kDigits - 1)], 1u);
     __syncthreads();
     for (int d = threadIdx.x; d < kDigits; d += kRBThreads) {
         uint32_t t = 0;
@@ -210,21 +214,22 @@ __device__ uint32_t block_exclusive_scan_u32(uint32_t x, uint32_t *s_wave /*[4]*
     return add + inc - x;
 }
 
-// Offsets of one segment's blocks per key, by a block of 256 kGroups threads: cnt[j * K +
-// k] (block j < nb of the segment, key k < K <= 256) are its blocks' key counts;
+// Offsets of one segment's blocks per key, by a block of kKeys kGroups threads: cnt[j * K +
+// k] (block j < nb of the segment, key k < K <= kKeys) are its blocks' key counts;
 // off[j * K + k] <- the position, relative to the segment's first element, of
 // block j's first element with key k (keys in order, blocks in order within a
 // key); off may be cnt. Returns to thread k < K of the first group the start of
 // key k's run (relative), and to every thread the segment's total in *all. The
-// blocks are split over the kGroups groups of 256 threads (thread = key), which
+// blocks are split over the kGroups groups of kKeys threads (thread = key), which
 // sum their share, 8 blocks per step with the loads in flight together, and
 // then write it from their prefix: a chain of nb / (8 kGroups) dependent loads
 // instead of nb / 8 (for segments of many blocks).
-template <int kGroups>
+template <int kKeys, int kGroups>
 __device__ uint32_t seg_key_offsets(const uint32_t *cnt, uint32_t *off, uint32_t nb, int K,
-                                    uint32_t (*s_part)[256] /*[kGroups][256]*/, uint32_t *s_wave /*[4]*/,
-                                    uint32_t *all) {
-    const int g = threadIdx.x >> 8, k = threadIdx.x & 255;
+                                    uint32_t (*s_part)[kKeys] /*[kGroups][kKeys]*/,
+                                    uint32_t *s_wave /*[kKeys / 64]*/, uint32_t *all) {
+    constexpr int kWaves = kKeys / 64;
+    const int g = threadIdx.x / kKeys, k = threadIdx.x % kKeys;
     const uint32_t per = (nb + kGroups - 1) / kGroups;
     const uint32_t j0 = min(nb, g * per), j1 = min(nb, j0 + per);
     uint32_t tot = 0;
@@ -239,7 +244,7 @@ __device__ uint32_t seg_key_offsets(const uint32_t *cnt, uint32_t *off, uint32_t
     }
     s_part[g][k] = tot;
     __syncthreads();
-    // key totals, scanned over the keys by the first 256 threads
+    // key totals, scanned over the keys by the first kKeys threads
     uint32_t key_tot = 0;
     if (g == 0) {
 #pragma unroll
@@ -254,7 +259,9 @@ __device__ uint32_t seg_key_offsets(const uint32_t *cnt, uint32_t *off, uint32_t
     }
     if (g == 0 && lane == 63) s_wave[wave] = inc;
     __syncthreads();
-    const uint32_t total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    uint32_t total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) total += s_wave[w];
     uint32_t start = 0;
     if (g == 0) {
         start = inc - key_tot;
@@ -287,20 +294,22 @@ __device__ uint32_t seg_key_offsets(const uint32_t *cnt, uint32_t *off, uint32_t
     return start;
 }
 
-// Per pose (one block): off[(p * nbp + j) * 256 + d] = position, relative to the
-// pose's first element, of radix block j's first element with digit d (digits in
-// order, blocks in order within a digit).
-constexpr int kOffGroups = 4;  // radix blocks per pose: tens to hundreds
-__global__ __launch_bounds__(256 * kOffGroups) void k_radix_offsets(const uint32_t *__restrict__ cnt, uint32_t nbp,
-                                                                   const uint32_t *__restrict__ vbase,
-                                                                   uint32_t *__restrict__ off) {
-    __shared__ uint32_t s_part[kOffGroups][256];
-    __shared__ uint32_t s_wave[4];
+// Per pose (one block): off[(p * nbp + j) * kDigits + d] = position, relative to
+// the pose's first element, of radix block j's first element with digit d
+// (digits in order, blocks in order within a digit).
+constexpr int kOffGroups = 1024 / kDigits;  // radix blocks per pose: tens to hundreds
+__global__ __launch_bounds__(kDigits * kOffGroups) void k_radix_offsets(const uint32_t *__restrict__ cnt, uint32_t nbp,
+                                                                       const uint32_t *__restrict__ vbase, int pass,
+                                                                       const unsigned long long *__restrict__ wide,
+                                                                       uint32_t *__restrict__ off) {
+    __shared__ uint32_t s_part[kOffGroups][kDigits];
+    __shared__ uint32_t s_wave[kDigits / 64];
+    if (!radix_pass_runs(pass, wide)) return;
     const int p = blockIdx.x;
     const uint32_t nb = (uint32_t)(((uint64_t)vbase[p + 1] - vbase[p] + kRB - 1) / kRB);
     uint32_t all = 0;
-    (void)seg_key_offsets<kOffGroups>(cnt + (uint64_t)p * nbp * kDigits, off + (uint64_t)p * nbp * kDigits, nb, kDigits, s_part,
-                          s_wave, &all);
+    (void)seg_key_offsets<kDigits, kOffGroups>(cnt + (uint64_t)p * nbp * kDigits, off + (uint64_t)p * nbp * kDigits,
+                                               nb, kDigits, s_part, s_wave, &all);
 }
 
 // vbase[p] = sum of nv[q] over q < p, for p in [0, P]. One block.
@@ -449,19 +458,24 @@ __device__ uint32_t block_exclusive_scan_waves(uint32_t x, uint32_t *s_wave /*[k
 // lays its elements out in LDS in output order (digits in order, waves in order
 // within a digit) and writes them from there, so consecutive threads store
 // consecutive positions of a digit's run (whole cache lines where the runs are
-// long) instead of 64 lanes storing to 64 runs. With kLast the keys are not
-// written: vout gets the sorted record slots and kout their tile counts, the
-// input of the pair emission.
-template <bool kLast>
-__global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int shift, uint32_t nbp, int n_poses,
+// long) instead of 64 lanes storing to 64 runs. The last pass (the third, or
+// the fourth when it runs) does not write the keys: vout gets the sorted record
+// slots and kout their tile counts, the input of the pair emission. LDS: the
+// per-wave counters (8 KB, later the digits' output deltas) and the staging
+// arrays (32 KB), 40 KB, so that 4 blocks share a compute unit.
+__global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int pass, uint32_t nbp, int n_poses,
                                                             const uint32_t *__restrict__ off,
+                                                            const unsigned long long *__restrict__ wide,
                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                             const uint2 *__restrict__ rect, int64_t n,
                                                             bool packed, uint32_t slot0) {
     __shared__ uint32_t s_cnt[kRBWaves][kDigits];
-    __shared__ uint32_t s_delta[kDigits];
     __shared__ uint32_t s_key[kRB], s_val[kRB];  // the block's elements in output order
-    __shared__ uint32_t s_wave[kRBWaves];
+    uint32_t *s_wave = s_key;                    // the scan's wave totals, before the staging
+    uint32_t *s_delta = s_cnt[0];                // after the staging: the digits' output deltas
+    if (!radix_pass_runs(pass, wide)) return;
+    const bool last = pass == kKeyPasses - 1 || (pass == kNarrowPasses - 1 && *wide == 0ull);
+    const int shift = kDigitBits * pass;
     // Workgroups go to the XCDs round robin by linear id; the mapping below puts
     // every block of pose p on XCD p % 8, in order, so the partial cache lines
     // that neighbouring blocks write at the ends of a digit's runs meet in one
@@ -491,8 +505,8 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int 
 #pragma unroll
     for (int c = 0; c < kRBChunks; ++c) {
         const bool valid = (vmask >> c) & 1u;
-        const uint32_t d = (key[c] >> shift) & 0xffu;
-        const uint64_t peers = match_peers<8>(d, valid);
+        const uint32_t d = (key[c] >> shift) & (kDigits - 1);
+        const uint64_t peers = match_peers<kDigitBits>(d, valid);
         const uint32_t r = (uint32_t)__popcll(peers & lt_mask);
         uint32_t old = 0;
         if (valid && r == 0) old = atomicAdd(&s_cnt[wave][d], (uint32_t)__popcll(peers));
@@ -503,39 +517,48 @@ __global__ __launch_bounds__(kRBThreads) void k_radix_scatter(RadixSrc src, int 
     __syncthreads();
     // Block-local order: digit d's elements go to [ls[d], ls[d] + tot[d]) of the
     // staging arrays, wave by wave; s_cnt[w][d] <- wave w's first slot there, and
-    // s_delta[d] = (output position of the block's first digit-d element) - ls[d].
-    uint32_t tot = 0;
-    if (threadIdx.x < kDigits) {
+    // delta[d] = (output position of the block's first digit-d element) - ls[d].
+    // Thread t takes digits 2t and 2t + 1.
+    static_assert(kDigits == 2 * kRBThreads, "two digits per thread");
+    const int d0 = 2 * threadIdx.x;
+    uint32_t tot0 = 0, tot1 = 0;
 #pragma unroll
-        for (int w = 0; w < kRBWaves; ++w) tot += s_cnt[w][threadIdx.x];
+    for (int w = 0; w < kRBWaves; ++w) {
+        tot0 += s_cnt[w][d0];
+        tot1 += s_cnt[w][d0 + 1];
     }
     uint32_t all = 0;
-    const uint32_t ls = block_exclusive_scan_waves<kRBWaves>(tot, s_wave, &all);
-    if (threadIdx.x < kDigits) {
-        const int d = threadIdx.x;
-        uint32_t run = ls;
+    const uint32_t ls0 = block_exclusive_scan_waves<kRBWaves>(tot0 + tot1, s_wave, &all), ls1 = ls0 + tot0;
+    {
+        uint32_t run0 = ls0, run1 = ls1;
 #pragma unroll
         for (int w = 0; w < kRBWaves; ++w) {
-            const uint32_t c = s_cnt[w][d];
-            s_cnt[w][d] = run;
-            run += c;
+            const uint32_t c0 = s_cnt[w][d0], c1 = s_cnt[w][d0 + 1];
+            s_cnt[w][d0] = run0;
+            s_cnt[w][d0 + 1] = run1;
+            run0 += c0;
+            run1 += c1;
         }
-        s_delta[d] = pose_base + off[((uint64_t)p * nbp + j) * kDigits + d] - ls;
     }
+    const uint32_t *o = off + ((uint64_t)p * nbp + j) * kDigits + d0;
+    const uint32_t delta0 = pose_base + o[0] - ls0, delta1 = pose_base + o[1] - ls1;
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < kRBChunks; ++c) {
         if (rnk[c] == 0xffffffffu) continue;
-        const uint32_t slot = s_cnt[wave][(key[c] >> shift) & 0xffu] + rnk[c];
+        const uint32_t slot = s_cnt[wave][(key[c] >> shift) & (kDigits - 1)] + rnk[c];
         s_key[slot] = key[c];
         s_val[slot] = val[c];
     }
     __syncthreads();
+    s_delta[d0] = delta0;  // (the counters are no longer read)
+    s_delta[d0 + 1] = delta1;
+    __syncthreads();
     // consecutive threads write consecutive positions of each digit's run
     for (uint32_t i = threadIdx.x; i < all; i += kRBThreads) {
         const uint32_t k = s_key[i], v = s_val[i];
-        const uint32_t pos = s_delta[(k >> shift) & 0xffu] + i;
-        if (kLast) {
+        const uint32_t pos = s_delta[(k >> shift) & (kDigits - 1)] + i;
+        if (last) {
             if (packed) {  // (index within the pose) | (tile count << kPackIndexBits)
                 vout[pos] = slot0 + (uint32_t)((uint64_t)p * (uint64_t)n) + (v & ((1u << kPackIndexBits) - 1u));
                 kout[pos] = v >> kPackIndexBits;
@@ -712,13 +735,13 @@ template <int kGroups>
 __global__ __launch_bounds__(256 * kGroups) void k_seg_offsets(SegPass ps, uint32_t *__restrict__ cnt,
                                                                const uint32_t *__restrict__ block_base, int per_row,
                                                                int row, uint64_t *__restrict__ starts) {
-    __shared__ uint32_t s_part[kGroups][256];
-    __shared__ uint32_t s_wave[4];
+    __shared__ uint32_t s_part[kGroups][kMaxKeys];
+    __shared__ uint32_t s_wave[kMaxKeys / 64];
     const int i = blockIdx.x;
     const uint32_t g0 = block_base[i], g1 = block_base[i + 1];
     uint32_t all = 0;
     uint32_t *c = cnt + (uint64_t)g0 * ps.n_keys;
-    const uint32_t start = seg_key_offsets<kGroups>(c, c, g1 - g0, ps.n_keys, s_part, s_wave, &all);
+    const uint32_t start = seg_key_offsets<kMaxKeys, kGroups>(c, c, g1 - g0, ps.n_keys, s_part, s_wave, &all);
     const int k = threadIdx.x;  // (first group: thread = key)
     const int col = (i % per_row) * ps.n_keys + k;
     if (k < ps.n_keys && col < row) starts[(uint64_t)(i / per_row) * row + col] = ps.seg[i] + start;
@@ -929,8 +952,8 @@ uint64_t radix_count_elems(int64_t n, int n_poses) {
 }
 
 void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint64_t *vmask, const uint2 *rect,
-                       uint32_t slot0, bool packed, uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
-                       uint32_t *rcnt, uint32_t *roff, uint32_t *nv, uint32_t *vbase) {
+                       uint32_t slot0, bool packed, const unsigned long long *wide, uint32_t *ka, uint32_t *va,
+                       uint32_t *kb, uint32_t *vb, uint32_t *rcnt, uint32_t *roff, uint32_t *nv, uint32_t *vbase) {
     const uint32_t nbp = (uint32_t)radix_blocks_per_pose(n);
     const int64_t n_regions = (n + 63) >> 6;
     const dim3 grid(nbp, (unsigned)n_poses);
@@ -947,26 +970,19 @@ void launch_depth_sort(hipStream_t s, int64_t n, int n_poses, const uint64_t *vm
                            dim3((unsigned)((n_waves + kCompactRegions * (kThreads / 64) - 1) /
                                            (kCompactRegions * (kThreads / 64)))),
                            dim3(kThreads), 0, s, vmask, n, n_poses, roff, vbase, kb, vb, ka, va);
-    // four dense passes: (ka, va) -> (kb, vb) -> (ka, va) -> (kb, vb) -> (ka = tile counts, va = slots)
+    // dense passes: (ka, va) -> (kb, vb) -> (ka, va) -> (kb, vb = tile counts, slots),
+    // or with the fourth pass -> (ka, va = tile counts, slots); a pass that does
+    // not run returns at once
+    static_assert(kKeyPasses == kNarrowPasses + 1, "one optional pass");
     const uint32_t *kin = ka, *vin = va;
-    for (int pass = 0; pass < 4; ++pass) {
+    for (int pass = 0; pass < kKeyPasses; ++pass) {
         RadixSrc src{kin, vin, vbase};
-        const int shift = 8 * pass;
-        // the top byte of a positive float depth (sign and high exponent bits) takes
-        // few values, so its counts are grouped per wave
-        if (pass == 3)
-            hipLaunchKernelGGL(k_radix_count<true>, grid, dim3(kRBThreads), 0, s, src, shift, nbp, rcnt);
-        else
-            hipLaunchKernelGGL(k_radix_count<false>, grid, dim3(kRBThreads), 0, s, src, shift, nbp, rcnt);
-        hipLaunchKernelGGL(k_radix_offsets, dim3((unsigned)n_poses), dim3(256 * kOffGroups), 0, s, rcnt, nbp, vbase,
-                           roff);
+        hipLaunchKernelGGL(k_radix_count, grid, dim3(kRBThreads), 0, s, src, pass, nbp, wide, rcnt);
+        hipLaunchKernelGGL(k_radix_offsets, dim3((unsigned)n_poses), dim3(kDigits * kOffGroups), 0, s, rcnt, nbp,
+                           vbase, pass, wide, roff);
         uint32_t *ko = (pass & 1) ? ka : kb, *vo = (pass & 1) ? va : vb;
-        if (pass == 3)
-            hipLaunchKernelGGL(k_radix_scatter<true>, sgrid, dim3(kRBThreads), 0, s, src, shift, nbp, n_poses, roff,
-                               ko, vo, rect, n, packed, slot0);
-        else
-            hipLaunchKernelGGL(k_radix_scatter<false>, sgrid, dim3(kRBThreads), 0, s, src, shift, nbp, n_poses, roff,
-                               ko, vo, rect, n, packed, slot0);
+        hipLaunchKernelGGL(k_radix_scatter, sgrid, dim3(kRBThreads), 0, s, src, pass, nbp, n_poses, roff, wide, ko,
+                           vo, rect, n, packed, slot0);
         kin = ko;
         vin = vo;
     }

@@ -116,6 +116,54 @@ def test_depth_sort_either_side_of_value_packing(ctx, n):
     sm.free()
 
 
+@pytest.mark.parametrize("z_near", [0.2, 0.0])
+def test_depth_sort_far_depths_and_the_fourth_pass(ctx, z_near):
+    """Depth keys are float32 depth bits minus the near plane's. Keys below 2^27
+    sort in three 9-bit radix passes; a key of 2^27 or more (beyond about 13 km
+    for a 0.2 m near plane, and every depth above 0.5 m for a near plane at 0)
+    makes the sort run a fourth pass and leave its output in the other buffers.
+    Depths up to 60 km, keys on either side of 2^27 and equal depths (ties in
+    index order) give records and sorted pairs equal to the oracle's bit for bit.
+    No depth here lies in (0, 0.2], so the oracle's 0.2 m near plane culls the
+    same Gaussians as a near plane at 0."""
+    from paper_2403_11367_amd import default_cfg
+    say(f"depth sort with depths to 60 km, near plane {z_near}, 64x48, 3 poses")
+    sc = W.tiny_scene(83, n=3000, width=64, height=48, n_poses=3, depth_range=(0.5, 30.0))
+    g = sc.gaussians
+    rng = np.random.default_rng(84)
+    means = g.means.astype(np.float64)
+    target = means[:, 1].copy()
+    far = rng.random(g.n) < 0.4
+    target[far] = rng.uniform(13_000.0, 60_000.0, int(far.sum()))
+    # depths whose keys (for a 0.2 m near plane) lie just below, at and above 2^27
+    z0 = int(np.float32(0.2).view(np.uint32))
+    edge = np.array([z0 + (1 << 27) - 2, z0 + (1 << 27) - 1, z0 + (1 << 27), z0 + (1 << 27) + 1],
+                    np.uint32).view(np.float32)
+    target[:4] = edge
+    target[4:8] = edge  # equal depths: the lower index first
+    means = (means / means[:, 1:2] * target[:, None]).astype(np.float32)
+    means[:8, 1] = np.concatenate([edge, edge])
+    means[8:16] = means[0:8]  # duplicated Gaussians: equal depths everywhere
+    gg = W.Gaussians(means, g.scales, g.quats, g.opacity, g.rgb)
+    sm = load(ctx, gg)
+    cfg = default_cfg(z_near=z_near)
+    rgb, dep, tf = gpu_render(ctx, sm, sc.camera, sc.poses, cfg)
+    recs, nts, offs, pairs = gpu_buffers(ctx)
+    pr = prep(gg)
+    T = _tiles(sc.camera)
+    n_far = 0
+    for p in range(3):
+        out, rec, ks, vs, rng_ = oracle_pose(pr, sc.poses[p], sc.camera)
+        check_records(recs, nts, rec, gg.n, p)
+        check_pairs(offs, pairs, ks, vs, rng_, p, T)
+        zk = rec.z[rec.visible].astype(np.float32).view(np.uint32).astype(np.int64) - z0
+        n_far += int((zk >= 1 << 27).sum())
+        if p == 1:
+            assert (zk < 1 << 27).sum() > 1000 and (zk >= 1 << 27).sum() > 1000
+    assert n_far > 1000
+    sm.free()
+
+
 @pytest.mark.parametrize("seed", [41, 42])
 def test_thin_tilted_and_huge_gaussians(ctx, seed):
     """Needle-thin tilted footprints and a few that cover the whole image: the
@@ -323,6 +371,9 @@ def test_argument_errors(ctx):
     assert e.value.status == -6
     with pytest.raises(GsrError):
         gpu_render(ctx, sm, sc.camera, sc.poses, default_cfg(tile_w=12))
+    with pytest.raises(GsrError) as e:  # depth keys need a near plane >= 0
+        gpu_render(ctx, sm, sc.camera, sc.poses, default_cfg(z_near=-0.1))
+    assert e.value.status == -1
     s = torch.zeros(4, device="cuda")
     with pytest.raises(GsrError):
         ctx.topk(s, 5)
