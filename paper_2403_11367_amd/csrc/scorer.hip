@@ -74,9 +74,14 @@ __device__ inline uint2 relu_bf16x4(float a0, float a1, float a2, float a3, floa
 // Forward epilogue of a wave whose accumulators hold D[c_out][pixel] (the
 // weights are the MFMA's A operand, the pixels its B operand): lane l holds the
 // pixel in column l % 32 of each pixel block r and, for g = 0..3, the output
-// channels 32 c + 8 g + 4 (l / 32) .. + 3 of each channel block c, which leave as
-// one 8-byte store each. dst[r]: the lane's pixel's first output channel of the
-// wave's channel range (null: the pixel is outside the output).
+// channels 32 c + 8 g + 4 (l / 32) .. + 3 of each channel block c. Lanes l and
+// l + 32 hold the same pixel, so one lane-half swap (v_permlane32_swap, lanes
+// 32..63 of the first operand with lanes 0..31 of the second) per register of
+// groups g and g + 1 gives lane l channels 16 h .. 16 h + 7 and lane l + 32
+// channels 16 h + 8 .. 16 h + 15 (h = g / 2), each leaving as one 16-byte store
+// (two per 32 channels instead of four 8-byte stores). dst[r]: the lane's
+// pixel's first output channel of the wave's channel range (null: the pixel is
+// outside the output, for both lanes of the pair).
 // The biases a lane's accumulators need (its RN channel blocks from `bias`), for
 // store_relu_bf16: loaded ahead of the main loop, so that their latency is not
 // waited out in the epilogue.
@@ -102,12 +107,19 @@ __device__ inline void store_relu_bf16(const f32x16 (&acc)[RM][RN], u16 *const (
     for (int r = 0; r < RM; ++r) {
         if (!dst[r]) continue;
 #pragma unroll
-        for (int c = 0; c < RN; ++c)
+        for (int c = 0; c < RN; ++c) {
+            uint2 q[4];
 #pragma unroll
             for (int g = 0; g < 4; ++g)
-                *(uint2 *)(dst[r] + 32 * c + 8 * g + 4 * kq) =
-                    relu_bf16x4(acc[r][c][4 * g], acc[r][c][4 * g + 1], acc[r][c][4 * g + 2], acc[r][c][4 * g + 3],
-                                bv.v[c][g]);
+                q[g] = relu_bf16x4(acc[r][c][4 * g], acc[r][c][4 * g + 1], acc[r][c][4 * g + 2],
+                                   acc[r][c][4 * g + 3], bv.v[c][g]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const auto sx = __builtin_amdgcn_permlane32_swap(q[2 * h].x, q[2 * h + 1].x, false, false);
+                const auto sy = __builtin_amdgcn_permlane32_swap(q[2 * h].y, q[2 * h + 1].y, false, false);
+                *(uint4 *)(dst[r] + 32 * c + 16 * h + 8 * kq) = make_uint4(sx[0], sy[0], sx[1], sy[1]);
+            }
+        }
     }
 }
 
