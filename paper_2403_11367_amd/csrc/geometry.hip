@@ -229,12 +229,11 @@ __global__ __launch_bounds__(kThreads) void k_preprocess(
 // S2, pair emission in front-to-back order. The depth-sorted visible Gaussians of
 // all poses are cut into emission blocks of kEmitTile elements (pose p owns
 // [vbase[p], vbase[p+1]); the sorted run holds their tile counts and record
-// slots). The
-// tile counts are summed per block, the block sums prefixed in two levels (within
-// spans of kSumSpan blocks, then across spans by a scan in sort.hip), and each
-// block then lays its pairs out contiguously from its prefix: element i writes
-// one pair per tile of its rectangle (row-major): the tile id within the pose and
-// the submap index.
+// slots). The tile counts are summed per block, the block sums prefixed in two
+// levels (within spans of kSumSpan blocks, then across spans by a scan in
+// sort.hip), and each block then lays its pairs out contiguously from its
+// prefix: element i writes one pair per tile of its rectangle (row-major): the
+// tile id within the pose and the submap index.
 constexpr int kEmitItems = 2;
 constexpr int kEmitTile = kThreads * kEmitItems;
 constexpr int kSumSpan = 8;
