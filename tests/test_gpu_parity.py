@@ -128,7 +128,8 @@ def test_depth_sort_far_depths_and_the_fourth_pass(ctx, z_near):
     same Gaussians as a near plane at 0."""
     from paper_2403_11367_amd import default_cfg
     say(f"depth sort with depths to 60 km, near plane {z_near}, 64x48, 3 poses")
-    sc = W.tiny_scene(83, n=3000, width=64, height=48, n_poses=3, depth_range=(0.5, 30.0))
+    # 12,000 Gaussians: each pose's visible run spans several radix blocks of 4,096
+    sc = W.tiny_scene(83, n=12_000, width=64, height=48, n_poses=3, depth_range=(0.5, 30.0))
     g = sc.gaussians
     rng = np.random.default_rng(84)
     means = g.means.astype(np.float64)
@@ -159,8 +160,8 @@ def test_depth_sort_far_depths_and_the_fourth_pass(ctx, z_near):
         zk = rec.z[rec.visible].astype(np.float32).view(np.uint32).astype(np.int64) - z0
         n_far += int((zk >= 1 << 27).sum())
         if p == 1:
-            assert (zk < 1 << 27).sum() > 1000 and (zk >= 1 << 27).sum() > 1000
-    assert n_far > 1000
+            assert (zk < 1 << 27).sum() > 4096 and (zk >= 1 << 27).sum() > 4096
+    assert n_far > 4096
     sm.free()
 
 
