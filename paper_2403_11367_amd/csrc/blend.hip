@@ -581,8 +581,10 @@ void launch_blend_t(hipStream_t s, const float4 *records, int64_t n, int n_poses
 }
 
 // The forward that also keeps the compositing state of long lists (chunks of 252).
+// Held to 64 registers like the plain forward (8 waves per SIMD; left to itself
+// the compiler takes 73 and 6 waves).
 template <int kTW>
-__global__ __launch_bounds__(kThreads) void k_blend_keep(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_blend_keep(
     const float4 *__restrict__ records, int64_t n, const uint32_t *__restrict__ pairs,
     const uint64_t *__restrict__ offsets, uint64_t capacity, int width, int height, int tiles_x, int n_tiles,
     BlendConsts k, float *__restrict__ out_rgb, float *__restrict__ out_depth, float *__restrict__ out_t,
