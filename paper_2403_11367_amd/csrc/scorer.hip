@@ -904,6 +904,116 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const u16 *__restrict__ x, c
     }
 }
 
+// Backward weight for c_in a multiple of 32, the same partial sums as
+// k_conv_wgrad, with the operands staged through LDS. A wave owns one 32 x 32
+// tile (32 output channels x 32 input channels of one tap) and walks the output
+// pixels of its rows 16 at a time. Per step it loads, for 16 consecutive output
+// pixels, the 32 channels of dy and the 32 channels of x at its tap (8-byte
+// loads of 4 channels of 2 neighbouring pixels per lane; steps go in pairs,
+// the next pair's loads in flight during this pair), writes both transposed
+// into its own LDS rows ([channel][pixel], 48-byte rows) as 32-bit words of two
+// pixels, and reads the MFMA fragments (8 consecutive pixels of one channel)
+// back as 16-byte reads: in place of 16 scalar 2-byte global loads per lane and
+// MFMA. One wave's LDS accesses complete in program order, so no barrier is
+// needed.
+template <int CI, int CO, int S>
+__global__ __launch_bounds__(256) void k_conv_wgrad_lds(const u16 *__restrict__ x, const u16 *__restrict__ dy,
+                                                         ConvDims d, int rows_per_split, float *__restrict__ part_w,
+                                                         float *__restrict__ part_b) {
+    static_assert(CI % 32 == 0 && CO % 32 == 0, "32-channel tiles");
+    constexpr int NCOL = 9 * CI, PITCH = 24;  // halves per LDS row: 16 pixels + 8 padding
+    __shared__ __align__(16) u16 s_t[4][2][32 * PITCH];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r32 = lane & 31, kq = lane >> 5;
+    const int colblk = blockIdx.x * 4 + wave;
+    if (colblk * 32 >= NCOL) return;  // (a whole wave; there is no block barrier)
+    const int tap = colblk * 32 / CI, ci0 = colblk * 32 - tap * CI;
+    const int kh = tap / 3, kw = tap - 3 * kh;
+    const int co0 = blockIdx.y * 32;
+    const int split = blockIdx.z;
+    const int R = d.n * d.Ho;
+    const int rb = split * rows_per_split, re = min(R, rb + rows_per_split);
+    u16 *sd = s_t[wave][0], *sx = s_t[wave][1];
+    const int pp = lane >> 3, cq = lane & 7;  // staging: pixels 2 pp and 2 pp + 1, channels 4 cq .. 4 cq + 3
+    const int nch = (d.Wo + 15) / 16;
+    const int64_t K = (int64_t)max(0, re - rb) * nch;
+    // step k's loads: v[0], v[1] = dy of the two pixels, v[2], v[3] = x; ok bit j: v[j] holds data
+    auto load = [&](int64_t k, uint2 (&v)[4], uint32_t &ok) {
+        const int row = rb + (int)(k / nch), ox0 = (int)(k % nch) * 16;
+        const int n = row / d.Ho, oy = row - n * d.Ho;
+        const int iy = oy * S - 1 + kh;
+        const bool row_ok = iy >= 0 && iy < d.H;
+        ok = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ox = ox0 + 2 * pp + h;
+            const bool okp = ox < d.Wo;
+            const int ix = ox * S - 1 + kw;
+            const bool okx = okp && row_ok && ix >= 0 && ix < d.W;
+            // (clamped addresses, no load under a branch)
+            v[h] = *(const uint2 *)(dy + ((int64_t)row * d.Wo + (okp ? ox : 0)) * CO + co0 + 4 * cq);
+            v[2 + h] = *(const uint2 *)(x + (((int64_t)n * d.H + (row_ok ? iy : 0)) * d.W + (okx ? ix : 0)) * CI +
+                                       ci0 + 4 * cq);
+            ok |= ((uint32_t)okp << h) | ((uint32_t)okx << (2 + h));
+        }
+    };
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+    float bsum = 0.f;
+    // one step: the loaded values to LDS, transposed (row = channel, two pixels
+    // per 32-bit word), then the fragments back and one MFMA
+    auto step = [&](uint2 (&v)[4], uint32_t ok) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (!((ok >> j) & 1u)) v[j] = make_uint2(0u, 0u);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            u16 *dst = t == 0 ? sd : sx;
+            const uint2 a = v[2 * t], b = v[2 * t + 1];
+            uint32_t *w = reinterpret_cast<uint32_t *>(dst + 4 * cq * PITCH + 2 * pp);
+            w[0] = (a.x & 0xffffu) | (b.x << 16);
+            w[PITCH / 2] = (a.x >> 16) | (b.x & 0xffff0000u);
+            w[PITCH] = (a.y & 0xffffu) | (b.y << 16);
+            w[3 * PITCH / 2] = (a.y >> 16) | (b.y & 0xffff0000u);
+        }
+        const u32x4 fa = *(const u32x4 *)(sd + r32 * PITCH + 8 * kq);  // dy[8 pixels][c_out r32]
+        const u32x4 fb = *(const u32x4 *)(sx + r32 * PITCH + 8 * kq);  // x[8 pixels][c_in r32]
+        acc = mfma(__builtin_bit_cast(bf16x8, fa), __builtin_bit_cast(bf16x8, fb), acc);
+        if (colblk == 0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) bsum += __uint_as_float(fa[e] << 16) + __uint_as_float(fa[e] & 0xffff0000u);
+        }
+    };
+    // steps in pairs, the next pair's loads in flight during this pair
+    uint2 c0[4], c1[4], n0[4], n1[4];
+    uint32_t ok0 = 0, ok1 = 0, okn0 = 0, okn1 = 0;
+    if (K > 0) load(0, c0, ok0);
+    if (K > 1) load(1, c1, ok1);
+    for (int64_t k = 0; k < K; k += 2) {
+        if (k + 2 < K) load(k + 2, n0, okn0);
+        if (k + 3 < K) load(k + 3, n1, okn1);
+        step(c0, ok0);
+        if (k + 1 < K) step(c1, ok1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            c0[j] = n0[j];
+            c1[j] = n1[j];
+        }
+        ok0 = okn0;
+        ok1 = okn1;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int rco = co0 + 8 * (i / 4) + 4 * kq + (i % 4);
+        part_w[((int64_t)split * CO + rco) * NCOL + colblk * 32 + r32] = acc[i];
+    }
+    if (colblk == 0) {
+        bsum += __shfl_xor(bsum, 32, 64);
+        if (kq == 0) part_b[(int64_t)split * CO + co0 + r32] = bsum;
+    }
+}
+
 // grad_w[e] = sum over splits of part_w, grad_b likewise, in split order.
 __global__ void k_wgrad_reduce(const float *__restrict__ part_w, const float *__restrict__ part_b, int nsplit,
                                int nw, int nb, float *__restrict__ grad_w, float *__restrict__ grad_b) {
@@ -1129,8 +1239,12 @@ void wgrad_layer(hipStream_t s, const u16 *x, const u16 *dy, ConvDims d, float *
     nsplit = std::max(1, nsplit);
     const int rows = (R + nsplit - 1) / nsplit;
     nsplit = (R + rows - 1) / rows;
-    hipLaunchKernelGGL((k_conv_wgrad<CI, CO, S>), dim3(colgroups, coblocks, nsplit), dim3(256), 0, s, x, dy, d, rows,
-                       part_w, part_w + (int64_t)nsplit * CO * NCOL);
+    if constexpr (CI % 32 == 0)
+        hipLaunchKernelGGL((k_conv_wgrad_lds<CI, CO, S>), dim3(colgroups, coblocks, nsplit), dim3(256), 0, s, x, dy,
+                           d, rows, part_w, part_w + (int64_t)nsplit * CO * NCOL);
+    else
+        hipLaunchKernelGGL((k_conv_wgrad<CI, CO, S>), dim3(colgroups, coblocks, nsplit), dim3(256), 0, s, x, dy, d,
+                           rows, part_w, part_w + (int64_t)nsplit * CO * NCOL);
     const int nw = CO * NCOL;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((nw + CO + 255) / 256), dim3(256), 0, s, part_w,
                        part_w + (int64_t)nsplit * CO * NCOL, nsplit, nw, CO, grad_w, grad_b);
