@@ -400,8 +400,9 @@ __global__ __launch_bounds__(kThreads) void k_compact(const uint64_t *__restrict
         my_src = (uint64_t)p * (uint64_t)n + ((uint64_t)r << 6);
         my_dst = (uint64_t)vbase[p] + reg_off[w];
     }
-    // every region's entries are loaded before the first store, so the wave's 16
-    // loads are in flight together instead of one memory latency per region
+    // every region's entries are loaded before the first store, so the wave's
+    // loads (two per region) are in flight together instead of one memory
+    // latency per region
     uint32_t kv[kCompactRegions], vv[kCompactRegions];
 #pragma unroll
     for (int i = 0; i < kCompactRegions; ++i) {
