@@ -916,16 +916,16 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const u16 *__restrict__ x, c
 // back as 16-byte reads: in place of 16 scalar 2-byte global loads per lane and
 // MFMA. One wave's LDS accesses complete in program order, so no barrier is
 // needed.
-template <int CI, int CO, int S>
-__global__ __launch_bounds__(256) void k_conv_wgrad_lds(const u16 *__restrict__ x, const u16 *__restrict__ dy,
+template <int CI, int CO, int S, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_conv_wgrad_lds(const u16 *__restrict__ x, const u16 *__restrict__ dy,
                                                          ConvDims d, int rows_per_split, float *__restrict__ part_w,
                                                          float *__restrict__ part_b) {
     static_assert(CI % 32 == 0 && CO % 32 == 0, "32-channel tiles");
     constexpr int NCOL = 9 * CI, PITCH = 24;  // halves per LDS row: 16 pixels + 8 padding
-    __shared__ __align__(16) u16 s_t[4][2][32 * PITCH];
+    __shared__ __align__(16) u16 s_t[WPB][2][32 * PITCH];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r32 = lane & 31, kq = lane >> 5;
-    const int colblk = blockIdx.x * 4 + wave;
+    const int colblk = blockIdx.x * WPB + wave;
     if (colblk * 32 >= NCOL) return;  // (a whole wave; there is no block barrier)
     const int tap = colblk * 32 / CI, ci0 = colblk * 32 - tap * CI;
     const int kh = tap / 3, kw = tap - 3 * kh;
@@ -1014,19 +1014,41 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_lds(const u16 *__restrict__ 
     }
 }
 
-// grad_w[e] = sum over splits of part_w, grad_b likewise, in split order.
-__global__ void k_wgrad_reduce(const float *__restrict__ part_w, const float *__restrict__ part_b, int nsplit,
-                               int nw, int nb, float *__restrict__ grad_w, float *__restrict__ grad_b) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < nw) {
-        float s = 0.f;
-        for (int k = 0; k < nsplit; ++k) s += part_w[(int64_t)k * nw + e];
-        grad_w[e] = s;
-    } else if (e < nw + nb) {
-        const int c = e - nw;
-        float s = 0.f;
-        for (int k = 0; k < nsplit; ++k) s += part_b[(int64_t)k * nb + c];
-        grad_b[c] = s;
+// grad_w[e] = sum over splits of part_w, grad_b likewise, in a fixed order: a
+// block takes 32 elements, and its 8 groups of 32 threads sum the splits g, g +
+// 8, g + 16, ... of them (4 loads in flight per thread), then the 8 group sums
+// are added in group order. (One thread per element walking all splits in turn
+// left most of the machine idle behind a chain of a few hundred loads.)
+constexpr int kRedElems = 32, kRedGroups = 8;
+__global__ __launch_bounds__(kRedElems * kRedGroups) void k_wgrad_reduce(const float *__restrict__ part_w,
+                                                                         const float *__restrict__ part_b, int nsplit,
+                                                                         int nw, int nb, float *__restrict__ grad_w,
+                                                                         float *__restrict__ grad_b) {
+    __shared__ float s_sum[kRedGroups][kRedElems];
+    const int el = threadIdx.x % kRedElems, g = threadIdx.x / kRedElems;
+    const int e = blockIdx.x * kRedElems + el;
+    const bool is_w = e < nw;
+    const float *src = is_w ? part_w + e : part_b + (e - nw);
+    const int64_t stride = is_w ? nw : nb;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    if (e < nw + nb) {
+        int k = g;
+        for (; k + 3 * kRedGroups < nsplit; k += 4 * kRedGroups) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += src[(int64_t)(k + u * kRedGroups) * stride];
+        }
+        for (; k < nsplit; k += kRedGroups) acc[0] += src[(int64_t)k * stride];
+    }
+    s_sum[g][el] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __syncthreads();
+    if (g == 0 && e < nw + nb) {
+        float t = 0.f;
+#pragma unroll
+        for (int h = 0; h < kRedGroups; ++h) t += s_sum[h][el];
+        if (is_w)
+            grad_w[e] = t;
+        else
+            grad_b[e - nw] = t;
     }
 }
 
@@ -1229,8 +1251,12 @@ void bwd_data_layer(hipStream_t s, const u16 *dy, ConvDims d, const u16 *wd, con
 template <int CI, int CO, int S>
 void wgrad_layer(hipStream_t s, const u16 *x, const u16 *dy, ConvDims d, float *part_w, int64_t part_cap,
                  float *grad_w, float *grad_b) {
-    constexpr int NCOL = 9 * CI;
-    const int colgroups = (NCOL / 32 + (NCOL % 32 ? 1 : 0) + 3) / 4;
+    constexpr int NCOL = 9 * CI, NCB = (NCOL + 31) / 32;  // 32-column blocks
+    // column blocks (waves) per block: 3 for c_in 32 (9 blocks, none idle; 716
+    // against 738 us), else 4 (c_in 64 with 3 per block measured slower: layer 4
+    // 800 against 704 us, layer 3 494 against 395)
+    constexpr int WPB = CI == 32 ? 3 : 4;
+    const int colgroups = (NCB + WPB - 1) / WPB;
     const int coblocks = CO / 32;
     const int R = d.n * d.Ho;
     // about 2048 blocks, and no more splits than the partial buffer holds
@@ -1240,14 +1266,14 @@ void wgrad_layer(hipStream_t s, const u16 *x, const u16 *dy, ConvDims d, float *
     const int rows = (R + nsplit - 1) / nsplit;
     nsplit = (R + rows - 1) / rows;
     if constexpr (CI % 32 == 0)
-        hipLaunchKernelGGL((k_conv_wgrad_lds<CI, CO, S>), dim3(colgroups, coblocks, nsplit), dim3(256), 0, s, x, dy,
-                           d, rows, part_w, part_w + (int64_t)nsplit * CO * NCOL);
+        hipLaunchKernelGGL((k_conv_wgrad_lds<CI, CO, S, WPB>), dim3(colgroups, coblocks, nsplit), dim3(64 * WPB), 0, s,
+                           x, dy, d, rows, part_w, part_w + (int64_t)nsplit * CO * NCOL);
     else
         hipLaunchKernelGGL((k_conv_wgrad<CI, CO, S>), dim3(colgroups, coblocks, nsplit), dim3(256), 0, s, x, dy, d,
                            rows, part_w, part_w + (int64_t)nsplit * CO * NCOL);
     const int nw = CO * NCOL;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((nw + CO + 255) / 256), dim3(256), 0, s, part_w,
-                       part_w + (int64_t)nsplit * CO * NCOL, nsplit, nw, CO, grad_w, grad_b);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((nw + CO + kRedElems - 1) / kRedElems), dim3(kRedElems * kRedGroups), 0, s,
+                       part_w, part_w + (int64_t)nsplit * CO * NCOL, nsplit, nw, CO, grad_w, grad_b);
 }
 
 }  // namespace
